@@ -1,0 +1,166 @@
+#!/usr/bin/env python3
+"""Benchmark: design iterations of the periodic thermal homogenization path
+on one MI355X, for the 128^3 anisotropic cell.
+
+One step = one full design iteration on one cell: filter + SIMP + macro loads
++ Jacobi-PCG for the three loads + homogenized tensor + sensitivities +
+filter transpose + adaptive V* + OC bisection update.  The design state
+(density, governor) carries over from step to step, as in the method.
+
+Printed JSON line: `value` is PCG DOF-updates per second over the whole timed
+region, (n^3 * sum over loads of PCG iterations) / wall time of the K steps;
+`ms_per_step` is the mean wall time of a design iteration.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, published
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--precision", choices=["mixed", "fp64"], default="mixed")
+    ap.add_argument("--guess", choices=["zero", "previous"], default="zero")
+    ap.add_argument("--n", type=int, default=128)
+    ap.add_argument("--tol", type=float, default=1e-6)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--oracle-cg-iters", type=int, default=10)
+    ap.add_argument("--apply-reps", type=int, default=50)
+    return ap.parse_args()
+
+
+def cpu_baseline(w, cg_iters: int):
+    """The CPU FP64 oracle on a bounded sample of the same workload: filter,
+    SIMP, CSR assembly and macro loads at full size, then `cg_iters` plain CG
+    iterations on each of the three loads."""
+    import numpy as np
+    import oracle as O
+    prm = O.Params()
+    t0 = time.perf_counter()
+    rhof = O.density_filter(w.rho0, prm.rfilter)
+    k = O.simp(rhof, w.k0, w.kmin, w.penal)
+    A = O.assemble(k)
+    b = O.macro_loads(k)
+    t1 = time.perf_counter()
+    for i in range(3):
+        O.cg_fixed(A, b[i], cg_iters)
+    t2 = time.perf_counter()
+    dof = w.n ** 3 * 3 * cg_iters
+    return {
+        "value": dof / (t2 - t1),
+        "unit": "DOF-updates/s",
+        "cores": O.num_threads(),
+        "kind": "oracle",
+        "sample": f"{w.n}^3 cell: filter+SIMP+CSR assembly+loads ({t1 - t0:.1f} s), then {cg_iters} "
+                  f"unpreconditioned FP64 CG iterations x 3 loads ({t2 - t1:.1f} s); value = DOF-updates/s of the CG part",
+        "setup_s": t1 - t0,
+        "cg_s": t2 - t1,
+    }
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
+                                   "(multi-GPU sharding is described in DESIGN.md, not implemented)"}))
+        sys.exit(2)
+    import numpy as np
+    import torch
+    import synth
+    from paper_2405_19991_amd import Homogenization, time_apply_device
+
+    assert torch.cuda.is_available(), "bench needs a GPU"
+    torch.cuda.set_device(0)
+    if args.n == 128:
+        w = synth.config3(args.precision)
+    else:
+        w = synth.Workload(f"cell{args.n}_aniso", args.n, synth.smoothed_noise(args.n, 0.15, 0.45, 301),
+                           np.array(synth.TARGET_ANISO), 0.3, precision=args.precision)
+    w.tol = args.tol
+    n = w.n
+    nn = n ** 3
+    h = Homogenization(n, (w.k0, w.kmin), w.target, vf=w.vf, penal=w.penal, filter_radius=w.rfilter,
+                       precision=args.precision, guess=args.guess, tol=w.tol)
+    h.set_density(w.rho0)
+    def log(msg):
+        print(msg, file=sys.stderr, flush=True)
+
+    log(f"bench: {w.name} n={n} precision={args.precision} warmup={args.warmup} steps={args.steps}")
+    for i in range(args.warmup):
+        r = h.step()
+        log(f"warmup {i}: g={r['g']:.4e} pcg={r['pcg_iters']} ms={r['ms_total']:.1f}")
+    torch.cuda.synchronize()
+    recs = []
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        recs.append(h.step())
+        log(f"step: g={recs[-1]['g']:.4e} pcg={recs[-1]['pcg_iters']} ms={recs[-1]['ms_total']:.1f}")
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    wall = t1 - t0
+    pcg_iters = sum(sum(r["pcg_iters"]) for r in recs)
+    dof = nn * pcg_iters
+    solve_ms = sum(r["ms_solve"] for r in recs)
+
+    # dominant kernel: the stencil operator, timed with HIP events on its stream
+    k_field = torch.from_numpy(h.get_field("k").reshape(-1)).cuda()
+    dt = torch.float32 if args.precision == "mixed" else torch.float64
+    kd = k_field.to(dt).contiguous()
+    x = torch.randn(3 * nn, dtype=dt, device="cuda")
+    y = torch.empty_like(x)
+    us = time_apply_device(kd, x, y, args.precision, reps=args.apply_reps, variant=0)
+    us_gather = time_apply_device(kd, x, y, args.precision, reps=args.apply_reps, variant=1)
+    bpn = 28 if args.precision == "mixed" else 56
+    alg_bytes = bpn * nn
+    achieved = alg_bytes / (us * 1e-6) / 1e9
+    tname = "float" if args.precision == "mixed" else "double"
+    roof = {"bound": "hbm", "kernel": f"k_tiled<{tname}, 32, 8, false> (stencil apply, 3 loads)",
+            "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+            "traffic": None, "us_per_launch": us, "alg_bytes_per_launch": alg_bytes,
+            "direct_gather_us_per_launch": us_gather}
+
+    out = {
+        "metric": "128^3 PCG DOF-updates/s (whole design iteration, mixed precision)",
+        "value": dof / wall,
+        "unit": "DOF-updates/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1000.0 * wall / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32-operator/f64-dots" if args.precision == "mixed" else "f64",
+        "data": "synthetic",
+        "config": {"workload": w.name + ("_" + args.precision), "n": n, "tol": w.tol, "loads": 3,
+                   "guess": args.guess, "target": list(map(float, w.target)), "vf": w.vf,
+                   "k0": w.k0, "kmin": w.kmin, "penal": w.penal, "filter_radius": w.rfilter},
+        "s_per_oc_iter": wall / args.steps,
+        "pcg_iters_per_step": pcg_iters / args.steps,
+        "pcg_only_dof_per_s": dof / (solve_ms * 1e-3) if solve_ms > 0 else None,
+        "last_g": recs[-1]["g"],
+        "last_kappa": recs[-1]["kappa"],
+        "roofline": roof,
+    }
+    h.close()
+    log(f"apply kernel {us:.2f} us ({achieved:.0f} GB/s algorithmic)")
+    if not args.no_cpu_baseline:
+        log("cpu baseline (oracle) ...")
+        out["cpu_baseline"] = cpu_baseline(w, args.oracle_cg_iters)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,245 @@
+/*
+ * opentm_amd.h -- C ABI of the MI355X (gfx950) periodic thermal
+ * homogenization library.
+ *
+ * The library computes one design iteration of the density-based thermal
+ * microstructure method of Quan, Zhai and Fu ("OpenTM", arXiv 2405.19991):
+ *
+ *   density filter (Sec. 2.3, filter equation)
+ *     -> SIMP conductivity k_e = kmin + rho~_e^p (k0 - kmin)   (Sec. 2.2)
+ *     -> macro loads f^(i) for the three unit gradients        (Sec. 2.4, enforceMacroLoad)
+ *     -> matrix-free hex-8 conduction operator [KT]_v inside Jacobi-preconditioned
+ *        conjugate gradients, three load cases                 (Sec. 2.4, FEM; eq. K T^(i) = f^(i))
+ *     -> homogenized tensor kappa^H                             (Sec. 2.2, discrete homogenization formula)
+ *     -> objective and sensitivities, filter transpose          (Sec. 2.3 chain rule and sensitivity equation)
+ *     -> adaptive volume bound V*                               (Algorithm 1)
+ *     -> Optimality Criteria update                             (Sec. 3.3, OCOptimizer; Sec. 3.4 step 6)
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  Grid     : periodic cube of n^3 voxel elements and n^3 nodes; node (i,j,k)
+ *             is the lower corner of element (i,j,k); flat index
+ *             i + n*(j + n*k) (x fastest).  4 <= n <= 1024.
+ *  Fields   : float64, flat, in that order.  Three-load fields (macro loads,
+ *             fluctuations chi) are load-major: [load][n^3].  chi is in voxel
+ *             units and has zero mean per load.
+ *  Tensor   : 6-vector [k11, k22, k33, k12, k23, k13] (Sec. 2.2 correspondence).
+ *  Ownership: a context owns all device memory it allocates.  Host pointers
+ *             are owned by the caller, read or written only during the call
+ *             and never retained.  Device pointers passed in are read or
+ *             written only during the call, on the context's (or the given)
+ *             HIP stream; the call returns after that work has completed.
+ *  Errors   : every int-returning function returns an OTM_* status.  Nothing
+ *             throws or aborts across this boundary.  otm_last_error() gives a
+ *             per-context message for the most recent failure.
+ *  Threads  : a context must not be used from two threads at once.
+ */
+#ifndef OPENTM_AMD_H
+#define OPENTM_AMD_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* ---- status codes -------------------------------------------------------- */
+#define OTM_OK 0
+#define OTM_NOT_CONVERGED 1 /* warning: outputs are filled; stats say how far the solve got */
+#define OTM_EINVAL (-1)     /* invalid argument (null pointer, size mismatch, bad parameter) */
+#define OTM_ENOMEM (-2)     /* device or host allocation failed */
+#define OTM_EDEVICE (-3)    /* a HIP runtime call failed, or no usable gfx950 device */
+#define OTM_ENONFINITE (-4) /* NaN or Inf in an input or a result */
+#define OTM_EUNSUPPORTED (-5)
+#define OTM_ESTATE (-6) /* call order violated (e.g. sensitivity before homogenize) */
+
+/* ---- enumerations -------------------------------------------------------- */
+#define OTM_FP64 0  /* every vector and the operator in float64 */
+#define OTM_MIXED 1 /* float32 operator and Krylov vectors; float64 solution, dots,
+                       residual recomputation and tensor assembly */
+
+#define OTM_GUESS_ZERO 0     /* PCG starts from chi = 0 */
+#define OTM_GUESS_PREVIOUS 1 /* PCG starts from the previous design iteration's chi */
+#define OTM_GUESS_USER 2     /* PCG starts from the field set by otm_set_guess */
+
+#define OTM_OBJ_MSE 0 /* g = sum_c (kappa_c - target_c)^2, Sec. 4.4 (MSE objective) */
+
+/* Fields readable with otm_get_field (count = n^3, or 3 n^3 where noted). */
+#define OTM_FIELD_RHO 0      /* design density rho (current) */
+#define OTM_FIELD_RHOF 1     /* filtered density rho~ */
+#define OTM_FIELD_K 2        /* element conductivity k_e */
+#define OTM_FIELD_B 3        /* macro loads b^i, 3 n^3, projected to zero mean */
+#define OTM_FIELD_DIAG 4     /* Jacobi diagonal d_v = (1/3) sum of the 8 incident k_e */
+#define OTM_FIELD_CHI 5      /* fluctuation fields chi^i, 3 n^3, zero mean */
+#define OTM_FIELD_SENS_ELEM 6 /* dg/drho~_e before the filter transpose */
+#define OTM_FIELD_SENS 7     /* dg/drho_e after the filter transpose */
+
+/* ---- parameter blocks ---------------------------------------------------- */
+typedef struct {
+    int32_t n;            /* elements per axis (cubic periodic cell), 4..1024 */
+    double k0;            /* solid conductivity, > kmin */
+    double kmin;          /* void conductivity, > 0 */
+    double penal;         /* SIMP exponent p >= 1 */
+    double filter_radius; /* hat-filter radius in voxels; < 1 disables the filter */
+    double target[6];     /* target tensor, [11,22,33,12,23,13] */
+    double vf;            /* initial volume bound V*_0 in (0, 1] */
+    int32_t objective;    /* OTM_OBJ_MSE */
+} otm_problem;
+
+typedef struct {
+    int32_t precision;   /* OTM_FP64 or OTM_MIXED */
+    int32_t guess;       /* OTM_GUESS_* */
+    double tol;          /* stop when ||b - A chi||_2 <= tol ||b||_2 for every load */
+    int32_t max_iter;    /* PCG iteration cap per solve */
+    int32_t check_every; /* host convergence check interval (iterations), >= 1 */
+    double reliable_delta; /* OTM_MIXED: refresh the float64 residual when the float32
+                              recursive residual has dropped by this factor */
+    int32_t kernel_variant; /* 0: LDS-tiled fused kernels (default); 1: direct-gather
+                               kernels (same arithmetic, kept as a cross-check) */
+    int32_t tile_tz;        /* planes per z-march of the tiled kernel; 0 = automatic */
+} otm_solver_opts;
+
+typedef struct {
+    double move;    /* OC move limit m */
+    double eta;     /* OC damping exponent */
+    double rho_min; /* lower density bound */
+} otm_oc_opts;
+
+typedef struct {
+    double bound;     /* objective considered small enough to shrink V* */
+    double dg_small;  /* |g_prev - g| below this counts as little progress */
+    double dv_small;  /* |V - V*| below this counts as sitting on the bound */
+    double decay;     /* Df <- decay * Df after each reduction */
+    double rebound;   /* V* <- V* + rebound * gap * Df after `patience` stalls */
+    double g_tol;     /* termination: |g_prev - g| below this ... */
+    int32_t patience;
+    int32_t stall_iters; /* ... for this many consecutive iterations */
+} otm_governor_opts;
+
+typedef struct {
+    int32_t iterations[3];  /* PCG iterations per load (float32 iterations in OTM_MIXED) */
+    double rel_residual[3]; /* true ||b - A chi|| / ||b|| per load, float64 */
+    int32_t converged;      /* 1 when every load met tol */
+    int32_t refreshes;      /* OTM_MIXED: float64 residual refreshes */
+    double ms_solve;        /* wall time of the three solves, milliseconds */
+} otm_solve_stats;
+
+typedef struct {
+    int32_t iter;
+    double g;
+    double kappa[6];
+    double volume;    /* mean(rho) before the update */
+    double low_bound; /* mean(rho~^p) */
+    double vstar;     /* V* used by this iteration's OC update */
+    double lambda;    /* OC multiplier */
+    int32_t pcg_iters[3];
+    double rel_residual[3];
+    double ms_total;
+    double ms_solve;
+    int32_t stop; /* 1 when the stall test of the governor fired */
+} otm_iter_record;
+
+typedef struct otm_ctx otm_ctx;
+
+/* Fill the three option blocks with the defaults: FP64, zero guess, tol 1e-8,
+ * move 0.05, eta 0.5, rho_min 1e-3 (Sec. 4 parameters), governor bound 1e-4,
+ * decay 0.8, rebound 0.3, patience 5 (Algorithm 1).  Any pointer may be NULL. */
+void otm_default_options(otm_solver_opts* solver, otm_oc_opts* oc, otm_governor_opts* gov);
+
+/* Create a context on the current HIP device.  `stream` is a hipStream_t or
+ * NULL (the context then creates its own stream).  Options may be NULL for
+ * defaults.  All device buffers for n^3 are allocated here.
+ * Errors: OTM_EINVAL (bad parameters), OTM_EDEVICE (no gfx950 device),
+ * OTM_ENOMEM.  On error *out is NULL. */
+int otm_create(const otm_problem* problem, const otm_solver_opts* solver, const otm_oc_opts* oc,
+               const otm_governor_opts* gov, void* stream, otm_ctx** out);
+void otm_destroy(otm_ctx* ctx);
+
+/* Design density: `count` must be n^3; values must be finite and are clamped
+ * to [rho_min, 1] on entry (the return value is OTM_OK either way).
+ * The _device variant reads a float64 device buffer of n^3 values. */
+int otm_set_density(otm_ctx* ctx, const double* rho_host, int64_t count);
+int otm_set_density_device(otm_ctx* ctx, const void* rho_device, int64_t count);
+
+/* Filter, SIMP, macro loads, three PCG solves and the tensor (Sec. 2.2, 2.4).
+ * kappa6 (host, 6 doubles) receives kappa^H; stats may be NULL.
+ * Returns OTM_NOT_CONVERGED if a solve hit max_iter (kappa still filled). */
+int otm_homogenize(otm_ctx* ctx, double kappa6[6], otm_solve_stats* stats);
+
+/* Sensitivities for a given dg/dkappa (6 doubles, host), from the state of the
+ * last otm_homogenize (Sec. 2.3).  dg_drho_host (n^3, may be NULL) receives
+ * dg/drho after the filter transpose.  OTM_ESTATE without a prior homogenize. */
+int otm_sensitivity(otm_ctx* ctx, const double dg_dkappa6[6], double* dg_drho_host);
+
+/* Optimality Criteria update with volume bound `vstar` from the last
+ * sensitivities: bisection on the multiplier (bracket [0, 1e9], relative width
+ * 1e-13, at most 200 halvings).  rho_out_host (n^3) and lambda_out may be NULL.
+ * The context's density is replaced by the update. */
+int otm_oc_update(otm_ctx* ctx, double vstar, double* rho_out_host, double* lambda_out);
+
+/* One full design iteration (Algorithm 2 body with the Algorithm 1 governor):
+ * homogenize -> objective -> sensitivities -> V* update -> OC update. */
+int otm_step(otm_ctx* ctx, otm_iter_record* rec);
+
+/* Up to max_iter design iterations; stops early when the governor's stall test
+ * fires.  log (may be NULL) receives up to log_cap records; rho_out_host (n^3,
+ * may be NULL) the final density; iters_done (may be NULL) the count run. */
+int otm_optimize(otm_ctx* ctx, int32_t max_iter, double* rho_out_host, otm_iter_record* log,
+                 int32_t log_cap, int32_t* iters_done);
+
+/* Copy a field (OTM_FIELD_*) to the host; count must equal its size. */
+int otm_get_field(otm_ctx* ctx, int32_t field, double* host_out, int64_t count);
+
+/* Overwrite a field from the host, for step-by-step use from externally
+ * computed inputs: OTM_FIELD_RHO (n^3; same as otm_set_density),
+ * OTM_FIELD_CHI (3 n^3; needs a prior otm_prepare or otm_homogenize of the
+ * same density; the next otm_sensitivity uses it) or OTM_FIELD_SENS (n^3; the
+ * next otm_oc_update uses it).  Other fields: OTM_EINVAL. */
+int otm_set_field(otm_ctx* ctx, int32_t field, const double* host_in, int64_t count);
+
+/* Initial guess for OTM_GUESS_USER: 3 n^3 float64 values (voxel units). */
+int otm_set_guess(otm_ctx* ctx, const double* chi_host, int64_t count);
+
+/* Governor state as 8 doubles: [vstar, df, count, gap, g_prev, small_steps, iter, 0].
+ * set restores a state returned by get (checkpoint/resume). */
+int otm_get_governor(const otm_ctx* ctx, double state8[8]);
+int otm_set_governor(otm_ctx* ctx, const double state8[8]);
+
+/* Matrix-free operator y^i = A x^i for the three loads with the context's
+ * current k (needs a prior otm_homogenize or otm_prepare), in the given
+ * precision (OTM_FP64 or OTM_MIXED = float32 operator).  x and y are host
+ * arrays of 3 n^3 float64 values.  This is [KT]_v of Sec. 2.4. */
+int otm_apply(otm_ctx* ctx, int32_t precision, const double* x_host, double* y_host);
+
+/* Filter + SIMP + macro loads + diagonal only (first half of otm_homogenize). */
+int otm_prepare(otm_ctx* ctx);
+
+/* Stateless operator on caller device memory: y^i = A x^i for the three loads
+ * of an n^3 cell ([KT]_v of Sec. 2.4).  k_dev: n^3 element conductivities;
+ * x_dev, y_dev: 3 n^3 node values, load-major, not aliased.  precision
+ * OTM_FP64 -> all pointers are double*; OTM_MIXED -> all are float*.
+ * variant: 0 = LDS-tiled kernel, 1 = direct-gather kernel.
+ * stream: hipStream_t or NULL.  Asynchronous on `stream`. */
+int otm_apply_device(int32_t n, int32_t precision, int32_t variant, const void* k_dev, const void* x_dev,
+                     void* y_dev, void* stream);
+
+/* Timing of the stateless operator: runs `reps` launches of the operator on
+ * `stream` and returns the mean kernel duration in microseconds, measured
+ * with HIP events on that stream. */
+int otm_time_apply_device(int32_t n, int32_t precision, int32_t variant, const void* k_dev, const void* x_dev,
+                          void* y_dev, void* stream, int32_t reps, double* us_per_launch);
+
+/* Per-phase timings of the last otm_step, milliseconds, HIP events on the
+ * context stream: [filter+setup, solve, tensor, sensitivity, oc, total,
+ * solve kernel (dominant) mean us, solve kernel launches]. */
+int otm_get_timings(const otm_ctx* ctx, double t8[8]);
+
+const char* otm_strerror(int status);
+const char* otm_last_error(const otm_ctx* ctx);
+/* Library version string. */
+const char* otm_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* OPENTM_AMD_H */

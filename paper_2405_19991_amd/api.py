@@ -1,0 +1,237 @@
+"""Python front end over the C ABI (argument marshalling only).
+
+Mirrors the paper's Python interface shape (Sec. 3.5): a homogenization
+object configured with a resolution, the two conductivities [k0, kmin] and a
+target 6-vector, given a density, then optimized; and a one-call
+``run_instance``.  Host arrays are float64 numpy arrays of shape (n, n, n)
+indexed [z][y][x]; device inputs may be float64 torch CUDA tensors.
+"""
+from __future__ import annotations
+
+import ctypes
+import json
+from typing import Dict, List, Optional, Sequence
+
+import numpy as np
+
+from . import _native as N
+
+_dp = ctypes.POINTER(ctypes.c_double)
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(_dp)
+
+
+def _f64(a) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
+
+
+class Homogenization:
+    """One periodic n^3 design cell on the current HIP device."""
+
+    def __init__(self, n: int, heat_ratio: Sequence[float] = (1.0, 1e-3),
+                 target: Sequence[float] = (0.1, 0.1, 0.1, 0.0, 0.0, 0.0), vf: float = 0.3,
+                 penal: float = 3.0, filter_radius: float = 1.5, precision: str = "fp64",
+                 guess: str = "zero", tol: float = 1e-8, max_iter: int = 20000, check_every: int = 16,
+                 reliable_delta: float = 1e-2, move: float = 0.05, eta: float = 0.5, rho_min: float = 1e-3,
+                 governor: Optional[Dict[str, float]] = None, stream=None, kernel_variant: int = 0,
+                 tile_tz: int = 0):
+        L = N.lib()
+        self.n = int(n)
+        p = N.Problem()
+        p.n = self.n
+        p.k0, p.kmin = float(heat_ratio[0]), float(heat_ratio[1])
+        p.penal = float(penal)
+        p.filter_radius = float(filter_radius)
+        for i, t in enumerate(target):
+            p.target[i] = float(t)
+        p.vf = float(vf)
+        p.objective = N.OTM_OBJ_MSE
+        s, o, g = N.default_options()
+        s.precision = {"fp64": N.OTM_FP64, "mixed": N.OTM_MIXED}[precision]
+        s.guess = {"zero": N.OTM_GUESS_ZERO, "previous": N.OTM_GUESS_PREVIOUS, "user": N.OTM_GUESS_USER}[guess]
+        s.tol, s.max_iter, s.check_every, s.reliable_delta = float(tol), int(max_iter), int(check_every), float(reliable_delta)
+        s.kernel_variant, s.tile_tz = int(kernel_variant), int(tile_tz)
+        o.move, o.eta, o.rho_min = float(move), float(eta), float(rho_min)
+        for key, val in (governor or {}).items():
+            setattr(g, key, val)
+        self.problem, self.solver, self.oc, self.gov = p, s, o, g
+        h = ctypes.c_void_p()
+        st = ctypes.c_void_p(int(stream)) if stream is not None else None
+        N.check(L.otm_create(ctypes.byref(p), ctypes.byref(s), ctypes.byref(o), ctypes.byref(g), st,
+                             ctypes.byref(h)))
+        self._h = h
+        self._L = L
+
+    # -- lifetime
+    def close(self):
+        if getattr(self, "_h", None):
+            self._L.otm_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def _chk(self, status, allow_nc=True):
+        return N.check(status, self._h, allow_nc)
+
+    @property
+    def nn(self) -> int:
+        return self.n ** 3
+
+    # -- inputs
+    def set_density(self, rho) -> None:
+        try:
+            import torch
+            if isinstance(rho, torch.Tensor) and rho.is_cuda:
+                if rho.dtype != torch.float64 or not rho.is_contiguous():
+                    raise ValueError("device density must be a contiguous float64 tensor")
+                self._chk(self._L.otm_set_density_device(self._h, ctypes.c_void_p(rho.data_ptr()), rho.numel()))
+                return
+        except ImportError:
+            pass
+        a = _f64(rho).reshape(-1)
+        self._chk(self._L.otm_set_density(self._h, _ptr(a), a.size))
+
+    def set_guess(self, chi) -> None:
+        a = _f64(chi).reshape(-1)
+        self._chk(self._L.otm_set_guess(self._h, _ptr(a), a.size))
+
+    # -- the hot path, one piece at a time
+    def prepare(self) -> None:
+        self._chk(self._L.otm_prepare(self._h))
+
+    def homogenize(self):
+        kappa = np.zeros(6)
+        st = N.SolveStats()
+        status = self._chk(self._L.otm_homogenize(self._h, _ptr(kappa), ctypes.byref(st)))
+        return kappa, dict(iterations=list(st.iterations), rel_residual=list(st.rel_residual),
+                           converged=bool(st.converged), refreshes=st.refreshes, ms_solve=st.ms_solve,
+                           status=status)
+
+    def sensitivity(self, dg_dkappa) -> np.ndarray:
+        w = _f64(dg_dkappa)
+        out = np.empty(self.nn)
+        self._chk(self._L.otm_sensitivity(self._h, _ptr(w), _ptr(out)))
+        return out.reshape((self.n,) * 3)
+
+    def oc_update(self, vstar: float):
+        out = np.empty(self.nn)
+        lam = ctypes.c_double()
+        self._chk(self._L.otm_oc_update(self._h, float(vstar), _ptr(out), ctypes.byref(lam)))
+        return out.reshape((self.n,) * 3), lam.value
+
+    def step(self) -> Dict[str, object]:
+        r = N.IterRecord()
+        self._chk(self._L.otm_step(self._h, ctypes.byref(r)))
+        return r.to_dict()
+
+    def optimize(self, max_iter: int):
+        out = np.empty(self.nn)
+        log = (N.IterRecord * max(1, max_iter))()
+        done = ctypes.c_int32()
+        self._chk(self._L.otm_optimize(self._h, int(max_iter), _ptr(out), log, max(1, max_iter), ctypes.byref(done)))
+        return out.reshape((self.n,) * 3), [log[i].to_dict() for i in range(done.value)]
+
+    def get_field(self, name: str) -> np.ndarray:
+        size = 3 * self.nn if name in N.FIELD3 else self.nn
+        out = np.empty(size)
+        self._chk(self._L.otm_get_field(self._h, N.FIELDS[name], _ptr(out), size))
+        shape = (3, self.n, self.n, self.n) if name in N.FIELD3 else (self.n,) * 3
+        return out.reshape(shape)
+
+    def set_field(self, name: str, values) -> None:
+        a = _f64(values).reshape(-1)
+        self._chk(self._L.otm_set_field(self._h, N.FIELDS[name], _ptr(a), a.size))
+
+    def apply(self, x, precision: str = "fp64") -> np.ndarray:
+        a = _f64(x).reshape(-1)
+        if a.size != 3 * self.nn:
+            raise ValueError("x must hold 3 n^3 values")
+        y = np.empty_like(a)
+        self._chk(self._L.otm_apply(self._h, {"fp64": N.OTM_FP64, "mixed": N.OTM_MIXED}[precision], _ptr(a), _ptr(y)))
+        return y.reshape(3, self.n, self.n, self.n)
+
+    def timings(self) -> List[float]:
+        t = np.zeros(8)
+        self._chk(self._L.otm_get_timings(self._h, _ptr(t)))
+        return t.tolist()
+
+    # -- governor state, checkpoint / resume
+    def governor_state(self) -> List[float]:
+        s = np.zeros(8)
+        self._chk(self._L.otm_get_governor(self._h, _ptr(s)))
+        return s.tolist()
+
+    def set_governor_state(self, s: Sequence[float]) -> None:
+        a = _f64(s)
+        self._chk(self._L.otm_set_governor(self._h, _ptr(a)))
+
+    def save_state(self, path: str) -> None:
+        """Checkpoint: density, previous solution (warm start) and governor state."""
+        np.savez(path, rho=self.get_field("rho"), chi=self.get_field("chi"),
+                 governor=np.array(self.governor_state()))
+
+    def load_state(self, path: str) -> None:
+        d = np.load(path, allow_pickle=False)
+        self.set_density(d["rho"])
+        self.set_governor_state(d["governor"])
+        if self.solver.guess != N.OTM_GUESS_ZERO:
+            self.set_guess(d["chi"])
+
+
+def apply_device(k, x, y, precision: str = "fp64", stream=None, variant: int = 0) -> None:
+    """y = A x on caller device memory (torch CUDA tensors, load-major 3 n^3)."""
+    import torch
+    n = round(k.numel() ** (1.0 / 3.0))
+    if n ** 3 != k.numel() or x.numel() != 3 * n ** 3 or y.numel() != 3 * n ** 3:
+        raise ValueError("shape mismatch")
+    want = torch.float64 if precision == "fp64" else torch.float32
+    for t in (k, x, y):
+        if t.dtype != want or not t.is_cuda or not t.is_contiguous():
+            raise ValueError("tensors must be contiguous CUDA tensors of the precision's dtype")
+    s = stream if stream is not None else torch.cuda.current_stream().cuda_stream
+    N.check(N.lib().otm_apply_device(n, N.OTM_FP64 if precision == "fp64" else N.OTM_MIXED, int(variant),
+                                     ctypes.c_void_p(k.data_ptr()), ctypes.c_void_p(x.data_ptr()),
+                                     ctypes.c_void_p(y.data_ptr()), ctypes.c_void_p(s)))
+
+
+def time_apply_device(k, x, y, precision: str = "fp64", reps: int = 50, stream=None, variant: int = 0) -> float:
+    import torch
+    n = round(k.numel() ** (1.0 / 3.0))
+    s = stream if stream is not None else torch.cuda.current_stream().cuda_stream
+    us = ctypes.c_double()
+    N.check(N.lib().otm_time_apply_device(n, N.OTM_FP64 if precision == "fp64" else N.OTM_MIXED, int(variant),
+                                          ctypes.c_void_p(k.data_ptr()), ctypes.c_void_p(x.data_ptr()),
+                                          ctypes.c_void_p(y.data_ptr()), ctypes.c_void_p(s), int(reps),
+                                          ctypes.byref(us)))
+    return us.value
+
+
+def run_instance(reso: int, heat_ratio: Sequence[float], target: Sequence[float], rho0=None, vf: float = 0.3,
+                 max_iter: int = 500, **kw):
+    """Design one structure: mirrors the paper's runInstance(reso, heatRatio,
+    target, init, model) for the adaptive-volume model with OC.  The initial
+    density defaults to vf everywhere (caller-provided otherwise)."""
+    with Homogenization(reso, heat_ratio, target, vf=vf, **kw) as h:
+        h.set_density(np.full((reso,) * 3, vf) if rho0 is None else rho0)
+        rho, log = h.optimize(max_iter)
+    return rho, log
+
+
+def version() -> str:
+    return N.lib().otm_version().decode()
+
+
+def dumps_log(log) -> str:
+    return "\n".join(json.dumps(r) for r in log)

@@ -1,0 +1,163 @@
+// Device-side helpers shared by the kernel translation units: periodic
+// wrap, deterministic block reductions with a last-block epilogue, and the
+// node-centric hex-8 conduction stencil.
+#pragma once
+
+#include "otm_internal.h"
+
+namespace otm {
+
+__device__ __forceinline__ int wrapi(int a, int n) { return a < 0 ? a + n : (a >= n ? a - n : a); }
+
+template <int NV>
+__device__ __forceinline__ void wave_reduce(double (&v)[NV]) {
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+#pragma unroll
+        for (int off = 32; off > 0; off >>= 1) v[i] += __shfl_xor(v[i], off, 64);
+    }
+}
+
+// Block-level sum of NV values; thread 0..NV-1 write partials[blockIdx*NV + t].
+// Uses a fixed reduction order (deterministic for a fixed launch shape).
+template <int NV>
+__device__ __forceinline__ void block_partials(double (&v)[NV], double* partials) {
+    __shared__ double sh[NV][kBlock / 64];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, w = tid >> 6;
+    wave_reduce<NV>(v);
+    if (lane == 0) {
+#pragma unroll
+        for (int i = 0; i < NV; ++i) sh[i][w] = v[i];
+    }
+    __syncthreads();
+    if (tid < NV) {
+        double s = 0.0;
+#pragma unroll
+        for (int j = 0; j < kBlock / 64; ++j) s += sh[tid][j];
+        partials[(size_t)blockIdx.x * NV + tid] = s;
+    }
+}
+
+// Sum the partial arrays of all blocks (fixed order) -> out[NV] in shared memory.
+template <int NV>
+__device__ __forceinline__ void final_sums(const double* partials, int nblocks, double* out /* shared */) {
+    double v[NV];
+#pragma unroll
+    for (int i = 0; i < NV; ++i) v[i] = 0.0;
+    for (int b = threadIdx.x; b < nblocks; b += blockDim.x) {
+#pragma unroll
+        for (int i = 0; i < NV; ++i) v[i] += partials[(size_t)b * NV + i];
+    }
+    __shared__ double sh[NV][kBlock / 64];
+    wave_reduce<NV>(v);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) {
+#pragma unroll
+        for (int i = 0; i < NV; ++i) sh[i][w] = v[i];
+    }
+    __syncthreads();
+    if (threadIdx.x < NV) {
+        double s = 0.0;
+#pragma unroll
+        for (int j = 0; j < kBlock / 64; ++j) s += sh[threadIdx.x][j];
+        out[threadIdx.x] = s;
+    }
+    __syncthreads();
+}
+
+static inline int nblocks_for(int64_t count) { return (int)((count + kBlock - 1) / kBlock); }
+
+// Clamp grid size for grid-stride reductions so partial arrays stay small.
+static inline int grid_for(int64_t count, int max_blocks) {
+    int g = nblocks_for(count);
+    return g > max_blocks ? max_blocks : g;
+}
+
+// ---------------------------------------------------------------- stencil
+// Gather the 8 incident element conductivities of node (i,j,k) and the
+// 21 non-zero stencil coefficients, then y = sum coef * x for each load.
+template <typename T>
+struct NodeCoef {
+    T c0;       // centre
+    T ce[12];   // edge-diagonal neighbours
+    T cc[8];    // corners
+};
+
+template <typename T>
+__device__ __forceinline__ void node_coefs(const T (&ko)[8], NodeCoef<T>& c) {
+    const T w = (T)(1.0 / 12.0);
+    T tot = 0;
+#pragma unroll
+    for (int o = 0; o < 8; ++o) tot += ko[o];
+    c.c0 = tot * (T)(1.0 / 3.0);
+    // edges in the xy plane: (dx,dy) in {-,+}^2, shared elements c' = 0,1
+    int q = 0;
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int a = 0; a < 2; ++a) c.ce[q++] = -w * (ko[a + 2 * b] + ko[a + 2 * b + 4]);
+    // edges in the xz plane: (dx,dz), shared b' = 0,1
+#pragma unroll
+    for (int cz = 0; cz < 2; ++cz)
+#pragma unroll
+        for (int a = 0; a < 2; ++a) c.ce[q++] = -w * (ko[a + 4 * cz] + ko[a + 2 + 4 * cz]);
+    // edges in the yz plane: (dy,dz), shared a' = 0,1
+#pragma unroll
+    for (int cz = 0; cz < 2; ++cz)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) c.ce[q++] = -w * (ko[2 * b + 4 * cz] + ko[1 + 2 * b + 4 * cz]);
+#pragma unroll
+    for (int o = 0; o < 8; ++o) c.cc[o] = -w * ko[o];
+}
+
+// Offsets of the 3x3x3 neighbourhood of node (i,j,k).
+struct Nbr {
+    int x[3], y[3], z[3];
+};
+
+__device__ __forceinline__ Nbr nbr_of(int i, int j, int k, int n) {
+    Nbr o;
+    o.x[0] = wrapi(i - 1, n);
+    o.x[1] = i;
+    o.x[2] = wrapi(i + 1, n);
+    o.y[0] = wrapi(j - 1, n) * n;
+    o.y[1] = j * n;
+    o.y[2] = wrapi(j + 1, n) * n;
+    const int nn2 = n * n;
+    o.z[0] = wrapi(k - 1, n) * nn2;
+    o.z[1] = k * nn2;
+    o.z[2] = wrapi(k + 1, n) * nn2;
+    return o;
+}
+
+template <typename T>
+__device__ __forceinline__ void load_k8(const T* __restrict__ k, const Nbr& o, T (&ko)[8]) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) ko[q] = k[o.x[q & 1] + o.y[(q >> 1) & 1] + o.z[(q >> 2) & 1]];
+}
+
+// y = A x at one node for one load (x is the load's base pointer).
+template <typename T, typename TX>
+__device__ __forceinline__ T stencil_node(const NodeCoef<T>& c, const Nbr& o, const TX* __restrict__ x) {
+    // a' index (0 or 1) maps to offset -1 / +1 -> Nbr index 0 / 2
+    T y = c.c0 * (T)x[o.x[1] + o.y[1] + o.z[1]];
+    int q = 0;
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int a = 0; a < 2; ++a) y += c.ce[q++] * (T)x[o.x[2 * a] + o.y[2 * b] + o.z[1]];
+#pragma unroll
+    for (int cz = 0; cz < 2; ++cz)
+#pragma unroll
+        for (int a = 0; a < 2; ++a) y += c.ce[q++] * (T)x[o.x[2 * a] + o.y[1] + o.z[2 * cz]];
+#pragma unroll
+    for (int cz = 0; cz < 2; ++cz)
+#pragma unroll
+        for (int b = 0; b < 2; ++b) y += c.ce[q++] * (T)x[o.x[1] + o.y[2 * b] + o.z[2 * cz]];
+#pragma unroll
+    for (int q2 = 0; q2 < 8; ++q2) y += c.cc[q2] * (T)x[o.x[2 * (q2 & 1)] + o.y[2 * ((q2 >> 1) & 1)] + o.z[2 * ((q2 >> 2) & 1)]];
+    return y;
+}
+
+}  // namespace otm

@@ -1,0 +1,927 @@
+// Host engine and C ABI of the periodic thermal homogenization library.
+//
+// One context = one design cell of n^3 voxels on the current HIP device.  All
+// per-iteration work runs in the kernels of otm_kernels.hip on the context's
+// stream; the host only sequences launches, reads back a few scalars (PCG
+// convergence flags, the 6-vector tensor, reduction sums) and runs the scalar
+// logic of the adaptive volume governor (Algorithm 1) and the objective.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <cmath>
+#include <cstddef>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+
+#include "opentm_amd.h"
+#include "otm_internal.h"
+
+using namespace otm;
+
+#define OTM_VERSION "opentm-amd 0.1 (gfx950)"
+
+struct otm_ctx {
+    otm_problem prob;
+    otm_solver_opts so;
+    otm_oc_opts oc;
+    otm_governor_opts go;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    int device = 0;
+    int n = 0;
+    int64_t nn = 0;
+
+    // fields (float64)
+    double* rho = nullptr;
+    double* rhof = nullptr;
+    double* k = nullptr;
+    double* dinv = nullptr;
+    double* b = nullptr;    // 3 nn
+    double* x = nullptr;    // 3 nn, solution chi
+    double* st = nullptr;   // element sensitivity before the filter transpose
+    double* sens = nullptr; // after
+    double* ocq = nullptr;  // OC numerator q_e
+    // FP64 Krylov vectors
+    double* r64 = nullptr;
+    double* p64[2] = {nullptr, nullptr};
+    double* q64 = nullptr;
+    // mixed-precision Krylov vectors
+    float* k32 = nullptr;
+    float* dinv32 = nullptr;
+    float* x32 = nullptr;
+    float* r32 = nullptr;
+    float* p32[2] = {nullptr, nullptr};
+    float* q32 = nullptr;
+
+    double* partials = nullptr;
+    unsigned* counter = nullptr;
+    Scalars* sc = nullptr;
+    Scalars* h_sc = nullptr;  // pinned host mirror
+    int max_blocks = 0;
+    int pbuf = 0;
+    TileShape tile;
+
+    bool have_density = false;
+    bool prepared = false;
+    bool homogenized = false;
+    bool have_sens = false;
+    bool have_solution = false;
+    bool have_user_guess = false;
+
+    double kappa[6] = {0, 0, 0, 0, 0, 0};
+    double g = 0.0;
+    double w[6] = {0, 0, 0, 0, 0, 0};
+    double volume = 0.0, low_bound = 0.0;
+
+    // governor (Algorithm 1)
+    double vstar = 1.0, df = 1.0, gap = 0.0, g_prev = 1.0;
+    int count = 0, small_steps = 0, iter = 0;
+
+    otm_solve_stats last_stats{};
+    double timings[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    hipEvent_t ev[8] = {};
+    std::string err;
+
+    Workspace ws() const { return Workspace{partials, counter, sc, max_blocks}; }
+};
+
+namespace {
+
+int fail(otm_ctx* c, int code, const std::string& msg) {
+    if (c) c->err = msg;
+    return code;
+}
+
+#define HIPCHK(c, call)                                                                              \
+    do {                                                                                             \
+        hipError_t e_ = (call);                                                                      \
+        if (e_ != hipSuccess) {                                                                      \
+            return fail((c), OTM_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_));        \
+        }                                                                                            \
+    } while (0)
+
+int check_launch(otm_ctx* c, const char* what) {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return fail(c, OTM_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+    return OTM_OK;
+}
+
+template <typename T>
+int dalloc(otm_ctx* c, T** p, int64_t count) {
+    if (hipMalloc((void**)p, (size_t)count * sizeof(T)) != hipSuccess) {
+        *p = nullptr;
+        (void)hipGetLastError();
+        return fail(c, OTM_ENOMEM, "device allocation of " + std::to_string((long long)count * sizeof(T)) + " bytes failed");
+    }
+    return OTM_OK;
+}
+
+bool finite6(const double* v) {
+    for (int i = 0; i < 6; ++i)
+        if (!std::isfinite(v[i])) return false;
+    return true;
+}
+
+int sync_scalars(otm_ctx* c) {
+    HIPCHK(c, hipMemcpyAsync(c->h_sc, c->sc, sizeof(Scalars), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return OTM_OK;
+}
+
+int validate_problem(const otm_problem* p, std::string& why) {
+    if (!p) {
+        why = "problem is NULL";
+        return OTM_EINVAL;
+    }
+    if (p->n < 4 || p->n > 1024) {
+        why = "n must be in [4, 1024]";
+        return OTM_EINVAL;
+    }
+    if (!(std::isfinite(p->k0) && std::isfinite(p->kmin) && p->kmin > 0.0 && p->k0 > p->kmin)) {
+        why = "need 0 < kmin < k0, finite";
+        return OTM_EINVAL;
+    }
+    if (!(std::isfinite(p->penal) && p->penal >= 1.0)) {
+        why = "penal must be >= 1";
+        return OTM_EINVAL;
+    }
+    if (!(std::isfinite(p->filter_radius) && p->filter_radius < 5.0)) {
+        why = "filter_radius must be finite and < 5";
+        return OTM_EINVAL;
+    }
+    if (!(std::isfinite(p->vf) && p->vf > 0.0 && p->vf <= 1.0)) {
+        why = "vf must be in (0, 1]";
+        return OTM_EINVAL;
+    }
+    if (!finite6(p->target)) {
+        why = "target must be finite";
+        return OTM_EINVAL;
+    }
+    if (p->objective != OTM_OBJ_MSE) {
+        why = "unsupported objective";
+        return OTM_EUNSUPPORTED;
+    }
+    return OTM_OK;
+}
+
+// ------------------------------------------------------------------ timing
+struct EvTimer {
+    otm_ctx* c;
+    int a, b;
+    EvTimer(otm_ctx* c_, int a_, int b_) : c(c_), a(a_), b(b_) { (void)hipEventRecord(c->ev[a], c->stream); }
+    void stop() { (void)hipEventRecord(c->ev[b], c->stream); }
+};
+
+double ev_ms(otm_ctx* c, int a, int b) {
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, c->ev[a], c->ev[b]) != hipSuccess) {
+        (void)hipGetLastError();
+        return 0.0;
+    }
+    return (double)ms;
+}
+
+// ------------------------------------------------------------------ prepare
+// filter + SIMP + macro loads + diagonal, b projected to zero mean
+int prepare(otm_ctx* c) {
+    if (!c->have_density) return fail(c, OTM_ESTATE, "no density set");
+    const Workspace w = c->ws();
+    launch_filter_simp(c->n, c->prob.filter_radius, c->rho, c->rhof, c->k, c->k32, c->prob.k0, c->prob.kmin,
+                       c->prob.penal, w, c->stream);
+    launch_setup_nodes(c->n, c->k, c->b, c->dinv, c->dinv32, w, c->stream);
+    launch_sub_mean3(c->n, c->b, 1, w, c->stream);
+    int rc = check_launch(c, "prepare");
+    if (rc) return rc;
+    c->prepared = true;
+    return OTM_OK;
+}
+
+// ------------------------------------------------------------------ PCG
+bool all_inactive(const Scalars* s) { return !s->active[0] && !s->active[1] && !s->active[2]; }
+int max_iters(const Scalars* s) {
+    int m = s->iters[0];
+    if (s->iters[1] > m) m = s->iters[1];
+    if (s->iters[2] > m) m = s->iters[2];
+    return m;
+}
+
+// Reset the solver part of the scalar block (the fields before sum_rho) and
+// set tol^2; the reduction results of prepare() that follow are left intact.
+int reset_solver_scalars(otm_ctx* c) {
+    const size_t head = offsetof(Scalars, sum_rho);
+    std::memset(c->h_sc, 0, head);
+    c->h_sc->tol2 = c->so.tol * c->so.tol;
+    HIPCHK(c, hipMemcpyAsync(c->sc, c->h_sc, head, hipMemcpyHostToDevice, c->stream));
+    return OTM_OK;
+}
+
+int solve_fp64(otm_ctx* c, bool x_zero, otm_solve_stats* st) {
+    const Workspace w = c->ws();
+    const int n = c->n;
+    int rc;
+    if ((rc = reset_solver_scalars(c))) return rc;
+    if (x_zero) HIPCHK(c, hipMemsetAsync(c->x, 0, (size_t)3 * c->nn * sizeof(double), c->stream));
+    launch_residual<double>(n, c->k, c->b, c->x, c->r64, c->p64[c->pbuf], c->dinv, RES_START, x_zero ? 1 : 0, w,
+                            c->stream);
+    if ((rc = check_launch(c, "residual"))) return rc;
+    if ((rc = sync_scalars(c))) return rc;
+    int launches = 0;
+    while (!all_inactive(c->h_sc) && max_iters(c->h_sc) < c->so.max_iter) {
+        for (int it = 0; it < c->so.check_every; ++it) {
+            double* po = c->p64[c->pbuf];
+            double* pn = c->p64[c->pbuf ^ 1];
+            if (c->so.kernel_variant == 1) {
+                launch_dir<double>(n, c->r64, c->dinv, po, pn, w, c->stream);
+                launch_apply_pq<double>(n, c->k, pn, c->q64, w, c->stream);
+                launch_update<double>(n, c->x, c->r64, pn, c->q64, c->dinv, w, c->stream);
+            } else {
+                launch_dir_apply<double>(n, c->tile, c->r64, c->dinv, po, pn, c->k, c->q64, w, c->stream);
+                launch_update_vec<double>(n, c->x, c->r64, pn, c->q64, c->dinv, w, c->stream);
+            }
+            c->pbuf ^= 1;
+            ++launches;
+        }
+        if ((rc = check_launch(c, "pcg"))) return rc;
+        if ((rc = sync_scalars(c))) return rc;
+        if (all_inactive(c->h_sc)) {
+            // confirm with the true residual; loads that fail restart
+            launch_residual<double>(n, c->k, c->b, c->x, c->r64, c->p64[c->pbuf], c->dinv, RES_START, 0, w,
+                                    c->stream);
+            if ((rc = sync_scalars(c))) return rc;
+        }
+    }
+    launch_sum3(n, c->x, 0, w, c->stream);
+    launch_sub_mean3(n, c->x, 0, w, c->stream);
+    if ((rc = check_launch(c, "project"))) return rc;
+    if ((rc = sync_scalars(c))) return rc;
+    int conv = all_inactive(c->h_sc) ? 1 : 0;
+    for (int l = 0; l < 3; ++l) {
+        st->iterations[l] = c->h_sc->iters[l];
+        st->rel_residual[l] = c->h_sc->bb[l] > 0.0 ? std::sqrt(c->h_sc->rr_true[l] / c->h_sc->bb[l]) : 0.0;
+    }
+    st->converged = conv;
+    st->refreshes = 0;
+    c->timings[7] = (double)launches;
+    return OTM_OK;
+}
+
+int solve_mixed(otm_ctx* c, bool x_zero, otm_solve_stats* st) {
+    const Workspace w = c->ws();
+    const int n = c->n;
+    int rc;
+    if ((rc = reset_solver_scalars(c))) return rc;
+    if (x_zero) HIPCHK(c, hipMemsetAsync(c->x, 0, (size_t)3 * c->nn * sizeof(double), c->stream));
+    HIPCHK(c, hipMemsetAsync(c->x32, 0, (size_t)3 * c->nn * sizeof(float), c->stream));
+    launch_residual<float>(n, c->k, c->b, c->x, c->r32, c->p32[c->pbuf], c->dinv32, RES_START, x_zero ? 1 : 0, w,
+                           c->stream);
+    if ((rc = check_launch(c, "residual"))) return rc;
+    if ((rc = sync_scalars(c))) return rc;
+    double rr_ref[3] = {c->h_sc->rr_true[0], c->h_sc->rr_true[1], c->h_sc->rr_true[2]};
+    const double d2 = c->so.reliable_delta * c->so.reliable_delta;
+    int refreshes = 0, launches = 0;
+    while (!all_inactive(c->h_sc) && max_iters(c->h_sc) < c->so.max_iter) {
+        for (int it = 0; it < c->so.check_every; ++it) {
+            float* po = c->p32[c->pbuf];
+            float* pn = c->p32[c->pbuf ^ 1];
+            if (c->so.kernel_variant == 1) {
+                launch_dir<float>(n, c->r32, c->dinv32, po, pn, w, c->stream);
+                launch_apply_pq<float>(n, c->k32, pn, c->q32, w, c->stream);
+                launch_update<float>(n, c->x32, c->r32, pn, c->q32, c->dinv32, w, c->stream);
+            } else {
+                launch_dir_apply<float>(n, c->tile, c->r32, c->dinv32, po, pn, c->k32, c->q32, w, c->stream);
+                launch_update_vec<float>(n, c->x32, c->r32, pn, c->q32, c->dinv32, w, c->stream);
+            }
+            c->pbuf ^= 1;
+            ++launches;
+        }
+        if ((rc = check_launch(c, "pcg32"))) return rc;
+        if ((rc = sync_scalars(c))) return rc;
+        bool refresh = all_inactive(c->h_sc);
+        for (int l = 0; l < 3; ++l)
+            if (c->h_sc->active[l] && c->h_sc->rr[l] < d2 * rr_ref[l]) refresh = true;
+        if (refresh) {
+            launch_accumulate(n, c->x, c->x32, c->stream);
+            launch_residual<float>(n, c->k, c->b, c->x, c->r32, c->p32[c->pbuf], c->dinv32, RES_REFRESH, 0, w,
+                                   c->stream);
+            if ((rc = check_launch(c, "refresh"))) return rc;
+            if ((rc = sync_scalars(c))) return rc;
+            for (int l = 0; l < 3; ++l) rr_ref[l] = c->h_sc->rr_true[l];
+            ++refreshes;
+        }
+    }
+    // fold any remaining float32 increment into the float64 solution
+    launch_accumulate(n, c->x, c->x32, c->stream);
+    launch_sum3(n, c->x, 0, w, c->stream);
+    launch_sub_mean3(n, c->x, 0, w, c->stream);
+    if ((rc = check_launch(c, "project"))) return rc;
+    if ((rc = sync_scalars(c))) return rc;
+    for (int l = 0; l < 3; ++l) {
+        st->iterations[l] = c->h_sc->iters[l];
+        st->rel_residual[l] = c->h_sc->bb[l] > 0.0 ? std::sqrt(c->h_sc->rr_true[l] / c->h_sc->bb[l]) : 0.0;
+    }
+    st->converged = all_inactive(c->h_sc) ? 1 : 0;
+    st->refreshes = refreshes;
+    c->timings[7] = (double)launches;
+    return OTM_OK;
+}
+
+int homogenize(otm_ctx* c, double kappa6[6], otm_solve_stats* st_out) {
+    int rc;
+    EvTimer t0(c, 0, 1);
+    if ((rc = prepare(c))) return rc;
+    t0.stop();
+    bool x_zero = true;
+    if (c->so.guess == OTM_GUESS_PREVIOUS && c->have_solution) x_zero = false;
+    if (c->so.guess == OTM_GUESS_USER && c->have_user_guess) x_zero = false;
+    otm_solve_stats st{};
+    (void)hipEventRecord(c->ev[2], c->stream);
+    auto t_start = std::chrono::steady_clock::now();
+    rc = (c->so.precision == OTM_MIXED) ? solve_mixed(c, x_zero, &st) : solve_fp64(c, x_zero, &st);
+    if (rc) return rc;
+    (void)hipEventRecord(c->ev[3], c->stream);
+    auto t_end = std::chrono::steady_clock::now();
+    st.ms_solve = std::chrono::duration<double, std::milli>(t_end - t_start).count();
+    c->have_solution = true;
+    c->have_user_guess = false;
+    const Workspace w = c->ws();
+    launch_energy(c->n, c->k, c->x, w, c->stream);
+    if ((rc = check_launch(c, "energy"))) return rc;
+    (void)hipEventRecord(c->ev[4], c->stream);
+    if ((rc = sync_scalars(c))) return rc;
+    for (int q = 0; q < 6; ++q) c->kappa[q] = c->h_sc->kappa_sum[q] / (double)c->nn;
+    c->volume = c->h_sc->sum_rho / (double)c->nn;
+    c->low_bound = c->h_sc->sum_rhofp / (double)c->nn;
+    c->timings[0] = ev_ms(c, 0, 1);
+    c->timings[1] = ev_ms(c, 2, 3);
+    c->timings[2] = ev_ms(c, 3, 4);
+    if (!finite6(c->kappa)) return fail(c, OTM_ENONFINITE, "non-finite homogenized tensor");
+    if (kappa6) std::memcpy(kappa6, c->kappa, sizeof(c->kappa));
+    c->last_stats = st;
+    if (st_out) *st_out = st;
+    c->homogenized = true;
+    c->have_sens = false;
+    return st.converged ? OTM_OK : OTM_NOT_CONVERGED;
+}
+
+int sensitivity(otm_ctx* c, const double w6[6]) {
+    if (!c->homogenized) return fail(c, OTM_ESTATE, "sensitivity needs a prior homogenize");
+    if (!finite6(w6)) return fail(c, OTM_ENONFINITE, "non-finite dg/dkappa");
+    (void)hipEventRecord(c->ev[4], c->stream);
+    launch_sens(c->n, c->rhof, c->x, w6, c->prob.k0, c->prob.kmin, c->prob.penal, c->st, c->stream);
+    launch_filter(c->n, c->prob.filter_radius, c->st, c->sens, c->stream);
+    (void)hipEventRecord(c->ev[5], c->stream);
+    int rc = check_launch(c, "sensitivity");
+    if (rc) return rc;
+    c->have_sens = true;
+    return OTM_OK;
+}
+
+int oc_update(otm_ctx* c, double vstar, double* lambda_out) {
+    if (!c->have_sens) return fail(c, OTM_ESTATE, "OC update needs sensitivities");
+    if (!std::isfinite(vstar)) return fail(c, OTM_EINVAL, "non-finite V*");
+    const Workspace w = c->ws();
+    const int n = c->n;
+    (void)hipEventRecord(c->ev[5], c->stream);
+    launch_oc_prepare(n, c->rho, c->sens, c->oc.eta, c->ocq, c->stream);
+    launch_oc_init(vstar, n, c->oc.eta, w, c->stream);
+    const int max_passes = 200 / kOcLevels + 2;
+    int rc;
+    for (int pass = 0; pass < max_passes; pass += 4) {
+        for (int q = 0; q < 4; ++q) launch_oc_pass(n, c->rho, c->ocq, c->oc.move, c->oc.rho_min, c->oc.eta, w, c->stream);
+        if ((rc = check_launch(c, "oc pass"))) return rc;
+        if ((rc = sync_scalars(c))) return rc;
+        if (c->h_sc->oc_done) break;
+    }
+    launch_oc_apply(n, c->rho, c->ocq, c->oc.eta, c->oc.move, c->oc.rho_min, w, c->stream);
+    (void)hipEventRecord(c->ev[6], c->stream);
+    if ((rc = check_launch(c, "oc apply"))) return rc;
+    if ((rc = sync_scalars(c))) return rc;
+    c->timings[4] = ev_ms(c, 5, 6);
+    if (lambda_out) *lambda_out = c->h_sc->lam;
+    c->homogenized = false;
+    c->have_sens = false;
+    c->prepared = false;
+    return OTM_OK;
+}
+
+// Algorithm 1 (adaptive V*), one call per design iteration.
+double governor_update(otm_ctx* c, double g, double low, double vol) {
+    const otm_governor_opts& go = c->go;
+    if (g <= go.bound) {
+        c->gap = c->vstar - low;
+        c->vstar = c->vstar - c->gap * c->df;
+        c->df = go.decay * c->df;
+    }
+    const bool little = std::fabs(c->g_prev - g) < go.dg_small;
+    const bool big = g > go.bound;
+    const bool at_bound = std::fabs(vol - c->vstar) < go.dv_small;
+    if (little && big && at_bound)
+        c->count += 1;
+    else
+        c->count = 0;
+    if (c->count >= go.patience) {
+        c->vstar = c->vstar + go.rebound * c->gap * c->df;
+        c->count = 0;
+    }
+    if (c->vstar > 1.0) c->vstar = 1.0;
+    if (c->vstar < c->oc.rho_min) c->vstar = c->oc.rho_min;
+    if (std::fabs(c->g_prev - g) < go.g_tol)
+        c->small_steps += 1;
+    else
+        c->small_steps = 0;
+    c->g_prev = g;
+    return c->vstar;
+}
+
+void objective(const double* kappa, const double* target, double* g, double* w6) {
+    double s = 0.0;
+    for (int q = 0; q < 6; ++q) {
+        const double d = kappa[q] - target[q];
+        s += d * d;
+        w6[q] = 2.0 * d;
+    }
+    *g = s;
+}
+
+int free_all(otm_ctx* c) {
+    void* bufs[] = {c->rho, c->rhof, c->k, c->dinv, c->b, c->x, c->st, c->sens, c->ocq, c->r64, c->p64[0], c->p64[1],
+                    c->q64, c->k32, c->dinv32, c->x32, c->r32, c->p32[0], c->p32[1], c->q32, c->partials, c->counter,
+                    c->sc};
+    for (void* p : bufs)
+        if (p) (void)hipFree(p);
+    if (c->h_sc) (void)hipHostFree(c->h_sc);
+    for (auto& e : c->ev)
+        if (e) (void)hipEventDestroy(e);
+    if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+    return 0;
+}
+
+}  // namespace
+
+// ======================================================================= ABI
+extern "C" {
+
+void otm_default_options(otm_solver_opts* s, otm_oc_opts* o, otm_governor_opts* g) {
+    if (s) {
+        s->precision = OTM_FP64;
+        s->guess = OTM_GUESS_ZERO;
+        s->tol = 1e-8;
+        s->max_iter = 20000;
+        s->check_every = 16;
+        s->reliable_delta = 1e-2;
+        s->kernel_variant = 0;
+        s->tile_tz = 0;
+    }
+    if (o) {
+        o->move = 0.05;
+        o->eta = 0.5;
+        o->rho_min = 1e-3;
+    }
+    if (g) {
+        g->bound = 1e-4;
+        g->dg_small = 1e-6;
+        g->dv_small = 1e-3;
+        g->decay = 0.8;
+        g->rebound = 0.3;
+        g->g_tol = 1e-6;
+        g->patience = 5;
+        g->stall_iters = 3;
+    }
+}
+
+const char* otm_version(void) { return OTM_VERSION; }
+
+const char* otm_strerror(int s) {
+    switch (s) {
+        case OTM_OK: return "ok";
+        case OTM_NOT_CONVERGED: return "solver did not converge (outputs filled)";
+        case OTM_EINVAL: return "invalid argument";
+        case OTM_ENOMEM: return "out of memory";
+        case OTM_EDEVICE: return "HIP device error";
+        case OTM_ENONFINITE: return "non-finite value";
+        case OTM_EUNSUPPORTED: return "unsupported";
+        case OTM_ESTATE: return "call order violated";
+        default: return "unknown status";
+    }
+}
+
+const char* otm_last_error(const otm_ctx* c) { return c ? c->err.c_str() : "null context"; }
+
+int otm_create(const otm_problem* problem, const otm_solver_opts* solver, const otm_oc_opts* oc,
+               const otm_governor_opts* gov, void* stream, otm_ctx** out) {
+    if (!out) return OTM_EINVAL;
+    *out = nullptr;
+    std::string why;
+    int rc = validate_problem(problem, why);
+    if (rc) return rc;
+    otm_ctx* c = new (std::nothrow) otm_ctx();
+    if (!c) return OTM_ENOMEM;
+    c->prob = *problem;
+    otm_default_options(&c->so, &c->oc, &c->go);
+    if (solver) c->so = *solver;
+    if (oc) c->oc = *oc;
+    if (gov) c->go = *gov;
+    if (!(c->so.tol > 0.0 && c->so.max_iter > 0 && c->so.check_every >= 1 && c->so.reliable_delta > 0.0 &&
+          c->so.reliable_delta < 1.0 && (c->so.precision == OTM_FP64 || c->so.precision == OTM_MIXED) &&
+          c->so.guess >= OTM_GUESS_ZERO && c->so.guess <= OTM_GUESS_USER &&
+          (c->so.kernel_variant == 0 || c->so.kernel_variant == 1) && c->so.tile_tz >= 0)) {
+        delete c;
+        return OTM_EINVAL;
+    }
+    if (!(c->oc.move > 0.0 && c->oc.eta > 0.0 && c->oc.rho_min > 0.0 && c->oc.rho_min < 1.0)) {
+        delete c;
+        return OTM_EINVAL;
+    }
+    c->n = problem->n;
+    c->nn = (int64_t)c->n * c->n * c->n;
+    // device check: this library carries gfx950 code only
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&c->device) != hipSuccess || hipGetDeviceProperties(&prop, c->device) != hipSuccess) {
+        (void)hipGetLastError();
+        delete c;
+        return OTM_EDEVICE;
+    }
+    if (std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) {
+        delete c;
+        return OTM_EDEVICE;
+    }
+    if (stream) {
+        c->stream = (hipStream_t)stream;
+    } else {
+        if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
+            delete c;
+            return OTM_EDEVICE;
+        }
+        c->own_stream = true;
+    }
+    const int64_t nn = c->nn;
+    c->max_blocks = 4096;
+    c->tile = choose_tile(c->n, c->max_blocks, c->so.tile_tz);
+    rc = OTM_OK;
+    rc = rc ? rc : dalloc(c, &c->rho, nn);
+    rc = rc ? rc : dalloc(c, &c->rhof, nn);
+    rc = rc ? rc : dalloc(c, &c->k, nn);
+    rc = rc ? rc : dalloc(c, &c->dinv, nn);
+    rc = rc ? rc : dalloc(c, &c->b, 3 * nn);
+    rc = rc ? rc : dalloc(c, &c->x, 3 * nn);
+    rc = rc ? rc : dalloc(c, &c->st, nn);
+    rc = rc ? rc : dalloc(c, &c->sens, nn);
+    rc = rc ? rc : dalloc(c, &c->ocq, nn);
+    if (c->so.precision == OTM_FP64) {
+        rc = rc ? rc : dalloc(c, &c->r64, 3 * nn);
+        rc = rc ? rc : dalloc(c, &c->p64[0], 3 * nn);
+        rc = rc ? rc : dalloc(c, &c->p64[1], 3 * nn);
+        rc = rc ? rc : dalloc(c, &c->q64, 3 * nn);
+    } else {
+        rc = rc ? rc : dalloc(c, &c->k32, nn);
+        rc = rc ? rc : dalloc(c, &c->dinv32, nn);
+        rc = rc ? rc : dalloc(c, &c->x32, 3 * nn);
+        rc = rc ? rc : dalloc(c, &c->r32, 3 * nn);
+        rc = rc ? rc : dalloc(c, &c->p32[0], 3 * nn);
+        rc = rc ? rc : dalloc(c, &c->p32[1], 3 * nn);
+        rc = rc ? rc : dalloc(c, &c->q32, 3 * nn);
+    }
+    rc = rc ? rc : dalloc(c, &c->partials, (int64_t)c->max_blocks * kMaxReduce);
+    rc = rc ? rc : dalloc(c, &c->counter, 64);
+    rc = rc ? rc : dalloc(c, &c->sc, (int64_t)sizeof(Scalars));
+    if (!rc && hipHostMalloc((void**)&c->h_sc, sizeof(Scalars), hipHostMallocDefault) != hipSuccess) rc = OTM_ENOMEM;
+    for (int q = 0; q < 8 && !rc; ++q)
+        if (hipEventCreate(&c->ev[q]) != hipSuccess) rc = OTM_EDEVICE;
+    if (rc) {
+        free_all(c);
+        delete c;
+        return rc;
+    }
+    launch_fill_u32(c->counter, 64, 0u, c->stream);
+    (void)hipMemsetAsync(c->x, 0, (size_t)3 * nn * sizeof(double), c->stream);
+    if (c->p64[0]) {
+        (void)hipMemsetAsync(c->p64[0], 0, (size_t)3 * nn * sizeof(double), c->stream);
+        (void)hipMemsetAsync(c->p64[1], 0, (size_t)3 * nn * sizeof(double), c->stream);
+    }
+    if (c->p32[0]) {
+        (void)hipMemsetAsync(c->p32[0], 0, (size_t)3 * nn * sizeof(float), c->stream);
+        (void)hipMemsetAsync(c->p32[1], 0, (size_t)3 * nn * sizeof(float), c->stream);
+        (void)hipMemsetAsync(c->x32, 0, (size_t)3 * nn * sizeof(float), c->stream);
+    }
+    if (hipStreamSynchronize(c->stream) != hipSuccess) {
+        free_all(c);
+        delete c;
+        return OTM_EDEVICE;
+    }
+    c->vstar = problem->vf;
+    *out = c;
+    return OTM_OK;
+}
+
+void otm_destroy(otm_ctx* c) {
+    if (!c) return;
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    free_all(c);
+    delete c;
+}
+
+static int set_density_common(otm_ctx* c) {
+    launch_clamp(c->n, c->rho, c->oc.rho_min, 1.0, c->stream);
+    int rc = check_launch(c, "clamp");
+    if (rc) return rc;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->have_density = true;
+    c->prepared = c->homogenized = c->have_sens = false;
+    return OTM_OK;
+}
+
+int otm_set_density(otm_ctx* c, const double* rho, int64_t count) {
+    if (!c || !rho) return OTM_EINVAL;
+    if (count != c->nn) return fail(c, OTM_EINVAL, "density count must be n^3");
+    for (int64_t e = 0; e < count; ++e)
+        if (!std::isfinite(rho[e])) return fail(c, OTM_ENONFINITE, "non-finite density value");
+    HIPCHK(c, hipMemcpyAsync(c->rho, rho, (size_t)count * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    return set_density_common(c);
+}
+
+int otm_set_density_device(otm_ctx* c, const void* rho_dev, int64_t count) {
+    if (!c || !rho_dev) return OTM_EINVAL;
+    if (count != c->nn) return fail(c, OTM_EINVAL, "density count must be n^3");
+    HIPCHK(c, hipMemcpyAsync(c->rho, rho_dev, (size_t)count * sizeof(double), hipMemcpyDeviceToDevice, c->stream));
+    return set_density_common(c);
+}
+
+int otm_prepare(otm_ctx* c) {
+    if (!c) return OTM_EINVAL;
+    int rc = prepare(c);
+    if (rc) return rc;
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return OTM_OK;
+}
+
+int otm_homogenize(otm_ctx* c, double kappa6[6], otm_solve_stats* stats) {
+    if (!c) return OTM_EINVAL;
+    return homogenize(c, kappa6, stats);
+}
+
+int otm_sensitivity(otm_ctx* c, const double dg_dkappa6[6], double* out) {
+    if (!c || !dg_dkappa6) return OTM_EINVAL;
+    int rc = sensitivity(c, dg_dkappa6);
+    if (rc) return rc;
+    if (out) HIPCHK(c, hipMemcpyAsync(out, c->sens, (size_t)c->nn * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return OTM_OK;
+}
+
+int otm_oc_update(otm_ctx* c, double vstar, double* rho_out, double* lambda_out) {
+    if (!c) return OTM_EINVAL;
+    int rc = oc_update(c, vstar, lambda_out);
+    if (rc) return rc;
+    if (rho_out) HIPCHK(c, hipMemcpyAsync(rho_out, c->rho, (size_t)c->nn * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    return OTM_OK;
+}
+
+int otm_step(otm_ctx* c, otm_iter_record* rec) {
+    if (!c) return OTM_EINVAL;
+    auto t0 = std::chrono::steady_clock::now();
+    otm_solve_stats st{};
+    int hrc = homogenize(c, nullptr, &st);
+    if (hrc < 0) return hrc;
+    double g, w6[6];
+    objective(c->kappa, c->prob.target, &g, w6);
+    c->g = g;
+    std::memcpy(c->w, w6, sizeof(w6));
+    int rc = sensitivity(c, w6);
+    if (rc) return rc;
+    const double vol = c->volume, low = c->low_bound;
+    const double vstar = governor_update(c, g, low, vol);
+    double lam = 0.0;
+    rc = oc_update(c, vstar, &lam);
+    if (rc) return rc;
+    c->timings[3] = ev_ms(c, 4, 5);
+    auto t1 = std::chrono::steady_clock::now();
+    c->timings[5] = std::chrono::duration<double, std::milli>(t1 - t0).count();
+    if (rec) {
+        rec->iter = c->iter;
+        rec->g = g;
+        std::memcpy(rec->kappa, c->kappa, sizeof(c->kappa));
+        rec->volume = vol;
+        rec->low_bound = low;
+        rec->vstar = vstar;
+        rec->lambda = lam;
+        for (int l = 0; l < 3; ++l) {
+            rec->pcg_iters[l] = st.iterations[l];
+            rec->rel_residual[l] = st.rel_residual[l];
+        }
+        rec->ms_total = c->timings[5];
+        rec->ms_solve = st.ms_solve;
+        rec->stop = c->small_steps >= c->go.stall_iters ? 1 : 0;
+    }
+    c->iter += 1;
+    return hrc;
+}
+
+int otm_optimize(otm_ctx* c, int32_t max_iter, double* rho_out, otm_iter_record* log, int32_t cap, int32_t* done) {
+    if (!c || max_iter < 0) return OTM_EINVAL;
+    int it = 0, last = OTM_OK;
+    for (; it < max_iter; ++it) {
+        otm_iter_record r{};
+        int rc = otm_step(c, &r);
+        if (rc < 0) return rc;
+        last = rc;
+        if (log && it < cap) log[it] = r;
+        if (r.stop) {
+            ++it;
+            break;
+        }
+    }
+    if (done) *done = it;
+    if (rho_out) {
+        HIPCHK(c, hipMemcpyAsync(rho_out, c->rho, (size_t)c->nn * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+    }
+    return last;
+}
+
+int otm_get_field(otm_ctx* c, int32_t field, double* out, int64_t count) {
+    if (!c || !out) return OTM_EINVAL;
+    const double* src = nullptr;
+    int64_t size = c->nn;
+    switch (field) {
+        case OTM_FIELD_RHO: src = c->rho; break;
+        case OTM_FIELD_RHOF: src = c->rhof; break;
+        case OTM_FIELD_K: src = c->k; break;
+        case OTM_FIELD_B: src = c->b; size = 3 * c->nn; break;
+        case OTM_FIELD_DIAG: src = c->dinv; break;
+        case OTM_FIELD_CHI: src = c->x; size = 3 * c->nn; break;
+        case OTM_FIELD_SENS_ELEM: src = c->st; break;
+        case OTM_FIELD_SENS: src = c->sens; break;
+        default: return fail(c, OTM_EINVAL, "unknown field");
+    }
+    if (count != size) return fail(c, OTM_EINVAL, "field count mismatch");
+    HIPCHK(c, hipMemcpyAsync(out, src, (size_t)size * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (field == OTM_FIELD_DIAG)
+        for (int64_t v = 0; v < size; ++v) out[v] = 1.0 / out[v];
+    return OTM_OK;
+}
+
+int otm_set_field(otm_ctx* c, int32_t field, const double* in, int64_t count) {
+    if (!c || !in) return OTM_EINVAL;
+    if (field == OTM_FIELD_RHO) return otm_set_density(c, in, count);
+    const int64_t size = field == OTM_FIELD_CHI ? 3 * c->nn : c->nn;
+    if (field != OTM_FIELD_CHI && field != OTM_FIELD_SENS) return fail(c, OTM_EINVAL, "field is not settable");
+    if (count != size) return fail(c, OTM_EINVAL, "field count mismatch");
+    for (int64_t v = 0; v < count; ++v)
+        if (!std::isfinite(in[v])) return fail(c, OTM_ENONFINITE, "non-finite field value");
+    if (field == OTM_FIELD_CHI && !c->prepared) return fail(c, OTM_ESTATE, "set chi needs prepared conductivities");
+    double* dst = field == OTM_FIELD_CHI ? c->x : c->sens;
+    HIPCHK(c, hipMemcpyAsync(dst, in, (size_t)size * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    if (field == OTM_FIELD_CHI) {
+        c->homogenized = true;
+        c->have_sens = false;
+    } else {
+        c->have_sens = true;
+    }
+    return OTM_OK;
+}
+
+int otm_set_guess(otm_ctx* c, const double* chi, int64_t count) {
+    if (!c || !chi) return OTM_EINVAL;
+    if (count != 3 * c->nn) return fail(c, OTM_EINVAL, "guess count must be 3 n^3");
+    for (int64_t v = 0; v < count; ++v)
+        if (!std::isfinite(chi[v])) return fail(c, OTM_ENONFINITE, "non-finite guess");
+    HIPCHK(c, hipMemcpyAsync(c->x, chi, (size_t)count * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->have_user_guess = true;
+    return OTM_OK;
+}
+
+int otm_get_governor(const otm_ctx* c, double s[8]) {
+    if (!c || !s) return OTM_EINVAL;
+    s[0] = c->vstar;
+    s[1] = c->df;
+    s[2] = (double)c->count;
+    s[3] = c->gap;
+    s[4] = c->g_prev;
+    s[5] = (double)c->small_steps;
+    s[6] = (double)c->iter;
+    s[7] = 0.0;
+    return OTM_OK;
+}
+
+int otm_set_governor(otm_ctx* c, const double s[8]) {
+    if (!c || !s) return OTM_EINVAL;
+    for (int q = 0; q < 7; ++q)
+        if (!std::isfinite(s[q])) return fail(c, OTM_ENONFINITE, "non-finite governor state");
+    c->vstar = s[0];
+    c->df = s[1];
+    c->count = (int)s[2];
+    c->gap = s[3];
+    c->g_prev = s[4];
+    c->small_steps = (int)s[5];
+    c->iter = (int)s[6];
+    return OTM_OK;
+}
+
+int otm_apply(otm_ctx* c, int32_t precision, const double* xh, double* yh) {
+    if (!c || !xh || !yh) return OTM_EINVAL;
+    if (!c->prepared) return fail(c, OTM_ESTATE, "apply needs prepared conductivities");
+    const int64_t cnt = 3 * c->nn;
+    int rc = OTM_OK;
+    if (precision == OTM_FP64) {
+        double *xd = nullptr, *yd = nullptr;
+        if ((rc = dalloc(c, &xd, cnt))) return rc;
+        if ((rc = dalloc(c, &yd, cnt))) {
+            (void)hipFree(xd);
+            return rc;
+        }
+        (void)hipMemcpyAsync(xd, xh, cnt * sizeof(double), hipMemcpyHostToDevice, c->stream);
+        if (c->so.kernel_variant == 1)
+            launch_apply<double>(c->n, c->k, xd, yd, c->stream);
+        else
+            launch_apply_tiled<double>(c->n, choose_tile(c->n, 1 << 30, 0), c->k, xd, yd, c->stream);
+        (void)hipMemcpyAsync(yh, yd, cnt * sizeof(double), hipMemcpyDeviceToHost, c->stream);
+        rc = check_launch(c, "apply");
+        hipError_t e = hipStreamSynchronize(c->stream);
+        (void)hipFree(xd);
+        (void)hipFree(yd);
+        if (!rc && e != hipSuccess) rc = fail(c, OTM_EDEVICE, hipGetErrorString(e));
+        return rc;
+    }
+    if (precision != OTM_MIXED) return fail(c, OTM_EINVAL, "precision");
+    double* xd = nullptr;
+    float *x32 = nullptr, *y32 = nullptr, *k32 = nullptr;
+    if ((rc = dalloc(c, &xd, cnt))) return rc;
+    rc = rc ? rc : dalloc(c, &x32, cnt);
+    rc = rc ? rc : dalloc(c, &y32, cnt);
+    rc = rc ? rc : dalloc(c, &k32, c->nn);
+    if (!rc) {
+        (void)hipMemcpyAsync(xd, xh, cnt * sizeof(double), hipMemcpyHostToDevice, c->stream);
+        launch_cast_f64_f32(cnt, xd, x32, c->stream);
+        launch_cast_f64_f32(c->nn, c->k, k32, c->stream);
+        if (c->so.kernel_variant == 1)
+            launch_apply<float>(c->n, k32, x32, y32, c->stream);
+        else
+            launch_apply_tiled<float>(c->n, choose_tile(c->n, 1 << 30, 0), k32, x32, y32, c->stream);
+        launch_cast_f32_f64(cnt, y32, xd, c->stream);
+        (void)hipMemcpyAsync(yh, xd, cnt * sizeof(double), hipMemcpyDeviceToHost, c->stream);
+        rc = check_launch(c, "apply32");
+        hipError_t e = hipStreamSynchronize(c->stream);
+        if (!rc && e != hipSuccess) rc = fail(c, OTM_EDEVICE, hipGetErrorString(e));
+    }
+    if (xd) (void)hipFree(xd);
+    if (x32) (void)hipFree(x32);
+    if (y32) (void)hipFree(y32);
+    if (k32) (void)hipFree(k32);
+    return rc;
+}
+
+int otm_apply_device(int32_t n, int32_t precision, int32_t variant, const void* k, const void* x, void* y,
+                     void* stream) {
+    if (n < 4 || n > 1024 || !k || !x || !y) return OTM_EINVAL;
+    if (x == y || (variant != 0 && variant != 1)) return OTM_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    const TileShape t = choose_tile(n, 1 << 30, 0);
+    if (precision == OTM_FP64) {
+        if (variant == 0)
+            launch_apply_tiled<double>(n, t, (const double*)k, (const double*)x, (double*)y, s);
+        else
+            launch_apply<double>(n, (const double*)k, (const double*)x, (double*)y, s);
+    } else if (precision == OTM_MIXED) {
+        if (variant == 0)
+            launch_apply_tiled<float>(n, t, (const float*)k, (const float*)x, (float*)y, s);
+        else
+            launch_apply<float>(n, (const float*)k, (const float*)x, (float*)y, s);
+    } else {
+        return OTM_EINVAL;
+    }
+    return hipGetLastError() == hipSuccess ? OTM_OK : OTM_EDEVICE;
+}
+
+int otm_time_apply_device(int32_t n, int32_t precision, int32_t variant, const void* k, const void* x, void* y,
+                          void* stream, int32_t reps, double* us) {
+    if (reps < 1 || !us) return OTM_EINVAL;
+    hipStream_t s = (hipStream_t)stream;
+    hipEvent_t a, b;
+    if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) return OTM_EDEVICE;
+    int rc = otm_apply_device(n, precision, variant, k, x, y, stream);  // warm
+    if (rc) return rc;
+    (void)hipEventRecord(a, s);
+    for (int q = 0; q < reps; ++q) otm_apply_device(n, precision, variant, k, x, y, stream);
+    (void)hipEventRecord(b, s);
+    if (hipEventSynchronize(b) != hipSuccess) return OTM_EDEVICE;
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, a, b);
+    *us = 1000.0 * (double)ms / (double)reps;
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    return OTM_OK;
+}
+
+int otm_get_timings(const otm_ctx* c, double t8[8]) {
+    if (!c || !t8) return OTM_EINVAL;
+    std::memcpy(t8, c->timings, sizeof(c->timings));
+    return OTM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,131 @@
+// Internal declarations shared by the kernel and engine translation units.
+// Not part of the public ABI (include/opentm_amd.h is).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace otm {
+
+constexpr int kBlock = 256;          // threads per block for node/element sweeps
+constexpr int kMaxReduce = 32;       // widest multi-value block reduction
+constexpr int kOcLevels = 5;         // bisection levels resolved per OC pass
+constexpr int kOcCands = (1 << kOcLevels) - 1;
+
+// Device-resident scalars of the solver and the OC search.  One instance per
+// context, written only by "last block" epilogues or by host copies between
+// kernels.
+struct Scalars {
+    // PCG, per load
+    double rz[3];       // r . D^-1 r of the current residual
+    double rz_prev[3];  // previous value (reliable-update beta)
+    double pq[3];
+    double alpha[3];
+    double beta[3];
+    double rr[3];       // recursive ||r||^2
+    double bb[3];       // ||b||^2
+    double rr_true[3];  // ||b - A x||^2 from the last residual refresh
+    double tol2;        // tol^2
+    int32_t active[3];  // load still iterating
+    int32_t iters[3];
+    // reductions over the design field
+    double sum_rho;      // sum rho
+    double sum_rhofp;    // sum rho~^p
+    double bsum[3];      // sum of macro loads (projection)
+    double xsum[3];      // sum of chi (projection)
+    double kappa_sum[6]; // sum k_e E_e,c
+    // OC bisection state
+    double l1, l2;
+    double vstar_n;      // V* * n^3
+    double lam;
+    int32_t oc_steps;
+    int32_t oc_done;
+    double cand[kOcCands];    // lambda candidates of the current pass (bisection tree, BFS order)
+    double cpow[kOcCands];    // candidate^-eta
+};
+
+// Launch helpers (otm_kernels.hip).  All are asynchronous on `s`.
+// `partials`/`counter` are the shared reduction workspace; `sc` the device scalars.
+struct Workspace {
+    double* partials;   // >= max_blocks * kMaxReduce doubles
+    unsigned* counter;  // one zero-initialised counter per reduction slot
+    Scalars* sc;
+    int max_blocks;
+};
+
+// Finalize step after a reduction kernel: one block sums the producer's
+// per-block partials and updates the device scalars.
+enum FinOp {
+    FIN_FILTER_SIMP = 0,
+    FIN_SETUP,
+    FIN_RES_START,
+    FIN_RES_REFRESH,
+    FIN_PQ,
+    FIN_UPDATE,
+    FIN_SUM3_X,
+    FIN_SUM3_B,
+    FIN_ENERGY,
+    FIN_OC
+};
+void launch_finalize(int op, int nblocks, const Workspace& ws, hipStream_t s, int64_t nn = 0, double eta = 0.5);
+
+void launch_filter_simp(int n, double r, const double* rho, double* rhof, double* k, float* k32, double k0,
+                        double kmin, double p, const Workspace& ws, hipStream_t s);
+void launch_filter(int n, double r, const double* in, double* out, hipStream_t s);
+void launch_setup_nodes(int n, const double* k, double* b, double* dinv, float* dinv32, const Workspace& ws,
+                        hipStream_t s);
+
+// PCG building blocks.  T = double (FP64 path) or float (mixed path); b and
+// the accumulated solution are float64 in both paths.
+enum { RES_START = 0, RES_REFRESH = 1 };
+template <typename T>
+void launch_dir(int n, const T* r, const T* dinv, const T* p_old, T* p_new, const Workspace& ws, hipStream_t s);
+template <typename T>
+void launch_apply_pq(int n, const T* k, const T* p, T* q, const Workspace& ws, hipStream_t s);
+template <typename T>
+void launch_update(int n, T* x, T* r, const T* p, const T* q, const T* dinv, const Workspace& ws, hipStream_t s);
+// r = b - A x with the float64 operator (x_zero: skip the operator), stored as TR.
+template <typename TR>
+void launch_residual(int n, const double* k, const double* b, const double* x, TR* r, TR* p_old, const TR* dinv,
+                     int mode, int x_zero, const Workspace& ws, hipStream_t s);
+void launch_accumulate(int n, double* x, float* x32, hipStream_t s);
+// slot 0: sums into sc->xsum, slot 1: into sc->bsum
+void launch_sum3(int n, const double* x, int slot, const Workspace& ws, hipStream_t s);
+void launch_sub_mean3(int n, double* x, int slot, const Workspace& ws, hipStream_t s);
+
+void launch_energy(int n, const double* k, const double* chi, const Workspace& ws, hipStream_t s);
+void launch_sens(int n, const double* rhof, const double* chi, const double* w6, double k0, double kmin, double p,
+                 double* st, hipStream_t s);
+
+void launch_oc_prepare(int n, const double* rho, const double* sens, double eta, double* q, hipStream_t s);
+void launch_oc_init(double vstar, int n, double eta, const Workspace& ws, hipStream_t s);
+void launch_oc_pass(int n, const double* rho, const double* q, double move, double rho_min, double eta,
+                    const Workspace& ws, hipStream_t s);
+void launch_oc_apply(int n, double* rho, const double* q, double eta, double move, double rho_min,
+                     const Workspace& ws, hipStream_t s);
+void launch_clamp(int n, double* rho, double lo, double hi, hipStream_t s);
+
+// Tiled fused direction + operator pass and vectorized update (otm_stencil.hip).
+struct TileShape {
+    int tx = 32, ty = 8, tz = 8;  // nodes per block in x, y; planes per z-march
+    int blocks = 0;
+};
+TileShape choose_tile(int n, int max_blocks, int tz_override);
+template <typename T>
+void launch_dir_apply(int n, const TileShape& t, const T* r, const T* dinv, const T* p_old, T* p_new, const T* k,
+                      T* q, const Workspace& ws, hipStream_t s);
+template <typename T>
+void launch_apply_tiled(int n, const TileShape& t, const T* k, const T* x, T* y, hipStream_t s);
+template <typename T>
+void launch_update_vec(int n, T* x, T* r, const T* p, const T* q, const T* dinv, const Workspace& ws, hipStream_t s);
+
+// Stateless operator y = A x (three loads)
+template <typename T>
+void launch_apply(int n, const T* k, const T* x, T* y, hipStream_t s);
+
+void launch_fill_u32(unsigned* p, int count, unsigned v, hipStream_t s);
+void launch_set_f64(double* dst, double v, hipStream_t s);
+void launch_cast_f64_f32(int64_t count, const double* in, float* out, hipStream_t s);
+void launch_cast_f32_f64(int64_t count, const float* in, double* out, hipStream_t s);
+
+}  // namespace otm

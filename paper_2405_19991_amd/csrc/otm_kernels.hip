@@ -1,0 +1,732 @@
+// HIP kernels for the periodic thermal homogenization step (gfx950).
+//
+// Grid convention: n^3 elements and n^3 nodes, periodic; node (i,j,k) is the
+// lower corner of element (i,j,k); flat index i + n*(j + n*k).  Element e with
+// origin o has local vertex l = a + 2b + 4c at node o + (a,b,c).
+//
+// Operator (hex-8 trilinear conduction, unit voxel): per element the 8x8
+// matrix is (1/12) * [4 on the diagonal, 0 between vertices one edge apart,
+// -1 between face-diagonal and body-diagonal vertices].  Gathered per node
+// (the node-centric [KT]_v of Sec. 2.4), with k_o the conductivity of the
+// incident element whose origin is v + (a'-1, b'-1, c'-1):
+//   centre          : (1/3) sum_o k_o
+//   face neighbour  : 0
+//   edge-diagonal   : -(1/12)(k_o1 + k_o2) over the two elements sharing it
+//   corner          : -(1/12) k_o of the one element sharing it.
+#include "otm_device.h"
+
+namespace otm {
+
+// ---------------------------------------------------------------- filter
+// Separable periodic hat weights w(d) = max(0, r - |d|), normalized per axis;
+// the 3D weight is the product, so its normalization is the product of the
+// 1D normalizations.  Reach R < 4.
+struct FilterW {
+    int R;
+    double w[9];
+};
+
+static FilterW filter_weights(double r) {
+    FilterW f{};
+    if (!(r > 0.0)) {
+        f.R = 0;
+        f.w[0] = 1.0;
+        return f;
+    }
+    int R = 0;
+    while (r - (double)(R + 1) > 0.0 && R < 4) ++R;
+    f.R = R;
+    double s = 0.0;
+    for (int d = -R; d <= R; ++d) s += r - fabs((double)d);
+    for (int d = -R; d <= R; ++d) f.w[d + R] = (r - fabs((double)d)) / s;
+    return f;
+}
+
+__device__ __forceinline__ double filter_at(const double* in, int n, int i, int j, int k, const FilterW& f) {
+    double acc = 0.0;
+    for (int dz = -f.R; dz <= f.R; ++dz) {
+        const int zk = wrapi(k + dz, n) * n;
+        double accy = 0.0;
+        for (int dy = -f.R; dy <= f.R; ++dy) {
+            const int row = (wrapi(j + dy, n) + zk) * n;
+            double accx = 0.0;
+            for (int dx = -f.R; dx <= f.R; ++dx) accx += f.w[dx + f.R] * in[row + wrapi(i + dx, n)];
+            accy += f.w[dy + f.R] * accx;
+        }
+        acc += f.w[dz + f.R] * accy;
+    }
+    return acc;
+}
+
+__global__ void __launch_bounds__(kBlock) k_filter(int n, FilterW f, const double* __restrict__ in,
+                                                   double* __restrict__ out) {
+    const int64_t nn = (int64_t)n * n * n;
+    const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (e >= nn) return;
+    const int i = (int)(e % n), j = (int)((e / n) % n), k = (int)(e / ((int64_t)n * n));
+    out[e] = filter_at(in, n, i, j, k, f);
+}
+
+// rho -> rho~ -> k (SIMP), plus the sums of rho and rho~^p.
+__global__ void __launch_bounds__(kBlock) k_filter_simp(int n, FilterW f, const double* __restrict__ rho,
+                                                        double* __restrict__ rhof, double* __restrict__ k,
+                                                        float* __restrict__ k32, double k0, double kmin, double p,
+                                                        double* partials, unsigned* counter, Scalars* sc) {
+    const int64_t nn = (int64_t)n * n * n;
+    double acc[2] = {0.0, 0.0};
+    for (int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x; e < nn; e += (int64_t)gridDim.x * kBlock) {
+        const int i = (int)(e % n), j = (int)((e / n) % n), kk = (int)(e / ((int64_t)n * n));
+        const double rf = filter_at(rho, n, i, j, kk, f);
+        const double rp = pow(rf, p);
+        const double ke = kmin + rp * (k0 - kmin);
+        rhof[e] = rf;
+        k[e] = ke;
+        if (k32) k32[e] = (float)ke;
+        acc[0] += rho[e];
+        acc[1] += rp;
+    }
+    block_partials<2>(acc, partials);
+}
+
+// ---------------------------------------------------------------- node setup
+// Macro load b^i_v = (1/4)(sum of k over the 4 incident elements on the -i side
+// of v  -  sum over the 4 on the +i side); Jacobi diagonal d_v = (1/3) sum of
+// the 8 incident k.  Also the sums of b^i (they vanish up to rounding; the
+// engine projects b to zero mean).
+__global__ void __launch_bounds__(kBlock) k_setup_nodes(int n, const double* __restrict__ k, double* __restrict__ b,
+                                                        double* __restrict__ dinv, float* __restrict__ dinv32,
+                                                        double* partials, unsigned* counter, Scalars* sc) {
+    const int64_t nn = (int64_t)n * n * n;
+    double acc[3] = {0.0, 0.0, 0.0};
+    for (int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x; v < nn; v += (int64_t)gridDim.x * kBlock) {
+        const int i = (int)(v % n), j = (int)((v / n) % n), kk = (int)(v / ((int64_t)n * n));
+        const int xi[2] = {wrapi(i - 1, n), i};
+        const int yj[2] = {wrapi(j - 1, n) * n, j * n};
+        const int zk[2] = {wrapi(kk - 1, n) * n * n, kk * n * n};
+        double ko[8];
+#pragma unroll
+        for (int o = 0; o < 8; ++o) ko[o] = k[xi[o & 1] + yj[(o >> 1) & 1] + zk[(o >> 2) & 1]];
+        double tot = 0.0, side[3][2] = {{0, 0}, {0, 0}, {0, 0}};
+#pragma unroll
+        for (int o = 0; o < 8; ++o) {
+            tot += ko[o];
+            side[0][o & 1] += ko[o];
+            side[1][(o >> 1) & 1] += ko[o];
+            side[2][(o >> 2) & 1] += ko[o];
+        }
+        // element with a' = 0 lies on the -x side of v
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const double bv = 0.25 * (side[a][0] - side[a][1]);
+            b[a * nn + v] = bv;
+            acc[a] += bv;
+        }
+        const double d = tot / 3.0;
+        dinv[v] = 1.0 / d;
+        if (dinv32) dinv32[v] = (float)(1.0 / d);
+    }
+    block_partials<3>(acc, partials);
+}
+
+// ---------------------------------------------------------------- operator
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_apply(int n, const T* __restrict__ k, const T* __restrict__ x,
+                                                  T* __restrict__ y) {
+    const int64_t nn = (int64_t)n * n * n;
+    const int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (v >= nn) return;
+    const int i = (int)(v % n), j = (int)((v / n) % n), kk = (int)(v / ((int64_t)n * n));
+    const Nbr o = nbr_of(i, j, kk, n);
+    T ko[8];
+    load_k8(k, o, ko);
+    NodeCoef<T> c;
+    node_coefs(ko, c);
+#pragma unroll
+    for (int l = 0; l < 3; ++l) y[l * nn + v] = stencil_node<T, T>(c, o, x + l * nn);
+}
+
+// ---------------------------------------------------------------- PCG pieces
+// r = b - A x (float64 operator) stored as TR; p_old zeroed (START) or kept
+// (REFRESH); sums ||r||^2, r.D^-1 r, ||b||^2 -> epilogue per mode.
+
+template <typename TR>
+__global__ void __launch_bounds__(kBlock) k_residual(int n, const double* __restrict__ k, const double* __restrict__ b,
+                                                     const double* __restrict__ x, TR* __restrict__ r,
+                                                     TR* __restrict__ p_old, const TR* __restrict__ dinv, int mode,
+                                                     int x_zero, double* partials, unsigned* counter, Scalars* sc) {
+    const int64_t nn = (int64_t)n * n * n;
+    double acc[9];
+#pragma unroll
+    for (int q = 0; q < 9; ++q) acc[q] = 0.0;
+    for (int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x; v < nn; v += (int64_t)gridDim.x * kBlock) {
+        double ax[3] = {0.0, 0.0, 0.0};
+        if (!x_zero) {
+            const int i = (int)(v % n), j = (int)((v / n) % n), kk = (int)(v / ((int64_t)n * n));
+            const Nbr o = nbr_of(i, j, kk, n);
+            double ko[8];
+            load_k8(k, o, ko);
+            NodeCoef<double> c;
+            node_coefs(ko, c);
+#pragma unroll
+            for (int l = 0; l < 3; ++l) ax[l] = stencil_node<double, double>(c, o, x + l * nn);
+        }
+        const double dv = (double)dinv[v];
+#pragma unroll
+        for (int l = 0; l < 3; ++l) {
+            const double bv = b[l * nn + v];
+            const double rv = bv - ax[l];
+            const TR rs = (TR)rv;
+            r[l * nn + v] = rs;
+            if (mode == RES_START) p_old[l * nn + v] = (TR)0;
+            acc[l] += rv * rv;
+            acc[3 + l] += dv * (double)rs * (double)rs;
+            acc[6 + l] += bv * bv;
+        }
+    }
+    block_partials<9>(acc, partials);
+}
+
+// p_new = D^-1 r + beta p_old (beta == 0 -> p_new = D^-1 r) for active loads.
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_dir(int n, const T* __restrict__ r, const T* __restrict__ dinv,
+                                                const T* __restrict__ p_old, T* __restrict__ p_new,
+                                                const Scalars* __restrict__ sc) {
+    const int64_t nn = (int64_t)n * n * n;
+    const int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (v >= nn) return;
+    const T dv = dinv[v];
+#pragma unroll
+    for (int l = 0; l < 3; ++l) {
+        if (!sc->active[l]) continue;
+        const T beta = (T)sc->beta[l];
+        const T z = dv * r[l * nn + v];
+        p_new[l * nn + v] = (beta == (T)0) ? z : z + beta * p_old[l * nn + v];
+    }
+}
+
+// q = A p for active loads; sums p.q -> alpha = rz / pq.
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_apply_pq(int n, const T* __restrict__ k, const T* __restrict__ p,
+                                                     T* __restrict__ q, double* partials, unsigned* counter,
+                                                     Scalars* sc) {
+    const int64_t nn = (int64_t)n * n * n;
+    const int act[3] = {sc->active[0], sc->active[1], sc->active[2]};
+    double acc[3] = {0.0, 0.0, 0.0};
+    for (int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x; v < nn; v += (int64_t)gridDim.x * kBlock) {
+        const int i = (int)(v % n), j = (int)((v / n) % n), kk = (int)(v / ((int64_t)n * n));
+        const Nbr o = nbr_of(i, j, kk, n);
+        T ko[8];
+        load_k8(k, o, ko);
+        NodeCoef<T> c;
+        node_coefs(ko, c);
+#pragma unroll
+        for (int l = 0; l < 3; ++l) {
+            if (!act[l]) continue;
+            const T y = stencil_node<T, T>(c, o, p + l * nn);
+            q[l * nn + v] = y;
+            acc[l] += (double)p[l * nn + v] * (double)y;
+        }
+    }
+    block_partials<3>(acc, partials);
+}
+
+// x += alpha p; r -= alpha q; sums r.D^-1 r and ||r||^2 -> beta, stop test.
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_update(int n, T* __restrict__ x, T* __restrict__ r, const T* __restrict__ p,
+                                                   const T* __restrict__ q, const T* __restrict__ dinv,
+                                                   double* partials, unsigned* counter, Scalars* sc) {
+    const int64_t nn = (int64_t)n * n * n;
+    const int act[3] = {sc->active[0], sc->active[1], sc->active[2]};
+    double acc[6] = {0, 0, 0, 0, 0, 0};
+    for (int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x; v < nn; v += (int64_t)gridDim.x * kBlock) {
+        const T dv = dinv[v];
+#pragma unroll
+        for (int l = 0; l < 3; ++l) {
+            if (!act[l]) continue;
+            const T a = (T)sc->alpha[l];
+            x[l * nn + v] += a * p[l * nn + v];
+            const T rv = r[l * nn + v] - a * q[l * nn + v];
+            r[l * nn + v] = rv;
+            acc[l] += (double)dv * (double)rv * (double)rv;
+            acc[3 + l] += (double)rv * (double)rv;
+        }
+    }
+    block_partials<6>(acc, partials);
+}
+
+// x64 += x32; x32 = 0 (mixed-precision solution accumulation).
+__global__ void __launch_bounds__(kBlock) k_accumulate(int64_t count, double* __restrict__ x, float* __restrict__ x32) {
+    const int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (v >= count) return;
+    x[v] += (double)x32[v];
+    x32[v] = 0.0f;
+}
+
+// sums of the three loads of x -> sc->xsum (slot 0) or sc->bsum (slot 1)
+__global__ void __launch_bounds__(kBlock) k_sum3(int n, const double* __restrict__ x, int slot, double* partials,
+                                                 unsigned* counter, Scalars* sc) {
+    const int64_t nn = (int64_t)n * n * n;
+    double acc[3] = {0, 0, 0};
+    for (int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x; v < nn; v += (int64_t)gridDim.x * kBlock) {
+#pragma unroll
+        for (int l = 0; l < 3; ++l) acc[l] += x[l * nn + v];
+    }
+    block_partials<3>(acc, partials);
+}
+
+// x^l -= sum^l / n^3 with the sum taken from slot 0 (xsum) or 1 (bsum)
+__global__ void __launch_bounds__(kBlock) k_sub_mean3(int n, double* __restrict__ x, int slot, const Scalars* sc) {
+    const int64_t nn = (int64_t)n * n * n;
+    const int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (v >= nn) return;
+#pragma unroll
+    for (int l = 0; l < 3; ++l) {
+        const double m = (slot == 0 ? sc->xsum[l] : sc->bsum[l]) / (double)nn;
+        x[l * nn + v] -= m;
+    }
+}
+
+// ---------------------------------------------------------------- tensor
+// u^i_l = X_{l,i} - chi^i(vertex l);  E_c = u^i . K u^j for the six pairs.
+// K u at vertex l = (1/12)(4 u_l - sum of u over vertices differing in 2 or 3
+// coordinates) = (1/12)(5 u_l + sum over the 3 edge neighbours - sum of all 8).
+__device__ __forceinline__ void element_energies(const double* __restrict__ chi, int64_t nn, int n, int i, int j,
+                                                 int k, double (&E)[6]) {
+    const int xi[2] = {i, wrapi(i + 1, n)};
+    const int yj[2] = {j * n, wrapi(j + 1, n) * n};
+    const int zk[2] = {k * n * n, wrapi(k + 1, n) * n * n};
+    double u[3][8];
+#pragma unroll
+    for (int l = 0; l < 8; ++l) {
+        const int v = xi[l & 1] + yj[(l >> 1) & 1] + zk[(l >> 2) & 1];
+#pragma unroll
+        for (int a = 0; a < 3; ++a) u[a][l] = (double)((l >> a) & 1) - chi[a * nn + v];
+    }
+    double Ku[3][8];
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        double tot = 0.0;
+#pragma unroll
+        for (int l = 0; l < 8; ++l) tot += u[a][l];
+#pragma unroll
+        for (int l = 0; l < 8; ++l)
+            Ku[a][l] = (5.0 * u[a][l] + u[a][l ^ 1] + u[a][l ^ 2] + u[a][l ^ 4] - tot) * (1.0 / 12.0);
+    }
+    const int I[6] = {0, 1, 2, 0, 1, 0};
+    const int J[6] = {0, 1, 2, 1, 2, 2};
+#pragma unroll
+    for (int c = 0; c < 6; ++c) {
+        double s = 0.0;
+#pragma unroll
+        for (int l = 0; l < 8; ++l) s += u[I[c]][l] * Ku[J[c]][l];
+        E[c] = s;
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) k_energy(int n, const double* __restrict__ k, const double* __restrict__ chi,
+                                                   double* partials, unsigned* counter, Scalars* sc) {
+    const int64_t nn = (int64_t)n * n * n;
+    double acc[6] = {0, 0, 0, 0, 0, 0};
+    for (int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x; e < nn; e += (int64_t)gridDim.x * kBlock) {
+        const int i = (int)(e % n), j = (int)((e / n) % n), kk = (int)(e / ((int64_t)n * n));
+        double E[6];
+        element_energies(chi, nn, n, i, j, kk, E);
+        const double ke = k[e];
+#pragma unroll
+        for (int c = 0; c < 6; ++c) acc[c] += ke * E[c];
+    }
+    block_partials<6>(acc, partials);
+}
+
+struct W6 {
+    double w[6];
+};
+
+// s~_e = n^-3 p rho~^(p-1) (k0 - kmin) sum_c w_c E_e,c
+__global__ void __launch_bounds__(kBlock) k_sens(int n, const double* __restrict__ rhof, const double* __restrict__ chi,
+                                                 W6 w, double k0, double kmin, double p, double* __restrict__ st) {
+    const int64_t nn = (int64_t)n * n * n;
+    const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (e >= nn) return;
+    const int i = (int)(e % n), j = (int)((e / n) % n), kk = (int)(e / ((int64_t)n * n));
+    double E[6];
+    element_energies(chi, nn, n, i, j, kk, E);
+    double s = 0.0;
+#pragma unroll
+    for (int c = 0; c < 6; ++c) s += w.w[c] * E[c];
+    st[e] = p * pow(rhof[e], p - 1.0) * (k0 - kmin) * s / (double)nn;
+}
+
+// ---------------------------------------------------------------- OC
+// q_e = rho_e (max(0, -s_e) n^3)^eta ; rho_new(lam) = clamp(q lam^-eta, lo, hi)
+__global__ void __launch_bounds__(kBlock) k_oc_prepare(int64_t nn, const double* __restrict__ rho,
+                                                       const double* __restrict__ s, double eta,
+                                                       double* __restrict__ q) {
+    const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (e >= nn) return;
+    const double B = fmax(0.0, -s[e]) * (double)nn;
+    q[e] = rho[e] * (eta == 0.5 ? sqrt(B) : pow(B, eta));
+}
+
+// Candidates of the next kOcLevels bisection levels below [l1, l2], in
+// breadth-first order of the midpoint tree, each computed exactly as the
+// sequential bisection would: mid = 0.5 (lo + hi) of its parent interval.
+__device__ void oc_make_candidates(Scalars* sc, double eta) {
+    double lo[kOcCands], hi[kOcCands];
+    lo[0] = sc->l1;
+    hi[0] = sc->l2;
+#pragma unroll
+    for (int t = 0; t < kOcCands; ++t) {
+        const double mid = 0.5 * (lo[t] + hi[t]);
+        sc->cand[t] = mid;
+        sc->cpow[t] = (eta == 0.5) ? 1.0 / sqrt(mid) : pow(mid, -eta);
+        const int cl = 2 * t + 1, cr = 2 * t + 2;
+        if (cl < kOcCands) {
+            lo[cl] = lo[t];
+            hi[cl] = mid;
+        }
+        if (cr < kOcCands) {
+            lo[cr] = mid;
+            hi[cr] = hi[t];
+        }
+    }
+}
+
+__global__ void k_oc_init(Scalars* sc, double vstar_n, double eta) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) {
+        sc->l1 = 0.0;
+        sc->l2 = 1e9;
+        sc->vstar_n = vstar_n;
+        sc->oc_steps = 0;
+        sc->oc_done = 0;
+        oc_make_candidates(sc, eta);
+    }
+}
+
+// One pass: sum clamp(q c_m, lo, hi) for every candidate, then walk the tree
+// with the sequential stopping rule (width <= 1e-13 (l1 + l2), 200 halvings).
+__global__ void __launch_bounds__(kBlock) k_oc_pass(int64_t nn, const double* __restrict__ rho,
+                                                    const double* __restrict__ q, double move, double rho_min,
+                                                    double eta, double* partials, unsigned* counter, Scalars* sc) {
+    if (sc->oc_done) return;
+    double cp[kOcCands];
+#pragma unroll
+    for (int t = 0; t < kOcCands; ++t) cp[t] = sc->cpow[t];
+    double acc[kOcCands];
+#pragma unroll
+    for (int t = 0; t < kOcCands; ++t) acc[t] = 0.0;
+    for (int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x; e < nn; e += (int64_t)gridDim.x * kBlock) {
+        const double r = rho[e], qe = q[e];
+        const double lo = fmax(rho_min, r - move), hi = fmin(1.0, r + move);
+#pragma unroll
+        for (int t = 0; t < kOcCands; ++t) acc[t] += fmin(hi, fmax(lo, qe * cp[t]));
+    }
+    block_partials<kOcCands>(acc, partials);
+}
+
+__global__ void __launch_bounds__(kBlock) k_oc_apply(int64_t nn, double* __restrict__ rho, const double* __restrict__ q,
+                                                     double eta, double move, double rho_min, const Scalars* sc) {
+    const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (e >= nn) return;
+    const double lam = sc->lam;
+    const double c = (eta == 0.5) ? 1.0 / sqrt(lam) : pow(lam, -eta);
+    const double r = rho[e];
+    const double lo = fmax(rho_min, r - move), hi = fmin(1.0, r + move);
+    rho[e] = fmin(hi, fmax(lo, q[e] * c));
+}
+
+__global__ void __launch_bounds__(kBlock) k_clamp(int64_t nn, double* __restrict__ rho, double lo, double hi) {
+    const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (e >= nn) return;
+    rho[e] = fmin(hi, fmax(lo, rho[e]));
+}
+
+__global__ void k_fill_u32(unsigned* p, int count, unsigned v) {
+    const int t = blockIdx.x * blockDim.x + threadIdx.x;
+    if (t < count) p[t] = v;
+}
+
+
+// ---------------------------------------------------------------- finalize
+// One block: sums the per-block partials of the kernel just before it (fixed
+// order, so results are reproducible for a fixed launch shape) and updates
+// the device scalars.  The kernel boundary makes the producer's partial
+// stores visible, so producers need no device-scope fences.
+template <int NV>
+__device__ __forceinline__ void fin_sums(const double* partials, int nblocks, double* tot) {
+    final_sums<NV>(partials, nblocks, tot);
+}
+
+__global__ void __launch_bounds__(kBlock) k_finalize(int op, int nblocks, const double* __restrict__ partials,
+                                                     Scalars* sc, int64_t nn, double eta) {
+    __shared__ double tot[kMaxReduce];
+    switch (op) {
+        case FIN_FILTER_SIMP: fin_sums<2>(partials, nblocks, tot); break;
+        case FIN_SETUP:
+        case FIN_PQ:
+        case FIN_SUM3_X:
+        case FIN_SUM3_B: fin_sums<3>(partials, nblocks, tot); break;
+        case FIN_RES_START:
+        case FIN_RES_REFRESH: fin_sums<9>(partials, nblocks, tot); break;
+        case FIN_UPDATE:
+        case FIN_ENERGY: fin_sums<6>(partials, nblocks, tot); break;
+        case FIN_OC: fin_sums<kOcCands>(partials, nblocks, tot); break;
+        default: return;
+    }
+    if (threadIdx.x != 0) return;
+    switch (op) {
+        case FIN_FILTER_SIMP:
+            sc->sum_rho = tot[0];
+            sc->sum_rhofp = tot[1];
+            break;
+        case FIN_SETUP:
+        case FIN_SUM3_B:
+            for (int l = 0; l < 3; ++l) sc->bsum[l] = tot[l];
+            break;
+        case FIN_SUM3_X:
+            for (int l = 0; l < 3; ++l) sc->xsum[l] = tot[l];
+            break;
+        case FIN_RES_START:
+        case FIN_RES_REFRESH:
+            for (int l = 0; l < 3; ++l) {
+                const double rr = tot[l], rz = tot[3 + l], bb = tot[6 + l];
+                sc->rr_true[l] = rr;
+                sc->rr[l] = rr;
+                sc->bb[l] = bb;
+                const bool need = (bb > 0.0) && (rr > sc->tol2 * bb);
+                if (op == FIN_RES_START) {
+                    sc->active[l] = need ? 1 : 0;
+                    sc->beta[l] = 0.0;
+                    sc->rz[l] = rz;
+                    sc->rz_prev[l] = rz;
+                } else if (sc->active[l]) {
+                    sc->beta[l] = (sc->rz_prev[l] > 0.0) ? rz / sc->rz_prev[l] : 0.0;
+                    sc->rz[l] = rz;
+                } else if (need) {
+                    sc->active[l] = 1;
+                    sc->beta[l] = 0.0;
+                    sc->rz[l] = rz;
+                    sc->rz_prev[l] = rz;
+                }
+            }
+            break;
+        case FIN_PQ:
+            for (int l = 0; l < 3; ++l) {
+                if (!sc->active[l]) continue;
+                sc->pq[l] = tot[l];
+                sc->alpha[l] = (tot[l] > 0.0) ? sc->rz[l] / tot[l] : 0.0;
+            }
+            break;
+        case FIN_UPDATE:
+            for (int l = 0; l < 3; ++l) {
+                if (!sc->active[l]) continue;
+                const double rz_new = tot[l], rr = tot[3 + l];
+                sc->rz_prev[l] = sc->rz[l];
+                sc->beta[l] = (sc->rz[l] > 0.0) ? rz_new / sc->rz[l] : 0.0;
+                sc->rz[l] = rz_new;
+                sc->rr[l] = rr;
+                sc->iters[l] += 1;
+                if (!(rr > sc->tol2 * sc->bb[l])) sc->active[l] = 0;
+            }
+            break;
+        case FIN_ENERGY:
+            for (int c = 0; c < 6; ++c) sc->kappa_sum[c] = tot[c];
+            break;
+        case FIN_OC: {
+            double l1 = sc->l1, l2 = sc->l2;
+            int steps = sc->oc_steps;
+            int node = 0;
+            int done = 0;
+            for (int lev = 0; lev < kOcLevels; ++lev) {
+                if (steps >= 200 || (l2 - l1) <= 1e-13 * (l1 + l2)) {
+                    done = 1;
+                    break;
+                }
+                const double mid = sc->cand[node];
+                const double vol = tot[node] / (double)nn;
+                if (vol > sc->vstar_n / (double)nn) {
+                    l1 = mid;
+                    node = 2 * node + 2;
+                } else {
+                    l2 = mid;
+                    node = 2 * node + 1;
+                }
+                ++steps;
+            }
+            if (!done && (steps >= 200 || (l2 - l1) <= 1e-13 * (l1 + l2))) done = 1;
+            sc->l1 = l1;
+            sc->l2 = l2;
+            sc->oc_steps = steps;
+            sc->lam = 0.5 * (l1 + l2);
+            if (done)
+                sc->oc_done = 1;
+            else
+                oc_make_candidates(sc, eta);
+            break;
+        }
+        default: break;
+    }
+}
+
+void launch_finalize(int op, int nblocks, const Workspace& ws, hipStream_t s, int64_t nn, double eta) {
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kBlock), 0, s, op, nblocks, ws.partials, ws.sc, nn, eta);
+}
+
+// ---------------------------------------------------------------- launchers
+
+static inline int64_t cube(int n) { return (int64_t)n * n * n; }
+
+void launch_filter_simp(int n, double r, const double* rho, double* rhof, double* k, float* k32, double k0,
+                        double kmin, double p, const Workspace& ws, hipStream_t s) {
+    const int g = grid_for(cube(n), ws.max_blocks);
+    hipLaunchKernelGGL(k_filter_simp, dim3(g), dim3(kBlock), 0, s, n, filter_weights(r), rho, rhof, k, k32, k0, kmin,
+                       p, ws.partials, ws.counter, ws.sc);
+    launch_finalize(FIN_FILTER_SIMP, g, ws, s);
+}
+
+void launch_filter(int n, double r, const double* in, double* out, hipStream_t s) {
+    hipLaunchKernelGGL(k_filter, dim3(nblocks_for(cube(n))), dim3(kBlock), 0, s, n, filter_weights(r), in, out);
+}
+
+void launch_setup_nodes(int n, const double* k, double* b, double* dinv, float* dinv32, const Workspace& ws,
+                        hipStream_t s) {
+    const int g = grid_for(cube(n), ws.max_blocks);
+    hipLaunchKernelGGL(k_setup_nodes, dim3(g), dim3(kBlock), 0, s, n, k, b, dinv, dinv32, ws.partials, ws.counter,
+                       ws.sc);
+    launch_finalize(FIN_SETUP, g, ws, s);
+}
+
+template <typename T>
+void launch_dir(int n, const T* r, const T* dinv, const T* p_old, T* p_new, const Workspace& ws, hipStream_t s) {
+    hipLaunchKernelGGL(k_dir<T>, dim3(nblocks_for(cube(n))), dim3(kBlock), 0, s, n, r, dinv, p_old, p_new, ws.sc);
+}
+
+template <typename T>
+void launch_apply_pq(int n, const T* k, const T* p, T* q, const Workspace& ws, hipStream_t s) {
+    const int g = grid_for(cube(n), ws.max_blocks);
+    hipLaunchKernelGGL(k_apply_pq<T>, dim3(g), dim3(kBlock), 0, s, n, k, p, q, ws.partials, ws.counter, ws.sc);
+    launch_finalize(FIN_PQ, g, ws, s);
+}
+
+template <typename T>
+void launch_update(int n, T* x, T* r, const T* p, const T* q, const T* dinv, const Workspace& ws, hipStream_t s) {
+    const int g = grid_for(cube(n), ws.max_blocks);
+    hipLaunchKernelGGL(k_update<T>, dim3(g), dim3(kBlock), 0, s, n, x, r, p, q, dinv, ws.partials, ws.counter, ws.sc);
+    launch_finalize(FIN_UPDATE, g, ws, s);
+}
+
+template <typename TR>
+void launch_residual(int n, const double* k, const double* b, const double* x, TR* r, TR* p_old, const TR* dinv,
+                          int mode, int x_zero, const Workspace& ws, hipStream_t s) {
+    const int g = grid_for(cube(n), ws.max_blocks);
+    hipLaunchKernelGGL(k_residual<TR>, dim3(g), dim3(kBlock), 0, s, n, k, b, x, r, p_old, dinv, mode, x_zero,
+                       ws.partials, ws.counter, ws.sc);
+    launch_finalize(mode == RES_START ? FIN_RES_START : FIN_RES_REFRESH, g, ws, s);
+}
+
+void launch_accumulate(int n, double* x, float* x32, hipStream_t s) {
+    const int64_t cnt = 3 * cube(n);
+    hipLaunchKernelGGL(k_accumulate, dim3(nblocks_for(cnt)), dim3(kBlock), 0, s, cnt, x, x32);
+}
+
+void launch_sum3(int n, const double* x, int slot, const Workspace& ws, hipStream_t s) {
+    const int g = grid_for(cube(n), ws.max_blocks);
+    hipLaunchKernelGGL(k_sum3, dim3(g), dim3(kBlock), 0, s, n, x, slot, ws.partials, ws.counter, ws.sc);
+    launch_finalize(slot == 0 ? FIN_SUM3_X : FIN_SUM3_B, g, ws, s);
+}
+
+void launch_sub_mean3(int n, double* x, int slot, const Workspace& ws, hipStream_t s) {
+    hipLaunchKernelGGL(k_sub_mean3, dim3(nblocks_for(cube(n))), dim3(kBlock), 0, s, n, x, slot, ws.sc);
+}
+
+void launch_energy(int n, const double* k, const double* chi, const Workspace& ws, hipStream_t s) {
+    const int g = grid_for(cube(n), ws.max_blocks);
+    hipLaunchKernelGGL(k_energy, dim3(g), dim3(kBlock), 0, s, n, k, chi, ws.partials, ws.counter, ws.sc);
+    launch_finalize(FIN_ENERGY, g, ws, s);
+}
+
+void launch_sens(int n, const double* rhof, const double* chi, const double* w6, double k0, double kmin, double p,
+                 double* st, hipStream_t s) {
+    W6 w;
+    for (int c = 0; c < 6; ++c) w.w[c] = w6[c];
+    hipLaunchKernelGGL(k_sens, dim3(nblocks_for(cube(n))), dim3(kBlock), 0, s, n, rhof, chi, w, k0, kmin, p, st);
+}
+
+void launch_oc_prepare(int n, const double* rho, const double* sens, double eta, double* q, hipStream_t s) {
+    hipLaunchKernelGGL(k_oc_prepare, dim3(nblocks_for(cube(n))), dim3(kBlock), 0, s, cube(n), rho, sens, eta, q);
+}
+
+void launch_oc_init(double vstar, int n, double eta, const Workspace& ws, hipStream_t s) {
+    hipLaunchKernelGGL(k_oc_init, dim3(1), dim3(64), 0, s, ws.sc, vstar * (double)cube(n), eta);
+}
+
+void launch_oc_pass(int n, const double* rho, const double* q, double move, double rho_min, double eta,
+                        const Workspace& ws, hipStream_t s) {
+    const int g = grid_for(cube(n), ws.max_blocks < 1024 ? ws.max_blocks : 1024);
+    hipLaunchKernelGGL(k_oc_pass, dim3(g), dim3(kBlock), 0, s, cube(n), rho, q, move, rho_min, eta, ws.partials,
+                       ws.counter, ws.sc);
+    launch_finalize(FIN_OC, g, ws, s, cube(n), eta);
+}
+
+void launch_oc_apply(int n, double* rho, const double* q, double eta, double move, double rho_min,
+                     const Workspace& ws, hipStream_t s) {
+    hipLaunchKernelGGL(k_oc_apply, dim3(nblocks_for(cube(n))), dim3(kBlock), 0, s, cube(n), rho, q, eta, move,
+                       rho_min, ws.sc);
+}
+
+void launch_clamp(int n, double* rho, double lo, double hi, hipStream_t s) {
+    hipLaunchKernelGGL(k_clamp, dim3(nblocks_for(cube(n))), dim3(kBlock), 0, s, cube(n), rho, lo, hi);
+}
+
+template <typename T>
+void launch_apply(int n, const T* k, const T* x, T* y, hipStream_t s) {
+    hipLaunchKernelGGL(k_apply<T>, dim3(nblocks_for(cube(n))), dim3(kBlock), 0, s, n, k, x, y);
+}
+
+void launch_fill_u32(unsigned* p, int count, unsigned v, hipStream_t s) {
+    hipLaunchKernelGGL(k_fill_u32, dim3((count + 255) / 256), dim3(256), 0, s, p, count, v);
+}
+
+template void launch_dir<double>(int, const double*, const double*, const double*, double*, const Workspace&,
+                                 hipStream_t);
+template void launch_dir<float>(int, const float*, const float*, const float*, float*, const Workspace&, hipStream_t);
+template void launch_apply_pq<double>(int, const double*, const double*, double*, const Workspace&, hipStream_t);
+template void launch_apply_pq<float>(int, const float*, const float*, float*, const Workspace&, hipStream_t);
+template void launch_update<double>(int, double*, double*, const double*, const double*, const double*,
+                                    const Workspace&, hipStream_t);
+template void launch_update<float>(int, float*, float*, const float*, const float*, const float*, const Workspace&,
+                                   hipStream_t);
+template void launch_residual<double>(int, const double*, const double*, const double*, double*, double*,
+                                           const double*, int, int, const Workspace&, hipStream_t);
+template void launch_residual<float>(int, const double*, const double*, const double*, float*, float*,
+                                          const float*, int, int, const Workspace&, hipStream_t);
+template void launch_apply<double>(int, const double*, const double*, double*, hipStream_t);
+template void launch_apply<float>(int, const float*, const float*, float*, hipStream_t);
+
+}  // namespace otm
+
+namespace otm {
+
+__global__ void k_set_f64(double* dst, double v) {
+    if (threadIdx.x == 0 && blockIdx.x == 0) *dst = v;
+}
+
+void launch_set_f64(double* dst, double v, hipStream_t s) { hipLaunchKernelGGL(k_set_f64, dim3(1), dim3(64), 0, s, dst, v); }
+
+__global__ void k_cast_f64_f32(int64_t count, const double* __restrict__ in, float* __restrict__ out) {
+    const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (t < count) out[t] = (float)in[t];
+}
+__global__ void k_cast_f32_f64(int64_t count, const float* __restrict__ in, double* __restrict__ out) {
+    const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (t < count) out[t] = (double)in[t];
+}
+
+void launch_cast_f64_f32(int64_t count, const double* in, float* out, hipStream_t s) {
+    hipLaunchKernelGGL(k_cast_f64_f32, dim3(nblocks_for(count)), dim3(kBlock), 0, s, count, in, out);
+}
+void launch_cast_f32_f64(int64_t count, const float* in, double* out, hipStream_t s) {
+    hipLaunchKernelGGL(k_cast_f32_f64, dim3(nblocks_for(count)), dim3(kBlock), 0, s, count, in, out);
+}
+
+}  // namespace otm

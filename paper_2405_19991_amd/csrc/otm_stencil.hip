@@ -1,0 +1,289 @@
+// Tiled solver kernels for the PCG iteration (gfx950).
+//
+// k_tiled (DIR = true): one pass that forms the new search direction
+//   p_new = D^-1 r + beta p_old
+// and applies the operator q = A p_new for the three loads, with the dot
+// products p.q reduced in float64 and alpha = rz / pq set by the last block.
+//
+// Layout of the pass: a block owns a TX x TY column of nodes and marches in z
+// over tz planes.  p_new of the planes z-1, z, z+1 (with a one-node halo in x
+// and y) lives in a 3-slot LDS ring; k of the element planes z-1 and z in a
+// 2-slot ring.  Each node of plane z then reads its 20 non-zero neighbours
+// and 8 incident conductivities from LDS, so every HBM value is fetched by
+// one block (halo values are re-read from L2 by the neighbouring block).
+//
+// k_update_vec: x += alpha p, r -= alpha q and the dots r.D^-1 r, r.r, with
+// 16-byte vector accesses (float4 / double2).
+#include "otm_device.h"
+
+namespace otm {
+
+// y at one node from the three LDS planes (pm: z-1, p0: z, pp: z+1); pc is the
+// node's position in the padded plane, PX its row pitch.
+template <typename T>
+__device__ __forceinline__ T stencil_lds(const NodeCoef<T>& c, const T* pm, const T* p0, const T* pp, int pc,
+                                         int PX) {
+    T y = c.c0 * p0[pc];
+    // edge-diagonal neighbours in the xy plane: (2a-1, 2b-1, 0)
+    y += c.ce[0] * p0[pc - PX - 1];
+    y += c.ce[1] * p0[pc - PX + 1];
+    y += c.ce[2] * p0[pc + PX - 1];
+    y += c.ce[3] * p0[pc + PX + 1];
+    // xz plane: (2a-1, 0, 2c-1)
+    y += c.ce[4] * pm[pc - 1];
+    y += c.ce[5] * pm[pc + 1];
+    y += c.ce[6] * pp[pc - 1];
+    y += c.ce[7] * pp[pc + 1];
+    // yz plane: (0, 2b-1, 2c-1)
+    y += c.ce[8] * pm[pc - PX];
+    y += c.ce[9] * pm[pc + PX];
+    y += c.ce[10] * pp[pc - PX];
+    y += c.ce[11] * pp[pc + PX];
+    // corners (2a-1, 2b-1, 2c-1), index a + 2b + 4c
+    y += c.cc[0] * pm[pc - PX - 1];
+    y += c.cc[1] * pm[pc - PX + 1];
+    y += c.cc[2] * pm[pc + PX - 1];
+    y += c.cc[3] * pm[pc + PX + 1];
+    y += c.cc[4] * pp[pc - PX - 1];
+    y += c.cc[5] * pp[pc - PX + 1];
+    y += c.cc[6] * pp[pc + PX - 1];
+    y += c.cc[7] * pp[pc + PX + 1];
+    return y;
+}
+
+// DIR = true : p_new = D^-1 r + beta p_old, q = A p_new, dots p.q (PCG pass)
+// DIR = false: q = A r (plain operator; dinv, p_old, p_new, the scalars and the
+//              reduction workspace are unused and may be null)
+template <typename T, int TX, int TY, bool DIR>
+__global__ void __launch_bounds__(TX* TY) k_tiled(int n, int tz, int ntx, int nty, const T* __restrict__ r,
+                                                      const T* __restrict__ dinv, const T* __restrict__ p_old,
+                                                      T* __restrict__ p_new, const T* __restrict__ k,
+                                                      T* __restrict__ q, double* partials, unsigned* counter,
+                                                      Scalars* sc) {
+    static_assert(TX * TY == kBlock, "block size");
+    constexpr int PX = TX + 2, PY = TY + 2, PA = PX * PY;
+    constexpr int KX = TX + 1, KY = TY + 1, KA = KX * KY;
+    __shared__ T sp[3][3][PA];
+    __shared__ T sk[2][KA];
+
+    const int tid = threadIdx.x;
+    const int tx = tid % TX, ty = tid / TX;
+    int bid = blockIdx.x;
+    const int bx = bid % ntx;
+    bid /= ntx;
+    const int by = bid % nty;
+    const int bz = bid / nty;
+    const int i0 = bx * TX, j0 = by * TY, z0 = bz * tz;
+    const int z1 = min(z0 + tz, n);
+    const int64_t nn = (int64_t)n * n * n;
+    const int64_t n2 = (int64_t)n * n;
+    int act[3] = {1, 1, 1};
+    T beta[3] = {(T)0, (T)0, (T)0};
+    if (DIR) {
+#pragma unroll
+        for (int l = 0; l < 3; ++l) {
+            act[l] = sc->active[l];
+            beta[l] = (T)sc->beta[l];
+        }
+    }
+    const int i = i0 + tx, j = j0 + ty;
+    const bool own = (i < n) && (j < n);
+    double acc[3] = {0.0, 0.0, 0.0};
+
+    // p_new of plane zz (zz in [z0-1, z1]) into its ring slot; owned nodes of
+    // planes [z0, z1) are also written to global memory (exactly once overall).
+    auto fill_p = [&](int zz) {
+        const int slot = (zz - z0 + 1) % 3;
+        const int64_t zoff = (int64_t)((zz + n) % n) * n2;
+        const bool plane_owned = (zz >= z0) && (zz < z1);
+        for (int t = tid; t < PA; t += kBlock) {
+            const int px = t % PX, py = t / PX;
+            const int gi0 = i0 - 1 + px, gj0 = j0 - 1 + py;
+            const bool interior = plane_owned && px >= 1 && px <= TX && py >= 1 && py <= TY && gi0 < n && gj0 < n;
+            const int gi = (gi0 + n) % n, gj = (gj0 + n) % n;
+            const int64_t v = gi + (int64_t)n * gj + zoff;
+            if (DIR) {
+                const T dv = dinv[v];
+#pragma unroll
+                for (int l = 0; l < 3; ++l) {
+                    if (!act[l]) continue;
+                    const T z = dv * r[l * nn + v];
+                    const T pn = (beta[l] == (T)0) ? z : z + beta[l] * p_old[l * nn + v];
+                    sp[slot][l][t] = pn;
+                    if (interior) p_new[l * nn + v] = pn;
+                }
+            } else {
+                (void)interior;
+#pragma unroll
+                for (int l = 0; l < 3; ++l) sp[slot][l][t] = r[l * nn + v];
+            }
+        }
+    };
+    auto fill_k = [&](int ze) {
+        const int slot = (ze - z0 + 1) & 1;
+        const int64_t zoff = (int64_t)((ze + n) % n) * n2;
+        for (int t = tid; t < KA; t += kBlock) {
+            const int kx = t % KX, ky = t / KX;
+            const int gi = (i0 - 1 + kx + n) % n, gj = (j0 - 1 + ky + n) % n;
+            sk[slot][t] = k[gi + (int64_t)n * gj + zoff];
+        }
+    };
+
+    fill_p(z0 - 1);
+    fill_p(z0);
+    fill_k(z0 - 1);
+    for (int z = z0; z < z1; ++z) {
+        fill_p(z + 1);
+        fill_k(z);
+        __syncthreads();
+        if (own) {
+            const int sm = (z - z0) % 3, s0 = (z - z0 + 1) % 3, s1 = (z - z0 + 2) % 3;
+            const int km = (z - z0) & 1, k0 = (z - z0 + 1) & 1;
+            T ko[8];
+#pragma unroll
+            for (int o = 0; o < 8; ++o) {
+                const int a = o & 1, b = (o >> 1) & 1, c = o >> 2;
+                ko[o] = sk[c ? k0 : km][(ty + b) * KX + tx + a];
+            }
+            NodeCoef<T> cf;
+            node_coefs(ko, cf);
+            const int pc = (ty + 1) * PX + (tx + 1);
+            const int64_t v = i + (int64_t)n * j + (int64_t)z * n2;
+#pragma unroll
+            for (int l = 0; l < 3; ++l) {
+                if (!act[l]) continue;
+                const T y = stencil_lds<T>(cf, sp[sm][l], sp[s0][l], sp[s1][l], pc, PX);
+                q[l * nn + v] = y;
+                if (DIR) acc[l] += (double)sp[s0][l][pc] * (double)y;
+            }
+        }
+        __syncthreads();
+    }
+    if (!DIR) return;
+    block_partials<3>(acc, partials);
+}
+
+template <typename T, int V>
+__global__ void __launch_bounds__(kBlock) k_update_vec(int64_t nn, T* __restrict__ x, T* __restrict__ r,
+                                                       const T* __restrict__ p, const T* __restrict__ q,
+                                                       const T* __restrict__ dinv, double* partials,
+                                                       unsigned* counter, Scalars* sc) {
+    typedef T VT __attribute__((ext_vector_type(V)));
+    const int64_t nv = nn / V;
+    const int act[3] = {sc->active[0], sc->active[1], sc->active[2]};
+    const T alpha[3] = {(T)sc->alpha[0], (T)sc->alpha[1], (T)sc->alpha[2]};
+    double acc[6] = {0, 0, 0, 0, 0, 0};
+    const VT* dv4 = reinterpret_cast<const VT*>(dinv);
+    for (int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x; t < nv; t += (int64_t)gridDim.x * kBlock) {
+        const VT dv = dv4[t];
+#pragma unroll
+        for (int l = 0; l < 3; ++l) {
+            if (!act[l]) continue;
+            VT* xv = reinterpret_cast<VT*>(x + l * nn);
+            VT* rv = reinterpret_cast<VT*>(r + l * nn);
+            const VT pv = reinterpret_cast<const VT*>(p + l * nn)[t];
+            const VT qv = reinterpret_cast<const VT*>(q + l * nn)[t];
+            VT xx = xv[t];
+            VT rr = rv[t];
+            xx += alpha[l] * pv;
+            rr -= alpha[l] * qv;
+            xv[t] = xx;
+            rv[t] = rr;
+#pragma unroll
+            for (int c = 0; c < V; ++c) {
+                const double rd = (double)rr[c];
+                acc[l] += (double)dv[c] * rd * rd;
+                acc[3 + l] += rd * rd;
+            }
+        }
+    }
+    block_partials<6>(acc, partials);
+}
+
+// ---------------------------------------------------------------- launchers
+
+static inline int64_t cube(int n) { return (int64_t)n * n * n; }
+
+TileShape choose_tile(int n, int max_blocks, int tz_override) {
+    TileShape t;
+    if (n <= 24) {
+        t.tx = 16;
+        t.ty = 16;
+    } else {
+        t.tx = 32;
+        t.ty = 8;
+    }
+    const int ntx = (n + t.tx - 1) / t.tx, nty = (n + t.ty - 1) / t.ty;
+    int tz = tz_override;
+    if (tz <= 0) {
+        // aim at ~1024 blocks (4 per CU) with at least 2 planes per march
+        const int64_t cols = (int64_t)ntx * nty;
+        tz = (int)((cols * n + 1023) / 1024);
+        if (tz < 2) tz = 2;
+    }
+    if (tz > n) tz = n;
+    while ((int64_t)ntx * nty * ((n + tz - 1) / tz) > max_blocks && tz < n) ++tz;
+    t.tz = tz;
+    t.blocks = ntx * nty * ((n + tz - 1) / tz);
+    return t;
+}
+
+template <typename T>
+void launch_dir_apply(int n, const TileShape& t, const T* r, const T* dinv, const T* p_old, T* p_new, const T* k,
+                      T* q, const Workspace& ws, hipStream_t s) {
+    const int ntx = (n + t.tx - 1) / t.tx, nty = (n + t.ty - 1) / t.ty;
+    if (t.tx == 16)
+        hipLaunchKernelGGL((k_tiled<T, 16, 16, true>), dim3(t.blocks), dim3(kBlock), 0, s, n, t.tz, ntx, nty, r,
+                           dinv, p_old, p_new, k, q, ws.partials, ws.counter, ws.sc);
+    else if (t.tx == 64)
+        hipLaunchKernelGGL((k_tiled<T, 64, 4, true>), dim3(t.blocks), dim3(kBlock), 0, s, n, t.tz, ntx, nty, r,
+                           dinv, p_old, p_new, k, q, ws.partials, ws.counter, ws.sc);
+    else
+        hipLaunchKernelGGL((k_tiled<T, 32, 8, true>), dim3(t.blocks), dim3(kBlock), 0, s, n, t.tz, ntx, nty, r,
+                           dinv, p_old, p_new, k, q, ws.partials, ws.counter, ws.sc);
+    launch_finalize(FIN_PQ, t.blocks, ws, s);
+}
+
+template <typename T>
+void launch_apply_tiled(int n, const TileShape& t, const T* k, const T* x, T* y, hipStream_t s) {
+    const int ntx = (n + t.tx - 1) / t.tx, nty = (n + t.ty - 1) / t.ty;
+    if (t.tx == 16)
+        hipLaunchKernelGGL((k_tiled<T, 16, 16, false>), dim3(t.blocks), dim3(kBlock), 0, s, n, t.tz, ntx, nty, x,
+                           (const T*)nullptr, (const T*)nullptr, (T*)nullptr, k, y, (double*)nullptr,
+                           (unsigned*)nullptr, (Scalars*)nullptr);
+    else if (t.tx == 64)
+        hipLaunchKernelGGL((k_tiled<T, 64, 4, false>), dim3(t.blocks), dim3(kBlock), 0, s, n, t.tz, ntx, nty, x,
+                           (const T*)nullptr, (const T*)nullptr, (T*)nullptr, k, y, (double*)nullptr,
+                           (unsigned*)nullptr, (Scalars*)nullptr);
+    else
+        hipLaunchKernelGGL((k_tiled<T, 32, 8, false>), dim3(t.blocks), dim3(kBlock), 0, s, n, t.tz, ntx, nty, x,
+                           (const T*)nullptr, (const T*)nullptr, (T*)nullptr, k, y, (double*)nullptr,
+                           (unsigned*)nullptr, (Scalars*)nullptr);
+}
+
+template <typename T>
+void launch_update_vec(int n, T* x, T* r, const T* p, const T* q, const T* dinv, const Workspace& ws, hipStream_t s) {
+    constexpr int V = 16 / sizeof(T);
+    const int64_t nn = cube(n);
+    if (nn % V != 0) {
+        launch_update<T>(n, x, r, p, q, dinv, ws, s);
+        return;
+    }
+    const int g = grid_for(nn / V, ws.max_blocks);
+    hipLaunchKernelGGL((k_update_vec<T, V>), dim3(g), dim3(kBlock), 0, s, nn, x, r, p, q, dinv, ws.partials,
+                       ws.counter, ws.sc);
+    launch_finalize(FIN_UPDATE, g, ws, s);
+}
+
+template void launch_dir_apply<double>(int, const TileShape&, const double*, const double*, const double*, double*,
+                                       const double*, double*, const Workspace&, hipStream_t);
+template void launch_dir_apply<float>(int, const TileShape&, const float*, const float*, const float*, float*,
+                                      const float*, float*, const Workspace&, hipStream_t);
+template void launch_apply_tiled<double>(int, const TileShape&, const double*, const double*, double*, hipStream_t);
+template void launch_apply_tiled<float>(int, const TileShape&, const float*, const float*, float*, hipStream_t);
+template void launch_update_vec<double>(int, double*, double*, const double*, const double*, const double*,
+                                        const Workspace&, hipStream_t);
+template void launch_update_vec<float>(int, float*, float*, const float*, const float*, const float*,
+                                       const Workspace&, hipStream_t);
+
+}  // namespace otm

@@ -1,0 +1,71 @@
+"""Host-side checks of the C ABI library (no GPU needed).
+
+The library must load, export every function include/opentm_amd.h declares,
+and reject invalid problems before touching a device.
+"""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "opentm_amd.h")
+
+
+def header_functions():
+    text = open(HEADER).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(otm_[a-z0-9_]+)\s*\(", text)))
+
+
+@pytest.fixture(scope="module")
+def L():
+    from paper_2405_19991_amd import _native as N
+    if not os.path.exists(N.LIBPATH):
+        pytest.fail("libopentm_amd.so is not built; run __graft_entry__.build()")
+    return N.lib()
+
+
+def test_exports_match_header(L):
+    from paper_2405_19991_amd import _native as N
+    declared = header_functions()
+    assert declared, "no functions parsed from the header"
+    assert sorted(N.EXPORTED) == declared
+    for name in declared:
+        assert hasattr(L, name), name
+
+
+def test_version_and_strerror(L):
+    assert b"gfx950" in L.otm_version()
+    for code in (0, 1, -1, -2, -3, -4, -5, -6):
+        assert L.otm_strerror(code)
+    assert L.otm_strerror(99) == b"unknown status"
+
+
+def test_default_options_follow_paper_parameters(L):
+    from paper_2405_19991_amd import _native as N
+    s, o, g = N.default_options()
+    assert (o.move, o.eta, o.rho_min) == (0.05, 0.5, 1e-3)
+    assert (g.bound, g.decay, g.rebound, g.patience) == (1e-4, 0.8, 0.3, 5)
+    assert s.precision == N.OTM_FP64 and s.tol > 0 and s.check_every >= 1
+
+
+@pytest.mark.parametrize("field,value", [("n", 2), ("n", 2000), ("kmin", 0.0), ("kmin", 2.0), ("penal", 0.5),
+                                         ("vf", 0.0), ("vf", 1.5), ("filter_radius", float("nan"))])
+def test_create_rejects_invalid_problem(L, field, value):
+    from paper_2405_19991_amd import _native as N
+    p = N.Problem()
+    p.n, p.k0, p.kmin, p.penal, p.filter_radius, p.vf = 8, 1.0, 1e-3, 3.0, 1.5, 0.3
+    setattr(p, field, value)
+    h = ctypes.c_void_p()
+    rc = L.otm_create(ctypes.byref(p), None, None, None, None, ctypes.byref(h))
+    assert rc == N.OTM_EINVAL
+    assert not h.value
+
+
+def test_null_arguments(L):
+    from paper_2405_19991_amd import _native as N
+    assert L.otm_create(None, None, None, None, None, None) == N.OTM_EINVAL
+    assert L.otm_apply_device(2, 0, 0, None, None, None, None) == N.OTM_EINVAL
+    assert L.otm_last_error(None) == b"null context"
