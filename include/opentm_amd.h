@@ -94,9 +94,13 @@ typedef struct {
     int32_t check_every; /* host convergence check interval (iterations), >= 1 */
     double reliable_delta; /* OTM_MIXED: refresh the float64 residual when the float32
                               recursive residual has dropped by this factor */
-    int32_t kernel_variant; /* 0: LDS-tiled fused kernels (default); 1: direct-gather
-                               kernels (same arithmetic, kept as a cross-check) */
-    int32_t tile_tz;        /* planes per z-march of the tiled kernel; 0 = automatic */
+    int32_t kernel_variant; /* 0: streaming z-march kernels (default; two nodes per
+                               thread when n is even); 1: direct-gather kernels;
+                               2: LDS-ring tiled kernels; 3: z-march with one node
+                               per thread (same arithmetic, kept as cross-checks) */
+    int32_t tile_tz;        /* planes per z-march of the operator kernel; 0 = automatic */
+    int32_t tile_tx;        /* tile width in x in nodes: 16, 32 or 64 (32 or 64 for the
+                               two-node kernel); 0 = automatic */
 } otm_solver_opts;
 
 typedef struct {
@@ -218,16 +222,19 @@ int otm_prepare(otm_ctx* ctx);
  * of an n^3 cell ([KT]_v of Sec. 2.4).  k_dev: n^3 element conductivities;
  * x_dev, y_dev: 3 n^3 node values, load-major, not aliased.  precision
  * OTM_FP64 -> all pointers are double*; OTM_MIXED -> all are float*.
- * variant: 0 = LDS-tiled kernel, 1 = direct-gather kernel.
+ * variant: 0 = streaming z-march (two nodes per thread for even n),
+ * 1 = direct gather, 2 = LDS-ring tiled, 3 = z-march, one node per thread.
  * stream: hipStream_t or NULL.  Asynchronous on `stream`. */
 int otm_apply_device(int32_t n, int32_t precision, int32_t variant, const void* k_dev, const void* x_dev,
                      void* y_dev, void* stream);
 
 /* Timing of the stateless operator: runs `reps` launches of the operator on
  * `stream` and returns the mean kernel duration in microseconds, measured
- * with HIP events on that stream. */
-int otm_time_apply_device(int32_t n, int32_t precision, int32_t variant, const void* k_dev, const void* x_dev,
-                          void* y_dev, void* stream, int32_t reps, double* us_per_launch);
+ * with HIP events on that stream.  tile_tx / tile_tz: tile shape of the
+ * z-march and ring kernels (0 = automatic). */
+int otm_time_apply_device(int32_t n, int32_t precision, int32_t variant, int32_t tile_tx, int32_t tile_tz,
+                          const void* k_dev, const void* x_dev, void* y_dev, void* stream, int32_t reps,
+                          double* us_per_launch);
 
 /* Per-phase timings of the last otm_step, milliseconds, HIP events on the
  * context stream: [filter+setup, solve, tensor, sensitivity, oc, total,

@@ -49,7 +49,7 @@ class Problem(ctypes.Structure):
 class SolverOpts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("guess", ctypes.c_int32), ("tol", ctypes.c_double),
                 ("max_iter", ctypes.c_int32), ("check_every", ctypes.c_int32), ("reliable_delta", ctypes.c_double),
-                ("kernel_variant", ctypes.c_int32), ("tile_tz", ctypes.c_int32)]
+                ("kernel_variant", ctypes.c_int32), ("tile_tz", ctypes.c_int32), ("tile_tx", ctypes.c_int32)]
 
 
 class OcOpts(ctypes.Structure):
@@ -123,7 +123,7 @@ def lib():
         "otm_apply": ([ctx, i32, dp, dp], ctypes.c_int),
         "otm_prepare": ([ctx], ctypes.c_int),
         "otm_apply_device": ([i32, i32, i32, vp, vp, vp, vp], ctypes.c_int),
-        "otm_time_apply_device": ([i32, i32, i32, vp, vp, vp, vp, i32, dp], ctypes.c_int),
+        "otm_time_apply_device": ([i32, i32, i32, i32, i32, vp, vp, vp, vp, i32, dp], ctypes.c_int),
         "otm_get_timings": ([ctx, dp], ctypes.c_int),
         "otm_strerror": ([ctypes.c_int], ctypes.c_char_p),
         "otm_last_error": ([ctx], ctypes.c_char_p),

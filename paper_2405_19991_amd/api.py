@@ -36,7 +36,7 @@ class Homogenization:
                  guess: str = "zero", tol: float = 1e-8, max_iter: int = 20000, check_every: int = 16,
                  reliable_delta: float = 1e-2, move: float = 0.05, eta: float = 0.5, rho_min: float = 1e-3,
                  governor: Optional[Dict[str, float]] = None, stream=None, kernel_variant: int = 0,
-                 tile_tz: int = 0):
+                 tile_tz: int = 0, tile_tx: int = 0):
         L = N.lib()
         self.n = int(n)
         p = N.Problem()
@@ -52,7 +52,7 @@ class Homogenization:
         s.precision = {"fp64": N.OTM_FP64, "mixed": N.OTM_MIXED}[precision]
         s.guess = {"zero": N.OTM_GUESS_ZERO, "previous": N.OTM_GUESS_PREVIOUS, "user": N.OTM_GUESS_USER}[guess]
         s.tol, s.max_iter, s.check_every, s.reliable_delta = float(tol), int(max_iter), int(check_every), float(reliable_delta)
-        s.kernel_variant, s.tile_tz = int(kernel_variant), int(tile_tz)
+        s.kernel_variant, s.tile_tz, s.tile_tx = int(kernel_variant), int(tile_tz), int(tile_tx)
         o.move, o.eta, o.rho_min = float(move), float(eta), float(rho_min)
         for key, val in (governor or {}).items():
             setattr(g, key, val)
@@ -206,13 +206,14 @@ def apply_device(k, x, y, precision: str = "fp64", stream=None, variant: int = 0
                                      ctypes.c_void_p(y.data_ptr()), ctypes.c_void_p(s)))
 
 
-def time_apply_device(k, x, y, precision: str = "fp64", reps: int = 50, stream=None, variant: int = 0) -> float:
+def time_apply_device(k, x, y, precision: str = "fp64", reps: int = 50, stream=None, variant: int = 0,
+                      tile_tx: int = 0, tile_tz: int = 0) -> float:
     import torch
     n = round(k.numel() ** (1.0 / 3.0))
     s = stream if stream is not None else torch.cuda.current_stream().cuda_stream
     us = ctypes.c_double()
     N.check(N.lib().otm_time_apply_device(n, N.OTM_FP64 if precision == "fp64" else N.OTM_MIXED, int(variant),
-                                          ctypes.c_void_p(k.data_ptr()), ctypes.c_void_p(x.data_ptr()),
+                                          int(tile_tx), int(tile_tz), ctypes.c_void_p(k.data_ptr()), ctypes.c_void_p(x.data_ptr()),
                                           ctypes.c_void_p(y.data_ptr()), ctypes.c_void_p(s), int(reps),
                                           ctypes.byref(us)))
     return us.value

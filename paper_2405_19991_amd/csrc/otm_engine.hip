@@ -61,7 +61,9 @@ struct otm_ctx {
     Scalars* h_sc = nullptr;  // pinned host mirror
     int max_blocks = 0;
     int pbuf = 0;
-    TileShape tile;
+    TileShape tile;   // one-node-per-thread kernels (ring, march)
+    TileShape tile2;  // pair kernel (even n)
+    bool use_pair = false;
 
     bool have_density = false;
     bool prepared = false;
@@ -200,6 +202,7 @@ int prepare(otm_ctx* c) {
 
 // ------------------------------------------------------------------ PCG
 bool all_inactive(const Scalars* s) { return !s->active[0] && !s->active[1] && !s->active[2]; }
+bool all_active(const Scalars* s) { return s->active[0] && s->active[1] && s->active[2]; }
 int max_iters(const Scalars* s) {
     int m = s->iters[0];
     if (s->iters[1] > m) m = s->iters[1];
@@ -237,7 +240,13 @@ int solve_fp64(otm_ctx* c, bool x_zero, otm_solve_stats* st) {
                 launch_apply_pq<double>(n, c->k, pn, c->q64, w, c->stream);
                 launch_update<double>(n, c->x, c->r64, pn, c->q64, c->dinv, w, c->stream);
             } else {
-                launch_dir_apply<double>(n, c->tile, c->r64, c->dinv, po, pn, c->k, c->q64, w, c->stream);
+                if (c->so.kernel_variant == 2)
+                    launch_dir_apply<double>(n, c->tile, c->r64, c->dinv, po, pn, c->k, c->q64, w, c->stream);
+                else if (c->use_pair)
+                    launch_dir_march2<double>(n, c->tile2, all_active(c->h_sc), c->r64, c->dinv, po, pn, c->k, c->q64, w,
+                                           c->stream);
+                else
+                    launch_dir_march<double>(n, c->tile, c->r64, c->dinv, po, pn, c->k, c->q64, w, c->stream);
                 launch_update_vec<double>(n, c->x, c->r64, pn, c->q64, c->dinv, w, c->stream);
             }
             c->pbuf ^= 1;
@@ -290,7 +299,13 @@ int solve_mixed(otm_ctx* c, bool x_zero, otm_solve_stats* st) {
                 launch_apply_pq<float>(n, c->k32, pn, c->q32, w, c->stream);
                 launch_update<float>(n, c->x32, c->r32, pn, c->q32, c->dinv32, w, c->stream);
             } else {
-                launch_dir_apply<float>(n, c->tile, c->r32, c->dinv32, po, pn, c->k32, c->q32, w, c->stream);
+                if (c->so.kernel_variant == 2)
+                    launch_dir_apply<float>(n, c->tile, c->r32, c->dinv32, po, pn, c->k32, c->q32, w, c->stream);
+                else if (c->use_pair)
+                    launch_dir_march2<float>(n, c->tile2, all_active(c->h_sc), c->r32, c->dinv32, po, pn, c->k32, c->q32, w,
+                                           c->stream);
+                else
+                    launch_dir_march<float>(n, c->tile, c->r32, c->dinv32, po, pn, c->k32, c->q32, w, c->stream);
                 launch_update_vec<float>(n, c->x32, c->r32, pn, c->q32, c->dinv32, w, c->stream);
             }
             c->pbuf ^= 1;
@@ -473,6 +488,7 @@ void otm_default_options(otm_solver_opts* s, otm_oc_opts* o, otm_governor_opts* 
         s->reliable_delta = 1e-2;
         s->kernel_variant = 0;
         s->tile_tz = 0;
+        s->tile_tx = 0;
     }
     if (o) {
         o->move = 0.05;
@@ -526,7 +542,8 @@ int otm_create(const otm_problem* problem, const otm_solver_opts* solver, const 
     if (!(c->so.tol > 0.0 && c->so.max_iter > 0 && c->so.check_every >= 1 && c->so.reliable_delta > 0.0 &&
           c->so.reliable_delta < 1.0 && (c->so.precision == OTM_FP64 || c->so.precision == OTM_MIXED) &&
           c->so.guess >= OTM_GUESS_ZERO && c->so.guess <= OTM_GUESS_USER &&
-          (c->so.kernel_variant == 0 || c->so.kernel_variant == 1) && c->so.tile_tz >= 0)) {
+          c->so.kernel_variant >= 0 && c->so.kernel_variant <= 3 && c->so.tile_tz >= 0 &&
+          (c->so.tile_tx == 0 || c->so.tile_tx == 16 || c->so.tile_tx == 32 || c->so.tile_tx == 64))) {
         delete c;
         return OTM_EINVAL;
     }
@@ -558,7 +575,9 @@ int otm_create(const otm_problem* problem, const otm_solver_opts* solver, const 
     }
     const int64_t nn = c->nn;
     c->max_blocks = 4096;
-    c->tile = choose_tile(c->n, c->max_blocks, c->so.tile_tz);
+    c->tile = choose_tile(c->n, c->max_blocks, c->so.tile_tz, c->so.tile_tx);
+    c->tile2 = choose_tile2(c->n, c->max_blocks, c->so.tile_tz, c->so.tile_tx);
+    c->use_pair = (c->so.kernel_variant == 0) && (c->n % 2 == 0);
     rc = OTM_OK;
     rc = rc ? rc : dalloc(c, &c->rho, nn);
     rc = rc ? rc : dalloc(c, &c->rhof, nn);
@@ -836,10 +855,16 @@ int otm_apply(otm_ctx* c, int32_t precision, const double* xh, double* yh) {
             return rc;
         }
         (void)hipMemcpyAsync(xd, xh, cnt * sizeof(double), hipMemcpyHostToDevice, c->stream);
+        const TileShape t = choose_tile(c->n, 1 << 30, c->so.tile_tz, c->so.tile_tx);
         if (c->so.kernel_variant == 1)
             launch_apply<double>(c->n, c->k, xd, yd, c->stream);
+        else if (c->so.kernel_variant == 2)
+            launch_apply_tiled<double>(c->n, t, c->k, xd, yd, c->stream);
+        else if (c->use_pair)
+            launch_apply_march2<double>(c->n, choose_tile2(c->n, 1 << 30, c->so.tile_tz, c->so.tile_tx), c->k, xd,
+                                        yd, c->stream);
         else
-            launch_apply_tiled<double>(c->n, choose_tile(c->n, 1 << 30, 0), c->k, xd, yd, c->stream);
+            launch_apply_march<double>(c->n, t, c->k, xd, yd, c->stream);
         (void)hipMemcpyAsync(yh, yd, cnt * sizeof(double), hipMemcpyDeviceToHost, c->stream);
         rc = check_launch(c, "apply");
         hipError_t e = hipStreamSynchronize(c->stream);
@@ -859,10 +884,16 @@ int otm_apply(otm_ctx* c, int32_t precision, const double* xh, double* yh) {
         (void)hipMemcpyAsync(xd, xh, cnt * sizeof(double), hipMemcpyHostToDevice, c->stream);
         launch_cast_f64_f32(cnt, xd, x32, c->stream);
         launch_cast_f64_f32(c->nn, c->k, k32, c->stream);
+        const TileShape t = choose_tile(c->n, 1 << 30, c->so.tile_tz, c->so.tile_tx);
         if (c->so.kernel_variant == 1)
             launch_apply<float>(c->n, k32, x32, y32, c->stream);
+        else if (c->so.kernel_variant == 2)
+            launch_apply_tiled<float>(c->n, t, k32, x32, y32, c->stream);
+        else if (c->use_pair)
+            launch_apply_march2<float>(c->n, choose_tile2(c->n, 1 << 30, c->so.tile_tz, c->so.tile_tx), k32, x32,
+                                       y32, c->stream);
         else
-            launch_apply_tiled<float>(c->n, choose_tile(c->n, 1 << 30, 0), k32, x32, y32, c->stream);
+            launch_apply_march<float>(c->n, t, k32, x32, y32, c->stream);
         launch_cast_f32_f64(cnt, y32, xd, c->stream);
         (void)hipMemcpyAsync(yh, xd, cnt * sizeof(double), hipMemcpyDeviceToHost, c->stream);
         rc = check_launch(c, "apply32");
@@ -876,38 +907,63 @@ int otm_apply(otm_ctx* c, int32_t precision, const double* xh, double* yh) {
     return rc;
 }
 
-int otm_apply_device(int32_t n, int32_t precision, int32_t variant, const void* k, const void* x, void* y,
-                     void* stream) {
+static int apply_device_impl(int32_t n, int32_t precision, int32_t variant, int32_t tx, int32_t tz, const void* k,
+                             const void* x, void* y, void* stream) {
     if (n < 4 || n > 1024 || !k || !x || !y) return OTM_EINVAL;
-    if (x == y || (variant != 0 && variant != 1)) return OTM_EINVAL;
+    if (x == y || variant < 0 || variant > 3) return OTM_EINVAL;
+    if (!(tx == 0 || tx == 16 || tx == 32 || tx == 64) || tz < 0) return OTM_EINVAL;
+    if (variant == 0 && n % 2 != 0) variant = 3;
+    if (variant == 0 && tx == 16) return OTM_EINVAL;
     hipStream_t s = (hipStream_t)stream;
-    const TileShape t = choose_tile(n, 1 << 30, 0);
+    const TileShape t = choose_tile(n, 1 << 30, tz, tx);
+    const TileShape t2 = choose_tile2(n, 1 << 30, tz, tx);
     if (precision == OTM_FP64) {
+        const double *kd = (const double*)k, *xd = (const double*)x;
+        double* yd = (double*)y;
         if (variant == 0)
-            launch_apply_tiled<double>(n, t, (const double*)k, (const double*)x, (double*)y, s);
+            launch_apply_march2<double>(n, t2, kd, xd, yd, s);
+        else if (variant == 1)
+            launch_apply<double>(n, kd, xd, yd, s);
+        else if (variant == 2)
+            launch_apply_tiled<double>(n, t, kd, xd, yd, s);
         else
-            launch_apply<double>(n, (const double*)k, (const double*)x, (double*)y, s);
+            launch_apply_march<double>(n, t, kd, xd, yd, s);
     } else if (precision == OTM_MIXED) {
+        const float *kf = (const float*)k, *xf = (const float*)x;
+        float* yf = (float*)y;
         if (variant == 0)
-            launch_apply_tiled<float>(n, t, (const float*)k, (const float*)x, (float*)y, s);
+            launch_apply_march2<float>(n, t2, kf, xf, yf, s);
+        else if (variant == 1)
+            launch_apply<float>(n, kf, xf, yf, s);
+        else if (variant == 2)
+            launch_apply_tiled<float>(n, t, kf, xf, yf, s);
         else
-            launch_apply<float>(n, (const float*)k, (const float*)x, (float*)y, s);
+            launch_apply_march<float>(n, t, kf, xf, yf, s);
     } else {
         return OTM_EINVAL;
     }
     return hipGetLastError() == hipSuccess ? OTM_OK : OTM_EDEVICE;
 }
 
-int otm_time_apply_device(int32_t n, int32_t precision, int32_t variant, const void* k, const void* x, void* y,
-                          void* stream, int32_t reps, double* us) {
+int otm_apply_device(int32_t n, int32_t precision, int32_t variant, const void* k, const void* x, void* y,
+                     void* stream) {
+    return apply_device_impl(n, precision, variant, 0, 0, k, x, y, stream);
+}
+
+int otm_time_apply_device(int32_t n, int32_t precision, int32_t variant, int32_t tx, int32_t tz, const void* k,
+                          const void* x, void* y, void* stream, int32_t reps, double* us) {
     if (reps < 1 || !us) return OTM_EINVAL;
     hipStream_t s = (hipStream_t)stream;
     hipEvent_t a, b;
     if (hipEventCreate(&a) != hipSuccess || hipEventCreate(&b) != hipSuccess) return OTM_EDEVICE;
-    int rc = otm_apply_device(n, precision, variant, k, x, y, stream);  // warm
-    if (rc) return rc;
+    int rc = apply_device_impl(n, precision, variant, tx, tz, k, x, y, stream);  // warm
+    if (rc) {
+        (void)hipEventDestroy(a);
+        (void)hipEventDestroy(b);
+        return rc;
+    }
     (void)hipEventRecord(a, s);
-    for (int q = 0; q < reps; ++q) otm_apply_device(n, precision, variant, k, x, y, stream);
+    for (int q = 0; q < reps; ++q) (void)apply_device_impl(n, precision, variant, tx, tz, k, x, y, stream);
     (void)hipEventRecord(b, s);
     if (hipEventSynchronize(b) != hipSuccess) return OTM_EDEVICE;
     float ms = 0.f;

@@ -110,10 +110,22 @@ struct TileShape {
     int tx = 32, ty = 8, tz = 8;  // nodes per block in x, y; planes per z-march
     int blocks = 0;
 };
-TileShape choose_tile(int n, int max_blocks, int tz_override);
+TileShape choose_tile(int n, int max_blocks, int tz_override, int tx_override = 0);
 template <typename T>
 void launch_dir_apply(int n, const TileShape& t, const T* r, const T* dinv, const T* p_old, T* p_new, const T* k,
                       T* q, const Workspace& ws, hipStream_t s);
+template <typename T>
+void launch_dir_march(int n, const TileShape& t, const T* r, const T* dinv, const T* p_old, T* p_new, const T* k,
+                      T* q, const Workspace& ws, hipStream_t s);
+template <typename T>
+void launch_apply_march(int n, const TileShape& t, const T* k, const T* x, T* y, hipStream_t s);
+// Pair kernel (otm_march2.hip): two x-adjacent nodes per thread, even n only.
+TileShape choose_tile2(int n, int max_blocks, int tz_override, int tx_override);
+template <typename T>
+void launch_dir_march2(int n, const TileShape& t, bool all_active, const T* r, const T* dinv, const T* p_old,
+                       T* p_new, const T* k, T* q, const Workspace& ws, hipStream_t s);
+template <typename T>
+void launch_apply_march2(int n, const TileShape& t, const T* k, const T* x, T* y, hipStream_t s);
 template <typename T>
 void launch_apply_tiled(int n, const TileShape& t, const T* k, const T* x, T* y, hipStream_t s);
 template <typename T>

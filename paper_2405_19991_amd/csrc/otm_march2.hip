@@ -1,0 +1,350 @@
+// Streaming z-march operator, two nodes per thread (gfx950).
+//
+// Same arithmetic as k_march (otm_stencil.hip): each incoming node plane P
+// finishes node P-1 (its dz=+1 taps), adds the in-plane taps of node P and
+// starts node P+1 (dz=-1 taps), using the conductivities of element planes
+// P-1 and P.  Here every thread owns the x-adjacent node pair (i, i+1), i even,
+// so global and LDS traffic use 8-byte (float2 / double2) accesses and each
+// LDS row of the 3x4 neighbourhood costs three reads instead of six.
+// Requires an even n (a pair never straddles the periodic wrap).
+//
+// The march is unrolled by two planes so that the two-plane register
+// prefetch alternates between two register sets without copies.
+#include "otm_device.h"
+
+namespace otm {
+
+template <typename T>
+struct V2 {
+    typedef T type __attribute__((ext_vector_type(2)));
+};
+
+template <typename T, bool DIR>
+struct Pre2 {
+    typename V2<T>::type r[3], po[3], dv;  // own pair
+    T hr[3], hpo[3], hdv;                  // one halo node
+    typename V2<T>::type k;                // own element pair
+    T kh;                                  // one halo element
+};
+
+// ALL: every load is active (DIR) -- removes the per-load branches.
+template <typename T, int WX, int TY, bool DIR, bool ALL>
+__global__ void __launch_bounds__(WX* TY) k_march2(int n, int tz, int ntx, int nty, const T* __restrict__ r,
+                                                   const T* __restrict__ dinv, const T* __restrict__ p_old,
+                                                   T* __restrict__ p_new, const T* __restrict__ k,
+                                                   T* __restrict__ q, double* __restrict__ partials,
+                                                   const Scalars* __restrict__ sc) {
+    typedef typename V2<T>::type T2;
+    static_assert(WX * TY == kBlock, "block size");
+    constexpr int TX = 2 * WX;                   // nodes per tile row
+    constexpr int PX = TX + 2, PY = TY + 2;       // padded plane (halo 1)
+    constexpr int PXP = TX + 4;                   // row pitch, even; element px lives at px + 1
+    constexpr int NH = 2 * PX + 2 * (PY - 2);     // halo nodes
+    constexpr int KX = TX + 1, KY = TY + 1;       // element plane, low-side halo
+    constexpr int KXP = TX + 2;                   // even pitch; element kx lives at kx + 1
+    constexpr int NKH = KX + KY - 1;
+    static_assert(NH <= kBlock && NKH <= kBlock, "halo");
+    __shared__ __attribute__((aligned(16))) T sp[2][3][PY * PXP];
+    __shared__ __attribute__((aligned(16))) T sk[2][KY * KXP];
+
+    const int tid = threadIdx.x;
+    const int tx = tid % WX, ty = tid / WX;
+    int bid = blockIdx.x;
+    const int bx = bid % ntx;
+    bid /= ntx;
+    const int by = bid % nty;
+    const int bz = bid / nty;
+    const int i0 = bx * TX, j0 = by * TY, z0 = bz * tz;
+    const int z1 = min(z0 + tz, n);
+    const int64_t nn = (int64_t)n * n * n;
+    const int64_t n2 = (int64_t)n * n;
+
+    bool act[3] = {true, true, true};
+    T beta[3] = {(T)0, (T)0, (T)0};
+    if (DIR) {
+#pragma unroll
+        for (int l = 0; l < 3; ++l) {
+            act[l] = ALL ? true : (sc->active[l] != 0);
+            beta[l] = (T)sc->beta[l];
+        }
+    }
+    const int i = i0 + 2 * tx, j = j0 + ty;
+    const bool own_a = (i < n) && (j < n);
+    const bool own_b = (i + 1 < n) && (j < n);
+    const uint32_t xy_own = (uint32_t)(i % n) + (uint32_t)n * (uint32_t)(j % n);  // even
+    const int lp = (ty + 1) * PXP + (2 * tx + 1) + 1;  // LDS index of node a (even)
+    const int lk = (ty + 1) * KXP + (2 * tx + 1) + 1;  // LDS index of element a (even)
+    const bool has_h = tid < NH;
+    uint32_t xy_h = 0;
+    int lph = 0;
+    if (has_h) {
+        int px, py;
+        if (tid < PX) {
+            px = tid;
+            py = 0;
+        } else if (tid < 2 * PX) {
+            px = tid - PX;
+            py = PY - 1;
+        } else if (tid < 2 * PX + (PY - 2)) {
+            px = 0;
+            py = 1 + (tid - 2 * PX);
+        } else {
+            px = PX - 1;
+            py = 1 + (tid - 2 * PX - (PY - 2));
+        }
+        const int gi = (i0 - 1 + px + n) % n, gj = (j0 - 1 + py + n) % n;
+        xy_h = (uint32_t)gi + (uint32_t)n * (uint32_t)gj;
+        lph = py * PXP + px + 1;
+    }
+    const bool has_kh = tid < NKH;
+    uint32_t xy_kh = 0;
+    int lkh = 0;
+    if (has_kh) {
+        int kx, ky;
+        if (tid < KX) {
+            kx = tid;
+            ky = 0;
+        } else {
+            kx = 0;
+            ky = 1 + (tid - KX);
+        }
+        const int gi = (i0 - 1 + kx + n) % n, gj = (j0 - 1 + ky + n) % n;
+        xy_kh = (uint32_t)gi + (uint32_t)n * (uint32_t)gj;
+        lkh = ky * KXP + kx + 1;
+    }
+
+    auto plane_off = [&](int P) -> int64_t {
+        const int pw = P < 0 ? P + n : (P >= n ? P - n : P);
+        return (int64_t)pw * n2;
+    };
+
+    auto load_plane = [&](int P, Pre2<T, DIR>& f) {
+        const int64_t zoff = plane_off(P);
+        if (DIR) {
+            const T* dp = dinv + zoff;
+            f.dv = *reinterpret_cast<const T2*>(dp + xy_own);
+            if (has_h) f.hdv = dp[xy_h];
+        }
+#pragma unroll
+        for (int l = 0; l < 3; ++l) {
+            if (!act[l]) continue;
+            const T* rp = r + l * nn + zoff;
+            f.r[l] = *reinterpret_cast<const T2*>(rp + xy_own);
+            if (has_h) f.hr[l] = rp[xy_h];
+            if (DIR && beta[l] != (T)0) {
+                const T* pp = p_old + l * nn + zoff;
+                f.po[l] = *reinterpret_cast<const T2*>(pp + xy_own);
+                if (has_h) f.hpo[l] = pp[xy_h];
+            }
+        }
+        const T* kp = k + zoff;
+        f.k = *reinterpret_cast<const T2*>(kp + xy_own);
+        if (has_kh) f.kh = kp[xy_kh];
+    };
+
+    T2 pP[3];
+    auto store_plane = [&](int P, const Pre2<T, DIR>& f) {
+        const int slot = P & 1;
+        const bool in_range = P >= z0 && P < z1;
+        const int64_t zoff = plane_off(P);
+#pragma unroll
+        for (int l = 0; l < 3; ++l) {
+            if (!act[l]) continue;
+            T2 val = f.r[l];
+            T hv = f.hr[l];
+            if (DIR) {
+                val = f.dv * f.r[l];
+                hv = f.hdv * f.hr[l];
+                if (beta[l] != (T)0) {
+                    val += beta[l] * f.po[l];
+                    hv += beta[l] * f.hpo[l];
+                }
+                if (in_range) {
+                    T* pn = p_new + l * nn + zoff + xy_own;
+                    if (own_b)
+                        *reinterpret_cast<T2*>(pn) = val;
+                    else if (own_a)
+                        pn[0] = val.x;
+                }
+            }
+            *reinterpret_cast<T2*>(&sp[slot][l][lp]) = val;
+            if (has_h) sp[slot][l][lph] = hv;
+            pP[l] = val;
+        }
+        *reinterpret_cast<T2*>(&sk[slot][lk]) = f.k;
+        if (has_kh) sk[slot][lkh] = f.kh;
+    };
+
+    const T w = (T)(1.0 / 12.0);
+    const T third = (T)(1.0 / 3.0);
+    T2 yA[3], yB[3], pB[3];
+#pragma unroll
+    for (int l = 0; l < 3; ++l) {
+        yA[l] = (T2)((T)0);
+        yB[l] = (T2)((T)0);
+        pB[l] = (T2)((T)0);
+    }
+    // conductivities of the previous element plane around nodes a and b:
+    // kp = elements (i-1, i, i+1) at rows j-1 (m) and j (c)
+    T kpm0 = 0, kpm1 = 0, kpm2 = 0, kpc0 = 0, kpc1 = 0, kpc2 = 0;
+    double acc[3] = {0.0, 0.0, 0.0};
+
+    auto compute = [&](int P) {
+        const int slot = P & 1;
+        const T* K = sk[slot];
+        // element plane P: rows j-1 and j, columns i-1, i, i+1
+        const T km0 = K[lk - KXP - 1];
+        const T2 km12 = *reinterpret_cast<const T2*>(&K[lk - KXP]);
+        const T kc0 = K[lk - 1];
+        const T2 kc12 = *reinterpret_cast<const T2*>(&K[lk]);
+        const T km1 = km12.x, km2 = km12.y, kc1 = kc12.x, kc2 = kc12.y;
+        // node a uses columns (0,1), node b columns (1,2); K order (i-1,j-1),(i,j-1),(i-1,j),(i,j)
+        // previous plane pair sums / in-plane sums, per node
+        const T pa_xm = kpm0 + kpc0, pa_xp = kpm1 + kpc1, pa_ym = kpm0 + kpm1, pa_yp = kpc0 + kpc1;
+        const T pb_xm = kpm1 + kpc1, pb_xp = kpm2 + kpc2, pb_ym = kpm1 + kpm2, pb_yp = kpc1 + kpc2;
+        const T ca_xm = km0 + kc0, ca_xp = km1 + kc1, ca_ym = km0 + km1, ca_yp = kc0 + kc1;
+        const T cb_xm = km1 + kc1, cb_xp = km2 + kc2, cb_ym = km1 + km2, cb_yp = kc1 + kc2;
+        const T ea0 = kpm0 + km0, ea1 = kpm1 + km1, ea2 = kpc0 + kc0, ea3 = kpc1 + kc1;
+        const T eb0 = kpm1 + km1, eb1 = kpm2 + km2, eb2 = kpc1 + kc1, eb3 = kpc2 + kc2;
+        const T c0a = (ea0 + ea1 + ea2 + ea3) * third;
+        const T c0b = (eb0 + eb1 + eb2 + eb3) * third;
+        const bool done = P - 1 >= z0;
+        const int64_t vdone = (int64_t)(P - 1 < 0 ? 0 : (P - 1)) * n2 + xy_own;
+#pragma unroll
+        for (int l = 0; l < 3; ++l) {
+            if (!act[l]) continue;
+            const T* L = sp[slot][l];
+            // rows j-1 (m), j (c), j+1 (p); columns i-1 | i, i+1 | i+2
+            const T m0 = L[lp - PXP - 1];
+            const T2 m12 = *reinterpret_cast<const T2*>(&L[lp - PXP]);
+            const T m3 = L[lp - PXP + 2];
+            const T c0v = L[lp - 1];
+            const T2 c12 = *reinterpret_cast<const T2*>(&L[lp]);
+            const T c3 = L[lp + 2];
+            const T p0 = L[lp + PXP - 1];
+            const T2 p12 = *reinterpret_cast<const T2*>(&L[lp + PXP]);
+            const T p3 = L[lp + PXP + 2];
+            const T m1 = m12.x, m2 = m12.y, c1 = c12.x, c2 = c12.y, p1 = p12.x, p2 = p12.y;
+            // node a: xm=c0v xc=c1 xp=c2, ym=m1 yp=p1, diagonals m0 m2 p0 p2
+            const T opa = pa_xm * c0v + pa_xp * c2 + pa_ym * m1 + pa_yp * p1 + kpm0 * m0 + kpm1 * m2 + kpc0 * p0 +
+                          kpc1 * p2;
+            const T oca = ca_xm * c0v + ca_xp * c2 + ca_ym * m1 + ca_yp * p1 + km0 * m0 + km1 * m2 + kc0 * p0 +
+                          kc1 * p2;
+            const T ina = c0a * c1 - w * (ea0 * m0 + ea1 * m2 + ea2 * p0 + ea3 * p2);
+            // node b: xm=c1 xc=c2 xp=c3, ym=m2 yp=p2, diagonals m1 m3 p1 p3
+            const T opb = pb_xm * c1 + pb_xp * c3 + pb_ym * m2 + pb_yp * p2 + kpm1 * m1 + kpm2 * m3 + kpc1 * p1 +
+                          kpc2 * p3;
+            const T ocb = cb_xm * c1 + cb_xp * c3 + cb_ym * m2 + cb_yp * p2 + km1 * m1 + km2 * m3 + kc1 * p1 +
+                          kc2 * p3;
+            const T inb = c0b * c2 - w * (eb0 * m1 + eb1 * m3 + eb2 * p1 + eb3 * p3);
+            T2 ya;
+            ya.x = yA[l].x - w * opa;
+            ya.y = yA[l].y - w * opb;
+            if (done) {
+                T* qp = q + l * nn + vdone;
+                if (own_b)
+                    *reinterpret_cast<T2*>(qp) = ya;
+                else if (own_a)
+                    qp[0] = ya.x;
+                if (DIR) {
+                    if (own_a) acc[l] += (double)pB[l].x * (double)ya.x;
+                    if (own_b) acc[l] += (double)pB[l].y * (double)ya.y;
+                }
+            }
+            T2 yb;
+            yb.x = yB[l].x + ina;
+            yb.y = yB[l].y + inb;
+            yA[l] = yb;
+            yB[l].x = -w * oca;
+            yB[l].y = -w * ocb;
+            pB[l] = pP[l];
+        }
+        kpm0 = km0;
+        kpm1 = km1;
+        kpm2 = km2;
+        kpc0 = kc0;
+        kpc1 = kc1;
+        kpc2 = kc2;
+    };
+
+    Pre2<T, DIR> fa, fb;
+    load_plane(z0 - 1, fa);
+    load_plane(z0, fb);
+    int P = z0 - 1;
+    // two planes per trip: (fa holds P, fb holds P+1) -> (fb holds P+1, fa holds P+2)
+    for (; P + 1 <= z1; P += 2) {
+        store_plane(P, fa);
+        if (P + 2 <= z1) load_plane(P + 2, fa);
+        __syncthreads();
+        compute(P);
+        store_plane(P + 1, fb);
+        if (P + 3 <= z1) load_plane(P + 3, fb);
+        __syncthreads();
+        compute(P + 1);
+    }
+    if (P <= z1) {  // odd number of planes: the last one sits in fa
+        store_plane(P, fa);
+        __syncthreads();
+        compute(P);
+    }
+    if (!DIR) return;
+    block_partials<3>(acc, partials);
+}
+
+template <typename T, bool DIR, bool ALL>
+static void launch_m2(int n, const TileShape& t, const T* r, const T* dinv, const T* p_old, T* p_new, const T* k,
+                      T* q, double* partials, const Scalars* sc, hipStream_t s) {
+    const int ntx = (n + t.tx - 1) / t.tx, nty = (n + t.ty - 1) / t.ty;
+    if (t.tx == 32)
+        hipLaunchKernelGGL((k_march2<T, 16, 16, DIR, ALL>), dim3(t.blocks), dim3(kBlock), 0, s, n, t.tz, ntx, nty, r,
+                           dinv, p_old, p_new, k, q, partials, sc);
+    else
+        hipLaunchKernelGGL((k_march2<T, 32, 8, DIR, ALL>), dim3(t.blocks), dim3(kBlock), 0, s, n, t.tz, ntx, nty, r,
+                           dinv, p_old, p_new, k, q, partials, sc);
+}
+
+// Tile shapes of the pair kernel: tx in {32, 64} nodes (16 or 32 threads wide).
+TileShape choose_tile2(int n, int max_blocks, int tz_override, int tx_override) {
+    TileShape t;
+    if (tx_override == 32 || tx_override == 64)
+        t.tx = tx_override;
+    else
+        t.tx = n <= 40 ? 32 : 64;
+    t.ty = kBlock / (t.tx / 2);
+    const int ntx = (n + t.tx - 1) / t.tx, nty = (n + t.ty - 1) / t.ty;
+    int tz = tz_override;
+    if (tz <= 0) {
+        const int64_t cols = (int64_t)ntx * nty;
+        tz = (int)((cols * n + 1023) / 1024);
+        if (tz < 2) tz = 2;
+    }
+    if (tz > n) tz = n;
+    while ((int64_t)ntx * nty * ((n + tz - 1) / tz) > max_blocks && tz < n) ++tz;
+    t.tz = tz;
+    t.blocks = ntx * nty * ((n + tz - 1) / tz);
+    return t;
+}
+
+template <typename T>
+void launch_dir_march2(int n, const TileShape& t, bool all_active, const T* r, const T* dinv, const T* p_old,
+                       T* p_new, const T* k, T* q, const Workspace& ws, hipStream_t s) {
+    if (all_active)
+        launch_m2<T, true, true>(n, t, r, dinv, p_old, p_new, k, q, ws.partials, ws.sc, s);
+    else
+        launch_m2<T, true, false>(n, t, r, dinv, p_old, p_new, k, q, ws.partials, ws.sc, s);
+    launch_finalize(FIN_PQ, t.blocks, ws, s);
+}
+
+template <typename T>
+void launch_apply_march2(int n, const TileShape& t, const T* k, const T* x, T* y, hipStream_t s) {
+    launch_m2<T, false, true>(n, t, x, nullptr, nullptr, nullptr, k, y, nullptr, nullptr, s);
+}
+
+template void launch_dir_march2<double>(int, const TileShape&, bool, const double*, const double*, const double*,
+                                        double*, const double*, double*, const Workspace&, hipStream_t);
+template void launch_dir_march2<float>(int, const TileShape&, bool, const float*, const float*, const float*, float*,
+                                       const float*, float*, const Workspace&, hipStream_t);
+template void launch_apply_march2<double>(int, const TileShape&, const double*, const double*, double*, hipStream_t);
+template void launch_apply_march2<float>(int, const TileShape&, const float*, const float*, float*, hipStream_t);
+
+}  // namespace otm

@@ -45,7 +45,7 @@ def abs_scale(A: O.CSR27, x):
 
 # ------------------------------------------------------------------ operator
 
-@pytest.mark.parametrize("variant", [0, 1])
+@pytest.mark.parametrize("variant", [0, 1, 2, 3])
 @pytest.mark.parametrize("n", [5, 12, 13, 16, 33])
 def test_apply_fp64(n, variant):
     rho = synth.random_field(n, 100 + n, 1e-3, 1.0)
@@ -61,7 +61,7 @@ def test_apply_fp64(n, variant):
     assert np.all(np.abs(y - y_ref) <= 64 * np.finfo(float).eps * scale + 1e-300)
 
 
-@pytest.mark.parametrize("variant", [0, 1])
+@pytest.mark.parametrize("variant", [0, 1, 2, 3])
 @pytest.mark.parametrize("n", [5, 16, 40])
 def test_apply_mixed(n, variant):
     rho = synth.random_field(n, 300 + n, 1e-3, 1.0)
@@ -82,7 +82,7 @@ def test_stateless_apply_device_variants():
     agree with the oracle at a size with several tiles and a ragged tail."""
     import torch
     from paper_2405_19991_amd import apply_device
-    n = 37
+    n = 38
     rho = synth.random_field(n, 41, 1e-3, 1.0)
     prm = O.Params()
     k = O.simp(O.density_filter(rho, prm.rfilter), prm.k0, prm.kmin, prm.penal)
@@ -93,12 +93,42 @@ def test_stateless_apply_device_variants():
     for prec, dt, eps in (("fp64", torch.float64, np.finfo(float).eps), ("mixed", torch.float32, np.finfo(np.float32).eps)):
         kd = torch.from_numpy(k.reshape(-1)).to(dt).cuda()
         xd = torch.from_numpy(x.reshape(-1)).to(dt).cuda()
-        for variant in (0, 1):
+        for variant in (0, 1, 2, 3):
             yd = torch.full_like(xd, float("nan"))
             apply_device(kd, xd, yd, prec, variant=variant)
             torch.cuda.synchronize()
             y = yd.double().cpu().numpy().reshape(3, n, n, n)
             assert np.all(np.abs(y - y_ref) <= 64 * eps * scale), (prec, variant)
+
+
+@pytest.mark.parametrize("tx,tz", [(16, 1), (32, 3), (64, 2), (64, 7), (16, 40), (32, 1)])
+@pytest.mark.parametrize("n", [20, 37, 38])
+def test_apply_tile_shapes(n, tx, tz):
+    """The z-march and ring kernels for every tile width, plane counts that do
+    and do not divide n, and tiles wider than the cell (n < tile width)."""
+    rho = synth.random_field(n, 70 + n, 1e-3, 1.0)
+    x = synth.random_vectors(n, 3, 71 + n)
+    prm = O.Params()
+    k = O.simp(O.density_filter(rho, prm.rfilter), prm.k0, prm.kmin, prm.penal)
+    A = O.assemble(k)
+    y_ref = np.stack([A.matvec(x[i]) for i in range(3)])
+    scale = abs_scale(A, x)
+    for variant in (0, 2, 3):
+        with make(n, rho, kernel_variant=variant, tile_tx=tx, tile_tz=tz) as h:
+            h.prepare()
+            y = h.apply(x, "fp64")
+        assert np.all(np.abs(y - y_ref) <= 64 * np.finfo(float).eps * scale), variant
+
+
+def test_pcg_tile_shapes_agree():
+    """Full FP64 solves with different z-march tiles give the same tensor."""
+    n = 24
+    rho = synth.smoothed_noise(n, 0.05, 0.95, 73)
+    ref = O.homogenize(rho, O.Params(tol=1e-13))
+    for variant, tx, tz in ((0, 32, 5), (0, 64, 3), (3, 16, 5), (3, 32, 2), (3, 64, 24), (2, 32, 4)):
+        with make(n, rho, tol=1e-11, tile_tx=tx, tile_tz=tz, kernel_variant=variant) as h:
+            kappa, st = h.homogenize()
+        assert st["converged"] and rel_fro(kappa, ref["kappa"]) <= 1e-9, (variant, tx, tz)
 
 
 # ------------------------------------------------------------- setup fields
@@ -136,7 +166,7 @@ def rel_fro(a, b):
     return np.linalg.norm(np.asarray(a) - np.asarray(b)) / np.linalg.norm(b)
 
 
-@pytest.mark.parametrize("variant", [0, 1])
+@pytest.mark.parametrize("variant", [0, 1, 2, 3])
 @pytest.mark.parametrize("n", [6, 12, 16, 35])
 def test_homogenize_fp64(n, variant):
     rho = synth.random_field(n, 600 + n, 0.05, 1.0)
@@ -152,7 +182,7 @@ def test_homogenize_fp64(n, variant):
     assert np.abs(chi.reshape(3, -1).mean(axis=1)).max() < 1e-14
 
 
-@pytest.mark.parametrize("variant", [0, 1])
+@pytest.mark.parametrize("variant", [0, 1, 2, 3])
 @pytest.mark.parametrize("n", [8, 16, 34])
 def test_homogenize_mixed(n, variant):
     rho = synth.smoothed_noise(n, 0.1, 0.9, 700 + n)
