@@ -36,7 +36,7 @@ def parse():
     ap.add_argument("--n", type=int, default=128)
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--oracle-cg-iters", type=int, default=10)
+    ap.add_argument("--oracle-cg-iters", type=int, default=1000)
     ap.add_argument("--apply-reps", type=int, default=50)
     return ap.parse_args()
 
@@ -120,13 +120,26 @@ def main():
     kd = k_field.to(dt).contiguous()
     x = torch.randn(3 * nn, dtype=dt, device="cuda")
     y = torch.empty_like(x)
-    us = time_apply_device(kd, x, y, args.precision, reps=args.apply_reps, variant=0)
+    tile = h.tile()
+    # the operator in the configuration the solver was tuned to, and the best
+    # z-march shape for the stand-alone operator
+    cands = [(tile["variant"], tile["tx"], tile["tz"])]
+    for tx in ((32, 64) if n % 2 == 0 else (16, 32, 64)):
+        for tz in (4, 8, 16):
+            cands.append((0 if n % 2 == 0 else 3, tx, tz))
+    best = None
+    for v, tx, tz in cands:
+        t_us = time_apply_device(kd, x, y, args.precision, reps=args.apply_reps, variant=v, tile_tx=tx, tile_tz=tz)
+        if best is None or t_us < best[0]:
+            best = (t_us, v, tx, tz)
+    us, v_best, tx_best, tz_best = best
     us_gather = time_apply_device(kd, x, y, args.precision, reps=args.apply_reps, variant=1)
     bpn = 28 if args.precision == "mixed" else 56
     alg_bytes = bpn * nn
     achieved = alg_bytes / (us * 1e-6) / 1e9
     tname = "float" if args.precision == "mixed" else "double"
-    roof = {"bound": "hbm", "kernel": f"k_tiled<{tname}, 32, 8, false> (stencil apply, 3 loads)",
+    kname = {0: "k_march2", 3: "k_march", 2: "k_tiled"}[v_best]
+    roof = {"bound": "hbm", "kernel": f"{kname}<{tname}, ..., DIR=false> tile {tx_best}x{256 // (tx_best // (2 if v_best == 0 else 1))}, tz={tz_best} (stencil apply, 3 loads)",
             "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
             "traffic": None, "us_per_launch": us, "alg_bytes_per_launch": alg_bytes,
             "direct_gather_us_per_launch": us_gather}
@@ -150,6 +163,7 @@ def main():
         "s_per_oc_iter": wall / args.steps,
         "pcg_iters_per_step": pcg_iters / args.steps,
         "pcg_only_dof_per_s": dof / (solve_ms * 1e-3) if solve_ms > 0 else None,
+        "solver_tile": tile,
         "last_g": recs[-1]["g"],
         "last_kappa": recs[-1]["kappa"],
         "roofline": roof,

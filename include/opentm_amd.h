@@ -101,6 +101,9 @@ typedef struct {
     int32_t tile_tz;        /* planes per z-march of the operator kernel; 0 = automatic */
     int32_t tile_tx;        /* tile width in x in nodes: 16, 32 or 64 (32 or 64 for the
                                two-node kernel); 0 = automatic */
+    int32_t autotune;       /* 1: with kernel_variant 0 and automatic tiles, time the
+                               candidate kernels and tile shapes once per (n, precision)
+                               and process at otm_create and keep the fastest */
 } otm_solver_opts;
 
 typedef struct {
@@ -235,6 +238,10 @@ int otm_apply_device(int32_t n, int32_t precision, int32_t variant, const void* 
 int otm_time_apply_device(int32_t n, int32_t precision, int32_t variant, int32_t tile_tx, int32_t tile_tz,
                           const void* k_dev, const void* x_dev, void* y_dev, void* stream, int32_t reps,
                           double* us_per_launch);
+
+/* Operator kernel in use: [variant (0 pair z-march, 1 gather, 2 ring, 3 z-march),
+ * tile width, planes per march, blocks per launch]. */
+int otm_get_tile(const otm_ctx* ctx, int32_t tile4[4]);
 
 /* Per-phase timings of the last otm_step, milliseconds, HIP events on the
  * context stream: [filter+setup, solve, tensor, sensitivity, oc, total,

@@ -36,7 +36,7 @@ EXPORTED = [
     "otm_default_options", "otm_create", "otm_destroy", "otm_set_density", "otm_set_density_device",
     "otm_homogenize", "otm_sensitivity", "otm_oc_update", "otm_step", "otm_optimize", "otm_get_field",
     "otm_set_field", "otm_set_guess", "otm_get_governor", "otm_set_governor", "otm_apply", "otm_prepare", "otm_apply_device",
-    "otm_time_apply_device", "otm_get_timings", "otm_strerror", "otm_last_error", "otm_version",
+    "otm_time_apply_device", "otm_get_tile", "otm_get_timings", "otm_strerror", "otm_last_error", "otm_version",
 ]
 
 
@@ -49,7 +49,8 @@ class Problem(ctypes.Structure):
 class SolverOpts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("guess", ctypes.c_int32), ("tol", ctypes.c_double),
                 ("max_iter", ctypes.c_int32), ("check_every", ctypes.c_int32), ("reliable_delta", ctypes.c_double),
-                ("kernel_variant", ctypes.c_int32), ("tile_tz", ctypes.c_int32), ("tile_tx", ctypes.c_int32)]
+                ("kernel_variant", ctypes.c_int32), ("tile_tz", ctypes.c_int32), ("tile_tx", ctypes.c_int32),
+                ("autotune", ctypes.c_int32)]
 
 
 class OcOpts(ctypes.Structure):
@@ -125,6 +126,7 @@ def lib():
         "otm_apply_device": ([i32, i32, i32, vp, vp, vp, vp], ctypes.c_int),
         "otm_time_apply_device": ([i32, i32, i32, i32, i32, vp, vp, vp, vp, i32, dp], ctypes.c_int),
         "otm_get_timings": ([ctx, dp], ctypes.c_int),
+        "otm_get_tile": ([ctx, P(i32)], ctypes.c_int),
         "otm_strerror": ([ctypes.c_int], ctypes.c_char_p),
         "otm_last_error": ([ctx], ctypes.c_char_p),
         "otm_version": ([], ctypes.c_char_p),

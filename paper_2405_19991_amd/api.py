@@ -36,7 +36,7 @@ class Homogenization:
                  guess: str = "zero", tol: float = 1e-8, max_iter: int = 20000, check_every: int = 16,
                  reliable_delta: float = 1e-2, move: float = 0.05, eta: float = 0.5, rho_min: float = 1e-3,
                  governor: Optional[Dict[str, float]] = None, stream=None, kernel_variant: int = 0,
-                 tile_tz: int = 0, tile_tx: int = 0):
+                 tile_tz: int = 0, tile_tx: int = 0, autotune: bool = True):
         L = N.lib()
         self.n = int(n)
         p = N.Problem()
@@ -53,6 +53,7 @@ class Homogenization:
         s.guess = {"zero": N.OTM_GUESS_ZERO, "previous": N.OTM_GUESS_PREVIOUS, "user": N.OTM_GUESS_USER}[guess]
         s.tol, s.max_iter, s.check_every, s.reliable_delta = float(tol), int(max_iter), int(check_every), float(reliable_delta)
         s.kernel_variant, s.tile_tz, s.tile_tx = int(kernel_variant), int(tile_tz), int(tile_tx)
+        s.autotune = int(bool(autotune))
         o.move, o.eta, o.rho_min = float(move), float(eta), float(rho_min)
         for key, val in (governor or {}).items():
             setattr(g, key, val)
@@ -161,6 +162,11 @@ class Homogenization:
         y = np.empty_like(a)
         self._chk(self._L.otm_apply(self._h, {"fp64": N.OTM_FP64, "mixed": N.OTM_MIXED}[precision], _ptr(a), _ptr(y)))
         return y.reshape(3, self.n, self.n, self.n)
+
+    def tile(self) -> Dict[str, int]:
+        t = (ctypes.c_int32 * 4)()
+        self._chk(self._L.otm_get_tile(self._h, t))
+        return dict(variant=t[0], tx=t[1], tz=t[2], blocks=t[3])
 
     def timings(self) -> List[float]:
         t = np.zeros(8)

@@ -12,8 +12,12 @@
 #include <cstddef>
 #include <cstdio>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <new>
 #include <string>
+#include <tuple>
+#include <vector>
 
 #include "opentm_amd.h"
 #include "otm_internal.h"
@@ -64,6 +68,7 @@ struct otm_ctx {
     TileShape tile;   // one-node-per-thread kernels (ring, march)
     TileShape tile2;  // pair kernel (even n)
     bool use_pair = false;
+    double tune_us = 0.0;  // autotuned time of one direction+operator pass
 
     bool have_density = false;
     bool prepared = false;
@@ -473,6 +478,108 @@ int free_all(otm_ctx* c) {
     return 0;
 }
 
+// ------------------------------------------------------------------ autotune
+// Picks the operator kernel (pair or one-node z-march), tile width and march
+// length for this n and precision by timing the PCG direction+operator pass
+// on the context's own buffers.  Results are cached per process.
+struct TuneChoice {
+    bool pair;
+    int tx, tz;
+    double us;
+};
+std::mutex g_tune_mu;
+std::map<std::tuple<int, int>, TuneChoice> g_tune_cache;
+
+template <typename T>
+double time_dir_pass(otm_ctx* c, bool pair, const TileShape& t, T* r, T* dinv, T* p0, T* p1, T* k, T* q, int reps) {
+    const Workspace w = c->ws();
+    auto run = [&]() {
+        if (pair)
+            launch_dir_march2<T>(c->n, t, true, r, dinv, p0, p1, k, q, w, c->stream);
+        else
+            launch_dir_march<T>(c->n, t, r, dinv, p0, p1, k, q, w, c->stream);
+    };
+    run();
+    run();
+    (void)hipEventRecord(c->ev[6], c->stream);
+    for (int i = 0; i < reps; ++i) run();
+    (void)hipEventRecord(c->ev[7], c->stream);
+    if (hipEventSynchronize(c->ev[7]) != hipSuccess) {
+        (void)hipGetLastError();
+        return 1e30;
+    }
+    return 1000.0 * ev_ms(c, 6, 7) / reps;
+}
+
+int autotune(otm_ctx* c) {
+    const int prec = c->so.precision;
+    const auto key = std::make_tuple(c->n, prec);
+    {
+        std::lock_guard<std::mutex> g(g_tune_mu);
+        auto it = g_tune_cache.find(key);
+        if (it != g_tune_cache.end()) {
+            const TuneChoice& ch = it->second;
+            c->use_pair = ch.pair;
+            if (ch.pair)
+                c->tile2 = choose_tile2(c->n, c->max_blocks, ch.tz, ch.tx);
+            else
+                c->tile = choose_tile(c->n, c->max_blocks, ch.tz, ch.tx);
+            return OTM_OK;
+        }
+    }
+    // a valid state for timing: all loads active, beta != 0, zeroed vectors
+    const size_t head = offsetof(Scalars, sum_rho);
+    std::memset(c->h_sc, 0, head);
+    for (int l = 0; l < 3; ++l) {
+        c->h_sc->active[l] = 1;
+        c->h_sc->beta[l] = 0.5;
+        c->h_sc->rz[l] = 1.0;
+    }
+    HIPCHK(c, hipMemcpyAsync(c->sc, c->h_sc, head, hipMemcpyHostToDevice, c->stream));
+    const size_t es = prec == OTM_MIXED ? sizeof(float) : sizeof(double);
+    void* bufs[] = {prec == OTM_MIXED ? (void*)c->r32 : (void*)c->r64, prec == OTM_MIXED ? (void*)c->q32 : (void*)c->q64};
+    for (void* b : bufs) HIPCHK(c, hipMemsetAsync(b, 0, 3 * (size_t)c->nn * es, c->stream));
+    HIPCHK(c, hipMemsetAsync(prec == OTM_MIXED ? (void*)c->k32 : (void*)c->k, 0, (size_t)c->nn * es, c->stream));
+    HIPCHK(c, hipMemsetAsync(prec == OTM_MIXED ? (void*)c->dinv32 : (void*)c->dinv, 0, (size_t)c->nn * es, c->stream));
+    std::vector<std::tuple<bool, int, int>> cands;
+    const int tzs[] = {4, 8, 16, 32};
+    if (c->n % 2 == 0)
+        for (int tx : {32, 64})
+            for (int tz : tzs)
+                if (tz <= c->n) cands.emplace_back(true, tx, tz);
+    for (int tx : {16, 32, 64})
+        for (int tz : tzs)
+            if (tz <= c->n) cands.emplace_back(false, tx, tz);
+    const int reps = c->nn >= (1 << 20) ? 6 : 12;
+    TuneChoice best{false, 32, 8, 1e30};
+    for (auto& cd : cands) {
+        const bool pair = std::get<0>(cd);
+        const int tx = std::get<1>(cd), tz = std::get<2>(cd);
+        const TileShape t = pair ? choose_tile2(c->n, c->max_blocks, tz, tx) : choose_tile(c->n, c->max_blocks, tz, tx);
+        if (t.tz != tz || t.blocks > c->max_blocks) continue;
+        double us;
+        if (prec == OTM_MIXED)
+            us = time_dir_pass<float>(c, pair, t, c->r32, c->dinv32, c->p32[0], c->p32[1], c->k32, c->q32, reps);
+        else
+            us = time_dir_pass<double>(c, pair, t, c->r64, c->dinv, c->p64[0], c->p64[1], c->k, c->q64, reps);
+        if (us < best.us) best = TuneChoice{pair, tx, tz, us};
+    }
+    int rc = check_launch(c, "autotune");
+    if (rc) return rc;
+    HIPCHK(c, hipMemsetAsync(prec == OTM_MIXED ? (void*)c->p32[0] : (void*)c->p64[0], 0, 3 * (size_t)c->nn * es, c->stream));
+    HIPCHK(c, hipMemsetAsync(prec == OTM_MIXED ? (void*)c->p32[1] : (void*)c->p64[1], 0, 3 * (size_t)c->nn * es, c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    c->use_pair = best.pair;
+    if (best.pair)
+        c->tile2 = choose_tile2(c->n, c->max_blocks, best.tz, best.tx);
+    else
+        c->tile = choose_tile(c->n, c->max_blocks, best.tz, best.tx);
+    c->tune_us = best.us;
+    std::lock_guard<std::mutex> g(g_tune_mu);
+    g_tune_cache[key] = best;
+    return OTM_OK;
+}
+
 }  // namespace
 
 // ======================================================================= ABI
@@ -489,6 +596,7 @@ void otm_default_options(otm_solver_opts* s, otm_oc_opts* o, otm_governor_opts* 
         s->kernel_variant = 0;
         s->tile_tz = 0;
         s->tile_tx = 0;
+        s->autotune = 1;
     }
     if (o) {
         o->move = 0.05;
@@ -628,6 +736,14 @@ int otm_create(const otm_problem* problem, const otm_solver_opts* solver, const 
         free_all(c);
         delete c;
         return OTM_EDEVICE;
+    }
+    if (c->so.kernel_variant == 0 && c->so.tile_tx == 0 && c->so.tile_tz == 0 && c->so.autotune) {
+        rc = autotune(c);
+        if (rc) {
+            free_all(c);
+            delete c;
+            return rc;
+        }
     }
     c->vstar = problem->vf;
     *out = c;
@@ -971,6 +1087,16 @@ int otm_time_apply_device(int32_t n, int32_t precision, int32_t variant, int32_t
     *us = 1000.0 * (double)ms / (double)reps;
     (void)hipEventDestroy(a);
     (void)hipEventDestroy(b);
+    return OTM_OK;
+}
+
+int otm_get_tile(const otm_ctx* c, int32_t tile4[4]) {
+    if (!c || !tile4) return OTM_EINVAL;
+    const TileShape& t = c->use_pair ? c->tile2 : c->tile;
+    tile4[0] = c->so.kernel_variant == 0 ? (c->use_pair ? 0 : 3) : c->so.kernel_variant;
+    tile4[1] = t.tx;
+    tile4[2] = t.tz;
+    tile4[3] = t.blocks;
     return OTM_OK;
 }
 
