@@ -248,6 +248,33 @@ int otm_get_tile(const otm_ctx* ctx, int32_t tile4[4]);
  * solve kernel (dominant) mean us, solve kernel launches]. */
 int otm_get_timings(const otm_ctx* ctx, double t8[8]);
 
+/* ---- batches of designs (uneven n) -----------------------------------------
+ * Many independent cells in one set of device arenas; every phase of a design
+ * iteration is one launch over all designs (per-design scalars and
+ * reductions), and a chunk of PCG iterations is captured once as a hipGraph
+ * and replayed until every design has converged.  float64 path only; every n
+ * must be even (4..1024).  Problems may differ in n, target, vf and material
+ * constants; solver / OC / governor options are shared.  autotune (solver
+ * options) times tile widths and march lengths of the batched operator pass
+ * at creation.  Errors as for contexts; otm_batch_last_error gives details. */
+typedef struct otm_batch otm_batch;
+int otm_batch_create(const otm_problem* problems, int32_t count, const otm_solver_opts* solver,
+                     const otm_oc_opts* oc, const otm_governor_opts* gov, void* stream, otm_batch** out);
+void otm_batch_destroy(otm_batch* batch);
+/* design index d in [0, count); count = n_d^3 host values */
+int otm_batch_set_density(otm_batch* batch, int32_t d, const double* rho_host, int64_t count);
+/* OTM_FIELD_RHO, _RHOF, _K, _CHI (3 n_d^3), _SENS, _SENS_ELEM of design d */
+int otm_batch_get_field(otm_batch* batch, int32_t d, int32_t field, double* host_out, int64_t count);
+/* One design iteration for every design; recs (may be NULL) receives count
+ * records.  OTM_NOT_CONVERGED if some solve hit max_iter. */
+int otm_batch_step(otm_batch* batch, otm_iter_record* recs);
+/* 1 (default): replay the captured PCG chunk; 0: launch it eagerly. */
+int otm_batch_set_graph(otm_batch* batch, int32_t use_graph);
+/* [designs, total cells, operator work items, tile width, march length of
+ *  design 0, tuned operator-pass us, last solve ms, last step ms] */
+int otm_batch_info(const otm_batch* batch, double info8[8]);
+const char* otm_batch_last_error(const otm_batch* batch);
+
 const char* otm_strerror(int status);
 const char* otm_last_error(const otm_ctx* ctx);
 /* Library version string. */

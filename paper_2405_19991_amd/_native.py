@@ -37,6 +37,8 @@ EXPORTED = [
     "otm_homogenize", "otm_sensitivity", "otm_oc_update", "otm_step", "otm_optimize", "otm_get_field",
     "otm_set_field", "otm_set_guess", "otm_get_governor", "otm_set_governor", "otm_apply", "otm_prepare", "otm_apply_device",
     "otm_time_apply_device", "otm_get_tile", "otm_get_timings", "otm_strerror", "otm_last_error", "otm_version",
+    "otm_batch_create", "otm_batch_destroy", "otm_batch_set_density", "otm_batch_get_field", "otm_batch_step",
+    "otm_batch_set_graph", "otm_batch_info", "otm_batch_last_error",
 ]
 
 
@@ -130,6 +132,14 @@ def lib():
         "otm_strerror": ([ctypes.c_int], ctypes.c_char_p),
         "otm_last_error": ([ctx], ctypes.c_char_p),
         "otm_version": ([], ctypes.c_char_p),
+        "otm_batch_create": ([P(Problem), i32, P(SolverOpts), P(OcOpts), P(GovernorOpts), vp, P(vp)], ctypes.c_int),
+        "otm_batch_destroy": ([vp], None),
+        "otm_batch_set_density": ([vp, i32, dp, i64], ctypes.c_int),
+        "otm_batch_get_field": ([vp, i32, i32, dp, i64], ctypes.c_int),
+        "otm_batch_step": ([vp, P(IterRecord)], ctypes.c_int),
+        "otm_batch_set_graph": ([vp, i32], ctypes.c_int),
+        "otm_batch_info": ([vp, dp], ctypes.c_int),
+        "otm_batch_last_error": ([vp], ctypes.c_char_p),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)

@@ -242,3 +242,93 @@ def version() -> str:
 
 def dumps_log(log) -> str:
     return "\n".join(json.dumps(r) for r in log)
+
+
+class Batch:
+    """Many independent cells of uneven (even) n, stepped together: every
+    phase of a design iteration is one launch over all designs, and PCG
+    chunks replay a captured hipGraph.  float64 path."""
+
+    def __init__(self, problems: Sequence[Dict[str, object]], tol: float = 1e-6, max_iter: int = 20000,
+                 check_every: int = 16, guess: str = "zero", move: float = 0.05, eta: float = 0.5,
+                 rho_min: float = 1e-3, governor: Optional[Dict[str, float]] = None, autotune: bool = True,
+                 tile_tx: int = 0, tile_tz: int = 0, stream=None):
+        L = N.lib()
+        arr = (N.Problem * len(problems))()
+        self.ns = []
+        for i, pr in enumerate(problems):
+            p = arr[i]
+            p.n = int(pr["n"])
+            hr = pr.get("heat_ratio", (1.0, 1e-3))
+            p.k0, p.kmin = float(hr[0]), float(hr[1])
+            p.penal = float(pr.get("penal", 3.0))
+            p.filter_radius = float(pr.get("filter_radius", 1.5))
+            for q, t in enumerate(pr["target"]):
+                p.target[q] = float(t)
+            p.vf = float(pr.get("vf", 0.3))
+            p.objective = N.OTM_OBJ_MSE
+            self.ns.append(p.n)
+        s, o, g = N.default_options()
+        s.precision = N.OTM_FP64
+        s.guess = {"zero": N.OTM_GUESS_ZERO, "previous": N.OTM_GUESS_PREVIOUS}[guess]
+        s.tol, s.max_iter, s.check_every = float(tol), int(max_iter), int(check_every)
+        s.autotune, s.tile_tx, s.tile_tz = int(bool(autotune)), int(tile_tx), int(tile_tz)
+        o.move, o.eta, o.rho_min = float(move), float(eta), float(rho_min)
+        for key, val in (governor or {}).items():
+            setattr(g, key, val)
+        h = ctypes.c_void_p()
+        st = ctypes.c_void_p(int(stream)) if stream is not None else None
+        N.check(L.otm_batch_create(arr, len(problems), ctypes.byref(s), ctypes.byref(o), ctypes.byref(g), st,
+                                   ctypes.byref(h)))
+        self._h, self._L, self.count = h, L, len(problems)
+
+    def _chk(self, status, allow_nc=True):
+        if status == N.OTM_OK or (status == N.OTM_NOT_CONVERGED and allow_nc):
+            return status
+        msg = self._L.otm_strerror(status).decode()
+        raise N.OTMError(status, msg + " (" + self._L.otm_batch_last_error(self._h).decode() + ")")
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._L.otm_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def set_density(self, d: int, rho) -> None:
+        a = _f64(rho).reshape(-1)
+        self._chk(self._L.otm_batch_set_density(self._h, int(d), _ptr(a), a.size))
+
+    def get_field(self, d: int, name: str) -> np.ndarray:
+        n = self.ns[d]
+        size = 3 * n ** 3 if name in N.FIELD3 else n ** 3
+        out = np.empty(size)
+        self._chk(self._L.otm_batch_get_field(self._h, int(d), N.FIELDS[name], _ptr(out), size))
+        return out.reshape((3, n, n, n) if name in N.FIELD3 else (n, n, n))
+
+    def set_graph(self, on: bool) -> None:
+        self._chk(self._L.otm_batch_set_graph(self._h, int(bool(on))))
+
+    def step(self) -> List[Dict[str, object]]:
+        recs = (N.IterRecord * self.count)()
+        status = self._chk(self._L.otm_batch_step(self._h, recs))
+        out = [recs[i].to_dict() for i in range(self.count)]
+        for r in out:
+            r["status"] = status
+        return out
+
+    def info(self) -> Dict[str, float]:
+        a = np.zeros(8)
+        self._chk(self._L.otm_batch_info(self._h, _ptr(a)))
+        keys = ["designs", "cells", "work_items", "tile_tx", "tile_tz", "tuned_pass_us", "solve_ms", "step_ms"]
+        return dict(zip(keys, a.tolist()))

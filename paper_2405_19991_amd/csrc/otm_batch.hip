@@ -1,0 +1,622 @@
+// Host engine for batches of designs with uneven n (float64 path).
+//
+// All designs of a batch share one set of arenas; every phase of a design
+// iteration is one launch over the batch's work list (otm_kernels.hip,
+// otm_stencil.hip, otm_march2.hip), with per-design device scalars and a
+// per-design finalize.  A chunk of PCG iterations (direction+operator pass,
+// finalize, update, finalize, repeated) is captured once as a hipGraph and
+// replayed until every design has converged; the tile width and march length
+// of the batched operator pass are chosen by timing the candidates on the
+// batch itself.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstddef>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "opentm_amd.h"
+#include "otm_internal.h"
+
+using namespace otm;
+
+namespace {
+
+struct Gov {
+    double vstar = 1.0, df = 1.0, gap = 0.0, g_prev = 1.0;
+    int count = 0, small_steps = 0;
+};
+
+}  // namespace
+
+struct otm_batch {
+    int count = 0;
+    std::vector<otm_problem> prob;
+    otm_solver_opts so;
+    otm_oc_opts oc;
+    otm_governor_opts go;
+    hipStream_t stream = nullptr;
+    bool own_stream = false;
+    int64_t total = 0;
+    std::vector<int64_t> off;
+
+    // work lists
+    std::vector<BatchDesc> hdesc;
+    BatchDesc* ddesc = nullptr;
+    int* eb_design = nullptr;
+    int* mb_design = nullptr;
+    int eb_cap = 0, mb_cap = 0;
+    BatchTab tab{};
+    int wx = 16;  // z-march tile: WX threads x TY rows (tx = 2 WX nodes)
+    int march_grid = 1024, update_grid = 1024;
+
+    // arenas
+    double *rho = nullptr, *rhof = nullptr, *k = nullptr, *dinv = nullptr, *b = nullptr, *x = nullptr;
+    double *st = nullptr, *sens = nullptr, *ocq = nullptr, *r = nullptr, *p[2] = {nullptr, nullptr}, *q = nullptr;
+    W6* dw6 = nullptr;
+    double* dvstar = nullptr;
+    double* partials = nullptr;
+    int partial_slots = 0;
+    Scalars* sc = nullptr;
+    Scalars* h_sc = nullptr;
+    int pbuf = 0;
+
+    bool use_graph = true;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t gexec = nullptr;
+
+    std::vector<Gov> gov;
+    std::vector<double> kappa, g, volume, low;
+    std::vector<int> have_density;
+    bool have_solution = false;
+    int iter = 0;
+    double tune_us = 0.0;
+    double t_ms[8] = {0, 0, 0, 0, 0, 0, 0, 0};
+    std::string err;
+};
+
+namespace {
+
+int bfail(otm_batch* c, int code, const std::string& m) {
+    if (c) c->err = m;
+    return code;
+}
+
+#define BCHK(c, call)                                                                                \
+    do {                                                                                             \
+        hipError_t e_ = (call);                                                                      \
+        if (e_ != hipSuccess) return bfail((c), OTM_EDEVICE, std::string(#call) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+int blaunch_ok(otm_batch* c, const char* what) {
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return bfail(c, OTM_EDEVICE, std::string(what) + ": " + hipGetErrorString(e));
+    return OTM_OK;
+}
+
+template <typename T>
+int balloc(otm_batch* c, T** p, int64_t n) {
+    if (hipMalloc((void**)p, (size_t)n * sizeof(T)) != hipSuccess) {
+        *p = nullptr;
+        (void)hipGetLastError();
+        return bfail(c, OTM_ENOMEM, "device allocation failed");
+    }
+    return OTM_OK;
+}
+
+// Work lists for a given z-march tile (tx = 2 wx nodes wide, 256/wx rows) and
+// march length tz; element sweeps use up to 256 blocks per design.
+void build_tables(otm_batch* c, int wx, int tz) {
+    const int tx = 2 * wx, ty = kBlock / wx;
+    c->hdesc.resize(c->count);
+    std::vector<int> ebd, mbd;
+    for (int d = 0; d < c->count; ++d) {
+        BatchDesc& D = c->hdesc[d];
+        const int n = c->prob[d].n;
+        const int64_t nn = (int64_t)n * n * n;
+        D.n = n;
+        D.off = c->off[d];
+        D.eb_start = (int)ebd.size();
+        int64_t nb = (nn + kBlock - 1) / kBlock;
+        D.eb_count = (int)std::min<int64_t>(nb, 256);
+        for (int q = 0; q < D.eb_count; ++q) ebd.push_back(d);
+        D.ntx = (n + tx - 1) / tx;
+        D.nty = (n + ty - 1) / ty;
+        D.tz = std::min(tz, n);
+        D.mb_start = (int)mbd.size();
+        D.mb_count = D.ntx * D.nty * ((n + D.tz - 1) / D.tz);
+        for (int q = 0; q < D.mb_count; ++q) mbd.push_back(d);
+        D.k0 = c->prob[d].k0;
+        D.kmin = c->prob[d].kmin;
+        D.penal = c->prob[d].penal;
+        D.fw = filter_weights(c->prob[d].filter_radius);
+    }
+    c->tab.count = c->count;
+    c->tab.eb_total = (int)ebd.size();
+    c->tab.mb_total = (int)mbd.size();
+    c->wx = wx;
+    (void)hipMemcpyAsync(c->ddesc, c->hdesc.data(), c->count * sizeof(BatchDesc), hipMemcpyHostToDevice, c->stream);
+    (void)hipMemcpyAsync(c->eb_design, ebd.data(), ebd.size() * sizeof(int), hipMemcpyHostToDevice, c->stream);
+    (void)hipMemcpyAsync(c->mb_design, mbd.data(), mbd.size() * sizeof(int), hipMemcpyHostToDevice, c->stream);
+    c->tab.desc = c->ddesc;
+    c->tab.eb_design = c->eb_design;
+    c->tab.mb_design = c->mb_design;
+    c->march_grid = std::min(c->tab.mb_total, 1024);
+    c->update_grid = std::min(c->tab.eb_total, 2048);
+    // the host tables are staged from pageable memory: finish before they go away
+    (void)hipStreamSynchronize(c->stream);
+}
+
+void march_pass(otm_batch* c, const double* po, double* pn) {
+    if (c->wx == 32)
+        launch_b_dir_march2<32, 8>(c->tab, c->march_grid, c->r, c->dinv, po, pn, c->k, c->q, c->partials, c->sc,
+                                   c->stream);
+    else
+        launch_b_dir_march2<16, 16>(c->tab, c->march_grid, c->r, c->dinv, po, pn, c->k, c->q, c->partials, c->sc,
+                                    c->stream);
+}
+
+// check_every PCG iterations (even, so the direction buffers end where they began)
+void pcg_chunk(otm_batch* c) {
+    for (int it = 0; it < c->so.check_every; ++it) {
+        double* po = c->p[c->pbuf];
+        double* pn = c->p[c->pbuf ^ 1];
+        march_pass(c, po, pn);
+        launch_b_update_vec(c->tab, c->update_grid, c->x, c->r, pn, c->q, c->dinv, c->partials, c->sc, c->stream);
+        c->pbuf ^= 1;
+    }
+}
+
+int sync_sc(otm_batch* c) {
+    BCHK(c, hipMemcpyAsync(c->h_sc, c->sc, c->count * sizeof(Scalars), hipMemcpyDeviceToHost, c->stream));
+    BCHK(c, hipStreamSynchronize(c->stream));
+    return OTM_OK;
+}
+
+int reset_solver(otm_batch* c) {
+    const size_t head = offsetof(Scalars, sum_rho);
+    for (int d = 0; d < c->count; ++d) {
+        std::memset(&c->h_sc[d], 0, head);
+        c->h_sc[d].tol2 = c->so.tol * c->so.tol;
+        BCHK(c, hipMemcpyAsync(&c->sc[d], &c->h_sc[d], head, hipMemcpyHostToDevice, c->stream));
+    }
+    return OTM_OK;
+}
+
+bool all_inactive(const otm_batch* c) {
+    for (int d = 0; d < c->count; ++d)
+        for (int l = 0; l < 3; ++l)
+            if (c->h_sc[d].active[l]) return false;
+    return true;
+}
+
+int max_iters(const otm_batch* c) {
+    int m = 0;
+    for (int d = 0; d < c->count; ++d)
+        for (int l = 0; l < 3; ++l) m = std::max(m, c->h_sc[d].iters[l]);
+    return m;
+}
+
+int run_chunk(otm_batch* c) {
+    if (!c->use_graph) {
+        pcg_chunk(c);
+        return blaunch_ok(c, "pcg chunk");
+    }
+    if (!c->gexec) {
+        const int pb = c->pbuf;
+        BCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
+        pcg_chunk(c);
+        hipGraph_t g = nullptr;
+        BCHK(c, hipStreamEndCapture(c->stream, &g));
+        c->graph = g;
+        BCHK(c, hipGraphInstantiate(&c->gexec, c->graph, nullptr, nullptr, 0));
+        c->pbuf = pb;  // capture did not run anything
+    }
+    BCHK(c, hipGraphLaunch(c->gexec, c->stream));
+    // the chunk has an even number of iterations: pbuf is unchanged
+    return OTM_OK;
+}
+
+int solve(otm_batch* c, bool x_zero) {
+    int rc;
+    if ((rc = reset_solver(c))) return rc;
+    if (x_zero) BCHK(c, hipMemsetAsync(c->x, 0, (size_t)3 * c->total * sizeof(double), c->stream));
+    launch_b_residual(c->tab, c->k, c->b, c->x, c->r, c->p[c->pbuf], c->dinv, RES_START, x_zero ? 1 : 0, c->partials,
+                      c->sc, c->stream);
+    if ((rc = blaunch_ok(c, "residual"))) return rc;
+    if ((rc = sync_sc(c))) return rc;
+    while (!all_inactive(c) && max_iters(c) < c->so.max_iter) {
+        if ((rc = run_chunk(c))) return rc;
+        if ((rc = sync_sc(c))) return rc;
+        if (all_inactive(c)) {
+            launch_b_residual(c->tab, c->k, c->b, c->x, c->r, c->p[c->pbuf], c->dinv, RES_START, 0, c->partials, c->sc,
+                              c->stream);
+            if ((rc = sync_sc(c))) return rc;
+        }
+    }
+    launch_b_sum3(c->tab, c->x, 0, c->partials, c->sc, c->stream);
+    launch_b_sub_mean3(c->tab, c->x, 0, c->sc, c->stream);
+    return blaunch_ok(c, "project");
+}
+
+double gov_update(const otm_governor_opts& go, double rho_min, Gov& s, double g, double low, double vol) {
+    if (g <= go.bound) {
+        s.gap = s.vstar - low;
+        s.vstar = s.vstar - s.gap * s.df;
+        s.df = go.decay * s.df;
+    }
+    const bool little = std::fabs(s.g_prev - g) < go.dg_small;
+    const bool big = g > go.bound;
+    const bool at_bound = std::fabs(vol - s.vstar) < go.dv_small;
+    if (little && big && at_bound)
+        s.count += 1;
+    else
+        s.count = 0;
+    if (s.count >= go.patience) {
+        s.vstar = s.vstar + go.rebound * s.gap * s.df;
+        s.count = 0;
+    }
+    s.vstar = std::min(1.0, std::max(rho_min, s.vstar));
+    if (std::fabs(s.g_prev - g) < go.g_tol)
+        s.small_steps += 1;
+    else
+        s.small_steps = 0;
+    s.g_prev = g;
+    return s.vstar;
+}
+
+// Time the batched operator pass for a (tile width, march length) candidate.
+double time_candidate(otm_batch* c, int wx, int tz) {
+    build_tables(c, wx, tz);
+    hipEvent_t a, b;
+    (void)hipEventCreate(&a);
+    (void)hipEventCreate(&b);
+    march_pass(c, c->p[0], c->p[1]);
+    (void)hipEventRecord(a, c->stream);
+    const int reps = 5;
+    for (int i = 0; i < reps; ++i) march_pass(c, c->p[0], c->p[1]);
+    (void)hipEventRecord(b, c->stream);
+    (void)hipEventSynchronize(b);
+    float ms = 0.f;
+    (void)hipEventElapsedTime(&ms, a, b);
+    (void)hipEventDestroy(a);
+    (void)hipEventDestroy(b);
+    if (hipGetLastError() != hipSuccess) return 1e30;
+    return 1000.0 * ms / reps;
+}
+
+std::mutex g_btune_mu;
+std::map<std::vector<int>, std::pair<int, int>> g_btune;
+
+int autotune_batch(otm_batch* c) {
+    std::vector<int> key;
+    for (auto& p : c->prob) key.push_back(p.n);
+    std::sort(key.begin(), key.end());
+    {
+        std::lock_guard<std::mutex> g(g_btune_mu);
+        auto it = g_btune.find(key);
+        if (it != g_btune.end()) {
+            build_tables(c, it->second.first, it->second.second);
+            return OTM_OK;
+        }
+    }
+    // valid timing state: every load active, beta != 0, zeroed vectors
+    const size_t head = offsetof(Scalars, sum_rho);
+    for (int d = 0; d < c->count; ++d) {
+        std::memset(&c->h_sc[d], 0, head);
+        for (int l = 0; l < 3; ++l) {
+            c->h_sc[d].active[l] = 1;
+            c->h_sc[d].beta[l] = 0.5;
+            c->h_sc[d].rz[l] = 1.0;
+        }
+        BCHK(c, hipMemcpyAsync(&c->sc[d], &c->h_sc[d], head, hipMemcpyHostToDevice, c->stream));
+    }
+    const size_t v3 = (size_t)3 * c->total * sizeof(double), v1 = (size_t)c->total * sizeof(double);
+    BCHK(c, hipMemsetAsync(c->r, 0, v3, c->stream));
+    BCHK(c, hipMemsetAsync(c->q, 0, v3, c->stream));
+    BCHK(c, hipMemsetAsync(c->k, 0, v1, c->stream));
+    BCHK(c, hipMemsetAsync(c->dinv, 0, v1, c->stream));
+    int best_wx = 16, best_tz = 8;
+    double best = 1e30;
+    for (int wx : {16, 32})
+        for (int tz : {4, 8, 16, 32}) {
+            const double us = time_candidate(c, wx, tz);
+            if (us < best) {
+                best = us;
+                best_wx = wx;
+                best_tz = tz;
+            }
+        }
+    BCHK(c, hipMemsetAsync(c->p[0], 0, v3, c->stream));
+    BCHK(c, hipMemsetAsync(c->p[1], 0, v3, c->stream));
+    build_tables(c, best_wx, best_tz);
+    BCHK(c, hipStreamSynchronize(c->stream));
+    c->tune_us = best;
+    std::lock_guard<std::mutex> g(g_btune_mu);
+    g_btune[key] = {best_wx, best_tz};
+    return OTM_OK;
+}
+
+void free_batch(otm_batch* c) {
+    if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
+    if (c->graph) (void)hipGraphDestroy(c->graph);
+    void* bufs[] = {c->rho, c->rhof, c->k, c->dinv, c->b, c->x, c->st, c->sens, c->ocq, c->r, c->p[0], c->p[1], c->q,
+                    c->dw6, c->dvstar, c->partials, c->sc, c->ddesc, c->eb_design, c->mb_design};
+    for (void* p : bufs)
+        if (p) (void)hipFree(p);
+    if (c->h_sc) (void)hipHostFree(c->h_sc);
+    if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
+}
+
+}  // namespace
+
+extern "C" {
+
+int otm_batch_create(const otm_problem* problems, int32_t count, const otm_solver_opts* solver,
+                     const otm_oc_opts* oc, const otm_governor_opts* gov, void* stream, otm_batch** out) {
+    if (!out || !problems || count < 1 || count > 4096) return OTM_EINVAL;
+    *out = nullptr;
+    for (int d = 0; d < count; ++d) {
+        const otm_problem& p = problems[d];
+        if (p.n < 4 || p.n > 1024 || (p.n % 2) != 0) return OTM_EINVAL;  // the batched kernels need even n
+        if (!(p.kmin > 0.0 && p.k0 > p.kmin && p.penal >= 1.0 && p.filter_radius < 5.0 && p.vf > 0.0 && p.vf <= 1.0))
+            return OTM_EINVAL;
+        for (int q = 0; q < 6; ++q)
+            if (!std::isfinite(p.target[q])) return OTM_EINVAL;
+        if (p.objective != OTM_OBJ_MSE) return OTM_EUNSUPPORTED;
+    }
+    otm_batch* c = new (std::nothrow) otm_batch();
+    if (!c) return OTM_ENOMEM;
+    c->count = count;
+    c->prob.assign(problems, problems + count);
+    otm_default_options(&c->so, &c->oc, &c->go);
+    if (solver) c->so = *solver;
+    if (oc) c->oc = *oc;
+    if (gov) c->go = *gov;
+    if (c->so.precision != OTM_FP64 || !(c->so.tol > 0.0) || c->so.max_iter < 1 || c->so.check_every < 1) {
+        const int code = c->so.precision != OTM_FP64 ? OTM_EUNSUPPORTED : OTM_EINVAL;
+        delete c;
+        return code;
+    }
+    if (c->so.check_every % 2) c->so.check_every += 1;
+    hipDeviceProp_t prop;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess ||
+        std::strncmp(prop.gcnArchName, "gfx950", 6) != 0) {
+        (void)hipGetLastError();
+        delete c;
+        return OTM_EDEVICE;
+    }
+    if (stream) {
+        c->stream = (hipStream_t)stream;
+    } else {
+        if (hipStreamCreateWithFlags(&c->stream, hipStreamNonBlocking) != hipSuccess) {
+            delete c;
+            return OTM_EDEVICE;
+        }
+        c->own_stream = true;
+    }
+    c->off.resize(count);
+    int64_t total = 0;
+    int64_t max_eb = 0, max_mb = 0;
+    for (int d = 0; d < count; ++d) {
+        c->off[d] = total;
+        const int n = problems[d].n;
+        total += (int64_t)n * n * n;
+        max_eb += 256;
+        // smallest tile (32 x 16 nodes) and march (4 planes) bound the item count
+        max_mb += (int64_t)((n + 31) / 32) * ((n + 7) / 8) * ((n + 3) / 4);
+    }
+    c->total = total;
+    int rc = OTM_OK;
+    rc = rc ? rc : balloc(c, &c->rho, total);
+    rc = rc ? rc : balloc(c, &c->rhof, total);
+    rc = rc ? rc : balloc(c, &c->k, total);
+    rc = rc ? rc : balloc(c, &c->dinv, total);
+    rc = rc ? rc : balloc(c, &c->b, 3 * total);
+    rc = rc ? rc : balloc(c, &c->x, 3 * total);
+    rc = rc ? rc : balloc(c, &c->st, total);
+    rc = rc ? rc : balloc(c, &c->sens, total);
+    rc = rc ? rc : balloc(c, &c->ocq, total);
+    rc = rc ? rc : balloc(c, &c->r, 3 * total);
+    rc = rc ? rc : balloc(c, &c->p[0], 3 * total);
+    rc = rc ? rc : balloc(c, &c->p[1], 3 * total);
+    rc = rc ? rc : balloc(c, &c->q, 3 * total);
+    rc = rc ? rc : balloc(c, &c->dw6, count);
+    rc = rc ? rc : balloc(c, &c->dvstar, count);
+    c->partial_slots = (int)std::max(max_eb, max_mb);
+    rc = rc ? rc : balloc(c, &c->partials, (int64_t)c->partial_slots * kMaxReduce);
+    rc = rc ? rc : balloc(c, &c->sc, count);
+    rc = rc ? rc : balloc(c, &c->ddesc, count);
+    rc = rc ? rc : balloc(c, &c->eb_design, max_eb);
+    rc = rc ? rc : balloc(c, &c->mb_design, max_mb);
+    if (!rc && hipHostMalloc((void**)&c->h_sc, count * sizeof(Scalars), hipHostMallocDefault) != hipSuccess)
+        rc = OTM_ENOMEM;
+    if (rc) {
+        free_batch(c);
+        delete c;
+        return rc;
+    }
+    c->gov.resize(count);
+    for (int d = 0; d < count; ++d) c->gov[d].vstar = problems[d].vf;
+    c->kappa.assign(6 * count, 0.0);
+    c->g.assign(count, 0.0);
+    c->volume.assign(count, 0.0);
+    c->low.assign(count, 0.0);
+    c->have_density.assign(count, 0);
+    (void)hipMemsetAsync(c->x, 0, (size_t)3 * total * sizeof(double), c->stream);
+    (void)hipMemsetAsync(c->p[0], 0, (size_t)3 * total * sizeof(double), c->stream);
+    (void)hipMemsetAsync(c->p[1], 0, (size_t)3 * total * sizeof(double), c->stream);
+    if (c->so.autotune && c->so.tile_tz == 0 && c->so.tile_tx == 0) {
+        rc = autotune_batch(c);
+    } else {
+        const int wx = c->so.tile_tx == 64 ? 32 : 16;
+        build_tables(c, wx, c->so.tile_tz > 0 ? std::max(4, c->so.tile_tz) : 8);
+    }
+    if (!rc && hipStreamSynchronize(c->stream) != hipSuccess) rc = OTM_EDEVICE;
+    if (rc) {
+        free_batch(c);
+        delete c;
+        return rc;
+    }
+    *out = c;
+    return OTM_OK;
+}
+
+void otm_batch_destroy(otm_batch* c) {
+    if (!c) return;
+    if (c->stream) (void)hipStreamSynchronize(c->stream);
+    free_batch(c);
+    delete c;
+}
+
+int otm_batch_set_graph(otm_batch* c, int32_t use_graph) {
+    if (!c) return OTM_EINVAL;
+    c->use_graph = use_graph != 0;
+    return OTM_OK;
+}
+
+int otm_batch_set_density(otm_batch* c, int32_t d, const double* rho, int64_t count) {
+    if (!c || !rho || d < 0 || d >= c->count) return OTM_EINVAL;
+    const int n = c->prob[d].n;
+    if (count != (int64_t)n * n * n) return bfail(c, OTM_EINVAL, "density count must be n^3");
+    for (int64_t e = 0; e < count; ++e)
+        if (!std::isfinite(rho[e])) return bfail(c, OTM_ENONFINITE, "non-finite density");
+    BCHK(c, hipMemcpyAsync(c->rho + c->off[d], rho, count * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    BCHK(c, hipStreamSynchronize(c->stream));
+    c->have_density[d] = 1;
+    return OTM_OK;
+}
+
+int otm_batch_get_field(otm_batch* c, int32_t d, int32_t field, double* out, int64_t count) {
+    if (!c || !out || d < 0 || d >= c->count) return OTM_EINVAL;
+    const int64_t nn = (int64_t)c->prob[d].n * c->prob[d].n * c->prob[d].n;
+    const double* src = nullptr;
+    int64_t size = nn;
+    switch (field) {
+        case OTM_FIELD_RHO: src = c->rho + c->off[d]; break;
+        case OTM_FIELD_RHOF: src = c->rhof + c->off[d]; break;
+        case OTM_FIELD_K: src = c->k + c->off[d]; break;
+        case OTM_FIELD_CHI: src = c->x + 3 * c->off[d]; size = 3 * nn; break;
+        case OTM_FIELD_SENS: src = c->sens + c->off[d]; break;
+        case OTM_FIELD_SENS_ELEM: src = c->st + c->off[d]; break;
+        default: return bfail(c, OTM_EINVAL, "field not available for batches");
+    }
+    if (count != size) return bfail(c, OTM_EINVAL, "field count mismatch");
+    BCHK(c, hipMemcpyAsync(out, src, size * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    BCHK(c, hipStreamSynchronize(c->stream));
+    return OTM_OK;
+}
+
+int otm_batch_step(otm_batch* c, otm_iter_record* recs) {
+    if (!c) return OTM_EINVAL;
+    for (int d = 0; d < c->count; ++d)
+        if (!c->have_density[d]) return bfail(c, OTM_ESTATE, "every design needs a density");
+    int rc;
+    auto t0 = std::chrono::steady_clock::now();
+    // densities clamped to [rho_min, 1]
+    launch_b_clamp(c->tab, c->rho, c->oc.rho_min, 1.0, c->stream);
+    // filter + SIMP + loads + diagonal
+    launch_b_filter_simp(c->tab, c->rho, c->rhof, c->k, c->partials, c->sc, c->stream);
+    launch_b_setup_nodes(c->tab, c->k, c->b, c->dinv, c->partials, c->sc, c->stream);
+    launch_b_sub_mean3(c->tab, c->b, 1, c->sc, c->stream);
+    if ((rc = blaunch_ok(c, "prepare"))) return rc;
+    auto t1 = std::chrono::steady_clock::now();
+    const bool x_zero = !(c->so.guess == OTM_GUESS_PREVIOUS && c->have_solution);
+    if ((rc = solve(c, x_zero))) return rc;
+    c->have_solution = true;
+    auto t2 = std::chrono::steady_clock::now();
+    launch_b_energy(c->tab, c->k, c->x, c->partials, c->sc, c->stream);
+    if ((rc = sync_sc(c))) return rc;
+    std::vector<W6> w6(c->count);
+    std::vector<double> vstar(c->count);
+    bool conv = true;
+    for (int d = 0; d < c->count; ++d) {
+        const double nn = (double)c->prob[d].n * c->prob[d].n * c->prob[d].n;
+        const Scalars& s = c->h_sc[d];
+        double gg = 0.0;
+        for (int q = 0; q < 6; ++q) {
+            c->kappa[6 * d + q] = s.kappa_sum[q] / nn;
+            const double dv = c->kappa[6 * d + q] - c->prob[d].target[q];
+            gg += dv * dv;
+            w6[d].w[q] = 2.0 * dv;
+        }
+        if (!std::isfinite(gg)) return bfail(c, OTM_ENONFINITE, "non-finite tensor");
+        c->g[d] = gg;
+        c->volume[d] = s.sum_rho / nn;
+        c->low[d] = s.sum_rhofp / nn;
+        for (int l = 0; l < 3; ++l)
+            if (s.active[l]) conv = false;
+        if (recs) {
+            otm_iter_record& R = recs[d];
+            R.iter = c->iter;
+            R.g = gg;
+            std::memcpy(R.kappa, &c->kappa[6 * d], 6 * sizeof(double));
+            R.volume = c->volume[d];
+            R.low_bound = c->low[d];
+            for (int l = 0; l < 3; ++l) {
+                R.pcg_iters[l] = s.iters[l];
+                R.rel_residual[l] = s.bb[l] > 0.0 ? std::sqrt(s.rr_true[l] / s.bb[l]) : 0.0;
+            }
+        }
+        vstar[d] = gov_update(c->go, c->oc.rho_min, c->gov[d], gg, c->low[d], c->volume[d]);
+    }
+    BCHK(c, hipMemcpyAsync(c->dw6, w6.data(), c->count * sizeof(W6), hipMemcpyHostToDevice, c->stream));
+    BCHK(c, hipMemcpyAsync(c->dvstar, vstar.data(), c->count * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    // sensitivities and filter transpose
+    launch_b_sens(c->tab, c->rhof, c->x, c->dw6, c->st, c->stream);
+    launch_b_filter(c->tab, c->st, c->sens, c->stream);
+    // OC bisection for every design
+    launch_b_oc_prepare(c->tab, c->rho, c->sens, c->oc.eta, c->ocq, c->stream);
+    launch_b_oc_init(c->tab, c->sc, c->dvstar, c->oc.eta, c->stream);
+    const int max_passes = 200 / kOcLevels + 2;
+    for (int pass = 0; pass < max_passes; pass += 4) {
+        for (int q = 0; q < 4; ++q)
+            launch_b_oc_pass(c->tab, c->rho, c->ocq, c->oc.move, c->oc.rho_min, c->oc.eta, c->partials, c->sc,
+                             c->stream);
+        if ((rc = sync_sc(c))) return rc;
+        bool done = true;
+        for (int d = 0; d < c->count; ++d) done = done && c->h_sc[d].oc_done;
+        if (done) break;
+    }
+    launch_b_oc_apply(c->tab, c->rho, c->ocq, c->oc.eta, c->oc.move, c->oc.rho_min, c->sc, c->stream);
+    if ((rc = sync_sc(c))) return rc;
+    auto t3 = std::chrono::steady_clock::now();
+    if (recs)
+        for (int d = 0; d < c->count; ++d) {
+            recs[d].vstar = vstar[d];
+            recs[d].lambda = c->h_sc[d].lam;
+            recs[d].ms_total = std::chrono::duration<double, std::milli>(t3 - t0).count();
+            recs[d].ms_solve = std::chrono::duration<double, std::milli>(t2 - t1).count();
+            recs[d].stop = c->gov[d].small_steps >= c->go.stall_iters ? 1 : 0;
+        }
+    c->t_ms[0] = std::chrono::duration<double, std::milli>(t1 - t0).count();
+    c->t_ms[1] = std::chrono::duration<double, std::milli>(t2 - t1).count();
+    c->t_ms[2] = std::chrono::duration<double, std::milli>(t3 - t2).count();
+    c->t_ms[3] = std::chrono::duration<double, std::milli>(t3 - t0).count();
+    c->iter += 1;
+    return conv ? OTM_OK : OTM_NOT_CONVERGED;
+}
+
+int otm_batch_info(const otm_batch* c, double info8[8]) {
+    if (!c || !info8) return OTM_EINVAL;
+    info8[0] = (double)c->count;
+    info8[1] = (double)c->total;
+    info8[2] = (double)c->tab.mb_total;
+    info8[3] = (double)(2 * c->wx);
+    info8[4] = c->hdesc.empty() ? 0.0 : (double)c->hdesc[0].tz;
+    info8[5] = c->tune_us;
+    info8[6] = c->t_ms[1];
+    info8[7] = c->t_ms[3];
+    return OTM_OK;
+}
+
+const char* otm_batch_last_error(const otm_batch* c) { return c ? c->err.c_str() : "null batch"; }
+
+}  // extern "C"

@@ -18,10 +18,11 @@ __device__ __forceinline__ void wave_reduce(double (&v)[NV]) {
     }
 }
 
-// Block-level sum of NV values; thread 0..NV-1 write partials[blockIdx*NV + t].
+// Block-level sum of NV values; threads 0..NV-1 write partials[slot*NV + t]
+// (slot = blockIdx.x unless a persistent block processes several work items).
 // Uses a fixed reduction order (deterministic for a fixed launch shape).
 template <int NV>
-__device__ __forceinline__ void block_partials(double (&v)[NV], double* partials) {
+__device__ __forceinline__ void block_partials_at(double (&v)[NV], double* partials, int slot) {
     __shared__ double sh[NV][kBlock / 64];
     const int tid = threadIdx.x;
     const int lane = tid & 63, w = tid >> 6;
@@ -35,8 +36,14 @@ __device__ __forceinline__ void block_partials(double (&v)[NV], double* partials
         double s = 0.0;
 #pragma unroll
         for (int j = 0; j < kBlock / 64; ++j) s += sh[tid][j];
-        partials[(size_t)blockIdx.x * NV + tid] = s;
+        partials[(size_t)slot * NV + tid] = s;
     }
+    __syncthreads();
+}
+
+template <int NV>
+__device__ __forceinline__ void block_partials(double (&v)[NV], double* partials) {
+    block_partials_at<NV>(v, partials, blockIdx.x);
 }
 
 // Sum the partial arrays of all blocks (fixed order) -> out[NV] in shared memory.

@@ -44,6 +44,38 @@ struct Scalars {
     double cpow[kOcCands];    // candidate^-eta
 };
 
+// Separable periodic hat-filter weights (1-D, normalized), reach R <= 4.
+struct FilterW {
+    int R;
+    double w[9];
+};
+FilterW filter_weights(double r);
+
+struct W6 {
+    double w[6];
+};
+
+// ---- batched designs -------------------------------------------------------
+// Each design d owns the slice [off, off + n^3) of every n^3-sized arena and
+// [3 off, 3 off + 3 n^3) of every three-load arena.  Kernels over the batch
+// map work items to designs through the *_design tables; the items of a
+// design are contiguous so its per-item partial sums form one range.
+struct BatchDesc {
+    int n;
+    int64_t off;
+    int eb_start, eb_count;  // element/node sweep items
+    int mb_start, mb_count;  // z-march items
+    int ntx, nty, tz;        // z-march tiling of this design
+    double k0, kmin, penal;
+    FilterW fw;
+};
+struct BatchTab {
+    const BatchDesc* desc;
+    const int* eb_design;
+    const int* mb_design;
+    int count, eb_total, mb_total;
+};
+
 // Launch helpers (otm_kernels.hip).  All are asynchronous on `s`.
 // `partials`/`counter` are the shared reduction workspace; `sc` the device scalars.
 struct Workspace {
@@ -130,6 +162,37 @@ template <typename T>
 void launch_apply_tiled(int n, const TileShape& t, const T* k, const T* x, T* y, hipStream_t s);
 template <typename T>
 void launch_update_vec(int n, T* x, T* r, const T* p, const T* q, const T* dinv, const Workspace& ws, hipStream_t s);
+
+// Batched launches (one launch covers every design).
+void launch_b_clamp(const BatchTab& t, double* rho, double lo, double hi, hipStream_t s);
+void launch_b_filter_simp(const BatchTab& t, const double* rho, double* rhof, double* k, double* partials,
+                          Scalars* sc, hipStream_t s);
+void launch_b_setup_nodes(const BatchTab& t, const double* k, double* b, double* dinv, double* partials, Scalars* sc,
+                          hipStream_t s);
+void launch_b_sum3(const BatchTab& t, const double* x, int slot, double* partials, Scalars* sc, hipStream_t s);
+void launch_b_sub_mean3(const BatchTab& t, double* x, int slot, Scalars* sc, hipStream_t s);
+void launch_b_residual(const BatchTab& t, const double* k, const double* b, const double* x, double* r, double* p_old,
+                       const double* dinv, int mode, int x_zero, double* partials, Scalars* sc, hipStream_t s);
+void launch_b_energy(const BatchTab& t, const double* k, const double* chi, double* partials, Scalars* sc,
+                     hipStream_t s);
+void launch_b_sens(const BatchTab& t, const double* rhof, const double* chi, const W6* w6, double* st, hipStream_t s);
+void launch_b_filter(const BatchTab& t, const double* in, double* out, hipStream_t s);
+void launch_b_oc_prepare(const BatchTab& t, const double* rho, const double* sens, double eta, double* q,
+                         hipStream_t s);
+void launch_b_oc_init(const BatchTab& t, Scalars* sc, const double* vstar, double eta, hipStream_t s);
+void launch_b_oc_pass(const BatchTab& t, const double* rho, const double* q, double move, double rho_min, double eta,
+                      double* partials, Scalars* sc, hipStream_t s);
+void launch_b_oc_apply(const BatchTab& t, double* rho, const double* q, double eta, double move, double rho_min,
+                       Scalars* sc, hipStream_t s);
+void launch_b_finalize(const BatchTab& t, int op, int which_mb, double* partials, Scalars* sc, double eta,
+                       hipStream_t s);
+// z-march work-list launch (persistent blocks) and vector update, float64
+template <int WX, int TY>
+void launch_b_dir_march2(const BatchTab& t, int grid, const double* r, const double* dinv, const double* p_old,
+                         double* p_new, const double* k, double* q, double* partials, const Scalars* sc,
+                         hipStream_t s);
+void launch_b_update_vec(const BatchTab& t, int grid, double* x, double* r, const double* p, const double* q,
+                         const double* dinv, double* partials, const Scalars* sc, hipStream_t s);
 
 // Stateless operator y = A x (three loads)
 template <typename T>

@@ -21,12 +21,7 @@ namespace otm {
 // Separable periodic hat weights w(d) = max(0, r - |d|), normalized per axis;
 // the 3D weight is the product, so its normalization is the product of the
 // 1D normalizations.  Reach R < 4.
-struct FilterW {
-    int R;
-    double w[9];
-};
-
-static FilterW filter_weights(double r) {
+FilterW filter_weights(double r) {
     FilterW f{};
     if (!(r > 0.0)) {
         f.R = 0;
@@ -58,23 +53,26 @@ __device__ __forceinline__ double filter_at(const double* in, int n, int i, int 
     return acc;
 }
 
-__global__ void __launch_bounds__(kBlock) k_filter(int n, FilterW f, const double* __restrict__ in,
+__device__ __forceinline__ void b_filter(int bid_, int nblk_, int n, FilterW f, const double* __restrict__ in,
                                                    double* __restrict__ out) {
     const int64_t nn = (int64_t)n * n * n;
-    const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (e >= nn) return;
-    const int i = (int)(e % n), j = (int)((e / n) % n), k = (int)(e / ((int64_t)n * n));
-    out[e] = filter_at(in, n, i, j, k, f);
+    for (int64_t e = (int64_t)bid_ * kBlock + threadIdx.x; e < nn; e += (int64_t)nblk_ * kBlock) {
+        const int i = (int)(e % n), j = (int)((e / n) % n), k = (int)(e / ((int64_t)n * n));
+        out[e] = filter_at(in, n, i, j, k, f);
+    }
 }
 
+__global__ void __launch_bounds__(kBlock) k_filter(int n, FilterW f, const double* __restrict__ in,
+                                                   double* __restrict__ out) { b_filter(blockIdx.x, gridDim.x, n, f, in, out); }
+
 // rho -> rho~ -> k (SIMP), plus the sums of rho and rho~^p.
-__global__ void __launch_bounds__(kBlock) k_filter_simp(int n, FilterW f, const double* __restrict__ rho,
+__device__ __forceinline__ void b_filter_simp(int bid_, int nblk_, int n, FilterW f, const double* __restrict__ rho,
                                                         double* __restrict__ rhof, double* __restrict__ k,
                                                         float* __restrict__ k32, double k0, double kmin, double p,
                                                         double* partials, unsigned* counter, Scalars* sc) {
     const int64_t nn = (int64_t)n * n * n;
     double acc[2] = {0.0, 0.0};
-    for (int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x; e < nn; e += (int64_t)gridDim.x * kBlock) {
+    for (int64_t e = (int64_t)bid_ * kBlock + threadIdx.x; e < nn; e += (int64_t)nblk_ * kBlock) {
         const int i = (int)(e % n), j = (int)((e / n) % n), kk = (int)(e / ((int64_t)n * n));
         const double rf = filter_at(rho, n, i, j, kk, f);
         const double rp = pow(rf, p);
@@ -88,17 +86,22 @@ __global__ void __launch_bounds__(kBlock) k_filter_simp(int n, FilterW f, const 
     block_partials<2>(acc, partials);
 }
 
+__global__ void __launch_bounds__(kBlock) k_filter_simp(int n, FilterW f, const double* __restrict__ rho,
+                                                        double* __restrict__ rhof, double* __restrict__ k,
+                                                        float* __restrict__ k32, double k0, double kmin, double p,
+                                                        double* partials, unsigned* counter, Scalars* sc) { b_filter_simp(blockIdx.x, gridDim.x, n, f, rho, rhof, k, k32, k0, kmin, p, partials, counter, sc); }
+
 // ---------------------------------------------------------------- node setup
 // Macro load b^i_v = (1/4)(sum of k over the 4 incident elements on the -i side
 // of v  -  sum over the 4 on the +i side); Jacobi diagonal d_v = (1/3) sum of
 // the 8 incident k.  Also the sums of b^i (they vanish up to rounding; the
 // engine projects b to zero mean).
-__global__ void __launch_bounds__(kBlock) k_setup_nodes(int n, const double* __restrict__ k, double* __restrict__ b,
+__device__ __forceinline__ void b_setup_nodes(int bid_, int nblk_, int n, const double* __restrict__ k, double* __restrict__ b,
                                                         double* __restrict__ dinv, float* __restrict__ dinv32,
                                                         double* partials, unsigned* counter, Scalars* sc) {
     const int64_t nn = (int64_t)n * n * n;
     double acc[3] = {0.0, 0.0, 0.0};
-    for (int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x; v < nn; v += (int64_t)gridDim.x * kBlock) {
+    for (int64_t v = (int64_t)bid_ * kBlock + threadIdx.x; v < nn; v += (int64_t)nblk_ * kBlock) {
         const int i = (int)(v % n), j = (int)((v / n) % n), kk = (int)(v / ((int64_t)n * n));
         const int xi[2] = {wrapi(i - 1, n), i};
         const int yj[2] = {wrapi(j - 1, n) * n, j * n};
@@ -128,6 +131,10 @@ __global__ void __launch_bounds__(kBlock) k_setup_nodes(int n, const double* __r
     block_partials<3>(acc, partials);
 }
 
+__global__ void __launch_bounds__(kBlock) k_setup_nodes(int n, const double* __restrict__ k, double* __restrict__ b,
+                                                        double* __restrict__ dinv, float* __restrict__ dinv32,
+                                                        double* partials, unsigned* counter, Scalars* sc) { b_setup_nodes(blockIdx.x, gridDim.x, n, k, b, dinv, dinv32, partials, counter, sc); }
+
 // ---------------------------------------------------------------- operator
 template <typename T>
 __global__ void __launch_bounds__(kBlock) k_apply(int n, const T* __restrict__ k, const T* __restrict__ x,
@@ -150,7 +157,7 @@ __global__ void __launch_bounds__(kBlock) k_apply(int n, const T* __restrict__ k
 // (REFRESH); sums ||r||^2, r.D^-1 r, ||b||^2 -> epilogue per mode.
 
 template <typename TR>
-__global__ void __launch_bounds__(kBlock) k_residual(int n, const double* __restrict__ k, const double* __restrict__ b,
+__device__ __forceinline__ void b_residual(int bid_, int nblk_, int n, const double* __restrict__ k, const double* __restrict__ b,
                                                      const double* __restrict__ x, TR* __restrict__ r,
                                                      TR* __restrict__ p_old, const TR* __restrict__ dinv, int mode,
                                                      int x_zero, double* partials, unsigned* counter, Scalars* sc) {
@@ -158,7 +165,7 @@ __global__ void __launch_bounds__(kBlock) k_residual(int n, const double* __rest
     double acc[9];
 #pragma unroll
     for (int q = 0; q < 9; ++q) acc[q] = 0.0;
-    for (int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x; v < nn; v += (int64_t)gridDim.x * kBlock) {
+    for (int64_t v = (int64_t)bid_ * kBlock + threadIdx.x; v < nn; v += (int64_t)nblk_ * kBlock) {
         double ax[3] = {0.0, 0.0, 0.0};
         if (!x_zero) {
             const int i = (int)(v % n), j = (int)((v / n) % n), kk = (int)(v / ((int64_t)n * n));
@@ -185,6 +192,12 @@ __global__ void __launch_bounds__(kBlock) k_residual(int n, const double* __rest
     }
     block_partials<9>(acc, partials);
 }
+
+template <typename TR>
+__global__ void __launch_bounds__(kBlock) k_residual(int n, const double* __restrict__ k, const double* __restrict__ b,
+                                                     const double* __restrict__ x, TR* __restrict__ r,
+                                                     TR* __restrict__ p_old, const TR* __restrict__ dinv, int mode,
+                                                     int x_zero, double* partials, unsigned* counter, Scalars* sc) { b_residual<TR>(blockIdx.x, gridDim.x, n, k, b, x, r, p_old, dinv, mode, x_zero, partials, counter, sc); }
 
 // p_new = D^-1 r + beta p_old (beta == 0 -> p_new = D^-1 r) for active loads.
 template <typename T>
@@ -263,28 +276,33 @@ __global__ void __launch_bounds__(kBlock) k_accumulate(int64_t count, double* __
 }
 
 // sums of the three loads of x -> sc->xsum (slot 0) or sc->bsum (slot 1)
-__global__ void __launch_bounds__(kBlock) k_sum3(int n, const double* __restrict__ x, int slot, double* partials,
+__device__ __forceinline__ void b_sum3(int bid_, int nblk_, int n, const double* __restrict__ x, int slot, double* partials,
                                                  unsigned* counter, Scalars* sc) {
     const int64_t nn = (int64_t)n * n * n;
     double acc[3] = {0, 0, 0};
-    for (int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x; v < nn; v += (int64_t)gridDim.x * kBlock) {
+    for (int64_t v = (int64_t)bid_ * kBlock + threadIdx.x; v < nn; v += (int64_t)nblk_ * kBlock) {
 #pragma unroll
         for (int l = 0; l < 3; ++l) acc[l] += x[l * nn + v];
     }
     block_partials<3>(acc, partials);
 }
 
+__global__ void __launch_bounds__(kBlock) k_sum3(int n, const double* __restrict__ x, int slot, double* partials,
+                                                 unsigned* counter, Scalars* sc) { b_sum3(blockIdx.x, gridDim.x, n, x, slot, partials, counter, sc); }
+
 // x^l -= sum^l / n^3 with the sum taken from slot 0 (xsum) or 1 (bsum)
-__global__ void __launch_bounds__(kBlock) k_sub_mean3(int n, double* __restrict__ x, int slot, const Scalars* sc) {
+__device__ __forceinline__ void b_sub_mean3(int bid_, int nblk_, int n, double* __restrict__ x, int slot, const Scalars* sc) {
     const int64_t nn = (int64_t)n * n * n;
-    const int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (v >= nn) return;
+    for (int64_t v = (int64_t)bid_ * kBlock + threadIdx.x; v < nn; v += (int64_t)nblk_ * kBlock) {
 #pragma unroll
-    for (int l = 0; l < 3; ++l) {
-        const double m = (slot == 0 ? sc->xsum[l] : sc->bsum[l]) / (double)nn;
-        x[l * nn + v] -= m;
+        for (int l = 0; l < 3; ++l) {
+            const double m = (slot == 0 ? sc->xsum[l] : sc->bsum[l]) / (double)nn;
+            x[l * nn + v] -= m;
+        }
     }
 }
+
+__global__ void __launch_bounds__(kBlock) k_sub_mean3(int n, double* __restrict__ x, int slot, const Scalars* sc) { b_sub_mean3(blockIdx.x, gridDim.x, n, x, slot, sc); }
 
 // ---------------------------------------------------------------- tensor
 // u^i_l = X_{l,i} - chi^i(vertex l);  E_c = u^i . K u^j for the six pairs.
@@ -323,11 +341,11 @@ __device__ __forceinline__ void element_energies(const double* __restrict__ chi,
     }
 }
 
-__global__ void __launch_bounds__(kBlock) k_energy(int n, const double* __restrict__ k, const double* __restrict__ chi,
+__device__ __forceinline__ void b_energy(int bid_, int nblk_, int n, const double* __restrict__ k, const double* __restrict__ chi,
                                                    double* partials, unsigned* counter, Scalars* sc) {
     const int64_t nn = (int64_t)n * n * n;
     double acc[6] = {0, 0, 0, 0, 0, 0};
-    for (int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x; e < nn; e += (int64_t)gridDim.x * kBlock) {
+    for (int64_t e = (int64_t)bid_ * kBlock + threadIdx.x; e < nn; e += (int64_t)nblk_ * kBlock) {
         const int i = (int)(e % n), j = (int)((e / n) % n), kk = (int)(e / ((int64_t)n * n));
         double E[6];
         element_energies(chi, nn, n, i, j, kk, E);
@@ -338,16 +356,14 @@ __global__ void __launch_bounds__(kBlock) k_energy(int n, const double* __restri
     block_partials<6>(acc, partials);
 }
 
-struct W6 {
-    double w[6];
-};
+__global__ void __launch_bounds__(kBlock) k_energy(int n, const double* __restrict__ k, const double* __restrict__ chi,
+                                                   double* partials, unsigned* counter, Scalars* sc) { b_energy(blockIdx.x, gridDim.x, n, k, chi, partials, counter, sc); }
 
 // s~_e = n^-3 p rho~^(p-1) (k0 - kmin) sum_c w_c E_e,c
-__global__ void __launch_bounds__(kBlock) k_sens(int n, const double* __restrict__ rhof, const double* __restrict__ chi,
+__device__ __forceinline__ void b_sens(int bid_, int nblk_, int n, const double* __restrict__ rhof, const double* __restrict__ chi,
                                                  W6 w, double k0, double kmin, double p, double* __restrict__ st) {
     const int64_t nn = (int64_t)n * n * n;
-    const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (e >= nn) return;
+    for (int64_t e = (int64_t)bid_ * kBlock + threadIdx.x; e < nn; e += (int64_t)nblk_ * kBlock) {
     const int i = (int)(e % n), j = (int)((e / n) % n), kk = (int)(e / ((int64_t)n * n));
     double E[6];
     element_energies(chi, nn, n, i, j, kk, E);
@@ -355,18 +371,26 @@ __global__ void __launch_bounds__(kBlock) k_sens(int n, const double* __restrict
 #pragma unroll
     for (int c = 0; c < 6; ++c) s += w.w[c] * E[c];
     st[e] = p * pow(rhof[e], p - 1.0) * (k0 - kmin) * s / (double)nn;
+    }
 }
+
+__global__ void __launch_bounds__(kBlock) k_sens(int n, const double* __restrict__ rhof, const double* __restrict__ chi,
+                                                 W6 w, double k0, double kmin, double p, double* __restrict__ st) { b_sens(blockIdx.x, gridDim.x, n, rhof, chi, w, k0, kmin, p, st); }
 
 // ---------------------------------------------------------------- OC
 // q_e = rho_e (max(0, -s_e) n^3)^eta ; rho_new(lam) = clamp(q lam^-eta, lo, hi)
-__global__ void __launch_bounds__(kBlock) k_oc_prepare(int64_t nn, const double* __restrict__ rho,
+__device__ __forceinline__ void b_oc_prepare(int bid_, int nblk_, int64_t nn, const double* __restrict__ rho,
                                                        const double* __restrict__ s, double eta,
                                                        double* __restrict__ q) {
-    const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (e >= nn) return;
+    for (int64_t e = (int64_t)bid_ * kBlock + threadIdx.x; e < nn; e += (int64_t)nblk_ * kBlock) {
     const double B = fmax(0.0, -s[e]) * (double)nn;
     q[e] = rho[e] * (eta == 0.5 ? sqrt(B) : pow(B, eta));
+    }
 }
+
+__global__ void __launch_bounds__(kBlock) k_oc_prepare(int64_t nn, const double* __restrict__ rho,
+                                                       const double* __restrict__ s, double eta,
+                                                       double* __restrict__ q) { b_oc_prepare(blockIdx.x, gridDim.x, nn, rho, s, eta, q); }
 
 // Candidates of the next kOcLevels bisection levels below [l1, l2], in
 // breadth-first order of the midpoint tree, each computed exactly as the
@@ -405,7 +429,7 @@ __global__ void k_oc_init(Scalars* sc, double vstar_n, double eta) {
 
 // One pass: sum clamp(q c_m, lo, hi) for every candidate, then walk the tree
 // with the sequential stopping rule (width <= 1e-13 (l1 + l2), 200 halvings).
-__global__ void __launch_bounds__(kBlock) k_oc_pass(int64_t nn, const double* __restrict__ rho,
+__device__ __forceinline__ void b_oc_pass(int bid_, int nblk_, int64_t nn, const double* __restrict__ rho,
                                                     const double* __restrict__ q, double move, double rho_min,
                                                     double eta, double* partials, unsigned* counter, Scalars* sc) {
     if (sc->oc_done) return;
@@ -415,7 +439,7 @@ __global__ void __launch_bounds__(kBlock) k_oc_pass(int64_t nn, const double* __
     double acc[kOcCands];
 #pragma unroll
     for (int t = 0; t < kOcCands; ++t) acc[t] = 0.0;
-    for (int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x; e < nn; e += (int64_t)gridDim.x * kBlock) {
+    for (int64_t e = (int64_t)bid_ * kBlock + threadIdx.x; e < nn; e += (int64_t)nblk_ * kBlock) {
         const double r = rho[e], qe = q[e];
         const double lo = fmax(rho_min, r - move), hi = fmin(1.0, r + move);
 #pragma unroll
@@ -424,22 +448,31 @@ __global__ void __launch_bounds__(kBlock) k_oc_pass(int64_t nn, const double* __
     block_partials<kOcCands>(acc, partials);
 }
 
-__global__ void __launch_bounds__(kBlock) k_oc_apply(int64_t nn, double* __restrict__ rho, const double* __restrict__ q,
+__global__ void __launch_bounds__(kBlock) k_oc_pass(int64_t nn, const double* __restrict__ rho,
+                                                    const double* __restrict__ q, double move, double rho_min,
+                                                    double eta, double* partials, unsigned* counter, Scalars* sc) { b_oc_pass(blockIdx.x, gridDim.x, nn, rho, q, move, rho_min, eta, partials, counter, sc); }
+
+__device__ __forceinline__ void b_oc_apply(int bid_, int nblk_, int64_t nn, double* __restrict__ rho, const double* __restrict__ q,
                                                      double eta, double move, double rho_min, const Scalars* sc) {
-    const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (e >= nn) return;
+    for (int64_t e = (int64_t)bid_ * kBlock + threadIdx.x; e < nn; e += (int64_t)nblk_ * kBlock) {
     const double lam = sc->lam;
     const double c = (eta == 0.5) ? 1.0 / sqrt(lam) : pow(lam, -eta);
     const double r = rho[e];
     const double lo = fmax(rho_min, r - move), hi = fmin(1.0, r + move);
     rho[e] = fmin(hi, fmax(lo, q[e] * c));
+    }
 }
 
-__global__ void __launch_bounds__(kBlock) k_clamp(int64_t nn, double* __restrict__ rho, double lo, double hi) {
-    const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
-    if (e >= nn) return;
+__global__ void __launch_bounds__(kBlock) k_oc_apply(int64_t nn, double* __restrict__ rho, const double* __restrict__ q,
+                                                     double eta, double move, double rho_min, const Scalars* sc) { b_oc_apply(blockIdx.x, gridDim.x, nn, rho, q, eta, move, rho_min, sc); }
+
+__device__ __forceinline__ void b_clamp(int bid_, int nblk_, int64_t nn, double* __restrict__ rho, double lo, double hi) {
+    for (int64_t e = (int64_t)bid_ * kBlock + threadIdx.x; e < nn; e += (int64_t)nblk_ * kBlock) {
     rho[e] = fmin(hi, fmax(lo, rho[e]));
+    }
 }
+
+__global__ void __launch_bounds__(kBlock) k_clamp(int64_t nn, double* __restrict__ rho, double lo, double hi) { b_clamp(blockIdx.x, gridDim.x, nn, rho, lo, hi); }
 
 __global__ void k_fill_u32(unsigned* p, int count, unsigned v) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
@@ -457,8 +490,8 @@ __device__ __forceinline__ void fin_sums(const double* partials, int nblocks, do
     final_sums<NV>(partials, nblocks, tot);
 }
 
-__global__ void __launch_bounds__(kBlock) k_finalize(int op, int nblocks, const double* __restrict__ partials,
-                                                     Scalars* sc, int64_t nn, double eta) {
+__device__ __forceinline__ void b_finalize(int op, int nblocks, const double* __restrict__ partials, Scalars* sc,
+                                           int64_t nn, double eta) {
     __shared__ double tot[kMaxReduce];
     switch (op) {
         case FIN_FILTER_SIMP: fin_sums<2>(partials, nblocks, tot); break;
@@ -533,6 +566,7 @@ __global__ void __launch_bounds__(kBlock) k_finalize(int op, int nblocks, const 
             for (int c = 0; c < 6; ++c) sc->kappa_sum[c] = tot[c];
             break;
         case FIN_OC: {
+            if (sc->oc_done) break;
             double l1 = sc->l1, l2 = sc->l2;
             int steps = sc->oc_steps;
             int node = 0;
@@ -566,6 +600,11 @@ __global__ void __launch_bounds__(kBlock) k_finalize(int op, int nblocks, const 
         }
         default: break;
     }
+}
+
+__global__ void __launch_bounds__(kBlock) k_finalize(int op, int nblocks, const double* __restrict__ partials,
+                                                     Scalars* sc, int64_t nn, double eta) {
+    b_finalize(op, nblocks, partials, sc, nn, eta);
 }
 
 void launch_finalize(int op, int nblocks, const Workspace& ws, hipStream_t s, int64_t nn, double eta) {
@@ -727,6 +766,190 @@ void launch_cast_f64_f32(int64_t count, const double* in, float* out, hipStream_
 }
 void launch_cast_f32_f64(int64_t count, const float* in, double* out, hipStream_t s) {
     hipLaunchKernelGGL(k_cast_f32_f64, dim3(nblocks_for(count)), dim3(kBlock), 0, s, count, in, out);
+}
+
+}  // namespace otm
+
+// ====================================================================== batch
+// One launch covers every design of a batch: work item (block) g belongs to
+// design t.eb_design[g] and runs the single-design body on that design's
+// slices with the design-local block index.  Partial sums land in slot g, so
+// the items of design d occupy the contiguous range of its descriptor.
+namespace otm {
+
+#define OTM_BATCH_ITEM                                        \
+    const int g_ = blockIdx.x;                                \
+    const int d_ = t.eb_design[g_];                           \
+    const BatchDesc D = t.desc[d_];                           \
+    const int lb_ = g_ - D.eb_start;                          \
+    const int nb_ = D.eb_count;                               \
+    const int64_t o1 = D.off, o3 = 3 * D.off;                 \
+    (void)o1;                                                 \
+    (void)o3;
+
+__global__ void __launch_bounds__(kBlock) kb_clamp(BatchTab t, double* rho, double lo, double hi) {
+    OTM_BATCH_ITEM
+    b_clamp(lb_, nb_, (int64_t)D.n * D.n * D.n, rho + o1, lo, hi);
+}
+
+__global__ void __launch_bounds__(kBlock) kb_filter_simp(BatchTab t, const double* rho, double* rhof, double* k,
+                                                         double* partials, Scalars* sc) {
+    OTM_BATCH_ITEM
+    b_filter_simp(lb_, nb_, D.n, D.fw, rho + o1, rhof + o1, k + o1, nullptr, D.k0, D.kmin, D.penal, partials, nullptr,
+                  sc + d_);
+}
+
+__global__ void __launch_bounds__(kBlock) kb_setup_nodes(BatchTab t, const double* k, double* b, double* dinv,
+                                                         double* partials, Scalars* sc) {
+    OTM_BATCH_ITEM
+    b_setup_nodes(lb_, nb_, D.n, k + o1, b + o3, dinv + o1, nullptr, partials, nullptr, sc + d_);
+}
+
+__global__ void __launch_bounds__(kBlock) kb_sum3(BatchTab t, const double* x, int slot, double* partials,
+                                                  Scalars* sc) {
+    OTM_BATCH_ITEM
+    b_sum3(lb_, nb_, D.n, x + o3, slot, partials, nullptr, sc + d_);
+}
+
+__global__ void __launch_bounds__(kBlock) kb_sub_mean3(BatchTab t, double* x, int slot, Scalars* sc) {
+    OTM_BATCH_ITEM
+    b_sub_mean3(lb_, nb_, D.n, x + o3, slot, sc + d_);
+}
+
+__global__ void __launch_bounds__(kBlock) kb_residual(BatchTab t, const double* k, const double* b, const double* x,
+                                                      double* r, double* p_old, const double* dinv, int mode,
+                                                      int x_zero, double* partials, Scalars* sc) {
+    OTM_BATCH_ITEM
+    b_residual<double>(lb_, nb_, D.n, k + o1, b + o3, x + o3, r + o3, p_old + o3, dinv + o1, mode, x_zero, partials,
+                       nullptr, sc + d_);
+}
+
+__global__ void __launch_bounds__(kBlock) kb_energy(BatchTab t, const double* k, const double* chi, double* partials,
+                                                    Scalars* sc) {
+    OTM_BATCH_ITEM
+    b_energy(lb_, nb_, D.n, k + o1, chi + o3, partials, nullptr, sc + d_);
+}
+
+__global__ void __launch_bounds__(kBlock) kb_sens(BatchTab t, const double* rhof, const double* chi, const W6* w6,
+                                                  double* st) {
+    OTM_BATCH_ITEM
+    b_sens(lb_, nb_, D.n, rhof + o1, chi + o3, w6[d_], D.k0, D.kmin, D.penal, st + o1);
+}
+
+__global__ void __launch_bounds__(kBlock) kb_filter(BatchTab t, const double* in, double* out) {
+    OTM_BATCH_ITEM
+    b_filter(lb_, nb_, D.n, D.fw, in + o1, out + o1);
+}
+
+__global__ void __launch_bounds__(kBlock) kb_oc_prepare(BatchTab t, const double* rho, const double* sens, double eta,
+                                                        double* q) {
+    OTM_BATCH_ITEM
+    b_oc_prepare(lb_, nb_, (int64_t)D.n * D.n * D.n, rho + o1, sens + o1, eta, q + o1);
+}
+
+__global__ void kb_oc_init(BatchTab t, Scalars* sc, const double* vstar, double eta) {
+    const int d = blockIdx.x;
+    if (threadIdx.x != 0 || d >= t.count) return;
+    const int n = t.desc[d].n;
+    Scalars* s = sc + d;
+    s->l1 = 0.0;
+    s->l2 = 1e9;
+    s->vstar_n = vstar[d] * (double)n * n * n;
+    s->oc_steps = 0;
+    s->oc_done = 0;
+    oc_make_candidates(s, eta);
+}
+
+__global__ void __launch_bounds__(kBlock) kb_oc_pass(BatchTab t, const double* rho, const double* q, double move,
+                                                     double rho_min, double eta, double* partials, Scalars* sc) {
+    OTM_BATCH_ITEM
+    b_oc_pass(lb_, nb_, (int64_t)D.n * D.n * D.n, rho + o1, q + o1, move, rho_min, eta, partials, nullptr, sc + d_);
+}
+
+__global__ void __launch_bounds__(kBlock) kb_oc_apply(BatchTab t, double* rho, const double* q, double eta,
+                                                      double move, double rho_min, const Scalars* sc) {
+    OTM_BATCH_ITEM
+    b_oc_apply(lb_, nb_, (int64_t)D.n * D.n * D.n, rho + o1, q + o1, eta, move, rho_min, sc + d_);
+}
+
+static int fin_width(int op) {
+    switch (op) {
+        case FIN_FILTER_SIMP: return 2;
+        case FIN_RES_START:
+        case FIN_RES_REFRESH: return 9;
+        case FIN_UPDATE:
+        case FIN_ENERGY: return 6;
+        case FIN_OC: return kOcCands;
+        default: return 3;
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) kb_finalize(BatchTab t, int op, int which_mb, int width,
+                                                      const double* partials, Scalars* sc, double eta) {
+    const int d = blockIdx.x;
+    const BatchDesc D = t.desc[d];
+    const int start = which_mb ? D.mb_start : D.eb_start;
+    const int cnt = which_mb ? D.mb_count : D.eb_count;
+    b_finalize(op, cnt, partials + (size_t)start * width, sc + d, (int64_t)D.n * D.n * D.n, eta);
+}
+
+void launch_b_clamp(const BatchTab& t, double* rho, double lo, double hi, hipStream_t s) {
+    hipLaunchKernelGGL(kb_clamp, dim3(t.eb_total), dim3(kBlock), 0, s, t, rho, lo, hi);
+}
+void launch_b_filter_simp(const BatchTab& t, const double* rho, double* rhof, double* k, double* partials,
+                          Scalars* sc, hipStream_t s) {
+    hipLaunchKernelGGL(kb_filter_simp, dim3(t.eb_total), dim3(kBlock), 0, s, t, rho, rhof, k, partials, sc);
+    launch_b_finalize(t, FIN_FILTER_SIMP, 0, partials, sc, 0.5, s);
+}
+void launch_b_setup_nodes(const BatchTab& t, const double* k, double* b, double* dinv, double* partials, Scalars* sc,
+                          hipStream_t s) {
+    hipLaunchKernelGGL(kb_setup_nodes, dim3(t.eb_total), dim3(kBlock), 0, s, t, k, b, dinv, partials, sc);
+    launch_b_finalize(t, FIN_SETUP, 0, partials, sc, 0.5, s);
+}
+void launch_b_sum3(const BatchTab& t, const double* x, int slot, double* partials, Scalars* sc, hipStream_t s) {
+    hipLaunchKernelGGL(kb_sum3, dim3(t.eb_total), dim3(kBlock), 0, s, t, x, slot, partials, sc);
+    launch_b_finalize(t, slot == 0 ? FIN_SUM3_X : FIN_SUM3_B, 0, partials, sc, 0.5, s);
+}
+void launch_b_sub_mean3(const BatchTab& t, double* x, int slot, Scalars* sc, hipStream_t s) {
+    hipLaunchKernelGGL(kb_sub_mean3, dim3(t.eb_total), dim3(kBlock), 0, s, t, x, slot, sc);
+}
+void launch_b_residual(const BatchTab& t, const double* k, const double* b, const double* x, double* r, double* p_old,
+                       const double* dinv, int mode, int x_zero, double* partials, Scalars* sc, hipStream_t s) {
+    hipLaunchKernelGGL(kb_residual, dim3(t.eb_total), dim3(kBlock), 0, s, t, k, b, x, r, p_old, dinv, mode, x_zero,
+                       partials, sc);
+    launch_b_finalize(t, mode == RES_START ? FIN_RES_START : FIN_RES_REFRESH, 0, partials, sc, 0.5, s);
+}
+void launch_b_energy(const BatchTab& t, const double* k, const double* chi, double* partials, Scalars* sc,
+                     hipStream_t s) {
+    hipLaunchKernelGGL(kb_energy, dim3(t.eb_total), dim3(kBlock), 0, s, t, k, chi, partials, sc);
+    launch_b_finalize(t, FIN_ENERGY, 0, partials, sc, 0.5, s);
+}
+void launch_b_sens(const BatchTab& t, const double* rhof, const double* chi, const W6* w6, double* st, hipStream_t s) {
+    hipLaunchKernelGGL(kb_sens, dim3(t.eb_total), dim3(kBlock), 0, s, t, rhof, chi, w6, st);
+}
+void launch_b_filter(const BatchTab& t, const double* in, double* out, hipStream_t s) {
+    hipLaunchKernelGGL(kb_filter, dim3(t.eb_total), dim3(kBlock), 0, s, t, in, out);
+}
+void launch_b_oc_prepare(const BatchTab& t, const double* rho, const double* sens, double eta, double* q,
+                         hipStream_t s) {
+    hipLaunchKernelGGL(kb_oc_prepare, dim3(t.eb_total), dim3(kBlock), 0, s, t, rho, sens, eta, q);
+}
+void launch_b_oc_init(const BatchTab& t, Scalars* sc, const double* vstar, double eta, hipStream_t s) {
+    hipLaunchKernelGGL(kb_oc_init, dim3(t.count), dim3(64), 0, s, t, sc, vstar, eta);
+}
+void launch_b_oc_pass(const BatchTab& t, const double* rho, const double* q, double move, double rho_min, double eta,
+                      double* partials, Scalars* sc, hipStream_t s) {
+    hipLaunchKernelGGL(kb_oc_pass, dim3(t.eb_total), dim3(kBlock), 0, s, t, rho, q, move, rho_min, eta, partials, sc);
+    launch_b_finalize(t, FIN_OC, 0, partials, sc, eta, s);
+}
+void launch_b_oc_apply(const BatchTab& t, double* rho, const double* q, double eta, double move, double rho_min,
+                       Scalars* sc, hipStream_t s) {
+    hipLaunchKernelGGL(kb_oc_apply, dim3(t.eb_total), dim3(kBlock), 0, s, t, rho, q, eta, move, rho_min, sc);
+}
+void launch_b_finalize(const BatchTab& t, int op, int which_mb, double* partials, Scalars* sc, double eta,
+                       hipStream_t s) {
+    hipLaunchKernelGGL(kb_finalize, dim3(t.count), dim3(kBlock), 0, s, t, op, which_mb, fin_width(op), partials, sc,
+                       eta);
 }
 
 }  // namespace otm

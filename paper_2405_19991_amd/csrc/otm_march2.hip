@@ -29,11 +29,11 @@ struct Pre2 {
 
 // ALL: every load is active (DIR) -- removes the per-load branches.
 template <typename T, int WX, int TY, bool DIR, bool ALL>
-__global__ void __launch_bounds__(WX* TY) k_march2(int n, int tz, int ntx, int nty, const T* __restrict__ r,
-                                                   const T* __restrict__ dinv, const T* __restrict__ p_old,
-                                                   T* __restrict__ p_new, const T* __restrict__ k,
-                                                   T* __restrict__ q, double* __restrict__ partials,
-                                                   const Scalars* __restrict__ sc) {
+__device__ __forceinline__ void march2_body(int bid_, int slot_, int n, int tz, int ntx, int nty,
+                                            const T* __restrict__ r, const T* __restrict__ dinv,
+                                            const T* __restrict__ p_old, T* __restrict__ p_new,
+                                            const T* __restrict__ k, T* __restrict__ q, double* __restrict__ partials,
+                                            const Scalars* __restrict__ sc) {
     typedef typename V2<T>::type T2;
     static_assert(WX * TY == kBlock, "block size");
     constexpr int TX = 2 * WX;                   // nodes per tile row
@@ -49,7 +49,7 @@ __global__ void __launch_bounds__(WX* TY) k_march2(int n, int tz, int ntx, int n
 
     const int tid = threadIdx.x;
     const int tx = tid % WX, ty = tid / WX;
-    int bid = blockIdx.x;
+    int bid = bid_;
     const int bx = bid % ntx;
     bid /= ntx;
     const int by = bid % nty;
@@ -288,7 +288,17 @@ __global__ void __launch_bounds__(WX* TY) k_march2(int n, int tz, int ntx, int n
         compute(P);
     }
     if (!DIR) return;
-    block_partials<3>(acc, partials);
+    block_partials_at<3>(acc, partials, slot_);
+}
+
+template <typename T, int WX, int TY, bool DIR, bool ALL>
+__global__ void __launch_bounds__(WX* TY) k_march2(int n, int tz, int ntx, int nty, const T* __restrict__ r,
+                                                   const T* __restrict__ dinv, const T* __restrict__ p_old,
+                                                   T* __restrict__ p_new, const T* __restrict__ k,
+                                                   T* __restrict__ q, double* __restrict__ partials,
+                                                   const Scalars* __restrict__ sc) {
+    march2_body<T, WX, TY, DIR, ALL>(blockIdx.x, blockIdx.x, n, tz, ntx, nty, r, dinv, p_old, p_new, k, q, partials,
+                                     sc);
 }
 
 template <typename T, bool DIR, bool ALL>
@@ -346,5 +356,43 @@ template void launch_dir_march2<float>(int, const TileShape&, bool, const float*
                                        const float*, float*, const Workspace&, hipStream_t);
 template void launch_apply_march2<double>(int, const TileShape&, const double*, const double*, double*, hipStream_t);
 template void launch_apply_march2<float>(int, const TileShape&, const float*, const float*, float*, hipStream_t);
+
+}  // namespace otm
+
+namespace otm {
+
+// Batched direction + operator pass: persistent blocks walk the work list of
+// (design, tile) items; an item of an inactive or converged design still runs
+// (its loads' activity flags are read per design), which keeps the per-item
+// partial slots of every design filled for its finalize.
+template <int WX, int TY>
+__global__ void __launch_bounds__(WX* TY) kb_dir_march2(BatchTab t, const double* __restrict__ r,
+                                                        const double* __restrict__ dinv,
+                                                        const double* __restrict__ p_old, double* __restrict__ p_new,
+                                                        const double* __restrict__ k, double* __restrict__ q,
+                                                        double* __restrict__ partials, const Scalars* __restrict__ sc) {
+    for (int item = blockIdx.x; item < t.mb_total; item += gridDim.x) {
+        const int d = t.mb_design[item];
+        const BatchDesc D = t.desc[d];
+        const int64_t o1 = D.off, o3 = 3 * D.off;
+        __syncthreads();
+        march2_body<double, WX, TY, true, false>(item - D.mb_start, item, D.n, D.tz, D.ntx, D.nty, r + o3, dinv + o1,
+                                                 p_old + o3, p_new + o3, k + o1, q + o3, partials, sc + d);
+    }
+}
+
+template <int WX, int TY>
+void launch_b_dir_march2(const BatchTab& t, int grid, const double* r, const double* dinv, const double* p_old,
+                         double* p_new, const double* k, double* q, double* partials, const Scalars* sc,
+                         hipStream_t s) {
+    hipLaunchKernelGGL((kb_dir_march2<WX, TY>), dim3(grid), dim3(kBlock), 0, s, t, r, dinv, p_old, p_new, k, q,
+                       partials, sc);
+    launch_b_finalize(t, FIN_PQ, 1, partials, const_cast<Scalars*>(sc), 0.5, s);
+}
+
+template void launch_b_dir_march2<32, 8>(const BatchTab&, int, const double*, const double*, const double*, double*,
+                                         const double*, double*, double*, const Scalars*, hipStream_t);
+template void launch_b_dir_march2<16, 16>(const BatchTab&, int, const double*, const double*, const double*, double*,
+                                          const double*, double*, double*, const Scalars*, hipStream_t);
 
 }  // namespace otm

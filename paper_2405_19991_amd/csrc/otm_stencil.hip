@@ -381,17 +381,16 @@ __global__ void __launch_bounds__(TX* TY) k_march(int n, int tz, int ntx, int nt
 }
 
 template <typename T, int V>
-__global__ void __launch_bounds__(kBlock) k_update_vec(int64_t nn, T* __restrict__ x, T* __restrict__ r,
-                                                       const T* __restrict__ p, const T* __restrict__ q,
-                                                       const T* __restrict__ dinv, double* partials,
-                                                       unsigned* counter, Scalars* sc) {
+__device__ __forceinline__ void update_vec_body(int bid_, int nblk_, int slot_, int64_t nn, T* __restrict__ x,
+                                                T* __restrict__ r, const T* __restrict__ p, const T* __restrict__ q,
+                                                const T* __restrict__ dinv, double* partials, const Scalars* sc) {
     typedef T VT __attribute__((ext_vector_type(V)));
     const int64_t nv = nn / V;
     const int act[3] = {sc->active[0], sc->active[1], sc->active[2]};
     const T alpha[3] = {(T)sc->alpha[0], (T)sc->alpha[1], (T)sc->alpha[2]};
     double acc[6] = {0, 0, 0, 0, 0, 0};
     const VT* dv4 = reinterpret_cast<const VT*>(dinv);
-    for (int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x; t < nv; t += (int64_t)gridDim.x * kBlock) {
+    for (int64_t t = (int64_t)bid_ * kBlock + threadIdx.x; t < nv; t += (int64_t)nblk_ * kBlock) {
         const VT dv = dv4[t];
 #pragma unroll
         for (int l = 0; l < 3; ++l) {
@@ -414,7 +413,15 @@ __global__ void __launch_bounds__(kBlock) k_update_vec(int64_t nn, T* __restrict
             }
         }
     }
-    block_partials<6>(acc, partials);
+    block_partials_at<6>(acc, partials, slot_);
+}
+
+template <typename T, int V>
+__global__ void __launch_bounds__(kBlock) k_update_vec(int64_t nn, T* __restrict__ x, T* __restrict__ r,
+                                                       const T* __restrict__ p, const T* __restrict__ q,
+                                                       const T* __restrict__ dinv, double* partials,
+                                                       unsigned* counter, Scalars* sc) {
+    update_vec_body<T, V>(blockIdx.x, gridDim.x, blockIdx.x, nn, x, r, p, q, dinv, partials, sc);
 }
 
 // ---------------------------------------------------------------- launchers
@@ -542,5 +549,31 @@ template void launch_update_vec<double>(int, double*, double*, const double*, co
                                         const Workspace&, hipStream_t);
 template void launch_update_vec<float>(int, float*, float*, const float*, const float*, const float*,
                                        const Workspace&, hipStream_t);
+
+}  // namespace otm
+
+namespace otm {
+
+// Batched x/r update over the element-sweep work list (persistent blocks).
+__global__ void __launch_bounds__(kBlock) kb_update_vec(BatchTab t, double* __restrict__ x, double* __restrict__ r,
+                                                        const double* __restrict__ p, const double* __restrict__ q,
+                                                        const double* __restrict__ dinv, double* partials,
+                                                        const Scalars* sc) {
+    for (int item = blockIdx.x; item < t.eb_total; item += gridDim.x) {
+        const int d = t.eb_design[item];
+        const BatchDesc D = t.desc[d];
+        const int64_t o1 = D.off, o3 = 3 * D.off;
+        const int64_t nn = (int64_t)D.n * D.n * D.n;
+        __syncthreads();
+        update_vec_body<double, 2>(item - D.eb_start, D.eb_count, item, nn, x + o3, r + o3, p + o3, q + o3, dinv + o1,
+                                   partials, sc + d);
+    }
+}
+
+void launch_b_update_vec(const BatchTab& t, int grid, double* x, double* r, const double* p, const double* q,
+                         const double* dinv, double* partials, const Scalars* sc, hipStream_t s) {
+    hipLaunchKernelGGL(kb_update_vec, dim3(grid), dim3(kBlock), 0, s, t, x, r, p, q, dinv, partials, sc);
+    launch_b_finalize(t, FIN_UPDATE, 0, partials, const_cast<Scalars*>(sc), 0.5, s);
+}
 
 }  // namespace otm

@@ -69,3 +69,15 @@ def test_null_arguments(L):
     assert L.otm_create(None, None, None, None, None, None) == N.OTM_EINVAL
     assert L.otm_apply_device(2, 0, 0, None, None, None, None) == N.OTM_EINVAL
     assert L.otm_last_error(None) == b"null context"
+
+
+def test_batch_create_rejects_odd_or_bad_sizes(L):
+    from paper_2405_19991_amd import _native as N
+    arr = (N.Problem * 2)()
+    for p in arr:
+        p.n, p.k0, p.kmin, p.penal, p.filter_radius, p.vf = 8, 1.0, 1e-3, 3.0, 1.5, 0.3
+    arr[1].n = 9
+    h = ctypes.c_void_p()
+    assert L.otm_batch_create(arr, 2, None, None, None, None, ctypes.byref(h)) == N.OTM_EINVAL
+    assert L.otm_batch_create(arr, 0, None, None, None, None, ctypes.byref(h)) == N.OTM_EINVAL
+    assert L.otm_batch_last_error(None) == b"null batch"

@@ -1,0 +1,82 @@
+"""Batched designs (uneven n, one launch per phase, hipGraph-replayed PCG
+chunks) against single-design contexts and the CPU oracle."""
+import numpy as np
+import pytest
+
+import oracle as O
+import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def gpu():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU test run without a visible GPU")
+    torch.cuda.set_device(0)
+
+
+def problems(ns, seed):
+    g = synth.rng(seed)
+    out = []
+    for d, n in enumerate(ns):
+        vf = float(g.uniform(0.25, 0.4))
+        out.append(dict(n=n, target=synth.random_spd_target(g), vf=vf,
+                        rho=synth.smoothed_noise(n, vf - 0.15, vf + 0.15, seed + 17 * d)))
+    return out
+
+
+def test_batch_matches_single_designs():
+    from paper_2405_19991_amd import Batch, Homogenization
+    probs = problems([8, 16, 12, 16], 5)
+    steps = 3
+    with Batch(probs, tol=1e-10, autotune=False, tile_tz=4) as B:
+        for d, p in enumerate(probs):
+            B.set_density(d, p["rho"])
+        brec = [B.step() for _ in range(steps)]
+        brho = [B.get_field(d, "rho") for d in range(len(probs))]
+    for d, p in enumerate(probs):
+        with Homogenization(p["n"], (1.0, 1e-3), p["target"], vf=p["vf"], tol=1e-10) as h:
+            h.set_density(p["rho"])
+            for s in range(steps):
+                r = h.step()
+                assert brec[s][d]["g"] == pytest.approx(r["g"], rel=1e-8)
+                np.testing.assert_allclose(brec[s][d]["kappa"], r["kappa"], rtol=1e-9, atol=1e-12)
+                assert brec[s][d]["vstar"] == pytest.approx(r["vstar"], rel=1e-12)
+            np.testing.assert_allclose(brho[d], h.get_field("rho"), rtol=0, atol=1e-8)
+
+
+def test_batch_first_tensor_matches_oracle():
+    from paper_2405_19991_amd import Batch
+    probs = problems([10, 6], 9)
+    with Batch(probs, tol=1e-11) as B:
+        for d, p in enumerate(probs):
+            B.set_density(d, p["rho"])
+        recs = B.step()
+    for d, p in enumerate(probs):
+        ref = O.homogenize(p["rho"], O.Params(tol=1e-13))
+        rel = np.linalg.norm(np.array(recs[d]["kappa"]) - ref["kappa"]) / np.linalg.norm(ref["kappa"])
+        assert rel <= 1e-9
+
+
+def test_graph_replay_equals_eager():
+    """Replaying the captured PCG chunk, with eager host work and
+    synchronisation between replays, gives what eager launches give."""
+    from paper_2405_19991_amd import Batch
+    probs = problems([16, 8, 12], 13)
+    res = []
+    for use_graph in (True, False):
+        with Batch(probs, tol=1e-9, autotune=False, tile_tz=8) as B:
+            B.set_graph(use_graph)
+            for d, p in enumerate(probs):
+                B.set_density(d, p["rho"])
+            recs = [B.step() for _ in range(3)]
+            res.append((recs, [B.get_field(d, "rho") for d in range(len(probs))]))
+    (rg, pg), (re_, pe) = res
+    for s in range(3):
+        for d in range(len(probs)):
+            assert rg[s][d]["kappa"] == re_[s][d]["kappa"]
+            assert rg[s][d]["pcg_iters"] == re_[s][d]["pcg_iters"]
+    for a, b in zip(pg, pe):
+        np.testing.assert_array_equal(a, b)
