@@ -38,6 +38,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--oracle-cg-iters", type=int, default=1000)
     ap.add_argument("--apply-reps", type=int, default=50)
+    ap.add_argument("--no-batch", action="store_true", help="skip the 64-design batch leg")
+    ap.add_argument("--batch-steps", type=int, default=2)
     return ap.parse_args()
 
 
@@ -68,6 +70,33 @@ def cpu_baseline(w, cg_iters: int):
         "setup_s": t1 - t0,
         "cg_s": t2 - t1,
     }
+
+
+def batch_leg(steps: int, log):
+    """64 designs, n in {32, 48, 64} (seeded mix), FP64, tol 1e-6: one batched
+    design iteration per step (work-list launches, hipGraph PCG chunks)."""
+    import time as _t
+    import synth
+    from paper_2405_19991_amd import Batch
+    ws = synth.config4()
+    probs = [dict(n=w.n, target=w.target, vf=w.vf) for w in ws]
+    B = Batch(probs, tol=1e-6)
+    for d, w in enumerate(ws):
+        B.set_density(d, w.rho0)
+    B.step()  # warm-up (graph capture)
+    t0 = _t.perf_counter()
+    iters = 0
+    for _ in range(steps):
+        recs = B.step()
+        iters += sum(sum(r["pcg_iters"]) * ws[d].n ** 3 for d, r in enumerate(recs))
+        log(f"batch step: max pcg {max(max(r['pcg_iters']) for r in recs)}, mean g {sum(r['g'] for r in recs) / len(recs):.3e}")
+    t1 = _t.perf_counter()
+    info = B.info()
+    B.close()
+    return {"workload": "batch64_n32-64_fp64", "designs": len(ws), "cells": int(info["cells"]),
+            "s_per_oc_iter": (t1 - t0) / steps, "pcg_dof_updates_per_s": iters / (t1 - t0),
+            "tile_tx": int(info["tile_tx"]), "tile_tz": int(info["tile_tz"]), "work_items": int(info["work_items"]),
+            "steps": steps}
 
 
 def main():
@@ -170,6 +199,8 @@ def main():
     }
     h.close()
     log(f"apply kernel {us:.2f} us ({achieved:.0f} GB/s algorithmic)")
+    if not args.no_batch:
+        out["batch"] = batch_leg(args.batch_steps, log)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(w, args.oracle_cg_iters)

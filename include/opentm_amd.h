@@ -61,6 +61,9 @@ extern "C" {
 #define OTM_GUESS_ZERO 0     /* PCG starts from chi = 0 */
 #define OTM_GUESS_PREVIOUS 1 /* PCG starts from the previous design iteration's chi */
 #define OTM_GUESS_USER 2     /* PCG starts from the field set by otm_set_guess */
+#define OTM_GUESS_LEARNED 3  /* PCG starts from the attached network's prediction
+                                (otm_set_network); falls back to zero when that start
+                                has a larger residual than the zero start */
 
 #define OTM_OBJ_MSE 0 /* g = sum_c (kappa_c - target_c)^2, Sec. 4.4 (MSE objective) */
 
@@ -245,7 +248,8 @@ int otm_get_tile(const otm_ctx* ctx, int32_t tile4[4]);
 
 /* Per-phase timings of the last otm_step, milliseconds, HIP events on the
  * context stream: [filter+setup, solve, tensor, sensitivity, oc, total,
- * solve kernel (dominant) mean us, solve kernel launches]. */
+ * 1 if the last solve started from the network's prediction, PCG
+ * iterations launched in the last solve]. */
 int otm_get_timings(const otm_ctx* ctx, double t8[8]);
 
 /* ---- batches of designs (uneven n) -----------------------------------------
@@ -274,6 +278,37 @@ int otm_batch_set_graph(otm_batch* batch, int32_t use_graph);
  *  design 0, tuned operator-pass us, last solve ms, last step ms] */
 int otm_batch_info(const otm_batch* batch, double info8[8]);
 const char* otm_batch_last_error(const otm_batch* batch);
+
+/* ---- learned warm start ------------------------------------------------------
+ * A fully convolutional network (5 periodic 3x3x3 layers, channels
+ * 1-16-16-16-16-3, ReLU after the first four, output mean removed) maps the
+ * filtered density to the three fluctuation fields.  Convolutions run as bf16
+ * MFMA implicit GEMMs with float32 accumulation; parameters are float32 with
+ * Adam.  Grids must have n a multiple of 16, 16 <= n <= n_max.
+ * Parameter layout (compact, float32): for each layer, W[cout][cin][27] with
+ * tap 9(dz+1)+3(dy+1)+(dx+1) of the correlation y[v] = b + sum W x[v+d], then
+ * b[cout]. */
+typedef struct otm_nn otm_nn;
+int otm_nn_create(int32_t n_max, uint64_t seed, void* stream, otm_nn** out);
+void otm_nn_destroy(otm_nn* net);
+int32_t otm_nn_param_count(void);
+int otm_nn_get_params(otm_nn* net, float* host, int64_t count);
+int otm_nn_set_params(otm_nn* net, const float* host, int64_t count);
+/* accumulated gradients, same layout */
+int otm_nn_get_grads(otm_nn* net, float* host, int64_t count);
+/* device pointers: rhof n^3 float64 -> chi0 3 n^3 float64 (mean removed) */
+int otm_nn_forward(otm_nn* net, int32_t n, const void* rhof_dev, void* chi0_dev);
+/* forward + backward of the mean-squared error against chi (3 n^3 float64,
+ * device; mean removed inside), gradients added to the accumulator; loss_out
+ * (host, may be NULL) receives the loss. */
+int otm_nn_accumulate(otm_nn* net, int32_t n, const void* rhof_dev, const void* chi_dev, double* loss_out);
+/* Adam step with the accumulated gradients divided by batch; clears them. */
+int otm_nn_adam(otm_nn* net, double lr, int32_t batch);
+int otm_nn_zero_grads(otm_nn* net);
+const char* otm_nn_last_error(const otm_nn* net);
+/* Attach a network to a context for OTM_GUESS_LEARNED (NULL detaches).  The
+ * context does not own it. */
+int otm_set_network(otm_ctx* ctx, otm_nn* net);
 
 const char* otm_strerror(int status);
 const char* otm_last_error(const otm_ctx* ctx);

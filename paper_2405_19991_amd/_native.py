@@ -26,6 +26,7 @@ OTM_MIXED = 1
 OTM_GUESS_ZERO = 0
 OTM_GUESS_PREVIOUS = 1
 OTM_GUESS_USER = 2
+OTM_GUESS_LEARNED = 3
 OTM_OBJ_MSE = 0
 
 FIELDS = {"rho": 0, "rhof": 1, "k": 2, "b": 3, "diag": 4, "chi": 5, "sens_elem": 6, "sens": 7}
@@ -39,6 +40,9 @@ EXPORTED = [
     "otm_time_apply_device", "otm_get_tile", "otm_get_timings", "otm_strerror", "otm_last_error", "otm_version",
     "otm_batch_create", "otm_batch_destroy", "otm_batch_set_density", "otm_batch_get_field", "otm_batch_step",
     "otm_batch_set_graph", "otm_batch_info", "otm_batch_last_error",
+    "otm_nn_create", "otm_nn_destroy", "otm_nn_param_count", "otm_nn_get_params", "otm_nn_set_params",
+    "otm_nn_get_grads", "otm_nn_forward", "otm_nn_accumulate", "otm_nn_adam", "otm_nn_zero_grads",
+    "otm_nn_last_error", "otm_set_network",
 ]
 
 
@@ -140,6 +144,18 @@ def lib():
         "otm_batch_set_graph": ([vp, i32], ctypes.c_int),
         "otm_batch_info": ([vp, dp], ctypes.c_int),
         "otm_batch_last_error": ([vp], ctypes.c_char_p),
+        "otm_nn_create": ([i32, ctypes.c_uint64, vp, P(vp)], ctypes.c_int),
+        "otm_nn_destroy": ([vp], None),
+        "otm_nn_param_count": ([], i32),
+        "otm_nn_get_params": ([vp, P(ctypes.c_float), i64], ctypes.c_int),
+        "otm_nn_set_params": ([vp, P(ctypes.c_float), i64], ctypes.c_int),
+        "otm_nn_get_grads": ([vp, P(ctypes.c_float), i64], ctypes.c_int),
+        "otm_nn_forward": ([vp, i32, vp, vp], ctypes.c_int),
+        "otm_nn_accumulate": ([vp, i32, vp, vp, dp], ctypes.c_int),
+        "otm_nn_adam": ([vp, ctypes.c_double, i32], ctypes.c_int),
+        "otm_nn_zero_grads": ([vp], ctypes.c_int),
+        "otm_nn_last_error": ([vp], ctypes.c_char_p),
+        "otm_set_network": ([vp, vp], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)

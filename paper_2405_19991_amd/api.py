@@ -50,7 +50,8 @@ class Homogenization:
         p.objective = N.OTM_OBJ_MSE
         s, o, g = N.default_options()
         s.precision = {"fp64": N.OTM_FP64, "mixed": N.OTM_MIXED}[precision]
-        s.guess = {"zero": N.OTM_GUESS_ZERO, "previous": N.OTM_GUESS_PREVIOUS, "user": N.OTM_GUESS_USER}[guess]
+        s.guess = {"zero": N.OTM_GUESS_ZERO, "previous": N.OTM_GUESS_PREVIOUS, "user": N.OTM_GUESS_USER,
+                   "learned": N.OTM_GUESS_LEARNED}[guess]
         s.tol, s.max_iter, s.check_every, s.reliable_delta = float(tol), int(max_iter), int(check_every), float(reliable_delta)
         s.kernel_variant, s.tile_tz, s.tile_tx = int(kernel_variant), int(tile_tz), int(tile_tx)
         s.autotune = int(bool(autotune))
@@ -162,6 +163,11 @@ class Homogenization:
         y = np.empty_like(a)
         self._chk(self._L.otm_apply(self._h, {"fp64": N.OTM_FP64, "mixed": N.OTM_MIXED}[precision], _ptr(a), _ptr(y)))
         return y.reshape(3, self.n, self.n, self.n)
+
+    def set_network(self, net) -> None:
+        """Attach a Network for guess='learned' (None detaches)."""
+        self._net = net
+        self._chk(self._L.otm_set_network(self._h, net._h if net is not None else None))
 
     def tile(self) -> Dict[str, int]:
         t = (ctypes.c_int32 * 4)()
@@ -332,3 +338,90 @@ class Batch:
         self._chk(self._L.otm_batch_info(self._h, _ptr(a)))
         keys = ["designs", "cells", "work_items", "tile_tx", "tile_tz", "tuned_pass_us", "solve_ms", "step_ms"]
         return dict(zip(keys, a.tolist()))
+
+
+class Network:
+    """The learned warm start: periodic 3x3x3 CNN (1-16-16-16-16-3) on bf16 MFMA.
+    Training runs on the GPU through forward/backward kernels; Python only
+    sequences samples.  Device inputs are float64 torch CUDA tensors."""
+
+    def __init__(self, n_max: int = 128, seed: int = 0, stream=None):
+        L = N.lib()
+        h = ctypes.c_void_p()
+        st = ctypes.c_void_p(int(stream)) if stream is not None else None
+        N.check(L.otm_nn_create(int(n_max), int(seed), st, ctypes.byref(h)))
+        self._h, self._L, self.n_max = h, L, n_max
+        self.count = int(L.otm_nn_param_count())
+
+    def _chk(self, status):
+        if status != N.OTM_OK:
+            raise N.OTMError(status, self._L.otm_strerror(status).decode() + " (" +
+                             self._L.otm_nn_last_error(self._h).decode() + ")")
+
+    def close(self):
+        if getattr(self, "_h", None):
+            self._L.otm_nn_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def params(self) -> np.ndarray:
+        a = np.empty(self.count, dtype=np.float32)
+        self._chk(self._L.otm_nn_get_params(self._h, a.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), a.size))
+        return a
+
+    def set_params(self, a) -> None:
+        a = np.ascontiguousarray(a, dtype=np.float32)
+        self._chk(self._L.otm_nn_set_params(self._h, a.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), a.size))
+
+    def grads(self) -> np.ndarray:
+        a = np.empty(self.count, dtype=np.float32)
+        self._chk(self._L.otm_nn_get_grads(self._h, a.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), a.size))
+        return a
+
+    @staticmethod
+    def _n(t, k=1):
+        n = round((t.numel() // k) ** (1.0 / 3.0))
+        return n
+
+    def forward(self, rhof_dev, chi0_dev) -> None:
+        import torch
+        n = self._n(rhof_dev)
+        assert rhof_dev.dtype == torch.float64 and chi0_dev.dtype == torch.float64 and chi0_dev.numel() == 3 * n ** 3
+        self._chk(self._L.otm_nn_forward(self._h, n, ctypes.c_void_p(rhof_dev.data_ptr()),
+                                         ctypes.c_void_p(chi0_dev.data_ptr())))
+
+    def accumulate(self, rhof_dev, chi_dev) -> float:
+        n = self._n(rhof_dev)
+        loss = ctypes.c_double()
+        self._chk(self._L.otm_nn_accumulate(self._h, n, ctypes.c_void_p(rhof_dev.data_ptr()),
+                                            ctypes.c_void_p(chi_dev.data_ptr()), ctypes.byref(loss)))
+        return loss.value
+
+    def adam(self, lr: float, batch: int) -> None:
+        self._chk(self._L.otm_nn_adam(self._h, float(lr), int(batch)))
+
+    def zero_grads(self) -> None:
+        self._chk(self._L.otm_nn_zero_grads(self._h))
+
+    def save(self, path: str) -> None:
+        np.save(path, self.params())
+
+    def load(self, path: str) -> None:
+        self.set_params(np.load(path, allow_pickle=False))
+
+
+def compact_to_layers(a: np.ndarray, channels=(1, 16, 16, 16, 16, 3)):
+    """Split the compact parameter vector into [{'W': (cout, cin, 27), 'b': (cout,)}]."""
+    out, q = [], 0
+    for cin, cout in zip(channels[:-1], channels[1:]):
+        W = a[q:q + cout * cin * 27].reshape(cout, cin, 27)
+        q += cout * cin * 27
+        b = a[q:q + cout]
+        q += cout
+        out.append({"W": W.astype(np.float64), "b": b.astype(np.float64)})
+    return out

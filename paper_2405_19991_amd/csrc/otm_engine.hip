@@ -69,6 +69,8 @@ struct otm_ctx {
     TileShape tile2;  // pair kernel (even n)
     bool use_pair = false;
     double tune_us = 0.0;  // autotuned time of one direction+operator pass
+    otm_nn* net = nullptr;
+    int learned_used = 0;  // last solve started from the network's prediction
 
     bool have_density = false;
     bool prepared = false;
@@ -355,6 +357,29 @@ int homogenize(otm_ctx* c, double kappa6[6], otm_solve_stats* st_out) {
     bool x_zero = true;
     if (c->so.guess == OTM_GUESS_PREVIOUS && c->have_solution) x_zero = false;
     if (c->so.guess == OTM_GUESS_USER && c->have_user_guess) x_zero = false;
+    c->learned_used = 0;
+    if (c->so.guess == OTM_GUESS_LEARNED && c->net && c->n % 16 == 0) {
+        HIPCHK(c, hipStreamSynchronize(c->stream));
+        rc = otm_nn_forward(c->net, c->n, c->rhof, c->x);
+        if (rc) return fail(c, rc, "network forward failed");
+        // the network runs on its own stream
+        HIPCHK(c, hipDeviceSynchronize());
+        // keep the prediction only if it starts closer than zero for every load
+        const Workspace w0 = c->ws();
+        if ((rc = reset_solver_scalars(c))) return rc;
+        if (c->so.precision == OTM_MIXED)
+            launch_residual<float>(c->n, c->k, c->b, c->x, c->r32, c->p32[c->pbuf], c->dinv32, RES_START, 0, w0,
+                                   c->stream);
+        else
+            launch_residual<double>(c->n, c->k, c->b, c->x, c->r64, c->p64[c->pbuf], c->dinv, RES_START, 0, w0,
+                                    c->stream);
+        if ((rc = sync_scalars(c))) return rc;
+        bool better = true;
+        for (int l = 0; l < 3; ++l)
+            if (!(c->h_sc->rr_true[l] <= c->h_sc->bb[l])) better = false;
+        x_zero = !better;
+        c->learned_used = better ? 1 : 0;
+    }
     otm_solve_stats st{};
     (void)hipEventRecord(c->ev[2], c->stream);
     auto t_start = std::chrono::steady_clock::now();
@@ -374,6 +399,7 @@ int homogenize(otm_ctx* c, double kappa6[6], otm_solve_stats* st_out) {
     c->volume = c->h_sc->sum_rho / (double)c->nn;
     c->low_bound = c->h_sc->sum_rhofp / (double)c->nn;
     c->timings[0] = ev_ms(c, 0, 1);
+    c->timings[6] = (double)c->learned_used;
     c->timings[1] = ev_ms(c, 2, 3);
     c->timings[2] = ev_ms(c, 3, 4);
     if (!finite6(c->kappa)) return fail(c, OTM_ENONFINITE, "non-finite homogenized tensor");
@@ -649,7 +675,7 @@ int otm_create(const otm_problem* problem, const otm_solver_opts* solver, const 
     if (gov) c->go = *gov;
     if (!(c->so.tol > 0.0 && c->so.max_iter > 0 && c->so.check_every >= 1 && c->so.reliable_delta > 0.0 &&
           c->so.reliable_delta < 1.0 && (c->so.precision == OTM_FP64 || c->so.precision == OTM_MIXED) &&
-          c->so.guess >= OTM_GUESS_ZERO && c->so.guess <= OTM_GUESS_USER &&
+          c->so.guess >= OTM_GUESS_ZERO && c->so.guess <= OTM_GUESS_LEARNED &&
           c->so.kernel_variant >= 0 && c->so.kernel_variant <= 3 && c->so.tile_tz >= 0 &&
           (c->so.tile_tx == 0 || c->so.tile_tx == 16 || c->so.tile_tx == 32 || c->so.tile_tx == 64))) {
         delete c;
@@ -1087,6 +1113,12 @@ int otm_time_apply_device(int32_t n, int32_t precision, int32_t variant, int32_t
     *us = 1000.0 * (double)ms / (double)reps;
     (void)hipEventDestroy(a);
     (void)hipEventDestroy(b);
+    return OTM_OK;
+}
+
+int otm_set_network(otm_ctx* c, otm_nn* net) {
+    if (!c) return OTM_EINVAL;
+    c->net = net;
     return OTM_OK;
 }
 

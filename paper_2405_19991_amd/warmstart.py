@@ -1,0 +1,164 @@
+"""Training and evaluation of the learned PCG warm start.
+
+Pairs (filtered density, converged fluctuation fields) are produced by the
+method itself: seeded design runs of the GPU optimizer dump one pair per
+design iteration.  The network is trained on the GPU with the library's
+forward/backward kernels and Adam; this module only sequences samples.
+
+    python -m paper_2405_19991_amd.warmstart train --out weights.npy
+    python -m paper_2405_19991_amd.warmstart eval --weights weights.npy
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+from typing import Dict, List, Tuple
+
+import numpy as np
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+DEFAULT_WEIGHTS = os.path.join(HERE, "weights", "warmstart.npy")
+
+
+def _log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def design_runs() -> List[Tuple[str, int, object, object, float, int]]:
+    """(name, n, rho0, target, vf, iterations) for the training designs:
+    isotropic 16^3 cells, random-target 32^3 cells, orthotropic 64^3 cells and
+    anisotropic 128^3 cells (the evaluation seed 303 is held out)."""
+    sys.path.insert(0, os.path.dirname(HERE))
+    import synth
+    runs = []
+    for s in range(12):
+        runs.append((f"iso16_{s}", 16, synth.uniform_noise(16, 0.3, 0.05, 1000 + s), synth.TARGET_ISO, 0.3, 30))
+    g = synth.rng(2000)
+    for s in range(8):
+        vf = float(g.uniform(0.2, 0.4))
+        runs.append((f"rand32_{s}", 32, synth.smoothed_noise(32, vf - 0.15, vf + 0.15, 2100 + s),
+                     tuple(synth.random_spd_target(g)), vf, 25))
+    for s in range(4):
+        runs.append((f"ortho64_{s}", 64, synth.smoothed_noise(64, 0.2, 0.5, 201 + s), synth.TARGET_ORTHO, 0.35, 30))
+    for s in range(2):
+        runs.append((f"aniso128_{s}", 128, synth.smoothed_noise(128, 0.15, 0.45, 301 + s), synth.TARGET_ANISO, 0.3,
+                     15))
+    return runs
+
+
+def generate(runs=None, tol: float = 1e-6):
+    """Run the optimizer and keep (rho~, chi) of every design iteration on the GPU."""
+    import torch
+    from .api import Homogenization
+    runs = runs or design_runs()
+    data = []
+    for name, n, rho0, target, vf, iters in runs:
+        with Homogenization(n, (1.0, 1e-3), target, vf=vf, tol=tol, precision="mixed" if n >= 64 else "fp64",
+                            guess="previous") as h:
+            h.set_density(rho0)
+            for _ in range(iters):
+                h.step()
+                # the fields of the iteration just solved: rho~ of the density it used and chi
+                rf = torch.from_numpy(h.get_field("rhof").reshape(-1)).cuda()
+                chi = torch.from_numpy(h.get_field("chi").reshape(-1)).cuda()
+                data.append((n, rf, chi))
+        _log(f"data: {name} done, {len(data)} pairs")
+    return data
+
+
+def train(data, epochs: int = 12, batch: int = 8, lr: float = 2e-3, seed: int = 0, n_max: int = 128):
+    from .api import Network
+    net = Network(n_max=n_max, seed=seed)
+    g = np.random.Generator(np.random.PCG64(seed))
+    history = []
+    for ep in range(epochs):
+        order = g.permutation(len(data))
+        tot, cnt = 0.0, 0
+        net.zero_grads()
+        for q, idx in enumerate(order):
+            n, rf, chi = data[idx]
+            tot += net.accumulate(rf, chi)
+            cnt += 1
+            if cnt % batch == 0 or q == len(order) - 1:
+                net.adam(lr * (0.5 ** (ep // 4)), min(batch, cnt % batch or batch))
+        history.append(tot / len(order))
+        _log(f"epoch {ep}: mean loss {history[-1]:.4e}")
+    return net, history
+
+
+def time_to_tol(n: int, rho, target, vf: float, precision: str, guess: str, net=None, tol: float = 1e-6,
+                previous_steps: int = 0) -> Dict[str, float]:
+    """PCG iterations and solve time of one homogenization from the given start.
+    For guess='previous' the cell first runs previous_steps design iterations."""
+    import torch
+    from .api import Homogenization
+    with Homogenization(n, (1.0, 1e-3), target, vf=vf, tol=tol, precision=precision, guess=guess) as h:
+        if net is not None:
+            h.set_network(net)
+        h.set_density(rho)
+        for _ in range(previous_steps):
+            h.step()
+        h.homogenize()  # warm-up of this exact state (kernels, graphs)
+        torch.cuda.synchronize()
+        if guess == "previous":
+            pass
+        t0 = time.perf_counter()
+        kappa, st = h.homogenize()
+        t1 = time.perf_counter()
+        used = h.timings()[6]
+    return {"pcg_iters": int(sum(st["iterations"])), "max_load_iters": int(max(st["iterations"])),
+            "ms": 1000.0 * (t1 - t0), "converged": bool(st["converged"]), "learned_used": bool(used),
+            "kappa": [float(v) for v in kappa]}
+
+
+def evaluate(net, n: int = 128, seed: int = 303) -> Dict[str, Dict[str, float]]:
+    """Time to 1e-6 on a held-out 128^3 anisotropic cell (first design iteration)."""
+    sys.path.insert(0, os.path.dirname(HERE))
+    import synth
+    rho = synth.smoothed_noise(n, 0.15, 0.45, seed)
+    tgt = synth.TARGET_ANISO
+    out = {
+        "zero_fp64": time_to_tol(n, rho, tgt, 0.3, "fp64", "zero"),
+        "zero_mixed": time_to_tol(n, rho, tgt, 0.3, "mixed", "zero"),
+        "learned_mixed": time_to_tol(n, rho, tgt, 0.3, "mixed", "learned", net),
+        "learned_fp64": time_to_tol(n, rho, tgt, 0.3, "fp64", "learned", net),
+    }
+    return out
+
+
+def main(argv=None):
+    ap = argparse.ArgumentParser()
+    ap.add_argument("cmd", choices=["train", "eval"])
+    ap.add_argument("--out", default=DEFAULT_WEIGHTS)
+    ap.add_argument("--weights", default=DEFAULT_WEIGHTS)
+    ap.add_argument("--epochs", type=int, default=12)
+    ap.add_argument("--summary", default=None)
+    a = ap.parse_args(argv)
+    import torch
+    torch.cuda.set_device(0)
+    from .api import Network
+    if a.cmd == "train":
+        t0 = time.perf_counter()
+        data = generate()
+        t1 = time.perf_counter()
+        net, hist = train(data, epochs=a.epochs)
+        t2 = time.perf_counter()
+        os.makedirs(os.path.dirname(os.path.abspath(a.out)), exist_ok=True)
+        net.save(a.out)
+        ev = evaluate(net)
+        summary = {"pairs": len(data), "data_s": t1 - t0, "train_s": t2 - t1, "loss_history": hist, "eval_128": ev}
+        print(json.dumps(summary), flush=True)
+        if a.summary:
+            with open(a.summary, "w") as f:
+                json.dump(summary, f, indent=1)
+    else:
+        net = Network(n_max=128)
+        net.load(a.weights)
+        print(json.dumps(evaluate(net)), flush=True)
+
+
+if __name__ == "__main__":
+    main()
