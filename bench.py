@@ -40,6 +40,12 @@ def parse():
     ap.add_argument("--apply-reps", type=int, default=50)
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-design batch leg")
     ap.add_argument("--batch-steps", type=int, default=2)
+    ap.add_argument("--apply-only", action="store_true",
+                    help="run only the stand-alone operator (fixed tile) and a device copy of known size, for "
+                         "hardware-counter profiling; prints one JSON line with their HIP-event timings")
+    ap.add_argument("--apply-tx", type=int, default=64)
+    ap.add_argument("--apply-tz", type=int, default=8)
+    ap.add_argument("--learned", default=None, help="network weights (.npy) for the learned-start leg")
     return ap.parse_args()
 
 
@@ -99,8 +105,35 @@ def batch_leg(steps: int, log):
             "steps": steps}
 
 
+def apply_only(args):
+    """Operator and copy launches for counter runs (rocprofv3 --pmc)."""
+    import torch
+    from paper_2405_19991_amd import time_apply_device
+    torch.cuda.set_device(0)
+    n = args.n
+    nn = n ** 3
+    dt = torch.float32 if args.precision == "mixed" else torch.float64
+    k = (torch.rand(nn, dtype=torch.float64, device="cuda") * 0.999 + 0.001).to(dt)
+    x = torch.randn(3 * nn, dtype=dt, device="cuda")
+    y = torch.empty_like(x)
+    v = 0 if n % 2 == 0 else 3
+    us = time_apply_device(k, x, y, args.precision, reps=args.apply_reps, variant=v, tile_tx=args.apply_tx,
+                           tile_tz=args.apply_tz)
+    src = torch.empty(64 * 1024 * 1024, dtype=torch.uint8, device="cuda")  # 64 MiB copy
+    dst = torch.empty_like(src)
+    for _ in range(args.apply_reps):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    bpn = 28 if args.precision == "mixed" else 56
+    print(json.dumps({"apply_us": us, "alg_bytes": bpn * nn, "copy_bytes": src.numel(), "launches": args.apply_reps + 1,
+                      "tile": [v, args.apply_tx, args.apply_tz]}), flush=True)
+
+
 def main():
     args = parse()
+    if args.apply_only:
+        apply_only(args)
+        return
     if args.gpus != 1:
         print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
                                    "(multi-GPU sharding is described in DESIGN.md, not implemented)"}))

@@ -98,9 +98,14 @@ typedef struct {
     double reliable_delta; /* OTM_MIXED: refresh the float64 residual when the float32
                               recursive residual has dropped by this factor */
     int32_t kernel_variant; /* 0: streaming z-march kernels (default; two nodes per
-                               thread when n is even); 1: direct-gather kernels;
-                               2: LDS-ring tiled kernels; 3: z-march with one node
-                               per thread (same arithmetic, kept as cross-checks) */
+                               thread when n is even; with autotune on and automatic
+                               tiles the fused iteration of 4 is chosen when it is
+                               faster); 1: direct-gather kernels; 2: LDS-ring tiled
+                               kernels; 3: z-march with one node per thread (same
+                               arithmetic, kept as cross-checks); 4: fused PCG
+                               iteration, one z-march pass and one reduction per
+                               iteration (even n only, else OTM_EINVAL).  All give
+                               Jacobi-PCG iterates that agree in exact arithmetic. */
     int32_t tile_tz;        /* planes per z-march of the operator kernel; 0 = automatic */
     int32_t tile_tx;        /* tile width in x in nodes: 16, 32 or 64 (32 or 64 for the
                                two-node kernel); 0 = automatic */

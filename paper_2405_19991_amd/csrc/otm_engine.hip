@@ -51,6 +51,8 @@ struct otm_ctx {
     double* r64 = nullptr;
     double* p64[2] = {nullptr, nullptr};
     double* q64 = nullptr;
+    double* r64b = nullptr;  // second r, q of the fused iteration (ping-pong)
+    double* q64b = nullptr;
     // mixed-precision Krylov vectors
     float* k32 = nullptr;
     float* dinv32 = nullptr;
@@ -58,6 +60,8 @@ struct otm_ctx {
     float* r32 = nullptr;
     float* p32[2] = {nullptr, nullptr};
     float* q32 = nullptr;
+    float* r32b = nullptr;
+    float* q32b = nullptr;
 
     double* partials = nullptr;
     unsigned* counter = nullptr;
@@ -68,7 +72,8 @@ struct otm_ctx {
     TileShape tile;   // one-node-per-thread kernels (ring, march)
     TileShape tile2;  // pair kernel (even n)
     bool use_pair = false;
-    double tune_us = 0.0;  // autotuned time of one direction+operator pass
+    bool use_fused = false;  // one pass per PCG iteration (otm_fused.hip)
+    double tune_us = 0.0;  // autotuned time of one PCG iteration's passes
     otm_nn* net = nullptr;
     int learned_used = 0;  // last solve started from the network's prediction
 
@@ -227,7 +232,80 @@ int reset_solver_scalars(otm_ctx* c) {
     return OTM_OK;
 }
 
+// One pass and one reduction per iteration (otm_fused.hip).  r[cur], q[cur],
+// p[cur] hold what the next pass reads; x is the float64 solution (FP64) or the
+// float32 increment folded into it at each residual refresh (mixed).
+template <typename T>
+struct FusedBufs {
+    T* r[2];
+    T* q[2];
+    T* p[2];
+    T* x;
+    const T* dinv;
+    const T* k;
+};
+
+template <typename T>
+int solve_fused(otm_ctx* c, bool x_zero, bool mixed, const FusedBufs<T>& B, otm_solve_stats* st) {
+    const Workspace w = c->ws();
+    const int n = c->n;
+    int rc;
+    if ((rc = reset_solver_scalars(c))) return rc;
+    if (x_zero) HIPCHK(c, hipMemsetAsync(c->x, 0, (size_t)3 * c->nn * sizeof(double), c->stream));
+    if (mixed) HIPCHK(c, hipMemsetAsync(c->x32, 0, (size_t)3 * c->nn * sizeof(float), c->stream));
+    int cur = 0;
+    launch_residual_f<T>(n, c->k, c->b, c->x, B.r[cur], nullptr, B.dinv, true, x_zero ? 1 : 0, w, c->stream);
+    if ((rc = check_launch(c, "residual"))) return rc;
+    if ((rc = sync_scalars(c))) return rc;
+    double rr_ref[3] = {c->h_sc->rr_true[0], c->h_sc->rr_true[1], c->h_sc->rr_true[2]};
+    const double d2 = c->so.reliable_delta * c->so.reliable_delta;
+    int refreshes = 0, launches = 0;
+    while (!all_inactive(c->h_sc) && max_iters(c->h_sc) < c->so.max_iter) {
+        const bool all = all_active(c->h_sc);
+        for (int it = 0; it < c->so.check_every; ++it) {
+            const int nx = cur ^ 1;
+            launch_fused<T>(n, c->tile2, all, B.r[cur], B.q[cur], B.p[cur], B.r[nx], B.q[nx], B.p[nx], B.x, B.dinv,
+                            B.k, w, c->stream);
+            cur = nx;
+            ++launches;
+        }
+        if ((rc = check_launch(c, "pcg fused"))) return rc;
+        if ((rc = sync_scalars(c))) return rc;
+        bool refresh = all_inactive(c->h_sc);
+        if (mixed)
+            for (int l = 0; l < 3; ++l)
+                if (c->h_sc->active[l] && c->h_sc->rr[l] < d2 * rr_ref[l]) refresh = true;
+        if (refresh) {
+            // float64 residual of the current solution; loads whose true
+            // residual misses the tolerance go on (or restart)
+            if (mixed) launch_accumulate(n, c->x, c->x32, c->stream);
+            launch_residual_f<T>(n, c->k, c->b, c->x, B.r[cur], B.q[cur], B.dinv, false, 0, w, c->stream);
+            if ((rc = check_launch(c, "refresh"))) return rc;
+            if ((rc = sync_scalars(c))) return rc;
+            for (int l = 0; l < 3; ++l) rr_ref[l] = c->h_sc->rr_true[l];
+            if (mixed) ++refreshes;
+        }
+    }
+    if (mixed) launch_accumulate(n, c->x, c->x32, c->stream);
+    launch_sum3(n, c->x, 0, w, c->stream);
+    launch_sub_mean3(n, c->x, 0, w, c->stream);
+    if ((rc = check_launch(c, "project"))) return rc;
+    if ((rc = sync_scalars(c))) return rc;
+    for (int l = 0; l < 3; ++l) {
+        st->iterations[l] = c->h_sc->iters[l];
+        st->rel_residual[l] = c->h_sc->bb[l] > 0.0 ? std::sqrt(c->h_sc->rr_true[l] / c->h_sc->bb[l]) : 0.0;
+    }
+    st->converged = all_inactive(c->h_sc) ? 1 : 0;
+    st->refreshes = refreshes;
+    c->timings[7] = (double)launches;
+    return OTM_OK;
+}
+
 int solve_fp64(otm_ctx* c, bool x_zero, otm_solve_stats* st) {
+    if (c->use_fused) {
+        const FusedBufs<double> B{{c->r64, c->r64b}, {c->q64, c->q64b}, {c->p64[0], c->p64[1]}, c->x, c->dinv, c->k};
+        return solve_fused<double>(c, x_zero, false, B, st);
+    }
     const Workspace w = c->ws();
     const int n = c->n;
     int rc;
@@ -284,6 +362,11 @@ int solve_fp64(otm_ctx* c, bool x_zero, otm_solve_stats* st) {
 }
 
 int solve_mixed(otm_ctx* c, bool x_zero, otm_solve_stats* st) {
+    if (c->use_fused) {
+        const FusedBufs<float> B{{c->r32, c->r32b}, {c->q32, c->q32b}, {c->p32[0], c->p32[1]}, c->x32, c->dinv32,
+                                 c->k32};
+        return solve_fused<float>(c, x_zero, true, B, st);
+    }
     const Workspace w = c->ws();
     const int n = c->n;
     int rc;
@@ -494,7 +577,7 @@ void objective(const double* kappa, const double* target, double* g, double* w6)
 int free_all(otm_ctx* c) {
     void* bufs[] = {c->rho, c->rhof, c->k, c->dinv, c->b, c->x, c->st, c->sens, c->ocq, c->r64, c->p64[0], c->p64[1],
                     c->q64, c->k32, c->dinv32, c->x32, c->r32, c->p32[0], c->p32[1], c->q32, c->partials, c->counter,
-                    c->sc};
+                    c->sc, c->r64b, c->q64b, c->r32b, c->q32b};
     for (void* p : bufs)
         if (p) (void)hipFree(p);
     if (c->h_sc) (void)hipHostFree(c->h_sc);
@@ -505,26 +588,21 @@ int free_all(otm_ctx* c) {
 }
 
 // ------------------------------------------------------------------ autotune
-// Picks the operator kernel (pair or one-node z-march), tile width and march
-// length for this n and precision by timing the PCG direction+operator pass
-// on the context's own buffers.  Results are cached per process.
+// Picks the PCG iteration scheme and operator kernel for this n and precision
+// by timing them on the context's own buffers: the fused single pass (even n),
+// or a direction+operator pass (two-node or one-node z-march) followed by the
+// vector update, over tile widths and march lengths.  Results are cached per
+// process.
 struct TuneChoice {
-    bool pair;
+    bool pair, fused;
     int tx, tz;
-    double us;
+    double us;  // one PCG iteration (passes and finalizes)
 };
 std::mutex g_tune_mu;
 std::map<std::tuple<int, int>, TuneChoice> g_tune_cache;
 
-template <typename T>
-double time_dir_pass(otm_ctx* c, bool pair, const TileShape& t, T* r, T* dinv, T* p0, T* p1, T* k, T* q, int reps) {
-    const Workspace w = c->ws();
-    auto run = [&]() {
-        if (pair)
-            launch_dir_march2<T>(c->n, t, true, r, dinv, p0, p1, k, q, w, c->stream);
-        else
-            launch_dir_march<T>(c->n, t, r, dinv, p0, p1, k, q, w, c->stream);
-    };
+template <typename F>
+double time_us(otm_ctx* c, F run, int reps) {
     run();
     run();
     (void)hipEventRecord(c->ev[6], c->stream);
@@ -537,6 +615,97 @@ double time_dir_pass(otm_ctx* c, bool pair, const TileShape& t, T* r, T* dinv, T
     return 1000.0 * ev_ms(c, 6, 7) / reps;
 }
 
+void apply_choice(otm_ctx* c, const TuneChoice& ch) {
+    c->use_pair = ch.pair;
+    c->use_fused = ch.fused;
+    if (ch.pair)
+        c->tile2 = choose_tile2(c->n, c->max_blocks, ch.tz, ch.tx);
+    else
+        c->tile = choose_tile(c->n, c->max_blocks, ch.tz, ch.tx);
+}
+
+// Scalar state for timing: every load active with a non-zero step and
+// direction weight, so each candidate does its full work.
+int upload_timing_scalars(otm_ctx* c) {
+    const size_t head = offsetof(Scalars, sum_rho);
+    std::memset(c->h_sc, 0, head);
+    for (int l = 0; l < 3; ++l) {
+        c->h_sc->active[l] = 1;
+        c->h_sc->alpha[l] = 0.5;
+        c->h_sc->beta[l] = 0.5;
+        c->h_sc->rz[l] = 1.0;
+    }
+    HIPCHK(c, hipMemcpyAsync(c->sc, c->h_sc, head, hipMemcpyHostToDevice, c->stream));
+    return OTM_OK;
+}
+
+template <typename T>
+int tune_precision(otm_ctx* c, T* r, T* rb, T* q, T* qb, T* p0, T* p1, T* x, T* dinv, T* k, TuneChoice& best) {
+    const Workspace w = c->ws();
+    const int n = c->n;
+    const int reps = c->nn >= (1 << 20) ? 6 : 12;
+    const int tzs[] = {4, 8, 16, 32};
+    int rc;
+    best = TuneChoice{false, false, 32, 8, 1e30};
+    // fused candidates first (finalize timed apart: it would retire the loads)
+    double fin_us = 0.0, upd_us = 0.0;
+    if ((rc = upload_timing_scalars(c))) return rc;
+    if (rb && qb) {
+        for (int tx : {32, 64})
+            for (int tz : tzs) {
+                if (tz > n) continue;
+                const TileShape t = choose_tile2(n, c->max_blocks, tz, tx);
+                if (t.tz != tz || t.blocks > c->max_blocks) continue;
+                int par = 0;
+                const double us = time_us(
+                    c,
+                    [&]() {
+                        T* ri = par ? rb : r;
+                        T* ro = par ? r : rb;
+                        T* qi = par ? qb : q;
+                        T* qo = par ? q : qb;
+                        T* pi = par ? p1 : p0;
+                        T* po = par ? p0 : p1;
+                        launch_fused<T>(n, t, true, ri, qi, pi, ro, qo, po, x, dinv, k, w, c->stream, false);
+                        par ^= 1;
+                    },
+                    reps);
+                if (us < best.us) best = TuneChoice{true, true, tx, tz, us};
+            }
+        upd_us = time_us(c, [&]() { launch_update_vec<T>(n, x, r, p0, q, dinv, w, c->stream, false); }, reps);
+        fin_us = time_us(c, [&]() { launch_finalize(FIN_F_PASS, 512, w, c->stream); }, reps);
+        best.us += fin_us;
+        if ((rc = upload_timing_scalars(c))) return rc;
+    }
+    // direction+operator pass (its finalize included) + update + finalize
+    std::vector<std::tuple<bool, int, int>> cands;
+    if (n % 2 == 0)
+        for (int tx : {32, 64})
+            for (int tz : tzs)
+                if (tz <= n) cands.emplace_back(true, tx, tz);
+    for (int tx : {16, 32, 64})
+        for (int tz : tzs)
+            if (tz <= n) cands.emplace_back(false, tx, tz);
+    for (auto& cd : cands) {
+        const bool pair = std::get<0>(cd);
+        const int tx = std::get<1>(cd), tz = std::get<2>(cd);
+        const TileShape t = pair ? choose_tile2(n, c->max_blocks, tz, tx) : choose_tile(n, c->max_blocks, tz, tx);
+        if (t.tz != tz || t.blocks > c->max_blocks) continue;
+        const double us = time_us(
+                              c,
+                              [&]() {
+                                  if (pair)
+                                      launch_dir_march2<T>(n, t, true, r, dinv, p0, p1, k, q, w, c->stream);
+                                  else
+                                      launch_dir_march<T>(n, t, r, dinv, p0, p1, k, q, w, c->stream);
+                              },
+                              reps) +
+                          upd_us + fin_us;
+        if (us < best.us) best = TuneChoice{pair, false, tx, tz, us};
+    }
+    return check_launch(c, "autotune");
+}
+
 int autotune(otm_ctx* c) {
     const int prec = c->so.precision;
     const auto key = std::make_tuple(c->n, prec);
@@ -544,62 +713,37 @@ int autotune(otm_ctx* c) {
         std::lock_guard<std::mutex> g(g_tune_mu);
         auto it = g_tune_cache.find(key);
         if (it != g_tune_cache.end()) {
-            const TuneChoice& ch = it->second;
-            c->use_pair = ch.pair;
-            if (ch.pair)
-                c->tile2 = choose_tile2(c->n, c->max_blocks, ch.tz, ch.tx);
-            else
-                c->tile = choose_tile(c->n, c->max_blocks, ch.tz, ch.tx);
+            apply_choice(c, it->second);
             return OTM_OK;
         }
     }
-    // a valid state for timing: all loads active, beta != 0, zeroed vectors
-    const size_t head = offsetof(Scalars, sum_rho);
-    std::memset(c->h_sc, 0, head);
-    for (int l = 0; l < 3; ++l) {
-        c->h_sc->active[l] = 1;
-        c->h_sc->beta[l] = 0.5;
-        c->h_sc->rz[l] = 1.0;
-    }
-    HIPCHK(c, hipMemcpyAsync(c->sc, c->h_sc, head, hipMemcpyHostToDevice, c->stream));
-    const size_t es = prec == OTM_MIXED ? sizeof(float) : sizeof(double);
-    void* bufs[] = {prec == OTM_MIXED ? (void*)c->r32 : (void*)c->r64, prec == OTM_MIXED ? (void*)c->q32 : (void*)c->q64};
-    for (void* b : bufs) HIPCHK(c, hipMemsetAsync(b, 0, 3 * (size_t)c->nn * es, c->stream));
-    HIPCHK(c, hipMemsetAsync(prec == OTM_MIXED ? (void*)c->k32 : (void*)c->k, 0, (size_t)c->nn * es, c->stream));
-    HIPCHK(c, hipMemsetAsync(prec == OTM_MIXED ? (void*)c->dinv32 : (void*)c->dinv, 0, (size_t)c->nn * es, c->stream));
-    std::vector<std::tuple<bool, int, int>> cands;
-    const int tzs[] = {4, 8, 16, 32};
-    if (c->n % 2 == 0)
-        for (int tx : {32, 64})
-            for (int tz : tzs)
-                if (tz <= c->n) cands.emplace_back(true, tx, tz);
-    for (int tx : {16, 32, 64})
-        for (int tz : tzs)
-            if (tz <= c->n) cands.emplace_back(false, tx, tz);
-    const int reps = c->nn >= (1 << 20) ? 6 : 12;
-    TuneChoice best{false, 32, 8, 1e30};
-    for (auto& cd : cands) {
-        const bool pair = std::get<0>(cd);
-        const int tx = std::get<1>(cd), tz = std::get<2>(cd);
-        const TileShape t = pair ? choose_tile2(c->n, c->max_blocks, tz, tx) : choose_tile(c->n, c->max_blocks, tz, tx);
-        if (t.tz != tz || t.blocks > c->max_blocks) continue;
-        double us;
-        if (prec == OTM_MIXED)
-            us = time_dir_pass<float>(c, pair, t, c->r32, c->dinv32, c->p32[0], c->p32[1], c->k32, c->q32, reps);
-        else
-            us = time_dir_pass<double>(c, pair, t, c->r64, c->dinv, c->p64[0], c->p64[1], c->k, c->q64, reps);
-        if (us < best.us) best = TuneChoice{pair, tx, tz, us};
-    }
-    int rc = check_launch(c, "autotune");
-    if (rc) return rc;
-    HIPCHK(c, hipMemsetAsync(prec == OTM_MIXED ? (void*)c->p32[0] : (void*)c->p64[0], 0, 3 * (size_t)c->nn * es, c->stream));
-    HIPCHK(c, hipMemsetAsync(prec == OTM_MIXED ? (void*)c->p32[1] : (void*)c->p64[1], 0, 3 * (size_t)c->nn * es, c->stream));
-    HIPCHK(c, hipStreamSynchronize(c->stream));
-    c->use_pair = best.pair;
-    if (best.pair)
-        c->tile2 = choose_tile2(c->n, c->max_blocks, best.tz, best.tx);
+    // zeroed vectors and coefficients: every candidate computes on zeros
+    const bool mixed = prec == OTM_MIXED;
+    const size_t es = mixed ? sizeof(float) : sizeof(double);
+    const size_t v3 = 3 * (size_t)c->nn * es, v1 = (size_t)c->nn * es;
+    void* vecs[] = {mixed ? (void*)c->r32 : (void*)c->r64, mixed ? (void*)c->q32 : (void*)c->q64,
+                    mixed ? (void*)c->r32b : (void*)c->r64b, mixed ? (void*)c->q32b : (void*)c->q64b,
+                    mixed ? (void*)c->p32[0] : (void*)c->p64[0], mixed ? (void*)c->p32[1] : (void*)c->p64[1],
+                    mixed ? (void*)c->x32 : nullptr};
+    for (void* v : vecs)
+        if (v) HIPCHK(c, hipMemsetAsync(v, 0, v3, c->stream));
+    HIPCHK(c, hipMemsetAsync(mixed ? (void*)c->k32 : (void*)c->k, 0, v1, c->stream));
+    HIPCHK(c, hipMemsetAsync(mixed ? (void*)c->dinv32 : (void*)c->dinv, 0, v1, c->stream));
+    // FP64 timing updates a scratch x: the solution buffer is restored below
+    TuneChoice best;
+    int rc;
+    if (mixed)
+        rc = tune_precision<float>(c, c->r32, c->r32b, c->q32, c->q32b, c->p32[0], c->p32[1], c->x32, c->dinv32,
+                                   c->k32, best);
     else
-        c->tile = choose_tile(c->n, c->max_blocks, best.tz, best.tx);
+        rc = tune_precision<double>(c, c->r64, c->r64b, c->q64, c->q64b, c->p64[0], c->p64[1], c->x, c->dinv, c->k,
+                                    best);
+    if (rc) return rc;
+    for (void* v : vecs)
+        if (v) HIPCHK(c, hipMemsetAsync(v, 0, v3, c->stream));
+    HIPCHK(c, hipMemsetAsync(c->x, 0, 3 * (size_t)c->nn * sizeof(double), c->stream));
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    apply_choice(c, best);
     c->tune_us = best.us;
     std::lock_guard<std::mutex> g(g_tune_mu);
     g_tune_cache[key] = best;
@@ -676,7 +820,7 @@ int otm_create(const otm_problem* problem, const otm_solver_opts* solver, const 
     if (!(c->so.tol > 0.0 && c->so.max_iter > 0 && c->so.check_every >= 1 && c->so.reliable_delta > 0.0 &&
           c->so.reliable_delta < 1.0 && (c->so.precision == OTM_FP64 || c->so.precision == OTM_MIXED) &&
           c->so.guess >= OTM_GUESS_ZERO && c->so.guess <= OTM_GUESS_LEARNED &&
-          c->so.kernel_variant >= 0 && c->so.kernel_variant <= 3 && c->so.tile_tz >= 0 &&
+          c->so.kernel_variant >= 0 && c->so.kernel_variant <= 4 && c->so.tile_tz >= 0 &&
           (c->so.tile_tx == 0 || c->so.tile_tx == 16 || c->so.tile_tx == 32 || c->so.tile_tx == 64))) {
         delete c;
         return OTM_EINVAL;
@@ -711,7 +855,16 @@ int otm_create(const otm_problem* problem, const otm_solver_opts* solver, const 
     c->max_blocks = 4096;
     c->tile = choose_tile(c->n, c->max_blocks, c->so.tile_tz, c->so.tile_tx);
     c->tile2 = choose_tile2(c->n, c->max_blocks, c->so.tile_tz, c->so.tile_tx);
-    c->use_pair = (c->so.kernel_variant == 0) && (c->n % 2 == 0);
+    c->use_pair = (c->so.kernel_variant == 0 || c->so.kernel_variant == 4) && (c->n % 2 == 0);
+    c->use_fused = (c->so.kernel_variant == 4);
+    if (c->use_fused && c->n % 2 != 0) {
+        if (c->own_stream) (void)hipStreamDestroy(c->stream);
+        delete c;
+        return OTM_EINVAL;
+    }
+    // the fused iteration needs second r, q buffers (automatic choice or forced)
+    const bool fused_bufs = c->use_pair && (c->so.kernel_variant == 4 || (c->so.kernel_variant == 0 && c->so.autotune &&
+                                                                        c->so.tile_tx == 0 && c->so.tile_tz == 0));
     rc = OTM_OK;
     rc = rc ? rc : dalloc(c, &c->rho, nn);
     rc = rc ? rc : dalloc(c, &c->rhof, nn);
@@ -727,6 +880,10 @@ int otm_create(const otm_problem* problem, const otm_solver_opts* solver, const 
         rc = rc ? rc : dalloc(c, &c->p64[0], 3 * nn);
         rc = rc ? rc : dalloc(c, &c->p64[1], 3 * nn);
         rc = rc ? rc : dalloc(c, &c->q64, 3 * nn);
+        if (fused_bufs) {
+            rc = rc ? rc : dalloc(c, &c->r64b, 3 * nn);
+            rc = rc ? rc : dalloc(c, &c->q64b, 3 * nn);
+        }
     } else {
         rc = rc ? rc : dalloc(c, &c->k32, nn);
         rc = rc ? rc : dalloc(c, &c->dinv32, nn);
@@ -735,6 +892,10 @@ int otm_create(const otm_problem* problem, const otm_solver_opts* solver, const 
         rc = rc ? rc : dalloc(c, &c->p32[0], 3 * nn);
         rc = rc ? rc : dalloc(c, &c->p32[1], 3 * nn);
         rc = rc ? rc : dalloc(c, &c->q32, 3 * nn);
+        if (fused_bufs) {
+            rc = rc ? rc : dalloc(c, &c->r32b, 3 * nn);
+            rc = rc ? rc : dalloc(c, &c->q32b, 3 * nn);
+        }
     }
     rc = rc ? rc : dalloc(c, &c->partials, (int64_t)c->max_blocks * kMaxReduce);
     rc = rc ? rc : dalloc(c, &c->counter, 64);
@@ -1125,7 +1286,7 @@ int otm_set_network(otm_ctx* c, otm_nn* net) {
 int otm_get_tile(const otm_ctx* c, int32_t tile4[4]) {
     if (!c || !tile4) return OTM_EINVAL;
     const TileShape& t = c->use_pair ? c->tile2 : c->tile;
-    tile4[0] = c->so.kernel_variant == 0 ? (c->use_pair ? 0 : 3) : c->so.kernel_variant;
+    tile4[0] = c->use_fused ? 4 : (c->so.kernel_variant == 0 ? (c->use_pair ? 0 : 3) : c->so.kernel_variant);
     tile4[1] = t.tx;
     tile4[2] = t.tz;
     tile4[3] = t.blocks;

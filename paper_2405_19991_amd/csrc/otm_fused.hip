@@ -1,0 +1,430 @@
+// Fused Jacobi-PCG iteration: one streaming pass and one reduction per
+// iteration (gfx950).
+//
+// Plain PCG reduces twice per iteration (p.Ap for alpha, then r.D^-1 r for
+// beta), so it needs two passes over the vectors.  Here the updates of
+// iteration m-1 and the direction and operator of iteration m share one
+// z-march:
+//
+//   r_m = r_{m-1} - a q_{m-1},   x += a p_{m-1},
+//   z_m = D^-1 r_m,   p_m = z_m + b p_{m-1},   q_m = A p_m,
+//
+// where a = rz_{m-1} / pq_{m-1} and b = rz_m / rz_{m-1}.  rz_m is needed before
+// r_m exists; it follows from the expansion
+//   (r - a q)^T D^-1 (r - a q) = r^T D^-1 r - 2a q^T D^-1 r + a^2 q^T D^-1 q,
+// whose terms the previous pass reduced next to p.q.  The same pass also
+// reduces the exact r_m^T z_m and r_m^T r_m, so alpha and the convergence test
+// use exact values and the expansion only bridges one step (no drift).  In exact
+// arithmetic the iterates are those of plain Jacobi-PCG.
+//
+// Halo nodes of p_m are recomputed from r_{m-1}, q_{m-1}, p_{m-1}: r, q and p are
+// double-buffered so no pass overwrites what a neighbouring block still reads.
+// x is updated in place (own nodes only).  Two x-adjacent nodes per thread with
+// 8-byte accesses, as the pair operator; even n only.
+#include "otm_device.h"
+
+namespace otm {
+
+template <typename T>
+struct FV2 {
+    typedef T type __attribute__((ext_vector_type(2)));
+};
+
+template <typename T>
+struct PreF {
+    typename FV2<T>::type r[3], q[3], p[3], x[3], dv, k;  // own pair
+    T hr[3], hq[3], hp[3], hdv, kh;                      // one halo node / element
+};
+
+// Partial sums per block, per load l: [l] p.q, [3+l] q.z, [6+l] q.D^-1 q,
+// [9+l] r.z, [12+l] r.r (r, z of the updated residual).
+constexpr int kFusedSums = 15;
+
+template <typename T, int WX, int TY, bool ALL>
+__device__ __forceinline__ void fused_body(int n, int tz, int ntx, int nty, const T* __restrict__ r_in,
+                                           const T* __restrict__ q_in, const T* __restrict__ p_in,
+                                           T* __restrict__ r_out, T* __restrict__ q_out, T* __restrict__ p_out,
+                                           T* __restrict__ x, const T* __restrict__ dinv, const T* __restrict__ k,
+                                           double* __restrict__ partials, const Scalars* __restrict__ sc) {
+    typedef typename FV2<T>::type T2;
+    static_assert(WX * TY == kBlock, "block size");
+    constexpr int TX = 2 * WX;
+    constexpr int PX = TX + 2, PY = TY + 2;
+    constexpr int PXP = TX + 4;
+    constexpr int NH = 2 * PX + 2 * (PY - 2);
+    constexpr int KX = TX + 1, KY = TY + 1;
+    constexpr int KXP = TX + 2;
+    constexpr int NKH = KX + KY - 1;
+    static_assert(NH <= kBlock && NKH <= kBlock, "halo");
+    __shared__ __attribute__((aligned(16))) T sp[2][3][PY * PXP];
+    __shared__ __attribute__((aligned(16))) T sk[2][KY * KXP];
+
+    const int tid = threadIdx.x;
+    const int tx = tid % WX, ty = tid / WX;
+    int bid = blockIdx.x;
+    const int bx = bid % ntx;
+    bid /= ntx;
+    const int by = bid % nty;
+    const int bz = bid / nty;
+    const int i0 = bx * TX, j0 = by * TY, z0 = bz * tz;
+    const int z1 = min(z0 + tz, n);
+    const int64_t nn = (int64_t)n * n * n;
+    const int64_t n2 = (int64_t)n * n;
+
+    // per-load uniforms: activity, step a (alpha), direction weight b (beta)
+    bool act[3], ua[3], up[3];
+    T al[3], be[3];
+#pragma unroll
+    for (int l = 0; l < 3; ++l) {
+        act[l] = ALL ? true : (sc->active[l] != 0);
+        al[l] = (T)sc->alpha[l];
+        be[l] = (T)sc->beta[l];
+        ua[l] = act[l] && al[l] != (T)0;
+        up[l] = ua[l] || (act[l] && be[l] != (T)0);
+    }
+    const int i = i0 + 2 * tx, j = j0 + ty;
+    const bool own = (i < n) && (j < n);  // n even: i < n implies i + 1 < n
+    const uint32_t xy_own = (uint32_t)(i % n) + (uint32_t)n * (uint32_t)(j % n);
+    const int lp = (ty + 1) * PXP + (2 * tx + 1) + 1;
+    const int lk = (ty + 1) * KXP + (2 * tx + 1) + 1;
+    const bool has_h = tid < NH;
+    uint32_t xy_h = 0;
+    int lph = 0;
+    if (has_h) {
+        int px, py;
+        if (tid < PX) {
+            px = tid;
+            py = 0;
+        } else if (tid < 2 * PX) {
+            px = tid - PX;
+            py = PY - 1;
+        } else if (tid < 2 * PX + (PY - 2)) {
+            px = 0;
+            py = 1 + (tid - 2 * PX);
+        } else {
+            px = PX - 1;
+            py = 1 + (tid - 2 * PX - (PY - 2));
+        }
+        const int gi = (i0 - 1 + px + n) % n, gj = (j0 - 1 + py + n) % n;
+        xy_h = (uint32_t)gi + (uint32_t)n * (uint32_t)gj;
+        lph = py * PXP + px + 1;
+    }
+    const bool has_kh = tid < NKH;
+    uint32_t xy_kh = 0;
+    int lkh = 0;
+    if (has_kh) {
+        int kx, ky;
+        if (tid < KX) {
+            kx = tid;
+            ky = 0;
+        } else {
+            kx = 0;
+            ky = 1 + (tid - KX);
+        }
+        const int gi = (i0 - 1 + kx + n) % n, gj = (j0 - 1 + ky + n) % n;
+        xy_kh = (uint32_t)gi + (uint32_t)n * (uint32_t)gj;
+        lkh = ky * KXP + kx + 1;
+    }
+
+    auto plane_off = [&](int P) -> int64_t {
+        const int pw = P < 0 ? P + n : (P >= n ? P - n : P);
+        return (int64_t)pw * n2;
+    };
+
+    auto load_plane = [&](int P, PreF<T>& f) {
+        const int64_t zoff = plane_off(P);
+        const bool inr = P >= z0 && P < z1;
+        const T* dp = dinv + zoff;
+        f.dv = *reinterpret_cast<const T2*>(dp + xy_own);
+        if (has_h) f.hdv = dp[xy_h];
+#pragma unroll
+        for (int l = 0; l < 3; ++l) {
+            if (!act[l]) continue;
+            const int64_t o = l * nn + zoff;
+            f.r[l] = *reinterpret_cast<const T2*>(r_in + o + xy_own);
+            if (has_h) f.hr[l] = r_in[o + xy_h];
+            if (ua[l]) {
+                f.q[l] = *reinterpret_cast<const T2*>(q_in + o + xy_own);
+                if (has_h) f.hq[l] = q_in[o + xy_h];
+                if (inr) f.x[l] = *reinterpret_cast<const T2*>(x + o + xy_own);
+            }
+            if (up[l]) {
+                f.p[l] = *reinterpret_cast<const T2*>(p_in + o + xy_own);
+                if (has_h) f.hp[l] = p_in[o + xy_h];
+            }
+        }
+        const T* kp = k + zoff;
+        f.k = *reinterpret_cast<const T2*>(kp + xy_own);
+        if (has_kh) f.kh = kp[xy_kh];
+    };
+
+    // per-thread partials in T (at most 2 tz terms each), block and grid sums in float64
+    T acc[kFusedSums];
+#pragma unroll
+    for (int q = 0; q < kFusedSums; ++q) acc[q] = (T)0;
+    T2 pP[3], zP[3], dvP;
+
+    auto store_plane = [&](int P, const PreF<T>& f) {
+        const int slot = P & 1;
+        const bool inr = P >= z0 && P < z1;
+        const int64_t zoff = plane_off(P);
+#pragma unroll
+        for (int l = 0; l < 3; ++l) {
+            if (!act[l]) continue;
+            T2 rn = f.r[l];
+            T hrn = f.hr[l];
+            if (ua[l]) {
+                rn -= al[l] * f.q[l];
+                hrn -= al[l] * f.hq[l];
+            }
+            const T2 z = f.dv * rn;
+            const T hz = f.hdv * hrn;
+            T2 pn = z;
+            T hpn = hz;
+            if (up[l]) {
+                pn += be[l] * f.p[l];
+                hpn += be[l] * f.hp[l];
+            }
+            if (inr && own) {
+                const int64_t o = l * nn + zoff + xy_own;
+                *reinterpret_cast<T2*>(r_out + o) = rn;
+                *reinterpret_cast<T2*>(p_out + o) = pn;
+                if (ua[l]) *reinterpret_cast<T2*>(x + o) = f.x[l] + al[l] * f.p[l];
+                acc[9 + l] += rn.x * z.x + rn.y * z.y;
+                acc[12 + l] += rn.x * rn.x + rn.y * rn.y;
+            }
+            *reinterpret_cast<T2*>(&sp[slot][l][lp]) = pn;
+            if (has_h) sp[slot][l][lph] = hpn;
+            pP[l] = pn;
+            zP[l] = z;
+        }
+        dvP = f.dv;
+        *reinterpret_cast<T2*>(&sk[slot][lk]) = f.k;
+        if (has_kh) sk[slot][lkh] = f.kh;
+    };
+
+    const T w = (T)(1.0 / 12.0);
+    const T third = (T)(1.0 / 3.0);
+    T2 yA[3], yB[3], pB[3], zB[3], dvB = (T2)((T)0);
+#pragma unroll
+    for (int l = 0; l < 3; ++l) {
+        yA[l] = (T2)((T)0);
+        yB[l] = (T2)((T)0);
+        pB[l] = (T2)((T)0);
+        zB[l] = (T2)((T)0);
+    }
+    T kpm0 = 0, kpm1 = 0, kpm2 = 0, kpc0 = 0, kpc1 = 0, kpc2 = 0;
+
+    // Node plane P arrives: finish node P-1 (its dz = +1 taps), add the
+    // in-plane taps of node P, start node P+1 (dz = -1 taps).
+    auto compute = [&](int P) {
+        const int slot = P & 1;
+        const T* K = sk[slot];
+        const T km0 = K[lk - KXP - 1];
+        const T2 km12 = *reinterpret_cast<const T2*>(&K[lk - KXP]);
+        const T kc0 = K[lk - 1];
+        const T2 kc12 = *reinterpret_cast<const T2*>(&K[lk]);
+        const T km1 = km12.x, km2 = km12.y, kc1 = kc12.x, kc2 = kc12.y;
+        const T pa_xm = kpm0 + kpc0, pa_xp = kpm1 + kpc1, pa_ym = kpm0 + kpm1, pa_yp = kpc0 + kpc1;
+        const T pb_xm = kpm1 + kpc1, pb_xp = kpm2 + kpc2, pb_ym = kpm1 + kpm2, pb_yp = kpc1 + kpc2;
+        const T ca_xm = km0 + kc0, ca_xp = km1 + kc1, ca_ym = km0 + km1, ca_yp = kc0 + kc1;
+        const T cb_xm = km1 + kc1, cb_xp = km2 + kc2, cb_ym = km1 + km2, cb_yp = kc1 + kc2;
+        const T ea0 = kpm0 + km0, ea1 = kpm1 + km1, ea2 = kpc0 + kc0, ea3 = kpc1 + kc1;
+        const T eb0 = kpm1 + km1, eb1 = kpm2 + km2, eb2 = kpc1 + kc1, eb3 = kpc2 + kc2;
+        const T c0a = (ea0 + ea1 + ea2 + ea3) * third;
+        const T c0b = (eb0 + eb1 + eb2 + eb3) * third;
+        const bool done = (P - 1 >= z0) && own;
+        const int64_t vdone = (int64_t)(P - 1 < 0 ? 0 : (P - 1)) * n2 + xy_own;
+#pragma unroll
+        for (int l = 0; l < 3; ++l) {
+            if (!act[l]) continue;
+            const T* L = sp[slot][l];
+            const T m0 = L[lp - PXP - 1];
+            const T2 m12 = *reinterpret_cast<const T2*>(&L[lp - PXP]);
+            const T m3 = L[lp - PXP + 2];
+            const T c0v = L[lp - 1];
+            const T2 c12 = *reinterpret_cast<const T2*>(&L[lp]);
+            const T c3 = L[lp + 2];
+            const T p0 = L[lp + PXP - 1];
+            const T2 p12 = *reinterpret_cast<const T2*>(&L[lp + PXP]);
+            const T p3 = L[lp + PXP + 2];
+            const T m1 = m12.x, m2 = m12.y, c1 = c12.x, c2 = c12.y, p1 = p12.x, p2 = p12.y;
+            const T opa = pa_xm * c0v + pa_xp * c2 + pa_ym * m1 + pa_yp * p1 + kpm0 * m0 + kpm1 * m2 + kpc0 * p0 +
+                          kpc1 * p2;
+            const T oca = ca_xm * c0v + ca_xp * c2 + ca_ym * m1 + ca_yp * p1 + km0 * m0 + km1 * m2 + kc0 * p0 +
+                          kc1 * p2;
+            const T ina = c0a * c1 - w * (ea0 * m0 + ea1 * m2 + ea2 * p0 + ea3 * p2);
+            const T opb = pb_xm * c1 + pb_xp * c3 + pb_ym * m2 + pb_yp * p2 + kpm1 * m1 + kpm2 * m3 + kpc1 * p1 +
+                          kpc2 * p3;
+            const T ocb = cb_xm * c1 + cb_xp * c3 + cb_ym * m2 + cb_yp * p2 + km1 * m1 + km2 * m3 + kc1 * p1 +
+                          kc2 * p3;
+            const T inb = c0b * c2 - w * (eb0 * m1 + eb1 * m3 + eb2 * p1 + eb3 * p3);
+            T2 qv;
+            qv.x = yA[l].x - w * opa;
+            qv.y = yA[l].y - w * opb;
+            if (done) {
+                *reinterpret_cast<T2*>(q_out + l * nn + vdone) = qv;
+                acc[l] += pB[l].x * qv.x + pB[l].y * qv.y;
+                acc[3 + l] += zB[l].x * qv.x + zB[l].y * qv.y;
+                acc[6 + l] += dvB.x * qv.x * qv.x + dvB.y * qv.y * qv.y;
+            }
+            T2 yb;
+            yb.x = yB[l].x + ina;
+            yb.y = yB[l].y + inb;
+            yA[l] = yb;
+            yB[l].x = -w * oca;
+            yB[l].y = -w * ocb;
+            pB[l] = pP[l];
+            zB[l] = zP[l];
+        }
+        dvB = dvP;
+        kpm0 = km0;
+        kpm1 = km1;
+        kpm2 = km2;
+        kpc0 = kc0;
+        kpc1 = kc1;
+        kpc2 = kc2;
+    };
+
+    PreF<T> fa, fb;
+    load_plane(z0 - 1, fa);
+    load_plane(z0, fb);
+    int P = z0 - 1;
+    for (; P + 1 <= z1; P += 2) {
+        store_plane(P, fa);
+        if (P + 2 <= z1) load_plane(P + 2, fa);
+        __syncthreads();
+        compute(P);
+        store_plane(P + 1, fb);
+        if (P + 3 <= z1) load_plane(P + 3, fb);
+        __syncthreads();
+        compute(P + 1);
+    }
+    if (P <= z1) {
+        store_plane(P, fa);
+        __syncthreads();
+        compute(P);
+    }
+    double accd[kFusedSums];
+#pragma unroll
+    for (int q = 0; q < kFusedSums; ++q) accd[q] = (double)acc[q];
+    block_partials_at<kFusedSums>(accd, partials, blockIdx.x);
+}
+
+// float32: two waves per SIMD (two blocks per CU) must fit, i.e. at most 256
+// registers per lane; float64 state does not fit that and runs one wave per SIMD.
+template <int WX, int TY, bool ALL>
+__global__ void __launch_bounds__(WX* TY) __attribute__((amdgpu_waves_per_eu(2)))
+    k_fused_f32(int n, int tz, int ntx, int nty, const float* __restrict__ r_in, const float* __restrict__ q_in,
+                const float* __restrict__ p_in, float* __restrict__ r_out, float* __restrict__ q_out,
+                float* __restrict__ p_out, float* __restrict__ x, const float* __restrict__ dinv,
+                const float* __restrict__ k, double* __restrict__ partials, const Scalars* __restrict__ sc) {
+    fused_body<float, WX, TY, ALL>(n, tz, ntx, nty, r_in, q_in, p_in, r_out, q_out, p_out, x, dinv, k, partials, sc);
+}
+
+template <int WX, int TY, bool ALL>
+__global__ void __launch_bounds__(WX* TY)
+    k_fused_f64(int n, int tz, int ntx, int nty, const double* __restrict__ r_in, const double* __restrict__ q_in,
+                const double* __restrict__ p_in, double* __restrict__ r_out, double* __restrict__ q_out,
+                double* __restrict__ p_out, double* __restrict__ x, const double* __restrict__ dinv,
+                const double* __restrict__ k, double* __restrict__ partials, const Scalars* __restrict__ sc) {
+    fused_body<double, WX, TY, ALL>(n, tz, ntx, nty, r_in, q_in, p_in, r_out, q_out, p_out, x, dinv, k, partials,
+                                    sc);
+}
+
+template <typename T, int WX, int TY, bool ALL>
+struct FusedKernel;
+template <int WX, int TY, bool ALL>
+struct FusedKernel<float, WX, TY, ALL> {
+    static constexpr auto fn = k_fused_f32<WX, TY, ALL>;
+};
+template <int WX, int TY, bool ALL>
+struct FusedKernel<double, WX, TY, ALL> {
+    static constexpr auto fn = k_fused_f64<WX, TY, ALL>;
+};
+
+template <typename T, bool ALL>
+static void launch_f(int n, const TileShape& t, const T* r_in, const T* q_in, const T* p_in, T* r_out, T* q_out,
+                     T* p_out, T* x, const T* dinv, const T* k, double* partials, const Scalars* sc, hipStream_t s) {
+    const int ntx = (n + t.tx - 1) / t.tx, nty = (n + t.ty - 1) / t.ty;
+    if (t.tx == 32)
+        hipLaunchKernelGGL((FusedKernel<T, 16, 16, ALL>::fn), dim3(t.blocks), dim3(kBlock), 0, s, n, t.tz, ntx, nty, r_in,
+                           q_in, p_in, r_out, q_out, p_out, x, dinv, k, partials, sc);
+    else
+        hipLaunchKernelGGL((FusedKernel<T, 32, 8, ALL>::fn), dim3(t.blocks), dim3(kBlock), 0, s, n, t.tz, ntx, nty, r_in,
+                           q_in, p_in, r_out, q_out, p_out, x, dinv, k, partials, sc);
+}
+
+template <typename T>
+void launch_fused(int n, const TileShape& t, bool all_active, const T* r_in, const T* q_in, const T* p_in, T* r_out,
+                  T* q_out, T* p_out, T* x, const T* dinv, const T* k, const Workspace& ws, hipStream_t s, bool fin) {
+    if (all_active)
+        launch_f<T, true>(n, t, r_in, q_in, p_in, r_out, q_out, p_out, x, dinv, k, ws.partials, ws.sc, s);
+    else
+        launch_f<T, false>(n, t, r_in, q_in, p_in, r_out, q_out, p_out, x, dinv, k, ws.partials, ws.sc, s);
+    if (fin) launch_finalize(FIN_F_PASS, t.blocks, ws, s);
+}
+
+template void launch_fused<float>(int, const TileShape&, bool, const float*, const float*, const float*, float*,
+                                  float*, float*, float*, const float*, const float*, const Workspace&, hipStream_t,
+                                  bool);
+template void launch_fused<double>(int, const TileShape&, bool, const double*, const double*, const double*, double*,
+                                   double*, double*, double*, const double*, const double*, const Workspace&,
+                                   hipStream_t, bool);
+
+// r = b - A x with the float64 operator, stored as TR, with the sums the fused
+// iteration restarts from: per load [l] r.r (float64 r), [3+l] r.D^-1 r and
+// [9+l] q.D^-1 r (stored r), [6+l] b.b.  q may be null (start: no pending step).
+template <typename TR>
+__global__ void __launch_bounds__(kBlock)
+    k_residual_f(int n, const double* __restrict__ k, const double* __restrict__ b, const double* __restrict__ x,
+                 TR* __restrict__ r, const TR* __restrict__ q, const TR* __restrict__ dinv, int x_zero,
+                 double* __restrict__ partials) {
+    const int64_t nn = (int64_t)n * n * n;
+    double acc[12];
+#pragma unroll
+    for (int c = 0; c < 12; ++c) acc[c] = 0.0;
+    for (int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x; v < nn; v += (int64_t)gridDim.x * kBlock) {
+        double ax[3] = {0.0, 0.0, 0.0};
+        if (!x_zero) {
+            const int i = (int)(v % n), j = (int)((v / n) % n), kk = (int)(v / ((int64_t)n * n));
+            const Nbr o = nbr_of(i, j, kk, n);
+            double ko[8];
+            load_k8(k, o, ko);
+            NodeCoef<double> c;
+            node_coefs(ko, c);
+#pragma unroll
+            for (int l = 0; l < 3; ++l) ax[l] = stencil_node<double, double>(c, o, x + l * nn);
+        }
+        const double dv = (double)dinv[v];
+#pragma unroll
+        for (int l = 0; l < 3; ++l) {
+            const double bv = b[l * nn + v];
+            const double rv = bv - ax[l];
+            const TR rs = (TR)rv;
+            r[l * nn + v] = rs;
+            const double zs = dv * (double)rs;
+            acc[l] += rv * rv;
+            acc[3 + l] += zs * (double)rs;
+            acc[6 + l] += bv * bv;
+            if (q) acc[9 + l] += (double)q[l * nn + v] * zs;
+        }
+    }
+    block_partials<12>(acc, partials);
+}
+
+template <typename TR>
+void launch_residual_f(int n, const double* k, const double* b, const double* x, TR* r, const TR* q, const TR* dinv,
+                       bool start, int x_zero, const Workspace& ws, hipStream_t s) {
+    const int64_t nn = (int64_t)n * n * n;
+    const int g = grid_for(nn, ws.max_blocks);
+    hipLaunchKernelGGL(k_residual_f<TR>, dim3(g), dim3(kBlock), 0, s, n, k, b, x, r, q, dinv, x_zero, ws.partials);
+    launch_finalize(start ? FIN_F_START : FIN_F_REFRESH, g, ws, s);
+}
+
+template void launch_residual_f<float>(int, const double*, const double*, const double*, float*, const float*,
+                                       const float*, bool, int, const Workspace&, hipStream_t);
+template void launch_residual_f<double>(int, const double*, const double*, const double*, double*, const double*,
+                                        const double*, bool, int, const Workspace&, hipStream_t);
+
+}  // namespace otm

@@ -20,6 +20,7 @@ struct Scalars {
     double rz[3];       // r . D^-1 r of the current residual
     double rz_prev[3];  // previous value (reliable-update beta)
     double pq[3];
+    double qdq[3];      // q . D^-1 q of the last pass (fused iteration)
     double alpha[3];
     double beta[3];
     double rr[3];       // recursive ||r||^2
@@ -97,7 +98,10 @@ enum FinOp {
     FIN_SUM3_X,
     FIN_SUM3_B,
     FIN_ENERGY,
-    FIN_OC
+    FIN_OC,
+    FIN_F_START,    // fused iteration: residual at the start of a solve
+    FIN_F_REFRESH,  // fused iteration: float64 residual replaces the recursive one
+    FIN_F_PASS      // fused iteration: after each pass
 };
 void launch_finalize(int op, int nblocks, const Workspace& ws, hipStream_t s, int64_t nn = 0, double eta = 0.5);
 
@@ -158,10 +162,24 @@ void launch_dir_march2(int n, const TileShape& t, bool all_active, const T* r, c
                        T* p_new, const T* k, T* q, const Workspace& ws, hipStream_t s);
 template <typename T>
 void launch_apply_march2(int n, const TileShape& t, const T* k, const T* x, T* y, hipStream_t s);
+// Fused single-pass PCG iteration (otm_fused.hip): even n, pair tiles of
+// choose_tile2.  r, q, p are read from *_in and written to *_out (ping-pong);
+// x is updated in place.  fin = false skips the finalize (timing only).
+template <typename T>
+void launch_fused(int n, const TileShape& t, bool all_active, const T* r_in, const T* q_in, const T* p_in, T* r_out,
+                  T* q_out, T* p_out, T* x, const T* dinv, const T* k, const Workspace& ws, hipStream_t s,
+                  bool fin = true);
+// r = b - A x (float64 operator) for the fused iteration; start: begin a solve
+// (q unused, may be null), else refresh the recursive residual keeping the
+// pending step (q = the last pass's A p).
+template <typename TR>
+void launch_residual_f(int n, const double* k, const double* b, const double* x, TR* r, const TR* q, const TR* dinv,
+                       bool start, int x_zero, const Workspace& ws, hipStream_t s);
 template <typename T>
 void launch_apply_tiled(int n, const TileShape& t, const T* k, const T* x, T* y, hipStream_t s);
 template <typename T>
-void launch_update_vec(int n, T* x, T* r, const T* p, const T* q, const T* dinv, const Workspace& ws, hipStream_t s);
+void launch_update_vec(int n, T* x, T* r, const T* p, const T* q, const T* dinv, const Workspace& ws, hipStream_t s,
+                       bool fin = true);
 
 // Batched launches (one launch covers every design).
 void launch_b_clamp(const BatchTab& t, double* rho, double lo, double hi, hipStream_t s);

@@ -490,6 +490,18 @@ __device__ __forceinline__ void fin_sums(const double* partials, int nblocks, do
     final_sums<NV>(partials, nblocks, tot);
 }
 
+// Step of the fused iteration from the current residual's r.z (rz) and the
+// pending direction's p.q, q.D^-1 q (stored) and q.z (qz):
+// alpha = rz / pq; the next r.z follows from expanding (r - alpha q)^T D^-1 (r - alpha q).
+__device__ __forceinline__ void fused_step(Scalars* sc, int l, double rz, double qz) {
+    const double pq = sc->pq[l];
+    const double a = (pq > 0.0) ? rz / pq : 0.0;
+    const double rz_next = rz - 2.0 * a * qz + a * a * sc->qdq[l];
+    sc->rz[l] = rz;
+    sc->alpha[l] = a;
+    sc->beta[l] = (rz > 0.0 && rz_next > 0.0) ? rz_next / rz : 0.0;
+}
+
 __device__ __forceinline__ void b_finalize(int op, int nblocks, const double* __restrict__ partials, Scalars* sc,
                                            int64_t nn, double eta) {
     __shared__ double tot[kMaxReduce];
@@ -504,6 +516,9 @@ __device__ __forceinline__ void b_finalize(int op, int nblocks, const double* __
         case FIN_UPDATE:
         case FIN_ENERGY: fin_sums<6>(partials, nblocks, tot); break;
         case FIN_OC: fin_sums<kOcCands>(partials, nblocks, tot); break;
+        case FIN_F_START:
+        case FIN_F_REFRESH: fin_sums<12>(partials, nblocks, tot); break;
+        case FIN_F_PASS: fin_sums<15>(partials, nblocks, tot); break;
         default: return;
     }
     if (threadIdx.x != 0) return;
@@ -564,6 +579,49 @@ __device__ __forceinline__ void b_finalize(int op, int nblocks, const double* __
             break;
         case FIN_ENERGY:
             for (int c = 0; c < 6; ++c) sc->kappa_sum[c] = tot[c];
+            break;
+        case FIN_F_START:
+        case FIN_F_REFRESH:
+            // sums: [l] r.r (float64), [3+l] r.D^-1 r, [6+l] b.b, [9+l] q.D^-1 r
+            for (int l = 0; l < 3; ++l) {
+                const double rr = tot[l], rz = tot[3 + l], bb = tot[6 + l], qz = tot[9 + l];
+                sc->rr_true[l] = rr;
+                sc->rr[l] = rr;
+                sc->bb[l] = bb;
+                const bool need = (bb > 0.0) && (rr > sc->tol2 * bb);
+                if (!need) {
+                    sc->active[l] = 0;
+                    sc->alpha[l] = 0.0;
+                    sc->beta[l] = 0.0;
+                } else if (op == FIN_F_REFRESH && sc->active[l] && sc->alpha[l] != 0.0) {
+                    // keep the pending step p, q; re-derive it from the new residual
+                    fused_step(sc, l, rz, qz);
+                } else {
+                    // (re)start: the next pass takes p = D^-1 r and no step
+                    sc->active[l] = 1;
+                    sc->alpha[l] = 0.0;
+                    sc->beta[l] = 0.0;
+                    sc->rz[l] = rz;
+                }
+            }
+            break;
+        case FIN_F_PASS:
+            // sums: [l] p.q, [3+l] q.z, [6+l] q.D^-1 q, [9+l] r.z, [12+l] r.r
+            for (int l = 0; l < 3; ++l) {
+                if (!sc->active[l]) continue;
+                if (sc->alpha[l] != 0.0) sc->iters[l] += 1;
+                const double rr = tot[12 + l];
+                sc->rr[l] = rr;
+                if (!(rr > sc->tol2 * sc->bb[l])) {
+                    sc->active[l] = 0;
+                    sc->alpha[l] = 0.0;
+                    sc->beta[l] = 0.0;
+                    continue;
+                }
+                sc->pq[l] = tot[l];
+                sc->qdq[l] = tot[6 + l];
+                fused_step(sc, l, tot[9 + l], tot[3 + l]);
+            }
             break;
         case FIN_OC: {
             if (sc->oc_done) break;
@@ -880,6 +938,9 @@ static int fin_width(int op) {
         case FIN_UPDATE:
         case FIN_ENERGY: return 6;
         case FIN_OC: return kOcCands;
+        case FIN_F_START:
+        case FIN_F_REFRESH: return 12;
+        case FIN_F_PASS: return 15;
         default: return 3;
     }
 }

@@ -69,7 +69,8 @@ def generate(runs=None, tol: float = 1e-6):
     return data
 
 
-def train(data, epochs: int = 12, batch: int = 8, lr: float = 2e-3, seed: int = 0, n_max: int = 128):
+def train(data, epochs: int = 40, batch: int = 8, lr: float = 2e-3, seed: int = 0, n_max: int = 128,
+          halve_every: int = 10):
     from .api import Network
     net = Network(n_max=n_max, seed=seed)
     g = np.random.Generator(np.random.PCG64(seed))
@@ -83,50 +84,65 @@ def train(data, epochs: int = 12, batch: int = 8, lr: float = 2e-3, seed: int = 
             tot += net.accumulate(rf, chi)
             cnt += 1
             if cnt % batch == 0 or q == len(order) - 1:
-                net.adam(lr * (0.5 ** (ep // 4)), min(batch, cnt % batch or batch))
+                net.adam(lr * (0.5 ** (ep // halve_every)), min(batch, cnt % batch or batch))
         history.append(tot / len(order))
         _log(f"epoch {ep}: mean loss {history[-1]:.4e}")
     return net, history
 
 
-def time_to_tol(n: int, rho, target, vf: float, precision: str, guess: str, net=None, tol: float = 1e-6,
-                previous_steps: int = 0) -> Dict[str, float]:
-    """PCG iterations and solve time of one homogenization from the given start.
-    For guess='previous' the cell first runs previous_steps design iterations."""
+def _solve_record(h, kappa, st, ms):
+    return {"pcg_iters": int(sum(st["iterations"])), "max_load_iters": int(max(st["iterations"])),
+            "ms": ms, "converged": bool(st["converged"]), "learned_used": bool(h.timings()[6]),
+            "kappa": [float(v) for v in kappa]}
+
+
+def time_to_tol(n: int, rho, target, vf: float, precision: str, guess: str, net=None,
+                tol: float = 1e-6) -> Dict[str, float]:
+    """PCG iterations and wall time of one homogenization of the density rho
+    from a zero or learned start (a warm-up solve of the same state first).
+    The time includes the network's forward pass for the learned start."""
     import torch
     from .api import Homogenization
     with Homogenization(n, (1.0, 1e-3), target, vf=vf, tol=tol, precision=precision, guess=guess) as h:
         if net is not None:
             h.set_network(net)
         h.set_density(rho)
-        for _ in range(previous_steps):
-            h.step()
-        h.homogenize()  # warm-up of this exact state (kernels, graphs)
+        h.homogenize()
         torch.cuda.synchronize()
-        if guess == "previous":
-            pass
         t0 = time.perf_counter()
         kappa, st = h.homogenize()
-        t1 = time.perf_counter()
-        used = h.timings()[6]
-    return {"pcg_iters": int(sum(st["iterations"])), "max_load_iters": int(max(st["iterations"])),
-            "ms": 1000.0 * (t1 - t0), "converged": bool(st["converged"]), "learned_used": bool(used),
-            "kappa": [float(v) for v in kappa]}
+        ms = 1000.0 * (time.perf_counter() - t0)
+        return _solve_record(h, kappa, st, ms)
 
 
-def evaluate(net, n: int = 128, seed: int = 303) -> Dict[str, Dict[str, float]]:
-    """Time to 1e-6 on a held-out 128^3 anisotropic cell (first design iteration)."""
+def evaluate(net, n: int = 128, seed: int = 303, at_iter: int = 5, tol: float = 1e-6) -> Dict[str, Dict[str, float]]:
+    """Time to tol on a held-out 128^3 anisotropic cell at design iteration
+    `at_iter`: the previous design iteration's solution as the start (that
+    solve, timed inside the design run), then zero and learned starts on the
+    same density."""
+    import torch
     sys.path.insert(0, os.path.dirname(HERE))
     import synth
-    rho = synth.smoothed_noise(n, 0.15, 0.45, seed)
-    tgt = synth.TARGET_ANISO
-    out = {
-        "zero_fp64": time_to_tol(n, rho, tgt, 0.3, "fp64", "zero"),
-        "zero_mixed": time_to_tol(n, rho, tgt, 0.3, "mixed", "zero"),
-        "learned_mixed": time_to_tol(n, rho, tgt, 0.3, "mixed", "learned", net),
-        "learned_fp64": time_to_tol(n, rho, tgt, 0.3, "fp64", "learned", net),
+    from .api import Homogenization
+    rho0 = synth.smoothed_noise(n, 0.15, 0.45, seed)
+    tgt, vf = synth.TARGET_ANISO, 0.3
+    with Homogenization(n, (1.0, 1e-3), tgt, vf=vf, tol=tol, precision="mixed", guess="previous") as h:
+        h.set_density(rho0)
+        for _ in range(at_iter):
+            h.step()
+        rho_k = h.get_field("rho")
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        kappa, st = h.homogenize()
+        prev = _solve_record(h, kappa, st, 1000.0 * (time.perf_counter() - t0))
+    return {
+        "design_iteration": at_iter,
+        "zero_fp64": time_to_tol(n, rho_k, tgt, vf, "fp64", "zero", tol=tol),
+        "zero_mixed": time_to_tol(n, rho_k, tgt, vf, "mixed", "zero", tol=tol),
+        "previous_mixed": prev,
+        "learned_mixed": time_to_tol(n, rho_k, tgt, vf, "mixed", "learned", net, tol=tol),
+        "learned_fp64": time_to_tol(n, rho_k, tgt, vf, "fp64", "learned", net, tol=tol),
     }
-    return out
 
 
 def main(argv=None):
@@ -134,7 +150,7 @@ def main(argv=None):
     ap.add_argument("cmd", choices=["train", "eval"])
     ap.add_argument("--out", default=DEFAULT_WEIGHTS)
     ap.add_argument("--weights", default=DEFAULT_WEIGHTS)
-    ap.add_argument("--epochs", type=int, default=12)
+    ap.add_argument("--epochs", type=int, default=40)
     ap.add_argument("--summary", default=None)
     a = ap.parse_args(argv)
     import torch
