@@ -45,7 +45,9 @@ def parse():
                          "hardware-counter profiling; prints one JSON line with their HIP-event timings")
     ap.add_argument("--apply-tx", type=int, default=64)
     ap.add_argument("--apply-tz", type=int, default=8)
-    ap.add_argument("--learned", default=None, help="network weights (.npy) for the learned-start leg")
+    ap.add_argument("--weights", default=None,
+                    help="network weights (.npy) for the warm-start leg (default: the package's trained weights)")
+    ap.add_argument("--no-warm-start", action="store_true", help="skip the warm-start leg")
     return ap.parse_args()
 
 
@@ -103,6 +105,27 @@ def batch_leg(steps: int, log):
             "s_per_oc_iter": (t1 - t0) / steps, "pcg_dof_updates_per_s": iters / (t1 - t0),
             "tile_tx": int(info["tile_tx"]), "tile_tz": int(info["tile_tz"]), "work_items": int(info["work_items"]),
             "steps": steps}
+
+
+def warm_start_leg(weights, log):
+    """Time to 1e-6 on the held-out 128^3 cell at design iteration 5: zero
+    start (FP64, mixed), previous design iteration's solution, and the trained
+    network's prediction (forward pass included)."""
+    from paper_2405_19991_amd import Network
+    from paper_2405_19991_amd import warmstart as W
+    path = weights or W.DEFAULT_WEIGHTS
+    if not os.path.exists(path):
+        log(f"warm start: no weights at {path}, leg skipped")
+        return None
+    net = Network(n_max=128)
+    net.load(path)
+    ev = W.evaluate(net)
+    for k, v in ev.items():
+        if isinstance(v, dict):
+            v.pop("kappa", None)
+            log(f"warm start {k}: {v['pcg_iters']} PCG iterations, {v['ms']:.2f} ms")
+    ev["weights"] = os.path.relpath(path, ROOT)
+    return ev
 
 
 def apply_only(args):
@@ -164,6 +187,7 @@ def main():
         r = h.step()
         log(f"warmup {i}: g={r['g']:.4e} pcg={r['pcg_iters']} ms={r['ms_total']:.1f}")
     torch.cuda.synchronize()
+    h.pass_timing(reset=True)
     recs = []
     t0 = time.perf_counter()
     for _ in range(args.steps):
@@ -175,6 +199,7 @@ def main():
     pcg_iters = sum(sum(r["pcg_iters"]) for r in recs)
     dof = nn * pcg_iters
     solve_ms = sum(r["ms_solve"] for r in recs)
+    live = h.pass_timing()
 
     # dominant kernel: the stencil operator, timed with HIP events on its stream
     k_field = torch.from_numpy(h.get_field("k").reshape(-1)).cuda()
@@ -202,10 +227,24 @@ def main():
     achieved = alg_bytes / (us * 1e-6) / 1e9
     tname = "float" if args.precision == "mixed" else "double"
     kname = {0: "k_march2", 3: "k_march", 2: "k_tiled"}[v_best]
-    roof = {"bound": "hbm", "kernel": f"{kname}<{tname}, ..., DIR=false> tile {tx_best}x{256 // (tx_best // (2 if v_best == 0 else 1))}, tz={tz_best} (stencil apply, 3 loads)",
-            "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None, "us_per_launch": us, "alg_bytes_per_launch": alg_bytes,
-            "direct_gather_us_per_launch": us_gather}
+    operator = {"kernel": f"{kname}<{tname}, ..., DIR=false> tile {tx_best}x{256 // (tx_best // (2 if v_best == 0 else 1))}, tz={tz_best} (stencil apply, 3 loads)",
+                "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+                "us_per_launch": us, "alg_bytes_per_launch": alg_bytes, "direct_gather_us_per_launch": us_gather}
+    # dominant kernel of the timed design iterations, timed live (HIP events
+    # around one sampled launch per check interval, on the solver's stream)
+    if live["launches"] > 0:
+        ach = live["bytes"] / (live["us"] * 1e-6) / 1e9
+        kdesc = ("k_fused_f32 (fused PCG pass: r -= a q, x += a p, p = D^-1 r + b p, q = A p, five dots; 3 loads)"
+                 if live["kernel"] == 4 else
+                 f"k_march2<{tname}, ..., DIR=true> (direction + operator pass, 3 loads)")
+        if live["kernel"] == 4 and args.precision == "fp64":
+            kdesc = kdesc.replace("k_fused_f32", "k_fused_f64")
+        roof = {"bound": "hbm", "kernel": kdesc, "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": ach / HBM_PEAK_GBS, "traffic": None, "us_per_launch": live["us"],
+                "alg_bytes_per_launch": live["bytes"], "sampled_launches": live["launches"],
+                "tile": {"tx": tile["tx"], "tz": tile["tz"], "blocks": tile["blocks"]}}
+    else:
+        roof = dict(operator, bound="hbm", traffic=None)
 
     out = {
         "metric": "128^3 PCG DOF-updates/s (whole design iteration, mixed precision)",
@@ -230,11 +269,14 @@ def main():
         "last_g": recs[-1]["g"],
         "last_kappa": recs[-1]["kappa"],
         "roofline": roof,
+        "operator": operator,
     }
     h.close()
     log(f"apply kernel {us:.2f} us ({achieved:.0f} GB/s algorithmic)")
     if not args.no_batch:
         out["batch"] = batch_leg(args.batch_steps, log)
+    if not args.no_warm_start and n == 128:
+        out["warm_start"] = warm_start_leg(args.weights, log)
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(w, args.oracle_cg_iters)

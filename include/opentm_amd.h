@@ -247,9 +247,19 @@ int otm_time_apply_device(int32_t n, int32_t precision, int32_t variant, int32_t
                           const void* k_dev, const void* x_dev, void* y_dev, void* stream, int32_t reps,
                           double* us_per_launch);
 
-/* Operator kernel in use: [variant (0 pair z-march, 1 gather, 2 ring, 3 z-march),
- * tile width, planes per march, blocks per launch]. */
+/* Operator kernel in use: [variant (0 pair z-march, 1 gather, 2 ring, 3 z-march,
+ * 4 fused PCG iteration), tile width, planes per march, blocks per launch]. */
 int otm_get_tile(const otm_ctx* ctx, int32_t tile4[4]);
+
+/* Live timing of the solver's dominant kernel (the fused pass, or the
+ * direction+operator pass of the two-pass iteration with the two-node
+ * z-march), accumulated over the solves since the last reset: one launch per
+ * host check interval is bracketed with HIP events on the context stream
+ * when every load takes a full step.  out4 = [sampled launches, mean
+ * microseconds per launch, algorithmic bytes per launch, kernel (4 fused,
+ * 0 direction+operator)].  reset != 0 clears the accumulators after reading.
+ * Other kernel variants are not sampled (count 0). */
+int otm_pass_timing(otm_ctx* ctx, int32_t reset, double out4[4]);
 
 /* Per-phase timings of the last otm_step, milliseconds, HIP events on the
  * context stream: [filter+setup, solve, tensor, sensitivity, oc, total,

@@ -37,7 +37,7 @@ EXPORTED = [
     "otm_default_options", "otm_create", "otm_destroy", "otm_set_density", "otm_set_density_device",
     "otm_homogenize", "otm_sensitivity", "otm_oc_update", "otm_step", "otm_optimize", "otm_get_field",
     "otm_set_field", "otm_set_guess", "otm_get_governor", "otm_set_governor", "otm_apply", "otm_prepare", "otm_apply_device",
-    "otm_time_apply_device", "otm_get_tile", "otm_get_timings", "otm_strerror", "otm_last_error", "otm_version",
+    "otm_time_apply_device", "otm_get_tile", "otm_pass_timing", "otm_get_timings", "otm_strerror", "otm_last_error", "otm_version",
     "otm_batch_create", "otm_batch_destroy", "otm_batch_set_density", "otm_batch_get_field", "otm_batch_step",
     "otm_batch_set_graph", "otm_batch_info", "otm_batch_last_error",
     "otm_nn_create", "otm_nn_destroy", "otm_nn_param_count", "otm_nn_get_params", "otm_nn_set_params",
@@ -133,6 +133,7 @@ def lib():
         "otm_time_apply_device": ([i32, i32, i32, i32, i32, vp, vp, vp, vp, i32, dp], ctypes.c_int),
         "otm_get_timings": ([ctx, dp], ctypes.c_int),
         "otm_get_tile": ([ctx, P(i32)], ctypes.c_int),
+        "otm_pass_timing": ([ctx, i32, dp], ctypes.c_int),
         "otm_strerror": ([ctypes.c_int], ctypes.c_char_p),
         "otm_last_error": ([ctx], ctypes.c_char_p),
         "otm_version": ([], ctypes.c_char_p),

@@ -174,6 +174,12 @@ class Homogenization:
         self._chk(self._L.otm_get_tile(self._h, t))
         return dict(variant=t[0], tx=t[1], tz=t[2], blocks=t[3])
 
+    def pass_timing(self, reset: bool = False) -> Dict[str, float]:
+        """Live HIP-event timing of the solver's dominant kernel since the last reset."""
+        t = np.zeros(4)
+        self._chk(self._L.otm_pass_timing(self._h, int(bool(reset)), _ptr(t)))
+        return dict(launches=int(t[0]), us=float(t[1]), bytes=float(t[2]), kernel=int(t[3]))
+
     def timings(self) -> List[float]:
         t = np.zeros(8)
         self._chk(self._L.otm_get_timings(self._h, _ptr(t)))

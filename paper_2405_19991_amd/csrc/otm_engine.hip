@@ -96,6 +96,13 @@ struct otm_ctx {
     otm_solve_stats last_stats{};
     double timings[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     hipEvent_t ev[8] = {};
+    // live timing of the dominant solver kernel: one sampled launch per
+    // check interval with every load active (events 0/1 of pev)
+    hipEvent_t pev[2] = {};
+    double pass_ms = 0.0;
+    int64_t pass_count = 0;
+    double pass_bytes = 0.0;  // algorithmic bytes of one sampled launch
+    int pass_kind = 0;        // 4: fused pass, 0: direction+operator pass
     std::string err;
 
     Workspace ws() const { return Workspace{partials, counter, sc, max_blocks}; }
@@ -232,6 +239,20 @@ int reset_solver_scalars(otm_ctx* c) {
     return OTM_OK;
 }
 
+// Adds the sampled launch of the last check interval (if any) to the live timing.
+void collect_pass_sample(otm_ctx* c, bool sampled, double bytes, int kind) {
+    if (!sampled) return;
+    float ms = 0.f;
+    if (hipEventElapsedTime(&ms, c->pev[0], c->pev[1]) != hipSuccess) {
+        (void)hipGetLastError();
+        return;
+    }
+    c->pass_ms += (double)ms;
+    c->pass_count += 1;
+    c->pass_bytes = bytes;
+    c->pass_kind = kind;
+}
+
 // One pass and one reduction per iteration (otm_fused.hip).  r[cur], q[cur],
 // p[cur] hold what the next pass reads; x is the float64 solution (FP64) or the
 // float32 increment folded into it at each residual refresh (mixed).
@@ -262,15 +283,24 @@ int solve_fused(otm_ctx* c, bool x_zero, bool mixed, const FusedBufs<T>& B, otm_
     int refreshes = 0, launches = 0;
     while (!all_inactive(c->h_sc) && max_iters(c->h_sc) < c->so.max_iter) {
         const bool all = all_active(c->h_sc);
+        bool sampled = false;
         for (int it = 0; it < c->so.check_every; ++it) {
             const int nx = cur ^ 1;
+            // sample the chunk's last pass when every load takes a full step
+            const bool sample = all && launches > 0 && it == c->so.check_every - 1;
+            if (sample) (void)hipEventRecord(c->pev[0], c->stream);
             launch_fused<T>(n, c->tile2, all, B.r[cur], B.q[cur], B.p[cur], B.r[nx], B.q[nx], B.p[nx], B.x, B.dinv,
-                            B.k, w, c->stream);
+                            B.k, w, c->stream, false);
+            if (sample) (void)hipEventRecord(c->pev[1], c->stream);
+            launch_finalize(FIN_F_PASS, c->tile2.blocks, w, c->stream);
+            sampled = sampled || sample;
             cur = nx;
             ++launches;
         }
         if ((rc = check_launch(c, "pcg fused"))) return rc;
         if ((rc = sync_scalars(c))) return rc;
+        // fused pass: r, q, p, x read and written, D^-1 and k read (three loads)
+        collect_pass_sample(c, sampled, (double)c->nn * (8.0 * 3 + 1 + 1) * sizeof(T), 4);
         bool refresh = all_inactive(c->h_sc);
         if (mixed)
             for (int l = 0; l < 3; ++l)
@@ -317,6 +347,8 @@ int solve_fp64(otm_ctx* c, bool x_zero, otm_solve_stats* st) {
     if ((rc = sync_scalars(c))) return rc;
     int launches = 0;
     while (!all_inactive(c->h_sc) && max_iters(c->h_sc) < c->so.max_iter) {
+        const bool all = all_active(c->h_sc);
+        bool sampled = false;
         for (int it = 0; it < c->so.check_every; ++it) {
             double* po = c->p64[c->pbuf];
             double* pn = c->p64[c->pbuf ^ 1];
@@ -327,9 +359,14 @@ int solve_fp64(otm_ctx* c, bool x_zero, otm_solve_stats* st) {
             } else {
                 if (c->so.kernel_variant == 2)
                     launch_dir_apply<double>(n, c->tile, c->r64, c->dinv, po, pn, c->k, c->q64, w, c->stream);
-                else if (c->use_pair)
-                    launch_dir_march2<double>(n, c->tile2, all_active(c->h_sc), c->r64, c->dinv, po, pn, c->k, c->q64, w,
-                                           c->stream);
+                else if (c->use_pair) {
+                    const bool sample = all && it == c->so.check_every - 1;
+                    if (sample) (void)hipEventRecord(c->pev[0], c->stream);
+                    launch_dir_march2<double>(n, c->tile2, all, c->r64, c->dinv, po, pn, c->k, c->q64, w, c->stream, false);
+                    if (sample) (void)hipEventRecord(c->pev[1], c->stream);
+                    launch_finalize(FIN_PQ, c->tile2.blocks, w, c->stream);
+                    sampled = sampled || sample;
+                }
                 else
                     launch_dir_march<double>(n, c->tile, c->r64, c->dinv, po, pn, c->k, c->q64, w, c->stream);
                 launch_update_vec<double>(n, c->x, c->r64, pn, c->q64, c->dinv, w, c->stream);
@@ -339,6 +376,8 @@ int solve_fp64(otm_ctx* c, bool x_zero, otm_solve_stats* st) {
         }
         if ((rc = check_launch(c, "pcg"))) return rc;
         if ((rc = sync_scalars(c))) return rc;
+        // direction+operator pass: r, p_old read, p, q written, D^-1 and k read
+        collect_pass_sample(c, sampled, (double)c->nn * (4.0 * 3 + 1 + 1) * sizeof(double), 0);
         if (all_inactive(c->h_sc)) {
             // confirm with the true residual; loads that fail restart
             launch_residual<double>(n, c->k, c->b, c->x, c->r64, c->p64[c->pbuf], c->dinv, RES_START, 0, w,
@@ -381,6 +420,8 @@ int solve_mixed(otm_ctx* c, bool x_zero, otm_solve_stats* st) {
     const double d2 = c->so.reliable_delta * c->so.reliable_delta;
     int refreshes = 0, launches = 0;
     while (!all_inactive(c->h_sc) && max_iters(c->h_sc) < c->so.max_iter) {
+        const bool all = all_active(c->h_sc);
+        bool sampled = false;
         for (int it = 0; it < c->so.check_every; ++it) {
             float* po = c->p32[c->pbuf];
             float* pn = c->p32[c->pbuf ^ 1];
@@ -391,9 +432,14 @@ int solve_mixed(otm_ctx* c, bool x_zero, otm_solve_stats* st) {
             } else {
                 if (c->so.kernel_variant == 2)
                     launch_dir_apply<float>(n, c->tile, c->r32, c->dinv32, po, pn, c->k32, c->q32, w, c->stream);
-                else if (c->use_pair)
-                    launch_dir_march2<float>(n, c->tile2, all_active(c->h_sc), c->r32, c->dinv32, po, pn, c->k32, c->q32, w,
-                                           c->stream);
+                else if (c->use_pair) {
+                    const bool sample = all && it == c->so.check_every - 1;
+                    if (sample) (void)hipEventRecord(c->pev[0], c->stream);
+                    launch_dir_march2<float>(n, c->tile2, all, c->r32, c->dinv32, po, pn, c->k32, c->q32, w, c->stream, false);
+                    if (sample) (void)hipEventRecord(c->pev[1], c->stream);
+                    launch_finalize(FIN_PQ, c->tile2.blocks, w, c->stream);
+                    sampled = sampled || sample;
+                }
                 else
                     launch_dir_march<float>(n, c->tile, c->r32, c->dinv32, po, pn, c->k32, c->q32, w, c->stream);
                 launch_update_vec<float>(n, c->x32, c->r32, pn, c->q32, c->dinv32, w, c->stream);
@@ -403,6 +449,8 @@ int solve_mixed(otm_ctx* c, bool x_zero, otm_solve_stats* st) {
         }
         if ((rc = check_launch(c, "pcg32"))) return rc;
         if ((rc = sync_scalars(c))) return rc;
+        // direction+operator pass: r, p_old read, p, q written, D^-1 and k read
+        collect_pass_sample(c, sampled, (double)c->nn * (4.0 * 3 + 1 + 1) * sizeof(float), 0);
         bool refresh = all_inactive(c->h_sc);
         for (int l = 0; l < 3; ++l)
             if (c->h_sc->active[l] && c->h_sc->rr[l] < d2 * rr_ref[l]) refresh = true;
@@ -582,6 +630,8 @@ int free_all(otm_ctx* c) {
         if (p) (void)hipFree(p);
     if (c->h_sc) (void)hipHostFree(c->h_sc);
     for (auto& e : c->ev)
+        if (e) (void)hipEventDestroy(e);
+    for (auto& e : c->pev)
         if (e) (void)hipEventDestroy(e);
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
     return 0;
@@ -903,6 +953,8 @@ int otm_create(const otm_problem* problem, const otm_solver_opts* solver, const 
     if (!rc && hipHostMalloc((void**)&c->h_sc, sizeof(Scalars), hipHostMallocDefault) != hipSuccess) rc = OTM_ENOMEM;
     for (int q = 0; q < 8 && !rc; ++q)
         if (hipEventCreate(&c->ev[q]) != hipSuccess) rc = OTM_EDEVICE;
+    for (int q = 0; q < 2 && !rc; ++q)
+        if (hipEventCreate(&c->pev[q]) != hipSuccess) rc = OTM_EDEVICE;
     if (rc) {
         free_all(c);
         delete c;
@@ -1280,6 +1332,19 @@ int otm_time_apply_device(int32_t n, int32_t precision, int32_t variant, int32_t
 int otm_set_network(otm_ctx* c, otm_nn* net) {
     if (!c) return OTM_EINVAL;
     c->net = net;
+    return OTM_OK;
+}
+
+int otm_pass_timing(otm_ctx* c, int32_t reset, double out4[4]) {
+    if (!c || !out4) return OTM_EINVAL;
+    out4[0] = (double)c->pass_count;
+    out4[1] = c->pass_count ? 1000.0 * c->pass_ms / (double)c->pass_count : 0.0;
+    out4[2] = c->pass_bytes;
+    out4[3] = (double)c->pass_kind;
+    if (reset) {
+        c->pass_ms = 0.0;
+        c->pass_count = 0;
+    }
     return OTM_OK;
 }
 

@@ -159,7 +159,7 @@ void launch_apply_march(int n, const TileShape& t, const T* k, const T* x, T* y,
 TileShape choose_tile2(int n, int max_blocks, int tz_override, int tx_override);
 template <typename T>
 void launch_dir_march2(int n, const TileShape& t, bool all_active, const T* r, const T* dinv, const T* p_old,
-                       T* p_new, const T* k, T* q, const Workspace& ws, hipStream_t s);
+                       T* p_new, const T* k, T* q, const Workspace& ws, hipStream_t s, bool fin = true);
 template <typename T>
 void launch_apply_march2(int n, const TileShape& t, const T* k, const T* x, T* y, hipStream_t s);
 // Fused single-pass PCG iteration (otm_fused.hip): even n, pair tiles of

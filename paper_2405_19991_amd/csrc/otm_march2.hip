@@ -337,12 +337,12 @@ TileShape choose_tile2(int n, int max_blocks, int tz_override, int tx_override) 
 
 template <typename T>
 void launch_dir_march2(int n, const TileShape& t, bool all_active, const T* r, const T* dinv, const T* p_old,
-                       T* p_new, const T* k, T* q, const Workspace& ws, hipStream_t s) {
+                       T* p_new, const T* k, T* q, const Workspace& ws, hipStream_t s, bool fin) {
     if (all_active)
         launch_m2<T, true, true>(n, t, r, dinv, p_old, p_new, k, q, ws.partials, ws.sc, s);
     else
         launch_m2<T, true, false>(n, t, r, dinv, p_old, p_new, k, q, ws.partials, ws.sc, s);
-    launch_finalize(FIN_PQ, t.blocks, ws, s);
+    if (fin) launch_finalize(FIN_PQ, t.blocks, ws, s);
 }
 
 template <typename T>
@@ -351,9 +351,9 @@ void launch_apply_march2(int n, const TileShape& t, const T* k, const T* x, T* y
 }
 
 template void launch_dir_march2<double>(int, const TileShape&, bool, const double*, const double*, const double*,
-                                        double*, const double*, double*, const Workspace&, hipStream_t);
+                                        double*, const double*, double*, const Workspace&, hipStream_t, bool);
 template void launch_dir_march2<float>(int, const TileShape&, bool, const float*, const float*, const float*, float*,
-                                       const float*, float*, const Workspace&, hipStream_t);
+                                       const float*, float*, const Workspace&, hipStream_t, bool);
 template void launch_apply_march2<double>(int, const TileShape&, const double*, const double*, double*, hipStream_t);
 template void launch_apply_march2<float>(int, const TileShape&, const float*, const float*, float*, hipStream_t);
 
