@@ -48,7 +48,44 @@ def parse():
     ap.add_argument("--weights", default=None,
                     help="network weights (.npy) for the warm-start leg (default: the package's trained weights)")
     ap.add_argument("--no-warm-start", action="store_true", help="skip the warm-start leg")
+    ap.add_argument("--variant", type=int, default=0,
+                    help="solver kernel: 0 automatic (autotuned), 4 fused iteration, 1-3 cross-check kernels")
+    ap.add_argument("--solver-tx", type=int, default=0, help="solver tile width (0: automatic)")
+    ap.add_argument("--solver-tz", type=int, default=0, help="solver planes per z-march (0: automatic)")
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="after the timed steps, run three 64 MiB device copies (a kernel of known traffic, "
+                         "for scaling hardware byte counters)")
     return ap.parse_args()
+
+
+# Counter-measured HBM bytes of a kernel come from a committed rocprofv3
+# summary; they stand only while the kernel's sources hash as they did when
+# the counters were taken (else the traffic field is null).
+TRAFFIC_RECORDS = {
+    4: ("profiles/k_fused_f32_cell128_traffic.md",
+        ("paper_2405_19991_amd/csrc/otm_fused.hip", "paper_2405_19991_amd/csrc/otm_device.h")),
+}
+
+
+def sources_sha256(paths):
+    import hashlib
+    h = hashlib.sha256()
+    for p in paths:
+        with open(os.path.join(ROOT, p), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def recorded_traffic(kind: int):
+    rec = TRAFFIC_RECORDS.get(kind)
+    if rec is None or not os.path.exists(os.path.join(ROOT, rec[0])):
+        return None
+    for line in open(os.path.join(ROOT, rec[0])):
+        if line.startswith("record: "):
+            d = json.loads(line[len("record: "):])
+            if d.get("sha256") == sources_sha256(rec[1]):
+                return d
+    return None
 
 
 def cpu_baseline(w, cg_iters: int):
@@ -177,7 +214,8 @@ def main():
     n = w.n
     nn = n ** 3
     h = Homogenization(n, (w.k0, w.kmin), w.target, vf=w.vf, penal=w.penal, filter_radius=w.rfilter,
-                       precision=args.precision, guess=args.guess, tol=w.tol)
+                       precision=args.precision, guess=args.guess, tol=w.tol, kernel_variant=args.variant,
+                       tile_tx=args.solver_tx, tile_tz=args.solver_tz)
     h.set_density(w.rho0)
     def log(msg):
         print(msg, file=sys.stderr, flush=True)
@@ -239,8 +277,13 @@ def main():
                  f"k_march2<{tname}, ..., DIR=true> (direction + operator pass, 3 loads)")
         if live["kernel"] == 4 and args.precision == "fp64":
             kdesc = kdesc.replace("k_fused_f32", "k_fused_f64")
+        trec = recorded_traffic(live["kernel"]) if args.precision == "mixed" and n == 128 else None
+        if trec and (trec.get("tile_tx"), trec.get("tile_tz")) != (tile["tx"], tile["tz"]):
+            trec = None  # counters were taken for another tile
         roof = {"bound": "hbm", "kernel": kdesc, "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": ach / HBM_PEAK_GBS, "traffic": None, "us_per_launch": live["us"],
+                "frac": ach / HBM_PEAK_GBS, "traffic": trec["traffic_bytes_per_launch"] if trec else None,
+                "traffic_source": TRAFFIC_RECORDS[live["kernel"]][0] if trec else None,
+                "us_per_launch": live["us"],
                 "alg_bytes_per_launch": live["bytes"], "sampled_launches": live["launches"],
                 "tile": {"tx": tile["tx"], "tz": tile["tz"], "blocks": tile["blocks"]}}
     else:
@@ -272,6 +315,13 @@ def main():
         "operator": operator,
     }
     h.close()
+    if args.calib_copy:
+        src = torch.empty(64 * 1024 * 1024, dtype=torch.uint8, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
     log(f"apply kernel {us:.2f} us ({achieved:.0f} GB/s algorithmic)")
     if not args.no_batch:
         out["batch"] = batch_leg(args.batch_steps, log)

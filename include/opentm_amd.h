@@ -58,12 +58,15 @@ extern "C" {
 #define OTM_MIXED 1 /* float32 operator and Krylov vectors; float64 solution, dots,
                        residual recomputation and tensor assembly */
 
+/* Warm starts (PREVIOUS, USER, LEARNED) are scaled per load by
+ * s = b.x / x.A x, the factor minimising the quadratic energy along the guess,
+ * so the start is never farther from the solution in the energy norm than
+ * chi = 0; a load with b.x <= 0 starts from zero. */
 #define OTM_GUESS_ZERO 0     /* PCG starts from chi = 0 */
 #define OTM_GUESS_PREVIOUS 1 /* PCG starts from the previous design iteration's chi */
 #define OTM_GUESS_USER 2     /* PCG starts from the field set by otm_set_guess */
 #define OTM_GUESS_LEARNED 3  /* PCG starts from the attached network's prediction
-                                (otm_set_network); falls back to zero when that start
-                                has a larger residual than the zero start */
+                                (otm_set_network; n a multiple of 16, else zero) */
 
 #define OTM_OBJ_MSE 0 /* g = sum_c (kappa_c - target_c)^2, Sec. 4.4 (MSE objective) */
 
@@ -254,7 +257,8 @@ int otm_get_tile(const otm_ctx* ctx, int32_t tile4[4]);
 /* Live timing of the solver's dominant kernel (the fused pass, or the
  * direction+operator pass of the two-pass iteration with the two-node
  * z-march), accumulated over the solves since the last reset: one launch per
- * host check interval is bracketed with HIP events on the context stream
+ * host check interval is timed with HIP events that the launch itself records
+ * at the kernel's start and end on the context stream (hipExtLaunchKernelGGL),
  * when every load takes a full step.  out4 = [sampled launches, mean
  * microseconds per launch, algorithmic bytes per launch, kernel (4 fused,
  * 0 direction+operator)].  reset != 0 clears the accumulators after reading.

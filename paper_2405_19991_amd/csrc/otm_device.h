@@ -73,6 +73,32 @@ __device__ __forceinline__ void final_sums(const double* partials, int nblocks, 
     __syncthreads();
 }
 
+// Global access at a block-uniform base plus a per-thread 32-bit byte offset:
+// the base stays in scalar registers and the address needs no 64-bit vector
+// arithmetic (the offsets of one plane stay far below 4 GiB).
+// (The empty asm keeps the offset a 32-bit value at the access, so the
+// compiler does not hoist its widening out of the march loop.)
+template <typename V>
+__device__ __forceinline__ V ld_at(const void* base, uint32_t boff) {
+    asm volatile("" : "+v"(boff));
+    return *reinterpret_cast<const V*>(reinterpret_cast<const char*>(base) + boff);
+}
+template <typename V>
+__device__ __forceinline__ void st_at(void* base, uint32_t boff, V v) {
+    asm volatile("" : "+v"(boff));
+    *reinterpret_cast<V*>(reinterpret_cast<char*>(base) + boff) = v;
+}
+
+// Workgroups of a launch are dispatched round-robin over the 8 XCDs, each
+// with its own L2.  This bijection gives every XCD a contiguous range of tile
+// ids, so neighbouring tiles (whose halos overlap) share one L2.
+constexpr int kXcds = 8;
+__device__ __forceinline__ int xcd_tile(int bid, int nb) {
+    const int q = nb / kXcds, r = nb % kXcds;
+    const int x = bid % kXcds, k = bid / kXcds;
+    return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + k;
+}
+
 static inline int nblocks_for(int64_t count) { return (int)((count + kBlock - 1) / kBlock); }
 
 // Clamp grid size for grid-stride reductions so partial arrays stay small.

@@ -97,7 +97,8 @@ struct otm_ctx {
     double timings[8] = {0, 0, 0, 0, 0, 0, 0, 0};
     hipEvent_t ev[8] = {};
     // live timing of the dominant solver kernel: one sampled launch per
-    // check interval with every load active (events 0/1 of pev)
+    // check interval with every load active, bracketed by the launch's own
+    // start/end events (hipExtLaunchKernelGGL)
     hipEvent_t pev[2] = {};
     double pass_ms = 0.0;
     int64_t pass_count = 0;
@@ -288,11 +289,8 @@ int solve_fused(otm_ctx* c, bool x_zero, bool mixed, const FusedBufs<T>& B, otm_
             const int nx = cur ^ 1;
             // sample the chunk's last pass when every load takes a full step
             const bool sample = all && launches > 0 && it == c->so.check_every - 1;
-            if (sample) (void)hipEventRecord(c->pev[0], c->stream);
             launch_fused<T>(n, c->tile2, all, B.r[cur], B.q[cur], B.p[cur], B.r[nx], B.q[nx], B.p[nx], B.x, B.dinv,
-                            B.k, w, c->stream, false);
-            if (sample) (void)hipEventRecord(c->pev[1], c->stream);
-            launch_finalize(FIN_F_PASS, c->tile2.blocks, w, c->stream);
+                            B.k, w, c->stream, true, sample ? c->pev[0] : nullptr, sample ? c->pev[1] : nullptr);
             sampled = sampled || sample;
             cur = nx;
             ++launches;
@@ -361,10 +359,8 @@ int solve_fp64(otm_ctx* c, bool x_zero, otm_solve_stats* st) {
                     launch_dir_apply<double>(n, c->tile, c->r64, c->dinv, po, pn, c->k, c->q64, w, c->stream);
                 else if (c->use_pair) {
                     const bool sample = all && it == c->so.check_every - 1;
-                    if (sample) (void)hipEventRecord(c->pev[0], c->stream);
-                    launch_dir_march2<double>(n, c->tile2, all, c->r64, c->dinv, po, pn, c->k, c->q64, w, c->stream, false);
-                    if (sample) (void)hipEventRecord(c->pev[1], c->stream);
-                    launch_finalize(FIN_PQ, c->tile2.blocks, w, c->stream);
+                    launch_dir_march2<double>(n, c->tile2, all, c->r64, c->dinv, po, pn, c->k, c->q64, w, c->stream, true,
+                                           sample ? c->pev[0] : nullptr, sample ? c->pev[1] : nullptr);
                     sampled = sampled || sample;
                 }
                 else
@@ -434,10 +430,8 @@ int solve_mixed(otm_ctx* c, bool x_zero, otm_solve_stats* st) {
                     launch_dir_apply<float>(n, c->tile, c->r32, c->dinv32, po, pn, c->k32, c->q32, w, c->stream);
                 else if (c->use_pair) {
                     const bool sample = all && it == c->so.check_every - 1;
-                    if (sample) (void)hipEventRecord(c->pev[0], c->stream);
-                    launch_dir_march2<float>(n, c->tile2, all, c->r32, c->dinv32, po, pn, c->k32, c->q32, w, c->stream, false);
-                    if (sample) (void)hipEventRecord(c->pev[1], c->stream);
-                    launch_finalize(FIN_PQ, c->tile2.blocks, w, c->stream);
+                    launch_dir_march2<float>(n, c->tile2, all, c->r32, c->dinv32, po, pn, c->k32, c->q32, w, c->stream, true,
+                                           sample ? c->pev[0] : nullptr, sample ? c->pev[1] : nullptr);
                     sampled = sampled || sample;
                 }
                 else
@@ -485,9 +479,11 @@ int homogenize(otm_ctx* c, double kappa6[6], otm_solve_stats* st_out) {
     EvTimer t0(c, 0, 1);
     if ((rc = prepare(c))) return rc;
     t0.stop();
-    bool x_zero = true;
-    if (c->so.guess == OTM_GUESS_PREVIOUS && c->have_solution) x_zero = false;
-    if (c->so.guess == OTM_GUESS_USER && c->have_user_guess) x_zero = false;
+    // warm starts: the previous solution, a user field or the network's
+    // prediction, each load scaled by its energy-minimising factor
+    bool have_guess = false;
+    if (c->so.guess == OTM_GUESS_PREVIOUS && c->have_solution) have_guess = true;
+    if (c->so.guess == OTM_GUESS_USER && c->have_user_guess) have_guess = true;
     c->learned_used = 0;
     if (c->so.guess == OTM_GUESS_LEARNED && c->net && c->n % 16 == 0) {
         HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -495,21 +491,16 @@ int homogenize(otm_ctx* c, double kappa6[6], otm_solve_stats* st_out) {
         if (rc) return fail(c, rc, "network forward failed");
         // the network runs on its own stream
         HIPCHK(c, hipDeviceSynchronize());
-        // keep the prediction only if it starts closer than zero for every load
-        const Workspace w0 = c->ws();
-        if ((rc = reset_solver_scalars(c))) return rc;
-        if (c->so.precision == OTM_MIXED)
-            launch_residual<float>(c->n, c->k, c->b, c->x, c->r32, c->p32[c->pbuf], c->dinv32, RES_START, 0, w0,
-                                   c->stream);
-        else
-            launch_residual<double>(c->n, c->k, c->b, c->x, c->r64, c->p64[c->pbuf], c->dinv, RES_START, 0, w0,
-                                    c->stream);
+        have_guess = true;
+    }
+    bool x_zero = true;
+    if (have_guess) {
+        launch_guess_scale(c->n, c->k, c->b, c->x, c->ws(), c->stream);
+        if ((rc = check_launch(c, "guess scale"))) return rc;
         if ((rc = sync_scalars(c))) return rc;
-        bool better = true;
-        for (int l = 0; l < 3; ++l)
-            if (!(c->h_sc->rr_true[l] <= c->h_sc->bb[l])) better = false;
-        x_zero = !better;
-        c->learned_used = better ? 1 : 0;
+        const double* gs = c->h_sc->gscale;
+        x_zero = !(gs[0] > 0.0 || gs[1] > 0.0 || gs[2] > 0.0);
+        if (c->so.guess == OTM_GUESS_LEARNED) c->learned_used = x_zero ? 0 : 1;
     }
     otm_solve_stats st{};
     (void)hipEventRecord(c->ev[2], c->stream);

@@ -21,6 +21,8 @@
 // double-buffered so no pass overwrites what a neighbouring block still reads.
 // x is updated in place (own nodes only).  Two x-adjacent nodes per thread with
 // 8-byte accesses, as the pair operator; even n only.
+#include <hip/hip_ext.h>
+
 #include "otm_device.h"
 
 namespace otm {
@@ -61,7 +63,7 @@ __device__ __forceinline__ void fused_body(int n, int tz, int ntx, int nty, cons
 
     const int tid = threadIdx.x;
     const int tx = tid % WX, ty = tid / WX;
-    int bid = blockIdx.x;
+    int bid = xcd_tile(blockIdx.x, gridDim.x);  // tiles in x, then y, then z
     const int bx = bid % ntx;
     bid /= ntx;
     const int by = bid % nty;
@@ -131,31 +133,35 @@ __device__ __forceinline__ void fused_body(int n, int tz, int ntx, int nty, cons
         return (int64_t)pw * n2;
     };
 
+    const uint32_t bo = xy_own * (uint32_t)sizeof(T);   // own pair
+    const uint32_t bh = xy_h * (uint32_t)sizeof(T);     // halo node
+    const uint32_t bkh = xy_kh * (uint32_t)sizeof(T);   // halo element
+
     auto load_plane = [&](int P, PreF<T>& f) {
         const int64_t zoff = plane_off(P);
         const bool inr = P >= z0 && P < z1;
         const T* dp = dinv + zoff;
-        f.dv = *reinterpret_cast<const T2*>(dp + xy_own);
-        if (has_h) f.hdv = dp[xy_h];
+        f.dv = ld_at<T2>(dp, bo);
+        if (has_h) f.hdv = ld_at<T>(dp, bh);
 #pragma unroll
         for (int l = 0; l < 3; ++l) {
             if (!act[l]) continue;
             const int64_t o = l * nn + zoff;
-            f.r[l] = *reinterpret_cast<const T2*>(r_in + o + xy_own);
-            if (has_h) f.hr[l] = r_in[o + xy_h];
+            f.r[l] = ld_at<T2>(r_in + o, bo);
+            if (has_h) f.hr[l] = ld_at<T>(r_in + o, bh);
             if (ua[l]) {
-                f.q[l] = *reinterpret_cast<const T2*>(q_in + o + xy_own);
-                if (has_h) f.hq[l] = q_in[o + xy_h];
-                if (inr) f.x[l] = *reinterpret_cast<const T2*>(x + o + xy_own);
+                f.q[l] = ld_at<T2>(q_in + o, bo);
+                if (has_h) f.hq[l] = ld_at<T>(q_in + o, bh);
+                if (inr) f.x[l] = ld_at<T2>(x + o, bo);
             }
             if (up[l]) {
-                f.p[l] = *reinterpret_cast<const T2*>(p_in + o + xy_own);
-                if (has_h) f.hp[l] = p_in[o + xy_h];
+                f.p[l] = ld_at<T2>(p_in + o, bo);
+                if (has_h) f.hp[l] = ld_at<T>(p_in + o, bh);
             }
         }
         const T* kp = k + zoff;
-        f.k = *reinterpret_cast<const T2*>(kp + xy_own);
-        if (has_kh) f.kh = kp[xy_kh];
+        f.k = ld_at<T2>(kp, bo);
+        if (has_kh) f.kh = ld_at<T>(kp, bkh);
     };
 
     // per-thread partials in T (at most 2 tz terms each), block and grid sums in float64
@@ -186,10 +192,10 @@ __device__ __forceinline__ void fused_body(int n, int tz, int ntx, int nty, cons
                 hpn += be[l] * f.hp[l];
             }
             if (inr && own) {
-                const int64_t o = l * nn + zoff + xy_own;
-                *reinterpret_cast<T2*>(r_out + o) = rn;
-                *reinterpret_cast<T2*>(p_out + o) = pn;
-                if (ua[l]) *reinterpret_cast<T2*>(x + o) = f.x[l] + al[l] * f.p[l];
+                const int64_t o = l * nn + zoff;
+                st_at<T2>(r_out + o, bo, rn);
+                st_at<T2>(p_out + o, bo, pn);
+                if (ua[l]) st_at<T2>(x + o, bo, f.x[l] + al[l] * f.p[l]);
                 acc[9 + l] += rn.x * z.x + rn.y * z.y;
                 acc[12 + l] += rn.x * rn.x + rn.y * rn.y;
             }
@@ -234,7 +240,7 @@ __device__ __forceinline__ void fused_body(int n, int tz, int ntx, int nty, cons
         const T c0a = (ea0 + ea1 + ea2 + ea3) * third;
         const T c0b = (eb0 + eb1 + eb2 + eb3) * third;
         const bool done = (P - 1 >= z0) && own;
-        const int64_t vdone = (int64_t)(P - 1 < 0 ? 0 : (P - 1)) * n2 + xy_own;
+        const int64_t zdone = (int64_t)(P - 1 < 0 ? 0 : (P - 1)) * n2;
 #pragma unroll
         for (int l = 0; l < 3; ++l) {
             if (!act[l]) continue;
@@ -263,7 +269,7 @@ __device__ __forceinline__ void fused_body(int n, int tz, int ntx, int nty, cons
             qv.x = yA[l].x - w * opa;
             qv.y = yA[l].y - w * opb;
             if (done) {
-                *reinterpret_cast<T2*>(q_out + l * nn + vdone) = qv;
+                st_at<T2>(q_out + l * nn + zdone, bo, qv);
                 acc[l] += pB[l].x * qv.x + pB[l].y * qv.y;
                 acc[3 + l] += zB[l].x * qv.x + zB[l].y * qv.y;
                 acc[6 + l] += dvB.x * qv.x * qv.x + dvB.y * qv.y * qv.y;
@@ -343,34 +349,37 @@ struct FusedKernel<double, WX, TY, ALL> {
     static constexpr auto fn = k_fused_f64<WX, TY, ALL>;
 };
 
+// ev0/ev1 (optional): HIP events recorded at the kernel's start and end.
 template <typename T, bool ALL>
 static void launch_f(int n, const TileShape& t, const T* r_in, const T* q_in, const T* p_in, T* r_out, T* q_out,
-                     T* p_out, T* x, const T* dinv, const T* k, double* partials, const Scalars* sc, hipStream_t s) {
+                     T* p_out, T* x, const T* dinv, const T* k, double* partials, const Scalars* sc, hipStream_t s,
+                     hipEvent_t ev0, hipEvent_t ev1) {
     const int ntx = (n + t.tx - 1) / t.tx, nty = (n + t.ty - 1) / t.ty;
     if (t.tx == 32)
-        hipLaunchKernelGGL((FusedKernel<T, 16, 16, ALL>::fn), dim3(t.blocks), dim3(kBlock), 0, s, n, t.tz, ntx, nty, r_in,
-                           q_in, p_in, r_out, q_out, p_out, x, dinv, k, partials, sc);
+        hipExtLaunchKernelGGL((FusedKernel<T, 16, 16, ALL>::fn), dim3(t.blocks), dim3(kBlock), 0, s, ev0, ev1, 0, n,
+                              t.tz, ntx, nty, r_in, q_in, p_in, r_out, q_out, p_out, x, dinv, k, partials, sc);
     else
-        hipLaunchKernelGGL((FusedKernel<T, 32, 8, ALL>::fn), dim3(t.blocks), dim3(kBlock), 0, s, n, t.tz, ntx, nty, r_in,
-                           q_in, p_in, r_out, q_out, p_out, x, dinv, k, partials, sc);
+        hipExtLaunchKernelGGL((FusedKernel<T, 32, 8, ALL>::fn), dim3(t.blocks), dim3(kBlock), 0, s, ev0, ev1, 0, n,
+                              t.tz, ntx, nty, r_in, q_in, p_in, r_out, q_out, p_out, x, dinv, k, partials, sc);
 }
 
 template <typename T>
 void launch_fused(int n, const TileShape& t, bool all_active, const T* r_in, const T* q_in, const T* p_in, T* r_out,
-                  T* q_out, T* p_out, T* x, const T* dinv, const T* k, const Workspace& ws, hipStream_t s, bool fin) {
+                  T* q_out, T* p_out, T* x, const T* dinv, const T* k, const Workspace& ws, hipStream_t s, bool fin,
+                  hipEvent_t ev0, hipEvent_t ev1) {
     if (all_active)
-        launch_f<T, true>(n, t, r_in, q_in, p_in, r_out, q_out, p_out, x, dinv, k, ws.partials, ws.sc, s);
+        launch_f<T, true>(n, t, r_in, q_in, p_in, r_out, q_out, p_out, x, dinv, k, ws.partials, ws.sc, s, ev0, ev1);
     else
-        launch_f<T, false>(n, t, r_in, q_in, p_in, r_out, q_out, p_out, x, dinv, k, ws.partials, ws.sc, s);
+        launch_f<T, false>(n, t, r_in, q_in, p_in, r_out, q_out, p_out, x, dinv, k, ws.partials, ws.sc, s, ev0, ev1);
     if (fin) launch_finalize(FIN_F_PASS, t.blocks, ws, s);
 }
 
 template void launch_fused<float>(int, const TileShape&, bool, const float*, const float*, const float*, float*,
                                   float*, float*, float*, const float*, const float*, const Workspace&, hipStream_t,
-                                  bool);
+                                  bool, hipEvent_t, hipEvent_t);
 template void launch_fused<double>(int, const TileShape&, bool, const double*, const double*, const double*, double*,
                                    double*, double*, double*, const double*, const double*, const Workspace&,
-                                   hipStream_t, bool);
+                                   hipStream_t, bool, hipEvent_t, hipEvent_t);
 
 // r = b - A x with the float64 operator, stored as TR, with the sums the fused
 // iteration restarts from: per load [l] r.r (float64 r), [3+l] r.D^-1 r and

@@ -35,6 +35,7 @@ struct Scalars {
     double bsum[3];      // sum of macro loads (projection)
     double xsum[3];      // sum of chi (projection)
     double kappa_sum[6]; // sum k_e E_e,c
+    double gscale[3];    // energy-minimising factor of the start guess, per load
     // OC bisection state
     double l1, l2;
     double vstar_n;      // V* * n^3
@@ -101,7 +102,8 @@ enum FinOp {
     FIN_OC,
     FIN_F_START,    // fused iteration: residual at the start of a solve
     FIN_F_REFRESH,  // fused iteration: float64 residual replaces the recursive one
-    FIN_F_PASS      // fused iteration: after each pass
+    FIN_F_PASS,     // fused iteration: after each pass
+    FIN_GUESS       // scale factors of a start guess
 };
 void launch_finalize(int op, int nblocks, const Workspace& ws, hipStream_t s, int64_t nn = 0, double eta = 0.5);
 
@@ -125,6 +127,9 @@ template <typename TR>
 void launch_residual(int n, const double* k, const double* b, const double* x, TR* r, TR* p_old, const TR* dinv,
                      int mode, int x_zero, const Workspace& ws, hipStream_t s);
 void launch_accumulate(int n, double* x, float* x32, hipStream_t s);
+// Scales each load of the start guess x by s = b.x / x.A x (float64 operator),
+// the factor that minimises the quadratic energy along x (0 if b.x <= 0).
+void launch_guess_scale(int n, const double* k, const double* b, double* x, const Workspace& ws, hipStream_t s);
 // slot 0: sums into sc->xsum, slot 1: into sc->bsum
 void launch_sum3(int n, const double* x, int slot, const Workspace& ws, hipStream_t s);
 void launch_sub_mean3(int n, double* x, int slot, const Workspace& ws, hipStream_t s);
@@ -159,7 +164,8 @@ void launch_apply_march(int n, const TileShape& t, const T* k, const T* x, T* y,
 TileShape choose_tile2(int n, int max_blocks, int tz_override, int tx_override);
 template <typename T>
 void launch_dir_march2(int n, const TileShape& t, bool all_active, const T* r, const T* dinv, const T* p_old,
-                       T* p_new, const T* k, T* q, const Workspace& ws, hipStream_t s, bool fin = true);
+                       T* p_new, const T* k, T* q, const Workspace& ws, hipStream_t s, bool fin = true,
+                       hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 template <typename T>
 void launch_apply_march2(int n, const TileShape& t, const T* k, const T* x, T* y, hipStream_t s);
 // Fused single-pass PCG iteration (otm_fused.hip): even n, pair tiles of
@@ -168,7 +174,7 @@ void launch_apply_march2(int n, const TileShape& t, const T* k, const T* x, T* y
 template <typename T>
 void launch_fused(int n, const TileShape& t, bool all_active, const T* r_in, const T* q_in, const T* p_in, T* r_out,
                   T* q_out, T* p_out, T* x, const T* dinv, const T* k, const Workspace& ws, hipStream_t s,
-                  bool fin = true);
+                  bool fin = true, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 // r = b - A x (float64 operator) for the fused iteration; start: begin a solve
 // (q unused, may be null), else refresh the recursive residual keeping the
 // pending step (q = the last pass's A p).

@@ -519,6 +519,7 @@ __device__ __forceinline__ void b_finalize(int op, int nblocks, const double* __
         case FIN_F_START:
         case FIN_F_REFRESH: fin_sums<12>(partials, nblocks, tot); break;
         case FIN_F_PASS: fin_sums<15>(partials, nblocks, tot); break;
+        case FIN_GUESS: fin_sums<6>(partials, nblocks, tot); break;
         default: return;
     }
     if (threadIdx.x != 0) return;
@@ -605,6 +606,12 @@ __device__ __forceinline__ void b_finalize(int op, int nblocks, const double* __
                 }
             }
             break;
+        case FIN_GUESS:
+            for (int l = 0; l < 3; ++l) {
+                const double bx = tot[l], xax = tot[3 + l];
+                sc->gscale[l] = (bx > 0.0 && xax > 0.0) ? bx / xax : 0.0;
+            }
+            break;
         case FIN_F_PASS:
             // sums: [l] p.q, [3+l] q.z, [6+l] q.D^-1 q, [9+l] r.z, [12+l] r.r
             for (int l = 0; l < 3; ++l) {
@@ -667,6 +674,39 @@ __global__ void __launch_bounds__(kBlock) k_finalize(int op, int nblocks, const 
 
 void launch_finalize(int op, int nblocks, const Workspace& ws, hipStream_t s, int64_t nn, double eta) {
     hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kBlock), 0, s, op, nblocks, ws.partials, ws.sc, nn, eta);
+}
+
+// Start guess along its own direction, per load: b.x and x.A x with the
+// float64 operator.  The energy 1/2 (s x)^T A (s x) - b^T (s x) is minimal at
+// s = b.x / x.A x, where it is -(b.x)^2 / (2 x.A x) < 0, the energy of x = 0:
+// the scaled guess is never farther from the solution in the A-norm than zero.
+__global__ void __launch_bounds__(kBlock) k_guess_dots(int n, const double* __restrict__ k,
+                                                       const double* __restrict__ b, const double* __restrict__ x,
+                                                       double* partials) {
+    const int64_t nn = (int64_t)n * n * n;
+    double acc[6] = {0, 0, 0, 0, 0, 0};
+    for (int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x; v < nn; v += (int64_t)gridDim.x * kBlock) {
+        const int i = (int)(v % n), j = (int)((v / n) % n), kk = (int)(v / ((int64_t)n * n));
+        const Nbr o = nbr_of(i, j, kk, n);
+        double ko[8];
+        load_k8(k, o, ko);
+        NodeCoef<double> c;
+        node_coefs(ko, c);
+#pragma unroll
+        for (int l = 0; l < 3; ++l) {
+            const double xv = x[l * nn + v];
+            acc[l] += b[l * nn + v] * xv;
+            acc[3 + l] += xv * stencil_node<double, double>(c, o, x + l * nn);
+        }
+    }
+    block_partials<6>(acc, partials);
+}
+
+__global__ void __launch_bounds__(kBlock) k_scale3(int64_t nn, double* __restrict__ x, const Scalars* __restrict__ sc) {
+    const int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (v >= nn) return;
+#pragma unroll
+    for (int l = 0; l < 3; ++l) x[l * nn + v] *= sc->gscale[l];
 }
 
 // ---------------------------------------------------------------- launchers
@@ -734,6 +774,14 @@ void launch_sum3(int n, const double* x, int slot, const Workspace& ws, hipStrea
 
 void launch_sub_mean3(int n, double* x, int slot, const Workspace& ws, hipStream_t s) {
     hipLaunchKernelGGL(k_sub_mean3, dim3(nblocks_for(cube(n))), dim3(kBlock), 0, s, n, x, slot, ws.sc);
+}
+
+void launch_guess_scale(int n, const double* k, const double* b, double* x, const Workspace& ws, hipStream_t s) {
+    const int64_t nn = cube(n);
+    const int g = grid_for(nn, ws.max_blocks);
+    hipLaunchKernelGGL(k_guess_dots, dim3(g), dim3(kBlock), 0, s, n, k, b, x, ws.partials);
+    launch_finalize(FIN_GUESS, g, ws, s);
+    hipLaunchKernelGGL(k_scale3, dim3(nblocks_for(nn)), dim3(kBlock), 0, s, nn, x, ws.sc);
 }
 
 void launch_energy(int n, const double* k, const double* chi, const Workspace& ws, hipStream_t s) {
@@ -941,6 +989,7 @@ static int fin_width(int op) {
         case FIN_F_START:
         case FIN_F_REFRESH: return 12;
         case FIN_F_PASS: return 15;
+        case FIN_GUESS: return 6;
         default: return 3;
     }
 }

@@ -10,6 +10,8 @@
 //
 // The march is unrolled by two planes so that the two-plane register
 // prefetch alternates between two register sets without copies.
+#include <hip/hip_ext.h>
+
 #include "otm_device.h"
 
 namespace otm {
@@ -118,28 +120,32 @@ __device__ __forceinline__ void march2_body(int bid_, int slot_, int n, int tz, 
         return (int64_t)pw * n2;
     };
 
+    const uint32_t bo = xy_own * (uint32_t)sizeof(T);
+    const uint32_t bh = xy_h * (uint32_t)sizeof(T);
+    const uint32_t bkh = xy_kh * (uint32_t)sizeof(T);
+
     auto load_plane = [&](int P, Pre2<T, DIR>& f) {
         const int64_t zoff = plane_off(P);
         if (DIR) {
             const T* dp = dinv + zoff;
-            f.dv = *reinterpret_cast<const T2*>(dp + xy_own);
-            if (has_h) f.hdv = dp[xy_h];
+            f.dv = ld_at<T2>(dp, bo);
+            if (has_h) f.hdv = ld_at<T>(dp, bh);
         }
 #pragma unroll
         for (int l = 0; l < 3; ++l) {
             if (!act[l]) continue;
             const T* rp = r + l * nn + zoff;
-            f.r[l] = *reinterpret_cast<const T2*>(rp + xy_own);
-            if (has_h) f.hr[l] = rp[xy_h];
+            f.r[l] = ld_at<T2>(rp, bo);
+            if (has_h) f.hr[l] = ld_at<T>(rp, bh);
             if (DIR && beta[l] != (T)0) {
                 const T* pp = p_old + l * nn + zoff;
-                f.po[l] = *reinterpret_cast<const T2*>(pp + xy_own);
-                if (has_h) f.hpo[l] = pp[xy_h];
+                f.po[l] = ld_at<T2>(pp, bo);
+                if (has_h) f.hpo[l] = ld_at<T>(pp, bh);
             }
         }
         const T* kp = k + zoff;
-        f.k = *reinterpret_cast<const T2*>(kp + xy_own);
-        if (has_kh) f.kh = kp[xy_kh];
+        f.k = ld_at<T2>(kp, bo);
+        if (has_kh) f.kh = ld_at<T>(kp, bkh);
     };
 
     T2 pP[3];
@@ -160,11 +166,11 @@ __device__ __forceinline__ void march2_body(int bid_, int slot_, int n, int tz, 
                     hv += beta[l] * f.hpo[l];
                 }
                 if (in_range) {
-                    T* pn = p_new + l * nn + zoff + xy_own;
+                    T* pn = p_new + l * nn + zoff;
                     if (own_b)
-                        *reinterpret_cast<T2*>(pn) = val;
+                        st_at<T2>(pn, bo, val);
                     else if (own_a)
-                        pn[0] = val.x;
+                        st_at<T>(pn, bo, val.x);
                 }
             }
             *reinterpret_cast<T2*>(&sp[slot][l][lp]) = val;
@@ -209,7 +215,7 @@ __device__ __forceinline__ void march2_body(int bid_, int slot_, int n, int tz, 
         const T c0a = (ea0 + ea1 + ea2 + ea3) * third;
         const T c0b = (eb0 + eb1 + eb2 + eb3) * third;
         const bool done = P - 1 >= z0;
-        const int64_t vdone = (int64_t)(P - 1 < 0 ? 0 : (P - 1)) * n2 + xy_own;
+        const int64_t zdone = (int64_t)(P - 1 < 0 ? 0 : (P - 1)) * n2;
 #pragma unroll
         for (int l = 0; l < 3; ++l) {
             if (!act[l]) continue;
@@ -241,11 +247,11 @@ __device__ __forceinline__ void march2_body(int bid_, int slot_, int n, int tz, 
             ya.x = yA[l].x - w * opa;
             ya.y = yA[l].y - w * opb;
             if (done) {
-                T* qp = q + l * nn + vdone;
+                T* qp = q + l * nn + zdone;
                 if (own_b)
-                    *reinterpret_cast<T2*>(qp) = ya;
+                    st_at<T2>(qp, bo, ya);
                 else if (own_a)
-                    qp[0] = ya.x;
+                    st_at<T>(qp, bo, ya.x);
                 if (DIR) {
                     if (own_a) acc[l] += (double)pB[l].x * (double)ya.x;
                     if (own_b) acc[l] += (double)pB[l].y * (double)ya.y;
@@ -297,20 +303,22 @@ __global__ void __launch_bounds__(WX* TY) k_march2(int n, int tz, int ntx, int n
                                                    T* __restrict__ p_new, const T* __restrict__ k,
                                                    T* __restrict__ q, double* __restrict__ partials,
                                                    const Scalars* __restrict__ sc) {
-    march2_body<T, WX, TY, DIR, ALL>(blockIdx.x, blockIdx.x, n, tz, ntx, nty, r, dinv, p_old, p_new, k, q, partials,
-                                     sc);
+    march2_body<T, WX, TY, DIR, ALL>(xcd_tile(blockIdx.x, gridDim.x), blockIdx.x, n, tz, ntx, nty, r, dinv, p_old,
+                                     p_new, k, q, partials, sc);
 }
 
+// ev0/ev1 (optional): HIP events recorded at the kernel's start and end.
 template <typename T, bool DIR, bool ALL>
 static void launch_m2(int n, const TileShape& t, const T* r, const T* dinv, const T* p_old, T* p_new, const T* k,
-                      T* q, double* partials, const Scalars* sc, hipStream_t s) {
+                      T* q, double* partials, const Scalars* sc, hipStream_t s, hipEvent_t ev0 = nullptr,
+                      hipEvent_t ev1 = nullptr) {
     const int ntx = (n + t.tx - 1) / t.tx, nty = (n + t.ty - 1) / t.ty;
     if (t.tx == 32)
-        hipLaunchKernelGGL((k_march2<T, 16, 16, DIR, ALL>), dim3(t.blocks), dim3(kBlock), 0, s, n, t.tz, ntx, nty, r,
-                           dinv, p_old, p_new, k, q, partials, sc);
+        hipExtLaunchKernelGGL((k_march2<T, 16, 16, DIR, ALL>), dim3(t.blocks), dim3(kBlock), 0, s, ev0, ev1, 0, n,
+                              t.tz, ntx, nty, r, dinv, p_old, p_new, k, q, partials, sc);
     else
-        hipLaunchKernelGGL((k_march2<T, 32, 8, DIR, ALL>), dim3(t.blocks), dim3(kBlock), 0, s, n, t.tz, ntx, nty, r,
-                           dinv, p_old, p_new, k, q, partials, sc);
+        hipExtLaunchKernelGGL((k_march2<T, 32, 8, DIR, ALL>), dim3(t.blocks), dim3(kBlock), 0, s, ev0, ev1, 0, n,
+                              t.tz, ntx, nty, r, dinv, p_old, p_new, k, q, partials, sc);
 }
 
 // Tile shapes of the pair kernel: tx in {32, 64} nodes (16 or 32 threads wide).
@@ -337,11 +345,12 @@ TileShape choose_tile2(int n, int max_blocks, int tz_override, int tx_override) 
 
 template <typename T>
 void launch_dir_march2(int n, const TileShape& t, bool all_active, const T* r, const T* dinv, const T* p_old,
-                       T* p_new, const T* k, T* q, const Workspace& ws, hipStream_t s, bool fin) {
+                       T* p_new, const T* k, T* q, const Workspace& ws, hipStream_t s, bool fin, hipEvent_t ev0,
+                       hipEvent_t ev1) {
     if (all_active)
-        launch_m2<T, true, true>(n, t, r, dinv, p_old, p_new, k, q, ws.partials, ws.sc, s);
+        launch_m2<T, true, true>(n, t, r, dinv, p_old, p_new, k, q, ws.partials, ws.sc, s, ev0, ev1);
     else
-        launch_m2<T, true, false>(n, t, r, dinv, p_old, p_new, k, q, ws.partials, ws.sc, s);
+        launch_m2<T, true, false>(n, t, r, dinv, p_old, p_new, k, q, ws.partials, ws.sc, s, ev0, ev1);
     if (fin) launch_finalize(FIN_PQ, t.blocks, ws, s);
 }
 
@@ -351,9 +360,11 @@ void launch_apply_march2(int n, const TileShape& t, const T* k, const T* x, T* y
 }
 
 template void launch_dir_march2<double>(int, const TileShape&, bool, const double*, const double*, const double*,
-                                        double*, const double*, double*, const Workspace&, hipStream_t, bool);
+                                        double*, const double*, double*, const Workspace&, hipStream_t, bool,
+                                        hipEvent_t, hipEvent_t);
 template void launch_dir_march2<float>(int, const TileShape&, bool, const float*, const float*, const float*, float*,
-                                       const float*, float*, const Workspace&, hipStream_t, bool);
+                                       const float*, float*, const Workspace&, hipStream_t, bool, hipEvent_t,
+                                       hipEvent_t);
 template void launch_apply_march2<double>(int, const TileShape&, const double*, const double*, double*, hipStream_t);
 template void launch_apply_march2<float>(int, const TileShape&, const float*, const float*, float*, hipStream_t);
 
