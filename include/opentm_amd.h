@@ -107,8 +107,12 @@ typedef struct {
                                kernels; 3: z-march with one node per thread (same
                                arithmetic, kept as cross-checks); 4: fused PCG
                                iteration, one z-march pass and one reduction per
-                               iteration (even n only, else OTM_EINVAL).  All give
-                               Jacobi-PCG iterates that agree in exact arithmetic. */
+                               iteration (even n only, else OTM_EINVAL); 5: as 4,
+                               with the passes of a check interval chained (each
+                               block reduces its predecessor's sums itself; same
+                               sums in the same order, so the iterates equal 4's).
+                               All give Jacobi-PCG iterates that agree in exact
+                               arithmetic. */
     int32_t tile_tz;        /* planes per z-march of the operator kernel; 0 = automatic */
     int32_t tile_tx;        /* tile width in x in nodes: 16, 32 or 64 (32 or 64 for the
                                two-node kernel); 0 = automatic */
@@ -251,7 +255,8 @@ int otm_time_apply_device(int32_t n, int32_t precision, int32_t variant, int32_t
                           double* us_per_launch);
 
 /* Operator kernel in use: [variant (0 pair z-march, 1 gather, 2 ring, 3 z-march,
- * 4 fused PCG iteration), tile width, planes per march, blocks per launch]. */
+ * 4 fused PCG iteration, 5 fused with chained passes), tile width, planes per
+ * march, blocks per launch]. */
 int otm_get_tile(const otm_ctx* ctx, int32_t tile4[4]);
 
 /* Live timing of the solver's dominant kernel (the fused pass, or the

@@ -46,6 +46,54 @@ __device__ __forceinline__ void block_partials(double (&v)[NV], double* partials
     block_partials_at<NV>(v, partials, blockIdx.x);
 }
 
+// Value-major variant: value i of slot b at partials[i * kMaxBlocks + b], so
+// the one-block sum below reads each value with coalesced loads.
+template <int NV>
+__device__ __forceinline__ void block_partials_vm(double (&v)[NV], double* partials, int slot) {
+    __shared__ double sh[NV][kBlock / 64];
+    const int tid = threadIdx.x;
+    const int lane = tid & 63, w = tid >> 6;
+    wave_reduce<NV>(v);
+    if (lane == 0) {
+#pragma unroll
+        for (int i = 0; i < NV; ++i) sh[i][w] = v[i];
+    }
+    __syncthreads();
+    if (tid < NV) {
+        double s = 0.0;
+#pragma unroll
+        for (int j = 0; j < kBlock / 64; ++j) s += sh[tid][j];
+        partials[(size_t)tid * kMaxBlocks + slot] = s;
+    }
+    __syncthreads();
+}
+
+template <int NV>
+__device__ __forceinline__ void final_sums_vm(const double* partials, int nblocks, double* out /* shared */) {
+    double v[NV];
+#pragma unroll
+    for (int i = 0; i < NV; ++i) v[i] = 0.0;
+    for (int b = threadIdx.x; b < nblocks; b += blockDim.x) {
+#pragma unroll
+        for (int i = 0; i < NV; ++i) v[i] += partials[(size_t)i * kMaxBlocks + b];
+    }
+    __shared__ double sh[NV][kBlock / 64];
+    wave_reduce<NV>(v);
+    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+    if (lane == 0) {
+#pragma unroll
+        for (int i = 0; i < NV; ++i) sh[i][w] = v[i];
+    }
+    __syncthreads();
+    if (threadIdx.x < NV) {
+        double s = 0.0;
+#pragma unroll
+        for (int j = 0; j < kBlock / 64; ++j) s += sh[threadIdx.x][j];
+        out[threadIdx.x] = s;
+    }
+    __syncthreads();
+}
+
 // Sum the partial arrays of all blocks (fixed order) -> out[NV] in shared memory.
 template <int NV>
 __device__ __forceinline__ void final_sums(const double* partials, int nblocks, double* out /* shared */) {
@@ -97,6 +145,55 @@ __device__ __forceinline__ int xcd_tile(int bid, int nb) {
     const int q = nb / kXcds, r = nb % kXcds;
     const int x = bid % kXcds, k = bid / kXcds;
     return (x < r ? x * (q + 1) : r * (q + 1) + (x - r) * q) + k;
+}
+
+// Bookkeeping of the fused iteration after a pass.  in: the state the pass
+// ran with; tot: its reduced sums, per load [l] p.q, [3+l] q.z, [6+l] q.D^-1 q,
+// [9+l] r.z, [12+l] r.r.  out: the state of the next pass.  alpha = r.z / p.q;
+// beta = (next r.z) / r.z with the next r.z expanded as
+// r.z - 2 alpha q.z + alpha^2 q.D^-1 q.  A load whose r.r meets tol^2 b.b stops.
+__device__ inline void fused_advance(const FusedState& in, const double* tot, FusedState& out) {
+    out = in;
+    for (int l = 0; l < 3; ++l) {
+        if (!in.active[l]) {
+            out.alpha[l] = 0.0;
+            out.beta[l] = 0.0;
+            continue;
+        }
+        if (in.alpha[l] != 0.0) out.iters[l] += 1;
+        const double rr = tot[12 + l];
+        out.rr[l] = rr;
+        if (!(rr > in.tol2 * in.bb[l])) {
+            out.active[l] = 0;
+            out.alpha[l] = 0.0;
+            out.beta[l] = 0.0;
+            continue;
+        }
+        const double pq = tot[l], qz = tot[3 + l], qdq = tot[6 + l], rz = tot[9 + l];
+        const double a = (pq > 0.0) ? rz / pq : 0.0;
+        const double rz_next = rz - 2.0 * a * qz + a * a * qdq;
+        out.rz[l] = rz;
+        out.pq[l] = pq;
+        out.qdq[l] = qdq;
+        out.alpha[l] = a;
+        out.beta[l] = (rz > 0.0 && rz_next > 0.0) ? rz_next / rz : 0.0;
+    }
+}
+
+// The fused state held in the scalar block (after a residual or a finalize).
+__device__ inline void fused_state_of(const Scalars* sc, FusedState& s) {
+    for (int l = 0; l < 3; ++l) {
+        s.alpha[l] = sc->alpha[l];
+        s.beta[l] = sc->beta[l];
+        s.rz[l] = sc->rz[l];
+        s.pq[l] = sc->pq[l];
+        s.qdq[l] = sc->qdq[l];
+        s.rr[l] = sc->rr[l];
+        s.bb[l] = sc->bb[l];
+        s.active[l] = sc->active[l];
+        s.iters[l] = sc->iters[l];
+    }
+    s.tol2 = sc->tol2;
 }
 
 static inline int nblocks_for(int64_t count) { return (int)((count + kBlock - 1) / kBlock); }

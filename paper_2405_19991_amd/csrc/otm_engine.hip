@@ -73,6 +73,7 @@ struct otm_ctx {
     TileShape tile2;  // pair kernel (even n)
     bool use_pair = false;
     bool use_fused = false;  // one pass per PCG iteration (otm_fused.hip)
+    bool fused_chain = false;  // passes within a check interval reduce their predecessor's sums
     double tune_us = 0.0;  // autotuned time of one PCG iteration's passes
     otm_nn* net = nullptr;
     int learned_used = 0;  // last solve started from the network's prediction
@@ -289,8 +290,14 @@ int solve_fused(otm_ctx* c, bool x_zero, bool mixed, const FusedBufs<T>& B, otm_
             const int nx = cur ^ 1;
             // sample the chunk's last pass when every load takes a full step
             const bool sample = all && launches > 0 && it == c->so.check_every - 1;
+            // chained: passes after the first of a chunk reduce their
+            // predecessor's sums themselves and the chunk's last pass is closed
+            // by a finalize; else a finalize follows every pass
+            const bool chained = c->fused_chain && it > 0;
+            const bool fin = !c->fused_chain || it == c->so.check_every - 1;
             launch_fused<T>(n, c->tile2, all, B.r[cur], B.q[cur], B.p[cur], B.r[nx], B.q[nx], B.p[nx], B.x, B.dinv,
-                            B.k, w, c->stream, true, sample ? c->pev[0] : nullptr, sample ? c->pev[1] : nullptr);
+                            B.k, w, c->stream, cur, chained, fin, sample ? c->pev[0] : nullptr,
+                            sample ? c->pev[1] : nullptr);
             sampled = sampled || sample;
             cur = nx;
             ++launches;
@@ -635,7 +642,7 @@ int free_all(otm_ctx* c) {
 // vector update, over tile widths and march lengths.  Results are cached per
 // process.
 struct TuneChoice {
-    bool pair, fused;
+    bool pair, fused, chain;
     int tx, tz;
     double us;  // one PCG iteration (passes and finalizes)
 };
@@ -659,6 +666,7 @@ double time_us(otm_ctx* c, F run, int reps) {
 void apply_choice(otm_ctx* c, const TuneChoice& ch) {
     c->use_pair = ch.pair;
     c->use_fused = ch.fused;
+    c->fused_chain = ch.chain;
     if (ch.pair)
         c->tile2 = choose_tile2(c->n, c->max_blocks, ch.tz, ch.tx);
     else
@@ -687,35 +695,42 @@ int tune_precision(otm_ctx* c, T* r, T* rb, T* q, T* qb, T* p0, T* p1, T* x, T* 
     const int reps = c->nn >= (1 << 20) ? 6 : 12;
     const int tzs[] = {4, 8, 16, 32};
     int rc;
-    best = TuneChoice{false, false, 32, 8, 1e30};
-    // fused candidates first (finalize timed apart: it would retire the loads)
+    best = TuneChoice{false, false, false, 32, 8, 1e30};
+    // fused candidates: a finalize after every pass, or chains of passes that
+    // reduce their predecessor's sums (closing finalize amortized over the
+    // check interval)
     double fin_us = 0.0, upd_us = 0.0;
     if ((rc = upload_timing_scalars(c))) return rc;
     if (rb && qb) {
-        for (int tx : {32, 64})
-            for (int tz : tzs) {
-                if (tz > n) continue;
-                const TileShape t = choose_tile2(n, c->max_blocks, tz, tx);
-                if (t.tz != tz || t.blocks > c->max_blocks) continue;
-                int par = 0;
-                const double us = time_us(
-                    c,
-                    [&]() {
-                        T* ri = par ? rb : r;
-                        T* ro = par ? r : rb;
-                        T* qi = par ? qb : q;
-                        T* qo = par ? q : qb;
-                        T* pi = par ? p1 : p0;
-                        T* po = par ? p0 : p1;
-                        launch_fused<T>(n, t, true, ri, qi, pi, ro, qo, po, x, dinv, k, w, c->stream, false);
-                        par ^= 1;
-                    },
-                    reps);
-                if (us < best.us) best = TuneChoice{true, true, tx, tz, us};
-            }
+        fin_us = time_us(c, [&]() { launch_finalize(FIN_PQ, 512, w, c->stream); }, reps);
+        if ((rc = upload_timing_scalars(c))) return rc;
+        for (int chain = 0; chain < 2; ++chain)
+            for (int tx : {32, 64})
+                for (int tz : tzs) {
+                    if (tz > n) continue;
+                    const TileShape t = choose_tile2(n, c->max_blocks, tz, tx);
+                    if (t.tz != tz || t.blocks > c->max_blocks) continue;
+                    int par = 0, calls = 0;
+                    double us = time_us(
+                        c,
+                        [&]() {
+                            T* ri = par ? rb : r;
+                            T* ro = par ? r : rb;
+                            T* qi = par ? qb : q;
+                            T* qo = par ? q : qb;
+                            T* pi = par ? p1 : p0;
+                            T* po = par ? p0 : p1;
+                            launch_fused<T>(n, t, true, ri, qi, pi, ro, qo, po, x, dinv, k, w, c->stream, par,
+                                            chain && calls > 0, !chain);
+                            par ^= 1;
+                            ++calls;
+                        },
+                        reps);
+                    if (chain) us += fin_us / c->so.check_every;
+                    if (us < best.us) best = TuneChoice{true, true, chain != 0, tx, tz, us};
+                    if ((rc = upload_timing_scalars(c))) return rc;
+                }
         upd_us = time_us(c, [&]() { launch_update_vec<T>(n, x, r, p0, q, dinv, w, c->stream, false); }, reps);
-        fin_us = time_us(c, [&]() { launch_finalize(FIN_F_PASS, 512, w, c->stream); }, reps);
-        best.us += fin_us;
         if ((rc = upload_timing_scalars(c))) return rc;
     }
     // direction+operator pass (its finalize included) + update + finalize
@@ -742,7 +757,7 @@ int tune_precision(otm_ctx* c, T* r, T* rb, T* q, T* qb, T* p0, T* p1, T* x, T* 
                               },
                               reps) +
                           upd_us + fin_us;
-        if (us < best.us) best = TuneChoice{pair, false, tx, tz, us};
+        if (us < best.us) best = TuneChoice{pair, false, false, tx, tz, us};
     }
     return check_launch(c, "autotune");
 }
@@ -768,8 +783,17 @@ int autotune(otm_ctx* c) {
                     mixed ? (void*)c->x32 : nullptr};
     for (void* v : vecs)
         if (v) HIPCHK(c, hipMemsetAsync(v, 0, v3, c->stream));
-    HIPCHK(c, hipMemsetAsync(mixed ? (void*)c->k32 : (void*)c->k, 0, v1, c->stream));
-    HIPCHK(c, hipMemsetAsync(mixed ? (void*)c->dinv32 : (void*)c->dinv, 0, v1, c->stream));
+    // a residual of hashed values, unit conductivities and a constant diagonal:
+    // the timed passes are genuine iterations (non-zero steps, all loads active)
+    if (mixed) {
+        launch_fill_hash<float>(c->r32, 3 * c->nn, 12345u, c->stream);
+        launch_fill_const<float>(c->k32, c->nn, 1.0f, c->stream);
+        launch_fill_const<float>(c->dinv32, c->nn, 0.375f, c->stream);
+    } else {
+        launch_fill_hash<double>(c->r64, 3 * c->nn, 12345u, c->stream);
+        launch_fill_const<double>(c->k, c->nn, 1.0, c->stream);
+        launch_fill_const<double>(c->dinv, c->nn, 0.375, c->stream);
+    }
     // FP64 timing updates a scratch x: the solution buffer is restored below
     TuneChoice best;
     int rc;
@@ -861,7 +885,7 @@ int otm_create(const otm_problem* problem, const otm_solver_opts* solver, const 
     if (!(c->so.tol > 0.0 && c->so.max_iter > 0 && c->so.check_every >= 1 && c->so.reliable_delta > 0.0 &&
           c->so.reliable_delta < 1.0 && (c->so.precision == OTM_FP64 || c->so.precision == OTM_MIXED) &&
           c->so.guess >= OTM_GUESS_ZERO && c->so.guess <= OTM_GUESS_LEARNED &&
-          c->so.kernel_variant >= 0 && c->so.kernel_variant <= 4 && c->so.tile_tz >= 0 &&
+          c->so.kernel_variant >= 0 && c->so.kernel_variant <= 5 && c->so.tile_tz >= 0 &&
           (c->so.tile_tx == 0 || c->so.tile_tx == 16 || c->so.tile_tx == 32 || c->so.tile_tx == 64))) {
         delete c;
         return OTM_EINVAL;
@@ -893,18 +917,19 @@ int otm_create(const otm_problem* problem, const otm_solver_opts* solver, const 
         c->own_stream = true;
     }
     const int64_t nn = c->nn;
-    c->max_blocks = 4096;
+    c->max_blocks = kMaxBlocks;
     c->tile = choose_tile(c->n, c->max_blocks, c->so.tile_tz, c->so.tile_tx);
     c->tile2 = choose_tile2(c->n, c->max_blocks, c->so.tile_tz, c->so.tile_tx);
-    c->use_pair = (c->so.kernel_variant == 0 || c->so.kernel_variant == 4) && (c->n % 2 == 0);
-    c->use_fused = (c->so.kernel_variant == 4);
+    c->use_pair = (c->so.kernel_variant == 0 || c->so.kernel_variant >= 4) && (c->n % 2 == 0);
+    c->use_fused = (c->so.kernel_variant >= 4);
+    c->fused_chain = (c->so.kernel_variant == 5);
     if (c->use_fused && c->n % 2 != 0) {
         if (c->own_stream) (void)hipStreamDestroy(c->stream);
         delete c;
         return OTM_EINVAL;
     }
     // the fused iteration needs second r, q buffers (automatic choice or forced)
-    const bool fused_bufs = c->use_pair && (c->so.kernel_variant == 4 || (c->so.kernel_variant == 0 && c->so.autotune &&
+    const bool fused_bufs = c->use_pair && (c->so.kernel_variant >= 4 || (c->so.kernel_variant == 0 && c->so.autotune &&
                                                                         c->so.tile_tx == 0 && c->so.tile_tz == 0));
     rc = OTM_OK;
     rc = rc ? rc : dalloc(c, &c->rho, nn);
@@ -1342,7 +1367,8 @@ int otm_pass_timing(otm_ctx* c, int32_t reset, double out4[4]) {
 int otm_get_tile(const otm_ctx* c, int32_t tile4[4]) {
     if (!c || !tile4) return OTM_EINVAL;
     const TileShape& t = c->use_pair ? c->tile2 : c->tile;
-    tile4[0] = c->use_fused ? 4 : (c->so.kernel_variant == 0 ? (c->use_pair ? 0 : 3) : c->so.kernel_variant);
+    tile4[0] = c->use_fused ? (c->fused_chain ? 5 : 4)
+                            : (c->so.kernel_variant == 0 ? (c->use_pair ? 0 : 3) : c->so.kernel_variant);
     tile4[1] = t.tx;
     tile4[2] = t.tz;
     tile4[3] = t.blocks;

@@ -42,12 +42,18 @@ struct PreF {
 // [9+l] r.z, [12+l] r.r (r, z of the updated residual).
 constexpr int kFusedSums = 15;
 
-template <typename T, int WX, int TY, bool ALL>
+// Partial sums of a pass: value-major, one buffer per pass parity.
+constexpr int64_t kFusedStride = (int64_t)kFusedSums * kMaxBlocks;
+
+// CHAIN: the block first reduces the previous pass's partial sums (parity
+// par ^ 1) and advances the state itself; else it takes the state from the
+// scalar block.  Block 0 records the state it ran with as fs[par].
+template <typename T, int WX, int TY, bool ALL, bool CHAIN>
 __device__ __forceinline__ void fused_body(int n, int tz, int ntx, int nty, const T* __restrict__ r_in,
                                            const T* __restrict__ q_in, const T* __restrict__ p_in,
                                            T* __restrict__ r_out, T* __restrict__ q_out, T* __restrict__ p_out,
                                            T* __restrict__ x, const T* __restrict__ dinv, const T* __restrict__ k,
-                                           double* __restrict__ partials, const Scalars* __restrict__ sc) {
+                                           double* __restrict__ partials, Scalars* __restrict__ sc, int par) {
     typedef typename FV2<T>::type T2;
     static_assert(WX * TY == kBlock, "block size");
     constexpr int TX = 2 * WX;
@@ -73,16 +79,19 @@ __device__ __forceinline__ void fused_body(int n, int tz, int ntx, int nty, cons
     const int64_t nn = (int64_t)n * n * n;
     const int64_t n2 = (int64_t)n * n;
 
-    // per-load uniforms: activity, step a (alpha), direction weight b (beta)
+    // per-load uniforms: activity, step a (alpha), direction weight b (beta);
+    // a chained pass with every load active prefetches its first planes with
+    // every field before its state is known (fields it then does not need
+    // are simply not used)
     bool act[3], ua[3], up[3];
     T al[3], be[3];
 #pragma unroll
     for (int l = 0; l < 3; ++l) {
-        act[l] = ALL ? true : (sc->active[l] != 0);
-        al[l] = (T)sc->alpha[l];
-        be[l] = (T)sc->beta[l];
-        ua[l] = act[l] && al[l] != (T)0;
-        up[l] = ua[l] || (act[l] && be[l] != (T)0);
+        act[l] = true;
+        ua[l] = true;
+        up[l] = true;
+        al[l] = (T)0;
+        be[l] = (T)0;
     }
     const int i = i0 + 2 * tx, j = j0 + ty;
     const bool own = (i < n) && (j < n);  // n even: i < n implies i + 1 < n
@@ -292,9 +301,44 @@ __device__ __forceinline__ void fused_body(int n, int tz, int ntx, int nty, cons
         kpc2 = kc2;
     };
 
+    __shared__ FusedState st_sh;
+    __shared__ double tot[kFusedSums];
+    auto take_state = [&]() {
+        if (CHAIN) {
+            final_sums_vm<kFusedSums>(partials + (par ^ 1) * kFusedStride, gridDim.x, tot);
+            if (tid == 0) {
+                FusedState s;
+                fused_advance(sc->fs[par ^ 1], tot, s);
+                st_sh = s;
+                if (blockIdx.x == 0) sc->fs[par] = s;
+            }
+        } else if (tid == 0) {
+            FusedState s;
+            fused_state_of(sc, s);
+            st_sh = s;
+            if (blockIdx.x == 0) sc->fs[par] = s;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int l = 0; l < 3; ++l) {
+            act[l] = ALL ? true : (st_sh.active[l] != 0);
+            al[l] = (T)st_sh.alpha[l];
+            be[l] = (T)st_sh.beta[l];
+            ua[l] = act[l] && al[l] != (T)0;
+            up[l] = ua[l] || (act[l] && be[l] != (T)0);
+        }
+    };
+
     PreF<T> fa, fb;
-    load_plane(z0 - 1, fa);
-    load_plane(z0, fb);
+    if (ALL && CHAIN) {
+        load_plane(z0 - 1, fa);
+        load_plane(z0, fb);
+        take_state();
+    } else {
+        take_state();
+        load_plane(z0 - 1, fa);
+        load_plane(z0, fb);
+    }
     int P = z0 - 1;
     for (; P + 1 <= z1; P += 2) {
         store_plane(P, fa);
@@ -314,72 +358,140 @@ __device__ __forceinline__ void fused_body(int n, int tz, int ntx, int nty, cons
     double accd[kFusedSums];
 #pragma unroll
     for (int q = 0; q < kFusedSums; ++q) accd[q] = (double)acc[q];
-    block_partials_at<kFusedSums>(accd, partials, blockIdx.x);
+    block_partials_vm<kFusedSums>(accd, partials + par * kFusedStride, blockIdx.x);
+}
+
+// Closes a chain of passes: reduces the last pass's partial sums, advances the
+// state and writes it to the scalar block (host-visible).
+__global__ void __launch_bounds__(kBlock) k_fused_fin(int nblocks, const double* __restrict__ partials,
+                                                      Scalars* __restrict__ sc, int par) {
+    __shared__ double tot[kFusedSums];
+    final_sums_vm<kFusedSums>(partials + par * kFusedStride, nblocks, tot);
+    if (threadIdx.x != 0) return;
+    FusedState s;
+    fused_advance(sc->fs[par], tot, s);
+    for (int l = 0; l < 3; ++l) {
+        sc->alpha[l] = s.alpha[l];
+        sc->beta[l] = s.beta[l];
+        sc->rz[l] = s.rz[l];
+        sc->pq[l] = s.pq[l];
+        sc->qdq[l] = s.qdq[l];
+        sc->rr[l] = s.rr[l];
+        sc->active[l] = s.active[l];
+        sc->iters[l] = s.iters[l];
+    }
 }
 
 // float32: two waves per SIMD (two blocks per CU) must fit, i.e. at most 256
 // registers per lane; float64 state does not fit that and runs one wave per SIMD.
-template <int WX, int TY, bool ALL>
+template <int WX, int TY, bool ALL, bool CHAIN>
 __global__ void __launch_bounds__(WX* TY) __attribute__((amdgpu_waves_per_eu(2)))
     k_fused_f32(int n, int tz, int ntx, int nty, const float* __restrict__ r_in, const float* __restrict__ q_in,
                 const float* __restrict__ p_in, float* __restrict__ r_out, float* __restrict__ q_out,
                 float* __restrict__ p_out, float* __restrict__ x, const float* __restrict__ dinv,
-                const float* __restrict__ k, double* __restrict__ partials, const Scalars* __restrict__ sc) {
-    fused_body<float, WX, TY, ALL>(n, tz, ntx, nty, r_in, q_in, p_in, r_out, q_out, p_out, x, dinv, k, partials, sc);
+                const float* __restrict__ k, double* __restrict__ partials, Scalars* __restrict__ sc, int par) {
+    fused_body<float, WX, TY, ALL, CHAIN>(n, tz, ntx, nty, r_in, q_in, p_in, r_out, q_out, p_out, x, dinv, k,
+                                          partials, sc, par);
 }
 
-template <int WX, int TY, bool ALL>
+template <int WX, int TY, bool ALL, bool CHAIN>
 __global__ void __launch_bounds__(WX* TY)
     k_fused_f64(int n, int tz, int ntx, int nty, const double* __restrict__ r_in, const double* __restrict__ q_in,
                 const double* __restrict__ p_in, double* __restrict__ r_out, double* __restrict__ q_out,
                 double* __restrict__ p_out, double* __restrict__ x, const double* __restrict__ dinv,
-                const double* __restrict__ k, double* __restrict__ partials, const Scalars* __restrict__ sc) {
-    fused_body<double, WX, TY, ALL>(n, tz, ntx, nty, r_in, q_in, p_in, r_out, q_out, p_out, x, dinv, k, partials,
-                                    sc);
+                const double* __restrict__ k, double* __restrict__ partials, Scalars* __restrict__ sc, int par) {
+    fused_body<double, WX, TY, ALL, CHAIN>(n, tz, ntx, nty, r_in, q_in, p_in, r_out, q_out, p_out, x, dinv, k,
+                                           partials, sc, par);
 }
 
-template <typename T, int WX, int TY, bool ALL>
+template <typename T, int WX, int TY, bool ALL, bool CHAIN>
 struct FusedKernel;
-template <int WX, int TY, bool ALL>
-struct FusedKernel<float, WX, TY, ALL> {
-    static constexpr auto fn = k_fused_f32<WX, TY, ALL>;
+template <int WX, int TY, bool ALL, bool CHAIN>
+struct FusedKernel<float, WX, TY, ALL, CHAIN> {
+    static constexpr auto fn = k_fused_f32<WX, TY, ALL, CHAIN>;
 };
-template <int WX, int TY, bool ALL>
-struct FusedKernel<double, WX, TY, ALL> {
-    static constexpr auto fn = k_fused_f64<WX, TY, ALL>;
+template <int WX, int TY, bool ALL, bool CHAIN>
+struct FusedKernel<double, WX, TY, ALL, CHAIN> {
+    static constexpr auto fn = k_fused_f64<WX, TY, ALL, CHAIN>;
 };
 
 // ev0/ev1 (optional): HIP events recorded at the kernel's start and end.
-template <typename T, bool ALL>
+template <typename T, bool ALL, bool CHAIN>
 static void launch_f(int n, const TileShape& t, const T* r_in, const T* q_in, const T* p_in, T* r_out, T* q_out,
-                     T* p_out, T* x, const T* dinv, const T* k, double* partials, const Scalars* sc, hipStream_t s,
+                     T* p_out, T* x, const T* dinv, const T* k, double* partials, Scalars* sc, int par, hipStream_t s,
                      hipEvent_t ev0, hipEvent_t ev1) {
     const int ntx = (n + t.tx - 1) / t.tx, nty = (n + t.ty - 1) / t.ty;
     if (t.tx == 32)
-        hipExtLaunchKernelGGL((FusedKernel<T, 16, 16, ALL>::fn), dim3(t.blocks), dim3(kBlock), 0, s, ev0, ev1, 0, n,
-                              t.tz, ntx, nty, r_in, q_in, p_in, r_out, q_out, p_out, x, dinv, k, partials, sc);
+        hipExtLaunchKernelGGL((FusedKernel<T, 16, 16, ALL, CHAIN>::fn), dim3(t.blocks), dim3(kBlock), 0, s, ev0, ev1,
+                              0, n, t.tz, ntx, nty, r_in, q_in, p_in, r_out, q_out, p_out, x, dinv, k, partials, sc,
+                              par);
     else
-        hipExtLaunchKernelGGL((FusedKernel<T, 32, 8, ALL>::fn), dim3(t.blocks), dim3(kBlock), 0, s, ev0, ev1, 0, n,
-                              t.tz, ntx, nty, r_in, q_in, p_in, r_out, q_out, p_out, x, dinv, k, partials, sc);
+        hipExtLaunchKernelGGL((FusedKernel<T, 32, 8, ALL, CHAIN>::fn), dim3(t.blocks), dim3(kBlock), 0, s, ev0, ev1, 0,
+                              n, t.tz, ntx, nty, r_in, q_in, p_in, r_out, q_out, p_out, x, dinv, k, partials, sc, par);
 }
 
 template <typename T>
 void launch_fused(int n, const TileShape& t, bool all_active, const T* r_in, const T* q_in, const T* p_in, T* r_out,
-                  T* q_out, T* p_out, T* x, const T* dinv, const T* k, const Workspace& ws, hipStream_t s, bool fin,
-                  hipEvent_t ev0, hipEvent_t ev1) {
-    if (all_active)
-        launch_f<T, true>(n, t, r_in, q_in, p_in, r_out, q_out, p_out, x, dinv, k, ws.partials, ws.sc, s, ev0, ev1);
-    else
-        launch_f<T, false>(n, t, r_in, q_in, p_in, r_out, q_out, p_out, x, dinv, k, ws.partials, ws.sc, s, ev0, ev1);
-    if (fin) launch_finalize(FIN_F_PASS, t.blocks, ws, s);
+                  T* q_out, T* p_out, T* x, const T* dinv, const T* k, const Workspace& ws, hipStream_t s, int par,
+                  bool chained, bool fin, hipEvent_t ev0, hipEvent_t ev1) {
+    if (all_active) {
+        if (chained)
+            launch_f<T, true, true>(n, t, r_in, q_in, p_in, r_out, q_out, p_out, x, dinv, k, ws.partials, ws.sc, par,
+                                    s, ev0, ev1);
+        else
+            launch_f<T, true, false>(n, t, r_in, q_in, p_in, r_out, q_out, p_out, x, dinv, k, ws.partials, ws.sc, par,
+                                     s, ev0, ev1);
+    } else {
+        if (chained)
+            launch_f<T, false, true>(n, t, r_in, q_in, p_in, r_out, q_out, p_out, x, dinv, k, ws.partials, ws.sc, par,
+                                     s, ev0, ev1);
+        else
+            launch_f<T, false, false>(n, t, r_in, q_in, p_in, r_out, q_out, p_out, x, dinv, k, ws.partials, ws.sc,
+                                      par, s, ev0, ev1);
+    }
+    if (fin) hipLaunchKernelGGL(k_fused_fin, dim3(1), dim3(kBlock), 0, s, t.blocks, ws.partials, ws.sc, par);
 }
 
 template void launch_fused<float>(int, const TileShape&, bool, const float*, const float*, const float*, float*,
                                   float*, float*, float*, const float*, const float*, const Workspace&, hipStream_t,
-                                  bool, hipEvent_t, hipEvent_t);
+                                  int, bool, bool, hipEvent_t, hipEvent_t);
 template void launch_fused<double>(int, const TileShape&, bool, const double*, const double*, const double*, double*,
                                    double*, double*, double*, const double*, const double*, const Workspace&,
-                                   hipStream_t, bool, hipEvent_t, hipEvent_t);
+                                   hipStream_t, int, bool, bool, hipEvent_t, hipEvent_t);
+
+// Deterministic fills for timing inputs: a 32-bit integer hash of the index
+// mapped to [-0.5, 0.5), and a constant.
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_fill_hash(T* __restrict__ p, int64_t count, uint32_t seed) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i >= count) return;
+    uint32_t h = (uint32_t)i * 2654435761u ^ seed;
+    h ^= h >> 16;
+    h *= 2246822519u;
+    h ^= h >> 13;
+    h *= 3266489917u;
+    h ^= h >> 16;
+    p[i] = (T)((double)h * (1.0 / 4294967296.0) - 0.5);
+}
+
+template <typename T>
+__global__ void __launch_bounds__(kBlock) k_fill_const(T* __restrict__ p, int64_t count, T v) {
+    const int64_t i = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (i < count) p[i] = v;
+}
+
+template <typename T>
+void launch_fill_hash(T* p, int64_t count, uint32_t seed, hipStream_t s) {
+    hipLaunchKernelGGL(k_fill_hash<T>, dim3(nblocks_for(count)), dim3(kBlock), 0, s, p, count, seed);
+}
+template <typename T>
+void launch_fill_const(T* p, int64_t count, T v, hipStream_t s) {
+    hipLaunchKernelGGL(k_fill_const<T>, dim3(nblocks_for(count)), dim3(kBlock), 0, s, p, count, v);
+}
+template void launch_fill_hash<float>(float*, int64_t, uint32_t, hipStream_t);
+template void launch_fill_hash<double>(double*, int64_t, uint32_t, hipStream_t);
+template void launch_fill_const<float>(float*, int64_t, float, hipStream_t);
+template void launch_fill_const<double>(double*, int64_t, double, hipStream_t);
 
 // r = b - A x with the float64 operator, stored as TR, with the sums the fused
 // iteration restarts from: per load [l] r.r (float64 r), [3+l] r.D^-1 r and

@@ -9,8 +9,22 @@ namespace otm {
 
 constexpr int kBlock = 256;          // threads per block for node/element sweeps
 constexpr int kMaxReduce = 32;       // widest multi-value block reduction
+constexpr int kMaxBlocks = 4096;     // producer blocks per reduction (workspace rows)
 constexpr int kOcLevels = 5;         // bisection levels resolved per OC pass
 constexpr int kOcCands = (1 << kOcLevels) - 1;
+
+// State of the fused PCG iteration between passes (per load): the step and
+// direction weight a pass used, the last reduced dots, and the constants the
+// convergence test needs.  Two copies, by pass parity, live in Scalars: a pass
+// reads its predecessor's copy and writes its own.
+struct FusedState {
+    double alpha[3], beta[3];
+    double rz[3], pq[3], qdq[3], rr[3];
+    double bb[3];
+    double tol2;
+    int32_t active[3];
+    int32_t iters[3];
+};
 
 // Device-resident scalars of the solver and the OC search.  One instance per
 // context, written only by "last block" epilogues or by host copies between
@@ -44,6 +58,7 @@ struct Scalars {
     int32_t oc_done;
     double cand[kOcCands];    // lambda candidates of the current pass (bisection tree, BFS order)
     double cpow[kOcCands];    // candidate^-eta
+    FusedState fs[2];         // fused iteration, by pass parity
 };
 
 // Separable periodic hat-filter weights (1-D, normalized), reach R <= 4.
@@ -102,7 +117,6 @@ enum FinOp {
     FIN_OC,
     FIN_F_START,    // fused iteration: residual at the start of a solve
     FIN_F_REFRESH,  // fused iteration: float64 residual replaces the recursive one
-    FIN_F_PASS,     // fused iteration: after each pass
     FIN_GUESS       // scale factors of a start guess
 };
 void launch_finalize(int op, int nblocks, const Workspace& ws, hipStream_t s, int64_t nn = 0, double eta = 0.5);
@@ -170,11 +184,20 @@ template <typename T>
 void launch_apply_march2(int n, const TileShape& t, const T* k, const T* x, T* y, hipStream_t s);
 // Fused single-pass PCG iteration (otm_fused.hip): even n, pair tiles of
 // choose_tile2.  r, q, p are read from *_in and written to *_out (ping-pong);
-// x is updated in place.  fin = false skips the finalize (timing only).
+// x is updated in place.  par: parity of the pass (its partial sums and state
+// copy).  chained = false: the pass takes its step from the device scalars
+// (after a residual or a finalize); chained = true: every block first reduces
+// the previous pass's partial sums itself (same fixed order in every block).
+// fin: close the chain with a finalize that writes the device scalars.
 template <typename T>
 void launch_fused(int n, const TileShape& t, bool all_active, const T* r_in, const T* q_in, const T* p_in, T* r_out,
-                  T* q_out, T* p_out, T* x, const T* dinv, const T* k, const Workspace& ws, hipStream_t s,
-                  bool fin = true, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+                  T* q_out, T* p_out, T* x, const T* dinv, const T* k, const Workspace& ws, hipStream_t s, int par,
+                  bool chained, bool fin, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+// Deterministic pseudo-random fill in [-0.5, 0.5) (timing inputs), and a constant fill.
+template <typename T>
+void launch_fill_hash(T* p, int64_t count, uint32_t seed, hipStream_t s);
+template <typename T>
+void launch_fill_const(T* p, int64_t count, T v, hipStream_t s);
 // r = b - A x (float64 operator) for the fused iteration; start: begin a solve
 // (q unused, may be null), else refresh the recursive residual keeping the
 // pending step (q = the last pass's A p).

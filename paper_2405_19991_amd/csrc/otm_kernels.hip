@@ -518,7 +518,6 @@ __device__ __forceinline__ void b_finalize(int op, int nblocks, const double* __
         case FIN_OC: fin_sums<kOcCands>(partials, nblocks, tot); break;
         case FIN_F_START:
         case FIN_F_REFRESH: fin_sums<12>(partials, nblocks, tot); break;
-        case FIN_F_PASS: fin_sums<15>(partials, nblocks, tot); break;
         case FIN_GUESS: fin_sums<6>(partials, nblocks, tot); break;
         default: return;
     }
@@ -610,24 +609,6 @@ __device__ __forceinline__ void b_finalize(int op, int nblocks, const double* __
             for (int l = 0; l < 3; ++l) {
                 const double bx = tot[l], xax = tot[3 + l];
                 sc->gscale[l] = (bx > 0.0 && xax > 0.0) ? bx / xax : 0.0;
-            }
-            break;
-        case FIN_F_PASS:
-            // sums: [l] p.q, [3+l] q.z, [6+l] q.D^-1 q, [9+l] r.z, [12+l] r.r
-            for (int l = 0; l < 3; ++l) {
-                if (!sc->active[l]) continue;
-                if (sc->alpha[l] != 0.0) sc->iters[l] += 1;
-                const double rr = tot[12 + l];
-                sc->rr[l] = rr;
-                if (!(rr > sc->tol2 * sc->bb[l])) {
-                    sc->active[l] = 0;
-                    sc->alpha[l] = 0.0;
-                    sc->beta[l] = 0.0;
-                    continue;
-                }
-                sc->pq[l] = tot[l];
-                sc->qdq[l] = tot[6 + l];
-                fused_step(sc, l, tot[9 + l], tot[3 + l]);
             }
             break;
         case FIN_OC: {
@@ -988,7 +969,6 @@ static int fin_width(int op) {
         case FIN_OC: return kOcCands;
         case FIN_F_START:
         case FIN_F_REFRESH: return 12;
-        case FIN_F_PASS: return 15;
         case FIN_GUESS: return 6;
         default: return 3;
     }

@@ -12,6 +12,8 @@
 // prefetch alternates between two register sets without copies.
 #include <hip/hip_ext.h>
 
+#include <type_traits>
+
 #include "otm_device.h"
 
 namespace otm {
@@ -307,6 +309,16 @@ __global__ void __launch_bounds__(WX* TY) k_march2(int n, int tz, int ntx, int n
                                      p_new, k, q, partials, sc);
 }
 
+// Stand-alone float32 operator (no direction, no dots): its register state
+// fits three waves per SIMD (float64 would spill there and keeps k_march2).
+template <int WX, int TY>
+__global__ void __launch_bounds__(WX* TY) __attribute__((amdgpu_waves_per_eu(3)))
+    k_apply2_f32(int n, int tz, int ntx, int nty, const float* __restrict__ x, const float* __restrict__ k,
+                 float* __restrict__ y) {
+    march2_body<float, WX, TY, false, true>(xcd_tile(blockIdx.x, gridDim.x), blockIdx.x, n, tz, ntx, nty, x, nullptr,
+                                            nullptr, nullptr, k, y, nullptr, nullptr);
+}
+
 // ev0/ev1 (optional): HIP events recorded at the kernel's start and end.
 template <typename T, bool DIR, bool ALL>
 static void launch_m2(int n, const TileShape& t, const T* r, const T* dinv, const T* p_old, T* p_new, const T* k,
@@ -356,7 +368,15 @@ void launch_dir_march2(int n, const TileShape& t, bool all_active, const T* r, c
 
 template <typename T>
 void launch_apply_march2(int n, const TileShape& t, const T* k, const T* x, T* y, hipStream_t s) {
-    launch_m2<T, false, true>(n, t, x, nullptr, nullptr, nullptr, k, y, nullptr, nullptr, s);
+    if constexpr (std::is_same<T, float>::value) {
+        const int ntx = (n + t.tx - 1) / t.tx, nty = (n + t.ty - 1) / t.ty;
+        if (t.tx == 32)
+            hipLaunchKernelGGL((k_apply2_f32<16, 16>), dim3(t.blocks), dim3(kBlock), 0, s, n, t.tz, ntx, nty, x, k, y);
+        else
+            hipLaunchKernelGGL((k_apply2_f32<32, 8>), dim3(t.blocks), dim3(kBlock), 0, s, n, t.tz, ntx, nty, x, k, y);
+    } else {
+        launch_m2<T, false, true>(n, t, x, nullptr, nullptr, nullptr, k, y, nullptr, nullptr, s);
+    }
 }
 
 template void launch_dir_march2<double>(int, const TileShape&, bool, const double*, const double*, const double*,
@@ -382,7 +402,9 @@ __global__ void __launch_bounds__(WX* TY) kb_dir_march2(BatchTab t, const double
                                                         const double* __restrict__ p_old, double* __restrict__ p_new,
                                                         const double* __restrict__ k, double* __restrict__ q,
                                                         double* __restrict__ partials, const Scalars* __restrict__ sc) {
-    for (int item = blockIdx.x; item < t.mb_total; item += gridDim.x) {
+    for (int v = blockIdx.x; v < t.mb_total; v += gridDim.x) {
+        // contiguous item ranges per XCD (the grid is a multiple of 8 or covers every item)
+        const int item = xcd_tile(v, t.mb_total);
         const int d = t.mb_design[item];
         const BatchDesc D = t.desc[d];
         const int64_t o1 = D.off, o3 = 3 * D.off;

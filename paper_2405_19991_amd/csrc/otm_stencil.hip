@@ -68,7 +68,7 @@ __global__ void __launch_bounds__(TX* TY) k_tiled(int n, int tz, int ntx, int nt
 
     const int tid = threadIdx.x;
     const int tx = tid % TX, ty = tid / TX;
-    int bid = blockIdx.x;
+    int bid = xcd_tile(blockIdx.x, gridDim.x);  // tiles in x, then y, then z
     const int bx = bid % ntx;
     bid /= ntx;
     const int by = bid % nty;
@@ -203,7 +203,7 @@ __global__ void __launch_bounds__(TX* TY) k_march(int n, int tz, int ntx, int nt
 
     const int tid = threadIdx.x;
     const int tx = tid % TX, ty = tid / TX;
-    int bid = blockIdx.x;
+    int bid = xcd_tile(blockIdx.x, gridDim.x);  // tiles in x, then y, then z
     const int bx = bid % ntx;
     bid /= ntx;
     const int by = bid % nty;

@@ -140,5 +140,40 @@ def test_fused_design_iterations_track_oracle():
 
 def test_fused_rejects_odd_n():
     from paper_2405_19991_amd import Homogenization
-    with pytest.raises(Exception):
-        Homogenization(13, (1.0, 1e-3), (0.1,) * 3 + (0.0,) * 3, vf=0.3, kernel_variant=4)
+    for v in (4, 5):
+        with pytest.raises(Exception):
+            Homogenization(13, (1.0, 1e-3), (0.1,) * 3 + (0.0,) * 3, vf=0.3, kernel_variant=v)
+
+
+@pytest.mark.parametrize("precision,n", [("fp64", 16), ("fp64", 34), ("mixed", 32), ("mixed", 64)])
+def test_chained_passes_equal_finalized_passes(precision, n):
+    """Chained passes (each block reduces its predecessor's partial sums) sum
+    the same values in the same order as the finalize kernel: the iterates,
+    iteration counts and tensors are bit-identical."""
+    rho = synth.smoothed_noise(n, 0.05, 0.95, 77 + n)
+    tol = 1e-11 if precision == "fp64" else 1e-6
+    res = {}
+    for v in (4, 5):
+        print(f"chain check {precision} n={n} variant={v}", flush=True)
+        with make(n, rho, precision=precision, tol=tol, kernel_variant=v, check_every=8) as h:
+            assert h.tile()["variant"] == v
+            kappa, st = h.homogenize()
+            res[v] = (st["iterations"], np.array(kappa), h.get_field("chi"))
+        assert st["converged"]
+    assert res[4][0] == res[5][0]
+    assert np.array_equal(res[4][1], res[5][1])
+    assert np.array_equal(res[4][2], res[5][2])
+
+
+def test_chained_inactive_loads_and_oracle():
+    """Chained passes with loads that are inactive from the start, against the
+    laminate closed forms."""
+    n = 16
+    layers = np.where(np.arange(n) % 4 < 2, 0.9, 0.2)
+    rho = np.broadcast_to(layers[:, None, None], (n, n, n)).copy()
+    prm = O.Params()
+    k = O.simp(O.density_filter(rho, prm.rfilter), prm.k0, prm.kmin, prm.penal)[:, 0, 0]
+    with make(n, rho, tol=1e-10, kernel_variant=5) as h:
+        kappa, st = h.homogenize()
+    assert st["converged"] and st["iterations"][0] == 0 and st["iterations"][1] == 0
+    np.testing.assert_allclose(kappa[:3], [k.mean(), k.mean(), 1.0 / np.mean(1.0 / k)], rtol=1e-9)
