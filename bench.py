@@ -48,6 +48,7 @@ def parse():
     ap.add_argument("--weights", default=None,
                     help="network weights (.npy) for the warm-start leg (default: the package's trained weights)")
     ap.add_argument("--no-warm-start", action="store_true", help="skip the warm-start leg")
+    ap.add_argument("--no-configs", action="store_true", help="skip the 16^3 / 64^3 legs")
     ap.add_argument("--variant", type=int, default=0,
                     help="solver kernel: 0 automatic (autotuned), 4 fused iteration, 1-3 cross-check kernels")
     ap.add_argument("--solver-tx", type=int, default=0, help="solver tile width (0: automatic)")
@@ -86,6 +87,20 @@ def recorded_traffic(kind: int):
             if d.get("sha256") == sources_sha256(rec[1]):
                 return d
     return None
+
+
+def oracle_tensor_error(w, kappa, tol):
+    """Relative Frobenius error of the first design iteration's tensor against
+    the CPU FP64 oracle's (stored by tests/golden/make_cell128_kappa.py, which
+    runs the oracle alone), for the 128^3 cell's initial density."""
+    path = os.path.join(ROOT, "tests", "golden", "cell128_kappa.json")
+    if w.n != 128 or not os.path.exists(path):
+        return None
+    import numpy as np
+    ref = json.load(open(path))
+    k_ref = np.array(ref["kappa"])
+    return {"value": float(np.linalg.norm(np.array(kappa) - k_ref) / np.linalg.norm(k_ref)),
+            "oracle_tol": ref["tol"], "gpu_tol": tol, "reference": "tests/golden/cell128_kappa.json"}
 
 
 def cpu_baseline(w, cg_iters: int):
@@ -142,6 +157,34 @@ def batch_leg(steps: int, log):
             "s_per_oc_iter": (t1 - t0) / steps, "pcg_dof_updates_per_s": iters / (t1 - t0),
             "tile_tx": int(info["tile_tx"]), "tile_tz": int(info["tile_tz"]), "work_items": int(info["work_items"]),
             "steps": steps}
+
+
+def config_legs(steps: int, log):
+    """Seconds per design iteration of the smaller cells: 16^3 isotropic (FP64,
+    tol 1e-8) and 64^3 orthotropic (FP64 and mixed, tol 1e-6); one warm-up
+    design iteration each, then `steps` timed ones."""
+    import synth
+    import torch
+    from paper_2405_19991_amd import Homogenization
+    out = []
+    for w in (synth.config1(), synth.config2("fp64"), synth.config2("mixed")):
+        with Homogenization(w.n, (w.k0, w.kmin), w.target, vf=w.vf, penal=w.penal, filter_radius=w.rfilter,
+                            precision=w.precision, tol=w.tol) as h:
+            h.set_density(w.rho0)
+            h.step()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            iters = 0
+            for _ in range(steps):
+                iters += sum(h.step()["pcg_iters"])
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+            name = w.name if w.name.endswith(w.precision) else w.name + "_" + w.precision
+            rec = {"workload": name, "n": w.n, "tol": w.tol, "s_per_oc_iter": dt / steps,
+                   "pcg_dof_updates_per_s": w.n ** 3 * iters / dt, "solver_tile": h.tile(), "steps": steps}
+        log(f"config {rec['workload']}: {1e3 * rec['s_per_oc_iter']:.2f} ms per design iteration")
+        out.append(rec)
+    return out
 
 
 def warm_start_leg(weights, log):
@@ -221,8 +264,11 @@ def main():
         print(msg, file=sys.stderr, flush=True)
 
     log(f"bench: {w.name} n={n} precision={args.precision} warmup={args.warmup} steps={args.steps}")
+    first_kappa = None
     for i in range(args.warmup):
         r = h.step()
+        if first_kappa is None:
+            first_kappa = r["kappa"]
         log(f"warmup {i}: g={r['g']:.4e} pcg={r['pcg_iters']} ms={r['ms_total']:.1f}")
     torch.cuda.synchronize()
     h.pass_timing(reset=True)
@@ -234,6 +280,8 @@ def main():
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     wall = t1 - t0
+    if first_kappa is None:
+        first_kappa = recs[0]["kappa"]
     pcg_iters = sum(sum(r["pcg_iters"]) for r in recs)
     dof = nn * pcg_iters
     solve_ms = sum(r["ms_solve"] for r in recs)
@@ -309,6 +357,7 @@ def main():
         "pcg_iters_per_step": pcg_iters / args.steps,
         "pcg_only_dof_per_s": dof / (solve_ms * 1e-3) if solve_ms > 0 else None,
         "solver_tile": tile,
+        "kappa_rel_err_vs_oracle": oracle_tensor_error(w, first_kappa, args.tol),
         "last_g": recs[-1]["g"],
         "last_kappa": recs[-1]["kappa"],
         "roofline": roof,
@@ -325,6 +374,8 @@ def main():
     log(f"apply kernel {us:.2f} us ({achieved:.0f} GB/s algorithmic)")
     if not args.no_batch:
         out["batch"] = batch_leg(args.batch_steps, log)
+    if not args.no_configs:
+        out["configs"] = config_legs(5, log)
     if not args.no_warm_start and n == 128:
         out["warm_start"] = warm_start_leg(args.weights, log)
     if not args.no_cpu_baseline:

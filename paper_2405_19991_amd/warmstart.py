@@ -28,24 +28,20 @@ def _log(msg):
 
 
 def design_runs() -> List[Tuple[str, int, object, object, float, int]]:
-    """(name, n, rho0, target, vf, iterations) for the training designs:
-    isotropic 16^3 cells, random-target 32^3 cells, orthotropic 64^3 cells and
-    anisotropic 128^3 cells (the evaluation seed 303 is held out)."""
+    """(name, n, rho0, target, vf, iterations) for the training designs, about
+    2000 (rho~, chi) pairs: 20 isotropic 16^3 cells x 30 design iterations,
+    8 orthotropic 64^3 cells x 100, 4 anisotropic 128^3 cells x 150 (the
+    evaluation cell, seed 303, is held out)."""
     sys.path.insert(0, os.path.dirname(HERE))
     import synth
     runs = []
-    for s in range(12):
+    for s in range(20):
         runs.append((f"iso16_{s}", 16, synth.uniform_noise(16, 0.3, 0.05, 1000 + s), synth.TARGET_ISO, 0.3, 30))
-    g = synth.rng(2000)
     for s in range(8):
-        vf = float(g.uniform(0.2, 0.4))
-        runs.append((f"rand32_{s}", 32, synth.smoothed_noise(32, vf - 0.15, vf + 0.15, 2100 + s),
-                     tuple(synth.random_spd_target(g)), vf, 25))
-    for s in range(4):
-        runs.append((f"ortho64_{s}", 64, synth.smoothed_noise(64, 0.2, 0.5, 201 + s), synth.TARGET_ORTHO, 0.35, 30))
-    for s in range(2):
-        runs.append((f"aniso128_{s}", 128, synth.smoothed_noise(128, 0.15, 0.45, 301 + s), synth.TARGET_ANISO, 0.3,
-                     15))
+        runs.append((f"ortho64_{s}", 64, synth.smoothed_noise(64, 0.2, 0.5, 201 + s), synth.TARGET_ORTHO, 0.35, 100))
+    for seed in (301, 302, 304, 305):
+        runs.append((f"aniso128_{seed}", 128, synth.smoothed_noise(128, 0.15, 0.45, seed), synth.TARGET_ANISO, 0.3,
+                     150))
     return runs
 
 
@@ -69,8 +65,8 @@ def generate(runs=None, tol: float = 1e-6):
     return data
 
 
-def train(data, epochs: int = 40, batch: int = 8, lr: float = 2e-3, seed: int = 0, n_max: int = 128,
-          halve_every: int = 10):
+def train(data, epochs: int = 30, batch: int = 8, lr: float = 2e-3, seed: int = 0, n_max: int = 128,
+          halve_every: int = 8):
     from .api import Network
     net = Network(n_max=n_max, seed=seed)
     g = np.random.Generator(np.random.PCG64(seed))
@@ -145,17 +141,52 @@ def evaluate(net, n: int = 128, seed: int = 303, at_iter: int = 5, tol: float = 
     }
 
 
+FLOP_FWD = 2 * 27 * (1 * 16 + 3 * 16 * 16 + 16 * 3)       # per voxel, forward
+FLOP_TRAIN = FLOP_FWD + 2 * 27 * (3 * 16 * 16 + 16 * 3) + FLOP_FWD  # + input and weight gradients
+
+
+def kernels(n: int = 128, reps: int = 5) -> Dict[str, float]:
+    """Wall time of one forward pass and of one training sample (forward,
+    input and weight gradients, loss) at n^3 on random inputs."""
+    import torch
+    from .api import Network
+    net = Network(n_max=n, seed=0)
+    g = torch.Generator(device="cuda").manual_seed(0)
+    rf = torch.rand(n ** 3, dtype=torch.float64, device="cuda", generator=g)
+    chi = torch.rand(3 * n ** 3, dtype=torch.float64, device="cuda", generator=g) - 0.5
+    out = torch.empty_like(chi)
+    net.forward(rf, out)
+    net.accumulate(rf, chi)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        net.forward(rf, out)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    for _ in range(reps):
+        net.accumulate(rf, chi)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    fwd, trn = (t1 - t0) / reps, (t2 - t1) / reps
+    vox = n ** 3
+    return {"n": n, "forward_ms": 1e3 * fwd, "train_sample_ms": 1e3 * trn,
+            "forward_tflops": FLOP_FWD * vox / fwd / 1e12, "train_tflops": FLOP_TRAIN * vox / trn / 1e12}
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("cmd", choices=["train", "eval"])
+    ap.add_argument("cmd", choices=["train", "eval", "kernels"])
     ap.add_argument("--out", default=DEFAULT_WEIGHTS)
     ap.add_argument("--weights", default=DEFAULT_WEIGHTS)
-    ap.add_argument("--epochs", type=int, default=40)
+    ap.add_argument("--epochs", type=int, default=30)
     ap.add_argument("--summary", default=None)
     a = ap.parse_args(argv)
     import torch
     torch.cuda.set_device(0)
     from .api import Network
+    if a.cmd == "kernels":
+        print(json.dumps(kernels()), flush=True)
+        return
     if a.cmd == "train":
         t0 = time.perf_counter()
         data = generate()
