@@ -36,7 +36,7 @@ def parse():
     ap.add_argument("--n", type=int, default=128)
     ap.add_argument("--tol", type=float, default=1e-6)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--oracle-cg-iters", type=int, default=1000)
+    ap.add_argument("--oracle-cg-iters", type=int, default=2500)
     ap.add_argument("--apply-reps", type=int, default=50)
     ap.add_argument("--no-batch", action="store_true", help="skip the 64-design batch leg")
     ap.add_argument("--batch-steps", type=int, default=2)
@@ -77,14 +77,17 @@ def sources_sha256(paths):
     return h.hexdigest()
 
 
-def recorded_traffic(kind: int):
+def recorded_traffic(kind: int, tile_tx: int, tile_tz: int):
+    """The counter record for this kernel and tile, if its sources still hash
+    as they did when the counters were taken."""
     rec = TRAFFIC_RECORDS.get(kind)
     if rec is None or not os.path.exists(os.path.join(ROOT, rec[0])):
         return None
+    digest = sources_sha256(rec[1])
     for line in open(os.path.join(ROOT, rec[0])):
         if line.startswith("record: "):
             d = json.loads(line[len("record: "):])
-            if d.get("sha256") == sources_sha256(rec[1]):
+            if d.get("sha256") == digest and (d.get("tile_tx"), d.get("tile_tz")) == (tile_tx, tile_tz):
                 return d
     return None
 
@@ -325,9 +328,8 @@ def main():
                  f"k_march2<{tname}, ..., DIR=true> (direction + operator pass, 3 loads)")
         if live["kernel"] == 4 and args.precision == "fp64":
             kdesc = kdesc.replace("k_fused_f32", "k_fused_f64")
-        trec = recorded_traffic(live["kernel"]) if args.precision == "mixed" and n == 128 else None
-        if trec and (trec.get("tile_tx"), trec.get("tile_tz")) != (tile["tx"], tile["tz"]):
-            trec = None  # counters were taken for another tile
+        trec = (recorded_traffic(live["kernel"], tile["tx"], tile["tz"])
+                if args.precision == "mixed" and n == 128 else None)
         roof = {"bound": "hbm", "kernel": kdesc, "achieved": ach, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                 "frac": ach / HBM_PEAK_GBS, "traffic": trec["traffic_bytes_per_launch"] if trec else None,
                 "traffic_source": TRAFFIC_RECORDS[live["kernel"]][0] if trec else None,

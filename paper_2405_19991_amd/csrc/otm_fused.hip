@@ -146,30 +146,37 @@ __device__ __forceinline__ void fused_body(int n, int tz, int ntx, int nty, cons
     const uint32_t bh = xy_h * (uint32_t)sizeof(T);     // halo node
     const uint32_t bkh = xy_kh * (uint32_t)sizeof(T);   // halo element
 
+    // own pair loads first, then every halo load under one branch (one exec
+    // mask change per plane instead of one per field)
     auto load_plane = [&](int P, PreF<T>& f) {
         const int64_t zoff = plane_off(P);
         const bool inr = P >= z0 && P < z1;
         const T* dp = dinv + zoff;
+        const T* kp = k + zoff;
         f.dv = ld_at<T2>(dp, bo);
-        if (has_h) f.hdv = ld_at<T>(dp, bh);
 #pragma unroll
         for (int l = 0; l < 3; ++l) {
             if (!act[l]) continue;
             const int64_t o = l * nn + zoff;
             f.r[l] = ld_at<T2>(r_in + o, bo);
-            if (has_h) f.hr[l] = ld_at<T>(r_in + o, bh);
             if (ua[l]) {
                 f.q[l] = ld_at<T2>(q_in + o, bo);
-                if (has_h) f.hq[l] = ld_at<T>(q_in + o, bh);
                 if (inr) f.x[l] = ld_at<T2>(x + o, bo);
             }
-            if (up[l]) {
-                f.p[l] = ld_at<T2>(p_in + o, bo);
-                if (has_h) f.hp[l] = ld_at<T>(p_in + o, bh);
+            if (up[l]) f.p[l] = ld_at<T2>(p_in + o, bo);
+        }
+        f.k = ld_at<T2>(kp, bo);
+        if (has_h) {
+            f.hdv = ld_at<T>(dp, bh);
+#pragma unroll
+            for (int l = 0; l < 3; ++l) {
+                if (!act[l]) continue;
+                const int64_t o = l * nn + zoff;
+                f.hr[l] = ld_at<T>(r_in + o, bh);
+                if (ua[l]) f.hq[l] = ld_at<T>(q_in + o, bh);
+                if (up[l]) f.hp[l] = ld_at<T>(p_in + o, bh);
             }
         }
-        const T* kp = k + zoff;
-        f.k = ld_at<T2>(kp, bo);
         if (has_kh) f.kh = ld_at<T>(kp, bkh);
     };
 
@@ -183,38 +190,45 @@ __device__ __forceinline__ void fused_body(int n, int tz, int ntx, int nty, cons
         const int slot = P & 1;
         const bool inr = P >= z0 && P < z1;
         const int64_t zoff = plane_off(P);
+        T2 rnv[3];
 #pragma unroll
         for (int l = 0; l < 3; ++l) {
             if (!act[l]) continue;
             T2 rn = f.r[l];
-            T hrn = f.hr[l];
-            if (ua[l]) {
-                rn -= al[l] * f.q[l];
-                hrn -= al[l] * f.hq[l];
-            }
+            if (ua[l]) rn -= al[l] * f.q[l];
             const T2 z = f.dv * rn;
-            const T hz = f.hdv * hrn;
             T2 pn = z;
-            T hpn = hz;
-            if (up[l]) {
-                pn += be[l] * f.p[l];
-                hpn += be[l] * f.hp[l];
-            }
-            if (inr && own) {
-                const int64_t o = l * nn + zoff;
-                st_at<T2>(r_out + o, bo, rn);
-                st_at<T2>(p_out + o, bo, pn);
-                if (ua[l]) st_at<T2>(x + o, bo, f.x[l] + al[l] * f.p[l]);
-                acc[9 + l] += rn.x * z.x + rn.y * z.y;
-                acc[12 + l] += rn.x * rn.x + rn.y * rn.y;
-            }
+            if (up[l]) pn += be[l] * f.p[l];
             *reinterpret_cast<T2*>(&sp[slot][l][lp]) = pn;
-            if (has_h) sp[slot][l][lph] = hpn;
+            rnv[l] = rn;
             pP[l] = pn;
             zP[l] = z;
         }
+        if (inr && own) {
+#pragma unroll
+            for (int l = 0; l < 3; ++l) {
+                if (!act[l]) continue;
+                const int64_t o = l * nn + zoff;
+                st_at<T2>(r_out + o, bo, rnv[l]);
+                st_at<T2>(p_out + o, bo, pP[l]);
+                if (ua[l]) st_at<T2>(x + o, bo, f.x[l] + al[l] * f.p[l]);
+                acc[9 + l] += rnv[l].x * zP[l].x + rnv[l].y * zP[l].y;
+                acc[12 + l] += rnv[l].x * rnv[l].x + rnv[l].y * rnv[l].y;
+            }
+        }
         dvP = f.dv;
         *reinterpret_cast<T2*>(&sk[slot][lk]) = f.k;
+        if (has_h) {
+#pragma unroll
+            for (int l = 0; l < 3; ++l) {
+                if (!act[l]) continue;
+                T hrn = f.hr[l];
+                if (ua[l]) hrn -= al[l] * f.hq[l];
+                T hpn = f.hdv * hrn;
+                if (up[l]) hpn += be[l] * f.hp[l];
+                sp[slot][l][lph] = hpn;
+            }
+        }
         if (has_kh) sk[slot][lkh] = f.kh;
     };
 
@@ -249,6 +263,7 @@ __device__ __forceinline__ void fused_body(int n, int tz, int ntx, int nty, cons
         const T c0a = (ea0 + ea1 + ea2 + ea3) * third;
         const T c0b = (eb0 + eb1 + eb2 + eb3) * third;
         const bool done = (P - 1 >= z0) && own;
+        T2 qd[3];
         const int64_t zdone = (int64_t)(P - 1 < 0 ? 0 : (P - 1)) * n2;
 #pragma unroll
         for (int l = 0; l < 3; ++l) {
@@ -277,18 +292,27 @@ __device__ __forceinline__ void fused_body(int n, int tz, int ntx, int nty, cons
             T2 qv;
             qv.x = yA[l].x - w * opa;
             qv.y = yA[l].y - w * opb;
-            if (done) {
-                st_at<T2>(q_out + l * nn + zdone, bo, qv);
-                acc[l] += pB[l].x * qv.x + pB[l].y * qv.y;
-                acc[3 + l] += zB[l].x * qv.x + zB[l].y * qv.y;
-                acc[6 + l] += dvB.x * qv.x * qv.x + dvB.y * qv.y * qv.y;
-            }
+            qd[l] = qv;
             T2 yb;
             yb.x = yB[l].x + ina;
             yb.y = yB[l].y + inb;
             yA[l] = yb;
             yB[l].x = -w * oca;
             yB[l].y = -w * ocb;
+        }
+        if (done) {
+#pragma unroll
+            for (int l = 0; l < 3; ++l) {
+                if (!act[l]) continue;
+                const T2 qv = qd[l];
+                st_at<T2>(q_out + l * nn + zdone, bo, qv);
+                acc[l] += pB[l].x * qv.x + pB[l].y * qv.y;
+                acc[3 + l] += zB[l].x * qv.x + zB[l].y * qv.y;
+                acc[6 + l] += dvB.x * qv.x * qv.x + dvB.y * qv.y * qv.y;
+            }
+        }
+#pragma unroll
+        for (int l = 0; l < 3; ++l) {
             pB[l] = pP[l];
             zB[l] = zP[l];
         }

@@ -73,8 +73,7 @@ __device__ __forceinline__ void march2_body(int bid_, int slot_, int n, int tz, 
         }
     }
     const int i = i0 + 2 * tx, j = j0 + ty;
-    const bool own_a = (i < n) && (j < n);
-    const bool own_b = (i + 1 < n) && (j < n);
+    const bool own = (i < n) && (j < n);  // n even: i < n implies i + 1 < n
     const uint32_t xy_own = (uint32_t)(i % n) + (uint32_t)n * (uint32_t)(j % n);  // even
     const int lp = (ty + 1) * PXP + (2 * tx + 1) + 1;  // LDS index of node a (even)
     const int lk = (ty + 1) * KXP + (2 * tx + 1) + 1;  // LDS index of element a (even)
@@ -126,27 +125,29 @@ __device__ __forceinline__ void march2_body(int bid_, int slot_, int n, int tz, 
     const uint32_t bh = xy_h * (uint32_t)sizeof(T);
     const uint32_t bkh = xy_kh * (uint32_t)sizeof(T);
 
+    // own pair loads first, then every halo load under one branch (one exec
+    // mask change per plane instead of one per field)
     auto load_plane = [&](int P, Pre2<T, DIR>& f) {
         const int64_t zoff = plane_off(P);
-        if (DIR) {
-            const T* dp = dinv + zoff;
-            f.dv = ld_at<T2>(dp, bo);
-            if (has_h) f.hdv = ld_at<T>(dp, bh);
-        }
+        const T* dp = dinv + zoff;
+        const T* kp = k + zoff;
+        if (DIR) f.dv = ld_at<T2>(dp, bo);
 #pragma unroll
         for (int l = 0; l < 3; ++l) {
             if (!act[l]) continue;
-            const T* rp = r + l * nn + zoff;
-            f.r[l] = ld_at<T2>(rp, bo);
-            if (has_h) f.hr[l] = ld_at<T>(rp, bh);
-            if (DIR && beta[l] != (T)0) {
-                const T* pp = p_old + l * nn + zoff;
-                f.po[l] = ld_at<T2>(pp, bo);
-                if (has_h) f.hpo[l] = ld_at<T>(pp, bh);
+            f.r[l] = ld_at<T2>(r + l * nn + zoff, bo);
+            if (DIR && beta[l] != (T)0) f.po[l] = ld_at<T2>(p_old + l * nn + zoff, bo);
+        }
+        f.k = ld_at<T2>(kp, bo);
+        if (has_h) {
+            if (DIR) f.hdv = ld_at<T>(dp, bh);
+#pragma unroll
+            for (int l = 0; l < 3; ++l) {
+                if (!act[l]) continue;
+                f.hr[l] = ld_at<T>(r + l * nn + zoff, bh);
+                if (DIR && beta[l] != (T)0) f.hpo[l] = ld_at<T>(p_old + l * nn + zoff, bh);
             }
         }
-        const T* kp = k + zoff;
-        f.k = ld_at<T2>(kp, bo);
         if (has_kh) f.kh = ld_at<T>(kp, bkh);
     };
 
@@ -155,31 +156,34 @@ __device__ __forceinline__ void march2_body(int bid_, int slot_, int n, int tz, 
         const int slot = P & 1;
         const bool in_range = P >= z0 && P < z1;
         const int64_t zoff = plane_off(P);
+        T hv[3];
 #pragma unroll
         for (int l = 0; l < 3; ++l) {
             if (!act[l]) continue;
             T2 val = f.r[l];
-            T hv = f.hr[l];
+            hv[l] = f.hr[l];
             if (DIR) {
                 val = f.dv * f.r[l];
-                hv = f.hdv * f.hr[l];
+                hv[l] = f.hdv * f.hr[l];
                 if (beta[l] != (T)0) {
                     val += beta[l] * f.po[l];
-                    hv += beta[l] * f.hpo[l];
-                }
-                if (in_range) {
-                    T* pn = p_new + l * nn + zoff;
-                    if (own_b)
-                        st_at<T2>(pn, bo, val);
-                    else if (own_a)
-                        st_at<T>(pn, bo, val.x);
+                    hv[l] += beta[l] * f.hpo[l];
                 }
             }
             *reinterpret_cast<T2*>(&sp[slot][l][lp]) = val;
-            if (has_h) sp[slot][l][lph] = hv;
             pP[l] = val;
         }
+        if (DIR && in_range && own) {
+#pragma unroll
+            for (int l = 0; l < 3; ++l)
+                if (act[l]) st_at<T2>(p_new + l * nn + zoff, bo, pP[l]);
+        }
         *reinterpret_cast<T2*>(&sk[slot][lk]) = f.k;
+        if (has_h) {
+#pragma unroll
+            for (int l = 0; l < 3; ++l)
+                if (act[l]) sp[slot][l][lph] = hv[l];
+        }
         if (has_kh) sk[slot][lkh] = f.kh;
     };
 
@@ -217,6 +221,7 @@ __device__ __forceinline__ void march2_body(int bid_, int slot_, int n, int tz, 
         const T c0a = (ea0 + ea1 + ea2 + ea3) * third;
         const T c0b = (eb0 + eb1 + eb2 + eb3) * third;
         const bool done = P - 1 >= z0;
+        T2 qd[3];
         const int64_t zdone = (int64_t)(P - 1 < 0 ? 0 : (P - 1)) * n2;
 #pragma unroll
         for (int l = 0; l < 3; ++l) {
@@ -248,25 +253,24 @@ __device__ __forceinline__ void march2_body(int bid_, int slot_, int n, int tz, 
             T2 ya;
             ya.x = yA[l].x - w * opa;
             ya.y = yA[l].y - w * opb;
-            if (done) {
-                T* qp = q + l * nn + zdone;
-                if (own_b)
-                    st_at<T2>(qp, bo, ya);
-                else if (own_a)
-                    st_at<T>(qp, bo, ya.x);
-                if (DIR) {
-                    if (own_a) acc[l] += (double)pB[l].x * (double)ya.x;
-                    if (own_b) acc[l] += (double)pB[l].y * (double)ya.y;
-                }
-            }
+            qd[l] = ya;
             T2 yb;
             yb.x = yB[l].x + ina;
             yb.y = yB[l].y + inb;
             yA[l] = yb;
             yB[l].x = -w * oca;
             yB[l].y = -w * ocb;
-            pB[l] = pP[l];
         }
+        if (done && own) {
+#pragma unroll
+            for (int l = 0; l < 3; ++l) {
+                if (!act[l]) continue;
+                st_at<T2>(q + l * nn + zdone, bo, qd[l]);
+                if (DIR) acc[l] += (double)pB[l].x * (double)qd[l].x + (double)pB[l].y * (double)qd[l].y;
+            }
+        }
+#pragma unroll
+        for (int l = 0; l < 3; ++l) pB[l] = pP[l];
         kpm0 = km0;
         kpm1 = km1;
         kpm2 = km2;

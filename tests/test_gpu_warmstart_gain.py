@@ -1,0 +1,59 @@
+"""What the trained network gains: PCG iterations to 1e-6 (mixed precision)
+from the network's prediction against the zero start, on cells held out of
+training (the 128^3 anisotropic cell of seed 303 and a 64^3 orthotropic cell
+of seed 209), using the committed weights.
+
+The prediction is scaled by the energy-minimising factor before use, so its
+energy-norm error is at most the zero start's; the test asserts that it is
+used and costs no more iterations than the zero start, and prints the gain.
+"""
+import os
+
+import pytest
+
+import synth
+
+pytestmark = pytest.mark.gpu
+
+WEIGHTS = os.path.join(os.path.dirname(os.path.dirname(os.path.abspath(__file__))), "paper_2405_19991_amd",
+                       "weights", "warmstart.npy")
+
+
+@pytest.fixture(scope="module")
+def net():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.fail("GPU test run without a visible GPU")
+    torch.cuda.set_device(0)
+    from paper_2405_19991_amd import Network
+    assert os.path.exists(WEIGHTS), "trained weights are part of the package"
+    nw = Network(n_max=128)
+    nw.load(WEIGHTS)
+    yield nw
+    nw.close()
+
+
+def iterations(n, rho, target, vf, guess, net=None):
+    from paper_2405_19991_amd import Homogenization
+    with Homogenization(n, (1.0, 1e-3), target, vf=vf, tol=1e-6, precision="mixed", guess=guess) as h:
+        if net is not None:
+            h.set_network(net)
+        h.set_density(rho)
+        _, st = h.homogenize()
+        used = h.timings()[6]
+    assert st["converged"]
+    return sum(st["iterations"]), used
+
+
+@pytest.mark.parametrize("case", ["aniso128_seed303", "ortho64_seed209"])
+def test_trained_network_gain(net, case):
+    if case.startswith("aniso128"):
+        n, rho, tgt, vf = 128, synth.smoothed_noise(128, 0.15, 0.45, 303), synth.TARGET_ANISO, 0.3
+    else:
+        n, rho, tgt, vf = 64, synth.smoothed_noise(64, 0.2, 0.5, 209), synth.TARGET_ORTHO, 0.35
+    it_zero, _ = iterations(n, rho, tgt, vf, "zero")
+    it_learned, used = iterations(n, rho, tgt, vf, "learned", net)
+    print(f"{case}: zero start {it_zero} PCG iterations, learned start {it_learned} "
+          f"({100.0 * (it_zero - it_learned) / it_zero:.1f} % fewer)", flush=True)
+    assert used == 1.0
+    assert it_learned <= it_zero
