@@ -45,70 +45,121 @@ __device__ __forceinline__ float bf2f(uint16_t h) { return __uint_as_float(((uin
 
 enum { NN_FWD_RELU = 0, NN_FWD_LAST = 1, NN_DGRAD_MASK = 2, NN_DGRAD = 3 };
 
-// out[v][0..15] for 16 consecutive voxels per wave-iteration.
+// One convolution layer: forward with bias and ReLU, the last layer in FP32,
+// or the input gradient masked by the forward activation.  A block computes a
+// 16x4x4 brick of voxels.  The brick and its one-voxel periodic halo (18x6x6
+// voxels, 16 bf16 channels each, 20.7 KB) are staged in LDS once and read by
+// all 27 taps, instead of every tap re-reading its shifted voxels from global
+// memory.  Wave w computes the four 16-voxel rows (y = 0..3) of brick plane
+// z = w as four independent chains of 27 MFMAs.
+constexpr int kBX = 16, kBY = 4, kBZ = 4;
+constexpr int kHX = kBX + 2, kHY = kBY + 2, kHZ = kBZ + 2;
+constexpr int kHVox = kHX * kHY * kHZ;
+
 template <int MODE>
-__global__ void __launch_bounds__(256) k_nn_conv(int n, const uint16_t* __restrict__ in, const uint16_t* __restrict__ wl,
-                                                 const float* __restrict__ bias, void* __restrict__ out,
-                                                 const uint16_t* __restrict__ mask) {
+__global__ void __launch_bounds__(256) k_nn_conv_b(int n, const uint16_t* __restrict__ in,
+                                                   const uint16_t* __restrict__ wl, const float* __restrict__ bias,
+                                                   void* __restrict__ out, const uint16_t* __restrict__ mask) {
+    __shared__ __attribute__((aligned(16))) uint16_t tile[kHVox * 16];
     const int lane = threadIdx.x & 63;
-    const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    const int nwaves = (gridDim.x * blockDim.x) >> 6;
-    // weights of the 27 taps in lane order: wl[(t*64 + lane)*4 + i]
+    const int wv = threadIdx.x >> 6;
+    const int nbx = n / kBX, nby = n / kBY;
+    const int nbricks = nbx * nby * (n / kBZ);
+    // weights of the 27 taps in lane order, wl[(t*64 + lane)*4 + i]: loaded once
+    // per block, which then walks its share of the bricks
     v4s w[27];
 #pragma unroll
     for (int t = 0; t < 27; ++t) {
         const uint2 raw = *reinterpret_cast<const uint2*>(wl + ((size_t)t * 64 + lane) * 4);
         w[t] = *reinterpret_cast<const v4s*>(&raw);
     }
-    const int m = lane & 15;         // voxel within the group (B column / D column)
+    const int m = lane & 15;         // voxel within the row (B column / D column)
     const int cg = (lane >> 4) * 4;  // channel quad (B rows k / D rows)
     float bq[4] = {0.f, 0.f, 0.f, 0.f};
     if (MODE == NN_FWD_RELU || MODE == NN_FWD_LAST) {
 #pragma unroll
         for (int i = 0; i < 4; ++i) bq[i] = bias[cg + i];
     }
-    const int groups_per_row = n / 16;
-    const int64_t ngroups = (int64_t)groups_per_row * n * n;
-    for (int64_t g = wave; g < ngroups; g += nwaves) {
-        const int gx = (int)(g % groups_per_row);
-        const int64_t row = g / groups_per_row;  // y + n z
-        const int y = (int)(row % n), z = (int)(row / n);
-        const int x = gx * 16 + m;
-        v4f acc = {0.f, 0.f, 0.f, 0.f};
+    constexpr int kChunks = kHVox * 2;
+    constexpr int kPer = (kChunks + 255) / 256;
+    // bricks in x, then y, then z; contiguous ranges per XCD (the grid is a
+    // multiple of 8 or covers every brick)
+    for (int vb = blockIdx.x; vb < nbricks; vb += gridDim.x) {
+        int b = xcd_tile(vb, nbricks);
+        const int bx = b % nbx;
+        b /= nbx;
+        const int by = b % nby;
+        const int bz = b / nby;
+        const int x0 = bx * kBX, y0 = by * kBY, z0 = bz * kBZ;
+        // stage the halo brick: two 16-byte chunks per voxel, a thread's loads
+        // all issued before its first LDS store
+        uint4 buf[kPer];
+#pragma unroll
+        for (int it = 0; it < kPer; ++it) {
+            const int c = threadIdx.x + it * 256;
+            if (c < kChunks) {
+                const int vox = c >> 1, half = c & 1;
+                const int hx = vox % kHX, hy = (vox / kHX) % kHY, hz = vox / (kHX * kHY);
+                int xs = x0 - 1 + hx, ys = y0 - 1 + hy, zs = z0 - 1 + hz;
+                xs = xs < 0 ? xs + n : (xs >= n ? xs - n : xs);
+                ys = ys < 0 ? ys + n : (ys >= n ? ys - n : ys);
+                zs = zs < 0 ? zs + n : (zs >= n ? zs - n : zs);
+                const size_t vs = (size_t)xs + (size_t)n * ((size_t)ys + (size_t)n * zs);
+                buf[it] = *reinterpret_cast<const uint4*>(in + vs * 16 + half * 8);
+            }
+        }
+        __syncthreads();  // the previous brick's reads of the tile are done
+#pragma unroll
+        for (int it = 0; it < kPer; ++it) {
+            const int c = threadIdx.x + it * 256;
+            if (c < kChunks) *reinterpret_cast<uint4*>(&tile[(c >> 1) * 16 + (c & 1) * 8]) = buf[it];
+        }
+        __syncthreads();
+        // the wave's four rows (y = 0..3 of brick plane z = wv) as four
+        // independent accumulator chains, tap by tap
+        const int zz = wv;
+        v4f acc[kBY];
+#pragma unroll
+        for (int yy = 0; yy < kBY; ++yy) acc[yy] = (v4f){0.f, 0.f, 0.f, 0.f};
 #pragma unroll
         for (int t = 0; t < 27; ++t) {
             const int dz = t / 9 - 1, dy = (t / 3) % 3 - 1, dx = t % 3 - 1;
-            int xs = x + dx, ys = y + dy, zs = z + dz;
-            xs = xs < 0 ? xs + n : (xs >= n ? xs - n : xs);
-            ys = ys < 0 ? ys + n : (ys >= n ? ys - n : ys);
-            zs = zs < 0 ? zs + n : (zs >= n ? zs - n : zs);
-            const size_t vs = (size_t)xs + (size_t)n * ((size_t)ys + (size_t)n * zs);
-            const uint2 raw = *reinterpret_cast<const uint2*>(in + vs * 16 + cg);
-            const v4s b = *reinterpret_cast<const v4s*>(&raw);
-            acc = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(w[t], b, acc, 0, 0, 0);
+            v4s bb[kBY];
+#pragma unroll
+            for (int yy = 0; yy < kBY; ++yy) {
+                const int hv = ((zz + 1 + dz) * kHY + (yy + 1 + dy)) * kHX + (m + 1 + dx);
+                const uint2 raw = *reinterpret_cast<const uint2*>(&tile[hv * 16 + cg]);
+                bb[yy] = *reinterpret_cast<const v4s*>(&raw);
+            }
+#pragma unroll
+            for (int yy = 0; yy < kBY; ++yy)
+                acc[yy] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(w[t], bb[yy], acc[yy], 0, 0, 0);
         }
-        const size_t v = (size_t)x + (size_t)n * ((size_t)y + (size_t)n * z);
-        if (MODE == NN_FWD_LAST) {
-            float4 o = make_float4(acc[0] + bq[0], acc[1] + bq[1], acc[2] + bq[2], acc[3] + bq[3]);
-            reinterpret_cast<float4*>(out)[v * 4 + (cg >> 2)] = o;
-        } else {
-            float o[4];
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                o[i] = acc[i] + bq[i];
-                if (MODE == NN_FWD_RELU) o[i] = fmaxf(o[i], 0.f);
-            }
-            if (MODE == NN_DGRAD_MASK) {
-                const uint2 mr = *reinterpret_cast<const uint2*>(mask + v * 16 + cg);
-                const uint16_t* mh = reinterpret_cast<const uint16_t*>(&mr);
+        for (int yy = 0; yy < kBY; ++yy) {
+            const size_t v = (size_t)(x0 + m) + (size_t)n * ((size_t)(y0 + yy) + (size_t)n * (z0 + zz));
+            if (MODE == NN_FWD_LAST) {
+                float4 o = make_float4(acc[yy][0] + bq[0], acc[yy][1] + bq[1], acc[yy][2] + bq[2], acc[yy][3] + bq[3]);
+                reinterpret_cast<float4*>(out)[v * 4 + (cg >> 2)] = o;
+            } else {
+                float o[4];
 #pragma unroll
-                for (int i = 0; i < 4; ++i)
-                    if (!(bf2f(mh[i]) > 0.f)) o[i] = 0.f;
+                for (int i = 0; i < 4; ++i) {
+                    o[i] = acc[yy][i] + bq[i];
+                    if (MODE == NN_FWD_RELU) o[i] = fmaxf(o[i], 0.f);
+                }
+                if (MODE == NN_DGRAD_MASK) {
+                    const uint2 mr = *reinterpret_cast<const uint2*>(mask + v * 16 + cg);
+                    const uint16_t* mh = reinterpret_cast<const uint16_t*>(&mr);
+#pragma unroll
+                    for (int i = 0; i < 4; ++i)
+                        if (!(bf2f(mh[i]) > 0.f)) o[i] = 0.f;
+                }
+                uint2 pk;
+                pk.x = (uint32_t)f2bf(o[0]) | ((uint32_t)f2bf(o[1]) << 16);
+                pk.y = (uint32_t)f2bf(o[2]) | ((uint32_t)f2bf(o[3]) << 16);
+                *reinterpret_cast<uint2*>(reinterpret_cast<uint16_t*>(out) + v * 16 + cg) = pk;
             }
-            uint2 pk;
-            pk.x = (uint32_t)f2bf(o[0]) | ((uint32_t)f2bf(o[1]) << 16);
-            pk.y = (uint32_t)f2bf(o[2]) | ((uint32_t)f2bf(o[3]) << 16);
-            *reinterpret_cast<uint2*>(reinterpret_cast<uint16_t*>(out) + v * 16 + cg) = pk;
         }
     }
 }
@@ -341,26 +392,27 @@ void prep_all(otm_nn* c) {
                            c->wd + (size_t)l * 27 * 256);
 }
 
-int conv_grid(int n) {
-    const int64_t groups = (int64_t)(n / 16) * n * n;
-    int64_t blocks = (groups + 3) / 4;  // 4 waves per block, one group each per sweep
-    if (blocks > 2048) blocks = 2048;
-    return (int)blocks;
+// blocks of the convolution: persistent over the 16x4x4 bricks (n is a
+// multiple of 16), at most 4 per CU
+int conv_bricks(int n) {
+    const int bricks = (n / kBX) * (n / kBY) * (n / kBZ);
+    return bricks < 1024 ? bricks : 1024;
 }
+
 
 int forward(otm_nn* c, int n, const double* rhof) {
     const int64_t nn = (int64_t)n * n * n;
     hipLaunchKernelGGL(k_nn_pack_input, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, c->stream, nn, rhof,
                        c->act[0]);
-    const int grid = conv_grid(n);
+    const int bricks = conv_bricks(n);
     for (int l = 0; l < kNNLayers; ++l) {
         const uint16_t* wl = c->wf + (size_t)l * 27 * 256;
         const float* b = c->p + (size_t)l * kLayerParams + kNNW;
         if (l < kNNLayers - 1)
-            hipLaunchKernelGGL(k_nn_conv<NN_FWD_RELU>, dim3(grid), dim3(256), 0, c->stream, n, c->act[l], wl, b,
+            hipLaunchKernelGGL(k_nn_conv_b<NN_FWD_RELU>, dim3(bricks), dim3(256), 0, c->stream, n, c->act[l], wl, b,
                                (void*)c->act[l + 1], (const uint16_t*)nullptr);
         else
-            hipLaunchKernelGGL(k_nn_conv<NN_FWD_LAST>, dim3(grid), dim3(256), 0, c->stream, n, c->act[l], wl, b,
+            hipLaunchKernelGGL(k_nn_conv_b<NN_FWD_LAST>, dim3(bricks), dim3(256), 0, c->stream, n, c->act[l], wl, b,
                                (void*)c->out, (const uint16_t*)nullptr);
     }
     return hipGetLastError() == hipSuccess ? OTM_OK : nn_fail(c, OTM_EDEVICE, "nn forward launch");
@@ -542,7 +594,6 @@ int otm_nn_accumulate(otm_nn* c, int32_t n, const void* rhof_dev, const void* ch
                        c->sums + 8);
     // backward: gA holds dL/d(out of layer l); the mean removal needs no
     // correction because the loss gradient already has zero mean per channel
-    const int grid = conv_grid(n);
     uint16_t* gcur = c->gA;
     uint16_t* gnext = c->gB;
     for (int l = kNNLayers - 1; l >= 0; --l) {
@@ -552,7 +603,7 @@ int otm_nn_accumulate(otm_nn* c, int32_t n, const void* rhof_dev, const void* ch
                            c->nwaves_wgrad, (const float*)c->wpart, c->g + (size_t)l * kLayerParams,
                            c->g + (size_t)l * kLayerParams + kNNW);
         if (l > 0) {
-            hipLaunchKernelGGL(k_nn_conv<NN_DGRAD_MASK>, dim3(grid), dim3(256), 0, c->stream, n,
+            hipLaunchKernelGGL(k_nn_conv_b<NN_DGRAD_MASK>, dim3(conv_bricks(n)), dim3(256), 0, c->stream, n,
                                (const uint16_t*)gcur, (const uint16_t*)(c->wd + (size_t)l * 27 * 256),
                                (const float*)nullptr, (void*)gnext, (const uint16_t*)c->act[l]);
             uint16_t* tmp = gcur;
