@@ -53,6 +53,10 @@ def parse():
                     help="solver kernel: 0 automatic (autotuned), 4 fused iteration, 1-3 cross-check kernels")
     ap.add_argument("--solver-tx", type=int, default=0, help="solver tile width (0: automatic)")
     ap.add_argument("--solver-tz", type=int, default=0, help="solver planes per z-march (0: automatic)")
+    ap.add_argument("--preconditioner", choices=["jacobi", "mg"], default="jacobi",
+                    help="preconditioner of the timed design iterations (mg: mixed precision only)")
+    ap.add_argument("--no-mg", action="store_true", help="skip the multigrid leg")
+    ap.add_argument("--mg-sweeps", type=int, default=2, help="relaxation steps per level and leg of the V-cycle")
     ap.add_argument("--calib-copy", action="store_true",
                     help="after the timed steps, run three 64 MiB device copies (a kernel of known traffic, "
                          "for scaling hardware byte counters)")
@@ -162,6 +166,31 @@ def batch_leg(steps: int, log):
             "steps": steps}
 
 
+def multigrid_leg(w, steps: int, log, sweeps: int = 2):
+    """The timed workload's design iterations with one multigrid V-cycle as
+    the preconditioner (mixed precision, same start and tolerance): one
+    warm-up design iteration, then `steps` timed ones."""
+    import torch
+    from paper_2405_19991_amd import Homogenization
+    with Homogenization(w.n, (w.k0, w.kmin), w.target, vf=w.vf, penal=w.penal, filter_radius=w.rfilter,
+                        precision="mixed", tol=w.tol, preconditioner="mg", mg_sweeps=sweeps) as h:
+        h.set_density(w.rho0)
+        first = h.step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        recs = [h.step() for _ in range(steps)]
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+    iters = sum(sum(r["pcg_iters"]) for r in recs)
+    out = {"workload": w.name + "_mixed_mg", "n": w.n, "tol": w.tol, "mg_sweeps": sweeps, "s_per_oc_iter": dt / steps,
+           "pcg_iters_per_step": iters / steps, "ms_solve_per_step": sum(r["ms_solve"] for r in recs) / steps,
+           "pcg_dof_updates_per_s": w.n ** 3 * iters / dt, "first_kappa": first["kappa"],
+           "first_pcg_iters": first["pcg_iters"], "steps": steps}
+    log(f"multigrid: {1e3 * out['s_per_oc_iter']:.2f} ms per design iteration, "
+        f"{out['pcg_iters_per_step']:.1f} PCG iterations per step")
+    return out
+
+
 def config_legs(steps: int, log):
     """Seconds per design iteration of the smaller cells: 16^3 isotropic (FP64,
     tol 1e-8) and 64^3 orthotropic (FP64 and mixed, tol 1e-6); one warm-up
@@ -261,7 +290,8 @@ def main():
     nn = n ** 3
     h = Homogenization(n, (w.k0, w.kmin), w.target, vf=w.vf, penal=w.penal, filter_radius=w.rfilter,
                        precision=args.precision, guess=args.guess, tol=w.tol, kernel_variant=args.variant,
-                       tile_tx=args.solver_tx, tile_tz=args.solver_tz)
+                       tile_tx=args.solver_tx, tile_tz=args.solver_tz, preconditioner=args.preconditioner,
+                       mg_sweeps=args.mg_sweeps)
     h.set_density(w.rho0)
     def log(msg):
         print(msg, file=sys.stderr, flush=True)
@@ -374,6 +404,10 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     log(f"apply kernel {us:.2f} us ({achieved:.0f} GB/s algorithmic)")
+    if not args.no_mg and args.preconditioner == "jacobi" and args.precision == "mixed" and n == 128:
+        mg = multigrid_leg(w, args.steps, log, args.mg_sweeps)
+        mg["kappa_rel_err_vs_oracle"] = oracle_tensor_error(w, mg.pop("first_kappa"), args.tol)
+        out["multigrid"] = mg
     if not args.no_batch:
         out["batch"] = batch_leg(args.batch_steps, log)
     if not args.no_configs:

@@ -68,6 +68,14 @@ extern "C" {
 #define OTM_GUESS_LEARNED 3  /* PCG starts from the attached network's prediction
                                 (otm_set_network; n a multiple of 16, else zero) */
 
+/* Preconditioners of the conjugate-gradient solve. */
+#define OTM_PRECOND_JACOBI 0 /* diagonal (Jacobi) preconditioner, Sec. 2.4 relaxation diagonal S_v */
+#define OTM_PRECOND_MG 1     /* one geometric multigrid V-cycle per iteration (Sec. 2.4, Algorithm 3):
+                                damped Jacobi relaxation on S_v, restriction of the residual,
+                                direct solve on the coarsest level, interpolation and correction.
+                                OTM_MIXED only (the V-cycle runs in float32); n = m 2^j with
+                                m in {3, 4} and n >= 6, else OTM_EINVAL */
+
 #define OTM_OBJ_MSE 0 /* g = sum_c (kappa_c - target_c)^2, Sec. 4.4 (MSE objective) */
 
 /* Fields readable with otm_get_field (count = n^3, or 3 n^3 where noted). */
@@ -97,7 +105,8 @@ typedef struct {
     int32_t guess;       /* OTM_GUESS_* */
     double tol;          /* stop when ||b - A chi||_2 <= tol ||b||_2 for every load */
     int32_t max_iter;    /* PCG iteration cap per solve */
-    int32_t check_every; /* host convergence check interval (iterations), >= 1 */
+    int32_t check_every; /* host convergence check interval (iterations), >= 1; with
+                            OTM_PRECOND_MG at most 2 is used */
     double reliable_delta; /* OTM_MIXED: refresh the float64 residual when the float32
                               recursive residual has dropped by this factor */
     int32_t kernel_variant; /* 0: streaming z-march kernels (default; two nodes per
@@ -119,6 +128,11 @@ typedef struct {
     int32_t autotune;       /* 1: with kernel_variant 0 and automatic tiles, time the
                                candidate kernels and tile shapes once per (n, precision)
                                and process at otm_create and keep the fastest */
+    int32_t preconditioner; /* OTM_PRECOND_JACOBI (default) or OTM_PRECOND_MG; with
+                               OTM_PRECOND_MG kernel_variant must be 0 and no autotuning
+                               is done */
+    int32_t mg_sweeps;      /* OTM_PRECOND_MG: relaxation steps before and after each
+                               coarse correction, 1..8 (default 2) */
 } otm_solver_opts;
 
 typedef struct {

@@ -27,6 +27,8 @@ OTM_GUESS_ZERO = 0
 OTM_GUESS_PREVIOUS = 1
 OTM_GUESS_USER = 2
 OTM_GUESS_LEARNED = 3
+OTM_PRECOND_JACOBI = 0
+OTM_PRECOND_MG = 1
 OTM_OBJ_MSE = 0
 
 FIELDS = {"rho": 0, "rhof": 1, "k": 2, "b": 3, "diag": 4, "chi": 5, "sens_elem": 6, "sens": 7}
@@ -56,7 +58,7 @@ class SolverOpts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("guess", ctypes.c_int32), ("tol", ctypes.c_double),
                 ("max_iter", ctypes.c_int32), ("check_every", ctypes.c_int32), ("reliable_delta", ctypes.c_double),
                 ("kernel_variant", ctypes.c_int32), ("tile_tz", ctypes.c_int32), ("tile_tx", ctypes.c_int32),
-                ("autotune", ctypes.c_int32)]
+                ("autotune", ctypes.c_int32), ("preconditioner", ctypes.c_int32), ("mg_sweeps", ctypes.c_int32)]
 
 
 class OcOpts(ctypes.Structure):

@@ -36,7 +36,8 @@ class Homogenization:
                  guess: str = "zero", tol: float = 1e-8, max_iter: int = 20000, check_every: int = 16,
                  reliable_delta: float = 1e-2, move: float = 0.05, eta: float = 0.5, rho_min: float = 1e-3,
                  governor: Optional[Dict[str, float]] = None, stream=None, kernel_variant: int = 0,
-                 tile_tz: int = 0, tile_tx: int = 0, autotune: bool = True):
+                 tile_tz: int = 0, tile_tx: int = 0, autotune: bool = True, preconditioner: str = "jacobi",
+                 mg_sweeps: int = 2):
         L = N.lib()
         self.n = int(n)
         p = N.Problem()
@@ -55,6 +56,8 @@ class Homogenization:
         s.tol, s.max_iter, s.check_every, s.reliable_delta = float(tol), int(max_iter), int(check_every), float(reliable_delta)
         s.kernel_variant, s.tile_tz, s.tile_tx = int(kernel_variant), int(tile_tz), int(tile_tx)
         s.autotune = int(bool(autotune))
+        s.preconditioner = {"jacobi": N.OTM_PRECOND_JACOBI, "mg": N.OTM_PRECOND_MG}[preconditioner]
+        s.mg_sweeps = int(mg_sweeps)
         o.move, o.eta, o.rho_min = float(move), float(eta), float(rho_min)
         for key, val in (governor or {}).items():
             setattr(g, key, val)

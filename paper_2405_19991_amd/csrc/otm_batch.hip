@@ -379,8 +379,10 @@ int otm_batch_create(const otm_problem* problems, int32_t count, const otm_solve
     if (solver) c->so = *solver;
     if (oc) c->oc = *oc;
     if (gov) c->go = *gov;
-    if (c->so.precision != OTM_FP64 || !(c->so.tol > 0.0) || c->so.max_iter < 1 || c->so.check_every < 1) {
-        const int code = c->so.precision != OTM_FP64 ? OTM_EUNSUPPORTED : OTM_EINVAL;
+    if (c->so.precision != OTM_FP64 || c->so.preconditioner != OTM_PRECOND_JACOBI || !(c->so.tol > 0.0) ||
+        c->so.max_iter < 1 || c->so.check_every < 1) {
+        const int code =
+            (c->so.precision != OTM_FP64 || c->so.preconditioner != OTM_PRECOND_JACOBI) ? OTM_EUNSUPPORTED : OTM_EINVAL;
         delete c;
         return code;
     }

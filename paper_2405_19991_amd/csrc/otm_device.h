@@ -73,6 +73,9 @@ __device__ __forceinline__ void final_sums_vm(const double* partials, int nblock
     double v[NV];
 #pragma unroll
     for (int i = 0; i < NV; ++i) v[i] = 0.0;
+    // unrolled so that several blocks' loads are in flight (the additions
+    // into v keep their order)
+#pragma unroll 4
     for (int b = threadIdx.x; b < nblocks; b += blockDim.x) {
 #pragma unroll
         for (int i = 0; i < NV; ++i) v[i] += partials[(size_t)i * kMaxBlocks + b];
@@ -100,6 +103,7 @@ __device__ __forceinline__ void final_sums(const double* partials, int nblocks, 
     double v[NV];
 #pragma unroll
     for (int i = 0; i < NV; ++i) v[i] = 0.0;
+#pragma unroll 4
     for (int b = threadIdx.x; b < nblocks; b += blockDim.x) {
 #pragma unroll
         for (int i = 0; i < NV; ++i) v[i] += partials[(size_t)b * NV + i];

@@ -78,6 +78,16 @@ struct otm_ctx {
     otm_nn* net = nullptr;
     int learned_used = 0;  // last solve started from the network's prediction
 
+    // multigrid preconditioner (float32 V-cycle, captured as a graph)
+    bool use_mg = false;
+    MgHierarchy mg;
+    std::vector<void*> mg_bufs;
+    float* ones32 = nullptr;       // D^-1 := 1 for the direction pass and the update
+    const float* mg_z = nullptr;   // z = M^-1 r written by the captured cycle
+    int mg_nb = 0;                 // blocks of its r.z partial sums
+    hipGraph_t mg_graph = nullptr;
+    hipGraphExec_t mg_exec = nullptr;
+
     bool have_density = false;
     bool prepared = false;
     bool homogenized = false;
@@ -215,6 +225,13 @@ int prepare(otm_ctx* c) {
                        c->prob.penal, w, c->stream);
     launch_setup_nodes(c->n, c->k, c->b, c->dinv, c->dinv32, w, c->stream);
     launch_sub_mean3(c->n, c->b, 1, w, c->stream);
+    if (c->use_mg) {
+        // coarse conductivities and diagonals, inverse of the coarsest operator
+        const MgHierarchy& H = c->mg;
+        for (int l = 1; l < H.levels; ++l)
+            launch_mg_coarsen(H.lv[l].n, H.lv[l - 1].k, H.lv[l].kc, H.lv[l].dinvc, c->stream);
+        launch_mg_coarse_setup(H.lv[H.levels - 1].n, H.lv[H.levels - 1].k, H.minv, c->stream);
+    }
     int rc = check_launch(c, "prepare");
     if (rc) return rc;
     c->prepared = true;
@@ -403,7 +420,77 @@ int solve_fp64(otm_ctx* c, bool x_zero, otm_solve_stats* st) {
     return OTM_OK;
 }
 
+// Multigrid-preconditioned CG in float32 with float64 residual refreshes
+// (the refresh rule of the Jacobi path); z = M^-1 r by the captured V-cycle.
+// PCG restarts (beta = 0) after each refresh.
+int solve_mg(otm_ctx* c, bool x_zero, otm_solve_stats* st) {
+    const Workspace w = c->ws();
+    const int n = c->n;
+    int rc;
+    if ((rc = reset_solver_scalars(c))) return rc;
+    if (x_zero) HIPCHK(c, hipMemsetAsync(c->x, 0, (size_t)3 * c->nn * sizeof(double), c->stream));
+    HIPCHK(c, hipMemsetAsync(c->x32, 0, (size_t)3 * c->nn * sizeof(float), c->stream));
+    launch_residual<float>(n, c->k, c->b, c->x, c->r32, c->p32[c->pbuf], c->dinv32, RES_START, x_zero ? 1 : 0, w,
+                           c->stream);
+    if ((rc = check_launch(c, "residual"))) return rc;
+    if ((rc = sync_scalars(c))) return rc;
+    double rr_ref[3] = {c->h_sc->rr_true[0], c->h_sc->rr_true[1], c->h_sc->rr_true[2]};
+    const double d2 = c->so.reliable_delta * c->so.reliable_delta;
+    int refreshes = 0, launches = 0;
+    bool restart = true;
+    // a V-cycle costs several operator passes and few are needed: check often
+    const int check = c->so.check_every < 2 ? c->so.check_every : 2;
+    while (!all_inactive(c->h_sc) && max_iters(c->h_sc) < c->so.max_iter) {
+        const bool all = all_active(c->h_sc);
+        bool sampled = false;
+        for (int it = 0; it < check; ++it) {
+            HIPCHK(c, hipGraphLaunch(c->mg_exec, c->stream));
+            launch_finalize(restart ? FIN_MG_RZ0 : FIN_MG_RZ, c->mg_nb, w, c->stream);
+            restart = false;
+            float* po = c->p32[c->pbuf];
+            float* pn = c->p32[c->pbuf ^ 1];
+            const bool sample = all && it == check - 1;
+            launch_dir_march2<float>(n, c->tile2, all, c->mg_z, c->ones32, po, pn, c->k32, c->q32, w, c->stream, true,
+                                     sample ? c->pev[0] : nullptr, sample ? c->pev[1] : nullptr);
+            sampled = sampled || sample;
+            launch_update_vec<float>(n, c->x32, c->r32, pn, c->q32, c->ones32, w, c->stream, true, FIN_MG_UPDATE);
+            c->pbuf ^= 1;
+            ++launches;
+        }
+        if ((rc = check_launch(c, "mg-pcg"))) return rc;
+        if ((rc = sync_scalars(c))) return rc;
+        collect_pass_sample(c, sampled, (double)c->nn * (4.0 * 3 + 1 + 1) * sizeof(float), 0);
+        bool refresh = all_inactive(c->h_sc);
+        for (int l = 0; l < 3; ++l)
+            if (c->h_sc->active[l] && c->h_sc->rr[l] < d2 * rr_ref[l]) refresh = true;
+        if (refresh) {
+            launch_accumulate(n, c->x, c->x32, c->stream);
+            launch_residual<float>(n, c->k, c->b, c->x, c->r32, c->p32[c->pbuf], c->dinv32, RES_REFRESH, 0, w,
+                                   c->stream);
+            if ((rc = check_launch(c, "refresh"))) return rc;
+            if ((rc = sync_scalars(c))) return rc;
+            for (int l = 0; l < 3; ++l) rr_ref[l] = c->h_sc->rr_true[l];
+            ++refreshes;
+            restart = true;
+        }
+    }
+    launch_accumulate(n, c->x, c->x32, c->stream);
+    launch_sum3(n, c->x, 0, w, c->stream);
+    launch_sub_mean3(n, c->x, 0, w, c->stream);
+    if ((rc = check_launch(c, "project"))) return rc;
+    if ((rc = sync_scalars(c))) return rc;
+    for (int l = 0; l < 3; ++l) {
+        st->iterations[l] = c->h_sc->iters[l];
+        st->rel_residual[l] = c->h_sc->bb[l] > 0.0 ? std::sqrt(c->h_sc->rr_true[l] / c->h_sc->bb[l]) : 0.0;
+    }
+    st->converged = all_inactive(c->h_sc) ? 1 : 0;
+    st->refreshes = refreshes;
+    c->timings[7] = (double)launches;
+    return OTM_OK;
+}
+
 int solve_mixed(otm_ctx* c, bool x_zero, otm_solve_stats* st) {
+    if (c->use_mg) return solve_mg(c, x_zero, st);
     if (c->use_fused) {
         const FusedBufs<float> B{{c->r32, c->r32b}, {c->q32, c->q32b}, {c->p32[0], c->p32[1]}, c->x32, c->dinv32,
                                  c->k32};
@@ -626,6 +713,10 @@ int free_all(otm_ctx* c) {
                     c->sc, c->r64b, c->q64b, c->r32b, c->q32b};
     for (void* p : bufs)
         if (p) (void)hipFree(p);
+    for (void* p : c->mg_bufs)
+        if (p) (void)hipFree(p);
+    if (c->mg_exec) (void)hipGraphExecDestroy(c->mg_exec);
+    if (c->mg_graph) (void)hipGraphDestroy(c->mg_graph);
     if (c->h_sc) (void)hipHostFree(c->h_sc);
     for (auto& e : c->ev)
         if (e) (void)hipEventDestroy(e);
@@ -633,6 +724,78 @@ int free_all(otm_ctx* c) {
         if (e) (void)hipEventDestroy(e);
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
     return 0;
+}
+
+// ------------------------------------------------------------------ multigrid
+// Levels n, n/2, ... while the side is even and above 4; the coarsest side
+// must end at 3 or 4 (at most 64 nodes, solved directly), with at least one
+// level above it.
+int mg_levels(int n, int* ns) {
+    int L = 0, m = n;
+    ns[L++] = m;
+    while (m % 2 == 0 && m > 4 && L < kMgMaxLevels) {
+        m /= 2;
+        ns[L++] = m;
+    }
+    if (m > 4 || L < 2) return 0;
+    return L;
+}
+
+template <typename T>
+int mg_alloc(otm_ctx* c, T** p, int64_t count) {
+    int rc = dalloc(c, p, count);
+    if (!rc) c->mg_bufs.push_back((void*)*p);
+    return rc;
+}
+
+// Buffers of every level and the captured V-cycle (fixed pointers).
+int mg_build(otm_ctx* c) {
+    MgHierarchy& H = c->mg;
+    int ns[kMgMaxLevels];
+    H.levels = mg_levels(c->n, ns);
+    if (!H.levels) return fail(c, OTM_EINVAL, "multigrid needs n = m 2^j with m in {3, 4} and n >= 6");
+    H.sweeps = c->so.mg_sweeps;
+    int rc = OTM_OK;
+    for (int l = 0; l < H.levels && !rc; ++l) {
+        MgLevel& a = H.lv[l];
+        a.n = ns[l];
+        const int64_t m = (int64_t)a.n * a.n * a.n;
+        rc = rc ? rc : mg_alloc(c, &a.x[0], 3 * m);
+        rc = rc ? rc : mg_alloc(c, &a.x[1], 3 * m);
+        rc = rc ? rc : mg_alloc(c, &a.t, 3 * m);
+        if (l == 0) {
+            a.k = c->k32;
+            a.dinv = c->dinv32;
+            a.f = c->r32;
+        } else {
+            rc = rc ? rc : mg_alloc(c, &a.kc, m);
+            rc = rc ? rc : mg_alloc(c, &a.dinvc, m);
+            rc = rc ? rc : mg_alloc(c, &a.f, 3 * m);
+            a.k = a.kc;
+            a.dinv = a.dinvc;
+        }
+        a.tile = choose_tile2(a.n, c->max_blocks, 0, 0);
+    }
+    rc = rc ? rc : mg_alloc(c, &H.minv, (int64_t)kMgCoarseMax * kMgCoarseMax);
+    rc = rc ? rc : mg_alloc(c, &c->ones32, c->nn);
+    if (rc) return rc;
+    launch_fill_const<float>(c->ones32, c->nn, 1.0f, c->stream);
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    // capture on a private stream (the context's may be the legacy default stream)
+    hipStream_t cs = nullptr;
+    HIPCHK(c, hipStreamCreateWithFlags(&cs, hipStreamNonBlocking));
+    hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        c->mg_nb = mg_vcycle(H, c->partials, c->max_blocks, cs, &c->mg_z);
+        e = hipStreamEndCapture(cs, &c->mg_graph);
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&c->mg_exec, c->mg_graph, nullptr, nullptr, 0);
+    (void)hipStreamDestroy(cs);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return fail(c, OTM_EDEVICE, std::string("multigrid graph capture: ") + hipGetErrorString(e));
+    }
+    return OTM_OK;
 }
 
 // ------------------------------------------------------------------ autotune
@@ -776,7 +939,7 @@ int autotune(otm_ctx* c) {
     // zeroed vectors and coefficients: every candidate computes on zeros
     const bool mixed = prec == OTM_MIXED;
     const size_t es = mixed ? sizeof(float) : sizeof(double);
-    const size_t v3 = 3 * (size_t)c->nn * es, v1 = (size_t)c->nn * es;
+    const size_t v3 = 3 * (size_t)c->nn * es;
     void* vecs[] = {mixed ? (void*)c->r32 : (void*)c->r64, mixed ? (void*)c->q32 : (void*)c->q64,
                     mixed ? (void*)c->r32b : (void*)c->r64b, mixed ? (void*)c->q32b : (void*)c->q64b,
                     mixed ? (void*)c->p32[0] : (void*)c->p64[0], mixed ? (void*)c->p32[1] : (void*)c->p64[1],
@@ -832,6 +995,8 @@ void otm_default_options(otm_solver_opts* s, otm_oc_opts* o, otm_governor_opts* 
         s->tile_tz = 0;
         s->tile_tx = 0;
         s->autotune = 1;
+        s->preconditioner = OTM_PRECOND_JACOBI;
+        s->mg_sweeps = 2;
     }
     if (o) {
         o->move = 0.05;
@@ -886,9 +1051,20 @@ int otm_create(const otm_problem* problem, const otm_solver_opts* solver, const 
           c->so.reliable_delta < 1.0 && (c->so.precision == OTM_FP64 || c->so.precision == OTM_MIXED) &&
           c->so.guess >= OTM_GUESS_ZERO && c->so.guess <= OTM_GUESS_LEARNED &&
           c->so.kernel_variant >= 0 && c->so.kernel_variant <= 5 && c->so.tile_tz >= 0 &&
-          (c->so.tile_tx == 0 || c->so.tile_tx == 16 || c->so.tile_tx == 32 || c->so.tile_tx == 64))) {
+          (c->so.tile_tx == 0 || c->so.tile_tx == 16 || c->so.tile_tx == 32 || c->so.tile_tx == 64) &&
+          (c->so.preconditioner == OTM_PRECOND_JACOBI || c->so.preconditioner == OTM_PRECOND_MG))) {
         delete c;
         return OTM_EINVAL;
+    }
+    if (c->so.preconditioner == OTM_PRECOND_MG) {
+        int ns[kMgMaxLevels];
+        if (c->so.precision != OTM_MIXED || c->so.kernel_variant != 0 || c->so.mg_sweeps < 1 ||
+            c->so.mg_sweeps > 8 || (c->so.tile_tx != 0 && c->so.tile_tx != 32 && c->so.tile_tx != 64) ||
+            !mg_levels(problem->n, ns)) {
+            delete c;
+            return OTM_EINVAL;
+        }
+        c->use_mg = true;
     }
     if (!(c->oc.move > 0.0 && c->oc.eta > 0.0 && c->oc.rho_min > 0.0 && c->oc.rho_min < 1.0)) {
         delete c;
@@ -992,7 +1168,15 @@ int otm_create(const otm_problem* problem, const otm_solver_opts* solver, const 
         delete c;
         return OTM_EDEVICE;
     }
-    if (c->so.kernel_variant == 0 && c->so.tile_tx == 0 && c->so.tile_tz == 0 && c->so.autotune) {
+    if (c->use_mg) {
+        rc = mg_build(c);
+        if (rc) {
+            free_all(c);
+            delete c;
+            return rc;
+        }
+    }
+    if (!c->use_mg && c->so.kernel_variant == 0 && c->so.tile_tx == 0 && c->so.tile_tz == 0 && c->so.autotune) {
         rc = autotune(c);
         if (rc) {
             free_all(c);

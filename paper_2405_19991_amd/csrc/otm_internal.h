@@ -117,7 +117,10 @@ enum FinOp {
     FIN_OC,
     FIN_F_START,    // fused iteration: residual at the start of a solve
     FIN_F_REFRESH,  // fused iteration: float64 residual replaces the recursive one
-    FIN_GUESS       // scale factors of a start guess
+    FIN_GUESS,      // scale factors of a start guess
+    FIN_MG_RZ0,     // multigrid PCG: r.z after the V-cycle, (re)start with beta = 0
+    FIN_MG_RZ,      // multigrid PCG: r.z after the V-cycle -> beta
+    FIN_MG_UPDATE   // multigrid PCG: r.r after the update -> convergence
 };
 void launch_finalize(int op, int nblocks, const Workspace& ws, hipStream_t s, int64_t nn = 0, double eta = 0.5);
 
@@ -193,6 +196,44 @@ template <typename T>
 void launch_fused(int n, const TileShape& t, bool all_active, const T* r_in, const T* q_in, const T* p_in, T* r_out,
                   T* q_out, T* p_out, T* x, const T* dinv, const T* k, const Workspace& ws, hipStream_t s, int par,
                   bool chained, bool fin, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
+// Multigrid V-cycle preconditioner (otm_mg.hip), float32.
+constexpr int kMgMaxLevels = 10;
+constexpr float kMgOmega = 0.8f;  // damped Jacobi weight of the relaxation
+enum MgMarch { MG_NONE = 0, MG_RELAX = 1, MG_RESID = 2 };
+constexpr int kMgCoarseMax = 64;  // nodes of the coarsest level (direct solve)
+struct MgLevel {
+    int n = 0;
+    const float* k = nullptr;  // level conductivities (level 0: the solver's)
+    const float* dinv = nullptr;
+    float* kc = nullptr;       // owned (levels >= 1)
+    float* dinvc = nullptr;
+    float* x[2] = {nullptr, nullptr};
+    float* f = nullptr;        // level right-hand side (level 0: the residual, not owned)
+    float* t = nullptr;        // A x scratch
+    TileShape tile;
+};
+struct MgHierarchy {
+    int levels = 0;
+    int sweeps = 2;          // damped Jacobi steps before and after the coarse correction
+    float* minv = nullptr;   // inverse of the coarsest operator (at most 64 x 64)
+    MgLevel lv[kMgMaxLevels];
+};
+void launch_mg_coarsen(int nc, const float* kf, float* kc, float* dinv_c, hipStream_t s);
+// One z-march pass of a level (n even): out = x + w D^-1 (f - A x) (MG_RELAX)
+// or f - A x (MG_RESID), with x = in, or x = w D^-1 f when from_f; MG_RELAX
+// with partials writes the per-block sums f . out (t.blocks of them).
+void launch_mg_march(int n, const TileShape& t, bool from_f, int mode, const float* in, const float* dinv,
+                     const float* f, const float* k, float* out, double* partials, hipStream_t s);
+void launch_mg_restrict(int nc, const float* r, float* fc, hipStream_t s);
+// x_f += P x_c, or x_f = w D^-1 f + P x_c when f0 is given
+void launch_mg_prolong(int nc, const float* xc, float* xf, const float* f0, const float* dinv0, hipStream_t s);
+void launch_mg_coarse_setup(int n, const float* k, float* minv, hipStream_t s);
+void launch_mg_coarse_solve(int n, const float* minv, const float* f, float* x, hipStream_t s);
+// z = V(r) for the three loads, r = lv[0].f; *z_out receives the level-0
+// buffer that holds z.  The last relaxation writes the per-block sums r.z
+// into partials; returns their block count.
+int mg_vcycle(const MgHierarchy& H, double* partials, int max_blocks, hipStream_t s, const float** z_out);
+
 // Deterministic pseudo-random fill in [-0.5, 0.5) (timing inputs), and a constant fill.
 template <typename T>
 void launch_fill_hash(T* p, int64_t count, uint32_t seed, hipStream_t s);
@@ -208,7 +249,7 @@ template <typename T>
 void launch_apply_tiled(int n, const TileShape& t, const T* k, const T* x, T* y, hipStream_t s);
 template <typename T>
 void launch_update_vec(int n, T* x, T* r, const T* p, const T* q, const T* dinv, const Workspace& ws, hipStream_t s,
-                       bool fin = true);
+                       bool fin = true, int fin_op = FIN_UPDATE);
 
 // Batched launches (one launch covers every design).
 void launch_b_clamp(const BatchTab& t, double* rho, double lo, double hi, hipStream_t s);

@@ -505,6 +505,7 @@ __device__ __forceinline__ void fused_step(Scalars* sc, int l, double rz, double
 __device__ __forceinline__ void b_finalize(int op, int nblocks, const double* __restrict__ partials, Scalars* sc,
                                            int64_t nn, double eta) {
     __shared__ double tot[kMaxReduce];
+    if (op == FIN_OC && sc->oc_done) return;  // passes after convergence are empty
     switch (op) {
         case FIN_FILTER_SIMP: fin_sums<2>(partials, nblocks, tot); break;
         case FIN_SETUP:
@@ -519,6 +520,9 @@ __device__ __forceinline__ void b_finalize(int op, int nblocks, const double* __
         case FIN_F_START:
         case FIN_F_REFRESH: fin_sums<12>(partials, nblocks, tot); break;
         case FIN_GUESS: fin_sums<6>(partials, nblocks, tot); break;
+        case FIN_MG_RZ0:
+        case FIN_MG_RZ: fin_sums<3>(partials, nblocks, tot); break;
+        case FIN_MG_UPDATE: fin_sums<6>(partials, nblocks, tot); break;
         default: return;
     }
     if (threadIdx.x != 0) return;
@@ -603,6 +607,27 @@ __device__ __forceinline__ void b_finalize(int op, int nblocks, const double* __
                     sc->beta[l] = 0.0;
                     sc->rz[l] = rz;
                 }
+            }
+            break;
+        case FIN_MG_RZ0:
+        case FIN_MG_RZ:
+            // z = M^-1 r from the V-cycle; rz_prev holds the previous r.z of
+            // this preconditioner only (the residual kernels' r.D^-1 r goes to rz)
+            for (int l = 0; l < 3; ++l) {
+                if (!sc->active[l]) continue;
+                const double rz = tot[l];
+                sc->beta[l] = (op == FIN_MG_RZ && sc->rz_prev[l] > 0.0) ? rz / sc->rz_prev[l] : 0.0;
+                sc->rz_prev[l] = rz;
+                sc->rz[l] = rz;
+            }
+            break;
+        case FIN_MG_UPDATE:
+            // update with D^-1 := 1: sums [l] r.r, [3+l] r.r
+            for (int l = 0; l < 3; ++l) {
+                if (!sc->active[l]) continue;
+                sc->rr[l] = tot[3 + l];
+                sc->iters[l] += 1;
+                if (!(tot[3 + l] > sc->tol2 * sc->bb[l])) sc->active[l] = 0;
             }
             break;
         case FIN_GUESS:
@@ -788,7 +813,9 @@ void launch_oc_init(double vstar, int n, double eta, const Workspace& ws, hipStr
 
 void launch_oc_pass(int n, const double* rho, const double* q, double move, double rho_min, double eta,
                         const Workspace& ws, hipStream_t s) {
-    const int g = grid_for(cube(n), ws.max_blocks < 1024 ? ws.max_blocks : 1024);
+    // 512 blocks: two waves per SIMD for the candidate sums, and a short
+    // 31 x 512 reduction in the finalize
+    const int g = grid_for(cube(n), ws.max_blocks < 512 ? ws.max_blocks : 512);
     hipLaunchKernelGGL(k_oc_pass, dim3(g), dim3(kBlock), 0, s, cube(n), rho, q, move, rho_min, eta, ws.partials,
                        ws.counter, ws.sc);
     launch_finalize(FIN_OC, g, ws, s, cube(n), eta);
@@ -969,7 +996,8 @@ static int fin_width(int op) {
         case FIN_OC: return kOcCands;
         case FIN_F_START:
         case FIN_F_REFRESH: return 12;
-        case FIN_GUESS: return 6;
+        case FIN_GUESS:
+        case FIN_MG_UPDATE: return 6;
         default: return 3;
     }
 }

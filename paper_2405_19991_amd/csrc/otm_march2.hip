@@ -32,7 +32,13 @@ struct Pre2 {
 };
 
 // ALL: every load is active (DIR) -- removes the per-load branches.
-template <typename T, int WX, int TY, bool DIR, bool ALL>
+// MG (multigrid relaxation, float32 V-cycle): the operator's result at a
+// finished node feeds an epilogue instead of being stored: MG_RELAX writes
+// x + w D^-1 (f - A x), MG_RESID writes f - A x.  The input is x (DIR false;
+// f comes in through p_old and D^-1 through dinv, own nodes only) or
+// w D^-1 f (DIR true, r = f: the Jacobi step from zero), all loads active.
+// MG_RELAX with partials also sums f . x_new per load (r.z of the cycle).
+template <typename T, int WX, int TY, bool DIR, bool ALL, int MG = MG_NONE>
 __device__ __forceinline__ void march2_body(int bid_, int slot_, int n, int tz, int ntx, int nty,
                                             const T* __restrict__ r, const T* __restrict__ dinv,
                                             const T* __restrict__ p_old, T* __restrict__ p_new,
@@ -65,7 +71,7 @@ __device__ __forceinline__ void march2_body(int bid_, int slot_, int n, int tz, 
 
     bool act[3] = {true, true, true};
     T beta[3] = {(T)0, (T)0, (T)0};
-    if (DIR) {
+    if (DIR && MG == MG_NONE) {
 #pragma unroll
         for (int l = 0; l < 3; ++l) {
             act[l] = ALL ? true : (sc->active[l] != 0);
@@ -131,12 +137,13 @@ __device__ __forceinline__ void march2_body(int bid_, int slot_, int n, int tz, 
         const int64_t zoff = plane_off(P);
         const T* dp = dinv + zoff;
         const T* kp = k + zoff;
-        if (DIR) f.dv = ld_at<T2>(dp, bo);
+        if (DIR || MG != MG_NONE) f.dv = ld_at<T2>(dp, bo);
 #pragma unroll
         for (int l = 0; l < 3; ++l) {
             if (!act[l]) continue;
             f.r[l] = ld_at<T2>(r + l * nn + zoff, bo);
-            if (DIR && beta[l] != (T)0) f.po[l] = ld_at<T2>(p_old + l * nn + zoff, bo);
+            if (DIR && MG == MG_NONE && beta[l] != (T)0) f.po[l] = ld_at<T2>(p_old + l * nn + zoff, bo);
+            if (!DIR && MG != MG_NONE) f.po[l] = ld_at<T2>(p_old + l * nn + zoff, bo);  // own f
         }
         f.k = ld_at<T2>(kp, bo);
         if (has_h) {
@@ -152,6 +159,7 @@ __device__ __forceinline__ void march2_body(int bid_, int slot_, int n, int tz, 
     };
 
     T2 pP[3];
+    T2 fP[3], dP;  // MG: own f and D^-1 of the stored plane
     auto store_plane = [&](int P, const Pre2<T, DIR>& f) {
         const int slot = P & 1;
         const bool in_range = P >= z0 && P < z1;
@@ -162,7 +170,10 @@ __device__ __forceinline__ void march2_body(int bid_, int slot_, int n, int tz, 
             if (!act[l]) continue;
             T2 val = f.r[l];
             hv[l] = f.hr[l];
-            if (DIR) {
+            if (DIR && MG != MG_NONE) {
+                val = ((T)kMgOmega * f.dv) * f.r[l];
+                hv[l] = ((T)kMgOmega * f.hdv) * f.hr[l];
+            } else if (DIR) {
                 val = f.dv * f.r[l];
                 hv[l] = f.hdv * f.hr[l];
                 if (beta[l] != (T)0) {
@@ -172,8 +183,10 @@ __device__ __forceinline__ void march2_body(int bid_, int slot_, int n, int tz, 
             }
             *reinterpret_cast<T2*>(&sp[slot][l][lp]) = val;
             pP[l] = val;
+            if (MG != MG_NONE) fP[l] = DIR ? f.r[l] : f.po[l];
         }
-        if (DIR && in_range && own) {
+        if (MG != MG_NONE) dP = f.dv;
+        if (DIR && MG == MG_NONE && in_range && own) {
 #pragma unroll
             for (int l = 0; l < 3; ++l)
                 if (act[l]) st_at<T2>(p_new + l * nn + zoff, bo, pP[l]);
@@ -189,12 +202,13 @@ __device__ __forceinline__ void march2_body(int bid_, int slot_, int n, int tz, 
 
     const T w = (T)(1.0 / 12.0);
     const T third = (T)(1.0 / 3.0);
-    T2 yA[3], yB[3], pB[3];
+    T2 yA[3], yB[3], pB[3], fB[3], dB = (T2)((T)0);
 #pragma unroll
     for (int l = 0; l < 3; ++l) {
         yA[l] = (T2)((T)0);
         yB[l] = (T2)((T)0);
         pB[l] = (T2)((T)0);
+        fB[l] = (T2)((T)0);
     }
     // conductivities of the previous element plane around nodes a and b:
     // kp = elements (i-1, i, i+1) at rows j-1 (m) and j (c)
@@ -261,7 +275,25 @@ __device__ __forceinline__ void march2_body(int bid_, int slot_, int n, int tz, 
             yB[l].x = -w * oca;
             yB[l].y = -w * ocb;
         }
-        if (done && own) {
+        if (MG != MG_NONE) {
+            if (done && own) {
+                const T2 wd = (T)kMgOmega * dB;
+#pragma unroll
+                for (int l = 0; l < 3; ++l) {
+                    const T2 res = fB[l] - qd[l];
+                    if (MG == MG_RELAX) {
+                        const T2 xn = pB[l] + wd * res;
+                        st_at<T2>(q + l * nn + zdone, bo, xn);
+                        acc[l] += (double)fB[l].x * (double)xn.x + (double)fB[l].y * (double)xn.y;
+                    } else {
+                        st_at<T2>(q + l * nn + zdone, bo, res);
+                    }
+                }
+            }
+#pragma unroll
+            for (int l = 0; l < 3; ++l) fB[l] = fP[l];
+            dB = dP;
+        } else if (done && own) {
 #pragma unroll
             for (int l = 0; l < 3; ++l) {
                 if (!act[l]) continue;
@@ -299,7 +331,11 @@ __device__ __forceinline__ void march2_body(int bid_, int slot_, int n, int tz, 
         __syncthreads();
         compute(P);
     }
-    if (!DIR) return;
+    if (MG == MG_RELAX) {
+        if (partials) block_partials_at<3>(acc, partials, slot_);
+        return;
+    }
+    if (!DIR || MG != MG_NONE) return;
     block_partials_at<3>(acc, partials, slot_);
 }
 
@@ -321,6 +357,43 @@ __global__ void __launch_bounds__(WX* TY) __attribute__((amdgpu_waves_per_eu(3))
                  float* __restrict__ y) {
     march2_body<float, WX, TY, false, true>(xcd_tile(blockIdx.x, gridDim.x), blockIdx.x, n, tz, ntx, nty, x, nullptr,
                                             nullptr, nullptr, k, y, nullptr, nullptr);
+}
+
+// Multigrid relaxation / residual pass (float32), see march2_body.
+template <int WX, int TY, bool FROM_F, int MG>
+__global__ void __launch_bounds__(WX* TY) __attribute__((amdgpu_waves_per_eu(2)))
+    k_mg_march(int n, int tz, int ntx, int nty, const float* __restrict__ in, const float* __restrict__ dinv,
+               const float* __restrict__ f, const float* __restrict__ k, float* __restrict__ out,
+               double* __restrict__ partials) {
+    march2_body<float, WX, TY, FROM_F, true, MG>(xcd_tile(blockIdx.x, gridDim.x), blockIdx.x, n, tz, ntx, nty,
+                                                 FROM_F ? f : in, dinv, f, nullptr, k, out, partials, nullptr);
+}
+
+template <int WX, int TY>
+static void launch_mg_march_t(int n, const TileShape& t, bool from_f, int mode, const float* in, const float* dinv,
+                              const float* f, const float* k, float* out, double* partials, hipStream_t s) {
+    const int ntx = (n + t.tx - 1) / t.tx, nty = (n + t.ty - 1) / t.ty;
+    const dim3 g(t.blocks), b(kBlock);
+    if (from_f && mode == MG_RELAX)
+        hipLaunchKernelGGL((k_mg_march<WX, TY, true, MG_RELAX>), g, b, 0, s, n, t.tz, ntx, nty, in, dinv, f, k, out,
+                           partials);
+    else if (from_f)
+        hipLaunchKernelGGL((k_mg_march<WX, TY, true, MG_RESID>), g, b, 0, s, n, t.tz, ntx, nty, in, dinv, f, k, out,
+                           partials);
+    else if (mode == MG_RELAX)
+        hipLaunchKernelGGL((k_mg_march<WX, TY, false, MG_RELAX>), g, b, 0, s, n, t.tz, ntx, nty, in, dinv, f, k, out,
+                           partials);
+    else
+        hipLaunchKernelGGL((k_mg_march<WX, TY, false, MG_RESID>), g, b, 0, s, n, t.tz, ntx, nty, in, dinv, f, k, out,
+                           partials);
+}
+
+void launch_mg_march(int n, const TileShape& t, bool from_f, int mode, const float* in, const float* dinv,
+                     const float* f, const float* k, float* out, double* partials, hipStream_t s) {
+    if (t.tx == 32)
+        launch_mg_march_t<16, 16>(n, t, from_f, mode, in, dinv, f, k, out, partials, s);
+    else
+        launch_mg_march_t<32, 8>(n, t, from_f, mode, in, dinv, f, k, out, partials, s);
 }
 
 // ev0/ev1 (optional): HIP events recorded at the kernel's start and end.

@@ -521,7 +521,7 @@ void launch_apply_tiled(int n, const TileShape& t, const T* k, const T* x, T* y,
 
 template <typename T>
 void launch_update_vec(int n, T* x, T* r, const T* p, const T* q, const T* dinv, const Workspace& ws, hipStream_t s,
-                       bool fin) {
+                       bool fin, int fin_op) {
     constexpr int V = 16 / sizeof(T);
     const int64_t nn = cube(n);
     if (nn % V != 0) {
@@ -531,7 +531,7 @@ void launch_update_vec(int n, T* x, T* r, const T* p, const T* q, const T* dinv,
     const int g = grid_for(nn / V, ws.max_blocks);
     hipLaunchKernelGGL((k_update_vec<T, V>), dim3(g), dim3(kBlock), 0, s, nn, x, r, p, q, dinv, ws.partials,
                        ws.counter, ws.sc);
-    if (fin) launch_finalize(FIN_UPDATE, g, ws, s);
+    if (fin) launch_finalize(fin_op, g, ws, s);
 }
 
 template void launch_dir_apply<double>(int, const TileShape&, const double*, const double*, const double*, double*,
@@ -547,9 +547,9 @@ template void launch_apply_march<float>(int, const TileShape&, const float*, con
 template void launch_apply_tiled<double>(int, const TileShape&, const double*, const double*, double*, hipStream_t);
 template void launch_apply_tiled<float>(int, const TileShape&, const float*, const float*, float*, hipStream_t);
 template void launch_update_vec<double>(int, double*, double*, const double*, const double*, const double*,
-                                        const Workspace&, hipStream_t, bool);
+                                        const Workspace&, hipStream_t, bool, int);
 template void launch_update_vec<float>(int, float*, float*, const float*, const float*, const float*,
-                                       const Workspace&, hipStream_t, bool);
+                                       const Workspace&, hipStream_t, bool, int);
 
 }  // namespace otm
 

@@ -93,13 +93,14 @@ def _solve_record(h, kappa, st, ms):
 
 
 def time_to_tol(n: int, rho, target, vf: float, precision: str, guess: str, net=None,
-                tol: float = 1e-6) -> Dict[str, float]:
+                tol: float = 1e-6, preconditioner: str = "jacobi") -> Dict[str, float]:
     """PCG iterations and wall time of one homogenization of the density rho
     from a zero or learned start (a warm-up solve of the same state first).
     The time includes the network's forward pass for the learned start."""
     import torch
     from .api import Homogenization
-    with Homogenization(n, (1.0, 1e-3), target, vf=vf, tol=tol, precision=precision, guess=guess) as h:
+    with Homogenization(n, (1.0, 1e-3), target, vf=vf, tol=tol, precision=precision, guess=guess,
+                        preconditioner=preconditioner) as h:
         if net is not None:
             h.set_network(net)
         h.set_density(rho)
@@ -138,6 +139,8 @@ def evaluate(net, n: int = 128, seed: int = 303, at_iter: int = 5, tol: float = 
         "previous_mixed": prev,
         "learned_mixed": time_to_tol(n, rho_k, tgt, vf, "mixed", "learned", net, tol=tol),
         "learned_fp64": time_to_tol(n, rho_k, tgt, vf, "fp64", "learned", net, tol=tol),
+        "zero_mixed_mg": time_to_tol(n, rho_k, tgt, vf, "mixed", "zero", tol=tol, preconditioner="mg"),
+        "learned_mixed_mg": time_to_tol(n, rho_k, tgt, vf, "mixed", "learned", net, tol=tol, preconditioner="mg"),
     }
 
 

@@ -81,3 +81,28 @@ def test_batch_create_rejects_odd_or_bad_sizes(L):
     assert L.otm_batch_create(arr, 2, None, None, None, None, ctypes.byref(h)) == N.OTM_EINVAL
     assert L.otm_batch_create(arr, 0, None, None, None, None, ctypes.byref(h)) == N.OTM_EINVAL
     assert L.otm_batch_last_error(None) == b"null batch"
+
+
+@pytest.mark.parametrize("n,precision,variant,sweeps", [(10, 1, 0, 2), (4, 1, 0, 2), (7, 1, 0, 2), (16, 0, 0, 2),
+                                                        (16, 1, 4, 2), (16, 1, 0, 0), (16, 1, 0, 9)])
+def test_multigrid_options_rejected(L, n, precision, variant, sweeps):
+    """The V-cycle needs n = m 2^j (m in {3, 4}, n >= 6), float32 Krylov vectors,
+    the two-pass iteration and 1..8 relaxation steps."""
+    from paper_2405_19991_amd import _native as N
+    p = N.Problem()
+    p.n, p.k0, p.kmin, p.penal, p.filter_radius, p.vf = n, 1.0, 1e-3, 3.0, 1.5, 0.3
+    s, o, g = N.default_options()
+    s.precision, s.kernel_variant, s.preconditioner, s.mg_sweeps = precision, variant, N.OTM_PRECOND_MG, sweeps
+    h = ctypes.c_void_p()
+    assert L.otm_create(ctypes.byref(p), ctypes.byref(s), None, None, None, ctypes.byref(h)) == N.OTM_EINVAL
+    assert not h.value
+
+
+def test_batch_rejects_multigrid(L):
+    from paper_2405_19991_amd import _native as N
+    arr = (N.Problem * 1)()
+    arr[0].n, arr[0].k0, arr[0].kmin, arr[0].penal, arr[0].filter_radius, arr[0].vf = 16, 1.0, 1e-3, 3.0, 1.5, 0.3
+    s, o, g = N.default_options()
+    s.preconditioner = N.OTM_PRECOND_MG
+    h = ctypes.c_void_p()
+    assert L.otm_batch_create(arr, 1, ctypes.byref(s), None, None, None, ctypes.byref(h)) == N.OTM_EUNSUPPORTED
