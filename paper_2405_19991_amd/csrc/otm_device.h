@@ -18,6 +18,52 @@ __device__ __forceinline__ void wave_reduce(double (&v)[NV]) {
     }
 }
 
+constexpr int pow2_up(int x) {
+    int p = 1;
+    while (p < x) p <<= 1;
+    return p;
+}
+
+// One step of the transposed wave reduction: lanes whose bit O is set keep
+// the upper half of the C values and send the lower half to their partner
+// (lane ^ O), which keeps the lower half; both add what they receive.  idx
+// collects the kept halves' bits.  With one value left, plain butterfly steps
+// finish the sum over the remaining lane bits.
+template <int C, int O>
+__device__ __forceinline__ void spread_step(double* a, int lane, int& idx) {
+    if constexpr (C > 1 && O > 0) {
+        constexpr int H = C / 2;
+        const bool hi = (lane & O) != 0;
+#pragma unroll
+        for (int j = 0; j < H; ++j) {
+            const double send = hi ? a[j] : a[j + H];
+            const double keep = hi ? a[j + H] : a[j];
+            a[j] = keep + __shfl_xor(send, O, 64);
+        }
+        idx = 2 * idx + (hi ? 1 : 0);
+        spread_step<H, O / 2>(a, lane, idx);
+    } else if constexpr (O > 0) {
+        a[0] += __shfl_xor(a[0], O, 64);
+        spread_step<C, O / 2>(a, lane, idx);
+    }
+}
+
+// Wave sums of NV values at about NV cross-lane moves instead of 6 NV: on
+// return every lane holds in a[0] the wave total of value idx (lanes that
+// differ only in their low log2(64 / P) bits hold the same one; P = NV rounded
+// up to a power of two).  Fixed order: deterministic.
+template <int NV>
+__device__ __forceinline__ double wave_reduce_spread(const double (&v)[NV], int& idx) {
+    constexpr int P = pow2_up(NV);
+    static_assert(P <= 64, "at most 64 values");
+    double a[P];
+#pragma unroll
+    for (int i = 0; i < P; ++i) a[i] = i < NV ? v[i] : 0.0;
+    idx = 0;
+    spread_step<P, 32>(a, threadIdx.x & 63, idx);
+    return a[0];
+}
+
 // Block-level sum of NV values; threads 0..NV-1 write partials[slot*NV + t]
 // (slot = blockIdx.x unless a persistent block processes several work items).
 // Uses a fixed reduction order (deterministic for a fixed launch shape).
@@ -26,11 +72,9 @@ __device__ __forceinline__ void block_partials_at(double (&v)[NV], double* parti
     __shared__ double sh[NV][kBlock / 64];
     const int tid = threadIdx.x;
     const int lane = tid & 63, w = tid >> 6;
-    wave_reduce<NV>(v);
-    if (lane == 0) {
-#pragma unroll
-        for (int i = 0; i < NV; ++i) sh[i][w] = v[i];
-    }
+    int idx;
+    const double t = wave_reduce_spread<NV>(v, idx);
+    if ((lane & (64 / pow2_up(NV) - 1)) == 0 && idx < NV) sh[idx][w] = t;
     __syncthreads();
     if (tid < NV) {
         double s = 0.0;
@@ -53,11 +97,9 @@ __device__ __forceinline__ void block_partials_vm(double (&v)[NV], double* parti
     __shared__ double sh[NV][kBlock / 64];
     const int tid = threadIdx.x;
     const int lane = tid & 63, w = tid >> 6;
-    wave_reduce<NV>(v);
-    if (lane == 0) {
-#pragma unroll
-        for (int i = 0; i < NV; ++i) sh[i][w] = v[i];
-    }
+    int idx;
+    const double t = wave_reduce_spread<NV>(v, idx);
+    if ((lane & (64 / pow2_up(NV) - 1)) == 0 && idx < NV) sh[idx][w] = t;
     __syncthreads();
     if (tid < NV) {
         double s = 0.0;

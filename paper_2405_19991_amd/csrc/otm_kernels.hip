@@ -395,36 +395,38 @@ __global__ void __launch_bounds__(kBlock) k_oc_prepare(int64_t nn, const double*
 // Candidates of the next kOcLevels bisection levels below [l1, l2], in
 // breadth-first order of the midpoint tree, each computed exactly as the
 // sequential bisection would: mid = 0.5 (lo + hi) of its parent interval.
-__device__ void oc_make_candidates(Scalars* sc, double eta) {
-    double lo[kOcCands], hi[kOcCands];
-    lo[0] = sc->l1;
-    hi[0] = sc->l2;
-#pragma unroll
-    for (int t = 0; t < kOcCands; ++t) {
-        const double mid = 0.5 * (lo[t] + hi[t]);
-        sc->cand[t] = mid;
-        sc->cpow[t] = (eta == 0.5) ? 1.0 / sqrt(mid) : pow(mid, -eta);
-        const int cl = 2 * t + 1, cr = 2 * t + 2;
-        if (cl < kOcCands) {
-            lo[cl] = lo[t];
-            hi[cl] = mid;
-        }
-        if (cr < kOcCands) {
-            lo[cr] = mid;
-            hi[cr] = hi[t];
-        }
+// The bisection tree's candidates below [l1, l2], node t at lane t (t <
+// kOcCands): the lane walks from the root to its node, halving the interval
+// with the same mid-point arithmetic as step-by-step bisection, so each
+// candidate equals the mid-point that sequential bisection would reach there.
+__device__ void oc_candidates_lane(Scalars* sc, double l1, double l2, double eta) {
+    const int t = threadIdx.x;
+    if (t >= kOcCands) return;
+    int path[kOcLevels];
+    int depth = 0;
+    for (int u = t; u > 0; u = (u - 1) / 2) path[depth++] = u & 1;  // 1: left child
+    double lo = l1, hi = l2;
+    for (int d = depth - 1; d >= 0; --d) {
+        const double mid = 0.5 * (lo + hi);
+        if (path[d])
+            hi = mid;
+        else
+            lo = mid;
     }
+    const double mid = 0.5 * (lo + hi);
+    sc->cand[t] = mid;
+    sc->cpow[t] = (eta == 0.5) ? 1.0 / sqrt(mid) : pow(mid, -eta);
 }
 
 __global__ void k_oc_init(Scalars* sc, double vstar_n, double eta) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) {
+    if (threadIdx.x == 0) {
         sc->l1 = 0.0;
         sc->l2 = 1e9;
         sc->vstar_n = vstar_n;
         sc->oc_steps = 0;
         sc->oc_done = 0;
-        oc_make_candidates(sc, eta);
     }
+    oc_candidates_lane(sc, 0.0, 1e9, eta);
 }
 
 // One pass: sum clamp(q c_m, lo, hi) for every candidate, then walk the tree
@@ -439,6 +441,7 @@ __device__ __forceinline__ void b_oc_pass(int bid_, int nblk_, int64_t nn, const
     double acc[kOcCands];
 #pragma unroll
     for (int t = 0; t < kOcCands; ++t) acc[t] = 0.0;
+#pragma unroll 2
     for (int64_t e = (int64_t)bid_ * kBlock + threadIdx.x; e < nn; e += (int64_t)nblk_ * kBlock) {
         const double r = rho[e], qe = q[e];
         const double lo = fmax(rho_min, r - move), hi = fmin(1.0, r + move);
@@ -490,6 +493,30 @@ __device__ __forceinline__ void fin_sums(const double* partials, int nblocks, do
     final_sums<NV>(partials, nblocks, tot);
 }
 
+// The OC candidates' sums (31 per block, slot-major): lane i of each 32-lane
+// group reads value i, so a wave reads two blocks' rows contiguously; the
+// groups' results are added in group order (fixed order).
+__device__ __forceinline__ void fin_sums_oc(const double* partials, int nblocks, double* tot) {
+    static_assert(kOcCands <= 32, "one lane per candidate");
+    constexpr int G = kBlock / 32;
+    __shared__ double sh[G][32];
+    const int g = threadIdx.x / 32, i = threadIdx.x % 32;
+    double v = 0.0;
+    if (i < kOcCands) {
+#pragma unroll 8
+        for (int b = g; b < nblocks; b += G) v += partials[(size_t)b * kOcCands + i];
+    }
+    sh[g][i] = v;
+    __syncthreads();
+    if (threadIdx.x < kOcCands) {
+        double s = 0.0;
+#pragma unroll
+        for (int q = 0; q < G; ++q) s += sh[q][threadIdx.x];
+        tot[threadIdx.x] = s;
+    }
+    __syncthreads();
+}
+
 // Step of the fused iteration from the current residual's r.z (rz) and the
 // pending direction's p.q, q.D^-1 q (stored) and q.z (qz):
 // alpha = rz / pq; the next r.z follows from expanding (r - alpha q)^T D^-1 (r - alpha q).
@@ -516,7 +543,7 @@ __device__ __forceinline__ void b_finalize(int op, int nblocks, const double* __
         case FIN_RES_REFRESH: fin_sums<9>(partials, nblocks, tot); break;
         case FIN_UPDATE:
         case FIN_ENERGY: fin_sums<6>(partials, nblocks, tot); break;
-        case FIN_OC: fin_sums<kOcCands>(partials, nblocks, tot); break;
+        case FIN_OC: fin_sums_oc(partials, nblocks, tot); break;
         case FIN_F_START:
         case FIN_F_REFRESH: fin_sums<12>(partials, nblocks, tot); break;
         case FIN_GUESS: fin_sums<6>(partials, nblocks, tot); break;
@@ -524,6 +551,46 @@ __device__ __forceinline__ void b_finalize(int op, int nblocks, const double* __
         case FIN_MG_RZ: fin_sums<3>(partials, nblocks, tot); break;
         case FIN_MG_UPDATE: fin_sums<6>(partials, nblocks, tot); break;
         default: return;
+    }
+    if (op == FIN_OC) {
+        // walk the candidate tree with the sequential stopping rule (width
+        // <= 1e-13 (l1 + l2), 200 halvings), then the next pass's candidates
+        __shared__ double sl[2];
+        __shared__ int sdone;
+        if (threadIdx.x == 0) {
+            double l1 = sc->l1, l2 = sc->l2;
+            int steps = sc->oc_steps;
+            int node = 0;
+            int done = 0;
+            for (int lev = 0; lev < kOcLevels; ++lev) {
+                if (steps >= 200 || (l2 - l1) <= 1e-13 * (l1 + l2)) {
+                    done = 1;
+                    break;
+                }
+                const double mid = sc->cand[node];
+                const double vol = tot[node] / (double)nn;
+                if (vol > sc->vstar_n / (double)nn) {
+                    l1 = mid;
+                    node = 2 * node + 2;
+                } else {
+                    l2 = mid;
+                    node = 2 * node + 1;
+                }
+                ++steps;
+            }
+            if (!done && (steps >= 200 || (l2 - l1) <= 1e-13 * (l1 + l2))) done = 1;
+            sc->l1 = l1;
+            sc->l2 = l2;
+            sc->oc_steps = steps;
+            sc->lam = 0.5 * (l1 + l2);
+            if (done) sc->oc_done = 1;
+            sl[0] = l1;
+            sl[1] = l2;
+            sdone = done;
+        }
+        __syncthreads();
+        if (!sdone) oc_candidates_lane(sc, sl[0], sl[1], eta);
+        return;
     }
     if (threadIdx.x != 0) return;
     switch (op) {
@@ -636,39 +703,6 @@ __device__ __forceinline__ void b_finalize(int op, int nblocks, const double* __
                 sc->gscale[l] = (bx > 0.0 && xax > 0.0) ? bx / xax : 0.0;
             }
             break;
-        case FIN_OC: {
-            if (sc->oc_done) break;
-            double l1 = sc->l1, l2 = sc->l2;
-            int steps = sc->oc_steps;
-            int node = 0;
-            int done = 0;
-            for (int lev = 0; lev < kOcLevels; ++lev) {
-                if (steps >= 200 || (l2 - l1) <= 1e-13 * (l1 + l2)) {
-                    done = 1;
-                    break;
-                }
-                const double mid = sc->cand[node];
-                const double vol = tot[node] / (double)nn;
-                if (vol > sc->vstar_n / (double)nn) {
-                    l1 = mid;
-                    node = 2 * node + 2;
-                } else {
-                    l2 = mid;
-                    node = 2 * node + 1;
-                }
-                ++steps;
-            }
-            if (!done && (steps >= 200 || (l2 - l1) <= 1e-13 * (l1 + l2))) done = 1;
-            sc->l1 = l1;
-            sc->l2 = l2;
-            sc->oc_steps = steps;
-            sc->lam = 0.5 * (l1 + l2);
-            if (done)
-                sc->oc_done = 1;
-            else
-                oc_make_candidates(sc, eta);
-            break;
-        }
         default: break;
     }
 }
@@ -813,8 +847,7 @@ void launch_oc_init(double vstar, int n, double eta, const Workspace& ws, hipStr
 
 void launch_oc_pass(int n, const double* rho, const double* q, double move, double rho_min, double eta,
                         const Workspace& ws, hipStream_t s) {
-    // 512 blocks: two waves per SIMD for the candidate sums, and a short
-    // 31 x 512 reduction in the finalize
+    // 512 blocks: a short 31 x 512 reduction in the finalize
     const int g = grid_for(cube(n), ws.max_blocks < 512 ? ws.max_blocks : 512);
     hipLaunchKernelGGL(k_oc_pass, dim3(g), dim3(kBlock), 0, s, cube(n), rho, q, move, rho_min, eta, ws.partials,
                        ws.counter, ws.sc);
@@ -963,15 +996,17 @@ __global__ void __launch_bounds__(kBlock) kb_oc_prepare(BatchTab t, const double
 
 __global__ void kb_oc_init(BatchTab t, Scalars* sc, const double* vstar, double eta) {
     const int d = blockIdx.x;
-    if (threadIdx.x != 0 || d >= t.count) return;
+    if (d >= t.count) return;
     const int n = t.desc[d].n;
     Scalars* s = sc + d;
-    s->l1 = 0.0;
-    s->l2 = 1e9;
-    s->vstar_n = vstar[d] * (double)n * n * n;
-    s->oc_steps = 0;
-    s->oc_done = 0;
-    oc_make_candidates(s, eta);
+    if (threadIdx.x == 0) {
+        s->l1 = 0.0;
+        s->l2 = 1e9;
+        s->vstar_n = vstar[d] * (double)n * n * n;
+        s->oc_steps = 0;
+        s->oc_done = 0;
+    }
+    oc_candidates_lane(s, 0.0, 1e9, eta);
 }
 
 __global__ void __launch_bounds__(kBlock) kb_oc_pass(BatchTab t, const double* rho, const double* q, double move,
