@@ -56,7 +56,8 @@ def parse():
     ap.add_argument("--preconditioner", choices=["jacobi", "mg"], default="jacobi",
                     help="preconditioner of the timed design iterations (mg: mixed precision only)")
     ap.add_argument("--no-mg", action="store_true", help="skip the multigrid leg")
-    ap.add_argument("--mg-sweeps", type=int, default=2, help="relaxation steps per level and leg of the V-cycle")
+    ap.add_argument("--mg-sweeps", type=int, default=1, help="relaxation steps per leg of the V-cycle, finest level")
+    ap.add_argument("--mg-coarse-sweeps", type=int, default=2, help="the same on coarser levels (0: as --mg-sweeps)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="after the timed steps, run three 64 MiB device copies (a kernel of known traffic, "
                          "for scaling hardware byte counters)")
@@ -166,14 +167,15 @@ def batch_leg(steps: int, log):
             "steps": steps}
 
 
-def multigrid_leg(w, steps: int, log, sweeps: int = 2):
+def multigrid_leg(w, steps: int, log, sweeps: int = 1, coarse_sweeps: int = 2):
     """The timed workload's design iterations with one multigrid V-cycle as
     the preconditioner (mixed precision, same start and tolerance): one
     warm-up design iteration, then `steps` timed ones."""
     import torch
     from paper_2405_19991_amd import Homogenization
     with Homogenization(w.n, (w.k0, w.kmin), w.target, vf=w.vf, penal=w.penal, filter_radius=w.rfilter,
-                        precision="mixed", tol=w.tol, preconditioner="mg", mg_sweeps=sweeps) as h:
+                        precision="mixed", tol=w.tol, preconditioner="mg", mg_sweeps=sweeps,
+                        mg_coarse_sweeps=coarse_sweeps) as h:
         h.set_density(w.rho0)
         first = h.step()
         torch.cuda.synchronize()
@@ -182,7 +184,7 @@ def multigrid_leg(w, steps: int, log, sweeps: int = 2):
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
     iters = sum(sum(r["pcg_iters"]) for r in recs)
-    out = {"workload": w.name + "_mixed_mg", "n": w.n, "tol": w.tol, "mg_sweeps": sweeps, "s_per_oc_iter": dt / steps,
+    out = {"workload": w.name + "_mixed_mg", "n": w.n, "tol": w.tol, "mg_sweeps": [sweeps, coarse_sweeps], "s_per_oc_iter": dt / steps,
            "pcg_iters_per_step": iters / steps, "ms_solve_per_step": sum(r["ms_solve"] for r in recs) / steps,
            "pcg_dof_updates_per_s": w.n ** 3 * iters / dt, "first_kappa": first["kappa"],
            "first_pcg_iters": first["pcg_iters"], "steps": steps}
@@ -291,7 +293,7 @@ def main():
     h = Homogenization(n, (w.k0, w.kmin), w.target, vf=w.vf, penal=w.penal, filter_radius=w.rfilter,
                        precision=args.precision, guess=args.guess, tol=w.tol, kernel_variant=args.variant,
                        tile_tx=args.solver_tx, tile_tz=args.solver_tz, preconditioner=args.preconditioner,
-                       mg_sweeps=args.mg_sweeps)
+                       mg_sweeps=args.mg_sweeps, mg_coarse_sweeps=args.mg_coarse_sweeps)
     h.set_density(w.rho0)
     def log(msg):
         print(msg, file=sys.stderr, flush=True)
@@ -405,7 +407,7 @@ def main():
         del src, dst
     log(f"apply kernel {us:.2f} us ({achieved:.0f} GB/s algorithmic)")
     if not args.no_mg and args.preconditioner == "jacobi" and args.precision == "mixed" and n == 128:
-        mg = multigrid_leg(w, args.steps, log, args.mg_sweeps)
+        mg = multigrid_leg(w, args.steps, log, args.mg_sweeps, args.mg_coarse_sweeps)
         mg["kappa_rel_err_vs_oracle"] = oracle_tensor_error(w, mg.pop("first_kappa"), args.tol)
         out["multigrid"] = mg
     if not args.no_batch:

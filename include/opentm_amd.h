@@ -132,7 +132,9 @@ typedef struct {
                                OTM_PRECOND_MG kernel_variant must be 0 and no autotuning
                                is done */
     int32_t mg_sweeps;      /* OTM_PRECOND_MG: relaxation steps before and after each
-                               coarse correction, 1..8 (default 2) */
+                               coarse correction on the finest level, 1..8 (default 1) */
+    int32_t mg_coarse_sweeps; /* the same on the coarser levels, 0..8; 0 = mg_sweeps
+                                 (default 2) */
 } otm_solver_opts;
 
 typedef struct {

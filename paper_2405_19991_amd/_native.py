@@ -58,7 +58,8 @@ class SolverOpts(ctypes.Structure):
     _fields_ = [("precision", ctypes.c_int32), ("guess", ctypes.c_int32), ("tol", ctypes.c_double),
                 ("max_iter", ctypes.c_int32), ("check_every", ctypes.c_int32), ("reliable_delta", ctypes.c_double),
                 ("kernel_variant", ctypes.c_int32), ("tile_tz", ctypes.c_int32), ("tile_tx", ctypes.c_int32),
-                ("autotune", ctypes.c_int32), ("preconditioner", ctypes.c_int32), ("mg_sweeps", ctypes.c_int32)]
+                ("autotune", ctypes.c_int32), ("preconditioner", ctypes.c_int32), ("mg_sweeps", ctypes.c_int32),
+                ("mg_coarse_sweeps", ctypes.c_int32)]
 
 
 class OcOpts(ctypes.Structure):

@@ -37,7 +37,7 @@ class Homogenization:
                  reliable_delta: float = 1e-2, move: float = 0.05, eta: float = 0.5, rho_min: float = 1e-3,
                  governor: Optional[Dict[str, float]] = None, stream=None, kernel_variant: int = 0,
                  tile_tz: int = 0, tile_tx: int = 0, autotune: bool = True, preconditioner: str = "jacobi",
-                 mg_sweeps: int = 2):
+                 mg_sweeps: int = 1, mg_coarse_sweeps: int = 2):
         L = N.lib()
         self.n = int(n)
         p = N.Problem()
@@ -57,7 +57,7 @@ class Homogenization:
         s.kernel_variant, s.tile_tz, s.tile_tx = int(kernel_variant), int(tile_tz), int(tile_tx)
         s.autotune = int(bool(autotune))
         s.preconditioner = {"jacobi": N.OTM_PRECOND_JACOBI, "mg": N.OTM_PRECOND_MG}[preconditioner]
-        s.mg_sweeps = int(mg_sweeps)
+        s.mg_sweeps, s.mg_coarse_sweeps = int(mg_sweeps), int(mg_coarse_sweeps)
         o.move, o.eta, o.rho_min = float(move), float(eta), float(rho_min)
         for key, val in (governor or {}).items():
             setattr(g, key, val)

@@ -755,6 +755,7 @@ int mg_build(otm_ctx* c) {
     H.levels = mg_levels(c->n, ns);
     if (!H.levels) return fail(c, OTM_EINVAL, "multigrid needs n = m 2^j with m in {3, 4} and n >= 6");
     H.sweeps = c->so.mg_sweeps;
+    H.coarse_sweeps = c->so.mg_coarse_sweeps > 0 ? c->so.mg_coarse_sweeps : c->so.mg_sweeps;
     int rc = OTM_OK;
     for (int l = 0; l < H.levels && !rc; ++l) {
         MgLevel& a = H.lv[l];
@@ -996,7 +997,8 @@ void otm_default_options(otm_solver_opts* s, otm_oc_opts* o, otm_governor_opts* 
         s->tile_tx = 0;
         s->autotune = 1;
         s->preconditioner = OTM_PRECOND_JACOBI;
-        s->mg_sweeps = 2;
+        s->mg_sweeps = 1;
+        s->mg_coarse_sweeps = 2;
     }
     if (o) {
         o->move = 0.05;
@@ -1059,7 +1061,7 @@ int otm_create(const otm_problem* problem, const otm_solver_opts* solver, const 
     if (c->so.preconditioner == OTM_PRECOND_MG) {
         int ns[kMgMaxLevels];
         if (c->so.precision != OTM_MIXED || c->so.kernel_variant != 0 || c->so.mg_sweeps < 1 ||
-            c->so.mg_sweeps > 8 || (c->so.tile_tx != 0 && c->so.tile_tx != 32 && c->so.tile_tx != 64) ||
+            c->so.mg_sweeps > 8 || c->so.mg_coarse_sweeps < 0 || c->so.mg_coarse_sweeps > 8 || (c->so.tile_tx != 0 && c->so.tile_tx != 32 && c->so.tile_tx != 64) ||
             !mg_levels(problem->n, ns)) {
             delete c;
             return OTM_EINVAL;

@@ -214,7 +214,8 @@ struct MgLevel {
 };
 struct MgHierarchy {
     int levels = 0;
-    int sweeps = 2;          // damped Jacobi steps before and after the coarse correction
+    int sweeps = 2;          // damped Jacobi steps before and after the coarse correction (finest level)
+    int coarse_sweeps = 2;   // the same on the coarser levels
     float* minv = nullptr;   // inverse of the coarsest operator (at most 64 x 64)
     MgLevel lv[kMgMaxLevels];
 };

@@ -137,7 +137,7 @@ __device__ __forceinline__ void march2_body(int bid_, int slot_, int n, int tz, 
         const int64_t zoff = plane_off(P);
         const T* dp = dinv + zoff;
         const T* kp = k + zoff;
-        if (DIR || MG != MG_NONE) f.dv = ld_at<T2>(dp, bo);
+        if (DIR || MG == MG_RELAX) f.dv = ld_at<T2>(dp, bo);
 #pragma unroll
         for (int l = 0; l < 3; ++l) {
             if (!act[l]) continue;
@@ -185,7 +185,7 @@ __device__ __forceinline__ void march2_body(int bid_, int slot_, int n, int tz, 
             pP[l] = val;
             if (MG != MG_NONE) fP[l] = DIR ? f.r[l] : f.po[l];
         }
-        if (MG != MG_NONE) dP = f.dv;
+        if (MG == MG_RELAX) dP = f.dv;
         if (DIR && MG == MG_NONE && in_range && own) {
 #pragma unroll
             for (int l = 0; l < 3; ++l)

@@ -234,12 +234,13 @@ void launch_mg_coarse_solve(int n, const float* minv, const float* f, float* x, 
 
 int mg_vcycle(const MgHierarchy& H, double* partials, int max_blocks, hipStream_t s, const float** z_out) {
     (void)max_blocks;
-    const int L = H.levels, nu = H.sweeps;
+    const int L = H.levels;
     int cur[kMgMaxLevels] = {};
     // down: nu relaxation steps from zero, the last one replaced by the
     // residual; restrict the residual (a.t)
     for (int l = 0; l < L - 1; ++l) {
         const MgLevel& a = H.lv[l];
+        const int nu = l == 0 ? H.sweeps : H.coarse_sweeps;
         int c = 0;
         if (nu == 1) {
             launch_mg_march(a.n, a.tile, true, MG_RESID, nullptr, a.dinv, a.f, a.k, a.t, nullptr, s);
@@ -262,6 +263,7 @@ int mg_vcycle(const MgHierarchy& H, double* partials, int max_blocks, hipStream_
     int nb = 0;
     for (int l = L - 2; l >= 0; --l) {
         const MgLevel& a = H.lv[l];
+        const int nu = l == 0 ? H.sweeps : H.coarse_sweeps;
         int c = cur[l];
         launch_mg_prolong(H.lv[l + 1].n, H.lv[l + 1].x[cur[l + 1]], a.x[c], nu == 1 ? a.f : nullptr,
                           nu == 1 ? a.dinv : nullptr, s);

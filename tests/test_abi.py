@@ -98,6 +98,19 @@ def test_multigrid_options_rejected(L, n, precision, variant, sweeps):
     assert not h.value
 
 
+def test_multigrid_coarse_sweeps_rejected(L):
+    from paper_2405_19991_amd import _native as N
+    p = N.Problem()
+    p.n, p.k0, p.kmin, p.penal, p.filter_radius, p.vf = 16, 1.0, 1e-3, 3.0, 1.5, 0.3
+    s, o, g = N.default_options()
+    assert (s.mg_sweeps, s.mg_coarse_sweeps) == (1, 2)
+    s.precision, s.preconditioner = N.OTM_MIXED, N.OTM_PRECOND_MG
+    h = ctypes.c_void_p()
+    for bad in (-1, 9):
+        s.mg_coarse_sweeps = bad
+        assert L.otm_create(ctypes.byref(p), ctypes.byref(s), None, None, None, ctypes.byref(h)) == N.OTM_EINVAL
+
+
 def test_batch_rejects_multigrid(L):
     from paper_2405_19991_amd import _native as N
     arr = (N.Problem * 1)()
