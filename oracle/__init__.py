@@ -13,7 +13,9 @@ What it computes (paper: Quan, Zhai, Fu, "OpenTM", arXiv 2405.19991):
   loads (Sec. 2.2, K T^(i) = f^(i); Sec. 2.4 enforceMacroLoad) -> plain
   conjugate gradients on the zero-mean subspace -> homogenized tensor
   (discrete homogenization formula, Sec. 2.2) as the 6-vector of Sec. 2.2.
-* ``objective``: the six-term squared error (Sec. 4.4, MSE objective).
+* ``objective``: the six-term squared error (Sec. 4.4, MSE objective), and
+  the relative and l1 objectives of the same section.
+* ``symmetrize_central``: the central-symmetry constraint (Sec. 4.3).
 * ``sensitivities``: chain rule of Sec. 2.3 through the tensor, SIMP and the
   filter transpose.
 * ``oc_update``: Optimality Criteria bisection (Sec. 3.3, OCOptimizer).
@@ -260,12 +262,40 @@ def homogenize(rho: np.ndarray, prm: Params, with_energies: bool = True) -> Dict
 
 
 OBJ_MSE = 0
+OBJ_REL = 1
+OBJ_L1 = 2
 
 
-def objective(kappa: np.ndarray, target: np.ndarray):
-    """g = sum_c (kappa_c - target_c)^2 over the six components; returns (g, dg/dkappa)."""
-    d = np.asarray(kappa, dtype=np.float64) - np.asarray(target, dtype=np.float64)
-    return float(np.sum(d * d)), 2.0 * d
+def objective(kappa: np.ndarray, target: np.ndarray, kind: int = OBJ_MSE):
+    """The objective over the six tensor components and dg/dkappa.
+
+    OBJ_MSE: sum_c (kappa_c - target_c)^2 (Sec. 4.4, MSE objective).
+    OBJ_REL: sum_c (kappa_c / target_c - 1)^2 (the relative objective of
+    Sec. 4.4; every target component must be nonzero).
+    OBJ_L1:  sum_c |kappa_c - target_c| (the l1 objective of Sec. 4.4), with
+    d|a|/da taken as 0 at a = 0 as the paper states."""
+    kap = np.asarray(kappa, dtype=np.float64)
+    tgt = np.asarray(target, dtype=np.float64)
+    if kind == OBJ_MSE:
+        d = kap - tgt
+        return float(np.sum(d * d)), 2.0 * d
+    if kind == OBJ_REL:
+        if np.any(tgt == 0.0):
+            raise ValueError("the relative objective needs every target component nonzero")
+        d = kap / tgt - 1.0
+        return float(np.sum(d * d)), 2.0 * d / tgt
+    if kind == OBJ_L1:
+        d = kap - tgt
+        return float(np.sum(np.abs(d))), np.sign(d)
+    raise ValueError(f"unknown objective {kind}")
+
+
+def symmetrize_central(field: np.ndarray) -> np.ndarray:
+    """Central symmetry (Sec. 4.3, customized microstructures): each element
+    and its image under the point reflection through the cell centre,
+    (i, j, k) -> (n-1-i, n-1-j, n-1-k), both take the mean of their two values."""
+    f = np.asarray(field, dtype=np.float64)
+    return 0.5 * (f + f[::-1, ::-1, ::-1])
 
 
 def sensitivities(h: Dict[str, object], w6: np.ndarray, prm: Params) -> np.ndarray:
@@ -348,12 +378,19 @@ class IterRecord:
     pcg_iters: List[int]
 
 
-def oc_iteration(rho: np.ndarray, target: np.ndarray, gov: Governor, prm: Params):
+def oc_iteration(rho: np.ndarray, target: np.ndarray, gov: Governor, prm: Params, objective_kind: int = OBJ_MSE,
+                 central_symmetry: bool = False):
     """One OC iteration in the order: homogenize -> objective -> sensitivities
-    -> governor(g, mean(rho~^p), mean(rho)) -> OC update with the new V*."""
+    -> governor(g, mean(rho~^p), mean(rho)) -> OC update with the new V*.
+    With central symmetry the densities are averaged over symmetric element
+    pairs before the evaluation and the sensitivities after it."""
+    if central_symmetry:
+        rho = symmetrize_central(rho)
     h = homogenize(rho, prm)
-    g, w = objective(h["kappa"], target)
+    g, w = objective(h["kappa"], target, objective_kind)
     s = sensitivities(h, w, prm)
+    if central_symmetry:
+        s = symmetrize_central(s)
     low = float(np.mean(np.power(h["rhof"], prm.penal)))
     vol = float(np.mean(rho))
     vstar = gov.update(g, low, vol)

@@ -383,3 +383,89 @@ def test_oracle_defaults_match_paper_parameters():
         d["penal"], d["filter_radius"], d["oc_move"], d["oc_damping"], d["rho_min"], d["k0"])
     assert (gp.decay, gp.rebound, gp.patience, gp.bound) == (
         d["governor_decay"], d["governor_rebound"], d["governor_patience"], d["tolerable_error"])
+
+
+# ------------------------------------------- objective variants, symmetry
+
+TGT6 = np.array([0.3, 0.2, 0.1, 0.05, 0.05, 0.05])
+
+
+def _fd_grad(f, x, h=1e-7):
+    g = np.zeros_like(x)
+    for q in range(x.size):
+        e = np.zeros_like(x)
+        e[q] = h
+        g[q] = (f(x + e) - f(x - e)) / (2 * h)
+    return g
+
+
+def test_relative_objective_closed_form_and_gradient():
+    """kappa = target (1 + delta) gives g = sum delta^2 and dg/dkappa = 2 delta / target."""
+    delta = np.array([0.1, -0.2, 0.05, 0.3, -0.1, 0.0])
+    kap = TGT6 * (1.0 + delta)
+    g, w = O.objective(kap, TGT6, O.OBJ_REL)
+    assert g == pytest.approx(np.sum(delta ** 2), rel=1e-13)
+    np.testing.assert_allclose(w, 2.0 * delta / TGT6, rtol=1e-12, atol=1e-14)
+    fd = _fd_grad(lambda k: O.objective(k, TGT6, O.OBJ_REL)[0], kap)
+    np.testing.assert_allclose(w, fd, rtol=1e-6, atol=1e-7)
+    with pytest.raises(ValueError):
+        O.objective(kap, np.array([0.3, 0.2, 0.1, 0.0, 0.05, 0.05]), O.OBJ_REL)
+
+
+def test_l1_objective_value_gradient_and_kink_convention():
+    d = np.array([0.02, -0.01, 0.0, 0.03, -0.04, 0.005])
+    kap = TGT6 + d
+    g, w = O.objective(kap, TGT6, O.OBJ_L1)
+    assert g == pytest.approx(np.sum(np.abs(d)), rel=1e-13)
+    np.testing.assert_array_equal(w, [1.0, -1.0, 0.0, 1.0, -1.0, 1.0])  # d|a|/da = 0 at a = 0
+    away = kap + np.array([0, 0, 0.001, 0, 0, 0])
+    fd = _fd_grad(lambda k: O.objective(k, TGT6, O.OBJ_L1)[0], away, 1e-6)
+    np.testing.assert_allclose(O.objective(away, TGT6, O.OBJ_L1)[1], fd, atol=1e-8)
+    # MSE reduces to the six-term squared error
+    g2, w2 = O.objective(kap, TGT6, O.OBJ_MSE)
+    assert g2 == pytest.approx(np.sum(d * d), rel=1e-13)
+
+
+def test_central_pairing_is_the_reversed_flat_index():
+    """The point reflection (i,j,k) -> (n-1-i, n-1-j, n-1-k) maps flat index e
+    to n^3 - 1 - e; averaging is idempotent and keeps the mean."""
+    n = 5
+    f = synth.random_field(n, 7, 0.0, 1.0)
+    s = O.symmetrize_central(f)
+    flat = s.reshape(-1)
+    np.testing.assert_array_equal(flat, flat[::-1])
+    i, j, k = 1, 3, 4
+    assert s[k, j, i] == 0.5 * (f[k, j, i] + f[n - 1 - k, n - 1 - j, n - 1 - i])
+    np.testing.assert_array_equal(O.symmetrize_central(s), s)
+    assert s.mean() == pytest.approx(f.mean(), rel=1e-15)
+
+
+def test_sensitivities_of_a_centrally_symmetric_design_are_symmetric():
+    """kappa is invariant under the point reflection (R = -I maps kappa to
+    R kappa R^T = kappa), so a design equal to its reflection has a reflected-
+    symmetric gradient, for any objective of kappa; a generic design does not."""
+    n = 6
+    prm = O.Params(tol=1e-13)
+    for sym in (True, False):
+        rho = synth.random_field(n, 11, 0.1, 0.9)
+        if sym:
+            rho = O.symmetrize_central(rho)
+        h = O.homogenize(rho, prm)
+        for kind in (O.OBJ_MSE, O.OBJ_REL, O.OBJ_L1):
+            _, w = O.objective(h["kappa"], TGT6, kind)
+            s = O.sensitivities(h, w, prm)
+            asym = np.abs(s - s[::-1, ::-1, ::-1]).max() / np.abs(s).max()
+            if sym:
+                assert asym < 1e-9, (kind, asym)
+            else:
+                assert asym > 1e-3, (kind, asym)
+
+
+def test_symmetric_oc_iteration_output_is_exactly_symmetric():
+    n = 6
+    rho = synth.random_field(n, 12, 0.2, 0.5)
+    gov = O.Governor(0.35)
+    rho_new, rec, _, s = O.oc_iteration(rho, TGT6, gov, O.Params(tol=1e-12), O.OBJ_REL, central_symmetry=True)
+    flat = rho_new.reshape(-1)
+    np.testing.assert_array_equal(flat, flat[::-1])
+    np.testing.assert_array_equal(s.reshape(-1), s.reshape(-1)[::-1])
