@@ -77,6 +77,17 @@ extern "C" {
                                 m in {3, 4} and n >= 6, else OTM_EINVAL */
 
 #define OTM_OBJ_MSE 0 /* g = sum_c (kappa_c - target_c)^2, Sec. 4.4 (MSE objective) */
+#define OTM_OBJ_REL 1 /* g = sum_c (kappa_c / target_c - 1)^2, Sec. 4.4 (relative objective);
+                         every target component must be nonzero, else OTM_EINVAL */
+#define OTM_OBJ_L1 2  /* g = sum_c |kappa_c - target_c|, Sec. 4.4 (l1 objective), with the
+                         derivative of |a| taken as 0 at a = 0 */
+
+/* Symmetry constraints on the design (Sec. 4.3, customized microstructures). */
+#define OTM_SYM_NONE 0
+#define OTM_SYM_CENTRAL 1 /* central symmetry: element (i,j,k) and its image (n-1-i, n-1-j, n-1-k)
+                             (flat indices e and n^3-1-e) both take the mean of their densities
+                             at the start of every evaluation and the mean of their
+                             sensitivities after it */
 
 /* Fields readable with otm_get_field (count = n^3, or 3 n^3 where noted). */
 #define OTM_FIELD_RHO 0      /* design density rho (current) */
@@ -97,7 +108,9 @@ typedef struct {
     double filter_radius; /* hat-filter radius in voxels; < 1 disables the filter */
     double target[6];     /* target tensor, [11,22,33,12,23,13] */
     double vf;            /* initial volume bound V*_0 in (0, 1] */
-    int32_t objective;    /* OTM_OBJ_MSE */
+    int32_t objective;    /* OTM_OBJ_MSE, OTM_OBJ_REL or OTM_OBJ_L1 */
+    int32_t symmetry;     /* OTM_SYM_NONE or OTM_SYM_CENTRAL (single contexts only; a batch
+                             returns OTM_EUNSUPPORTED for OTM_SYM_CENTRAL) */
 } otm_problem;
 
 typedef struct {

@@ -30,6 +30,10 @@ OTM_GUESS_LEARNED = 3
 OTM_PRECOND_JACOBI = 0
 OTM_PRECOND_MG = 1
 OTM_OBJ_MSE = 0
+OTM_OBJ_REL = 1
+OTM_OBJ_L1 = 2
+OTM_SYM_NONE = 0
+OTM_SYM_CENTRAL = 1
 
 FIELDS = {"rho": 0, "rhof": 1, "k": 2, "b": 3, "diag": 4, "chi": 5, "sens_elem": 6, "sens": 7}
 FIELD3 = {"b", "chi"}
@@ -51,7 +55,8 @@ EXPORTED = [
 class Problem(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int32), ("k0", ctypes.c_double), ("kmin", ctypes.c_double),
                 ("penal", ctypes.c_double), ("filter_radius", ctypes.c_double),
-                ("target", ctypes.c_double * 6), ("vf", ctypes.c_double), ("objective", ctypes.c_int32)]
+                ("target", ctypes.c_double * 6), ("vf", ctypes.c_double), ("objective", ctypes.c_int32),
+                ("symmetry", ctypes.c_int32)]
 
 
 class SolverOpts(ctypes.Structure):

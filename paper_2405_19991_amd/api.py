@@ -27,6 +27,9 @@ def _f64(a) -> np.ndarray:
     return np.ascontiguousarray(np.asarray(a, dtype=np.float64))
 
 
+OBJECTIVES = {"mse": N.OTM_OBJ_MSE, "rel": N.OTM_OBJ_REL, "l1": N.OTM_OBJ_L1}
+
+
 class Homogenization:
     """One periodic n^3 design cell on the current HIP device."""
 
@@ -37,7 +40,7 @@ class Homogenization:
                  reliable_delta: float = 1e-2, move: float = 0.05, eta: float = 0.5, rho_min: float = 1e-3,
                  governor: Optional[Dict[str, float]] = None, stream=None, kernel_variant: int = 0,
                  tile_tz: int = 0, tile_tx: int = 0, autotune: bool = True, preconditioner: str = "jacobi",
-                 mg_sweeps: int = 1, mg_coarse_sweeps: int = 2):
+                 mg_sweeps: int = 1, mg_coarse_sweeps: int = 2, objective: str = "mse", symmetry: str = "none"):
         L = N.lib()
         self.n = int(n)
         p = N.Problem()
@@ -48,7 +51,8 @@ class Homogenization:
         for i, t in enumerate(target):
             p.target[i] = float(t)
         p.vf = float(vf)
-        p.objective = N.OTM_OBJ_MSE
+        p.objective = OBJECTIVES[objective]
+        p.symmetry = {"none": N.OTM_SYM_NONE, "central": N.OTM_SYM_CENTRAL}[symmetry]
         s, o, g = N.default_options()
         s.precision = {"fp64": N.OTM_FP64, "mixed": N.OTM_MIXED}[precision]
         s.guess = {"zero": N.OTM_GUESS_ZERO, "previous": N.OTM_GUESS_PREVIOUS, "user": N.OTM_GUESS_USER,
@@ -281,7 +285,8 @@ class Batch:
             for q, t in enumerate(pr["target"]):
                 p.target[q] = float(t)
             p.vf = float(pr.get("vf", 0.3))
-            p.objective = N.OTM_OBJ_MSE
+            p.objective = OBJECTIVES[pr.get("objective", "mse")]
+            p.symmetry = N.OTM_SYM_NONE
             self.ns.append(p.n)
         s, o, g = N.default_options()
         s.precision = N.OTM_FP64

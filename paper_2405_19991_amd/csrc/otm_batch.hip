@@ -369,7 +369,12 @@ int otm_batch_create(const otm_problem* problems, int32_t count, const otm_solve
             return OTM_EINVAL;
         for (int q = 0; q < 6; ++q)
             if (!std::isfinite(p.target[q])) return OTM_EINVAL;
-        if (p.objective != OTM_OBJ_MSE) return OTM_EUNSUPPORTED;
+        if (p.objective != OTM_OBJ_MSE && p.objective != OTM_OBJ_REL && p.objective != OTM_OBJ_L1)
+            return OTM_EUNSUPPORTED;
+        if (p.objective == OTM_OBJ_REL)
+            for (int q = 0; q < 6; ++q)
+                if (p.target[q] == 0.0) return OTM_EINVAL;
+        if (p.symmetry != OTM_SYM_NONE) return OTM_EUNSUPPORTED;
     }
     otm_batch* c = new (std::nothrow) otm_batch();
     if (!c) return OTM_ENOMEM;
@@ -543,12 +548,8 @@ int otm_batch_step(otm_batch* c, otm_iter_record* recs) {
         const double nn = (double)c->prob[d].n * c->prob[d].n * c->prob[d].n;
         const Scalars& s = c->h_sc[d];
         double gg = 0.0;
-        for (int q = 0; q < 6; ++q) {
-            c->kappa[6 * d + q] = s.kappa_sum[q] / nn;
-            const double dv = c->kappa[6 * d + q] - c->prob[d].target[q];
-            gg += dv * dv;
-            w6[d].w[q] = 2.0 * dv;
-        }
+        for (int q = 0; q < 6; ++q) c->kappa[6 * d + q] = s.kappa_sum[q] / nn;
+        objective_grad(c->prob[d].objective, c->kappa.data() + 6 * d, c->prob[d].target, &gg, w6[d].w);
         if (!std::isfinite(gg)) return bfail(c, OTM_ENONFINITE, "non-finite tensor");
         c->g[d] = gg;
         c->volume[d] = s.sum_rho / nn;

@@ -192,9 +192,19 @@ int validate_problem(const otm_problem* p, std::string& why) {
         why = "target must be finite";
         return OTM_EINVAL;
     }
-    if (p->objective != OTM_OBJ_MSE) {
+    if (p->objective != OTM_OBJ_MSE && p->objective != OTM_OBJ_REL && p->objective != OTM_OBJ_L1) {
         why = "unsupported objective";
         return OTM_EUNSUPPORTED;
+    }
+    if (p->objective == OTM_OBJ_REL)
+        for (int q = 0; q < 6; ++q)
+            if (p->target[q] == 0.0) {
+                why = "the relative objective needs every target component nonzero";
+                return OTM_EINVAL;
+            }
+    if (p->symmetry != OTM_SYM_NONE && p->symmetry != OTM_SYM_CENTRAL) {
+        why = "unknown symmetry";
+        return OTM_EINVAL;
     }
     return OTM_OK;
 }
@@ -221,6 +231,7 @@ double ev_ms(otm_ctx* c, int a, int b) {
 int prepare(otm_ctx* c) {
     if (!c->have_density) return fail(c, OTM_ESTATE, "no density set");
     const Workspace w = c->ws();
+    if (c->prob.symmetry == OTM_SYM_CENTRAL) launch_sym_central(c->n, c->rho, c->stream);
     launch_filter_simp(c->n, c->prob.filter_radius, c->rho, c->rhof, c->k, c->k32, c->prob.k0, c->prob.kmin,
                        c->prob.penal, w, c->stream);
     launch_setup_nodes(c->n, c->k, c->b, c->dinv, c->dinv32, w, c->stream);
@@ -633,6 +644,7 @@ int sensitivity(otm_ctx* c, const double w6[6]) {
     (void)hipEventRecord(c->ev[4], c->stream);
     launch_sens(c->n, c->rhof, c->x, w6, c->prob.k0, c->prob.kmin, c->prob.penal, c->st, c->stream);
     launch_filter(c->n, c->prob.filter_radius, c->st, c->sens, c->stream);
+    if (c->prob.symmetry == OTM_SYM_CENTRAL) launch_sym_central(c->n, c->sens, c->stream);
     (void)hipEventRecord(c->ev[5], c->stream);
     int rc = check_launch(c, "sensitivity");
     if (rc) return rc;
@@ -697,15 +709,6 @@ double governor_update(otm_ctx* c, double g, double low, double vol) {
     return c->vstar;
 }
 
-void objective(const double* kappa, const double* target, double* g, double* w6) {
-    double s = 0.0;
-    for (int q = 0; q < 6; ++q) {
-        const double d = kappa[q] - target[q];
-        s += d * d;
-        w6[q] = 2.0 * d;
-    }
-    *g = s;
-}
 
 int free_all(otm_ctx* c) {
     void* bufs[] = {c->rho, c->rhof, c->k, c->dinv, c->b, c->x, c->st, c->sens, c->ocq, c->r64, c->p64[0], c->p64[1],
@@ -1262,7 +1265,7 @@ int otm_step(otm_ctx* c, otm_iter_record* rec) {
     int hrc = homogenize(c, nullptr, &st);
     if (hrc < 0) return hrc;
     double g, w6[6];
-    objective(c->kappa, c->prob.target, &g, w6);
+    objective_grad(c->prob.objective, c->kappa, c->prob.target, &g, w6);
     c->g = g;
     std::memcpy(c->w, w6, sizeof(w6));
     int rc = sensitivity(c, w6);

@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "opentm_amd.h"
+
 namespace otm {
 
 constexpr int kBlock = 256;          // threads per block for node/element sweeps
@@ -162,6 +164,30 @@ void launch_oc_pass(int n, const double* rho, const double* q, double move, doub
 void launch_oc_apply(int n, double* rho, const double* q, double eta, double move, double rho_min,
                      const Workspace& ws, hipStream_t s);
 void launch_clamp(int n, double* rho, double lo, double hi, hipStream_t s);
+// The objective over the six tensor components and dg/dkappa (Sec. 4.4):
+// squared error, relative squared error, or l1 with d|a|/da = 0 at a = 0.
+inline void objective_grad(int kind, const double* kappa, const double* target, double* g, double* w6) {
+    double s = 0.0;
+    for (int q = 0; q < 6; ++q) {
+        if (kind == OTM_OBJ_REL) {
+            const double d = kappa[q] / target[q] - 1.0;
+            s += d * d;
+            w6[q] = 2.0 * d / target[q];
+        } else if (kind == OTM_OBJ_L1) {
+            const double d = kappa[q] - target[q];
+            s += d < 0.0 ? -d : d;
+            w6[q] = d > 0.0 ? 1.0 : (d < 0.0 ? -1.0 : 0.0);
+        } else {
+            const double d = kappa[q] - target[q];
+            s += d * d;
+            w6[q] = 2.0 * d;
+        }
+    }
+    *g = s;
+}
+
+// f_e = f_{n^3-1-e} = (f_e + f_{n^3-1-e}) / 2: central symmetry of an element field
+void launch_sym_central(int n, double* f, hipStream_t s);
 
 // Tiled fused direction + operator pass and vectorized update (otm_stencil.hip).
 struct TileShape {

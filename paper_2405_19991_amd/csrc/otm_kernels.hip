@@ -477,6 +477,18 @@ __device__ __forceinline__ void b_clamp(int bid_, int nblk_, int64_t nn, double*
 
 __global__ void __launch_bounds__(kBlock) k_clamp(int64_t nn, double* __restrict__ rho, double lo, double hi) { b_clamp(blockIdx.x, gridDim.x, nn, rho, lo, hi); }
 
+// Element e and its image under the point reflection through the cell
+// centre, (i,j,k) -> (n-1-i, n-1-j, n-1-k), which is flat index n^3 - 1 - e,
+// both take their mean (an odd n leaves the centre element as it is).
+__global__ void __launch_bounds__(kBlock) k_sym_central(int64_t nn, double* __restrict__ f) {
+    const int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x;
+    if (e >= nn / 2) return;
+    const int64_t p = nn - 1 - e;
+    const double v = 0.5 * (f[e] + f[p]);
+    f[e] = v;
+    f[p] = v;
+}
+
 __global__ void k_fill_u32(unsigned* p, int count, unsigned v) {
     const int t = blockIdx.x * blockDim.x + threadIdx.x;
     if (t < count) p[t] = v;
@@ -858,6 +870,12 @@ void launch_oc_apply(int n, double* rho, const double* q, double eta, double mov
                      const Workspace& ws, hipStream_t s) {
     hipLaunchKernelGGL(k_oc_apply, dim3(nblocks_for(cube(n))), dim3(kBlock), 0, s, cube(n), rho, q, eta, move,
                        rho_min, ws.sc);
+}
+
+void launch_sym_central(int n, double* f, hipStream_t s) {
+    const int64_t nn = cube(n);
+    if (nn < 2) return;
+    hipLaunchKernelGGL(k_sym_central, dim3(nblocks_for(nn / 2)), dim3(kBlock), 0, s, nn, f);
 }
 
 void launch_clamp(int n, double* rho, double lo, double hi, hipStream_t s) {

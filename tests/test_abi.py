@@ -119,3 +119,30 @@ def test_batch_rejects_multigrid(L):
     s.preconditioner = N.OTM_PRECOND_MG
     h = ctypes.c_void_p()
     assert L.otm_batch_create(arr, 1, ctypes.byref(s), None, None, None, ctypes.byref(h)) == N.OTM_EUNSUPPORTED
+
+
+def _problem(N, n=8):
+    p = N.Problem()
+    p.n, p.k0, p.kmin, p.penal, p.filter_radius, p.vf = n, 1.0, 1e-3, 3.0, 1.5, 0.3
+    for q, t in enumerate((0.3, 0.2, 0.1, 0.05, 0.05, 0.05)):
+        p.target[q] = t
+    return p
+
+
+def test_objective_and_symmetry_validation(L):
+    from paper_2405_19991_amd import _native as N
+    h = ctypes.c_void_p()
+    p = _problem(N)
+    p.objective = 3
+    assert L.otm_create(ctypes.byref(p), None, None, None, None, ctypes.byref(h)) == N.OTM_EUNSUPPORTED
+    p = _problem(N)
+    p.objective = N.OTM_OBJ_REL
+    p.target[4] = 0.0  # the relative objective divides by every target component
+    assert L.otm_create(ctypes.byref(p), None, None, None, None, ctypes.byref(h)) == N.OTM_EINVAL
+    p = _problem(N)
+    p.symmetry = 2
+    assert L.otm_create(ctypes.byref(p), None, None, None, None, ctypes.byref(h)) == N.OTM_EINVAL
+    arr = (N.Problem * 1)()
+    arr[0] = _problem(N)
+    arr[0].symmetry = N.OTM_SYM_CENTRAL
+    assert L.otm_batch_create(arr, 1, None, None, None, None, ctypes.byref(h)) == N.OTM_EUNSUPPORTED
