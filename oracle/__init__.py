@@ -16,6 +16,7 @@ What it computes (paper: Quan, Zhai, Fu, "OpenTM", arXiv 2405.19991):
 * ``objective``: the six-term squared error (Sec. 4.4, MSE objective), and
   the relative and l1 objectives of the same section.
 * ``symmetrize_central``: the central-symmetry constraint (Sec. 4.3).
+* ``init_density``: the TPMS and centre-ball initial densities (Sec. 4.3).
 * ``sensitivities``: chain rule of Sec. 2.3 through the tensor, SIMP and the
   filter transpose.
 * ``oc_update``: Optimality Criteria bisection (Sec. 3.3, OCOptimizer).
@@ -288,6 +289,42 @@ def objective(kappa: np.ndarray, target: np.ndarray, kind: int = OBJ_MSE):
         d = kap - tgt
         return float(np.sum(np.abs(d))), np.sign(d)
     raise ValueError(f"unknown objective {kind}")
+
+
+INIT_KINDS = ("P", "D", "G", "IWP", "ball")
+
+
+def init_level(kind: str, n: int) -> np.ndarray:
+    """Level-set values at element centres, X = 2 pi (i + 1/2) / n, shape
+    (n, n, n) indexed [k][j][i]: the standard trigonometric approximations of
+    the Schwarz P and D surfaces, the gyroid and Schoen's IWP surface (the
+    classic initializations of Sec. 4.3), or minus the distance from the cell
+    centre for the centre ball."""
+    c = (np.arange(n) + 0.5)
+    Z, Y, X = np.meshgrid(2 * np.pi * c / n, 2 * np.pi * c / n, 2 * np.pi * c / n, indexing="ij")
+    if kind == "P":
+        return np.cos(X) + np.cos(Y) + np.cos(Z)
+    if kind == "D":
+        return np.cos(X) * np.cos(Y) * np.cos(Z) - np.sin(X) * np.sin(Y) * np.sin(Z)
+    if kind == "G":
+        return np.sin(X) * np.cos(Y) + np.sin(Y) * np.cos(Z) + np.sin(Z) * np.cos(X)
+    if kind == "IWP":
+        return (2 * (np.cos(X) * np.cos(Y) + np.cos(Y) * np.cos(Z) + np.cos(Z) * np.cos(X))
+                - (np.cos(2 * X) + np.cos(2 * Y) + np.cos(2 * Z)))
+    if kind == "ball":
+        zc, yc, xc = np.meshgrid(c - n / 2, c - n / 2, c - n / 2, indexing="ij")
+        return -np.sqrt(xc * xc + yc * yc + zc * zc)
+    raise ValueError(kind)
+
+
+def init_density(kind: str, n: int, vf: float) -> np.ndarray:
+    """Solid (1) on the round(vf n^3) elements with the smallest level-set
+    values (stable order of the flat index for ties), void (0) elsewhere."""
+    phi = init_level(kind, n).reshape(-1)
+    order = np.argsort(phi, kind="stable")
+    rho = np.zeros(n ** 3)
+    rho[order[:int(round(vf * n ** 3))]] = 1.0
+    return rho.reshape(n, n, n)
 
 
 def symmetrize_central(field: np.ndarray) -> np.ndarray:
