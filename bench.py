@@ -49,6 +49,8 @@ def parse():
                     help="network weights (.npy) for the warm-start leg (default: the package's trained weights)")
     ap.add_argument("--no-warm-start", action="store_true", help="skip the warm-start leg")
     ap.add_argument("--no-configs", action="store_true", help="skip the 16^3 / 64^3 legs")
+    ap.add_argument("--no-gallery", action="store_true", help="skip the 61-target traversal leg")
+    ap.add_argument("--gallery-iters", type=int, default=150)
     ap.add_argument("--variant", type=int, default=0,
                     help="solver kernel: 0 automatic (autotuned), 4 fused iteration, 1-3 cross-check kernels")
     ap.add_argument("--solver-tx", type=int, default=0, help="solver tile width (0: automatic)")
@@ -190,6 +192,35 @@ def multigrid_leg(w, steps: int, log, sweeps: int = 1, coarse_sweeps: int = 2):
            "first_pcg_iters": first["pcg_iters"], "steps": steps}
     log(f"multigrid: {1e3 * out['s_per_oc_iter']:.2f} ms per design iteration, "
         f"{out['pcg_iters_per_step']:.1f} PCG iterations per step")
+    return out
+
+
+def gallery_leg(iters: int, log, n: int = 32):
+    """Anisotropic-space traversal (Sec. 4.2): the 61 positive-definite targets
+    with diagonal [0.3, 0.2, 0.1] as one batch of n^3 designs, IWP start at
+    volume 0.3, volume bound starting at 1 (Algorithm 1), OC move 0.02,
+    `iters` batched design iterations."""
+    import numpy as np
+    import synth
+    from paper_2405_19991_amd import Batch, init_density
+    T = synth.gallery_targets()
+    B = Batch([dict(n=n, target=tuple(t), vf=1.0) for t in T], tol=1e-6, guess="previous", move=0.02)
+    rho0 = init_density(n, "IWP", 0.3)
+    for d in range(len(T)):
+        B.set_density(d, rho0)
+    g0 = np.array([r["g"] for r in B.step()])
+    t0 = time.perf_counter()
+    for _ in range(iters):
+        recs = B.step()
+    dt = time.perf_counter() - t0
+    B.close()
+    g = np.array([r["g"] for r in recs])
+    out = {"workload": f"gallery61_n{n}_fp64", "designs": len(T), "iterations": iters + 1,
+           "s_per_oc_iter": dt / iters, "g_start_median": float(np.median(g0)), "g_median": float(np.median(g)),
+           "g_max": float(g.max()), "designs_g_le_1e-4": int((g <= 1e-4).sum()),
+           "mean_volume": float(np.mean([r["volume"] for r in recs]))}
+    log(f"gallery: {1e3 * out['s_per_oc_iter']:.1f} ms per batched design iteration, g median "
+        f"{out['g_start_median']:.2e} -> {out['g_median']:.2e}, {out['designs_g_le_1e-4']} of 61 at g <= 1e-4")
     return out
 
 
@@ -414,6 +445,8 @@ def main():
         out["batch"] = batch_leg(args.batch_steps, log)
     if not args.no_configs:
         out["configs"] = config_legs(5, log)
+    if not args.no_gallery:
+        out["gallery"] = gallery_leg(args.gallery_iters, log)
     if not args.no_warm_start and n == 128:
         out["warm_start"] = warm_start_leg(args.weights, log)
     if not args.no_cpu_baseline:

@@ -82,6 +82,14 @@ extern "C" {
 #define OTM_OBJ_L1 2  /* g = sum_c |kappa_c - target_c|, Sec. 4.4 (l1 objective), with the
                          derivative of |a| taken as 0 at a = 0 */
 
+/* Initial density fields (Sec. 4.3, density initialization), otm_init_density. */
+#define OTM_INIT_P 0    /* Schwarz P:  cos X + cos Y + cos Z */
+#define OTM_INIT_D 1    /* Schwarz D:  cos X cos Y cos Z - sin X sin Y sin Z */
+#define OTM_INIT_G 2    /* gyroid:     sin X cos Y + sin Y cos Z + sin Z cos X */
+#define OTM_INIT_IWP 3  /* Schoen IWP: 2 (cos X cos Y + cos Y cos Z + cos Z cos X)
+                                       - (cos 2X + cos 2Y + cos 2Z) */
+#define OTM_INIT_BALL 4 /* centre ball: a solid cube with a spherical void at its centre */
+
 /* Symmetry constraints on the design (Sec. 4.3, customized microstructures). */
 #define OTM_SYM_NONE 0
 #define OTM_SYM_CENTRAL 1 /* central symmetry: element (i,j,k) and its image (n-1-i, n-1-j, n-1-k)
@@ -98,6 +106,18 @@ extern "C" {
 #define OTM_FIELD_CHI 5      /* fluctuation fields chi^i, 3 n^3, zero mean */
 #define OTM_FIELD_SENS_ELEM 6 /* dg/drho~_e before the filter transpose */
 #define OTM_FIELD_SENS 7     /* dg/drho_e after the filter transpose */
+
+/* ---- initial densities ---------------------------------------------------- */
+/* Writes an n^3 density field (host, float64, flat x-fastest) for the
+ * initialization `kind` (OTM_INIT_*): the level set is evaluated at element
+ * centres, X = 2 pi (i + 1/2) / n (Y, Z likewise; one period per cell), and
+ * exactly round(vf n^3) elements with the smallest values are solid (1), the
+ * rest void (0), ties broken by flat index.  For OTM_INIT_BALL the value is
+ * minus the distance from the cell centre, so the solid is the cube minus a
+ * central ball.  Host-only; needs no device and no context.
+ * Errors: OTM_EINVAL (null pointer, n outside 4..1024, vf outside (0, 1],
+ * unknown kind). */
+int otm_init_density(int32_t n, int32_t kind, double vf, double* rho_out);
 
 /* ---- parameter blocks ---------------------------------------------------- */
 typedef struct {

@@ -32,6 +32,11 @@ OTM_PRECOND_MG = 1
 OTM_OBJ_MSE = 0
 OTM_OBJ_REL = 1
 OTM_OBJ_L1 = 2
+OTM_INIT_P = 0
+OTM_INIT_D = 1
+OTM_INIT_G = 2
+OTM_INIT_IWP = 3
+OTM_INIT_BALL = 4
 OTM_SYM_NONE = 0
 OTM_SYM_CENTRAL = 1
 
@@ -48,7 +53,7 @@ EXPORTED = [
     "otm_batch_set_graph", "otm_batch_info", "otm_batch_last_error",
     "otm_nn_create", "otm_nn_destroy", "otm_nn_param_count", "otm_nn_get_params", "otm_nn_set_params",
     "otm_nn_get_grads", "otm_nn_forward", "otm_nn_accumulate", "otm_nn_adam", "otm_nn_zero_grads",
-    "otm_nn_last_error", "otm_set_network",
+    "otm_nn_last_error", "otm_set_network", "otm_init_density",
 ]
 
 
@@ -145,6 +150,7 @@ def lib():
         "otm_strerror": ([ctypes.c_int], ctypes.c_char_p),
         "otm_last_error": ([ctx], ctypes.c_char_p),
         "otm_version": ([], ctypes.c_char_p),
+        "otm_init_density": ([i32, i32, ctypes.c_double, dp], ctypes.c_int),
         "otm_batch_create": ([P(Problem), i32, P(SolverOpts), P(OcOpts), P(GovernorOpts), vp, P(vp)], ctypes.c_int),
         "otm_batch_destroy": ([vp], None),
         "otm_batch_set_density": ([vp, i32, dp, i64], ctypes.c_int),

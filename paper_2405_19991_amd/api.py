@@ -28,6 +28,15 @@ def _f64(a) -> np.ndarray:
 
 
 OBJECTIVES = {"mse": N.OTM_OBJ_MSE, "rel": N.OTM_OBJ_REL, "l1": N.OTM_OBJ_L1}
+INITS = {"P": N.OTM_INIT_P, "D": N.OTM_INIT_D, "G": N.OTM_INIT_G, "IWP": N.OTM_INIT_IWP, "ball": N.OTM_INIT_BALL}
+
+
+def init_density(n: int, kind: str = "IWP", vf: float = 0.3) -> np.ndarray:
+    """Initial density field (n, n, n) indexed [k][j][i]: P, D, G, IWP or the
+    centre ball, with exactly round(vf n^3) solid elements (otm_init_density)."""
+    out = np.empty(int(n) ** 3, dtype=np.float64)
+    N.check(N.lib().otm_init_density(int(n), INITS[kind], float(vf), _ptr(out)))
+    return out.reshape((int(n),) * 3)
 
 
 class Homogenization:
@@ -244,13 +253,15 @@ def time_apply_device(k, x, y, precision: str = "fp64", reps: int = 50, stream=N
     return us.value
 
 
-def run_instance(reso: int, heat_ratio: Sequence[float], target: Sequence[float], rho0=None, vf: float = 0.3,
+def run_instance(reso: int, heat_ratio: Sequence[float], target: Sequence[float], init="IWP", vf: float = 0.3,
                  max_iter: int = 500, **kw):
     """Design one structure: mirrors the paper's runInstance(reso, heatRatio,
-    target, init, model) for the adaptive-volume model with OC.  The initial
-    density defaults to vf everywhere (caller-provided otherwise)."""
+    target, init, model) for the adaptive-volume model with OC.  `init` is an
+    initializer name (P, D, G, IWP -- the paper's default -- or ball, at volume
+    fraction vf) or a density array."""
+    rho0 = init_density(reso, init, vf) if isinstance(init, str) else np.asarray(init, dtype=np.float64)
     with Homogenization(reso, heat_ratio, target, vf=vf, **kw) as h:
-        h.set_density(np.full((reso,) * 3, vf) if rho0 is None else rho0)
+        h.set_density(rho0)
         rho, log = h.optimize(max_iter)
     return rho, log
 

@@ -128,3 +128,27 @@ def random_field(n: int, seed: int, lo: float = 0.0, hi: float = 1.0) -> np.ndar
 def random_vectors(n: int, count: int, seed: int) -> np.ndarray:
     """(count, n, n, n) standard-normal vectors (operator-level parity inputs)."""
     return rng(seed).standard_normal((count, n, n, n))
+
+
+# Anisotropic-space traversal (Sec. 4.2): the diagonal fixed at [0.3, 0.2, 0.1]
+# and the off-diagonal entries stepped below the 2x2 principal-minor limits.
+# The printed k23 and k13 sets are swapped (their stated limits, sqrt(0.2*0.1)
+# and sqrt(0.3*0.1), only fit the other way round); swapped, 61 of the 96
+# combinations are positive definite, as the paper states.
+GALLERY_DIAG = (0.3, 0.2, 0.1)
+GALLERY_K12 = (0.0, 0.05, 0.1, 0.15, 0.2, 0.24)
+GALLERY_K23 = (0.0, 0.05, 0.1, 0.14)
+GALLERY_K13 = (0.0, 0.05, 0.1, 0.15)
+
+
+def gallery_targets() -> List[np.ndarray]:
+    """The positive-definite targets of the traversal, [k11,k22,k33,k12,k23,k13]."""
+    out = []
+    for k12 in GALLERY_K12:
+        for k23 in GALLERY_K23:
+            for k13 in GALLERY_K13:
+                t = np.array([*GALLERY_DIAG, k12, k23, k13])
+                m = np.array([[t[0], t[3], t[5]], [t[3], t[1], t[4]], [t[5], t[4], t[2]]])
+                if np.all(np.linalg.eigvalsh(m) > 0.0):
+                    out.append(t)
+    return out

@@ -72,3 +72,25 @@ def test_batch_objectives_match_single_contexts():
             rec = h.step()
         assert recs[d]["g"] == pytest.approx(rec["g"], rel=1e-8), k
         assert recs[d]["vstar"] == pytest.approx(rec["vstar"], rel=1e-12), k
+
+
+@pytest.mark.parametrize("kind", ["IWP", "G", "ball"])
+def test_initializer_start_tracks_oracle(kind):
+    """Design iterations from a binary TPMS / centre-ball start (contrast 1e3
+    after the clamp to rho_min) follow the oracle's."""
+    from paper_2405_19991_amd import Homogenization, init_density
+    n, vf = 16, 0.35
+    rho0 = init_density(n, kind, vf)
+    np.testing.assert_array_equal(rho0, O.init_density(kind, n, vf))
+    rho_ref = np.maximum(rho0, 1e-3)
+    prm = O.Params(tol=1e-10)
+    gov = O.Governor(vf)
+    with Homogenization(n, (1.0, 1e-3), TGT6, vf=vf, tol=1e-10, guess="previous") as h:
+        h.set_density(rho0)
+        for it in range(2):
+            rec = h.step()
+            rho_ref, r_ref, _, _ = O.oc_iteration(rho_ref, np.array(TGT6), gov, prm)
+            assert rec["g"] == pytest.approx(r_ref.g, rel=1e-6), it
+            np.testing.assert_allclose(rec["kappa"], r_ref.kappa, rtol=1e-6, atol=1e-9)
+        rho = h.get_field("rho")
+    assert np.abs(rho - rho_ref).max() < 1e-6
