@@ -256,6 +256,10 @@ void launch_mg_restrict(int nc, const float* r, float* fc, hipStream_t s);
 void launch_mg_prolong(int nc, const float* xc, float* xf, const float* f0, const float* dinv0, hipStream_t s);
 void launch_mg_coarse_setup(int n, const float* k, float* minv, hipStream_t s);
 void launch_mg_coarse_solve(int n, const float* minv, const float* f, float* x, hipStream_t s);
+// The second-coarsest level (n <= 8, even) and the coarsest below it in one
+// block: x = V(f) with nu relaxation steps per leg, written to x (3 n^3).
+void launch_mg_tail(int n, int nu, const float* f, const float* k, const float* dinv, const float* minv, float* x,
+                    hipStream_t s);
 // z = V(r) for the three loads, r = lv[0].f; *z_out receives the level-0
 // buffer that holds z.  The last relaxation writes the per-block sums r.z
 // into partials; returns their block count.

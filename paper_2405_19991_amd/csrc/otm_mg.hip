@@ -208,6 +208,169 @@ __global__ void __launch_bounds__(kBlock) k_mg_coarse_solve(int N, const float* 
     x[l * N + v] = s0 + s1;
 }
 
+// The last two levels in one block (the second-coarsest level has at most
+// 8^3 = 512 nodes, one thread each, everything in LDS): the same steps as the
+// level kernels -- nu damped Jacobi steps from zero, the residual, its
+// restriction, the direct coarse solve, interpolation and correction, nu
+// steps -- without a launch per step.  A x at a node is the 21-point form of
+// the hex-8 operator: (1/3) sum_8 k_e on the node, -(k_a + k_b)/12 for the 12
+// edge-diagonal neighbours (the two elements they share with the node),
+// -k_e/12 for the 8 corners, 0 for the 6 axis neighbours.
+constexpr int kMgTailMax = 512;
+
+__device__ __forceinline__ void tail_apply(int n, int i, int j, int kk, const float* __restrict__ sk,
+                                           const float (*__restrict__ x)[kMgTailMax], float y[3]) {
+    int ci[3], cj[3], ck[3];  // wrapped coordinates of offsets -1, 0, +1
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+        ci[d] = (i + d - 1 + n) % n;
+        cj[d] = (j + d - 1 + n) % n;
+        ck[d] = (kk + d - 1 + n) % n;
+    }
+    // conductivities of the 8 incident elements: ke[ez][ey][ex], ex = 1 is the
+    // element whose lower corner is the node, ex = 0 the one below it in x
+    float ke[2][2][2];
+    float ksum = 0.f;
+#pragma unroll
+    for (int ez = 0; ez < 2; ++ez)
+#pragma unroll
+        for (int ey = 0; ey < 2; ++ey)
+#pragma unroll
+            for (int ex = 0; ex < 2; ++ex) {
+                ke[ez][ey][ex] = sk[ci[ex] + n * (cj[ey] + n * ck[ez])];
+                ksum += ke[ez][ey][ex];
+            }
+    const int v = ci[1] + n * (cj[1] + n * ck[1]);
+#pragma unroll
+    for (int l = 0; l < 3; ++l) y[l] = (ksum * (1.f / 3.f)) * x[l][v];
+    const float w = 1.f / 12.f;
+#pragma unroll
+    for (int dz = 0; dz < 3; ++dz)
+#pragma unroll
+        for (int dy = 0; dy < 3; ++dy)
+#pragma unroll
+            for (int dx = 0; dx < 3; ++dx) {
+                const int nz = (dx != 1) + (dy != 1) + (dz != 1);
+                if (nz < 2) continue;  // the node itself and its axis neighbours
+                float c = 0.f;         // sum of the elements shared with this neighbour
+#pragma unroll
+                for (int ez = 0; ez < 2; ++ez)
+#pragma unroll
+                    for (int ey = 0; ey < 2; ++ey)
+#pragma unroll
+                        for (int ex = 0; ex < 2; ++ex) {
+                            const bool sx = dx == 1 || ex == (dx == 2 ? 1 : 0);
+                            const bool sy = dy == 1 || ey == (dy == 2 ? 1 : 0);
+                            const bool sz = dz == 1 || ez == (dz == 2 ? 1 : 0);
+                            if (sx && sy && sz) c += ke[ez][ey][ex];
+                        }
+                const int u = ci[dx] + n * (cj[dy] + n * ck[dz]);
+#pragma unroll
+                for (int l = 0; l < 3; ++l) y[l] -= w * c * x[l][u];
+            }
+}
+
+__global__ void __launch_bounds__(kMgTailMax) k_mg_tail(int n, int nu, const float* __restrict__ f,
+                                                       const float* __restrict__ k, const float* __restrict__ dinv,
+                                                       const float* __restrict__ minv, float* __restrict__ xout) {
+    __shared__ float sk[kMgTailMax];
+    __shared__ float sx[2][3][kMgTailMax];
+    __shared__ float sc[2][3][kMgCoarseMax];
+    const int N = n * n * n, nc = n / 2, Nc = nc * nc * nc;
+    const int v = threadIdx.x;
+    const bool own = v < N;
+    int i = 0, j = 0, kk = 0;
+    float fv[3] = {0.f, 0.f, 0.f}, wd = 0.f;
+    if (own) {
+        i = v % n;
+        j = (v / n) % n;
+        kk = v / (n * n);
+        sk[v] = k[v];
+        wd = kMgOmega * dinv[v];
+#pragma unroll
+        for (int l = 0; l < 3; ++l) {
+            fv[l] = f[l * N + v];
+            sx[0][l][v] = wd * fv[l];  // first step from zero
+        }
+    }
+    __syncthreads();
+    int cur = 0;
+    float y[3];
+    for (int it = 1; it < nu; ++it) {
+        if (own) {
+            tail_apply(n, i, j, kk, sk, sx[cur], y);
+#pragma unroll
+            for (int l = 0; l < 3; ++l) sx[cur ^ 1][l][v] = sx[cur][l][v] + wd * (fv[l] - y[l]);
+        }
+        __syncthreads();
+        cur ^= 1;
+    }
+    // residual into the other buffer, then its restriction to the coarsest level
+    if (own) {
+        tail_apply(n, i, j, kk, sk, sx[cur], y);
+#pragma unroll
+        for (int l = 0; l < 3; ++l) sx[cur ^ 1][l][v] = fv[l] - y[l];
+    }
+    __syncthreads();
+    if (v < Nc) {
+        const int I = v % nc, J = (v / nc) % nc, K = v / (nc * nc);
+        float r[3] = {0.f, 0.f, 0.f};
+        for (int dz = -1; dz <= 1; ++dz)
+            for (int dy = -1; dy <= 1; ++dy)
+                for (int dx = -1; dx <= 1; ++dx) {
+                    const float w = (dx ? 0.5f : 1.f) * (dy ? 0.5f : 1.f) * (dz ? 0.5f : 1.f);
+                    const int u = (2 * I + dx + n) % n + n * ((2 * J + dy + n) % n + n * ((2 * K + dz + n) % n));
+#pragma unroll
+                    for (int l = 0; l < 3; ++l) r[l] += w * sx[cur ^ 1][l][u];
+                }
+#pragma unroll
+        for (int l = 0; l < 3; ++l) sc[0][l][v] = r[l];
+    }
+    __syncthreads();
+    if (v < 3 * kMgCoarseMax) {
+        const int l = v / kMgCoarseMax, V = v % kMgCoarseMax;
+        if (V < Nc) {
+            float t = 0.f;
+            for (int u = 0; u < Nc; ++u) t += minv[u * Nc + V] * sc[0][l][u];
+            sc[1][l][V] = t;
+        }
+    }
+    __syncthreads();
+    if (own) {  // x += P x_c
+        const int i0 = i >> 1, j0 = j >> 1, k0 = kk >> 1;
+        const int i1 = (i & 1) ? (i0 + 1) % nc : i0, j1 = (j & 1) ? (j0 + 1) % nc : j0,
+                  k1 = (kk & 1) ? (k0 + 1) % nc : k0;
+#pragma unroll
+        for (int l = 0; l < 3; ++l) {
+            const float* c = sc[1][l];
+            const float t = (c[i0 + nc * (j0 + nc * k0)] + c[i1 + nc * (j0 + nc * k0)] + c[i0 + nc * (j1 + nc * k0)] +
+                             c[i1 + nc * (j1 + nc * k0)]) +
+                            (c[i0 + nc * (j0 + nc * k1)] + c[i1 + nc * (j0 + nc * k1)] + c[i0 + nc * (j1 + nc * k1)] +
+                             c[i1 + nc * (j1 + nc * k1)]);
+            sx[cur][l][v] += 0.125f * t;
+        }
+    }
+    __syncthreads();
+    for (int it = 0; it < nu; ++it) {
+        if (own) {
+            tail_apply(n, i, j, kk, sk, sx[cur], y);
+#pragma unroll
+            for (int l = 0; l < 3; ++l) sx[cur ^ 1][l][v] = sx[cur][l][v] + wd * (fv[l] - y[l]);
+        }
+        __syncthreads();
+        cur ^= 1;
+    }
+    if (own) {
+#pragma unroll
+        for (int l = 0; l < 3; ++l) xout[l * N + v] = sx[cur][l][v];
+    }
+}
+
+void launch_mg_tail(int n, int nu, const float* f, const float* k, const float* dinv, const float* minv, float* x,
+                    hipStream_t s) {
+    hipLaunchKernelGGL(k_mg_tail, dim3(1), dim3(kMgTailMax), 0, s, n, nu, f, k, dinv, minv, x);
+}
+
 void launch_mg_coarsen(int nc, const float* kf, float* kc, float* dinv_c, hipStream_t s) {
     const int64_t ncc = (int64_t)nc * nc * nc;
     hipLaunchKernelGGL(k_mg_coarsen, dim3(nblocks_for(ncc)), dim3(kBlock), 0, s, nc, kf, kc);
@@ -236,9 +399,12 @@ int mg_vcycle(const MgHierarchy& H, double* partials, int max_blocks, hipStream_
     (void)max_blocks;
     const int L = H.levels;
     int cur[kMgMaxLevels] = {};
+    // the last two levels run in one block when there is a level above them
+    const bool tail = L >= 3;
+    const int Ldown = tail ? L - 2 : L - 1;
     // down: nu relaxation steps from zero, the last one replaced by the
     // residual; restrict the residual (a.t)
-    for (int l = 0; l < L - 1; ++l) {
+    for (int l = 0; l < Ldown; ++l) {
         const MgLevel& a = H.lv[l];
         const int nu = l == 0 ? H.sweeps : H.coarse_sweeps;
         int c = 0;
@@ -255,13 +421,19 @@ int mg_vcycle(const MgHierarchy& H, double* partials, int max_blocks, hipStream_
         launch_mg_restrict(H.lv[l + 1].n, a.t, H.lv[l + 1].f, s);
         cur[l] = c;
     }
-    const MgLevel& cl = H.lv[L - 1];
-    launch_mg_coarse_solve(cl.n, H.minv, cl.f, cl.x[0], s);
-    cur[L - 1] = 0;
+    if (tail) {
+        const MgLevel& t = H.lv[L - 2];
+        launch_mg_tail(t.n, H.coarse_sweeps, t.f, t.k, t.dinv, H.minv, t.x[0], s);
+        cur[L - 2] = 0;
+    } else {
+        const MgLevel& cl = H.lv[L - 1];
+        launch_mg_coarse_solve(cl.n, H.minv, cl.f, cl.x[0], s);
+        cur[L - 1] = 0;
+    }
     // up: interpolate and correct, nu relaxation steps (the adjoint of the
     // way down, so the cycle is a symmetric operator)
     int nb = 0;
-    for (int l = L - 2; l >= 0; --l) {
+    for (int l = Ldown - 1; l >= 0; --l) {
         const MgLevel& a = H.lv[l];
         const int nu = l == 0 ? H.sweeps : H.coarse_sweeps;
         int c = cur[l];
