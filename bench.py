@@ -60,6 +60,9 @@ def parse():
     ap.add_argument("--no-mg", action="store_true", help="skip the multigrid leg")
     ap.add_argument("--mg-sweeps", type=int, default=1, help="relaxation steps per leg of the V-cycle, finest level")
     ap.add_argument("--mg-coarse-sweeps", type=int, default=2, help="the same on coarser levels (0: as --mg-sweeps)")
+    ap.add_argument("--reliable-delta", type=float, default=None,
+                    help="mixed precision: refresh the float64 residual after this relative drop "
+                         "(default 1e-2, or 1e-3 with the multigrid preconditioner)")
     ap.add_argument("--calib-copy", action="store_true",
                     help="after the timed steps, run three 64 MiB device copies (a kernel of known traffic, "
                          "for scaling hardware byte counters)")
@@ -324,7 +327,8 @@ def main():
     h = Homogenization(n, (w.k0, w.kmin), w.target, vf=w.vf, penal=w.penal, filter_radius=w.rfilter,
                        precision=args.precision, guess=args.guess, tol=w.tol, kernel_variant=args.variant,
                        tile_tx=args.solver_tx, tile_tz=args.solver_tz, preconditioner=args.preconditioner,
-                       mg_sweeps=args.mg_sweeps, mg_coarse_sweeps=args.mg_coarse_sweeps)
+                       mg_sweeps=args.mg_sweeps, mg_coarse_sweeps=args.mg_coarse_sweeps,
+                       reliable_delta=args.reliable_delta)
     h.set_density(w.rho0)
     def log(msg):
         print(msg, file=sys.stderr, flush=True)

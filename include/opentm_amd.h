@@ -141,7 +141,9 @@ typedef struct {
     int32_t check_every; /* host convergence check interval (iterations), >= 1; with
                             OTM_PRECOND_MG at most 2 is used */
     double reliable_delta; /* OTM_MIXED: refresh the float64 residual when the float32
-                              recursive residual has dropped by this factor */
+                              recursive residual has dropped by this factor (default
+                              1e-2; 1e-3 suits OTM_PRECOND_MG, whose iterations each cut
+                              the residual several-fold) */
     int32_t kernel_variant; /* 0: streaming z-march kernels (default; two nodes per
                                thread when n is even; with autotune on and automatic
                                tiles the fused iteration of 4 is chosen when it is

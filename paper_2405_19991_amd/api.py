@@ -46,7 +46,7 @@ class Homogenization:
                  target: Sequence[float] = (0.1, 0.1, 0.1, 0.0, 0.0, 0.0), vf: float = 0.3,
                  penal: float = 3.0, filter_radius: float = 1.5, precision: str = "fp64",
                  guess: str = "zero", tol: float = 1e-8, max_iter: int = 20000, check_every: int = 16,
-                 reliable_delta: float = 1e-2, move: float = 0.05, eta: float = 0.5, rho_min: float = 1e-3,
+                 reliable_delta: Optional[float] = None, move: float = 0.05, eta: float = 0.5, rho_min: float = 1e-3,
                  governor: Optional[Dict[str, float]] = None, stream=None, kernel_variant: int = 0,
                  tile_tz: int = 0, tile_tx: int = 0, autotune: bool = True, preconditioner: str = "jacobi",
                  mg_sweeps: int = 1, mg_coarse_sweeps: int = 2, objective: str = "mse", symmetry: str = "none"):
@@ -66,6 +66,8 @@ class Homogenization:
         s.precision = {"fp64": N.OTM_FP64, "mixed": N.OTM_MIXED}[precision]
         s.guess = {"zero": N.OTM_GUESS_ZERO, "previous": N.OTM_GUESS_PREVIOUS, "user": N.OTM_GUESS_USER,
                    "learned": N.OTM_GUESS_LEARNED}[guess]
+        if reliable_delta is None:  # a V-cycle iteration cuts the residual several-fold
+            reliable_delta = 1e-3 if preconditioner == "mg" else 1e-2
         s.tol, s.max_iter, s.check_every, s.reliable_delta = float(tol), int(max_iter), int(check_every), float(reliable_delta)
         s.kernel_variant, s.tile_tz, s.tile_tx = int(kernel_variant), int(tile_tz), int(tile_tx)
         s.autotune = int(bool(autotune))

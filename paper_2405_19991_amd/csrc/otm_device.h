@@ -242,6 +242,17 @@ __device__ inline void fused_state_of(const Scalars* sc, FusedState& s) {
     s.tol2 = sc->tol2;
 }
 
+// (i, j, k) of flat index v = i + n (j + n k) with 32-bit arithmetic (n^3 < 2^31
+// for n <= 1024): a 64-bit division is a long emulated sequence on the GPU.
+__device__ __forceinline__ void node_ijk(int64_t v, int n, int& i, int& j, int& k) {
+    const uint32_t u = (uint32_t)v, un = (uint32_t)n;
+    const uint32_t q = u / un;
+    i = (int)(u - q * un);
+    const uint32_t q2 = q / un;
+    j = (int)(q - q2 * un);
+    k = (int)q2;
+}
+
 static inline int nblocks_for(int64_t count) { return (int)((count + kBlock - 1) / kBlock); }
 
 // Clamp grid size for grid-stride reductions so partial arrays stay small.

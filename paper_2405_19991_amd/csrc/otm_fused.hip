@@ -532,7 +532,8 @@ __global__ void __launch_bounds__(kBlock)
     for (int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x; v < nn; v += (int64_t)gridDim.x * kBlock) {
         double ax[3] = {0.0, 0.0, 0.0};
         if (!x_zero) {
-            const int i = (int)(v % n), j = (int)((v / n) % n), kk = (int)(v / ((int64_t)n * n));
+            int i, j, kk;
+            node_ijk(v, n, i, j, kk);
             const Nbr o = nbr_of(i, j, kk, n);
             double ko[8];
             load_k8(k, o, ko);

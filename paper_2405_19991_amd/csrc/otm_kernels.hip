@@ -57,7 +57,8 @@ __device__ __forceinline__ void b_filter(int bid_, int nblk_, int n, FilterW f, 
                                                    double* __restrict__ out) {
     const int64_t nn = (int64_t)n * n * n;
     for (int64_t e = (int64_t)bid_ * kBlock + threadIdx.x; e < nn; e += (int64_t)nblk_ * kBlock) {
-        const int i = (int)(e % n), j = (int)((e / n) % n), k = (int)(e / ((int64_t)n * n));
+        int i, j, k;
+        node_ijk(e, n, i, j, k);
         out[e] = filter_at(in, n, i, j, k, f);
     }
 }
@@ -73,9 +74,10 @@ __device__ __forceinline__ void b_filter_simp(int bid_, int nblk_, int n, Filter
     const int64_t nn = (int64_t)n * n * n;
     double acc[2] = {0.0, 0.0};
     for (int64_t e = (int64_t)bid_ * kBlock + threadIdx.x; e < nn; e += (int64_t)nblk_ * kBlock) {
-        const int i = (int)(e % n), j = (int)((e / n) % n), kk = (int)(e / ((int64_t)n * n));
+        int i, j, kk;
+        node_ijk(e, n, i, j, kk);
         const double rf = filter_at(rho, n, i, j, kk, f);
-        const double rp = pow(rf, p);
+        const double rp = (p == 3.0) ? rf * rf * rf : pow(rf, p);  // the paper's p = 3 without pow
         const double ke = kmin + rp * (k0 - kmin);
         rhof[e] = rf;
         k[e] = ke;
@@ -102,7 +104,8 @@ __device__ __forceinline__ void b_setup_nodes(int bid_, int nblk_, int n, const 
     const int64_t nn = (int64_t)n * n * n;
     double acc[3] = {0.0, 0.0, 0.0};
     for (int64_t v = (int64_t)bid_ * kBlock + threadIdx.x; v < nn; v += (int64_t)nblk_ * kBlock) {
-        const int i = (int)(v % n), j = (int)((v / n) % n), kk = (int)(v / ((int64_t)n * n));
+        int i, j, kk;
+        node_ijk(v, n, i, j, kk);
         const int xi[2] = {wrapi(i - 1, n), i};
         const int yj[2] = {wrapi(j - 1, n) * n, j * n};
         const int zk[2] = {wrapi(kk - 1, n) * n * n, kk * n * n};
@@ -142,7 +145,8 @@ __global__ void __launch_bounds__(kBlock) k_apply(int n, const T* __restrict__ k
     const int64_t nn = (int64_t)n * n * n;
     const int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (v >= nn) return;
-    const int i = (int)(v % n), j = (int)((v / n) % n), kk = (int)(v / ((int64_t)n * n));
+    int i, j, kk;
+    node_ijk(v, n, i, j, kk);
     const Nbr o = nbr_of(i, j, kk, n);
     T ko[8];
     load_k8(k, o, ko);
@@ -168,7 +172,8 @@ __device__ __forceinline__ void b_residual(int bid_, int nblk_, int n, const dou
     for (int64_t v = (int64_t)bid_ * kBlock + threadIdx.x; v < nn; v += (int64_t)nblk_ * kBlock) {
         double ax[3] = {0.0, 0.0, 0.0};
         if (!x_zero) {
-            const int i = (int)(v % n), j = (int)((v / n) % n), kk = (int)(v / ((int64_t)n * n));
+            int i, j, kk;
+            node_ijk(v, n, i, j, kk);
             const Nbr o = nbr_of(i, j, kk, n);
             double ko[8];
             load_k8(k, o, ko);
@@ -226,7 +231,8 @@ __global__ void __launch_bounds__(kBlock) k_apply_pq(int n, const T* __restrict_
     const int act[3] = {sc->active[0], sc->active[1], sc->active[2]};
     double acc[3] = {0.0, 0.0, 0.0};
     for (int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x; v < nn; v += (int64_t)gridDim.x * kBlock) {
-        const int i = (int)(v % n), j = (int)((v / n) % n), kk = (int)(v / ((int64_t)n * n));
+        int i, j, kk;
+        node_ijk(v, n, i, j, kk);
         const Nbr o = nbr_of(i, j, kk, n);
         T ko[8];
         load_k8(k, o, ko);
@@ -346,7 +352,8 @@ __device__ __forceinline__ void b_energy(int bid_, int nblk_, int n, const doubl
     const int64_t nn = (int64_t)n * n * n;
     double acc[6] = {0, 0, 0, 0, 0, 0};
     for (int64_t e = (int64_t)bid_ * kBlock + threadIdx.x; e < nn; e += (int64_t)nblk_ * kBlock) {
-        const int i = (int)(e % n), j = (int)((e / n) % n), kk = (int)(e / ((int64_t)n * n));
+        int i, j, kk;
+        node_ijk(e, n, i, j, kk);
         double E[6];
         element_energies(chi, nn, n, i, j, kk, E);
         const double ke = k[e];
@@ -364,13 +371,15 @@ __device__ __forceinline__ void b_sens(int bid_, int nblk_, int n, const double*
                                                  W6 w, double k0, double kmin, double p, double* __restrict__ st) {
     const int64_t nn = (int64_t)n * n * n;
     for (int64_t e = (int64_t)bid_ * kBlock + threadIdx.x; e < nn; e += (int64_t)nblk_ * kBlock) {
-    const int i = (int)(e % n), j = (int)((e / n) % n), kk = (int)(e / ((int64_t)n * n));
+    int i, j, kk;
+    node_ijk(e, n, i, j, kk);
     double E[6];
     element_energies(chi, nn, n, i, j, kk, E);
     double s = 0.0;
 #pragma unroll
     for (int c = 0; c < 6; ++c) s += w.w[c] * E[c];
-    st[e] = p * pow(rhof[e], p - 1.0) * (k0 - kmin) * s / (double)nn;
+    const double rf = rhof[e];
+    st[e] = p * ((p == 3.0) ? rf * rf : pow(rf, p - 1.0)) * (k0 - kmin) * s / (double)nn;
     }
 }
 
@@ -738,7 +747,8 @@ __global__ void __launch_bounds__(kBlock) k_guess_dots(int n, const double* __re
     const int64_t nn = (int64_t)n * n * n;
     double acc[6] = {0, 0, 0, 0, 0, 0};
     for (int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x; v < nn; v += (int64_t)gridDim.x * kBlock) {
-        const int i = (int)(v % n), j = (int)((v / n) % n), kk = (int)(v / ((int64_t)n * n));
+        int i, j, kk;
+        node_ijk(v, n, i, j, kk);
         const Nbr o = nbr_of(i, j, kk, n);
         double ko[8];
         load_k8(k, o, ko);

@@ -41,7 +41,8 @@ __global__ void __launch_bounds__(kBlock) k_mg_dinv(int n, const float* __restri
     const uint32_t nn = (uint32_t)n * n * n;
     const uint32_t v = blockIdx.x * kBlock + threadIdx.x;
     if (v >= nn) return;
-    const int i = (int)(v % n), j = (int)((v / n) % n), kk = (int)(v / ((uint32_t)n * n));
+    int i, j, kk;
+    node_ijk(v, n, i, j, kk);
     float s = 0.f;
 #pragma unroll
     for (int c = 0; c < 8; ++c) {
