@@ -658,8 +658,9 @@ int oc_update(otm_ctx* c, double vstar, double* lambda_out) {
     const Workspace w = c->ws();
     const int n = c->n;
     (void)hipEventRecord(c->ev[5], c->stream);
-    launch_oc_prepare(n, c->rho, c->sens, c->oc.eta, c->ocq, c->stream);
-    launch_oc_init(vstar, n, c->oc.eta, w, c->stream);
+    int prep_blocks = 0;
+    launch_oc_prepare(n, c->rho, c->sens, c->oc.eta, c->oc.move, c->oc.rho_min, c->ocq, w, c->stream, &prep_blocks);
+    launch_oc_init(vstar, n, c->oc.eta, prep_blocks, w, c->stream);
     const int max_passes = 200 / kOcLevels + 2;
     int rc;
     for (int pass = 0; pass < max_passes; pass += 4) {

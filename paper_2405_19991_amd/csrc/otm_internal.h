@@ -157,8 +157,10 @@ void launch_energy(int n, const double* k, const double* chi, const Workspace& w
 void launch_sens(int n, const double* rhof, const double* chi, const double* w6, double k0, double kmin, double p,
                  double* st, hipStream_t s);
 
-void launch_oc_prepare(int n, const double* rho, const double* sens, double eta, double* q, hipStream_t s);
-void launch_oc_init(double vstar, int n, double eta, const Workspace& ws, hipStream_t s);
+// q_e and the bisection's upper bound per block (into ws.partials; their count in *nblocks_out)
+void launch_oc_prepare(int n, const double* rho, const double* sens, double eta, double move, double rho_min,
+                       double* q, const Workspace& ws, hipStream_t s, int* nblocks_out);
+void launch_oc_init(double vstar, int n, double eta, int prep_blocks, const Workspace& ws, hipStream_t s);
 void launch_oc_pass(int n, const double* rho, const double* q, double move, double rho_min, double eta,
                     const Workspace& ws, hipStream_t s);
 void launch_oc_apply(int n, double* rho, const double* q, double eta, double move, double rho_min,

@@ -401,6 +401,46 @@ __global__ void __launch_bounds__(kBlock) k_oc_prepare(int64_t nn, const double*
                                                        const double* __restrict__ s, double eta,
                                                        double* __restrict__ q) { b_oc_prepare(blockIdx.x, gridDim.x, nn, rho, s, eta, q); }
 
+// q as above, plus per block the largest (q_e / lo_e)^(1/eta) -- at or above
+// that lambda every element of the block sits at its lower move limit
+// lo_e = max(rho_min, rho_e - m) -- and the sum of lo_e (partials[2b], [2b+1]).
+__global__ void __launch_bounds__(kBlock) k_oc_prepare_max(int64_t nn, const double* __restrict__ rho,
+                                                           const double* __restrict__ s, double eta, double move,
+                                                           double rho_min, double* __restrict__ q,
+                                                           double* __restrict__ partials) {
+    double tmax = 0.0, losum = 0.0;
+    for (int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x; e < nn; e += (int64_t)gridDim.x * kBlock) {
+        const double B = fmax(0.0, -s[e]) * (double)nn;
+        const double r = rho[e];
+        const double qe = r * (eta == 0.5 ? sqrt(B) : pow(B, eta));
+        q[e] = qe;
+        const double lo = fmax(rho_min, r - move);
+        const double ratio = qe / lo;
+        tmax = fmax(tmax, eta == 0.5 ? ratio * ratio : pow(ratio, 1.0 / eta));
+        losum += lo;
+    }
+    __shared__ double sh[2][kBlock / 64];
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        tmax = fmax(tmax, __shfl_xor(tmax, off, 64));
+        losum += __shfl_xor(losum, off, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        sh[0][threadIdx.x >> 6] = tmax;
+        sh[1][threadIdx.x >> 6] = losum;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        double m = sh[0][0], t = sh[1][0];
+        for (int w = 1; w < kBlock / 64; ++w) {
+            m = fmax(m, sh[0][w]);
+            t += sh[1][w];
+        }
+        partials[2 * blockIdx.x] = m;
+        partials[2 * blockIdx.x + 1] = t;
+    }
+}
+
 // Candidates of the next kOcLevels bisection levels below [l1, l2], in
 // breadth-first order of the midpoint tree, each computed exactly as the
 // sequential bisection would: mid = 0.5 (lo + hi) of its parent interval.
@@ -427,15 +467,34 @@ __device__ void oc_candidates_lane(Scalars* sc, double l1, double l2, double eta
     sc->cpow[t] = (eta == 0.5) ? 1.0 / sqrt(mid) : pow(mid, -eta);
 }
 
-__global__ void k_oc_init(Scalars* sc, double vstar_n, double eta) {
+// Bisection bracket [0, l2]: l2 = 1e9, lowered to just above the largest
+// block bound of k_oc_prepare_max when that is smaller and the volume there
+// (every element at its lower move limit, the smallest volume any lambda
+// gives) is below V*: then no larger lambda can be the root, and the
+// bisection reaches its stopping width in fewer halvings.  Otherwise (no
+// positive bound, or a V* at or below that smallest volume, where the
+// bisection runs to the top of the bracket) the bracket stays [0, 1e9].
+// nblocks = 0 keeps 1e9.
+__global__ void k_oc_init(Scalars* sc, double vstar_n, double eta, const double* __restrict__ partials,
+                          int nblocks) {
+    __shared__ double sl2;
     if (threadIdx.x == 0) {
+        double t = 0.0, lo_sum = 0.0;
+        for (int b = 0; b < nblocks; ++b) {
+            t = fmax(t, partials[2 * b]);
+            lo_sum += partials[2 * b + 1];
+        }
+        const double up = t * (1.0 + 1e-12);
+        const bool lower = nblocks > 0 && t > 0.0 && up < 1e9 && lo_sum < vstar_n * (1.0 - 1e-12);
+        sl2 = lower ? up : 1e9;
         sc->l1 = 0.0;
-        sc->l2 = 1e9;
+        sc->l2 = sl2;
         sc->vstar_n = vstar_n;
         sc->oc_steps = 0;
         sc->oc_done = 0;
     }
-    oc_candidates_lane(sc, 0.0, 1e9, eta);
+    __syncthreads();
+    oc_candidates_lane(sc, 0.0, sl2, eta);
 }
 
 // One pass: sum clamp(q c_m, lo, hi) for every candidate, then walk the tree
@@ -859,12 +918,17 @@ void launch_sens(int n, const double* rhof, const double* chi, const double* w6,
     hipLaunchKernelGGL(k_sens, dim3(nblocks_for(cube(n))), dim3(kBlock), 0, s, n, rhof, chi, w, k0, kmin, p, st);
 }
 
-void launch_oc_prepare(int n, const double* rho, const double* sens, double eta, double* q, hipStream_t s) {
-    hipLaunchKernelGGL(k_oc_prepare, dim3(nblocks_for(cube(n))), dim3(kBlock), 0, s, cube(n), rho, sens, eta, q);
+void launch_oc_prepare(int n, const double* rho, const double* sens, double eta, double move, double rho_min,
+                       double* q, const Workspace& ws, hipStream_t s, int* nblocks_out) {
+    const int g = grid_for(cube(n), ws.max_blocks < 1024 ? ws.max_blocks : 1024);
+    hipLaunchKernelGGL(k_oc_prepare_max, dim3(g), dim3(kBlock), 0, s, cube(n), rho, sens, eta, move, rho_min, q,
+                       ws.partials);
+    *nblocks_out = g;
 }
 
-void launch_oc_init(double vstar, int n, double eta, const Workspace& ws, hipStream_t s) {
-    hipLaunchKernelGGL(k_oc_init, dim3(1), dim3(64), 0, s, ws.sc, vstar * (double)cube(n), eta);
+void launch_oc_init(double vstar, int n, double eta, int prep_blocks, const Workspace& ws, hipStream_t s) {
+    hipLaunchKernelGGL(k_oc_init, dim3(1), dim3(64), 0, s, ws.sc, vstar * (double)cube(n), eta, ws.partials,
+                       prep_blocks);
 }
 
 void launch_oc_pass(int n, const double* rho, const double* q, double move, double rho_min, double eta,
