@@ -475,14 +475,29 @@ __device__ void oc_candidates_lane(Scalars* sc, double l1, double l2, double eta
 // positive bound, or a V* at or below that smallest volume, where the
 // bisection runs to the top of the bracket) the bracket stays [0, 1e9].
 // nblocks = 0 keeps 1e9.
-__global__ void k_oc_init(Scalars* sc, double vstar_n, double eta, const double* __restrict__ partials,
-                          int nblocks) {
+__global__ void __launch_bounds__(kBlock) k_oc_init(Scalars* sc, double vstar_n, double eta,
+                                                    const double* __restrict__ partials, int nblocks) {
     __shared__ double sl2;
+    __shared__ double sh[2][kBlock / 64];
+    double t = 0.0, lo_sum = 0.0;
+    for (int b = threadIdx.x; b < nblocks; b += kBlock) {
+        t = fmax(t, partials[2 * b]);
+        lo_sum += partials[2 * b + 1];
+    }
+#pragma unroll
+    for (int off = 32; off > 0; off >>= 1) {
+        t = fmax(t, __shfl_xor(t, off, 64));
+        lo_sum += __shfl_xor(lo_sum, off, 64);
+    }
+    if ((threadIdx.x & 63) == 0) {
+        sh[0][threadIdx.x >> 6] = t;
+        sh[1][threadIdx.x >> 6] = lo_sum;
+    }
+    __syncthreads();
     if (threadIdx.x == 0) {
-        double t = 0.0, lo_sum = 0.0;
-        for (int b = 0; b < nblocks; ++b) {
-            t = fmax(t, partials[2 * b]);
-            lo_sum += partials[2 * b + 1];
+        for (int w = 1; w < kBlock / 64; ++w) {
+            t = fmax(t, sh[0][w]);
+            lo_sum += sh[1][w];
         }
         const double up = t * (1.0 + 1e-12);
         const bool lower = nblocks > 0 && t > 0.0 && up < 1e9 && lo_sum < vstar_n * (1.0 - 1e-12);
@@ -927,7 +942,7 @@ void launch_oc_prepare(int n, const double* rho, const double* sens, double eta,
 }
 
 void launch_oc_init(double vstar, int n, double eta, int prep_blocks, const Workspace& ws, hipStream_t s) {
-    hipLaunchKernelGGL(k_oc_init, dim3(1), dim3(64), 0, s, ws.sc, vstar * (double)cube(n), eta, ws.partials,
+    hipLaunchKernelGGL(k_oc_init, dim3(1), dim3(kBlock), 0, s, ws.sc, vstar * (double)cube(n), eta, ws.partials,
                        prep_blocks);
 }
 
