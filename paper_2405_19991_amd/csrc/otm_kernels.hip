@@ -849,8 +849,131 @@ __global__ void __launch_bounds__(kBlock) k_scale3(int64_t nn, double* __restric
 
 static inline int64_t cube(int n) { return (int64_t)n * n * n; }
 
+// Z-march form of the filter for reach 1 (radius in (1, 2], the default 1.5):
+// a block owns a column of 32 x 8 elements and marches tz planes in z.  Each
+// incoming plane (with a one-element periodic halo in x and y) goes to a
+// two-slot LDS ring; the thread filters it in x then y (the same order and
+// weights as filter_at), keeps the last three such values in registers, and
+// finishes element plane P-1 from planes P-2, P-1, P.  SIMP: also k, k32 and
+// the sums of rho and rho~^p.
+constexpr int kFzX = 32, kFzY = 8, kFzPX = kFzX + 2, kFzPY = kFzY + 2;
+constexpr int kFzHalo = 2 * kFzPX + 2 * kFzY;
+
+struct FzShape {
+    int ntx, nty, tz, blocks;
+};
+
+static FzShape fz_shape(int n, int max_blocks) {
+    FzShape f;
+    f.ntx = (n + kFzX - 1) / kFzX;
+    f.nty = (n + kFzY - 1) / kFzY;
+    const int cols = f.ntx * f.nty;
+    int nz = (n + 7) / 8;
+    if ((int64_t)cols * nz > max_blocks) nz = max_blocks / cols > 0 ? max_blocks / cols : 1;
+    f.tz = (n + nz - 1) / nz;
+    f.blocks = cols * ((n + f.tz - 1) / f.tz);
+    return f;
+}
+
+template <bool SIMP>
+__global__ void __launch_bounds__(kBlock) k_filter_zm(int n, int tz, int ntx, int nty, double w0, double w1,
+                                                      double w2, const double* __restrict__ in,
+                                                      double* __restrict__ out, double* __restrict__ kout,
+                                                      float* __restrict__ k32, double k0, double kmin, double p,
+                                                      double* __restrict__ partials) {
+    static_assert(kFzX * kFzY == kBlock && kFzHalo <= kBlock, "tile");
+    __shared__ double sp[2][kFzPY * kFzPX];
+    int bid = xcd_tile(blockIdx.x, gridDim.x);
+    const int bx = bid % ntx;
+    bid /= ntx;
+    const int by = bid % nty;
+    const int bz = bid / nty;
+    const int i0 = bx * kFzX, j0 = by * kFzY, z0 = bz * tz, z1 = min(z0 + tz, n);
+    const int tx = threadIdx.x % kFzX, ty = threadIdx.x / kFzX;
+    const int i = i0 + tx, j = j0 + ty;
+    const bool own = i < n && j < n;
+    const int64_t n2 = (int64_t)n * n;
+    // every interior cell is loaded (periodically wrapped) so that the own
+    // elements next to a partial tile's edge read correct neighbours
+    const int64_t xy_in = (int64_t)(i % n) + (int64_t)n * (j % n);
+    const int l_in = (ty + 1) * kFzPX + tx + 1;
+    const int tid = threadIdx.x;
+    const bool has_h = tid < kFzHalo;
+    int64_t xy_h = 0;
+    int l_h = 0;
+    if (has_h) {
+        int px, py;
+        if (tid < kFzPX) {
+            px = tid;
+            py = 0;
+        } else if (tid < 2 * kFzPX) {
+            px = tid - kFzPX;
+            py = kFzPY - 1;
+        } else if (tid < 2 * kFzPX + kFzY) {
+            px = 0;
+            py = 1 + tid - 2 * kFzPX;
+        } else {
+            px = kFzPX - 1;
+            py = 1 + tid - 2 * kFzPX - kFzY;
+        }
+        const int gi = ((i0 - 1 + px) % n + n) % n, gj = ((j0 - 1 + py) % n + n) % n;
+        xy_h = (int64_t)gi + (int64_t)n * gj;
+        l_h = py * kFzPX + px;
+    }
+    double f_m2 = 0.0, f_m1 = 0.0, own_m1 = 0.0;
+    double acc[2] = {0.0, 0.0};
+    for (int P = z0 - 1; P <= z1; ++P) {
+        const int pw = P < 0 ? P + n : (P >= n ? P - n : P);
+        const double* pl = in + (int64_t)pw * n2;
+        const int slot = P & 1;
+        const double vin = pl[xy_in];
+        sp[slot][l_in] = vin;
+        if (has_h) sp[slot][l_h] = pl[xy_h];
+        __syncthreads();
+        const double* L = sp[slot];
+        double fy = 0.0;
+#pragma unroll
+        for (int dy = -1; dy <= 1; ++dy) {
+            const double* row = L + l_in + dy * kFzPX;
+            double fx = 0.0;
+            fx += w0 * row[-1];
+            fx += w1 * row[0];
+            fx += w2 * row[1];
+            fy += (dy < 0 ? w0 : (dy == 0 ? w1 : w2)) * fx;
+        }
+        if (P - 1 >= z0 && own) {
+            double v = 0.0;
+            v += w0 * f_m2;
+            v += w1 * f_m1;
+            v += w2 * fy;
+            const int64_t e = (int64_t)(P - 1) * n2 + xy_in;
+            out[e] = v;
+            if (SIMP) {
+                const double rp = (p == 3.0) ? v * v * v : pow(v, p);
+                const double ke = kmin + rp * (k0 - kmin);
+                kout[e] = ke;
+                if (k32) k32[e] = (float)ke;
+                acc[0] += own_m1;
+                acc[1] += rp;
+            }
+        }
+        f_m2 = f_m1;
+        f_m1 = fy;
+        own_m1 = vin;
+    }
+    if (SIMP) block_partials<2>(acc, partials);
+}
+
 void launch_filter_simp(int n, double r, const double* rho, double* rhof, double* k, float* k32, double k0,
                         double kmin, double p, const Workspace& ws, hipStream_t s) {
+    const FilterW fw = filter_weights(r);
+    if (fw.R == 1) {
+        const FzShape z = fz_shape(n, ws.max_blocks);
+        hipLaunchKernelGGL(k_filter_zm<true>, dim3(z.blocks), dim3(kBlock), 0, s, n, z.tz, z.ntx, z.nty, fw.w[0],
+                           fw.w[1], fw.w[2], rho, rhof, k, k32, k0, kmin, p, ws.partials);
+        launch_finalize(FIN_FILTER_SIMP, z.blocks, ws, s);
+        return;
+    }
     const int g = grid_for(cube(n), ws.max_blocks);
     hipLaunchKernelGGL(k_filter_simp, dim3(g), dim3(kBlock), 0, s, n, filter_weights(r), rho, rhof, k, k32, k0, kmin,
                        p, ws.partials, ws.counter, ws.sc);
@@ -858,7 +981,14 @@ void launch_filter_simp(int n, double r, const double* rho, double* rhof, double
 }
 
 void launch_filter(int n, double r, const double* in, double* out, hipStream_t s) {
-    hipLaunchKernelGGL(k_filter, dim3(nblocks_for(cube(n))), dim3(kBlock), 0, s, n, filter_weights(r), in, out);
+    const FilterW fw = filter_weights(r);
+    if (fw.R == 1) {
+        const FzShape z = fz_shape(n, kMaxBlocks);
+        hipLaunchKernelGGL(k_filter_zm<false>, dim3(z.blocks), dim3(kBlock), 0, s, n, z.tz, z.ntx, z.nty, fw.w[0],
+                           fw.w[1], fw.w[2], in, out, nullptr, nullptr, 0.0, 0.0, 0.0, nullptr);
+        return;
+    }
+    hipLaunchKernelGGL(k_filter, dim3(nblocks_for(cube(n))), dim3(kBlock), 0, s, n, fw, in, out);
 }
 
 void launch_setup_nodes(int n, const double* k, double* b, double* dinv, float* dinv32, const Workspace& ws,
