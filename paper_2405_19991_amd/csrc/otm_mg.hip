@@ -219,8 +219,9 @@ __global__ void __launch_bounds__(kBlock) k_mg_coarse_solve(int N, const float* 
 // -k_e/12 for the 8 corners, 0 for the 6 axis neighbours.
 constexpr int kMgTailMax = 512;
 
+template <int PITCH>
 __device__ __forceinline__ void tail_apply(int n, int i, int j, int kk, const float* __restrict__ sk,
-                                           const float (*__restrict__ x)[kMgTailMax], float y[3]) {
+                                           const float (*__restrict__ x)[PITCH], float y[3]) {
     int ci[3], cj[3], ck[3];  // wrapped coordinates of offsets -1, 0, +1
 #pragma unroll
     for (int d = 0; d < 3; ++d) {
@@ -271,12 +272,15 @@ __device__ __forceinline__ void tail_apply(int n, int i, int j, int kk, const fl
             }
 }
 
-__global__ void __launch_bounds__(kMgTailMax) k_mg_tail(int n, int nu, const float* __restrict__ f,
-                                                       const float* __restrict__ k, const float* __restrict__ dinv,
-                                                       const float* __restrict__ minv, float* __restrict__ xout) {
-    __shared__ float sk[kMgTailMax];
-    __shared__ float sx[2][3][kMgTailMax];
-    __shared__ float sc[2][3][kMgCoarseMax];
+// One V-cycle over the second-coarsest level (n <= 8, one thread per node;
+// every thread of the block takes part in the barriers) and the coarsest
+// level below it, all in LDS: nu damped Jacobi steps from zero, the residual,
+// its restriction, the direct coarse solve, interpolation and correction, nu
+// steps.  f has pitch fp (global memory or LDS); k and D^-1 come from global
+// memory.  The result is left in sx[return value].
+__device__ __forceinline__ int mid_cycle(int n, int nu, const float* f, int fp, const float* __restrict__ k,
+                         const float* __restrict__ dinv, const float* __restrict__ minv, float* sk,
+                         float (*sx)[3][kMgTailMax], float (*sc)[3][kMgCoarseMax]) {
     const int N = n * n * n, nc = n / 2, Nc = nc * nc * nc;
     const int v = threadIdx.x;
     const bool own = v < N;
@@ -290,7 +294,7 @@ __global__ void __launch_bounds__(kMgTailMax) k_mg_tail(int n, int nu, const flo
         wd = kMgOmega * dinv[v];
 #pragma unroll
         for (int l = 0; l < 3; ++l) {
-            fv[l] = f[l * N + v];
+            fv[l] = f[l * fp + v];
             sx[0][l][v] = wd * fv[l];  // first step from zero
         }
     }
@@ -299,7 +303,7 @@ __global__ void __launch_bounds__(kMgTailMax) k_mg_tail(int n, int nu, const flo
     float y[3];
     for (int it = 1; it < nu; ++it) {
         if (own) {
-            tail_apply(n, i, j, kk, sk, sx[cur], y);
+            tail_apply<kMgTailMax>(n, i, j, kk, sk, sx[cur], y);
 #pragma unroll
             for (int l = 0; l < 3; ++l) sx[cur ^ 1][l][v] = sx[cur][l][v] + wd * (fv[l] - y[l]);
         }
@@ -308,7 +312,7 @@ __global__ void __launch_bounds__(kMgTailMax) k_mg_tail(int n, int nu, const flo
     }
     // residual into the other buffer, then its restriction to the coarsest level
     if (own) {
-        tail_apply(n, i, j, kk, sk, sx[cur], y);
+        tail_apply<kMgTailMax>(n, i, j, kk, sk, sx[cur], y);
 #pragma unroll
         for (int l = 0; l < 3; ++l) sx[cur ^ 1][l][v] = fv[l] - y[l];
     }
@@ -354,14 +358,26 @@ __global__ void __launch_bounds__(kMgTailMax) k_mg_tail(int n, int nu, const flo
     __syncthreads();
     for (int it = 0; it < nu; ++it) {
         if (own) {
-            tail_apply(n, i, j, kk, sk, sx[cur], y);
+            tail_apply<kMgTailMax>(n, i, j, kk, sk, sx[cur], y);
 #pragma unroll
             for (int l = 0; l < 3; ++l) sx[cur ^ 1][l][v] = sx[cur][l][v] + wd * (fv[l] - y[l]);
         }
         __syncthreads();
         cur ^= 1;
     }
-    if (own) {
+    return cur;
+}
+
+__global__ void __launch_bounds__(kMgTailMax) k_mg_tail(int n, int nu, const float* __restrict__ f,
+                                                       const float* __restrict__ k, const float* __restrict__ dinv,
+                                                       const float* __restrict__ minv, float* __restrict__ xout) {
+    __shared__ float sk[kMgTailMax];
+    __shared__ float sx[2][3][kMgTailMax];
+    __shared__ float sc[2][3][kMgCoarseMax];
+    const int N = n * n * n;
+    const int cur = mid_cycle(n, nu, f, N, k, dinv, minv, sk, sx, sc);
+    const int v = threadIdx.x;
+    if (v < N) {
 #pragma unroll
         for (int l = 0; l < 3; ++l) xout[l * N + v] = sx[cur][l][v];
     }
@@ -401,6 +417,8 @@ int mg_vcycle(const MgHierarchy& H, double* partials, int max_blocks, hipStream_
     const int L = H.levels;
     int cur[kMgMaxLevels] = {};
     // the last two levels run in one block when there is a level above them
+    // (one CU relaxes an 8^3 level faster than the launches would take; a
+    // 16^3 level is already slower there than as grid-wide passes)
     const bool tail = L >= 3;
     const int Ldown = tail ? L - 2 : L - 1;
     // down: nu relaxation steps from zero, the last one replaced by the
