@@ -226,7 +226,7 @@ void launch_fused(int n, const TileShape& t, bool all_active, const T* r_in, con
                   bool chained, bool fin, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 // Multigrid V-cycle preconditioner (otm_mg.hip), float32.
 constexpr int kMgMaxLevels = 10;
-constexpr float kMgOmega = 0.8f;  // damped Jacobi weight of the relaxation
+constexpr float kMgOmega = 0.9f;  // damped Jacobi weight of the relaxation
 enum MgMarch { MG_NONE = 0, MG_RELAX = 1, MG_RESID = 2 };
 constexpr int kMgCoarseMax = 64;  // nodes of the coarsest level (direct solve)
 struct MgLevel {

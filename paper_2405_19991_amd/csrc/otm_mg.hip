@@ -7,7 +7,7 @@
 // stiffness of a cube of edge h is h times the unit-cube matrix), so the
 // coarse operator is the same hex-8 stencil on the coarse conductivities.
 // Interpolation P is trilinear and restriction R = P^T.  Relaxation is damped
-// Jacobi (weight 0.8; by Gershgorin every eigenvalue of D^-1 A lies in [0, 2]
+// Jacobi (weight 0.9; by Gershgorin every eigenvalue of D^-1 A lies in [0, 2]
 // for any conductivity field), the same number of steps in both legs, so the
 // V-cycle is a symmetric positive definite operator and a valid PCG
 // preconditioner.  Each relaxation step (and the residual before a
