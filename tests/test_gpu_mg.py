@@ -141,3 +141,33 @@ def test_mg_cell128_matches_oracle():
     err = np.linalg.norm(np.array(kappa) - k_ref) / np.linalg.norm(k_ref)
     print(f"mg cell128: iterations {st['iterations']}, relative tensor error {err:.3e}", flush=True)
     assert err <= 1e-5
+
+
+def test_mg_cell256_properties():
+    """256^3 (16.8 M nodes; the oracle cannot assemble it): the multigrid
+    tensor equals the Jacobi-PCG tensor of the same cell at the mixed bar,
+    and both satisfy properties that hold at any size -- symmetric positive
+    definite, between the Reuss and Voigt bounds of the filtered
+    conductivities (harmonic and arithmetic means)."""
+    from paper_2405_19991_amd import Homogenization
+    n = 256
+    rho = synth.smoothed_noise(n, 0.15, 0.45, 256)
+    res = {}
+    for pc in ("mg", "jacobi"):
+        print(f"cell256 {pc}", flush=True)
+        with Homogenization(n, (1.0, 1e-3), (0.3, 0.2, 0.1, 0.1, 0.05, 0.05), vf=0.3, precision="mixed", tol=1e-6,
+                            preconditioner=pc) as h:
+            h.set_density(rho)
+            kappa, st = h.homogenize()
+            if pc == "mg":
+                k = h.get_field("k")
+        assert st["converged"], (pc, st)
+        res[pc] = (np.array(kappa), st["iterations"])
+    print(f"cell256 iterations: mg {res['mg'][1]}, jacobi {res['jacobi'][1]}", flush=True)
+    assert rel_fro(res["mg"][0], res["jacobi"][0]) <= 1e-5
+    kap = res["mg"][0]
+    K = np.array([[kap[0], kap[3], kap[5]], [kap[3], kap[1], kap[4]], [kap[5], kap[4], kap[2]]])
+    ev = np.linalg.eigvalsh(K)
+    voigt, reuss = k.mean(), 1.0 / np.mean(1.0 / k)
+    assert ev.min() > 0.0
+    assert ev.max() <= voigt * (1 + 1e-6) and ev.min() >= reuss * (1 - 1e-6)
