@@ -44,7 +44,7 @@ class Homogenization:
 
     def __init__(self, n: int, heat_ratio: Sequence[float] = (1.0, 1e-3),
                  target: Sequence[float] = (0.1, 0.1, 0.1, 0.0, 0.0, 0.0), vf: float = 0.3,
-                 penal: float = 3.0, filter_radius: float = 1.5, precision: str = "fp64",
+                 penal: float = 3.0, filter_radius: float = 1.5, precision: Optional[str] = None,
                  guess: str = "zero", tol: float = 1e-8, max_iter: int = 20000, check_every: int = 16,
                  reliable_delta: Optional[float] = None, move: float = 0.05, eta: float = 0.5, rho_min: float = 1e-3,
                  governor: Optional[Dict[str, float]] = None, stream=None, kernel_variant: int = 0,
@@ -63,6 +63,8 @@ class Homogenization:
         p.objective = OBJECTIVES[objective]
         p.symmetry = {"none": N.OTM_SYM_NONE, "central": N.OTM_SYM_CENTRAL}[symmetry]
         s, o, g = N.default_options()
+        if precision is None:  # the V-cycle runs in float32: multigrid implies mixed precision
+            precision = "mixed" if preconditioner == "mg" else "fp64"
         s.precision = {"fp64": N.OTM_FP64, "mixed": N.OTM_MIXED}[precision]
         s.guess = {"zero": N.OTM_GUESS_ZERO, "previous": N.OTM_GUESS_PREVIOUS, "user": N.OTM_GUESS_USER,
                    "learned": N.OTM_GUESS_LEARNED}[guess]

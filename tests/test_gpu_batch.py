@@ -80,3 +80,34 @@ def test_graph_replay_equals_eager():
             assert rg[s][d]["pcg_iters"] == re_[s][d]["pcg_iters"]
     for a, b in zip(pg, pe):
         np.testing.assert_array_equal(a, b)
+
+
+def test_batch_full_size_mix_matches_singles_and_oracle():
+    """The 64-design mix (n in {32, 48, 64}) exactly as the benchmark runs it
+    (autotuned tiles, tol 1e-6): the first tensors of one design of each size
+    equal single-design contexts', and the first 32^3 design's equals the
+    oracle's (the tensor error is second order in the solve tolerance)."""
+    from paper_2405_19991_amd import Batch, Homogenization
+    ws = synth.config4()
+    assert len(ws) == 64 and {w.n for w in ws} == {32, 48, 64}
+    B = Batch([dict(n=w.n, target=w.target, vf=w.vf) for w in ws], tol=1e-6)
+    for d, w in enumerate(ws):
+        B.set_density(d, w.rho0)
+    recs = B.step()
+    B.close()
+    picks = {}
+    for d, w in enumerate(ws):
+        picks.setdefault(w.n, d)
+    for n, d in sorted(picks.items()):
+        w = ws[d]
+        with Homogenization(n, (w.k0, w.kmin), w.target, vf=w.vf, tol=1e-6) as h:
+            h.set_density(w.rho0)
+            kappa, _ = h.homogenize()
+        rel = np.linalg.norm(np.array(recs[d]["kappa"]) - np.array(kappa)) / np.linalg.norm(kappa)
+        print(f"design {d} (n={n}): batch vs single {rel:.2e}", flush=True)
+        assert rel <= 1e-8
+    d = picks[32]
+    ref = O.homogenize(ws[d].rho0, O.Params(tol=1e-12))
+    rel = np.linalg.norm(np.array(recs[d]["kappa"]) - ref["kappa"]) / np.linalg.norm(ref["kappa"])
+    print(f"design {d} (n=32): batch vs oracle {rel:.2e}", flush=True)
+    assert rel <= 1e-8
