@@ -50,6 +50,7 @@ def parse():
     ap.add_argument("--no-warm-start", action="store_true", help="skip the warm-start leg")
     ap.add_argument("--no-configs", action="store_true", help="skip the 16^3 / 64^3 legs")
     ap.add_argument("--no-gallery", action="store_true", help="skip the 61-target traversal leg")
+    ap.add_argument("--no-full-run", action="store_true", help="skip the 150-iteration design runs")
     ap.add_argument("--gallery-iters", type=int, default=150)
     ap.add_argument("--variant", type=int, default=0,
                     help="solver kernel: 0 automatic (autotuned), 4 fused iteration, 1-3 cross-check kernels")
@@ -196,6 +197,33 @@ def multigrid_leg(w, steps: int, log, sweeps: int = 1, coarse_sweeps: int = 2):
     log(f"multigrid: {1e3 * out['s_per_oc_iter']:.2f} ms per design iteration, "
         f"{out['pcg_iters_per_step']:.1f} PCG iterations per step")
     return out
+
+
+def full_run_leg(w, log, iters: int = 150):
+    """The 128^3 configuration's whole design run (150 design iterations,
+    previous solution as the start, mixed precision, tol 1e-6) with the
+    multigrid and with the Jacobi preconditioner: seconds per design iteration
+    over iterations 2..150, PCG iterations per solve, final objective."""
+    import torch
+    from paper_2405_19991_amd import Homogenization
+    out = {}
+    for pc in ("mg", "jacobi"):
+        with Homogenization(w.n, (w.k0, w.kmin), w.target, vf=w.vf, penal=w.penal, filter_radius=w.rfilter,
+                            precision="mixed", tol=w.tol, preconditioner=pc, guess="previous") as h:
+            h.set_density(w.rho0)
+            h.step()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            recs = [h.step() for _ in range(iters - 1)]
+            torch.cuda.synchronize()
+            dt = time.perf_counter() - t0
+        its = [max(r["pcg_iters"]) for r in recs]
+        out[pc] = {"s_per_oc_iter": dt / (iters - 1), "s_total": dt, "pcg_iters_max": max(its),
+                   "pcg_iters_last": its[-1], "g_last": recs[-1]["g"],
+                   "max_rel_residual": max(max(r["rel_residual"]) for r in recs)}
+        log(f"full run {pc}: {1e3 * out[pc]['s_per_oc_iter']:.2f} ms per design iteration over {iters - 1}, "
+            f"g {recs[-1]['g']:.4e}")
+    return {"workload": w.name + "_mixed_150_iterations", "iterations": iters, **out}
 
 
 def gallery_leg(iters: int, log, n: int = 32):
@@ -445,6 +473,8 @@ def main():
         mg = multigrid_leg(w, args.steps, log, args.mg_sweeps, args.mg_coarse_sweeps)
         mg["kappa_rel_err_vs_oracle"] = oracle_tensor_error(w, mg.pop("first_kappa"), args.tol)
         out["multigrid"] = mg
+    if not args.no_full_run and args.precision == "mixed" and n == 128:
+        out["full_run"] = full_run_leg(w, log)
     if not args.no_batch:
         out["batch"] = batch_leg(args.batch_steps, log)
     if not args.no_configs:
