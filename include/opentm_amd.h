@@ -297,6 +297,12 @@ int otm_prepare(otm_ctx* ctx);
 int otm_apply_device(int32_t n, int32_t precision, int32_t variant, const void* k_dev, const void* x_dev,
                      void* y_dev, void* stream);
 
+/* As otm_apply_device with an explicit tile (tile_tx, tile_tz as for
+ * otm_time_apply_device; 0 = automatic): one launch on `stream`, no
+ * synchronisation.  Errors as otm_apply_device. */
+int otm_apply_device_tiled(int32_t n, int32_t precision, int32_t variant, int32_t tile_tx, int32_t tile_tz,
+                           const void* k_dev, const void* x_dev, void* y_dev, void* stream);
+
 /* Timing of the stateless operator: runs `reps` launches of the operator on
  * `stream` and returns the mean kernel duration in microseconds, measured
  * with HIP events on that stream.  tile_tx / tile_tz: tile shape of the

@@ -5,5 +5,5 @@ kernels, exposed through a C ABI (include/opentm_amd.h).
 The library is loaded lazily on first use and must have been built
 (``paper_2405_19991_amd/build.py``); there is no CPU fallback.
 """
-from .api import (Batch, Homogenization, Network, apply_device, init_density, run_instance,  # noqa: F401
-                  time_apply_device, version)
+from .api import (Batch, Homogenization, Network, apply_device, apply_device_tiled, init_density,  # noqa: F401
+                  run_instance, time_apply_device, version)

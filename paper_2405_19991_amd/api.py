@@ -244,6 +244,18 @@ def apply_device(k, x, y, precision: str = "fp64", stream=None, variant: int = 0
                                      ctypes.c_void_p(y.data_ptr()), ctypes.c_void_p(s)))
 
 
+def apply_device_tiled(k, x, y, precision: str, tile_tx: int, tile_tz: int, variant: int = 0, stream=None) -> None:
+    """One y = A x launch with an explicit tile, on the given (default: the
+    current torch) stream, not synchronised."""
+    import torch
+    n = round(k.numel() ** (1.0 / 3.0))
+    s = stream if stream is not None else torch.cuda.current_stream().cuda_stream
+    N.check(N.lib().otm_apply_device_tiled(n, N.OTM_FP64 if precision == "fp64" else N.OTM_MIXED, int(variant),
+                                           int(tile_tx), int(tile_tz), ctypes.c_void_p(k.data_ptr()),
+                                           ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr()),
+                                           ctypes.c_void_p(s)))
+
+
 def time_apply_device(k, x, y, precision: str = "fp64", reps: int = 50, stream=None, variant: int = 0,
                       tile_tx: int = 0, tile_tz: int = 0) -> float:
     import torch

@@ -1511,6 +1511,11 @@ int otm_apply_device(int32_t n, int32_t precision, int32_t variant, const void* 
     return apply_device_impl(n, precision, variant, 0, 0, k, x, y, stream);
 }
 
+int otm_apply_device_tiled(int32_t n, int32_t precision, int32_t variant, int32_t tx, int32_t tz, const void* k,
+                           const void* x, void* y, void* stream) {
+    return apply_device_impl(n, precision, variant, tx, tz, k, x, y, stream);
+}
+
 int otm_time_apply_device(int32_t n, int32_t precision, int32_t variant, int32_t tx, int32_t tz, const void* k,
                           const void* x, void* y, void* stream, int32_t reps, double* us) {
     if (reps < 1 || !us) return OTM_EINVAL;
