@@ -51,6 +51,7 @@ def parse():
     ap.add_argument("--no-configs", action="store_true", help="skip the 16^3 / 64^3 legs")
     ap.add_argument("--no-gallery", action="store_true", help="skip the 61-target traversal leg")
     ap.add_argument("--no-full-run", action="store_true", help="skip the 150-iteration design runs")
+    ap.add_argument("--no-fp64", action="store_true", help="skip the float64 leg")
     ap.add_argument("--gallery-iters", type=int, default=150)
     ap.add_argument("--variant", type=int, default=0,
                     help="solver kernel: 0 automatic (autotuned), 4 fused iteration, 1-3 cross-check kernels")
@@ -196,6 +197,33 @@ def multigrid_leg(w, steps: int, log, sweeps: int = 1, coarse_sweeps: int = 2):
            "first_pcg_iters": first["pcg_iters"], "steps": steps}
     log(f"multigrid: {1e3 * out['s_per_oc_iter']:.2f} ms per design iteration, "
         f"{out['pcg_iters_per_step']:.1f} PCG iterations per step")
+    return out
+
+
+def fp64_leg(steps: int, log):
+    """The 128^3 anisotropic cell with every vector and the operator in
+    float64 (Jacobi-PCG, tol 1e-6, zero start): one warm-up and `steps` timed
+    design iterations; PCG DOF-updates/s as for the headline value."""
+    import synth
+    import torch
+    from paper_2405_19991_amd import Homogenization
+    w = synth.config3("fp64")
+    w.tol = 1e-6
+    with Homogenization(w.n, (w.k0, w.kmin), w.target, vf=w.vf, penal=w.penal, filter_radius=w.rfilter,
+                        precision="fp64", tol=w.tol) as h:
+        h.set_density(w.rho0)
+        h.step()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        recs = [h.step() for _ in range(steps)]
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t0
+        tile = h.tile()
+    iters = sum(sum(r["pcg_iters"]) for r in recs)
+    out = {"workload": w.name + "_fp64", "n": w.n, "tol": w.tol, "steps": steps,
+           "pcg_dof_updates_per_s": w.n ** 3 * iters / dt, "s_per_oc_iter": dt / steps,
+           "pcg_iters_per_step": iters / steps, "solver_tile": tile}
+    log(f"fp64: {out['pcg_dof_updates_per_s']:.3e} DOF-updates/s, {1e3 * out['s_per_oc_iter']:.2f} ms per design iteration")
     return out
 
 
@@ -494,6 +522,8 @@ def main():
         mg = multigrid_leg(w, args.steps, log, args.mg_sweeps, args.mg_coarse_sweeps)
         mg["kappa_rel_err_vs_oracle"] = oracle_tensor_error(w, mg.pop("first_kappa"), args.tol)
         out["multigrid"] = mg
+    if not args.no_fp64 and args.precision == "mixed" and n == 128:
+        out["fp64"] = fp64_leg(args.steps, log)
     if not args.no_full_run and args.precision == "mixed" and n == 128:
         out["full_run"] = full_run_leg(w, log)
     if not args.no_batch:
