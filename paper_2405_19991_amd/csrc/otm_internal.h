@@ -320,7 +320,6 @@ template <typename T>
 void launch_apply(int n, const T* k, const T* x, T* y, hipStream_t s);
 
 void launch_fill_u32(unsigned* p, int count, unsigned v, hipStream_t s);
-void launch_set_f64(double* dst, double v, hipStream_t s);
 void launch_cast_f64_f32(int64_t count, const double* in, float* out, hipStream_t s);
 void launch_cast_f32_f64(int64_t count, const float* in, double* out, hipStream_t s);
 

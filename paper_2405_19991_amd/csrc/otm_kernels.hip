@@ -1130,12 +1130,6 @@ template void launch_apply<float>(int, const float*, const float*, float*, hipSt
 
 namespace otm {
 
-__global__ void k_set_f64(double* dst, double v) {
-    if (threadIdx.x == 0 && blockIdx.x == 0) *dst = v;
-}
-
-void launch_set_f64(double* dst, double v, hipStream_t s) { hipLaunchKernelGGL(k_set_f64, dim3(1), dim3(64), 0, s, dst, v); }
-
 __global__ void k_cast_f64_f32(int64_t count, const double* __restrict__ in, float* __restrict__ out) {
     const int64_t t = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (t < count) out[t] = (float)in[t];
