@@ -73,7 +73,8 @@ extern "C" {
 #define OTM_PRECOND_MG 1     /* one geometric multigrid V-cycle per iteration (Sec. 2.4, Algorithm 3):
                                 damped Jacobi relaxation on S_v, restriction of the residual,
                                 direct solve on the coarsest level, interpolation and correction.
-                                OTM_MIXED only (the V-cycle runs in float32); n = m 2^j with
+                                The V-cycle runs in float32; with OTM_FP64 the Krylov vectors,
+                                dots and convergence test stay float64.  n = m 2^j with
                                 m in {3, 4} and n >= 6, else OTM_EINVAL */
 
 #define OTM_OBJ_MSE 0 /* g = sum_c (kappa_c - target_c)^2, Sec. 4.4 (MSE objective) */

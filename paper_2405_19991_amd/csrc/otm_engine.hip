@@ -82,7 +82,9 @@ struct otm_ctx {
     bool use_mg = false;
     MgHierarchy mg;
     std::vector<void*> mg_bufs;
-    float* ones32 = nullptr;       // D^-1 := 1 for the direction pass and the update
+    float* ones32 = nullptr;       // D^-1 := 1 for the direction pass and the update (mixed)
+    double* ones64 = nullptr;      // the same for float64 contexts
+    double* z64 = nullptr;         // float64 copy of the cycle's output (float64 contexts)
     const float* mg_z = nullptr;   // z = M^-1 r written by the captured cycle
     int mg_nb = 0;                 // blocks of its r.z partial sums
     hipGraph_t mg_graph = nullptr;
@@ -364,7 +366,70 @@ int solve_fused(otm_ctx* c, bool x_zero, bool mixed, const FusedBufs<T>& B, otm_
     return OTM_OK;
 }
 
+// Float64 CG preconditioned by the float32 V-cycle: r is rounded to float32
+// for the cycle and z widened back; the Krylov vectors, dots and convergence
+// test stay float64 (the true residual confirms convergence, as in the Jacobi
+// path).  CG restarts (beta = 0) after such a confirmation.
+int solve_mg64(otm_ctx* c, bool x_zero, otm_solve_stats* st) {
+    const Workspace w = c->ws();
+    const int n = c->n;
+    const int64_t n3 = 3 * c->nn;
+    int rc;
+    if ((rc = reset_solver_scalars(c))) return rc;
+    if (x_zero) HIPCHK(c, hipMemsetAsync(c->x, 0, (size_t)n3 * sizeof(double), c->stream));
+    launch_residual<double>(n, c->k, c->b, c->x, c->r64, c->p64[c->pbuf], c->dinv, RES_START, x_zero ? 1 : 0, w,
+                            c->stream);
+    if ((rc = check_launch(c, "residual"))) return rc;
+    if ((rc = sync_scalars(c))) return rc;
+    int launches = 0;
+    bool restart = true;
+    const int check = c->so.check_every < 2 ? c->so.check_every : 2;
+    while (!all_inactive(c->h_sc) && max_iters(c->h_sc) < c->so.max_iter) {
+        const bool all = all_active(c->h_sc);
+        bool sampled = false;
+        for (int it = 0; it < check; ++it) {
+            launch_cast_f64_f32(n3, c->r64, c->r32, c->stream);
+            HIPCHK(c, hipGraphLaunch(c->mg_exec, c->stream));
+            launch_finalize(restart ? FIN_MG_RZ0 : FIN_MG_RZ, c->mg_nb, w, c->stream);
+            restart = false;
+            launch_cast_f32_f64(n3, c->mg_z, c->z64, c->stream);
+            double* po = c->p64[c->pbuf];
+            double* pn = c->p64[c->pbuf ^ 1];
+            const bool sample = all && it == check - 1;
+            launch_dir_march2<double>(n, c->tile2, all, c->z64, c->ones64, po, pn, c->k, c->q64, w, c->stream, true,
+                                      sample ? c->pev[0] : nullptr, sample ? c->pev[1] : nullptr);
+            sampled = sampled || sample;
+            launch_update_vec<double>(n, c->x, c->r64, pn, c->q64, c->ones64, w, c->stream, true, FIN_MG_UPDATE);
+            c->pbuf ^= 1;
+            ++launches;
+        }
+        if ((rc = check_launch(c, "mg-pcg64"))) return rc;
+        if ((rc = sync_scalars(c))) return rc;
+        collect_pass_sample(c, sampled, (double)c->nn * (4.0 * 3 + 1 + 1) * sizeof(double), 0);
+        if (all_inactive(c->h_sc)) {
+            // confirm with the true residual; loads that fail restart
+            launch_residual<double>(n, c->k, c->b, c->x, c->r64, c->p64[c->pbuf], c->dinv, RES_START, 0, w,
+                                    c->stream);
+            if ((rc = sync_scalars(c))) return rc;
+            restart = true;
+        }
+    }
+    launch_sum3(n, c->x, 0, w, c->stream);
+    launch_sub_mean3(n, c->x, 0, w, c->stream);
+    if ((rc = check_launch(c, "project"))) return rc;
+    if ((rc = sync_scalars(c))) return rc;
+    for (int l = 0; l < 3; ++l) {
+        st->iterations[l] = c->h_sc->iters[l];
+        st->rel_residual[l] = c->h_sc->bb[l] > 0.0 ? std::sqrt(c->h_sc->rr_true[l] / c->h_sc->bb[l]) : 0.0;
+    }
+    st->converged = all_inactive(c->h_sc) ? 1 : 0;
+    st->refreshes = 0;
+    c->timings[7] = (double)launches;
+    return OTM_OK;
+}
+
 int solve_fp64(otm_ctx* c, bool x_zero, otm_solve_stats* st) {
+    if (c->use_mg) return solve_mg64(c, x_zero, st);
     if (c->use_fused) {
         const FusedBufs<double> B{{c->r64, c->r64b}, {c->q64, c->q64b}, {c->p64[0], c->p64[1]}, c->x, c->dinv, c->k};
         return solve_fused<double>(c, x_zero, false, B, st);
@@ -782,9 +847,15 @@ int mg_build(otm_ctx* c) {
         a.tile = choose_tile2(a.n, c->max_blocks, 0, 0);
     }
     rc = rc ? rc : mg_alloc(c, &H.minv, (int64_t)kMgCoarseMax * kMgCoarseMax);
-    rc = rc ? rc : mg_alloc(c, &c->ones32, c->nn);
+    if (c->so.precision == OTM_MIXED) {
+        rc = rc ? rc : mg_alloc(c, &c->ones32, c->nn);
+    } else {
+        rc = rc ? rc : mg_alloc(c, &c->ones64, c->nn);
+        rc = rc ? rc : mg_alloc(c, &c->z64, 3 * c->nn);
+    }
     if (rc) return rc;
-    launch_fill_const<float>(c->ones32, c->nn, 1.0f, c->stream);
+    if (c->ones32) launch_fill_const<float>(c->ones32, c->nn, 1.0f, c->stream);
+    if (c->ones64) launch_fill_const<double>(c->ones64, c->nn, 1.0, c->stream);
     HIPCHK(c, hipStreamSynchronize(c->stream));
     // capture on a private stream (the context's may be the legacy default stream)
     hipStream_t cs = nullptr;
@@ -1064,7 +1135,7 @@ int otm_create(const otm_problem* problem, const otm_solver_opts* solver, const 
     }
     if (c->so.preconditioner == OTM_PRECOND_MG) {
         int ns[kMgMaxLevels];
-        if (c->so.precision != OTM_MIXED || c->so.kernel_variant != 0 || c->so.mg_sweeps < 1 ||
+        if (c->so.kernel_variant != 0 || c->so.mg_sweeps < 1 ||
             c->so.mg_sweeps > 8 || c->so.mg_coarse_sweeps < 0 || c->so.mg_coarse_sweeps > 8 || (c->so.tile_tx != 0 && c->so.tile_tx != 32 && c->so.tile_tx != 64) ||
             !mg_levels(problem->n, ns)) {
             delete c;
@@ -1124,6 +1195,11 @@ int otm_create(const otm_problem* problem, const otm_solver_opts* solver, const 
     rc = rc ? rc : dalloc(c, &c->sens, nn);
     rc = rc ? rc : dalloc(c, &c->ocq, nn);
     if (c->so.precision == OTM_FP64) {
+        if (c->use_mg) {  // the V-cycle runs in float32: its level-0 inputs
+            rc = rc ? rc : dalloc(c, &c->k32, nn);
+            rc = rc ? rc : dalloc(c, &c->dinv32, nn);
+            rc = rc ? rc : dalloc(c, &c->r32, 3 * nn);
+        }
         rc = rc ? rc : dalloc(c, &c->r64, 3 * nn);
         rc = rc ? rc : dalloc(c, &c->p64[0], 3 * nn);
         rc = rc ? rc : dalloc(c, &c->p64[1], 3 * nn);

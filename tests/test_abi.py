@@ -83,11 +83,11 @@ def test_batch_create_rejects_odd_or_bad_sizes(L):
     assert L.otm_batch_last_error(None) == b"null batch"
 
 
-@pytest.mark.parametrize("n,precision,variant,sweeps", [(10, 1, 0, 2), (4, 1, 0, 2), (7, 1, 0, 2), (16, 0, 0, 2),
-                                                        (16, 1, 4, 2), (16, 1, 0, 0), (16, 1, 0, 9)])
+@pytest.mark.parametrize("n,precision,variant,sweeps", [(10, 1, 0, 2), (4, 1, 0, 2), (7, 1, 0, 2), (10, 0, 0, 2),
+                                                        (16, 1, 4, 2), (16, 0, 1, 2), (16, 1, 0, 0), (16, 1, 0, 9)])
 def test_multigrid_options_rejected(L, n, precision, variant, sweeps):
-    """The V-cycle needs n = m 2^j (m in {3, 4}, n >= 6), float32 Krylov vectors,
-    the two-pass iteration and 1..8 relaxation steps."""
+    """The V-cycle needs n = m 2^j (m in {3, 4}, n >= 6), the two-pass
+    iteration and 1..8 relaxation steps (either precision)."""
     from paper_2405_19991_amd import _native as N
     p = N.Problem()
     p.n, p.k0, p.kmin, p.penal, p.filter_radius, p.vf = n, 1.0, 1e-3, 3.0, 1.5, 0.3
