@@ -339,6 +339,30 @@ def warm_start_leg(weights, log):
     return ev
 
 
+def apply_sizes(reps: int):
+    """Stand-alone operator (3 loads, two-node z-march) on random conductivities
+    at 128^3 and 256^3 in float32 and float64: microseconds per launch and
+    algorithmic GB/s (28 or 56 B per node) for the best of four tile shapes."""
+    import torch
+    from paper_2405_19991_amd import time_apply_device
+    out = []
+    for n in (128, 256):
+        nn = n ** 3
+        for prec, dt, bpn in (("mixed", torch.float32, 28), ("fp64", torch.float64, 56)):
+            k = (torch.rand(nn, dtype=torch.float64, device="cuda") * 0.999 + 0.001).to(dt)
+            x = torch.randn(3 * nn, dtype=dt, device="cuda")
+            y = torch.empty_like(x)
+            best = min((time_apply_device(k, x, y, prec, reps=reps, variant=0, tile_tx=64, tile_tz=tz), tz)
+                       for tz in (8, 16, 32))
+            ach = bpn * nn / (best[0] * 1e-6) / 1e9
+            out.append({"n": n, "dtype": "f32" if prec == "mixed" else "f64", "tile": [64, best[1]],
+                        "us_per_launch": best[0], "alg_bytes_per_launch": bpn * nn, "achieved": ach,
+                        "frac": ach / HBM_PEAK_GBS})
+            del k, x, y
+    torch.cuda.empty_cache()
+    return out
+
+
 def apply_only(args):
     """Operator and copy launches for counter runs (rocprofv3 --pmc)."""
     import torch
@@ -470,6 +494,9 @@ def main():
                 "rotating_sets": {"sets": 5, "us_per_launch": us_rot,
                                   "achieved": alg_bytes / (us_rot * 1e-6) / 1e9,
                                   "frac": alg_bytes / (us_rot * 1e-6) / 1e9 / HBM_PEAK_GBS}}
+    # the operator in the other precision and at 256^3 (whose buffers exceed
+    # the Infinity Cache): best of a few z-march shapes each
+    operator["sizes"] = apply_sizes(args.apply_reps)
     # dominant kernel of the timed design iterations, timed live (HIP events
     # around one sampled launch per check interval, on the solver's stream)
     if live["launches"] > 0:
@@ -525,6 +552,8 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     log(f"apply kernel {us:.2f} us ({achieved:.0f} GB/s algorithmic); rotating 5 sets {us_rot:.2f} us")
+    for a in operator["sizes"]:
+        log(f"apply {a['n']}^3 {a['dtype']}: {a['us_per_launch']:.2f} us, {a['frac']:.3f} of peak")
     if not args.no_mg and args.preconditioner == "jacobi" and args.precision == "mixed" and n == 128:
         mg = multigrid_leg(w, args.steps, log, args.mg_sweeps, args.mg_coarse_sweeps)
         mg["kappa_rel_err_vs_oracle"] = oracle_tensor_error(w, mg.pop("first_kappa"), args.tol)

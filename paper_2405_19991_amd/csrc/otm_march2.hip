@@ -18,6 +18,14 @@
 
 namespace otm {
 
+// Streaming store (nontemporal hint): the stand-alone operator's result is
+// not re-read by this launch, so it should not displace the inputs in cache.
+template <typename V>
+__device__ __forceinline__ void st_stream(void* base, uint32_t boff, V v) {
+    asm volatile("" : "+v"(boff));
+    __builtin_nontemporal_store(v, reinterpret_cast<V*>(reinterpret_cast<char*>(base) + boff));
+}
+
 template <typename T>
 struct V2 {
     typedef T type __attribute__((ext_vector_type(2)));
@@ -297,7 +305,10 @@ __device__ __forceinline__ void march2_body(int bid_, int slot_, int n, int tz, 
 #pragma unroll
             for (int l = 0; l < 3; ++l) {
                 if (!act[l]) continue;
-                st_at<T2>(q + l * nn + zdone, bo, qd[l]);
+                if (DIR)
+                    st_at<T2>(q + l * nn + zdone, bo, qd[l]);
+                else
+                    st_stream<T2>(q + l * nn + zdone, bo, qd[l]);
                 if (DIR) acc[l] += (double)pB[l].x * (double)qd[l].x + (double)pB[l].y * (double)qd[l].y;
             }
         }
