@@ -167,8 +167,9 @@ def batch_leg(steps: int, log):
         log(f"batch step: max pcg {max(max(r['pcg_iters']) for r in recs)}, mean g {sum(r['g'] for r in recs) / len(recs):.3e}")
     t1 = _t.perf_counter()
     info = B.info()
+    dev_bytes = B.device_bytes()
     B.close()
-    return {"workload": "batch64_n32-64_fp64", "designs": len(ws), "cells": int(info["cells"]),
+    return {"workload": "batch64_n32-64_fp64", "designs": len(ws), "cells": int(info["cells"]), "device_bytes": dev_bytes,
             "s_per_oc_iter": (t1 - t0) / steps, "pcg_dof_updates_per_s": iters / (t1 - t0),
             "tile_tx": int(info["tile_tx"]), "tile_tz": int(info["tile_tz"]), "work_items": int(info["work_items"]),
             "steps": steps}
@@ -190,8 +191,9 @@ def multigrid_leg(w, steps: int, log, sweeps: int = 1, coarse_sweeps: int = 2):
         recs = [h.step() for _ in range(steps)]
         torch.cuda.synchronize()
         dt = time.perf_counter() - t0
+        dev_bytes = h.device_bytes()
     iters = sum(sum(r["pcg_iters"]) for r in recs)
-    out = {"workload": w.name + "_mixed_mg", "n": w.n, "tol": w.tol, "mg_sweeps": [sweeps, coarse_sweeps], "s_per_oc_iter": dt / steps,
+    out = {"device_bytes": dev_bytes, "workload": w.name + "_mixed_mg", "n": w.n, "tol": w.tol, "mg_sweeps": [sweeps, coarse_sweeps], "s_per_oc_iter": dt / steps,
            "pcg_iters_per_step": iters / steps, "ms_solve_per_step": sum(r["ms_solve"] for r in recs) / steps,
            "pcg_dof_updates_per_s": w.n ** 3 * iters / dt, "first_kappa": first["kappa"],
            "first_pcg_iters": first["pcg_iters"], "steps": steps}
@@ -223,8 +225,9 @@ def fp64_leg(steps: int, log):
             torch.cuda.synchronize()
             dt = time.perf_counter() - t0
             tile = h.tile()
+            dev_bytes = h.device_bytes()
         iters = sum(sum(r["pcg_iters"]) for r in recs)
-        res[pc] = {"pcg_dof_updates_per_s": w.n ** 3 * iters / dt, "s_per_oc_iter": dt / steps,
+        res[pc] = {"device_bytes": dev_bytes, "pcg_dof_updates_per_s": w.n ** 3 * iters / dt, "s_per_oc_iter": dt / steps,
                    "pcg_iters_per_step": iters / steps, "solver_tile": tile}
         log(f"fp64 {pc}: {res[pc]['pcg_dof_updates_per_s']:.3e} DOF-updates/s, "
             f"{1e3 * res[pc]['s_per_oc_iter']:.2f} ms per design iteration")
@@ -451,6 +454,7 @@ def main():
     x = torch.randn(3 * nn, dtype=dt, device="cuda")
     y = torch.empty_like(x)
     tile = h.tile()
+    dev_bytes = h.device_bytes()
     # the operator in the configuration the solver was tuned to, and the best
     # z-march shape for the stand-alone operator
     # (the fused iteration's operator is the two-node z-march)
@@ -537,6 +541,7 @@ def main():
         "pcg_iters_per_step": pcg_iters / args.steps,
         "pcg_only_dof_per_s": dof / (solve_ms * 1e-3) if solve_ms > 0 else None,
         "solver_tile": tile,
+        "device_bytes": dev_bytes,
         "kappa_rel_err_vs_oracle": oracle_tensor_error(w, first_kappa, args.tol),
         "last_g": recs[-1]["g"],
         "last_kappa": recs[-1]["kappa"],

@@ -334,6 +334,12 @@ int otm_pass_timing(otm_ctx* ctx, int32_t reset, double out4[4]);
  * iterations launched in the last solve]. */
 int otm_get_timings(const otm_ctx* ctx, double t8[8]);
 
+/* Device memory the context holds (every buffer it allocated, the multigrid
+ * levels included; not the caller's tensors or a network), in bytes.  It is
+ * fixed at creation (otm_apply's temporaries, freed before it returns, are
+ * not counted). */
+int otm_device_bytes(const otm_ctx* ctx, int64_t* bytes);
+
 /* ---- batches of designs (uneven n) -----------------------------------------
  * Many independent cells in one set of device arenas; every phase of a design
  * iteration is one launch over all designs (per-design scalars and
@@ -359,6 +365,8 @@ int otm_batch_set_graph(otm_batch* batch, int32_t use_graph);
 /* [designs, total cells, operator work items, tile width, march length of
  *  design 0, tuned operator-pass us, last solve ms, last step ms] */
 int otm_batch_info(const otm_batch* batch, double info8[8]);
+/* Device memory the batch holds (its arenas, tables and graph buffers), bytes. */
+int otm_batch_device_bytes(const otm_batch* batch, int64_t* bytes);
 const char* otm_batch_last_error(const otm_batch* batch);
 
 /* ---- learned warm start ------------------------------------------------------

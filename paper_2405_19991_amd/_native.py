@@ -53,7 +53,8 @@ EXPORTED = [
     "otm_batch_set_graph", "otm_batch_info", "otm_batch_last_error",
     "otm_nn_create", "otm_nn_destroy", "otm_nn_param_count", "otm_nn_get_params", "otm_nn_set_params",
     "otm_nn_get_grads", "otm_nn_forward", "otm_nn_accumulate", "otm_nn_adam", "otm_nn_zero_grads",
-    "otm_nn_last_error", "otm_set_network", "otm_init_density", "otm_apply_device_tiled",
+    "otm_nn_last_error", "otm_set_network", "otm_init_density", "otm_apply_device_tiled", "otm_device_bytes",
+    "otm_batch_device_bytes",
 ]
 
 
@@ -146,6 +147,8 @@ def lib():
         "otm_apply_device_tiled": ([i32, i32, i32, i32, i32, vp, vp, vp, vp], ctypes.c_int),
         "otm_time_apply_device": ([i32, i32, i32, i32, i32, vp, vp, vp, vp, i32, dp], ctypes.c_int),
         "otm_get_timings": ([ctx, dp], ctypes.c_int),
+        "otm_device_bytes": ([ctx, P(ctypes.c_int64)], ctypes.c_int),
+        "otm_batch_device_bytes": ([vp, P(ctypes.c_int64)], ctypes.c_int),
         "otm_get_tile": ([ctx, P(i32)], ctypes.c_int),
         "otm_pass_timing": ([ctx, i32, dp], ctypes.c_int),
         "otm_strerror": ([ctypes.c_int], ctypes.c_char_p),

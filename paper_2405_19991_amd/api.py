@@ -205,6 +205,12 @@ class Homogenization:
         self._chk(self._L.otm_get_timings(self._h, _ptr(t)))
         return t.tolist()
 
+    def device_bytes(self) -> int:
+        """Device memory the context holds, bytes."""
+        b = ctypes.c_int64()
+        self._chk(self._L.otm_device_bytes(self._h, ctypes.byref(b)))
+        return int(b.value)
+
     # -- governor state, checkpoint / resume
     def governor_state(self) -> List[float]:
         s = np.zeros(8)
@@ -379,6 +385,12 @@ class Batch:
         self._chk(self._L.otm_batch_info(self._h, _ptr(a)))
         keys = ["designs", "cells", "work_items", "tile_tx", "tile_tz", "tuned_pass_us", "solve_ms", "step_ms"]
         return dict(zip(keys, a.tolist()))
+
+    def device_bytes(self) -> int:
+        """Device memory the batch holds, bytes."""
+        b = ctypes.c_int64()
+        self._chk(self._L.otm_batch_device_bytes(self._h, ctypes.byref(b)))
+        return int(b.value)
 
 
 class Network:

@@ -37,6 +37,7 @@ struct Gov {
 
 struct otm_batch {
     int count = 0;
+    int64_t dev_bytes = 0;  // device memory this batch holds
     std::vector<otm_problem> prob;
     otm_solver_opts so;
     otm_oc_opts oc;
@@ -107,6 +108,7 @@ int balloc(otm_batch* c, T** p, int64_t n) {
         (void)hipGetLastError();
         return bfail(c, OTM_ENOMEM, "device allocation failed");
     }
+    c->dev_bytes += n * (int64_t)sizeof(T);
     return OTM_OK;
 }
 
@@ -605,6 +607,12 @@ int otm_batch_step(otm_batch* c, otm_iter_record* recs) {
     c->t_ms[3] = std::chrono::duration<double, std::milli>(t3 - t0).count();
     c->iter += 1;
     return conv ? OTM_OK : OTM_NOT_CONVERGED;
+}
+
+int otm_batch_device_bytes(const otm_batch* c, int64_t* bytes) {
+    if (!c || !bytes) return OTM_EINVAL;
+    *bytes = c->dev_bytes;
+    return OTM_OK;
 }
 
 int otm_batch_info(const otm_batch* c, double info8[8]) {

@@ -36,6 +36,7 @@ struct otm_ctx {
     int device = 0;
     int n = 0;
     int64_t nn = 0;
+    int64_t dev_bytes = 0;  // device memory this context holds
 
     // fields (float64)
     double* rho = nullptr;
@@ -150,6 +151,7 @@ int dalloc(otm_ctx* c, T** p, int64_t count) {
         (void)hipGetLastError();
         return fail(c, OTM_ENOMEM, "device allocation of " + std::to_string((long long)count * sizeof(T)) + " bytes failed");
     }
+    c->dev_bytes += count * (int64_t)sizeof(T);
     return OTM_OK;
 }
 
@@ -1482,6 +1484,12 @@ int otm_set_governor(otm_ctx* c, const double s[8]) {
 int otm_apply(otm_ctx* c, int32_t precision, const double* xh, double* yh) {
     if (!c || !xh || !yh) return OTM_EINVAL;
     if (!c->prepared) return fail(c, OTM_ESTATE, "apply needs prepared conductivities");
+    // temporaries, freed before return: not part of what the context holds
+    struct HeldBytes {
+        otm_ctx* c;
+        int64_t v;
+        ~HeldBytes() { c->dev_bytes = v; }
+    } held{c, c->dev_bytes};
     const int64_t cnt = 3 * c->nn;
     int rc = OTM_OK;
     if (precision == OTM_FP64) {
@@ -1649,6 +1657,12 @@ int otm_get_tile(const otm_ctx* c, int32_t tile4[4]) {
 int otm_get_timings(const otm_ctx* c, double t8[8]) {
     if (!c || !t8) return OTM_EINVAL;
     std::memcpy(t8, c->timings, sizeof(c->timings));
+    return OTM_OK;
+}
+
+int otm_device_bytes(const otm_ctx* c, int64_t* bytes) {
+    if (!c || !bytes) return OTM_EINVAL;
+    *bytes = c->dev_bytes;
     return OTM_OK;
 }
 
