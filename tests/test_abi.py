@@ -69,6 +69,10 @@ def test_null_arguments(L):
     assert L.otm_create(None, None, None, None, None, None) == N.OTM_EINVAL
     assert L.otm_apply_device(2, 0, 0, None, None, None, None) == N.OTM_EINVAL
     assert L.otm_last_error(None) == b"null context"
+    b = ctypes.c_int64(-1)
+    assert L.otm_device_bytes(None, ctypes.byref(b)) == N.OTM_EINVAL
+    assert L.otm_batch_device_bytes(None, ctypes.byref(b)) == N.OTM_EINVAL
+    assert b.value == -1
 
 
 def test_batch_create_rejects_odd_or_bad_sizes(L):
