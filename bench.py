@@ -62,6 +62,8 @@ def parse():
     ap.add_argument("--no-mg", action="store_true", help="skip the multigrid leg")
     ap.add_argument("--mg-sweeps", type=int, default=1, help="relaxation steps per leg of the V-cycle, finest level")
     ap.add_argument("--mg-coarse-sweeps", type=int, default=2, help="the same on coarser levels (0: as --mg-sweeps)")
+    ap.add_argument("--check-every", type=int, default=16,
+                    help="PCG iterations between host convergence checks (at most 2 with multigrid)")
     ap.add_argument("--reliable-delta", type=float, default=None,
                     help="mixed precision: refresh the float64 residual after this relative drop "
                          "(default 1e-2, or 1e-3 with the multigrid preconditioner)")
@@ -418,7 +420,7 @@ def main():
                        precision=args.precision, guess=args.guess, tol=w.tol, kernel_variant=args.variant,
                        tile_tx=args.solver_tx, tile_tz=args.solver_tz, preconditioner=args.preconditioner,
                        mg_sweeps=args.mg_sweeps, mg_coarse_sweeps=args.mg_coarse_sweeps,
-                       reliable_delta=args.reliable_delta)
+                       reliable_delta=args.reliable_delta, check_every=args.check_every)
     h.set_density(w.rho0)
     def log(msg):
         print(msg, file=sys.stderr, flush=True)
