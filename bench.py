@@ -398,8 +398,8 @@ def main():
         apply_only(args)
         return
     if args.gpus != 1:
-        print(json.dumps({"error": "this build runs on one GPU only; --gpus must be 1 "
-                                   "(multi-GPU sharding is described in DESIGN.md, not implemented)"}))
+        print(json.dumps({"error": "this benchmark runs on one GPU only; --gpus must be 1 "
+                                   "(sharding over several GPUs is not implemented)"}))
         sys.exit(2)
     import numpy as np
     import torch
