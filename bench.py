@@ -500,9 +500,6 @@ def main():
                 "rotating_sets": {"sets": 5, "us_per_launch": us_rot,
                                   "achieved": alg_bytes / (us_rot * 1e-6) / 1e9,
                                   "frac": alg_bytes / (us_rot * 1e-6) / 1e9 / HBM_PEAK_GBS}}
-    # the operator in the other precision and at 256^3 (whose buffers exceed
-    # the Infinity Cache): best of a few z-march shapes each
-    operator["sizes"] = apply_sizes(args.apply_reps)
     # dominant kernel of the timed design iterations, timed live (HIP events
     # around one sampled launch per check interval, on the solver's stream)
     if live["launches"] > 0:
@@ -559,8 +556,6 @@ def main():
         torch.cuda.synchronize()
         del src, dst
     log(f"apply kernel {us:.2f} us ({achieved:.0f} GB/s algorithmic); rotating 5 sets {us_rot:.2f} us")
-    for a in operator["sizes"]:
-        log(f"apply {a['n']}^3 {a['dtype']}: {a['us_per_launch']:.2f} us, {a['frac']:.3f} of peak")
     if not args.no_mg and args.preconditioner == "jacobi" and args.precision == "mixed" and n == 128:
         mg = multigrid_leg(w, args.steps, log, args.mg_sweeps, args.mg_coarse_sweeps)
         mg["kappa_rel_err_vs_oracle"] = oracle_tensor_error(w, mg.pop("first_kappa"), args.tol)
@@ -577,6 +572,12 @@ def main():
         out["gallery"] = gallery_leg(args.gallery_iters, log)
     if not args.no_warm_start and n == 128:
         out["warm_start"] = warm_start_leg(args.weights, log)
+    # the operator in the other precision and at 256^3 (whose buffers exceed
+    # the Infinity Cache), best of a few z-march shapes each; last, because
+    # seconds of streaming at full bandwidth slow the GPU work right after it
+    operator["sizes"] = apply_sizes(args.apply_reps)
+    for a in operator["sizes"]:
+        log(f"apply {a['n']}^3 {a['dtype']}: {a['us_per_launch']:.2f} us, {a['frac']:.3f} of peak")
     if not args.no_cpu_baseline:
         log("cpu baseline (oracle) ...")
         out["cpu_baseline"] = cpu_baseline(w, args.oracle_cg_iters)
