@@ -1,7 +1,8 @@
 """Objective variants (Sec. 4.4: squared error, relative squared error, l1)
 and the central-symmetry constraint (Sec. 4.3) on the GPU against the oracle:
-three design iterations from the same start, FP64 solves to 1e-10, on a
-16^3 cell with the target of the paper's objective comparison."""
+three design iterations from the same start, FP64 solves to 1e-10 (Jacobi
+or multigrid preconditioner), on a 16^3 cell with the target of the paper's
+objective comparison."""
 import numpy as np
 import pytest
 
@@ -25,10 +26,11 @@ def gpu():
     yield
 
 
+@pytest.mark.parametrize("preconditioner", ["jacobi", "mg"])
 @pytest.mark.parametrize("objective", ["mse", "rel", "l1"])
 @pytest.mark.parametrize("symmetry", ["none", "central"])
-def test_design_iterations_track_oracle(objective, symmetry):
-    print(f"objective={objective} symmetry={symmetry}", flush=True)
+def test_design_iterations_track_oracle(objective, symmetry, preconditioner):
+    print(f"objective={objective} symmetry={symmetry} preconditioner={preconditioner}", flush=True)
     n, vf = 16, 0.35
     rho0 = synth.smoothed_noise(n, 0.2, 0.5, 5150)
     prm = O.Params(tol=1e-10)
@@ -36,7 +38,7 @@ def test_design_iterations_track_oracle(objective, symmetry):
     rho_ref = rho0.copy()
     from paper_2405_19991_amd import Homogenization
     with Homogenization(n, (1.0, 1e-3), TGT6, vf=vf, tol=1e-10, guess="previous", objective=objective,
-                        symmetry=symmetry) as h:
+                        symmetry=symmetry, precision="fp64", preconditioner=preconditioner) as h:
         h.set_density(rho0)
         for it in range(3):
             rec = h.step()
