@@ -390,7 +390,8 @@ int solve_mg64(otm_ctx* c, bool x_zero, otm_solve_stats* st) {
         const bool all = all_active(c->h_sc);
         bool sampled = false;
         for (int it = 0; it < check; ++it) {
-            launch_cast_f64_f32(n3, c->r64, c->r32, c->stream);
+            // the update writes the float32 copy of r; after a residual kernel it is cast here
+            if (restart) launch_cast_f64_f32(n3, c->r64, c->r32, c->stream);
             HIPCHK(c, hipGraphLaunch(c->mg_exec, c->stream));
             launch_finalize(restart ? FIN_MG_RZ0 : FIN_MG_RZ, c->mg_nb, w, c->stream);
             restart = false;
@@ -401,7 +402,8 @@ int solve_mg64(otm_ctx* c, bool x_zero, otm_solve_stats* st) {
             launch_dir_march2<double>(n, c->tile2, all, c->z64, c->ones64, po, pn, c->k, c->q64, w, c->stream, true,
                                       sample ? c->pev[0] : nullptr, sample ? c->pev[1] : nullptr);
             sampled = sampled || sample;
-            launch_update_vec<double>(n, c->x, c->r64, pn, c->q64, c->ones64, w, c->stream, true, FIN_MG_UPDATE);
+            launch_update_vec<double>(n, c->x, c->r64, pn, c->q64, c->ones64, w, c->stream, true, FIN_MG_UPDATE,
+                                      c->r32);
             c->pbuf ^= 1;
             ++launches;
         }

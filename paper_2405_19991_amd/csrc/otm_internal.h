@@ -282,7 +282,7 @@ template <typename T>
 void launch_apply_tiled(int n, const TileShape& t, const T* k, const T* x, T* y, hipStream_t s);
 template <typename T>
 void launch_update_vec(int n, T* x, T* r, const T* p, const T* q, const T* dinv, const Workspace& ws, hipStream_t s,
-                       bool fin = true, int fin_op = FIN_UPDATE);
+                       bool fin = true, int fin_op = FIN_UPDATE, float* r32 = nullptr);
 
 // Batched launches (one launch covers every design).
 void launch_b_clamp(const BatchTab& t, double* rho, double lo, double hi, hipStream_t s);

@@ -14,6 +14,8 @@
 //
 // k_update_vec: x += alpha p, r -= alpha q and the dots r.D^-1 r, r.r, with
 // 16-byte vector accesses (float4 / double2).
+#include <type_traits>
+
 #include "otm_device.h"
 
 namespace otm {
@@ -380,11 +382,15 @@ __global__ void __launch_bounds__(TX* TY) k_march(int n, int tz, int ntx, int nt
     block_partials<3>(acc, partials);
 }
 
+// r32 (optional): a float32 copy of the updated r of the active loads, the
+// input of a float32 preconditioner.
 template <typename T, int V>
 __device__ __forceinline__ void update_vec_body(int bid_, int nblk_, int slot_, int64_t nn, T* __restrict__ x,
                                                 T* __restrict__ r, const T* __restrict__ p, const T* __restrict__ q,
-                                                const T* __restrict__ dinv, double* partials, const Scalars* sc) {
+                                                const T* __restrict__ dinv, double* partials, const Scalars* sc,
+                                                float* __restrict__ r32 = nullptr) {
     typedef T VT __attribute__((ext_vector_type(V)));
+    typedef float VF __attribute__((ext_vector_type(V)));
     const int64_t nv = nn / V;
     const int act[3] = {sc->active[0], sc->active[1], sc->active[2]};
     const T alpha[3] = {(T)sc->alpha[0], (T)sc->alpha[1], (T)sc->alpha[2]};
@@ -405,6 +411,12 @@ __device__ __forceinline__ void update_vec_body(int bid_, int nblk_, int slot_, 
             rr -= alpha[l] * qv;
             xv[t] = xx;
             rv[t] = rr;
+            if (r32) {
+                VF f;
+#pragma unroll
+                for (int c = 0; c < V; ++c) f[c] = (float)rr[c];
+                reinterpret_cast<VF*>(r32 + l * nn)[t] = f;
+            }
 #pragma unroll
             for (int c = 0; c < V; ++c) {
                 const double rd = (double)rr[c];
@@ -420,8 +432,8 @@ template <typename T, int V>
 __global__ void __launch_bounds__(kBlock) k_update_vec(int64_t nn, T* __restrict__ x, T* __restrict__ r,
                                                        const T* __restrict__ p, const T* __restrict__ q,
                                                        const T* __restrict__ dinv, double* partials,
-                                                       unsigned* counter, Scalars* sc) {
-    update_vec_body<T, V>(blockIdx.x, gridDim.x, blockIdx.x, nn, x, r, p, q, dinv, partials, sc);
+                                                       unsigned* counter, Scalars* sc, float* __restrict__ r32) {
+    update_vec_body<T, V>(blockIdx.x, gridDim.x, blockIdx.x, nn, x, r, p, q, dinv, partials, sc, r32);
 }
 
 // ---------------------------------------------------------------- launchers
@@ -521,16 +533,19 @@ void launch_apply_tiled(int n, const TileShape& t, const T* k, const T* x, T* y,
 
 template <typename T>
 void launch_update_vec(int n, T* x, T* r, const T* p, const T* q, const T* dinv, const Workspace& ws, hipStream_t s,
-                       bool fin, int fin_op) {
+                       bool fin, int fin_op, float* r32) {
     constexpr int V = 16 / sizeof(T);
     const int64_t nn = cube(n);
     if (nn % V != 0) {
         launch_update<T>(n, x, r, p, q, dinv, ws, s);
+        if constexpr (std::is_same<T, double>::value) {
+            if (r32) launch_cast_f64_f32(3 * nn, r, r32, s);
+        }
         return;
     }
     const int g = grid_for(nn / V, ws.max_blocks);
     hipLaunchKernelGGL((k_update_vec<T, V>), dim3(g), dim3(kBlock), 0, s, nn, x, r, p, q, dinv, ws.partials,
-                       ws.counter, ws.sc);
+                       ws.counter, ws.sc, r32);
     if (fin) launch_finalize(fin_op, g, ws, s);
 }
 
@@ -547,9 +562,9 @@ template void launch_apply_march<float>(int, const TileShape&, const float*, con
 template void launch_apply_tiled<double>(int, const TileShape&, const double*, const double*, double*, hipStream_t);
 template void launch_apply_tiled<float>(int, const TileShape&, const float*, const float*, float*, hipStream_t);
 template void launch_update_vec<double>(int, double*, double*, const double*, const double*, const double*,
-                                        const Workspace&, hipStream_t, bool, int);
+                                        const Workspace&, hipStream_t, bool, int, float*);
 template void launch_update_vec<float>(int, float*, float*, const float*, const float*, const float*,
-                                       const Workspace&, hipStream_t, bool, int);
+                                       const Workspace&, hipStream_t, bool, int, float*);
 
 }  // namespace otm
 
