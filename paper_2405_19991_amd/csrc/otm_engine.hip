@@ -85,7 +85,6 @@ struct otm_ctx {
     std::vector<void*> mg_bufs;
     float* ones32 = nullptr;       // D^-1 := 1 for the direction pass and the update (mixed)
     double* ones64 = nullptr;      // the same for float64 contexts
-    double* z64 = nullptr;         // float64 copy of the cycle's output (float64 contexts)
     const float* mg_z = nullptr;   // z = M^-1 r written by the captured cycle
     int mg_nb = 0;                 // blocks of its r.z partial sums
     hipGraph_t mg_graph = nullptr;
@@ -369,7 +368,7 @@ int solve_fused(otm_ctx* c, bool x_zero, bool mixed, const FusedBufs<T>& B, otm_
 }
 
 // Float64 CG preconditioned by the float32 V-cycle: r is rounded to float32
-// for the cycle and z widened back; the Krylov vectors, dots and convergence
+// for the cycle and z widened as the direction pass reads it; the Krylov vectors, dots and convergence
 // test stay float64 (the true residual confirms convergence, as in the Jacobi
 // path).  CG restarts (beta = 0) after such a confirmation.
 int solve_mg64(otm_ctx* c, bool x_zero, otm_solve_stats* st) {
@@ -395,12 +394,12 @@ int solve_mg64(otm_ctx* c, bool x_zero, otm_solve_stats* st) {
             HIPCHK(c, hipGraphLaunch(c->mg_exec, c->stream));
             launch_finalize(restart ? FIN_MG_RZ0 : FIN_MG_RZ, c->mg_nb, w, c->stream);
             restart = false;
-            launch_cast_f32_f64(n3, c->mg_z, c->z64, c->stream);
             double* po = c->p64[c->pbuf];
             double* pn = c->p64[c->pbuf ^ 1];
             const bool sample = all && it == check - 1;
-            launch_dir_march2<double>(n, c->tile2, all, c->z64, c->ones64, po, pn, c->k, c->q64, w, c->stream, true,
-                                      sample ? c->pev[0] : nullptr, sample ? c->pev[1] : nullptr);
+            // the direction pass reads the cycle's float32 output directly
+            launch_dir_march2_zf(n, c->tile2, all, c->mg_z, c->ones64, po, pn, c->k, c->q64, w, c->stream,
+                                 sample ? c->pev[0] : nullptr, sample ? c->pev[1] : nullptr);
             sampled = sampled || sample;
             launch_update_vec<double>(n, c->x, c->r64, pn, c->q64, c->ones64, w, c->stream, true, FIN_MG_UPDATE,
                                       c->r32);
@@ -409,7 +408,8 @@ int solve_mg64(otm_ctx* c, bool x_zero, otm_solve_stats* st) {
         }
         if ((rc = check_launch(c, "mg-pcg64"))) return rc;
         if ((rc = sync_scalars(c))) return rc;
-        collect_pass_sample(c, sampled, (double)c->nn * (4.0 * 3 + 1 + 1) * sizeof(double), 0);
+        // direction pass: z (float32) read, p read and written, q written, ones and k read
+        collect_pass_sample(c, sampled, (double)c->nn * (3.0 * sizeof(float) + 11.0 * sizeof(double)), 0);
         if (all_inactive(c->h_sc)) {
             // confirm with the true residual; loads that fail restart
             launch_residual<double>(n, c->k, c->b, c->x, c->r64, c->p64[c->pbuf], c->dinv, RES_START, 0, w,
@@ -855,7 +855,6 @@ int mg_build(otm_ctx* c) {
         rc = rc ? rc : mg_alloc(c, &c->ones32, c->nn);
     } else {
         rc = rc ? rc : mg_alloc(c, &c->ones64, c->nn);
-        rc = rc ? rc : mg_alloc(c, &c->z64, 3 * c->nn);
     }
     if (rc) return rc;
     if (c->ones32) launch_fill_const<float>(c->ones32, c->nn, 1.0f, c->stream);

@@ -280,6 +280,11 @@ void launch_residual_f(int n, const double* k, const double* b, const double* x,
                        bool start, int x_zero, const Workspace& ws, hipStream_t s);
 template <typename T>
 void launch_apply_tiled(int n, const TileShape& t, const T* k, const T* x, T* y, hipStream_t s);
+// launch_dir_march2<double> with a float32 z (the multigrid cycle's output);
+// finalize (FIN_PQ) included.
+void launch_dir_march2_zf(int n, const TileShape& t, bool all_active, const float* z, const double* dinv,
+                          const double* p_old, double* p_new, const double* k, double* q, const Workspace& ws,
+                          hipStream_t s, hipEvent_t ev0 = nullptr, hipEvent_t ev1 = nullptr);
 template <typename T>
 void launch_update_vec(int n, T* x, T* r, const T* p, const T* q, const T* dinv, const Workspace& ws, hipStream_t s,
                        bool fin = true, int fin_op = FIN_UPDATE, float* r32 = nullptr);

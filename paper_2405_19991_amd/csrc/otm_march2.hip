@@ -46,9 +46,11 @@ struct Pre2 {
 // f comes in through p_old and D^-1 through dinv, own nodes only) or
 // w D^-1 f (DIR true, r = f: the Jacobi step from zero), all loads active.
 // MG_RELAX with partials also sums f . x_new per load (r.z of the cycle).
-template <typename T, int WX, int TY, bool DIR, bool ALL, int MG = MG_NONE>
+// TR: element type of r (float with T = double: a float32 preconditioner's
+// output read directly by the float64 direction pass).
+template <typename T, int WX, int TY, bool DIR, bool ALL, int MG = MG_NONE, typename TR = T>
 __device__ __forceinline__ void march2_body(int bid_, int slot_, int n, int tz, int ntx, int nty,
-                                            const T* __restrict__ r, const T* __restrict__ dinv,
+                                            const TR* __restrict__ r, const T* __restrict__ dinv,
                                             const T* __restrict__ p_old, T* __restrict__ p_new,
                                             const T* __restrict__ k, T* __restrict__ q, double* __restrict__ partials,
                                             const Scalars* __restrict__ sc) {
@@ -137,6 +139,9 @@ __device__ __forceinline__ void march2_body(int bid_, int slot_, int n, int tz, 
 
     const uint32_t bo = xy_own * (uint32_t)sizeof(T);
     const uint32_t bh = xy_h * (uint32_t)sizeof(T);
+    const uint32_t bor = xy_own * (uint32_t)sizeof(TR);  // the same nodes in r
+    const uint32_t bhr = xy_h * (uint32_t)sizeof(TR);
+    typedef typename V2<TR>::type TR2;
     const uint32_t bkh = xy_kh * (uint32_t)sizeof(T);
 
     // own pair loads first, then every halo load under one branch (one exec
@@ -149,7 +154,7 @@ __device__ __forceinline__ void march2_body(int bid_, int slot_, int n, int tz, 
 #pragma unroll
         for (int l = 0; l < 3; ++l) {
             if (!act[l]) continue;
-            f.r[l] = ld_at<T2>(r + l * nn + zoff, bo);
+            f.r[l] = __builtin_convertvector(ld_at<TR2>(r + l * nn + zoff, bor), T2);
             if (DIR && MG == MG_NONE && beta[l] != (T)0) f.po[l] = ld_at<T2>(p_old + l * nn + zoff, bo);
             if (!DIR && MG != MG_NONE) f.po[l] = ld_at<T2>(p_old + l * nn + zoff, bo);  // own f
         }
@@ -159,7 +164,7 @@ __device__ __forceinline__ void march2_body(int bid_, int slot_, int n, int tz, 
 #pragma unroll
             for (int l = 0; l < 3; ++l) {
                 if (!act[l]) continue;
-                f.hr[l] = ld_at<T>(r + l * nn + zoff, bh);
+                f.hr[l] = (T)ld_at<TR>(r + l * nn + zoff, bhr);
                 if (DIR && beta[l] != (T)0) f.hpo[l] = ld_at<T>(p_old + l * nn + zoff, bh);
             }
         }
@@ -360,6 +365,18 @@ __global__ void __launch_bounds__(WX* TY) k_march2(int n, int tz, int ntx, int n
                                      p_new, k, q, partials, sc);
 }
 
+// Direction + operator pass of float64 CG whose preconditioned residual z is
+// float32 (the multigrid cycle's output): p = z + beta p, q = A p, p.q.
+template <int WX, int TY, bool ALL>
+__global__ void __launch_bounds__(WX* TY) k_march2_zf(int n, int tz, int ntx, int nty, const float* __restrict__ z,
+                                                      const double* __restrict__ dinv,
+                                                      const double* __restrict__ p_old, double* __restrict__ p_new,
+                                                      const double* __restrict__ k, double* __restrict__ q,
+                                                      double* __restrict__ partials, const Scalars* __restrict__ sc) {
+    march2_body<double, WX, TY, true, ALL, MG_NONE, float>(xcd_tile(blockIdx.x, gridDim.x), blockIdx.x, n, tz, ntx,
+                                                           nty, z, dinv, p_old, p_new, k, q, partials, sc);
+}
+
 // Stand-alone float32 operator (no direction, no dots): its register state
 // fits three waves per SIMD (float64 would spill there and keeps k_march2).
 template <int WX, int TY>
@@ -452,6 +469,29 @@ void launch_dir_march2(int n, const TileShape& t, bool all_active, const T* r, c
     else
         launch_m2<T, true, false>(n, t, r, dinv, p_old, p_new, k, q, ws.partials, ws.sc, s, ev0, ev1);
     if (fin) launch_finalize(FIN_PQ, t.blocks, ws, s);
+}
+
+void launch_dir_march2_zf(int n, const TileShape& t, bool all_active, const float* z, const double* dinv,
+                          const double* p_old, double* p_new, const double* k, double* q, const Workspace& ws,
+                          hipStream_t s, hipEvent_t ev0, hipEvent_t ev1) {
+    const int ntx = (n + t.tx - 1) / t.tx, nty = (n + t.ty - 1) / t.ty;
+    const dim3 g(t.blocks), b(kBlock);
+    if (t.tx == 32) {
+        if (all_active)
+            hipExtLaunchKernelGGL((k_march2_zf<16, 16, true>), g, b, 0, s, ev0, ev1, 0, n, t.tz, ntx, nty, z, dinv,
+                                  p_old, p_new, k, q, ws.partials, ws.sc);
+        else
+            hipExtLaunchKernelGGL((k_march2_zf<16, 16, false>), g, b, 0, s, ev0, ev1, 0, n, t.tz, ntx, nty, z, dinv,
+                                  p_old, p_new, k, q, ws.partials, ws.sc);
+    } else {
+        if (all_active)
+            hipExtLaunchKernelGGL((k_march2_zf<32, 8, true>), g, b, 0, s, ev0, ev1, 0, n, t.tz, ntx, nty, z, dinv,
+                                  p_old, p_new, k, q, ws.partials, ws.sc);
+        else
+            hipExtLaunchKernelGGL((k_march2_zf<32, 8, false>), g, b, 0, s, ev0, ev1, 0, n, t.tz, ntx, nty, z, dinv,
+                                  p_old, p_new, k, q, ws.partials, ws.sc);
+    }
+    launch_finalize(FIN_PQ, t.blocks, ws, s);
 }
 
 template <typename T>
