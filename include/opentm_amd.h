@@ -179,6 +179,13 @@ typedef struct {
     double rho_min; /* lower density bound */
 } otm_oc_opts;
 
+/* Adaptive volume bound (Sec. 2.3, model 3; Algorithm 1).  Each design
+ * iteration: an objective g <= bound shrinks V* by the fraction Df of the gap
+ * to mean(rho~^p), and Df <- decay Df; otherwise an iteration with
+ * |dg| < dg_small and |mean(rho) - V*| < dv_small is a stall, and the
+ * patience-th consecutive stall raises V* by rebound * gap * Df.  V* stays in
+ * [rho_min, 1].  Thresholds finite and >= 0, decay in [0, 1], patience and
+ * stall_iters >= 1, else otm_create returns OTM_EINVAL. */
 typedef struct {
     double bound;     /* objective considered small enough to shrink V* */
     double dg_small;  /* |g_prev - g| below this counts as little progress */
@@ -274,7 +281,9 @@ int otm_set_field(otm_ctx* ctx, int32_t field, const double* host_in, int64_t co
 /* Initial guess for OTM_GUESS_USER: 3 n^3 float64 values (voxel units). */
 int otm_set_guess(otm_ctx* ctx, const double* chi_host, int64_t count);
 
-/* Governor state as 8 doubles: [vstar, df, count, gap, g_prev, small_steps, iter, 0].
+/* Adaptive volume bound (Algorithm 1) as 8 doubles: [V*, decrease factor Df,
+ * consecutive stalls (the algorithm's count), gap, previous objective,
+ * consecutive iterations with |dg| < g_tol, design iterations done, 0].
  * set restores a state returned by get (checkpoint/resume). */
 int otm_get_governor(const otm_ctx* ctx, double state8[8]);
 int otm_set_governor(otm_ctx* ctx, const double state8[8]);
@@ -365,6 +374,9 @@ int otm_batch_set_graph(otm_batch* batch, int32_t use_graph);
 /* [designs, total cells, operator work items, tile width, march length of
  *  design 0, tuned operator-pass us, last solve ms, last step ms] */
 int otm_batch_info(const otm_batch* batch, double info8[8]);
+/* Adaptive volume bound state of design d (Algorithm 1), the 8 doubles of
+ * otm_get_governor; the iteration count is the batch's. */
+int otm_batch_get_governor(const otm_batch* batch, int32_t d, double state8[8]);
 /* Device memory the batch holds (its arenas, tables and graph buffers), bytes. */
 int otm_batch_device_bytes(const otm_batch* batch, int64_t* bytes);
 const char* otm_batch_last_error(const otm_batch* batch);

@@ -356,49 +356,69 @@ class GovernorParams:
     rho_min: float = 1e-3
 
 
-class Governor:
-    """Adaptive volume bound V*(rho): Algorithm 1, one call per OC iteration.
+@dataclasses.dataclass(frozen=True)
+class GovernorState:
+    """What Algorithm 1 carries from one OC iteration to the next, in the
+    paper's notation: V*, the decrease factor Df, the stall counter `count`,
+    the last measured `gap`, g^[I-1]; plus the count of consecutive small
+    objective changes used by the termination test."""
+    vstar: float
+    df: float = 1.0
+    count: int = 0
+    gap: float = 0.0
+    g_prev: float = 1.0      # g^[0] = 1
+    small_steps: int = 0
 
-    State starts as Df = 1, count = 0, g^[0] = 1, gap = 0; V*_0 is the
+
+def governor_transition(st: GovernorState, g: float, low_bound: float, volume: float,
+                        gp: GovernorParams) -> GovernorState:
+    """Algorithm 1 on one OC iteration's observations: the objective g^[I],
+    lowBound = mean(rho~^p) and the volume V = mean(rho).  Returns the next
+    state; V* is clamped to [rho_min, 1] at the end."""
+    vstar, df, gap = st.vstar, st.df, st.gap
+    # Reduce V* only when the objective is tolerable: V* loses the fraction
+    # Df of its distance to lowBound, and Df decays for the next reduction.
+    if g <= gp.bound:
+        gap = vstar - low_bound
+        vstar, df = vstar - gap * df, gp.decay * df
+    # Little progress, still too large an objective, volume on the bound:
+    # all three (judged after the reduction) make a stalled iteration.
+    tests = (abs(st.g_prev - g) < gp.dg_small, g > gp.bound, abs(volume - vstar) < gp.dv_small)
+    count = st.count + 1 if all(tests) else 0
+    # Rebound V* once the stalls reach the patience.
+    if count >= gp.patience:
+        vstar, count = vstar + gp.rebound * gap * df, 0
+    vstar = min(1.0, max(gp.rho_min, vstar))
+    small = st.small_steps + 1 if abs(st.g_prev - g) < gp.g_tol else 0
+    return GovernorState(vstar, df, count, gap, g, small)
+
+
+class Governor:
+    """Adaptive volume bound V*(rho) (Sec. 2.3, model 3; Algorithm 1): holds a
+    GovernorState and advances it once per OC iteration.
+
+    The state starts at Df = 1, count = 0, g^[0] = 1, gap = 0; V*_0 is the
     configured volume fraction (vstar0 = 1 reproduces the algorithm's own
-    initial value).  V* is clamped to [rho_min, 1] after each update."""
+    initial value)."""
 
     def __init__(self, vstar0: float, gp: Optional[GovernorParams] = None):
         self.gp = gp or GovernorParams()
-        self.vstar = float(vstar0)
-        self.df = 1.0
-        self.count = 0
-        self.gap = 0.0
-        self.g_prev = 1.0
-        self.small_steps = 0
+        self.state = GovernorState(float(vstar0))
 
     def update(self, g: float, low_bound: float, volume: float) -> float:
-        gp = self.gp
-        if g <= gp.bound:
-            self.gap = self.vstar - low_bound
-            self.vstar = self.vstar - self.gap * self.df
-            self.df = gp.decay * self.df
-        little_progress = abs(self.g_prev - g) < gp.dg_small
-        need_reduction = g > gp.bound
-        at_boundary = abs(volume - self.vstar) < gp.dv_small
-        if little_progress and need_reduction and at_boundary:
-            self.count += 1
-        else:
-            self.count = 0
-        if self.count >= gp.patience:
-            self.vstar = self.vstar + gp.rebound * self.gap * self.df
-            self.count = 0
-        self.vstar = min(1.0, max(gp.rho_min, self.vstar))
-        # termination bookkeeping (three consecutive small changes of g)
-        if abs(self.g_prev - g) < gp.g_tol:
-            self.small_steps += 1
-        else:
-            self.small_steps = 0
-        self.g_prev = g
-        return self.vstar
+        self.state = governor_transition(self.state, g, low_bound, volume, self.gp)
+        return self.state.vstar
+
+    vstar = property(lambda self: self.state.vstar)
+    df = property(lambda self: self.state.df)
+    count = property(lambda self: self.state.count)
+    gap = property(lambda self: self.state.gap)
+    g_prev = property(lambda self: self.state.g_prev)
+    small_steps = property(lambda self: self.state.small_steps)
 
     @property
     def converged(self) -> bool:
+        """Termination: |g^[I-1] - g^[I]| < g_tol for stall_iters consecutive iterations."""
         return self.small_steps >= self.gp.stall_iters
 
 

@@ -54,7 +54,7 @@ EXPORTED = [
     "otm_nn_create", "otm_nn_destroy", "otm_nn_param_count", "otm_nn_get_params", "otm_nn_set_params",
     "otm_nn_get_grads", "otm_nn_forward", "otm_nn_accumulate", "otm_nn_adam", "otm_nn_zero_grads",
     "otm_nn_last_error", "otm_set_network", "otm_init_density", "otm_apply_device_tiled", "otm_device_bytes",
-    "otm_batch_device_bytes",
+    "otm_batch_device_bytes", "otm_batch_get_governor",
 ]
 
 
@@ -162,6 +162,7 @@ def lib():
         "otm_batch_step": ([vp, P(IterRecord)], ctypes.c_int),
         "otm_batch_set_graph": ([vp, i32], ctypes.c_int),
         "otm_batch_info": ([vp, dp], ctypes.c_int),
+        "otm_batch_get_governor": ([vp, i32, dp], ctypes.c_int),
         "otm_batch_last_error": ([vp], ctypes.c_char_p),
         "otm_nn_create": ([i32, ctypes.c_uint64, vp, P(vp)], ctypes.c_int),
         "otm_nn_destroy": ([vp], None),

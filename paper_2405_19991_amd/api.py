@@ -386,6 +386,12 @@ class Batch:
         keys = ["designs", "cells", "work_items", "tile_tx", "tile_tz", "tuned_pass_us", "solve_ms", "step_ms"]
         return dict(zip(keys, a.tolist()))
 
+    def governor_state(self, d: int) -> List[float]:
+        """Adaptive volume bound of design d: [V*, Df, stalls, gap, g_prev, flat, iter, 0]."""
+        s = np.zeros(8)
+        self._chk(self._L.otm_batch_get_governor(self._h, int(d), _ptr(s)))
+        return s.tolist()
+
     def device_bytes(self) -> int:
         """Device memory the batch holds, bytes."""
         b = ctypes.c_int64()

@@ -26,15 +26,6 @@
 
 using namespace otm;
 
-namespace {
-
-struct Gov {
-    double vstar = 1.0, df = 1.0, gap = 0.0, g_prev = 1.0;
-    int count = 0, small_steps = 0;
-};
-
-}  // namespace
-
 struct otm_batch {
     int count = 0;
     int64_t dev_bytes = 0;  // device memory this batch holds
@@ -72,7 +63,7 @@ struct otm_batch {
     hipGraph_t graph = nullptr;
     hipGraphExec_t gexec = nullptr;
 
-    std::vector<Gov> gov;
+    std::vector<VolumeBound> gov;
     std::vector<double> kappa, g, volume, low;
     std::vector<int> have_density;
     bool have_solution = false;
@@ -247,32 +238,6 @@ int solve(otm_batch* c, bool x_zero) {
     return blaunch_ok(c, "project");
 }
 
-double gov_update(const otm_governor_opts& go, double rho_min, Gov& s, double g, double low, double vol) {
-    if (g <= go.bound) {
-        s.gap = s.vstar - low;
-        s.vstar = s.vstar - s.gap * s.df;
-        s.df = go.decay * s.df;
-    }
-    const bool little = std::fabs(s.g_prev - g) < go.dg_small;
-    const bool big = g > go.bound;
-    const bool at_bound = std::fabs(vol - s.vstar) < go.dv_small;
-    if (little && big && at_bound)
-        s.count += 1;
-    else
-        s.count = 0;
-    if (s.count >= go.patience) {
-        s.vstar = s.vstar + go.rebound * s.gap * s.df;
-        s.count = 0;
-    }
-    s.vstar = std::min(1.0, std::max(rho_min, s.vstar));
-    if (std::fabs(s.g_prev - g) < go.g_tol)
-        s.small_steps += 1;
-    else
-        s.small_steps = 0;
-    s.g_prev = g;
-    return s.vstar;
-}
-
 // Time the batched operator pass for a (tile width, march length) candidate.
 double time_candidate(otm_batch* c, int wx, int tz) {
     build_tables(c, wx, tz);
@@ -392,6 +357,11 @@ int otm_batch_create(const otm_problem* problems, int32_t count, const otm_solve
             (c->so.precision != OTM_FP64 || c->so.preconditioner != OTM_PRECOND_JACOBI) ? OTM_EUNSUPPORTED : OTM_EINVAL;
         delete c;
         return code;
+    }
+    if (!(c->oc.move > 0.0 && c->oc.eta > 0.0 && c->oc.rho_min > 0.0 && c->oc.rho_min < 1.0) ||
+        !governor_opts_valid(c->go)) {
+        delete c;
+        return OTM_EINVAL;
     }
     if (c->so.check_every % 2) c->so.check_every += 1;
     hipDeviceProp_t prop;
@@ -570,7 +540,8 @@ int otm_batch_step(otm_batch* c, otm_iter_record* recs) {
                 R.rel_residual[l] = s.bb[l] > 0.0 ? std::sqrt(s.rr_true[l] / s.bb[l]) : 0.0;
             }
         }
-        vstar[d] = gov_update(c->go, c->oc.rho_min, c->gov[d], gg, c->low[d], c->volume[d]);
+        advance_volume_bound(c->go, c->oc.rho_min, c->gov[d], gg, c->low[d], c->volume[d]);
+        vstar[d] = c->gov[d].vstar;
     }
     BCHK(c, hipMemcpyAsync(c->dw6, w6.data(), c->count * sizeof(W6), hipMemcpyHostToDevice, c->stream));
     BCHK(c, hipMemcpyAsync(c->dvstar, vstar.data(), c->count * sizeof(double), hipMemcpyHostToDevice, c->stream));
@@ -599,7 +570,7 @@ int otm_batch_step(otm_batch* c, otm_iter_record* recs) {
             recs[d].lambda = c->h_sc[d].lam;
             recs[d].ms_total = std::chrono::duration<double, std::milli>(t3 - t0).count();
             recs[d].ms_solve = std::chrono::duration<double, std::milli>(t2 - t1).count();
-            recs[d].stop = c->gov[d].small_steps >= c->go.stall_iters ? 1 : 0;
+            recs[d].stop = c->gov[d].flat >= c->go.stall_iters ? 1 : 0;
         }
     c->t_ms[0] = std::chrono::duration<double, std::milli>(t1 - t0).count();
     c->t_ms[1] = std::chrono::duration<double, std::milli>(t2 - t1).count();
@@ -607,6 +578,20 @@ int otm_batch_step(otm_batch* c, otm_iter_record* recs) {
     c->t_ms[3] = std::chrono::duration<double, std::milli>(t3 - t0).count();
     c->iter += 1;
     return conv ? OTM_OK : OTM_NOT_CONVERGED;
+}
+
+int otm_batch_get_governor(const otm_batch* c, int32_t d, double s[8]) {
+    if (!c || !s || d < 0 || d >= c->count) return OTM_EINVAL;
+    const VolumeBound& v = c->gov[d];
+    s[0] = v.vstar;
+    s[1] = v.df;
+    s[2] = (double)v.stalls;
+    s[3] = v.gap;
+    s[4] = v.g_prev;
+    s[5] = (double)v.flat;
+    s[6] = (double)c->iter;
+    s[7] = 0.0;
+    return OTM_OK;
 }
 
 int otm_batch_device_bytes(const otm_batch* c, int64_t* bytes) {

@@ -102,9 +102,9 @@ struct otm_ctx {
     double w[6] = {0, 0, 0, 0, 0, 0};
     double volume = 0.0, low_bound = 0.0;
 
-    // governor (Algorithm 1)
-    double vstar = 1.0, df = 1.0, gap = 0.0, g_prev = 1.0;
-    int count = 0, small_steps = 0, iter = 0;
+    // adaptive volume bound (Algorithm 1) and the design iteration count
+    VolumeBound vb;
+    int iter = 0;
 
     otm_solve_stats last_stats{};
     double timings[8] = {0, 0, 0, 0, 0, 0, 0, 0};
@@ -750,36 +750,6 @@ int oc_update(otm_ctx* c, double vstar, double* lambda_out) {
     return OTM_OK;
 }
 
-// Algorithm 1 (adaptive V*), one call per design iteration.
-double governor_update(otm_ctx* c, double g, double low, double vol) {
-    const otm_governor_opts& go = c->go;
-    if (g <= go.bound) {
-        c->gap = c->vstar - low;
-        c->vstar = c->vstar - c->gap * c->df;
-        c->df = go.decay * c->df;
-    }
-    const bool little = std::fabs(c->g_prev - g) < go.dg_small;
-    const bool big = g > go.bound;
-    const bool at_bound = std::fabs(vol - c->vstar) < go.dv_small;
-    if (little && big && at_bound)
-        c->count += 1;
-    else
-        c->count = 0;
-    if (c->count >= go.patience) {
-        c->vstar = c->vstar + go.rebound * c->gap * c->df;
-        c->count = 0;
-    }
-    if (c->vstar > 1.0) c->vstar = 1.0;
-    if (c->vstar < c->oc.rho_min) c->vstar = c->oc.rho_min;
-    if (std::fabs(c->g_prev - g) < go.g_tol)
-        c->small_steps += 1;
-    else
-        c->small_steps = 0;
-    c->g_prev = g;
-    return c->vstar;
-}
-
-
 int free_all(otm_ctx* c) {
     void* bufs[] = {c->rho, c->rhof, c->k, c->dinv, c->b, c->x, c->st, c->sens, c->ocq, c->r64, c->p64[0], c->p64[1],
                     c->q64, c->k32, c->dinv32, c->x32, c->r32, c->p32[0], c->p32[1], c->q32, c->partials, c->counter,
@@ -1146,7 +1116,8 @@ int otm_create(const otm_problem* problem, const otm_solver_opts* solver, const 
         }
         c->use_mg = true;
     }
-    if (!(c->oc.move > 0.0 && c->oc.eta > 0.0 && c->oc.rho_min > 0.0 && c->oc.rho_min < 1.0)) {
+    if (!(c->oc.move > 0.0 && c->oc.eta > 0.0 && c->oc.rho_min > 0.0 && c->oc.rho_min < 1.0) ||
+        !governor_opts_valid(c->go)) {
         delete c;
         return OTM_EINVAL;
     }
@@ -1269,7 +1240,7 @@ int otm_create(const otm_problem* problem, const otm_solver_opts* solver, const 
             return rc;
         }
     }
-    c->vstar = problem->vf;
+    c->vb.vstar = problem->vf;
     *out = c;
     return OTM_OK;
 }
@@ -1351,7 +1322,8 @@ int otm_step(otm_ctx* c, otm_iter_record* rec) {
     int rc = sensitivity(c, w6);
     if (rc) return rc;
     const double vol = c->volume, low = c->low_bound;
-    const double vstar = governor_update(c, g, low, vol);
+    advance_volume_bound(c->go, c->oc.rho_min, c->vb, g, low, vol);
+    const double vstar = c->vb.vstar;
     double lam = 0.0;
     rc = oc_update(c, vstar, &lam);
     if (rc) return rc;
@@ -1372,7 +1344,7 @@ int otm_step(otm_ctx* c, otm_iter_record* rec) {
         }
         rec->ms_total = c->timings[5];
         rec->ms_solve = st.ms_solve;
-        rec->stop = c->small_steps >= c->go.stall_iters ? 1 : 0;
+        rec->stop = c->vb.flat >= c->go.stall_iters ? 1 : 0;
     }
     c->iter += 1;
     return hrc;
@@ -1457,12 +1429,12 @@ int otm_set_guess(otm_ctx* c, const double* chi, int64_t count) {
 
 int otm_get_governor(const otm_ctx* c, double s[8]) {
     if (!c || !s) return OTM_EINVAL;
-    s[0] = c->vstar;
-    s[1] = c->df;
-    s[2] = (double)c->count;
-    s[3] = c->gap;
-    s[4] = c->g_prev;
-    s[5] = (double)c->small_steps;
+    s[0] = c->vb.vstar;
+    s[1] = c->vb.df;
+    s[2] = (double)c->vb.stalls;
+    s[3] = c->vb.gap;
+    s[4] = c->vb.g_prev;
+    s[5] = (double)c->vb.flat;
     s[6] = (double)c->iter;
     s[7] = 0.0;
     return OTM_OK;
@@ -1472,12 +1444,12 @@ int otm_set_governor(otm_ctx* c, const double s[8]) {
     if (!c || !s) return OTM_EINVAL;
     for (int q = 0; q < 7; ++q)
         if (!std::isfinite(s[q])) return fail(c, OTM_ENONFINITE, "non-finite governor state");
-    c->vstar = s[0];
-    c->df = s[1];
-    c->count = (int)s[2];
-    c->gap = s[3];
-    c->g_prev = s[4];
-    c->small_steps = (int)s[5];
+    c->vb.vstar = s[0];
+    c->vb.df = s[1];
+    c->vb.stalls = (int)s[2];
+    c->vb.gap = s[3];
+    c->vb.g_prev = s[4];
+    c->vb.flat = (int)s[5];
     c->iter = (int)s[6];
     return OTM_OK;
 }

@@ -188,6 +188,61 @@ inline void objective_grad(int kind, const double* kappa, const double* target, 
     *g = s;
 }
 
+// Adaptive volume bound V* of the moving-constraint model (Sec. 2.3, model 3;
+// Algorithm 1), kept between design iterations of one design.  Single
+// contexts and batches hold one each and advance it with advance_volume_bound.
+struct VolumeBound {
+    double vstar = 1.0;   // the bound V* the next OC update enforces
+    double df = 1.0;      // decrease factor: the fraction of the gap removed by a shrink
+    double gap = 0.0;     // V* - lowBound as measured at the last shrink (sizes a rebound)
+    double g_prev = 1.0;  // objective of the previous design iteration (1 before the first)
+    int stalls = 0;       // consecutive iterations that made no headway against the bound
+    int flat = 0;         // consecutive iterations whose objective changed by less than g_tol
+};
+
+// One design iteration's transition, given its objective g, the
+// solid-equivalent volume low = mean(rho~^p) and the volume vol = mean(rho).
+// The rules of the adaptive bound:
+//  * shrink: an objective at or below the tolerable value means material can
+//    go; V* moves the fraction Df of the way down to `low`, and Df decays;
+//  * stall: an objective above that value that barely moved while the volume
+//    sits on V* means the bound is what holds the design back; such
+//    iterations are counted while consecutive (a shrink or any other
+//    iteration resets the count);
+//  * grow: the patience-th consecutive stall raises V* by rebound * gap * Df
+//    and starts the count again.
+// V* stays in [rho_min, 1].  `flat` feeds the termination test (the objective
+// changing little for several consecutive iterations).
+inline void advance_volume_bound(const otm_governor_opts& o, double rho_min, VolumeBound& s, double g, double low,
+                                 double vol) {
+    const double dg = g > s.g_prev ? g - s.g_prev : s.g_prev - g;
+    if (g <= o.bound) {
+        s.gap = s.vstar - low;
+        s.vstar = s.vstar - s.gap * s.df;
+        s.df = o.decay * s.df;
+        s.stalls = 0;
+    } else {
+        const double off = vol > s.vstar ? vol - s.vstar : s.vstar - vol;
+        s.stalls = (dg < o.dg_small && off < o.dv_small) ? s.stalls + 1 : 0;
+    }
+    if (s.stalls >= o.patience) {
+        s.vstar = s.vstar + o.rebound * s.gap * s.df;
+        s.stalls = 0;
+    }
+    s.vstar = s.vstar > 1.0 ? 1.0 : (s.vstar < rho_min ? rho_min : s.vstar);
+    s.flat = dg < o.g_tol ? s.flat + 1 : 0;
+    s.g_prev = g;
+}
+
+// Governor options are usable: finite, non-negative thresholds, decay in
+// [0, 1], patience and stall_iters >= 1.
+inline bool governor_opts_valid(const otm_governor_opts& o) {
+    auto fin = [](double v) { return v - v == 0.0; };
+    return fin(o.bound) && fin(o.dg_small) && fin(o.dv_small) && fin(o.decay) && fin(o.rebound) && fin(o.g_tol) &&
+           o.bound >= 0.0 && o.dg_small >= 0.0 && o.dv_small >= 0.0 && o.decay >= 0.0 && o.decay <= 1.0 &&
+           o.rebound >= 0.0 && o.g_tol >= 0.0 && o.patience >= 1 && o.stall_iters >= 1;
+}
+
 // f_e = f_{n^3-1-e} = (f_e + f_{n^3-1-e}) / 2: central symmetry of an element field
 void launch_sym_central(int n, double* f, hipStream_t s);
 

@@ -150,3 +150,22 @@ def test_objective_and_symmetry_validation(L):
     arr[0] = _problem(N)
     arr[0].symmetry = N.OTM_SYM_CENTRAL
     assert L.otm_batch_create(arr, 1, None, None, None, None, ctypes.byref(h)) == N.OTM_EUNSUPPORTED
+
+
+@pytest.mark.parametrize("field,value", [("patience", 0), ("stall_iters", 0), ("decay", 1.5), ("decay", -0.1),
+                                         ("bound", float("nan")), ("dg_small", -1.0), ("rebound", float("inf"))])
+def test_governor_options_rejected(L, field, value):
+    """Adaptive volume bound options are checked before any device work, for
+    single contexts and batches."""
+    from paper_2405_19991_amd import _native as N
+    p = _problem(N)
+    s, o, g = N.default_options()
+    setattr(g, field, value)
+    h = ctypes.c_void_p()
+    assert L.otm_create(ctypes.byref(p), None, None, ctypes.byref(g), None, ctypes.byref(h)) == N.OTM_EINVAL
+    assert not h.value
+    arr = (N.Problem * 1)()
+    arr[0] = _problem(N)
+    assert L.otm_batch_create(arr, 1, None, None, ctypes.byref(g), None, ctypes.byref(h)) == N.OTM_EINVAL
+    b8 = (ctypes.c_double * 8)()
+    assert L.otm_batch_get_governor(None, 0, b8) == N.OTM_EINVAL

@@ -65,3 +65,37 @@ def test_traversal_design_matches_single_context():
                 rec = h.step()
                 assert brecs[it][j]["g"] == pytest.approx(rec["g"], rel=1e-7), (d, it)
                 assert brecs[it][j]["vstar"] == pytest.approx(rec["vstar"], rel=1e-9), (d, it)
+
+
+def test_traversal_designs_follow_oracle():
+    """Three traversal design iterations (IWP start at volume 0.3, V*_0 = 1,
+    OC move 0.02, 16^3) of three gallery targets in one batch against the
+    oracle's own design iterations (CSR + CG to 1e-12, its OC bisection and
+    governor): objective, tensor, V*, lambda per iteration and the density
+    after the third."""
+    import oracle as O
+    from paper_2405_19991_amd import Batch, init_density
+    T = synth.gallery_targets()
+    n = 16
+    rho0 = init_density(n, "IWP", 0.3)
+    np.testing.assert_array_equal(rho0, O.init_density("IWP", n, 0.3))
+    picks = [0, 30, 60]
+    steps = 3
+    B = Batch([dict(n=n, target=tuple(T[d]), vf=1.0) for d in picks], tol=1e-10, guess="previous", move=0.02)
+    for d in range(len(picks)):
+        B.set_density(d, rho0)
+    brecs = [B.step() for _ in range(steps)]
+    brho = [B.get_field(j, "rho") for j in range(len(picks))]
+    B.close()
+    prm = O.Params(tol=1e-12, move=0.02)
+    for j, d in enumerate(picks):
+        gov = O.Governor(1.0)
+        rho = np.clip(rho0, prm.rho_min, 1.0)
+        for it in range(steps):
+            rho, ref, _, _ = O.oc_iteration(rho, np.asarray(T[d]), gov, prm)
+            r = brecs[it][j]
+            assert r["g"] == pytest.approx(ref.g, rel=1e-7), (d, it)
+            np.testing.assert_allclose(r["kappa"], ref.kappa, rtol=1e-8, atol=1e-11)
+            assert r["vstar"] == pytest.approx(ref.vstar, rel=1e-12), (d, it)
+            assert r["lam"] == pytest.approx(ref.lam, rel=1e-8, abs=1e-40), (d, it)
+        np.testing.assert_allclose(brho[j], rho, rtol=0, atol=1e-8)

@@ -363,6 +363,55 @@ def test_governor_clamp_and_termination():
     assert flags == [False, False, False, True, False]
 
 
+def test_governor_rebound_uses_decayed_factor_and_resets_count():
+    """Algorithm 1 with patience 2, all stall tests passing: the second stall
+    raises V* by 0.3 * gap * Df with the Df left by the last reduction
+    (0.8 after one), and the count starts again."""
+    gp = O.GovernorParams(bound=1e-4, dg_small=1.0, dv_small=1.0, patience=2)
+    gov = O.Governor(0.6, gp)
+    assert gov.update(1e-5, 0.2, 0.6) == pytest.approx(0.2, abs=1e-15)    # reduce: gap 0.4, Df 1 -> 0.8
+    assert gov.count == 0
+    assert gov.update(1e-3, 0.1, 0.2) == pytest.approx(0.2, abs=1e-15)    # first stall
+    assert gov.count == 1
+    assert gov.update(1e-3, 0.1, 0.2) == pytest.approx(0.296, abs=1e-15)  # rebound 0.3 * 0.4 * 0.8
+    assert (gov.count, gov.gap, gov.df) == (0, pytest.approx(0.4), pytest.approx(0.8))
+
+
+def _checkerboard(n, a, d):
+    i = np.arange(n)
+    par = (i[:, None, None] + i[None, :, None] + i[None, None, :]) % 2
+    return a + d * (1 - 2 * par)
+
+
+def test_oc_iteration_low_bound_is_mean_of_filtered_density_power():
+    """The composition of one OC iteration (reading R15/R17): the governor's
+    lowBound is mean(rho~^p) over elements, with rho~ the filtered density,
+    and the OC update of the same iteration enforces the V* it produced.
+
+    Element-parity checkerboard rho = a + d (-1)^(i+j+k): the r = 1.5 filter
+    has the 1-D symbol 0.6 - 0.4 = 0.2 on the alternating mode, so
+    rho~ = a + 0.008 d (-1)^(i+j+k) and mean(rho~^3) = a^3 + 3 a (0.008 d)^2.
+    With the bound so large that the first iteration reduces and Df = 1, V*
+    lands exactly on lowBound.  mean(rho^3) (no filter) gives a^3 + 3 a d^2,
+    mean(k_e) gives kmin + mean(rho~^3)(k0 - kmin): both differ here.  The
+    target exceeds every reachable conductivity, so every sensitivity is
+    negative and, with move 1, V* is reachable: mean(rho_new) = V*."""
+    n, a, d = 6, 0.5, 0.4
+    rho = _checkerboard(n, a, d)
+    prm = O.Params(k0=2.0, kmin=0.1, tol=1e-12, move=1.0)
+    gov = O.Governor(0.9, O.GovernorParams(bound=1e9))
+    rho_new, rec, h, s = O.oc_iteration(rho, np.array([10.0, 10.0, 10.0, 0.0, 0.0, 0.0]), gov, prm)
+    low = a ** 3 + 3 * a * (0.008 * d) ** 2
+    assert rec.low_bound == pytest.approx(low, rel=1e-13)
+    assert rec.vstar == pytest.approx(low, rel=1e-13)
+    assert abs(rec.vstar - (a ** 3 + 3 * a * d ** 2)) > 0.1
+    assert abs(rec.vstar - (0.1 + low * 1.9)) > 0.1
+    assert rec.volume == pytest.approx(a, rel=1e-15)
+    assert np.all(s < 0)
+    assert np.mean(rho_new) == pytest.approx(low, rel=1e-12)
+    assert gov.df == pytest.approx(0.8, abs=1e-15)
+
+
 # -------------------------------------------------------------- golden data
 
 def test_gallery_positive_definite_count():
