@@ -234,44 +234,47 @@ class Homogenization:
             self.set_guess(d["chi"])
 
 
-def apply_device(k, x, y, precision: str = "fp64", stream=None, variant: int = 0) -> None:
-    """y = A x on caller device memory (torch CUDA tensors, load-major 3 n^3)."""
+def _operator_args(k, x, y, precision: str, stream):
+    """Validate the tensors of a stateless operator call before any pointer
+    reaches the library: n^3 conductivities, 3 n^3 node values, contiguous
+    CUDA tensors of the precision's dtype on one device, y not aliasing x."""
     import torch
+    if precision not in ("fp64", "mixed", "fp32"):
+        raise ValueError(f"unknown precision {precision!r}")
     n = round(k.numel() ** (1.0 / 3.0))
-    if n ** 3 != k.numel() or x.numel() != 3 * n ** 3 or y.numel() != 3 * n ** 3:
-        raise ValueError("shape mismatch")
+    if n < 4 or n ** 3 != k.numel() or x.numel() != 3 * n ** 3 or y.numel() != 3 * n ** 3:
+        raise ValueError("shape mismatch: k needs n^3 values, x and y 3 n^3")
     want = torch.float64 if precision == "fp64" else torch.float32
     for t in (k, x, y):
-        if t.dtype != want or not t.is_cuda or not t.is_contiguous():
-            raise ValueError("tensors must be contiguous CUDA tensors of the precision's dtype")
-    s = stream if stream is not None else torch.cuda.current_stream().cuda_stream
-    N.check(N.lib().otm_apply_device(n, N.OTM_FP64 if precision == "fp64" else N.OTM_MIXED, int(variant),
-                                     ctypes.c_void_p(k.data_ptr()), ctypes.c_void_p(x.data_ptr()),
-                                     ctypes.c_void_p(y.data_ptr()), ctypes.c_void_p(s)))
+        if t.dtype != want or not t.is_cuda or not t.is_contiguous() or t.device != k.device:
+            raise ValueError("tensors must be contiguous CUDA tensors of the precision's dtype on one device")
+    if y.data_ptr() == x.data_ptr():
+        raise ValueError("y must not alias x")
+    s = stream if stream is not None else torch.cuda.current_stream(k.device).cuda_stream
+    prec = N.OTM_FP64 if precision == "fp64" else N.OTM_MIXED
+    return n, prec, ctypes.c_void_p(k.data_ptr()), ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr()), \
+        ctypes.c_void_p(s)
+
+
+def apply_device(k, x, y, precision: str = "fp64", stream=None, variant: int = 0) -> None:
+    """y = A x on caller device memory (torch CUDA tensors, load-major 3 n^3)."""
+    n, prec, kp, xp, yp, s = _operator_args(k, x, y, precision, stream)
+    N.check(N.lib().otm_apply_device(n, prec, int(variant), kp, xp, yp, s))
 
 
 def apply_device_tiled(k, x, y, precision: str, tile_tx: int, tile_tz: int, variant: int = 0, stream=None) -> None:
     """One y = A x launch with an explicit tile, on the given (default: the
     current torch) stream, not synchronised."""
-    import torch
-    n = round(k.numel() ** (1.0 / 3.0))
-    s = stream if stream is not None else torch.cuda.current_stream().cuda_stream
-    N.check(N.lib().otm_apply_device_tiled(n, N.OTM_FP64 if precision == "fp64" else N.OTM_MIXED, int(variant),
-                                           int(tile_tx), int(tile_tz), ctypes.c_void_p(k.data_ptr()),
-                                           ctypes.c_void_p(x.data_ptr()), ctypes.c_void_p(y.data_ptr()),
-                                           ctypes.c_void_p(s)))
+    n, prec, kp, xp, yp, s = _operator_args(k, x, y, precision, stream)
+    N.check(N.lib().otm_apply_device_tiled(n, prec, int(variant), int(tile_tx), int(tile_tz), kp, xp, yp, s))
 
 
 def time_apply_device(k, x, y, precision: str = "fp64", reps: int = 50, stream=None, variant: int = 0,
                       tile_tx: int = 0, tile_tz: int = 0) -> float:
-    import torch
-    n = round(k.numel() ** (1.0 / 3.0))
-    s = stream if stream is not None else torch.cuda.current_stream().cuda_stream
+    n, prec, kp, xp, yp, s = _operator_args(k, x, y, precision, stream)
     us = ctypes.c_double()
-    N.check(N.lib().otm_time_apply_device(n, N.OTM_FP64 if precision == "fp64" else N.OTM_MIXED, int(variant),
-                                          int(tile_tx), int(tile_tz), ctypes.c_void_p(k.data_ptr()), ctypes.c_void_p(x.data_ptr()),
-                                          ctypes.c_void_p(y.data_ptr()), ctypes.c_void_p(s), int(reps),
-                                          ctypes.byref(us)))
+    N.check(N.lib().otm_time_apply_device(n, prec, int(variant), int(tile_tx), int(tile_tz), kp, xp, yp, s,
+                                          int(reps), ctypes.byref(us)))
     return us.value
 
 
