@@ -258,6 +258,33 @@ int otm_sensitivity(otm_ctx* ctx, const double dg_dkappa6[6], double* dg_drho_ho
  * The context's density is replaced by the update. */
 int otm_oc_update(otm_ctx* ctx, double vstar, double* rho_out_host, double* lambda_out);
 
+/* Optimality Criteria update that allocates nothing, for callers that cannot
+ * allocate device memory: code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc.  It computes what otm_oc_update computes
+ * from caller device buffers, with no context:
+ *   rho_dev   n^3 float64 design densities (device; expected in [rho_min, 1])
+ *   sens_dev  n^3 float64 dg/drho (device)
+ *   vstar     volume bound, 0 < vstar <= 1
+ *   oc        move, eta, rho_min as for otm_create (host struct, read in-call)
+ *   rho_out_dev  n^3 float64 updated densities (device); may be rho_dev itself
+ *   lambda_dev   one float64 (device) receiving the multiplier; may be NULL
+ *   stream    hipStream_t or NULL
+ * The bisection's scratch (partial sums and device scalars, 132 KiB, the
+ * same for every n) is a static device array that each GPU holds until the
+ * process ends; q_e is recomputed from (rho_e, s_e), so no n^3 buffer is used.
+ * The call only enqueues kernels on `stream` (no synchronisation, no host
+ * read-back: every possible bisection pass is launched and those after the
+ * stop return at once) and returns.  Calls on one GPU share the scratch:
+ * calls that overlap on one GPU (other streams or threads) race, so the
+ * caller serialises them.  With the same inputs and options it gives the
+ * same rho and lambda as otm_oc_update.
+ * Errors: OTM_EINVAL (null rho/sens/rho_out/oc, n outside 4..1024, vstar
+ * outside (0, 1], invalid oc options, rho_out or lambda aliasing sens,
+ * lambda aliasing a field), OTM_EDEVICE (no device, the scratch address
+ * lookup or a launch failed), OTM_EUNSUPPORTED (device index >= 64). */
+int otm_oc_update_noalloc(int32_t n, const void* rho_dev, const void* sens_dev, double vstar,
+                          const otm_oc_opts* oc, void* rho_out_dev, void* lambda_dev, void* stream);
+
 /* One full design iteration (Algorithm 2 body with the Algorithm 1 governor):
  * homogenize -> objective -> sensitivities -> V* update -> OC update. */
 int otm_step(otm_ctx* ctx, otm_iter_record* rec);

@@ -6,4 +6,4 @@ The library is loaded lazily on first use and must have been built
 (``paper_2405_19991_amd/build.py``); there is no CPU fallback.
 """
 from .api import (Batch, Homogenization, Network, apply_device, apply_device_tiled, init_density,  # noqa: F401
-                  run_instance, time_apply_device, version)
+                  oc_update_noalloc, run_instance, time_apply_device, version)

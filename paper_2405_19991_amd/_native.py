@@ -54,7 +54,7 @@ EXPORTED = [
     "otm_nn_create", "otm_nn_destroy", "otm_nn_param_count", "otm_nn_get_params", "otm_nn_set_params",
     "otm_nn_get_grads", "otm_nn_forward", "otm_nn_accumulate", "otm_nn_adam", "otm_nn_zero_grads",
     "otm_nn_last_error", "otm_set_network", "otm_init_density", "otm_apply_device_tiled", "otm_device_bytes",
-    "otm_batch_device_bytes", "otm_batch_get_governor",
+    "otm_batch_device_bytes", "otm_batch_get_governor", "otm_oc_update_noalloc",
 ]
 
 
@@ -134,6 +134,7 @@ def lib():
         "otm_homogenize": ([ctx, dp, P(SolveStats)], ctypes.c_int),
         "otm_sensitivity": ([ctx, dp, dp], ctypes.c_int),
         "otm_oc_update": ([ctx, ctypes.c_double, dp, dp], ctypes.c_int),
+        "otm_oc_update_noalloc": ([i32, vp, vp, ctypes.c_double, P(OcOpts), vp, vp, vp], ctypes.c_int),
         "otm_step": ([ctx, P(IterRecord)], ctypes.c_int),
         "otm_optimize": ([ctx, i32, dp, P(IterRecord), i32, P(i32)], ctypes.c_int),
         "otm_get_field": ([ctx, i32, dp, i64], ctypes.c_int),

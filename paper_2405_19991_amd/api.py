@@ -278,6 +278,34 @@ def time_apply_device(k, x, y, precision: str = "fp64", reps: int = 50, stream=N
     return us.value
 
 
+def oc_update_noalloc(rho, sens, vstar: float, out=None, lam=None, move: float = 0.05, eta: float = 0.5,
+                      rho_min: float = 1e-3, stream=None):
+    """OC update on caller device memory with no device allocation in the
+    library (otm_oc_update_noalloc): rho, sens and out are float64 CUDA
+    tensors of n^3 values (out may be rho); lam, if given, a one-element
+    float64 CUDA tensor for the multiplier.  Enqueued on the stream (default:
+    the current torch stream), not synchronised.  Returns out."""
+    import torch
+    n = round(rho.numel() ** (1.0 / 3.0))
+    if n ** 3 != rho.numel() or sens.numel() != rho.numel():
+        raise ValueError("rho and sens need n^3 values each")
+    if out is None:
+        out = torch.empty_like(rho)
+    ts = [rho, sens, out] + ([lam] if lam is not None else [])
+    for t in ts:
+        if t.dtype != torch.float64 or not t.is_cuda or not t.is_contiguous() or t.device != rho.device:
+            raise ValueError("tensors must be contiguous float64 CUDA tensors on one device")
+    if out.numel() != rho.numel() or (lam is not None and lam.numel() != 1):
+        raise ValueError("out needs n^3 values, lam one")
+    oc = N.OcOpts(float(move), float(eta), float(rho_min))
+    s = stream if stream is not None else torch.cuda.current_stream(rho.device).cuda_stream
+    N.check(N.lib().otm_oc_update_noalloc(n, ctypes.c_void_p(rho.data_ptr()), ctypes.c_void_p(sens.data_ptr()),
+                                          float(vstar), ctypes.byref(oc), ctypes.c_void_p(out.data_ptr()),
+                                          ctypes.c_void_p(lam.data_ptr() if lam is not None else None),
+                                          ctypes.c_void_p(s)))
+    return out
+
+
 def run_instance(reso: int, heat_ratio: Sequence[float], target: Sequence[float], init="IWP", vf: float = 0.3,
                  max_iter: int = 500, **kw):
     """Design one structure: mirrors the paper's runInstance(reso, heatRatio,

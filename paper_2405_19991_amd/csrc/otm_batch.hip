@@ -551,7 +551,7 @@ int otm_batch_step(otm_batch* c, otm_iter_record* recs) {
     // OC bisection for every design
     launch_b_oc_prepare(c->tab, c->rho, c->sens, c->oc.eta, c->ocq, c->stream);
     launch_b_oc_init(c->tab, c->sc, c->dvstar, c->oc.eta, c->stream);
-    const int max_passes = 200 / kOcLevels + 2;
+    const int max_passes = kOcMaxPasses;
     for (int pass = 0; pass < max_passes; pass += 4) {
         for (int q = 0; q < 4; ++q)
             launch_b_oc_pass(c->tab, c->rho, c->ocq, c->oc.move, c->oc.rho_min, c->oc.eta, c->partials, c->sc,

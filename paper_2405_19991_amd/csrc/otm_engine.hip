@@ -730,7 +730,7 @@ int oc_update(otm_ctx* c, double vstar, double* lambda_out) {
     int prep_blocks = 0;
     launch_oc_prepare(n, c->rho, c->sens, c->oc.eta, c->oc.move, c->oc.rho_min, c->ocq, w, c->stream, &prep_blocks);
     launch_oc_init(vstar, n, c->oc.eta, prep_blocks, w, c->stream);
-    const int max_passes = 200 / kOcLevels + 2;
+    const int max_passes = kOcMaxPasses;
     int rc;
     for (int pass = 0; pass < max_passes; pass += 4) {
         for (int q = 0; q < 4; ++q) launch_oc_pass(n, c->rho, c->ocq, c->oc.move, c->oc.rho_min, c->oc.eta, w, c->stream);

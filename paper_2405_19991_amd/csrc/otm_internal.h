@@ -14,6 +14,8 @@ constexpr int kMaxReduce = 32;       // widest multi-value block reduction
 constexpr int kMaxBlocks = 4096;     // producer blocks per reduction (workspace rows)
 constexpr int kOcLevels = 5;         // bisection levels resolved per OC pass
 constexpr int kOcCands = (1 << kOcLevels) - 1;
+// passes that reach the bisection's 200-halving cap, plus the first and a spare
+constexpr int kOcMaxPasses = 200 / kOcLevels + 2;
 
 // State of the fused PCG iteration between passes (per load): the step and
 // direction weight a pass used, the last reduced dots, and the constants the
@@ -165,6 +167,14 @@ void launch_oc_pass(int n, const double* rho, const double* q, double move, doub
                     const Workspace& ws, hipStream_t s);
 void launch_oc_apply(int n, double* rho, const double* q, double eta, double move, double rho_min,
                      const Workspace& ws, hipStream_t s);
+// The whole OC update with q recomputed from (rho, sens) instead of stored:
+// prepare, bracket, kOcMaxPasses bisection passes (those after the stop return
+// at once) and the update into rho_out, all asynchronous on `s` with no host
+// round trip.  The same grids as the stored-q path, so the same lambda and
+// rho_out.  Scratch: ws.sc and 1024 x 2 / 512 x kOcCands doubles of ws.partials.
+void launch_oc_from_sens(int n, const double* rho, const double* sens, double* rho_out, double* lambda_out,
+                         double vstar, double eta, double move, double rho_min, const Workspace& ws,
+                         hipStream_t s);
 void launch_clamp(int n, double* rho, double lo, double hi, hipStream_t s);
 // The objective over the six tensor components and dg/dkappa (Sec. 4.4):
 // squared error, relative squared error, or l1 with d|a|/da = 0 at a = 0.

@@ -388,12 +388,18 @@ __global__ void __launch_bounds__(kBlock) k_sens(int n, const double* __restrict
 
 // ---------------------------------------------------------------- OC
 // q_e = rho_e (max(0, -s_e) n^3)^eta ; rho_new(lam) = clamp(q lam^-eta, lo, hi)
+// Every kernel that needs q_e (stored or recomputed from rho and s) evaluates
+// this one expression, so a recomputed q is bit-identical to a stored one.
+__device__ __forceinline__ double oc_q(double rho_e, double s_e, int64_t nn, double eta) {
+    const double B = fmax(0.0, -s_e) * (double)nn;
+    return rho_e * (eta == 0.5 ? sqrt(B) : pow(B, eta));
+}
+
 __device__ __forceinline__ void b_oc_prepare(int bid_, int nblk_, int64_t nn, const double* __restrict__ rho,
                                                        const double* __restrict__ s, double eta,
                                                        double* __restrict__ q) {
     for (int64_t e = (int64_t)bid_ * kBlock + threadIdx.x; e < nn; e += (int64_t)nblk_ * kBlock) {
-    const double B = fmax(0.0, -s[e]) * (double)nn;
-    q[e] = rho[e] * (eta == 0.5 ? sqrt(B) : pow(B, eta));
+    q[e] = oc_q(rho[e], s[e], nn, eta);
     }
 }
 
@@ -401,19 +407,19 @@ __global__ void __launch_bounds__(kBlock) k_oc_prepare(int64_t nn, const double*
                                                        const double* __restrict__ s, double eta,
                                                        double* __restrict__ q) { b_oc_prepare(blockIdx.x, gridDim.x, nn, rho, s, eta, q); }
 
-// q as above, plus per block the largest (q_e / lo_e)^(1/eta) -- at or above
-// that lambda every element of the block sits at its lower move limit
-// lo_e = max(rho_min, rho_e - m) -- and the sum of lo_e (partials[2b], [2b+1]).
+// q as above (stored when q is not null), plus per block the largest
+// (q_e / lo_e)^(1/eta) -- at or above that lambda every element of the block
+// sits at its lower move limit lo_e = max(rho_min, rho_e - m) -- and the sum of
+// lo_e (partials[2b], [2b+1]).
 __global__ void __launch_bounds__(kBlock) k_oc_prepare_max(int64_t nn, const double* __restrict__ rho,
                                                            const double* __restrict__ s, double eta, double move,
                                                            double rho_min, double* __restrict__ q,
                                                            double* __restrict__ partials) {
     double tmax = 0.0, losum = 0.0;
     for (int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x; e < nn; e += (int64_t)gridDim.x * kBlock) {
-        const double B = fmax(0.0, -s[e]) * (double)nn;
         const double r = rho[e];
-        const double qe = r * (eta == 0.5 ? sqrt(B) : pow(B, eta));
-        q[e] = qe;
+        const double qe = oc_q(r, s[e], nn, eta);
+        if (q) q[e] = qe;
         const double lo = fmax(rho_min, r - move);
         const double ratio = qe / lo;
         tmax = fmax(tmax, eta == 0.5 ? ratio * ratio : pow(ratio, 1.0 / eta));
@@ -514,6 +520,8 @@ __global__ void __launch_bounds__(kBlock) k_oc_init(Scalars* sc, double vstar_n,
 
 // One pass: sum clamp(q c_m, lo, hi) for every candidate, then walk the tree
 // with the sequential stopping rule (width <= 1e-13 (l1 + l2), 200 halvings).
+// kFromSens: `q` holds the sensitivities s and q_e is recomputed from them.
+template <bool kFromSens = false>
 __device__ __forceinline__ void b_oc_pass(int bid_, int nblk_, int64_t nn, const double* __restrict__ rho,
                                                     const double* __restrict__ q, double move, double rho_min,
                                                     double eta, double* partials, unsigned* counter, Scalars* sc) {
@@ -526,7 +534,7 @@ __device__ __forceinline__ void b_oc_pass(int bid_, int nblk_, int64_t nn, const
     for (int t = 0; t < kOcCands; ++t) acc[t] = 0.0;
 #pragma unroll 2
     for (int64_t e = (int64_t)bid_ * kBlock + threadIdx.x; e < nn; e += (int64_t)nblk_ * kBlock) {
-        const double r = rho[e], qe = q[e];
+        const double r = rho[e], qe = kFromSens ? oc_q(r, q[e], nn, eta) : q[e];
         const double lo = fmax(rho_min, r - move), hi = fmin(1.0, r + move);
 #pragma unroll
         for (int t = 0; t < kOcCands; ++t) acc[t] += fmin(hi, fmax(lo, qe * cp[t]));
@@ -551,6 +559,29 @@ __device__ __forceinline__ void b_oc_apply(int bid_, int nblk_, int64_t nn, doub
 
 __global__ void __launch_bounds__(kBlock) k_oc_apply(int64_t nn, double* __restrict__ rho, const double* __restrict__ q,
                                                      double eta, double move, double rho_min, const Scalars* sc) { b_oc_apply(blockIdx.x, gridDim.x, nn, rho, q, eta, move, rho_min, sc); }
+
+// Pass and update with q recomputed from the sensitivities (no q buffer):
+// the same sums over the same grid as k_oc_pass, so the same lambda.
+__global__ void __launch_bounds__(kBlock) k_oc_pass_s(int64_t nn, const double* __restrict__ rho,
+                                                      const double* __restrict__ s, double move, double rho_min,
+                                                      double eta, double* partials, Scalars* sc) {
+    b_oc_pass<true>(blockIdx.x, gridDim.x, nn, rho, s, move, rho_min, eta, partials, nullptr, sc);
+}
+
+// rho_out may be rho itself (each element is read and written by one thread).
+// lambda_out (device, may be null) receives the multiplier.
+__global__ void __launch_bounds__(kBlock) k_oc_apply_s(int64_t nn, const double* rho, const double* __restrict__ s,
+                                                       double* rho_out, double* __restrict__ lambda_out, double eta,
+                                                       double move, double rho_min, const Scalars* sc) {
+    const double lam = sc->lam;
+    const double c = (eta == 0.5) ? 1.0 / sqrt(lam) : pow(lam, -eta);
+    if (lambda_out && blockIdx.x == 0 && threadIdx.x == 0) *lambda_out = lam;
+    for (int64_t e = (int64_t)blockIdx.x * kBlock + threadIdx.x; e < nn; e += (int64_t)gridDim.x * kBlock) {
+        const double r = rho[e];
+        const double lo = fmax(rho_min, r - move), hi = fmin(1.0, r + move);
+        rho_out[e] = fmin(hi, fmax(lo, oc_q(r, s[e], nn, eta) * c));
+    }
+}
 
 __device__ __forceinline__ void b_clamp(int bid_, int nblk_, int64_t nn, double* __restrict__ rho, double lo, double hi) {
     for (int64_t e = (int64_t)bid_ * kBlock + threadIdx.x; e < nn; e += (int64_t)nblk_ * kBlock) {
@@ -1089,6 +1120,23 @@ void launch_oc_apply(int n, double* rho, const double* q, double eta, double mov
                      const Workspace& ws, hipStream_t s) {
     hipLaunchKernelGGL(k_oc_apply, dim3(nblocks_for(cube(n))), dim3(kBlock), 0, s, cube(n), rho, q, eta, move,
                        rho_min, ws.sc);
+}
+
+void launch_oc_from_sens(int n, const double* rho, const double* sens, double* rho_out, double* lambda_out,
+                         double vstar, double eta, double move, double rho_min, const Workspace& ws,
+                         hipStream_t s) {
+    int prep_blocks = 0;
+    launch_oc_prepare(n, rho, sens, eta, move, rho_min, nullptr, ws, s, &prep_blocks);
+    launch_oc_init(vstar, n, eta, prep_blocks, ws, s);
+    const int g = grid_for(cube(n), ws.max_blocks < 512 ? ws.max_blocks : 512);
+    // every pass the bisection could need; passes after it has stopped return at once
+    for (int pass = 0; pass < kOcMaxPasses; ++pass) {
+        hipLaunchKernelGGL(k_oc_pass_s, dim3(g), dim3(kBlock), 0, s, cube(n), rho, sens, move, rho_min, eta,
+                           ws.partials, ws.sc);
+        launch_finalize(FIN_OC, g, ws, s, cube(n), eta);
+    }
+    hipLaunchKernelGGL(k_oc_apply_s, dim3(grid_for(cube(n), 2048)), dim3(kBlock), 0, s, cube(n), rho, sens, rho_out,
+                       lambda_out, eta, move, rho_min, (const Scalars*)ws.sc);
 }
 
 void launch_sym_central(int n, double* f, hipStream_t s) {

@@ -169,3 +169,28 @@ def test_governor_options_rejected(L, field, value):
     assert L.otm_batch_create(arr, 1, None, None, ctypes.byref(g), None, ctypes.byref(h)) == N.OTM_EINVAL
     b8 = (ctypes.c_double * 8)()
     assert L.otm_batch_get_governor(None, 0, b8) == N.OTM_EINVAL
+
+
+def test_oc_noalloc_validates_before_any_device_call(L):
+    """The allocation-free OC update rejects null buffers, sizes beyond
+    4..1024, V* outside (0, 1], bad options and aliasing on the host, before
+    it looks up its scratch or launches anything (fake non-null addresses are
+    never dereferenced)."""
+    from paper_2405_19991_amd import _native as N
+    oc = N.OcOpts(0.05, 0.5, 1e-3)
+    a, b, c, d = (ctypes.c_void_p(v) for v in (0x1000, 0x2000, 0x3000, 0x4000))
+    f = L.otm_oc_update_noalloc
+    assert f(16, None, b, 0.3, ctypes.byref(oc), c, None, None) == N.OTM_EINVAL
+    assert f(16, a, None, 0.3, ctypes.byref(oc), c, None, None) == N.OTM_EINVAL
+    assert f(16, a, b, 0.3, ctypes.byref(oc), None, None, None) == N.OTM_EINVAL
+    assert f(16, a, b, 0.3, None, c, None, None) == N.OTM_EINVAL
+    for n in (3, 1025, 4096):
+        assert f(n, a, b, 0.3, ctypes.byref(oc), c, None, None) == N.OTM_EINVAL
+    for v in (0.0, -0.1, 1.5, float("nan")):
+        assert f(16, a, b, v, ctypes.byref(oc), c, None, None) == N.OTM_EINVAL
+    for bad in (N.OcOpts(0.0, 0.5, 1e-3), N.OcOpts(0.05, 0.0, 1e-3), N.OcOpts(0.05, 0.5, 0.0),
+                N.OcOpts(0.05, 0.5, 1.0)):
+        assert f(16, a, b, 0.3, ctypes.byref(bad), c, None, None) == N.OTM_EINVAL
+    assert f(16, a, b, 0.3, ctypes.byref(oc), b, None, None) == N.OTM_EINVAL  # out aliases sens
+    assert f(16, a, b, 0.3, ctypes.byref(oc), c, a, None) == N.OTM_EINVAL    # lambda aliases rho
+    assert f(16, a, b, 0.3, ctypes.byref(oc), c, c, None) == N.OTM_EINVAL    # lambda aliases out
