@@ -45,3 +45,74 @@ def test_cell128_tensor_matches_oracle(precision, tol, bar):
     err = np.linalg.norm(np.array(kappa) - k_ref) / np.linalg.norm(k_ref)
     print(f"relative tensor error {err:.3e}", flush=True)
     assert err <= bar
+
+
+@pytest.fixture(scope="module")
+def cell128_shared():
+    """The 128^3 anisotropic cell's density, a shared zero-mean fluctuation
+    field (smoothed noise, three loads; any chi defines the sensitivities) and
+    a dg/dkappa with every component nonzero (diagonal negative, as when the
+    tensor is below its target, so most sensitivities are negative and the
+    OC volume bound is reachable)."""
+    w = synth.config3("fp64")
+    chi = np.stack([synth.smoothed_noise(w.n, -0.5, 0.5, 3100 + l) for l in range(3)])
+    chi -= chi.mean(axis=(1, 2, 3), keepdims=True)
+    wk = np.array([-0.3, -0.2, -0.1, 0.05, -0.02, 0.01])
+    return w, chi, wk
+
+
+def test_cell128_fields_and_sensitivities_from_shared_chi(cell128_shared):
+    """A1, A2 and A7 at full size: filtered density, conductivities, macro
+    loads, element sensitivities and their filter transpose from the same
+    density and the same chi, against the oracle's (filter, SIMP, loads,
+    element energies and the sensitivity formula in FP64), element by element.
+    Bars 1e-12 relative to the field's largest entry (sensitivity row's
+    per-iteration OC/filter bar)."""
+    import oracle as O
+    from paper_2405_19991_amd import Homogenization
+    w, chi, wk = cell128_shared
+    prm = O.Params()
+    print("cell128 shared chi: oracle", flush=True)
+    rhof = O.density_filter(w.rho0, prm.rfilter)
+    k = O.simp(rhof, prm.k0, prm.kmin, prm.penal)
+    b = O.macro_loads(k)
+    b -= b.mean(axis=(1, 2, 3), keepdims=True)
+    st_ref = O.element_sensitivity(rhof, O.element_energies(chi), wk, prm.k0, prm.kmin, prm.penal)
+    s_ref = O.density_filter_T(st_ref, prm.rfilter)
+    print("cell128 shared chi: gpu", flush=True)
+    with Homogenization(w.n, (w.k0, w.kmin), w.target, vf=w.vf, penal=w.penal, filter_radius=w.rfilter) as h:
+        h.set_density(w.rho0)
+        h.prepare()
+        got = {f: h.get_field(f) for f in ("rhof", "k", "b")}
+        h.set_field("chi", chi)
+        s = h.sensitivity(wk)
+        st = h.get_field("sens_elem")
+    for name, ref in (("rhof", rhof), ("k", k), ("b", b)):
+        err = np.abs(got[name] - ref).max() / np.abs(ref).max()
+        assert err <= 1e-12, (name, err)
+    assert np.abs(st - st_ref).max() <= 1e-12 * np.abs(st_ref).max()
+    assert np.abs(s - s_ref).max() <= 1e-12 * np.abs(s_ref).max()
+
+
+@pytest.mark.parametrize("dv", [-0.01, 0.004])
+def test_cell128_oc_from_shared_sensitivities(cell128_shared, dv):
+    """A8 at full size: the OC bisection over 2.1 M elements (1024 / 512
+    reduction blocks, many bisection passes) from the oracle's sensitivities,
+    against the oracle's own bisection: lambda and every rho_new to 1e-12."""
+    import oracle as O
+    from paper_2405_19991_amd import Homogenization
+    w, chi, wk = cell128_shared
+    prm = O.Params()
+    rhof = O.density_filter(w.rho0, prm.rfilter)
+    s = O.density_filter_T(O.element_sensitivity(rhof, O.element_energies(chi), wk, prm.k0, prm.kmin, prm.penal),
+                           prm.rfilter)
+    vstar = float(w.rho0.mean() + dv)
+    rn_ref, lam_ref, steps = O.oc_update(w.rho0, s, vstar)
+    print(f"cell128 OC vstar {vstar:.4f}: oracle lambda {lam_ref:.6e} after {steps} halvings", flush=True)
+    with Homogenization(w.n, (w.k0, w.kmin), w.target, vf=w.vf) as h:
+        h.set_density(w.rho0)
+        h.set_field("sens", s)
+        rn, lam = h.oc_update(vstar)
+    assert lam == pytest.approx(lam_ref, rel=1e-12)
+    assert np.abs(rn - rn_ref).max() <= 1e-12
+    assert abs(rn.mean() - vstar) <= 1e-10
