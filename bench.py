@@ -483,7 +483,7 @@ def main():
     # the operator in the configuration the solver was tuned to, and the best
     # z-march shape for the stand-alone operator
     # (the fused iteration's operator is the two-node z-march)
-    cands = [(0 if tile["variant"] == 4 else tile["variant"], tile["tx"], tile["tz"])]
+    cands = [(0 if tile["variant"] in (4, 5) else tile["variant"], tile["tx"], tile["tz"])]
     for tx in ((32, 64) if n % 2 == 0 else (16, 32, 64)):
         for tz in (4, 5, 6, 8, 16):
             cands.append((0 if n % 2 == 0 else 3, tx, tz))

@@ -52,6 +52,7 @@ extern "C" {
 #define OTM_ENONFINITE (-4) /* NaN or Inf in an input or a result */
 #define OTM_EUNSUPPORTED (-5)
 #define OTM_ESTATE (-6) /* call order violated (e.g. sensitivity before homogenize) */
+#define OTM_EIO (-7)    /* a file could not be opened, read or written, or is malformed */
 
 /* ---- enumerations -------------------------------------------------------- */
 #define OTM_FP64 0  /* every vector and the operator in float64 */
@@ -315,6 +316,24 @@ int otm_set_guess(otm_ctx* ctx, const double* chi_host, int64_t count);
 int otm_get_governor(const otm_ctx* ctx, double state8[8]);
 int otm_set_governor(otm_ctx* ctx, const double state8[8]);
 
+/* Checkpoint / resume of a design run (the optimization loop of Sec. 3.4
+ * interrupted between design iterations): the design density rho, the last
+ * solution chi (the warm start of OTM_GUESS_PREVIOUS; present once a solve
+ * has run) and the adaptive volume bound's state (Algorithm 1, as
+ * otm_get_governor) go to one binary file that this library writes and reads:
+ *   "OTMSTATE" | u32 version 1 | i32 n | u32 flags (bit 0: chi present) |
+ *   u32 0 | f64[11] k0, kmin, penal, filter radius, target[6], objective |
+ *   f64[8] governor state | f64 rho[n^3] | f64 chi[3 n^3] if bit 0 |
+ *   u64 FNV-1a hash of every preceding byte; little-endian.
+ * save writes path.tmp and renames it over path.  load restores all three
+ * into a context created for the same n and problem constants, after which
+ * otm_step continues the interrupted run exactly (same iterates, bit for bit).
+ * Errors: OTM_EINVAL (null or empty path, another n or problem),
+ * OTM_ESTATE (save without a density), OTM_EIO (open/read/write failure,
+ * wrong magic, version, size or checksum), OTM_ENONFINITE, OTM_EDEVICE. */
+int otm_save_state(otm_ctx* ctx, const char* path);
+int otm_load_state(otm_ctx* ctx, const char* path);
+
 /* Matrix-free operator y^i = A x^i for the three loads with the context's
  * current k (needs a prior otm_homogenize or otm_prepare), in the given
  * precision (OTM_FP64 or OTM_MIXED = float32 operator).  x and y are host
@@ -435,6 +454,14 @@ int otm_nn_accumulate(otm_nn* net, int32_t n, const void* rhof_dev, const void* 
 int otm_nn_adam(otm_nn* net, double lr, int32_t batch);
 int otm_nn_zero_grads(otm_nn* net);
 const char* otm_nn_last_error(const otm_nn* net);
+/* Network weights as a file: the compact parameter vector (layout above) as
+ * a NumPy .npy array, dtype '<f4', shape (otm_nn_param_count(),), C order
+ * (format 1.0 written; 1.0-3.0 read).  load replaces the parameters and
+ * resets Adam's step count.  Errors: OTM_EINVAL (null or empty path),
+ * OTM_EIO (open/read/write failure, not .npy, another dtype, order, shape or
+ * size), OTM_ENONFINITE (a non-finite weight), OTM_EDEVICE. */
+int otm_nn_save(otm_nn* net, const char* path);
+int otm_nn_load(otm_nn* net, const char* path);
 /* Attach a network to a context for OTM_GUESS_LEARNED (NULL detaches).  The
  * context does not own it. */
 int otm_set_network(otm_ctx* ctx, otm_nn* net);

@@ -20,6 +20,7 @@ OTM_EDEVICE = -3
 OTM_ENONFINITE = -4
 OTM_EUNSUPPORTED = -5
 OTM_ESTATE = -6
+OTM_EIO = -7
 
 OTM_FP64 = 0
 OTM_MIXED = 1
@@ -55,6 +56,7 @@ EXPORTED = [
     "otm_nn_get_grads", "otm_nn_forward", "otm_nn_accumulate", "otm_nn_adam", "otm_nn_zero_grads",
     "otm_nn_last_error", "otm_set_network", "otm_init_density", "otm_apply_device_tiled", "otm_device_bytes",
     "otm_batch_device_bytes", "otm_batch_get_governor", "otm_oc_update_noalloc",
+    "otm_save_state", "otm_load_state", "otm_nn_save", "otm_nn_load",
 ]
 
 
@@ -177,6 +179,10 @@ def lib():
         "otm_nn_zero_grads": ([vp], ctypes.c_int),
         "otm_nn_last_error": ([vp], ctypes.c_char_p),
         "otm_set_network": ([vp, vp], ctypes.c_int),
+        "otm_save_state": ([ctx, ctypes.c_char_p], ctypes.c_int),
+        "otm_load_state": ([ctx, ctypes.c_char_p], ctypes.c_int),
+        "otm_nn_save": ([vp, ctypes.c_char_p], ctypes.c_int),
+        "otm_nn_load": ([vp, ctypes.c_char_p], ctypes.c_int),
     }
     for name, (args, res) in sig.items():
         f = getattr(L, name)

@@ -222,16 +222,13 @@ class Homogenization:
         self._chk(self._L.otm_set_governor(self._h, _ptr(a)))
 
     def save_state(self, path: str) -> None:
-        """Checkpoint: density, previous solution (warm start) and governor state."""
-        np.savez(path, rho=self.get_field("rho"), chi=self.get_field("chi"),
-                 governor=np.array(self.governor_state()))
+        """Checkpoint (otm_save_state): density, last solution (warm start)
+        and governor state in the library's binary state file."""
+        self._chk(self._L.otm_save_state(self._h, str(path).encode()))
 
     def load_state(self, path: str) -> None:
-        d = np.load(path, allow_pickle=False)
-        self.set_density(d["rho"])
-        self.set_governor_state(d["governor"])
-        if self.solver.guess != N.OTM_GUESS_ZERO:
-            self.set_guess(d["chi"])
+        """Resume from a file written by save_state (otm_load_state)."""
+        self._chk(self._L.otm_load_state(self._h, str(path).encode()))
 
 
 def _operator_args(k, x, y, precision: str, stream):
@@ -448,6 +445,12 @@ class Network:
             raise N.OTMError(status, self._L.otm_strerror(status).decode() + " (" +
                              self._L.otm_nn_last_error(self._h).decode() + ")")
 
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
     def close(self):
         if getattr(self, "_h", None):
             self._L.otm_nn_destroy(self._h)
@@ -499,10 +502,12 @@ class Network:
         self._chk(self._L.otm_nn_zero_grads(self._h))
 
     def save(self, path: str) -> None:
-        np.save(path, self.params())
+        """Weights as a float32 .npy file (otm_nn_save)."""
+        self._chk(self._L.otm_nn_save(self._h, str(path).encode()))
 
     def load(self, path: str) -> None:
-        self.set_params(np.load(path, allow_pickle=False))
+        """Weights from a float32 .npy file (otm_nn_load)."""
+        self._chk(self._L.otm_nn_load(self._h, str(path).encode()))
 
 
 def compact_to_layers(a: np.ndarray, channels=(1, 16, 16, 16, 16, 3)):

@@ -1077,6 +1077,7 @@ const char* otm_strerror(int s) {
         case OTM_ENONFINITE: return "non-finite value";
         case OTM_EUNSUPPORTED: return "unsupported";
         case OTM_ESTATE: return "call order violated";
+        case OTM_EIO: return "file could not be opened, read or written, or is malformed";
         default: return "unknown status";
     }
 }
@@ -1451,6 +1452,136 @@ int otm_set_governor(otm_ctx* c, const double s[8]) {
     c->vb.g_prev = s[4];
     c->vb.flat = (int)s[5];
     c->iter = (int)s[6];
+    return OTM_OK;
+}
+
+// ---- checkpoint / resume -----------------------------------------------------
+// A design run's state, in one little-endian binary file written here:
+//   "OTMSTATE" | u32 version 1 | i32 n | u32 flags (bit 0: solution present) |
+//   u32 0 | f64 problem[11] (k0, kmin, penal, filter radius, target[6],
+//   objective) | f64 governor[8] (as otm_get_governor) | f64 rho[n^3] |
+//   f64 chi[3 n^3] if bit 0 | u64 FNV-1a hash of every preceding byte.
+// The file is written under path.tmp and renamed over path, so a crash while
+// saving leaves any earlier checkpoint whole.
+namespace {
+
+const char kStateMagic[8] = {'O', 'T', 'M', 'S', 'T', 'A', 'T', 'E'};
+constexpr uint32_t kStateVersion = 1;
+
+struct Fnv1a {
+    uint64_t h = 1469598103934665603ull;
+    void add(const void* p, size_t len) {
+        const unsigned char* b = (const unsigned char*)p;
+        for (size_t i = 0; i < len; ++i) {
+            h ^= b[i];
+            h *= 1099511628211ull;
+        }
+    }
+};
+
+void problem_signature(const otm_problem& p, double out[11]) {
+    out[0] = p.k0;
+    out[1] = p.kmin;
+    out[2] = p.penal;
+    out[3] = p.filter_radius;
+    for (int q = 0; q < 6; ++q) out[4 + q] = p.target[q];
+    out[10] = (double)p.objective;
+}
+
+}  // namespace
+
+int otm_save_state(otm_ctx* c, const char* path) {
+    if (!c || !path || !path[0]) return OTM_EINVAL;
+    if (!c->have_density) return fail(c, OTM_ESTATE, "no density to save");
+    std::vector<double> rho((size_t)c->nn), chi;
+    HIPCHK(c, hipMemcpyAsync(rho.data(), c->rho, (size_t)c->nn * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    if (c->have_solution) {
+        chi.resize((size_t)(3 * c->nn));
+        HIPCHK(c, hipMemcpyAsync(chi.data(), c->x, chi.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    }
+    HIPCHK(c, hipStreamSynchronize(c->stream));
+    const uint32_t version = kStateVersion, flags = c->have_solution ? 1u : 0u, zero = 0u;
+    const int32_t n = c->n;
+    double sig[11], gov[8];
+    problem_signature(c->prob, sig);
+    otm_get_governor(c, gov);
+    const std::string tmp = std::string(path) + ".tmp";
+    FILE* f = std::fopen(tmp.c_str(), "wb");
+    if (!f) return fail(c, OTM_EIO, "cannot open " + tmp + " for writing");
+    Fnv1a h;
+    bool ok = true;
+    auto put = [&](const void* p, size_t len) {
+        if (!ok || len == 0) return;
+        h.add(p, len);
+        ok = std::fwrite(p, 1, len, f) == len;
+    };
+    put(kStateMagic, 8);
+    put(&version, 4);
+    put(&n, 4);
+    put(&flags, 4);
+    put(&zero, 4);
+    put(sig, sizeof(sig));
+    put(gov, sizeof(gov));
+    put(rho.data(), rho.size() * sizeof(double));
+    put(chi.data(), chi.size() * sizeof(double));
+    const uint64_t digest = h.h;
+    ok = ok && std::fwrite(&digest, 1, 8, f) == 8;
+    ok = (std::fclose(f) == 0) && ok;
+    if (!ok || std::rename(tmp.c_str(), path) != 0) {
+        std::remove(tmp.c_str());
+        return fail(c, OTM_EIO, std::string("cannot write ") + path);
+    }
+    return OTM_OK;
+}
+
+int otm_load_state(otm_ctx* c, const char* path) {
+    if (!c || !path || !path[0]) return OTM_EINVAL;
+    FILE* f = std::fopen(path, "rb");
+    if (!f) return fail(c, OTM_EIO, std::string("cannot open ") + path);
+    std::vector<unsigned char> buf;
+    unsigned char chunk[1 << 16];
+    size_t got;
+    while ((got = std::fread(chunk, 1, sizeof(chunk), f)) > 0) buf.insert(buf.end(), chunk, chunk + got);
+    const bool read_err = std::ferror(f) != 0;
+    std::fclose(f);
+    if (read_err) return fail(c, OTM_EIO, std::string("cannot read ") + path);
+    const size_t head = 8 + 4 * 4 + 11 * 8 + 8 * 8;
+    if (buf.size() < head + 8 || std::memcmp(buf.data(), kStateMagic, 8) != 0)
+        return fail(c, OTM_EIO, std::string(path) + " is not a state file");
+    uint32_t version, flags;
+    int32_t n;
+    std::memcpy(&version, &buf[8], 4);
+    std::memcpy(&n, &buf[12], 4);
+    std::memcpy(&flags, &buf[16], 4);
+    if (version != kStateVersion) return fail(c, OTM_EIO, "unsupported state file version");
+    if (n != c->n) return fail(c, OTM_EINVAL, "state file holds another resolution");
+    const size_t body = (size_t)c->nn * sizeof(double) * ((flags & 1u) ? 4 : 1);
+    if (buf.size() != head + body + 8) return fail(c, OTM_EIO, "state file size does not match its header");
+    Fnv1a h;
+    h.add(buf.data(), head + body);
+    uint64_t digest;
+    std::memcpy(&digest, &buf[head + body], 8);
+    if (digest != h.h) return fail(c, OTM_EIO, "state file checksum mismatch");
+    double sig[11], mine[11], gov[8];
+    std::memcpy(sig, &buf[24], sizeof(sig));
+    std::memcpy(gov, &buf[24 + sizeof(sig)], sizeof(gov));
+    problem_signature(c->prob, mine);
+    if (std::memcmp(sig, mine, sizeof(sig)) != 0)
+        return fail(c, OTM_EINVAL, "state file was written for another problem (constants, target or objective)");
+    std::vector<double> vals((size_t)(body / sizeof(double)));
+    std::memcpy(vals.data(), &buf[head], body);
+    for (double v : vals)
+        if (!std::isfinite(v)) return fail(c, OTM_ENONFINITE, "non-finite value in state file");
+    int rc = otm_set_governor(c, gov);
+    if (rc) return rc;
+    HIPCHK(c, hipMemcpyAsync(c->rho, vals.data(), (size_t)c->nn * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    if (flags & 1u)
+        HIPCHK(c, hipMemcpyAsync(c->x, vals.data() + c->nn, (size_t)(3 * c->nn) * sizeof(double),
+                                 hipMemcpyHostToDevice, c->stream));
+    rc = set_density_common(c);  // synchronises the stream, so vals may go
+    if (rc) return rc;
+    c->have_solution = (flags & 1u) != 0;
+    c->have_user_guess = false;
     return OTM_OK;
 }
 

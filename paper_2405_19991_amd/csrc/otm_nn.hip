@@ -643,4 +643,78 @@ int otm_nn_zero_grads(otm_nn* c) {
 
 const char* otm_nn_last_error(const otm_nn* c) { return c ? c->err.c_str() : "null network"; }
 
+// Weights file: the compact parameter vector as a NumPy .npy array (format
+// 1.0: magic, version, header length, a Python-literal header dict, then the
+// raw little-endian float32 values), so that numpy.load reads it too.
+int otm_nn_save(otm_nn* c, const char* path) {
+    if (!c || !path || !path[0]) return OTM_EINVAL;
+    const int64_t count = compact_count();
+    std::vector<float> w((size_t)count);
+    int rc = otm_nn_get_params(c, w.data(), count);
+    if (rc) return rc;
+    std::string hdr = "{'descr': '<f4', 'fortran_order': False, 'shape': (" + std::to_string(count) + ",), }";
+    const size_t pre = 6 + 2 + 2;  // magic, version, header length
+    while ((pre + hdr.size() + 1) % 64 != 0) hdr += ' ';
+    hdr += '\n';
+    const unsigned char magic[8] = {0x93, 'N', 'U', 'M', 'P', 'Y', 1, 0};
+    const uint16_t hlen = (uint16_t)hdr.size();
+    const std::string tmp = std::string(path) + ".tmp";
+    FILE* f = std::fopen(tmp.c_str(), "wb");
+    if (!f) return nn_fail(c, OTM_EIO, "cannot open " + tmp + " for writing");
+    bool ok = std::fwrite(magic, 1, 8, f) == 8 && std::fwrite(&hlen, 1, 2, f) == 2 &&
+              std::fwrite(hdr.data(), 1, hdr.size(), f) == hdr.size() &&
+              std::fwrite(w.data(), sizeof(float), w.size(), f) == w.size();
+    ok = (std::fclose(f) == 0) && ok;
+    if (!ok || std::rename(tmp.c_str(), path) != 0) {
+        std::remove(tmp.c_str());
+        return nn_fail(c, OTM_EIO, std::string("cannot write ") + path);
+    }
+    return OTM_OK;
+}
+
+int otm_nn_load(otm_nn* c, const char* path) {
+    if (!c || !path || !path[0]) return OTM_EINVAL;
+    FILE* f = std::fopen(path, "rb");
+    if (!f) return nn_fail(c, OTM_EIO, std::string("cannot open ") + path);
+    std::vector<unsigned char> buf;
+    unsigned char chunk[1 << 16];
+    size_t got;
+    while ((got = std::fread(chunk, 1, sizeof(chunk), f)) > 0) buf.insert(buf.end(), chunk, chunk + got);
+    const bool read_err = std::ferror(f) != 0;
+    std::fclose(f);
+    if (read_err) return nn_fail(c, OTM_EIO, std::string("cannot read ") + path);
+    static const unsigned char magic[6] = {0x93, 'N', 'U', 'M', 'P', 'Y'};
+    if (buf.size() < 10 || std::memcmp(buf.data(), magic, 6) != 0)
+        return nn_fail(c, OTM_EIO, std::string(path) + " is not a .npy file");
+    size_t hlen, hoff;
+    if (buf[6] == 1) {
+        hlen = (size_t)buf[8] | ((size_t)buf[9] << 8);
+        hoff = 10;
+    } else if ((buf[6] == 2 || buf[6] == 3) && buf.size() >= 12) {
+        hlen = (size_t)buf[8] | ((size_t)buf[9] << 8) | ((size_t)buf[10] << 16) | ((size_t)buf[11] << 24);
+        hoff = 12;
+    } else {
+        return nn_fail(c, OTM_EIO, "unsupported .npy version");
+    }
+    if (buf.size() < hoff + hlen) return nn_fail(c, OTM_EIO, "truncated .npy header");
+    std::string hdr(buf.begin() + hoff, buf.begin() + hoff + hlen);
+    std::string compact;
+    for (char ch : hdr)
+        if (ch != ' ') compact += ch;
+    const int64_t count = compact_count();
+    if (compact.find("'descr':'<f4'") == std::string::npos)
+        return nn_fail(c, OTM_EIO, "weights must be little-endian float32 ('<f4')");
+    if (compact.find("'fortran_order':False") == std::string::npos)
+        return nn_fail(c, OTM_EIO, "weights must be in C order");
+    const std::string shape1 = "'shape':(" + std::to_string(count) + ",)";
+    if (compact.find(shape1) == std::string::npos)
+        return nn_fail(c, OTM_EIO, "weights must be a 1-D array of " + std::to_string(count) + " values");
+    const size_t data = hoff + hlen;
+    if (buf.size() != data + (size_t)count * sizeof(float))
+        return nn_fail(c, OTM_EIO, "weights file size does not match its header");
+    std::vector<float> w((size_t)count);
+    std::memcpy(w.data(), &buf[data], (size_t)count * sizeof(float));
+    return otm_nn_set_params(c, w.data(), count);
+}
+
 }  // extern "C"

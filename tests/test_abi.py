@@ -38,7 +38,7 @@ def test_exports_match_header(L):
 
 def test_version_and_strerror(L):
     assert b"gfx950" in L.otm_version()
-    for code in (0, 1, -1, -2, -3, -4, -5, -6):
+    for code in (0, 1, -1, -2, -3, -4, -5, -6, -7):
         assert L.otm_strerror(code)
     assert L.otm_strerror(99) == b"unknown status"
 
