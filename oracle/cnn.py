@@ -13,6 +13,17 @@ with tap t = 9 (dz+1) + 3 (dy+1) + (dx+1).  Loss: mean over every value of
 (out - chi)^2 with both sides mean-removed per channel.
 
 Nothing here is shared with the HIP path; arrays are float64 numpy.
+
+Two modes.  The exact mode (net_forward / net_backward) is the network in
+float64.  The bf16 mode (net_forward_bf16 / net_backward_bf16) applies the
+rounding a bf16 implementation with float32 parameters must apply, at the
+points where such an implementation stores bf16 values: the input density
+(via float32), the weights, each ReLU activation, the loss gradient and
+each masked input gradient, every rounding to nearest-even in bf16 (the top
+16 bits of a float32); products and sums stay exact (float64), biases and
+the last layer's output are not rounded.  It is the reference for comparing
+a bf16 implementation element by element: only its accumulation order and
+width differ from this.
 """
 from __future__ import annotations
 
@@ -30,24 +41,27 @@ def shift(x: np.ndarray, dz: int, dy: int, dx: int) -> np.ndarray:
 
 
 def conv3_fwd(x: np.ndarray, W: np.ndarray, b: np.ndarray) -> np.ndarray:
-    """x: (Cin, N, N, N); W: (Cout, Cin, 27); b: (Cout,) -> (Cout, N, N, N)."""
-    y = np.zeros((W.shape[0],) + x.shape[1:])
+    """x: (Cin, N, N, N); W: (Cout, Cin, 27); b: (Cout,) -> (Cout, N, N, N).
+    Per tap, the channel mixing is a (Cout x Cin) by (Cin x N^3) matrix product."""
+    cin = x.shape[0]
+    y = np.zeros((W.shape[0], x[0].size))
     for t, (dz, dy, dx) in enumerate(TAPS):
-        y += np.einsum("oc,czyx->ozyx", W[:, :, t], shift(x, dz, dy, dx))
-    return y + b[:, None, None, None]
+        y += W[:, :, t] @ shift(x, dz, dy, dx).reshape(cin, -1)
+    return y.reshape((W.shape[0],) + x.shape[1:]) + b[:, None, None, None]
 
 
 def conv3_bwd(x: np.ndarray, W: np.ndarray, dy: np.ndarray) -> Tuple[np.ndarray, np.ndarray, np.ndarray]:
     """Gradients of sum(dy * conv3_fwd(x, W, b)) w.r.t. x, W and b."""
-    dx = np.zeros_like(x)
+    cin, cout = x.shape[0], dy.shape[0]
+    dx = np.zeros((cin, x[0].size))
     dW = np.zeros_like(W)
+    dyf = dy.reshape(cout, -1)
     for t, (dz, dyy, dxx) in enumerate(TAPS):
-        xs = shift(x, dz, dyy, dxx)
-        dW[:, :, t] = np.einsum("ozyx,czyx->oc", dy, xs)
+        dW[:, :, t] = dyf @ shift(x, dz, dyy, dxx).reshape(cin, -1).T
         # x[c, v + d] receives W[o, c, t] dy[o, v]  ->  dx[c, u] += W dy[o, u - d]
-        dx += np.einsum("oc,ozyx->czyx", W[:, :, t], shift(dy, -dz, -dyy, -dxx))
-    db = dy.sum(axis=(1, 2, 3))
-    return dx, dW, db
+        dx += W[:, :, t].T @ shift(dy, -dz, -dyy, -dxx).reshape(cout, -1)
+    db = dyf.sum(axis=1)
+    return dx.reshape(x.shape), dW, db
 
 
 def init_params(seed: int, channels: List[int] = CHANNELS) -> List[Dict[str, np.ndarray]]:
@@ -92,3 +106,79 @@ def loss(out: np.ndarray, chi: np.ndarray) -> Tuple[float, np.ndarray]:
     tgt = chi - chi.mean(axis=(1, 2, 3), keepdims=True)
     d = out - tgt
     return float(np.mean(d * d)), 2.0 * d / d.size
+
+
+# ----------------------------------------------------------------- bf16 mode
+
+def bf16(a) -> np.ndarray:
+    """Round to bf16 through float32: the float32 value's upper 16 bits,
+    rounded to nearest with ties to even (IEEE rounding of the 24-bit
+    significand to 8 bits); returned as float64 (exact)."""
+    f = np.ascontiguousarray(np.asarray(a, dtype=np.float64).astype(np.float32))
+    u = f.view(np.uint32).astype(np.uint64)
+    keep = (u >> 16) & 1
+    u = (u + 0x7FFF + keep) >> 16
+    return (u.astype(np.uint32) << 16).view(np.float32).astype(np.float64)
+
+
+def net_forward_bf16(params, rhof: np.ndarray):
+    """The network with a bf16 implementation's rounding (module docstring):
+    rhof (N, N, N) -> (out mean-removed (3, N, N, N), acts).  acts[l] is the
+    bf16 input of layer l; acts[-1] the last layer's unrounded output."""
+    acts = [bf16(rhof)[None]]
+    h = acts[0]
+    for li, p in enumerate(params):
+        h = conv3_fwd(h, bf16(p["W"]), np.asarray(p["b"], dtype=np.float32).astype(np.float64))
+        if li < len(params) - 1:
+            h = bf16(np.maximum(h, 0.0))
+        acts.append(h)
+    out = h - h.mean(axis=(1, 2, 3), keepdims=True)
+    return out, acts
+
+
+def loss_bf16(out: np.ndarray, chi: np.ndarray) -> Tuple[float, np.ndarray]:
+    """As loss(), with dL/dout rounded to bf16."""
+    L, d = loss(out, chi)
+    return L, bf16(d)
+
+
+def net_backward_bf16(params, acts, dout: np.ndarray):
+    """Gradients of sum(dout * out) with the bf16 weights; each layer's
+    masked input gradient is rounded to bf16 before it feeds the layer
+    below.  dout is taken as given (zero mean per channel is assumed, as
+    loss() returns)."""
+    g = dout
+    grads = [None] * len(params)
+    for li in range(len(params) - 1, -1, -1):
+        dx, dW, db = conv3_bwd(acts[li], bf16(params[li]["W"]), g)
+        grads[li] = {"W": dW, "b": db}
+        if li > 0:
+            g = bf16(dx * (acts[li] > 0.0))
+    return grads
+
+
+def net_forward_bf16_at(params, rhof: np.ndarray, voxels) -> np.ndarray:
+    """The bf16-mode network's last-layer output before the mean removal at
+    the given voxels (list of (z, y, x)), each from its own receptive field:
+    the periodic (2L+1)^3 window of the input around the voxel (L layers),
+    then L unpadded 3x3x3 correlations, each shrinking the window by one
+    voxel per side, with the same rounding as net_forward_bf16.  -> (K, 3)."""
+    L = len(params)
+    n = rhof.shape[0]
+    r = np.arange(-L, L + 1)
+    out = []
+    for (z, y, x) in voxels:
+        idx = np.ix_((z + r) % n, (y + r) % n, (x + r) % n)
+        h = bf16(rhof[idx])[None]
+        for li, p in enumerate(params):
+            w = h.shape[1] - 2
+            acc = np.zeros((p["W"].shape[0], w ** 3))
+            Wb = bf16(p["W"])
+            for t, (dz, dy, dx) in enumerate(TAPS):
+                xs = h[:, 1 + dz:1 + dz + w, 1 + dy:1 + dy + w, 1 + dx:1 + dx + w].reshape(h.shape[0], -1)
+                acc += Wb[:, :, t] @ xs
+            h = acc.reshape((-1, w, w, w)) + np.asarray(p["b"], dtype=np.float32).astype(np.float64)[:, None, None, None]
+            if li < L - 1:
+                h = bf16(np.maximum(h, 0.0))
+        out.append(h[:, 0, 0, 0])
+    return np.array(out)

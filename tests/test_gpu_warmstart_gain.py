@@ -6,6 +6,10 @@ of seed 209), using the committed weights.
 The prediction is scaled by the energy-minimising factor before use, so its
 energy-norm error is at most the zero start's; the test asserts that it is
 used and costs no more iterations than the zero start, and prints the gain.
+Because that scaling makes any output harmless, the prediction itself is
+checked too: its relative L2 error against the converged fields is below 1
+(closer than zero), and the scaled prediction's energy-norm error
+||s x - chi||_A / ||chi||_A is below 0.99 (a random field gives ~1).
 """
 import os
 
@@ -33,6 +37,34 @@ def net():
     nw.close()
 
 
+def prediction_errors(n, rho, target, vf, net):
+    """(relative L2 error of the raw prediction, relative energy-norm error
+    of the prediction scaled by s = b.x / x.A x, per load) against the
+    fields of a tight float64 solve."""
+    import numpy as np
+    import torch
+    from paper_2405_19991_amd import Homogenization
+    with Homogenization(n, (1.0, 1e-3), target, vf=vf, tol=1e-10) as h:
+        h.set_density(rho)
+        h.homogenize()
+        chi = h.get_field("chi")
+        b = h.get_field("b")
+        rf = torch.from_numpy(h.get_field("rhof").reshape(-1).copy()).cuda()
+        x0 = torch.empty(3 * n ** 3, dtype=torch.float64, device="cuda")
+        net.forward(rf, x0)
+        torch.cuda.synchronize()
+        x = x0.cpu().numpy().reshape(3, n, n, n)
+        ax = h.apply(x).reshape(3, n, n, n)
+    l2, en = [], []
+    for l in range(3):
+        l2.append(float(np.linalg.norm(x[l] - chi[l]) / np.linalg.norm(chi[l])))
+        xax, bx, bchi = float(np.sum(x[l] * ax[l])), float(np.sum(b[l] * x[l])), float(np.sum(b[l] * chi[l]))
+        s = max(bx, 0.0) / xax
+        # ||s x - chi||_A^2 = s^2 x.Ax - 2 s b.x + chi.b  (A chi = b)
+        en.append(float(np.sqrt(max(s * s * xax - 2 * s * bx + bchi, 0.0) / bchi)))
+    return l2, en
+
+
 def iterations(n, rho, target, vf, guess, net=None):
     from paper_2405_19991_amd import Homogenization
     with Homogenization(n, (1.0, 1e-3), target, vf=vf, tol=1e-6, precision="mixed", guess=guess) as h:
@@ -57,3 +89,7 @@ def test_trained_network_gain(net, case):
           f"({100.0 * (it_zero - it_learned) / it_zero:.1f} % fewer)", flush=True)
     assert used == 1.0
     assert it_learned <= it_zero
+    l2, en = prediction_errors(n, rho, tgt, vf, net)
+    print(f"{case}: prediction relative L2 error per load {[f'{e:.3f}' for e in l2]}, scaled energy-norm "
+          f"error {[f'{e:.3f}' for e in en]} (zero start: 1)", flush=True)
+    assert max(l2) < 1.0 and max(en) < 0.99
