@@ -172,6 +172,13 @@ typedef struct {
                                coarse correction on the finest level, 1..8 (default 1) */
     int32_t mg_coarse_sweeps; /* the same on the coarser levels, 0..8; 0 = mg_sweeps
                                  (default 2) */
+    int32_t stall_window;   /* stagnation: a solve stops when no active load's best
+                               recursive residual norm has halved within this many
+                               of its iterations (or a residual is not finite);
+                               0 = automatic, 200 + 10 n.  A stalled OTM_MIXED solve
+                               continues in float64 (two-pass Jacobi-PCG) from its
+                               solution, or from zero after a non-finite residual;
+                               a stalled float64 solve returns OTM_NOT_CONVERGED */
 } otm_solver_opts;
 
 typedef struct {
@@ -204,6 +211,8 @@ typedef struct {
     int32_t converged;      /* 1 when every load met tol */
     int32_t refreshes;      /* OTM_MIXED: float64 residual refreshes */
     double ms_solve;        /* wall time of the three solves, milliseconds */
+    int32_t stalled;        /* 0; 1 the (last) solve stagnated, 2 its residual was not finite */
+    int32_t fallback;       /* 1 when a mixed-precision solve finished in float64 */
 } otm_solve_stats;
 
 typedef struct {

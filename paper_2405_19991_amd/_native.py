@@ -72,7 +72,7 @@ class SolverOpts(ctypes.Structure):
                 ("max_iter", ctypes.c_int32), ("check_every", ctypes.c_int32), ("reliable_delta", ctypes.c_double),
                 ("kernel_variant", ctypes.c_int32), ("tile_tz", ctypes.c_int32), ("tile_tx", ctypes.c_int32),
                 ("autotune", ctypes.c_int32), ("preconditioner", ctypes.c_int32), ("mg_sweeps", ctypes.c_int32),
-                ("mg_coarse_sweeps", ctypes.c_int32)]
+                ("mg_coarse_sweeps", ctypes.c_int32), ("stall_window", ctypes.c_int32)]
 
 
 class OcOpts(ctypes.Structure):
@@ -87,7 +87,8 @@ class GovernorOpts(ctypes.Structure):
 
 class SolveStats(ctypes.Structure):
     _fields_ = [("iterations", ctypes.c_int32 * 3), ("rel_residual", ctypes.c_double * 3),
-                ("converged", ctypes.c_int32), ("refreshes", ctypes.c_int32), ("ms_solve", ctypes.c_double)]
+                ("converged", ctypes.c_int32), ("refreshes", ctypes.c_int32), ("ms_solve", ctypes.c_double),
+                ("stalled", ctypes.c_int32), ("fallback", ctypes.c_int32)]
 
 
 class IterRecord(ctypes.Structure):

@@ -49,7 +49,8 @@ class Homogenization:
                  reliable_delta: Optional[float] = None, move: float = 0.05, eta: float = 0.5, rho_min: float = 1e-3,
                  governor: Optional[Dict[str, float]] = None, stream=None, kernel_variant: int = 0,
                  tile_tz: int = 0, tile_tx: int = 0, autotune: bool = True, preconditioner: str = "jacobi",
-                 mg_sweeps: int = 1, mg_coarse_sweeps: int = 2, objective: str = "mse", symmetry: str = "none"):
+                 mg_sweeps: int = 1, mg_coarse_sweeps: int = 2, objective: str = "mse", symmetry: str = "none",
+                 stall_window: int = 0):
         L = N.lib()
         self.n = int(n)
         p = N.Problem()
@@ -75,6 +76,7 @@ class Homogenization:
         s.autotune = int(bool(autotune))
         s.preconditioner = {"jacobi": N.OTM_PRECOND_JACOBI, "mg": N.OTM_PRECOND_MG}[preconditioner]
         s.mg_sweeps, s.mg_coarse_sweeps = int(mg_sweeps), int(mg_coarse_sweeps)
+        s.stall_window = int(stall_window)
         o.move, o.eta, o.rho_min = float(move), float(eta), float(rho_min)
         for key, val in (governor or {}).items():
             setattr(g, key, val)
@@ -139,7 +141,7 @@ class Homogenization:
         status = self._chk(self._L.otm_homogenize(self._h, _ptr(kappa), ctypes.byref(st)))
         return kappa, dict(iterations=list(st.iterations), rel_residual=list(st.rel_residual),
                            converged=bool(st.converged), refreshes=st.refreshes, ms_solve=st.ms_solve,
-                           status=status)
+                           status=status, stalled=st.stalled, fallback=bool(st.fallback))
 
     def sensitivity(self, dg_dkappa) -> np.ndarray:
         w = _f64(dg_dkappa)

@@ -262,6 +262,51 @@ int max_iters(const Scalars* s) {
     return m;
 }
 
+// Stagnation and divergence watch over the host checks of one solve: the
+// best recursive residual of every active load must halve (its square drop
+// to a quarter) within `window` iterations of that load; a non-finite
+// residual is divergence.  The mixed-precision paths' recursive residual is
+// refreshed from the float64 one, so a float32 recursion that has lost
+// touch with the true residual stops improving the best value and trips it.
+struct SolveWatch {
+    double best[3] = {0, 0, 0};
+    int at[3] = {0, 0, 0};
+    int window = 0;
+    int verdict = 0;  // 0 running, 1 stalled, 2 non-finite residual
+    void start(const Scalars* s, int w) {
+        window = w;
+        verdict = 0;
+        for (int l = 0; l < 3; ++l) {
+            best[l] = s->rr[l];
+            at[l] = s->iters[l];
+        }
+    }
+    // true when the solve should stop
+    bool stop(const Scalars* s) {
+        bool stuck = false;
+        for (int l = 0; l < 3; ++l) {
+            if (!s->active[l]) continue;
+            if (!std::isfinite(s->rr[l])) {
+                verdict = 2;
+                return true;
+            }
+            if (s->rr[l] <= 0.25 * best[l]) {
+                best[l] = s->rr[l];
+                at[l] = s->iters[l];
+            } else if (s->iters[l] - at[l] > window) {
+                stuck = true;
+            }
+        }
+        if (stuck) verdict = 1;
+        return stuck;
+    }
+};
+
+// Iterations without progress before a solve counts as stagnant.
+int stall_window(const otm_ctx* c) {
+    return c->so.stall_window > 0 ? c->so.stall_window : 200 + 10 * c->n;
+}
+
 // Reset the solver part of the scalar block (the fields before sum_rho) and
 // set tol^2; the reduction results of prepare() that follow are left intact.
 int reset_solver_scalars(otm_ctx* c) {
@@ -314,6 +359,8 @@ int solve_fused(otm_ctx* c, bool x_zero, bool mixed, const FusedBufs<T>& B, otm_
     double rr_ref[3] = {c->h_sc->rr_true[0], c->h_sc->rr_true[1], c->h_sc->rr_true[2]};
     const double d2 = c->so.reliable_delta * c->so.reliable_delta;
     int refreshes = 0, launches = 0;
+    SolveWatch watch;
+    watch.start(c->h_sc, stall_window(c));
     while (!all_inactive(c->h_sc) && max_iters(c->h_sc) < c->so.max_iter) {
         const bool all = all_active(c->h_sc);
         bool sampled = false;
@@ -351,8 +398,11 @@ int solve_fused(otm_ctx* c, bool x_zero, bool mixed, const FusedBufs<T>& B, otm_
             for (int l = 0; l < 3; ++l) rr_ref[l] = c->h_sc->rr_true[l];
             if (mixed) ++refreshes;
         }
+        if (watch.stop(c->h_sc)) break;
     }
     if (mixed) launch_accumulate(n, c->x, c->x32, c->stream);
+    // a stopped solve reports the true residual of the solution it returns
+    if (watch.verdict) launch_residual_f<T>(n, c->k, c->b, c->x, B.r[cur], B.q[cur], B.dinv, false, 0, w, c->stream);
     launch_sum3(n, c->x, 0, w, c->stream);
     launch_sub_mean3(n, c->x, 0, w, c->stream);
     if ((rc = check_launch(c, "project"))) return rc;
@@ -363,6 +413,7 @@ int solve_fused(otm_ctx* c, bool x_zero, bool mixed, const FusedBufs<T>& B, otm_
     }
     st->converged = all_inactive(c->h_sc) ? 1 : 0;
     st->refreshes = refreshes;
+    st->stalled = watch.verdict;
     c->timings[7] = (double)launches;
     return OTM_OK;
 }
@@ -385,6 +436,8 @@ int solve_mg64(otm_ctx* c, bool x_zero, otm_solve_stats* st) {
     int launches = 0;
     bool restart = true;
     const int check = c->so.check_every < 2 ? c->so.check_every : 2;
+    SolveWatch watch;
+    watch.start(c->h_sc, stall_window(c));
     while (!all_inactive(c->h_sc) && max_iters(c->h_sc) < c->so.max_iter) {
         const bool all = all_active(c->h_sc);
         bool sampled = false;
@@ -417,7 +470,11 @@ int solve_mg64(otm_ctx* c, bool x_zero, otm_solve_stats* st) {
             if ((rc = sync_scalars(c))) return rc;
             restart = true;
         }
+        if (watch.stop(c->h_sc)) break;
     }
+    // a stopped solve reports the true residual of the solution it returns
+    if (watch.verdict)
+        launch_residual<double>(n, c->k, c->b, c->x, c->r64, c->p64[c->pbuf], c->dinv, RES_START, 0, w, c->stream);
     launch_sum3(n, c->x, 0, w, c->stream);
     launch_sub_mean3(n, c->x, 0, w, c->stream);
     if ((rc = check_launch(c, "project"))) return rc;
@@ -428,16 +485,14 @@ int solve_mg64(otm_ctx* c, bool x_zero, otm_solve_stats* st) {
     }
     st->converged = all_inactive(c->h_sc) ? 1 : 0;
     st->refreshes = 0;
+    st->stalled = watch.verdict;
     c->timings[7] = (double)launches;
     return OTM_OK;
 }
 
-int solve_fp64(otm_ctx* c, bool x_zero, otm_solve_stats* st) {
-    if (c->use_mg) return solve_mg64(c, x_zero, st);
-    if (c->use_fused) {
-        const FusedBufs<double> B{{c->r64, c->r64b}, {c->q64, c->q64b}, {c->p64[0], c->p64[1]}, c->x, c->dinv, c->k};
-        return solve_fused<double>(c, x_zero, false, B, st);
-    }
+// Float64 Jacobi-PCG with the two-pass iteration (direction + operator pass,
+// then the vector update); also the fallback of the float32 paths.
+int solve_fp64_twopass(otm_ctx* c, bool x_zero, otm_solve_stats* st) {
     const Workspace w = c->ws();
     const int n = c->n;
     int rc;
@@ -448,6 +503,8 @@ int solve_fp64(otm_ctx* c, bool x_zero, otm_solve_stats* st) {
     if ((rc = check_launch(c, "residual"))) return rc;
     if ((rc = sync_scalars(c))) return rc;
     int launches = 0;
+    SolveWatch watch;
+    watch.start(c->h_sc, stall_window(c));
     while (!all_inactive(c->h_sc) && max_iters(c->h_sc) < c->so.max_iter) {
         const bool all = all_active(c->h_sc);
         bool sampled = false;
@@ -484,7 +541,11 @@ int solve_fp64(otm_ctx* c, bool x_zero, otm_solve_stats* st) {
                                     c->stream);
             if ((rc = sync_scalars(c))) return rc;
         }
+        if (watch.stop(c->h_sc)) break;
     }
+    // a stopped solve reports the true residual of the solution it returns
+    if (watch.verdict)
+        launch_residual<double>(n, c->k, c->b, c->x, c->r64, c->p64[c->pbuf], c->dinv, RES_START, 0, w, c->stream);
     launch_sum3(n, c->x, 0, w, c->stream);
     launch_sub_mean3(n, c->x, 0, w, c->stream);
     if ((rc = check_launch(c, "project"))) return rc;
@@ -496,8 +557,18 @@ int solve_fp64(otm_ctx* c, bool x_zero, otm_solve_stats* st) {
     }
     st->converged = conv;
     st->refreshes = 0;
+    st->stalled = watch.verdict;
     c->timings[7] = (double)launches;
     return OTM_OK;
+}
+
+int solve_fp64(otm_ctx* c, bool x_zero, otm_solve_stats* st) {
+    if (c->use_mg) return solve_mg64(c, x_zero, st);
+    if (c->use_fused) {
+        const FusedBufs<double> B{{c->r64, c->r64b}, {c->q64, c->q64b}, {c->p64[0], c->p64[1]}, c->x, c->dinv, c->k};
+        return solve_fused<double>(c, x_zero, false, B, st);
+    }
+    return solve_fp64_twopass(c, x_zero, st);
 }
 
 // Multigrid-preconditioned CG in float32 with float64 residual refreshes
@@ -520,6 +591,8 @@ int solve_mg(otm_ctx* c, bool x_zero, otm_solve_stats* st) {
     bool restart = true;
     // a V-cycle costs several operator passes and few are needed: check often
     const int check = c->so.check_every < 2 ? c->so.check_every : 2;
+    SolveWatch watch;
+    watch.start(c->h_sc, stall_window(c));
     while (!all_inactive(c->h_sc) && max_iters(c->h_sc) < c->so.max_iter) {
         const bool all = all_active(c->h_sc);
         bool sampled = false;
@@ -553,8 +626,12 @@ int solve_mg(otm_ctx* c, bool x_zero, otm_solve_stats* st) {
             ++refreshes;
             restart = true;
         }
+        if (watch.stop(c->h_sc)) break;
     }
     launch_accumulate(n, c->x, c->x32, c->stream);
+    // a stopped solve reports the true residual of the solution it returns
+    if (watch.verdict)
+        launch_residual<float>(n, c->k, c->b, c->x, c->r32, c->p32[c->pbuf], c->dinv32, RES_REFRESH, 0, w, c->stream);
     launch_sum3(n, c->x, 0, w, c->stream);
     launch_sub_mean3(n, c->x, 0, w, c->stream);
     if ((rc = check_launch(c, "project"))) return rc;
@@ -565,6 +642,7 @@ int solve_mg(otm_ctx* c, bool x_zero, otm_solve_stats* st) {
     }
     st->converged = all_inactive(c->h_sc) ? 1 : 0;
     st->refreshes = refreshes;
+    st->stalled = watch.verdict;
     c->timings[7] = (double)launches;
     return OTM_OK;
 }
@@ -589,6 +667,8 @@ int solve_mixed(otm_ctx* c, bool x_zero, otm_solve_stats* st) {
     double rr_ref[3] = {c->h_sc->rr_true[0], c->h_sc->rr_true[1], c->h_sc->rr_true[2]};
     const double d2 = c->so.reliable_delta * c->so.reliable_delta;
     int refreshes = 0, launches = 0;
+    SolveWatch watch;
+    watch.start(c->h_sc, stall_window(c));
     while (!all_inactive(c->h_sc) && max_iters(c->h_sc) < c->so.max_iter) {
         const bool all = all_active(c->h_sc);
         bool sampled = false;
@@ -631,9 +711,13 @@ int solve_mixed(otm_ctx* c, bool x_zero, otm_solve_stats* st) {
             for (int l = 0; l < 3; ++l) rr_ref[l] = c->h_sc->rr_true[l];
             ++refreshes;
         }
+        if (watch.stop(c->h_sc)) break;
     }
     // fold any remaining float32 increment into the float64 solution
     launch_accumulate(n, c->x, c->x32, c->stream);
+    // a stopped solve reports the true residual of the solution it returns
+    if (watch.verdict)
+        launch_residual<float>(n, c->k, c->b, c->x, c->r32, c->p32[c->pbuf], c->dinv32, RES_REFRESH, 0, w, c->stream);
     launch_sum3(n, c->x, 0, w, c->stream);
     launch_sub_mean3(n, c->x, 0, w, c->stream);
     if ((rc = check_launch(c, "project"))) return rc;
@@ -644,8 +728,24 @@ int solve_mixed(otm_ctx* c, bool x_zero, otm_solve_stats* st) {
     }
     st->converged = all_inactive(c->h_sc) ? 1 : 0;
     st->refreshes = refreshes;
+    st->stalled = watch.verdict;
     c->timings[7] = (double)launches;
     return OTM_OK;
+}
+
+// The float64 Krylov vectors of the two-pass iteration, allocated on the
+// first fallback of a mixed-precision context (which does not hold them).
+int ensure_fp64_vectors(otm_ctx* c) {
+    int rc = OTM_OK;
+    const int64_t n3 = 3 * c->nn;
+    if (!c->r64) rc = dalloc(c, &c->r64, n3);
+    if (!rc && !c->q64) rc = dalloc(c, &c->q64, n3);
+    for (int q = 0; q < 2 && !rc; ++q)
+        if (!c->p64[q]) {
+            rc = dalloc(c, &c->p64[q], n3);
+            if (!rc) HIPCHK(c, hipMemsetAsync(c->p64[q], 0, (size_t)n3 * sizeof(double), c->stream));
+        }
+    return rc;
 }
 
 int homogenize(otm_ctx* c, double kappa6[6], otm_solve_stats* st_out) {
@@ -681,6 +781,21 @@ int homogenize(otm_ctx* c, double kappa6[6], otm_solve_stats* st_out) {
     auto t_start = std::chrono::steady_clock::now();
     rc = (c->so.precision == OTM_MIXED) ? solve_mixed(c, x_zero, &st) : solve_fp64(c, x_zero, &st);
     if (rc) return rc;
+    if (c->so.precision == OTM_MIXED && st.stalled) {
+        // the float32 recursion stopped making progress (or its residual left
+        // the finite range): finish in float64 from the current solution, or
+        // from zero after a non-finite residual
+        if ((rc = ensure_fp64_vectors(c))) return rc;
+        otm_solve_stats s2{};
+        rc = solve_fp64_twopass(c, st.stalled == 2, &s2);
+        if (rc) return rc;
+        for (int l = 0; l < 3; ++l) {
+            s2.iterations[l] += st.iterations[l];
+        }
+        s2.refreshes = st.refreshes;
+        s2.fallback = 1;
+        st = s2;
+    }
     (void)hipEventRecord(c->ev[3], c->stream);
     auto t_end = std::chrono::steady_clock::now();
     st.ms_solve = std::chrono::duration<double, std::milli>(t_end - t_start).count();
@@ -1047,6 +1162,7 @@ void otm_default_options(otm_solver_opts* s, otm_oc_opts* o, otm_governor_opts* 
         s->preconditioner = OTM_PRECOND_JACOBI;
         s->mg_sweeps = 1;
         s->mg_coarse_sweeps = 2;
+        s->stall_window = 0;
     }
     if (o) {
         o->move = 0.05;
@@ -1101,7 +1217,7 @@ int otm_create(const otm_problem* problem, const otm_solver_opts* solver, const 
     if (!(c->so.tol > 0.0 && c->so.max_iter > 0 && c->so.check_every >= 1 && c->so.reliable_delta > 0.0 &&
           c->so.reliable_delta < 1.0 && (c->so.precision == OTM_FP64 || c->so.precision == OTM_MIXED) &&
           c->so.guess >= OTM_GUESS_ZERO && c->so.guess <= OTM_GUESS_LEARNED &&
-          c->so.kernel_variant >= 0 && c->so.kernel_variant <= 5 && c->so.tile_tz >= 0 &&
+          c->so.kernel_variant >= 0 && c->so.kernel_variant <= 5 && c->so.tile_tz >= 0 && c->so.stall_window >= 0 &&
           (c->so.tile_tx == 0 || c->so.tile_tx == 16 || c->so.tile_tx == 32 || c->so.tile_tx == 64) &&
           (c->so.preconditioner == OTM_PRECOND_JACOBI || c->so.preconditioner == OTM_PRECOND_MG))) {
         delete c;

@@ -826,7 +826,8 @@ __device__ __forceinline__ void b_finalize(int op, int nblocks, const double* __
         case FIN_GUESS:
             for (int l = 0; l < 3; ++l) {
                 const double bx = tot[l], xax = tot[3 + l];
-                sc->gscale[l] = (bx > 0.0 && xax > 0.0) ? bx / xax : 0.0;
+                const double g = (bx > 0.0 && xax > 0.0) ? bx / xax : 0.0;
+                sc->gscale[l] = (isfinite(g) && g > 0.0) ? g : 0.0;
             }
             break;
         default: break;
@@ -873,7 +874,12 @@ __global__ void __launch_bounds__(kBlock) k_scale3(int64_t nn, double* __restric
     const int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x;
     if (v >= nn) return;
 #pragma unroll
-    for (int l = 0; l < 3; ++l) x[l * nn + v] *= sc->gscale[l];
+    for (int l = 0; l < 3; ++l) {
+        // a load whose guess is unusable (factor 0) starts from zero, also
+        // where the guess holds non-finite values
+        const double g = sc->gscale[l];
+        x[l * nn + v] = (g != 0.0) ? x[l * nn + v] * g : 0.0;
+    }
 }
 
 // ---------------------------------------------------------------- launchers

@@ -194,3 +194,15 @@ def test_oc_noalloc_validates_before_any_device_call(L):
     assert f(16, a, b, 0.3, ctypes.byref(oc), b, None, None) == N.OTM_EINVAL  # out aliases sens
     assert f(16, a, b, 0.3, ctypes.byref(oc), c, a, None) == N.OTM_EINVAL    # lambda aliases rho
     assert f(16, a, b, 0.3, ctypes.byref(oc), c, c, None) == N.OTM_EINVAL    # lambda aliases out
+
+
+def test_create_rejects_negative_stall_window(L):
+    from paper_2405_19991_amd import _native as N
+    p = N.Problem()
+    p.n, p.k0, p.kmin, p.penal, p.filter_radius, p.vf = 8, 1.0, 1e-3, 3.0, 1.5, 0.3
+    s, o, g = N.default_options()
+    assert s.stall_window == 0
+    s.stall_window = -1
+    h = ctypes.c_void_p()
+    assert L.otm_create(ctypes.byref(p), ctypes.byref(s), None, None, None, ctypes.byref(h)) == N.OTM_EINVAL
+    assert not h.value
