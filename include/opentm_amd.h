@@ -185,6 +185,12 @@ typedef struct {
     double move;    /* OC move limit m */
     double eta;     /* OC damping exponent */
     double rho_min; /* lower density bound */
+    double move_min; /* 0 (default): every design iteration (otm_step, otm_batch_step)
+                        moves by at most `move`.  In (0, move]: the limit adapts
+                        per design: halved after a design iteration whose objective
+                        rose, grown by a tenth after one whose objective fell, kept
+                        in [move_min, move].  otm_oc_update and
+                        otm_oc_update_noalloc always use `move`. */
 } otm_oc_opts;
 
 /* Adaptive volume bound (Sec. 2.3, model 3; Algorithm 1).  Each design
@@ -228,6 +234,7 @@ typedef struct {
     double ms_total;
     double ms_solve;
     int32_t stop; /* 1 when the stall test of the governor fired */
+    double move;  /* OC move limit this iteration's update used */
 } otm_iter_record;
 
 typedef struct otm_ctx otm_ctx;
@@ -320,7 +327,8 @@ int otm_set_guess(otm_ctx* ctx, const double* chi_host, int64_t count);
 
 /* Adaptive volume bound (Algorithm 1) as 8 doubles: [V*, decrease factor Df,
  * consecutive stalls (the algorithm's count), gap, previous objective,
- * consecutive iterations with |dg| < g_tol, design iterations done, 0].
+ * consecutive iterations with |dg| < g_tol, design iterations done, OC move
+ * limit of the last design iteration (0 before the first)].
  * set restores a state returned by get (checkpoint/resume). */
 int otm_get_governor(const otm_ctx* ctx, double state8[8]);
 int otm_set_governor(otm_ctx* ctx, const double state8[8]);

@@ -47,6 +47,7 @@ class Homogenization:
                  penal: float = 3.0, filter_radius: float = 1.5, precision: Optional[str] = None,
                  guess: str = "zero", tol: float = 1e-8, max_iter: int = 20000, check_every: int = 16,
                  reliable_delta: Optional[float] = None, move: float = 0.05, eta: float = 0.5, rho_min: float = 1e-3,
+                 move_min: float = 0.0,
                  governor: Optional[Dict[str, float]] = None, stream=None, kernel_variant: int = 0,
                  tile_tz: int = 0, tile_tx: int = 0, autotune: bool = True, preconditioner: str = "jacobi",
                  mg_sweeps: int = 1, mg_coarse_sweeps: int = 2, objective: str = "mse", symmetry: str = "none",
@@ -77,7 +78,7 @@ class Homogenization:
         s.preconditioner = {"jacobi": N.OTM_PRECOND_JACOBI, "mg": N.OTM_PRECOND_MG}[preconditioner]
         s.mg_sweeps, s.mg_coarse_sweeps = int(mg_sweeps), int(mg_coarse_sweeps)
         s.stall_window = int(stall_window)
-        o.move, o.eta, o.rho_min = float(move), float(eta), float(rho_min)
+        o.move, o.eta, o.rho_min, o.move_min = float(move), float(eta), float(rho_min), float(move_min)
         for key, val in (governor or {}).items():
             setattr(g, key, val)
         self.problem, self.solver, self.oc, self.gov = p, s, o, g
@@ -332,7 +333,7 @@ class Batch:
     chunks replay a captured hipGraph.  float64 path."""
 
     def __init__(self, problems: Sequence[Dict[str, object]], tol: float = 1e-6, max_iter: int = 20000,
-                 check_every: int = 16, guess: str = "zero", move: float = 0.05, eta: float = 0.5,
+                 check_every: int = 16, guess: str = "zero", move: float = 0.05, eta: float = 0.5, move_min: float = 0.0,
                  rho_min: float = 1e-3, governor: Optional[Dict[str, float]] = None, autotune: bool = True,
                  tile_tx: int = 0, tile_tz: int = 0, stream=None):
         L = N.lib()
@@ -356,7 +357,7 @@ class Batch:
         s.guess = {"zero": N.OTM_GUESS_ZERO, "previous": N.OTM_GUESS_PREVIOUS}[guess]
         s.tol, s.max_iter, s.check_every = float(tol), int(max_iter), int(check_every)
         s.autotune, s.tile_tx, s.tile_tz = int(bool(autotune)), int(tile_tx), int(tile_tz)
-        o.move, o.eta, o.rho_min = float(move), float(eta), float(rho_min)
+        o.move, o.eta, o.rho_min, o.move_min = float(move), float(eta), float(rho_min), float(move_min)
         for key, val in (governor or {}).items():
             setattr(g, key, val)
         h = ctypes.c_void_p()

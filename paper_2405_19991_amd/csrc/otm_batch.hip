@@ -53,6 +53,7 @@ struct otm_batch {
     double *st = nullptr, *sens = nullptr, *ocq = nullptr, *r = nullptr, *p[2] = {nullptr, nullptr}, *q = nullptr;
     W6* dw6 = nullptr;
     double* dvstar = nullptr;
+    double* dmove = nullptr;  // OC move limit per design
     double* partials = nullptr;
     int partial_slots = 0;
     Scalars* sc = nullptr;
@@ -314,7 +315,7 @@ void free_batch(otm_batch* c) {
     if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
     if (c->graph) (void)hipGraphDestroy(c->graph);
     void* bufs[] = {c->rho, c->rhof, c->k, c->dinv, c->b, c->x, c->st, c->sens, c->ocq, c->r, c->p[0], c->p[1], c->q,
-                    c->dw6, c->dvstar, c->partials, c->sc, c->ddesc, c->eb_design, c->mb_design};
+                    c->dw6, c->dvstar, c->dmove, c->partials, c->sc, c->ddesc, c->eb_design, c->mb_design};
     for (void* p : bufs)
         if (p) (void)hipFree(p);
     if (c->h_sc) (void)hipHostFree(c->h_sc);
@@ -358,7 +359,8 @@ int otm_batch_create(const otm_problem* problems, int32_t count, const otm_solve
         delete c;
         return code;
     }
-    if (!(c->oc.move > 0.0 && c->oc.eta > 0.0 && c->oc.rho_min > 0.0 && c->oc.rho_min < 1.0) ||
+    if (!(c->oc.move > 0.0 && c->oc.eta > 0.0 && c->oc.rho_min > 0.0 && c->oc.rho_min < 1.0 &&
+          c->oc.move_min >= 0.0 && c->oc.move_min <= c->oc.move) ||
         !governor_opts_valid(c->go)) {
         delete c;
         return OTM_EINVAL;
@@ -409,6 +411,7 @@ int otm_batch_create(const otm_problem* problems, int32_t count, const otm_solve
     rc = rc ? rc : balloc(c, &c->q, 3 * total);
     rc = rc ? rc : balloc(c, &c->dw6, count);
     rc = rc ? rc : balloc(c, &c->dvstar, count);
+    rc = rc ? rc : balloc(c, &c->dmove, count);
     c->partial_slots = (int)std::max(max_eb, max_mb);
     rc = rc ? rc : balloc(c, &c->partials, (int64_t)c->partial_slots * kMaxReduce);
     rc = rc ? rc : balloc(c, &c->sc, count);
@@ -514,7 +517,7 @@ int otm_batch_step(otm_batch* c, otm_iter_record* recs) {
     launch_b_energy(c->tab, c->k, c->x, c->partials, c->sc, c->stream);
     if ((rc = sync_sc(c))) return rc;
     std::vector<W6> w6(c->count);
-    std::vector<double> vstar(c->count);
+    std::vector<double> vstar(c->count), moves(c->count);
     bool conv = true;
     for (int d = 0; d < c->count; ++d) {
         const double nn = (double)c->prob[d].n * c->prob[d].n * c->prob[d].n;
@@ -540,11 +543,13 @@ int otm_batch_step(otm_batch* c, otm_iter_record* recs) {
                 R.rel_residual[l] = s.bb[l] > 0.0 ? std::sqrt(s.rr_true[l] / s.bb[l]) : 0.0;
             }
         }
+        moves[d] = next_move(c->oc, c->gov[d], gg);
         advance_volume_bound(c->go, c->oc.rho_min, c->gov[d], gg, c->low[d], c->volume[d]);
         vstar[d] = c->gov[d].vstar;
     }
     BCHK(c, hipMemcpyAsync(c->dw6, w6.data(), c->count * sizeof(W6), hipMemcpyHostToDevice, c->stream));
     BCHK(c, hipMemcpyAsync(c->dvstar, vstar.data(), c->count * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    BCHK(c, hipMemcpyAsync(c->dmove, moves.data(), c->count * sizeof(double), hipMemcpyHostToDevice, c->stream));
     // sensitivities and filter transpose
     launch_b_sens(c->tab, c->rhof, c->x, c->dw6, c->st, c->stream);
     launch_b_filter(c->tab, c->st, c->sens, c->stream);
@@ -554,19 +559,20 @@ int otm_batch_step(otm_batch* c, otm_iter_record* recs) {
     const int max_passes = kOcMaxPasses;
     for (int pass = 0; pass < max_passes; pass += 4) {
         for (int q = 0; q < 4; ++q)
-            launch_b_oc_pass(c->tab, c->rho, c->ocq, c->oc.move, c->oc.rho_min, c->oc.eta, c->partials, c->sc,
+            launch_b_oc_pass(c->tab, c->rho, c->ocq, c->dmove, c->oc.rho_min, c->oc.eta, c->partials, c->sc,
                              c->stream);
         if ((rc = sync_sc(c))) return rc;
         bool done = true;
         for (int d = 0; d < c->count; ++d) done = done && c->h_sc[d].oc_done;
         if (done) break;
     }
-    launch_b_oc_apply(c->tab, c->rho, c->ocq, c->oc.eta, c->oc.move, c->oc.rho_min, c->sc, c->stream);
+    launch_b_oc_apply(c->tab, c->rho, c->ocq, c->oc.eta, c->dmove, c->oc.rho_min, c->sc, c->stream);
     if ((rc = sync_sc(c))) return rc;
     auto t3 = std::chrono::steady_clock::now();
     if (recs)
         for (int d = 0; d < c->count; ++d) {
             recs[d].vstar = vstar[d];
+            recs[d].move = moves[d];
             recs[d].lambda = c->h_sc[d].lam;
             recs[d].ms_total = std::chrono::duration<double, std::milli>(t3 - t0).count();
             recs[d].ms_solve = std::chrono::duration<double, std::milli>(t2 - t1).count();
@@ -590,7 +596,7 @@ int otm_batch_get_governor(const otm_batch* c, int32_t d, double s[8]) {
     s[4] = v.g_prev;
     s[5] = (double)v.flat;
     s[6] = (double)c->iter;
-    s[7] = 0.0;
+    s[7] = v.move;
     return OTM_OK;
 }
 

@@ -836,24 +836,24 @@ int sensitivity(otm_ctx* c, const double w6[6]) {
     return OTM_OK;
 }
 
-int oc_update(otm_ctx* c, double vstar, double* lambda_out) {
+int oc_update(otm_ctx* c, double vstar, double move, double* lambda_out) {
     if (!c->have_sens) return fail(c, OTM_ESTATE, "OC update needs sensitivities");
     if (!std::isfinite(vstar)) return fail(c, OTM_EINVAL, "non-finite V*");
     const Workspace w = c->ws();
     const int n = c->n;
     (void)hipEventRecord(c->ev[5], c->stream);
     int prep_blocks = 0;
-    launch_oc_prepare(n, c->rho, c->sens, c->oc.eta, c->oc.move, c->oc.rho_min, c->ocq, w, c->stream, &prep_blocks);
+    launch_oc_prepare(n, c->rho, c->sens, c->oc.eta, move, c->oc.rho_min, c->ocq, w, c->stream, &prep_blocks);
     launch_oc_init(vstar, n, c->oc.eta, prep_blocks, w, c->stream);
     const int max_passes = kOcMaxPasses;
     int rc;
     for (int pass = 0; pass < max_passes; pass += 4) {
-        for (int q = 0; q < 4; ++q) launch_oc_pass(n, c->rho, c->ocq, c->oc.move, c->oc.rho_min, c->oc.eta, w, c->stream);
+        for (int q = 0; q < 4; ++q) launch_oc_pass(n, c->rho, c->ocq, move, c->oc.rho_min, c->oc.eta, w, c->stream);
         if ((rc = check_launch(c, "oc pass"))) return rc;
         if ((rc = sync_scalars(c))) return rc;
         if (c->h_sc->oc_done) break;
     }
-    launch_oc_apply(n, c->rho, c->ocq, c->oc.eta, c->oc.move, c->oc.rho_min, w, c->stream);
+    launch_oc_apply(n, c->rho, c->ocq, c->oc.eta, move, c->oc.rho_min, w, c->stream);
     (void)hipEventRecord(c->ev[6], c->stream);
     if ((rc = check_launch(c, "oc apply"))) return rc;
     if ((rc = sync_scalars(c))) return rc;
@@ -1168,6 +1168,7 @@ void otm_default_options(otm_solver_opts* s, otm_oc_opts* o, otm_governor_opts* 
         o->move = 0.05;
         o->eta = 0.5;
         o->rho_min = 1e-3;
+        o->move_min = 0.0;
     }
     if (g) {
         g->bound = 1e-4;
@@ -1233,7 +1234,8 @@ int otm_create(const otm_problem* problem, const otm_solver_opts* solver, const 
         }
         c->use_mg = true;
     }
-    if (!(c->oc.move > 0.0 && c->oc.eta > 0.0 && c->oc.rho_min > 0.0 && c->oc.rho_min < 1.0) ||
+    if (!(c->oc.move > 0.0 && c->oc.eta > 0.0 && c->oc.rho_min > 0.0 && c->oc.rho_min < 1.0 &&
+          c->oc.move_min >= 0.0 && c->oc.move_min <= c->oc.move) ||
         !governor_opts_valid(c->go)) {
         delete c;
         return OTM_EINVAL;
@@ -1419,7 +1421,7 @@ int otm_sensitivity(otm_ctx* c, const double dg_dkappa6[6], double* out) {
 
 int otm_oc_update(otm_ctx* c, double vstar, double* rho_out, double* lambda_out) {
     if (!c) return OTM_EINVAL;
-    int rc = oc_update(c, vstar, lambda_out);
+    int rc = oc_update(c, vstar, c->oc.move, lambda_out);
     if (rc) return rc;
     if (rho_out) HIPCHK(c, hipMemcpyAsync(rho_out, c->rho, (size_t)c->nn * sizeof(double), hipMemcpyDeviceToHost, c->stream));
     HIPCHK(c, hipStreamSynchronize(c->stream));
@@ -1439,10 +1441,11 @@ int otm_step(otm_ctx* c, otm_iter_record* rec) {
     int rc = sensitivity(c, w6);
     if (rc) return rc;
     const double vol = c->volume, low = c->low_bound;
+    const double move = next_move(c->oc, c->vb, g);
     advance_volume_bound(c->go, c->oc.rho_min, c->vb, g, low, vol);
     const double vstar = c->vb.vstar;
     double lam = 0.0;
-    rc = oc_update(c, vstar, &lam);
+    rc = oc_update(c, vstar, move, &lam);
     if (rc) return rc;
     c->timings[3] = ev_ms(c, 4, 5);
     auto t1 = std::chrono::steady_clock::now();
@@ -1462,6 +1465,7 @@ int otm_step(otm_ctx* c, otm_iter_record* rec) {
         rec->ms_total = c->timings[5];
         rec->ms_solve = st.ms_solve;
         rec->stop = c->vb.flat >= c->go.stall_iters ? 1 : 0;
+        rec->move = move;
     }
     c->iter += 1;
     return hrc;
@@ -1553,13 +1557,13 @@ int otm_get_governor(const otm_ctx* c, double s[8]) {
     s[4] = c->vb.g_prev;
     s[5] = (double)c->vb.flat;
     s[6] = (double)c->iter;
-    s[7] = 0.0;
+    s[7] = c->vb.move;
     return OTM_OK;
 }
 
 int otm_set_governor(otm_ctx* c, const double s[8]) {
     if (!c || !s) return OTM_EINVAL;
-    for (int q = 0; q < 7; ++q)
+    for (int q = 0; q < 8; ++q)
         if (!std::isfinite(s[q])) return fail(c, OTM_ENONFINITE, "non-finite governor state");
     c->vb.vstar = s[0];
     c->vb.df = s[1];
@@ -1568,6 +1572,7 @@ int otm_set_governor(otm_ctx* c, const double s[8]) {
     c->vb.g_prev = s[4];
     c->vb.flat = (int)s[5];
     c->iter = (int)s[6];
+    c->vb.move = s[7] > 0.0 ? s[7] : 0.0;
     return OTM_OK;
 }
 

@@ -208,7 +208,33 @@ struct VolumeBound {
     double g_prev = 1.0;  // objective of the previous design iteration (1 before the first)
     int stalls = 0;       // consecutive iterations that made no headway against the bound
     int flat = 0;         // consecutive iterations whose objective changed by less than g_tol
+    double move = 0.0;    // OC move limit of the next update (0: not yet set, take oc.move)
+    double dg_prev = 0.0; // g_prev - (the objective before it): the last change of the objective
 };
+
+// The OC move limit of the next update.  With oc.move_min = 0 it is oc.move
+// (a fixed step, as the paper's OC optimizer takes it).  With oc.move_min > 0
+// the step adapts to the objective's course: it halves after a design
+// iteration whose change of the objective reversed the previous change (a
+// zig-zag) and grows by a tenth after one that continued it, within
+// [move_min, move].  A fixed step that the volume bound cannot absorb moves
+// every element by the full step (a sign-of-gradient step), which circles the
+// optimum at the step's own scale, visible as an objective that alternately
+// rises and falls; the halving shrinks that circle.  A steady rise (the
+// bound taking material away) or fall leaves the step growing.  Call before
+// advance_volume_bound (which replaces g_prev).
+inline double next_move(const otm_oc_opts& oc, VolumeBound& s, double g) {
+    const double dg = g - s.g_prev;
+    if (oc.move_min <= 0.0 || s.move <= 0.0) {
+        s.move = oc.move;
+    } else if (dg * s.dg_prev < 0.0) {
+        s.move = 0.5 * s.move > oc.move_min ? 0.5 * s.move : oc.move_min;
+    } else {
+        s.move = 1.1 * s.move < oc.move ? 1.1 * s.move : oc.move;
+    }
+    s.dg_prev = dg;
+    return s.move;
+}
 
 // One design iteration's transition, given its objective g, the
 // solid-equivalent volume low = mean(rho~^p) and the volume vol = mean(rho).
@@ -371,10 +397,10 @@ void launch_b_filter(const BatchTab& t, const double* in, double* out, hipStream
 void launch_b_oc_prepare(const BatchTab& t, const double* rho, const double* sens, double eta, double* q,
                          hipStream_t s);
 void launch_b_oc_init(const BatchTab& t, Scalars* sc, const double* vstar, double eta, hipStream_t s);
-void launch_b_oc_pass(const BatchTab& t, const double* rho, const double* q, double move, double rho_min, double eta,
-                      double* partials, Scalars* sc, hipStream_t s);
-void launch_b_oc_apply(const BatchTab& t, double* rho, const double* q, double eta, double move, double rho_min,
-                       Scalars* sc, hipStream_t s);
+void launch_b_oc_pass(const BatchTab& t, const double* rho, const double* q, const double* moves, double rho_min,
+                      double eta, double* partials, Scalars* sc, hipStream_t s);
+void launch_b_oc_apply(const BatchTab& t, double* rho, const double* q, double eta, const double* moves,
+                       double rho_min, Scalars* sc, hipStream_t s);
 void launch_b_finalize(const BatchTab& t, int op, int which_mb, double* partials, Scalars* sc, double eta,
                        hipStream_t s);
 // z-march work-list launch (persistent blocks) and vector update, float64

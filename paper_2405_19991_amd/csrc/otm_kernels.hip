@@ -1294,16 +1294,20 @@ __global__ void kb_oc_init(BatchTab t, Scalars* sc, const double* vstar, double 
     oc_candidates_lane(s, 0.0, 1e9, eta);
 }
 
-__global__ void __launch_bounds__(kBlock) kb_oc_pass(BatchTab t, const double* rho, const double* q, double move,
-                                                     double rho_min, double eta, double* partials, Scalars* sc) {
+// moves[d]: the OC move limit of design d
+__global__ void __launch_bounds__(kBlock) kb_oc_pass(BatchTab t, const double* rho, const double* q,
+                                                     const double* __restrict__ moves, double rho_min, double eta,
+                                                     double* partials, Scalars* sc) {
     OTM_BATCH_ITEM
-    b_oc_pass(lb_, nb_, (int64_t)D.n * D.n * D.n, rho + o1, q + o1, move, rho_min, eta, partials, nullptr, sc + d_);
+    b_oc_pass(lb_, nb_, (int64_t)D.n * D.n * D.n, rho + o1, q + o1, moves[d_], rho_min, eta, partials, nullptr,
+              sc + d_);
 }
 
 __global__ void __launch_bounds__(kBlock) kb_oc_apply(BatchTab t, double* rho, const double* q, double eta,
-                                                      double move, double rho_min, const Scalars* sc) {
+                                                      const double* __restrict__ moves, double rho_min,
+                                                      const Scalars* sc) {
     OTM_BATCH_ITEM
-    b_oc_apply(lb_, nb_, (int64_t)D.n * D.n * D.n, rho + o1, q + o1, eta, move, rho_min, sc + d_);
+    b_oc_apply(lb_, nb_, (int64_t)D.n * D.n * D.n, rho + o1, q + o1, eta, moves[d_], rho_min, sc + d_);
 }
 
 static int fin_width(int op) {
@@ -1375,14 +1379,14 @@ void launch_b_oc_prepare(const BatchTab& t, const double* rho, const double* sen
 void launch_b_oc_init(const BatchTab& t, Scalars* sc, const double* vstar, double eta, hipStream_t s) {
     hipLaunchKernelGGL(kb_oc_init, dim3(t.count), dim3(64), 0, s, t, sc, vstar, eta);
 }
-void launch_b_oc_pass(const BatchTab& t, const double* rho, const double* q, double move, double rho_min, double eta,
-                      double* partials, Scalars* sc, hipStream_t s) {
-    hipLaunchKernelGGL(kb_oc_pass, dim3(t.eb_total), dim3(kBlock), 0, s, t, rho, q, move, rho_min, eta, partials, sc);
+void launch_b_oc_pass(const BatchTab& t, const double* rho, const double* q, const double* moves, double rho_min,
+                      double eta, double* partials, Scalars* sc, hipStream_t s) {
+    hipLaunchKernelGGL(kb_oc_pass, dim3(t.eb_total), dim3(kBlock), 0, s, t, rho, q, moves, rho_min, eta, partials, sc);
     launch_b_finalize(t, FIN_OC, 0, partials, sc, eta, s);
 }
-void launch_b_oc_apply(const BatchTab& t, double* rho, const double* q, double eta, double move, double rho_min,
-                       Scalars* sc, hipStream_t s) {
-    hipLaunchKernelGGL(kb_oc_apply, dim3(t.eb_total), dim3(kBlock), 0, s, t, rho, q, eta, move, rho_min, sc);
+void launch_b_oc_apply(const BatchTab& t, double* rho, const double* q, double eta, const double* moves,
+                       double rho_min, Scalars* sc, hipStream_t s) {
+    hipLaunchKernelGGL(kb_oc_apply, dim3(t.eb_total), dim3(kBlock), 0, s, t, rho, q, eta, moves, rho_min, sc);
 }
 void launch_b_finalize(const BatchTab& t, int op, int which_mb, double* partials, Scalars* sc, double eta,
                        hipStream_t s) {

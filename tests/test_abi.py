@@ -206,3 +206,17 @@ def test_create_rejects_negative_stall_window(L):
     h = ctypes.c_void_p()
     assert L.otm_create(ctypes.byref(p), ctypes.byref(s), None, None, None, ctypes.byref(h)) == N.OTM_EINVAL
     assert not h.value
+
+
+@pytest.mark.parametrize("move_min", [-1e-3, 0.06, float("nan")])
+def test_create_rejects_bad_move_floor(L, move_min):
+    """The adaptive OC move floor must lie in [0, move] (default move 0.05)."""
+    from paper_2405_19991_amd import _native as N
+    p = N.Problem()
+    p.n, p.k0, p.kmin, p.penal, p.filter_radius, p.vf = 8, 1.0, 1e-3, 3.0, 1.5, 0.3
+    s, o, g = N.default_options()
+    assert o.move_min == 0.0
+    o.move_min = move_min
+    h = ctypes.c_void_p()
+    assert L.otm_create(ctypes.byref(p), None, ctypes.byref(o), None, None, ctypes.byref(h)) == N.OTM_EINVAL
+    assert not h.value

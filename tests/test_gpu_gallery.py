@@ -2,8 +2,10 @@
 positive-definite targets with the diagonal fixed at [0.3, 0.2, 0.1], every
 design started from the IWP field at volume 0.3 with the volume bound of
 Algorithm 1 starting at 1.  Checks: the target count, one batch holding all
-61 designs, every design's objective falling, and a design of the batch
-following a single-design context step for step.  Whether each design
+61 designs, every design's objective falling, a design of the batch
+following a single-design context step for step, three designs following
+the oracle's own design iterations, and the adaptive OC move limit
+following its rule in single and batched designs.  Whether each design
 reaches g <= 1e-4 is reported by bench.py's gallery leg, not asserted: the
 paper's figures are stripped, so the end designs are parity unpinned."""
 import numpy as np
@@ -99,3 +101,59 @@ def test_traversal_designs_follow_oracle():
             assert r["vstar"] == pytest.approx(ref.vstar, rel=1e-12), (d, it)
             assert r["lam"] == pytest.approx(ref.lam, rel=1e-8, abs=1e-40), (d, it)
         np.testing.assert_allclose(brho[j], rho, rtol=0, atol=1e-8)
+
+
+def expected_moves(gs, move, move_min):
+    """The move limit each design iteration used, from its objectives: the
+    full limit first, then halved (not below move_min) after a reversal of
+    the objective's change and grown by a tenth (not above move) otherwise."""
+    out, m, dg_prev, g_prev = [], 0.0, 0.0, 1.0
+    for g in gs:
+        dg = g - g_prev
+        if m <= 0.0:
+            m = move
+        elif dg * dg_prev < 0.0:
+            m = max(move_min, 0.5 * m)
+        else:
+            m = min(move, 1.1 * m)
+        dg_prev, g_prev = dg, g
+        out.append(m)
+    return out
+
+
+def test_adaptive_move_limit_single_and_batch():
+    """With move_min > 0 each design iteration's OC update uses the move the
+    rule gives for the objective's course (exactly), moves no element by
+    more than it, and a batched design follows a single context step for
+    step, move included.  16^3, two gallery targets, 40 iterations (the
+    limit is halved and regrown along the way)."""
+    from paper_2405_19991_amd import Batch, Homogenization, init_density
+    T = synth.gallery_targets()
+    n, iters, move, move_min = 16, 40, 0.05, 0.002
+    rho0 = init_density(n, "IWP", 0.3)
+    picks = [10, 45]
+    B = Batch([dict(n=n, target=tuple(T[d]), vf=1.0) for d in picks], tol=1e-10, guess="previous", move=move,
+              move_min=move_min)
+    for d in range(len(picks)):
+        B.set_density(d, rho0)
+    brecs = [B.step() for _ in range(iters)]
+    B.close()
+    adapted = []
+    for j, d in enumerate(picks):
+        recs, steps = [], []
+        with Homogenization(n, (1.0, 1e-3), tuple(T[d]), vf=1.0, tol=1e-10, guess="previous", move=move,
+                            move_min=move_min) as h:
+            h.set_density(rho0)
+            for it in range(iters):
+                before = h.get_field("rho")
+                recs.append(h.step())
+                steps.append(np.abs(h.get_field("rho") - before).max())
+        moves = [r["move"] for r in recs]
+        assert moves == expected_moves([r["g"] for r in recs], move, move_min), d
+        adapted.append(len(set(moves)) > 2)
+        for it in range(iters):
+            assert steps[it] <= moves[it] * (1 + 1e-12), (d, it)
+            assert brecs[it][j]["move"] == moves[it], (d, it)
+            assert brecs[it][j]["g"] == pytest.approx(recs[it]["g"], rel=1e-7), (d, it)
+        print(f"target {d}: moves {[round(m, 4) for m in moves]}", flush=True)
+    assert any(adapted)  # the limit was halved and regrown somewhere
