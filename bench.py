@@ -53,6 +53,8 @@ def parse():
     ap.add_argument("--no-fp64", action="store_true", help="skip the float64 leg")
     ap.add_argument("--gallery-iters", type=int, default=500)
     ap.add_argument("--gallery-n", type=int, default=32)
+    ap.add_argument("--retune", action="store_true",
+                    help="time the kernel candidates at start-up instead of using the shipped tuning file")
     ap.add_argument("--variant", type=int, default=0,
                     help="solver kernel: 0 automatic (autotuned), 4 fused iteration, 1-3 cross-check kernels")
     ap.add_argument("--solver-tx", type=int, default=0, help="solver tile width (0: automatic)")
@@ -430,6 +432,28 @@ def apply_only(args):
                       "tile": [v, args.apply_tx, args.apply_tz]}), flush=True)
 
 
+TUNE_FILE = os.path.join(ROOT, "paper_2405_19991_amd", "tuning", "gfx950.tune")
+
+
+def use_shipped_tuning(retune: bool):
+    """Kernel and tile choices: unless OTM_TUNE_CACHE is already set or
+    --retune is given, the autotuners start from a private copy of the
+    package's tuning file (choices timed on an MI355X), so that the timed
+    configuration does not depend on the timing noise of one start-up; new
+    configurations are tuned and added to the copy."""
+    if "OTM_TUNE_CACHE" in os.environ:
+        return {"source": "OTM_TUNE_CACHE", "path": os.environ["OTM_TUNE_CACHE"]}
+    if retune or not os.path.exists(TUNE_FILE):
+        return {"source": "timed at start-up"}
+    import shutil
+    import tempfile
+    fd, path = tempfile.mkstemp(prefix="otm_tune_", suffix=".txt")
+    os.close(fd)
+    shutil.copyfile(TUNE_FILE, path)
+    os.environ["OTM_TUNE_CACHE"] = path
+    return {"source": os.path.relpath(TUNE_FILE, ROOT)}
+
+
 def main():
     args = parse()
     if args.apply_only:
@@ -439,6 +463,7 @@ def main():
         print(json.dumps({"error": "this benchmark runs on one GPU only; --gpus must be 1 "
                                    "(sharding over several GPUs is not implemented)"}))
         sys.exit(2)
+    tuning = use_shipped_tuning(args.retune)
     import numpy as np
     import torch
     import synth
@@ -589,6 +614,7 @@ def main():
         "pcg_iters_per_step": pcg_iters / args.steps,
         "pcg_only_dof_per_s": dof / (solve_ms * 1e-3) if solve_ms > 0 else None,
         "solver_tile": tile,
+        "tuning": tuning,
         "device_bytes": dev_bytes,
         "kappa_rel_err_vs_oracle": oracle_tensor_error(w, first_kappa, args.tol),
         "last_g": recs[-1]["g"],

@@ -164,7 +164,15 @@ typedef struct {
                                two-node kernel); 0 = automatic */
     int32_t autotune;       /* 1: with kernel_variant 0 and automatic tiles, time the
                                candidate kernels and tile shapes once per (n, precision)
-                               and process at otm_create and keep the fastest */
+                               and process at otm_create and keep the fastest (a
+                               candidate must be 2 % faster to displace an earlier one).
+                               When the environment variable OTM_TUNE_CACHE names a
+                               file, a choice stored there for this device architecture
+                               and (n, precision) is used without timing, and a new
+                               choice is appended to it (text, one line per choice:
+                               architecture, key, values; the last line wins; lines a
+                               context could not have chosen are ignored).  Batches do
+                               the same per mix of n. */
     int32_t preconditioner; /* OTM_PRECOND_JACOBI (default) or OTM_PRECOND_MG; with
                                OTM_PRECOND_MG kernel_variant must be 0 and no autotuning
                                is done */

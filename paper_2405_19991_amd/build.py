@@ -7,7 +7,7 @@ PKG = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(PKG)
 CSRC = os.path.join(PKG, "csrc")
 LIB = os.path.join(PKG, "libopentm_amd.so")
-SOURCES = ["otm_kernels.hip", "otm_stencil.hip", "otm_march2.hip", "otm_fused.hip", "otm_engine.hip", "otm_batch.hip", "otm_nn.hip", "otm_mg.hip", "otm_init.hip", "otm_noalloc.hip"]
+SOURCES = ["otm_kernels.hip", "otm_stencil.hip", "otm_march2.hip", "otm_fused.hip", "otm_engine.hip", "otm_batch.hip", "otm_nn.hip", "otm_mg.hip", "otm_init.hip", "otm_noalloc.hip", "otm_tunecache.hip"]
 ARCH = "gfx950"
 
 FLAGS = [

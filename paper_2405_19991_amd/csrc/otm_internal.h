@@ -5,6 +5,9 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <string>
+#include <vector>
+
 #include "opentm_amd.h"
 
 namespace otm {
@@ -176,6 +179,14 @@ void launch_oc_from_sens(int n, const double* rho, const double* sens, double* r
                          double vstar, double eta, double move, double rho_min, const Workspace& ws,
                          hipStream_t s);
 void launch_clamp(int n, double* rho, double lo, double hi, hipStream_t s);
+// Persistent tuning choices (otm_tunecache.hip): keyed by the current
+// device's architecture and `key`, in the file named by OTM_TUNE_CACHE (no
+// file: lookups miss, stores do nothing).  lookup fills vals (its size is the
+// expected count) from the last matching line.
+std::string device_arch();
+bool tune_cache_lookup(const std::string& key, std::vector<double>& vals);
+void tune_cache_store(const std::string& key, const std::vector<double>& vals);
+
 // The objective over the six tensor components and dg/dkappa (Sec. 4.4):
 // squared error, relative squared error, or l1 with d|a|/da = 0 at a = 0.
 inline void objective_grad(int kind, const double* kappa, const double* target, double* g, double* w6) {
