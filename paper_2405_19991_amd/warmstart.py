@@ -7,6 +7,7 @@ forward/backward kernels and Adam; this module only sequences samples.
 
     python -m paper_2405_19991_amd.warmstart train --out weights.npy
     python -m paper_2405_19991_amd.warmstart eval --weights weights.npy
+    python -m paper_2405_19991_amd.warmstart spectrum --weights weights.npy
 """
 from __future__ import annotations
 
@@ -176,9 +177,55 @@ def kernels(n: int = 128, reps: int = 5) -> Dict[str, float]:
             "forward_tflops": FLOP_FWD * vox / fwd / 1e12, "train_tflops": FLOP_TRAIN * vox / trn / 1e12}
 
 
+def error_spectrum(net, n: int = 128, seed: int = 303, at_iter: int = 5) -> Dict[str, object]:
+    """Where the warm starts' errors lie, on the held-out anisotropic cell at
+    design iteration `at_iter`: for the network's prediction and for the
+    previous design iteration's solution, each scaled by its energy factor
+    s = b.x / x.A x, per load the relative energy-norm and L2 errors against a
+    float64 solve to 1e-10 and the fraction of the error's energy (its
+    squared Fourier coefficients) at wavenumbers |k| <= 2, 4, 8, 16; and the
+    same fractions for chi itself."""
+    import torch
+    sys.path.insert(0, os.path.dirname(HERE))
+    import synth
+    from .api import Homogenization
+    rho = synth.smoothed_noise(n, 0.15, 0.45, seed)
+    kk = np.fft.fftfreq(n) * n
+    K = np.sqrt(kk[:, None, None] ** 2 + kk[None, :, None] ** 2 + kk[None, None, :] ** 2)
+
+    def bands(e):
+        E = np.abs(np.fft.fftn(e)) ** 2
+        return {f"|k|<={kc}": float(E[K <= kc].sum() / E.sum()) for kc in (2, 4, 8, 16)}
+
+    out: Dict[str, object] = {"n": n, "seed": seed, "design_iteration": at_iter}
+    with Homogenization(n, (1.0, 1e-3), synth.TARGET_ANISO, vf=0.3, tol=1e-10, guess="previous") as h:
+        h.set_density(rho)
+        for _ in range(at_iter):
+            h.step()
+        chi_prev = h.get_field("chi")
+        h.homogenize()
+        chi, b = h.get_field("chi"), h.get_field("b")
+        rf = torch.from_numpy(h.get_field("rhof").reshape(-1).copy()).cuda()
+        x0 = torch.empty(3 * n ** 3, dtype=torch.float64, device="cuda")
+        net.forward(rf, x0)
+        torch.cuda.synchronize()
+        for name, x in (("learned", x0.cpu().numpy().reshape(3, n, n, n)), ("previous", chi_prev)):
+            ax = h.apply(x).reshape(3, n, n, n)
+            rec = []
+            for l in range(3):
+                xax, bx, bchi = float(np.sum(x[l] * ax[l])), float(np.sum(b[l] * x[l])), float(np.sum(b[l] * chi[l]))
+                sc = max(bx, 0.0) / xax
+                e = sc * x[l] - chi[l]
+                rec.append({"scale": sc, "energy_err": float(np.sqrt(max(sc * sc * xax - 2 * sc * bx + bchi, 0.0) / bchi)),
+                            "l2_err": float(np.linalg.norm(e) / np.linalg.norm(chi[l])), **bands(e)})
+            out[name] = rec
+        out["chi"] = [bands(chi[l]) for l in range(3)]
+    return out
+
+
 def main(argv=None):
     ap = argparse.ArgumentParser()
-    ap.add_argument("cmd", choices=["train", "eval", "kernels"])
+    ap.add_argument("cmd", choices=["train", "eval", "kernels", "spectrum"])
     ap.add_argument("--out", default=DEFAULT_WEIGHTS)
     ap.add_argument("--weights", default=DEFAULT_WEIGHTS)
     ap.add_argument("--epochs", type=int, default=30)
@@ -189,6 +236,11 @@ def main(argv=None):
     from .api import Network
     if a.cmd == "kernels":
         print(json.dumps(kernels()), flush=True)
+        return
+    if a.cmd == "spectrum":
+        net = Network(n_max=128)
+        net.load(a.weights)
+        print(json.dumps(error_spectrum(net), indent=1), flush=True)
         return
     if a.cmd == "train":
         t0 = time.perf_counter()
