@@ -72,11 +72,19 @@ extern "C" {
 /* Preconditioners of the conjugate-gradient solve. */
 #define OTM_PRECOND_JACOBI 0 /* diagonal (Jacobi) preconditioner, Sec. 2.4 relaxation diagonal S_v */
 #define OTM_PRECOND_MG 1     /* one geometric multigrid V-cycle per iteration (Sec. 2.4, Algorithm 3):
-                                damped Jacobi relaxation on S_v, restriction of the residual,
+                                relaxation on S_v (damped Jacobi or 8-colour Gauss-Seidel,
+                                mg_smoother), restriction of the residual,
                                 direct solve on the coarsest level, interpolation and correction.
                                 The V-cycle runs in float32; with OTM_FP64 the Krylov vectors,
                                 dots and convergence test stay float64.  n = m 2^j with
                                 m in {3, 4} and n >= 6, else OTM_EINVAL */
+
+/* Relaxation of the multigrid V-cycle (OTM_PRECOND_MG). */
+#define OTM_MG_JACOBI 0 /* damped Jacobi, weight 0.9 (default) */
+#define OTM_MG_GS8 1    /* 8-colour Gauss-Seidel (Sec. 2.4): S_v T_v = f_v - M_v for the nodes of
+                           one parity class (i mod 2, j mod 2, k mod 2) at a time, colours 0..7
+                           before the coarse correction and 7..0 after it (a symmetric cycle);
+                           mg_sweeps / mg_coarse_sweeps count full sweeps of 8 colours */
 
 #define OTM_OBJ_MSE 0 /* g = sum_c (kappa_c - target_c)^2, Sec. 4.4 (MSE objective) */
 #define OTM_OBJ_REL 1 /* g = sum_c (kappa_c / target_c - 1)^2, Sec. 4.4 (relative objective);
@@ -187,6 +195,7 @@ typedef struct {
                                continues in float64 (two-pass Jacobi-PCG) from its
                                solution, or from zero after a non-finite residual;
                                a stalled float64 solve returns OTM_NOT_CONVERGED */
+    int32_t mg_smoother;    /* OTM_PRECOND_MG: OTM_MG_JACOBI (default) or OTM_MG_GS8 */
 } otm_solver_opts;
 
 typedef struct {

@@ -30,6 +30,8 @@ OTM_GUESS_USER = 2
 OTM_GUESS_LEARNED = 3
 OTM_PRECOND_JACOBI = 0
 OTM_PRECOND_MG = 1
+OTM_MG_JACOBI = 0
+OTM_MG_GS8 = 1
 OTM_OBJ_MSE = 0
 OTM_OBJ_REL = 1
 OTM_OBJ_L1 = 2
@@ -72,7 +74,8 @@ class SolverOpts(ctypes.Structure):
                 ("max_iter", ctypes.c_int32), ("check_every", ctypes.c_int32), ("reliable_delta", ctypes.c_double),
                 ("kernel_variant", ctypes.c_int32), ("tile_tz", ctypes.c_int32), ("tile_tx", ctypes.c_int32),
                 ("autotune", ctypes.c_int32), ("preconditioner", ctypes.c_int32), ("mg_sweeps", ctypes.c_int32),
-                ("mg_coarse_sweeps", ctypes.c_int32), ("stall_window", ctypes.c_int32)]
+                ("mg_coarse_sweeps", ctypes.c_int32), ("stall_window", ctypes.c_int32),
+                ("mg_smoother", ctypes.c_int32)]
 
 
 class OcOpts(ctypes.Structure):

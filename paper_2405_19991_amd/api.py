@@ -47,7 +47,7 @@ class Homogenization:
                  penal: float = 3.0, filter_radius: float = 1.5, precision: Optional[str] = None,
                  guess: str = "zero", tol: float = 1e-8, max_iter: int = 20000, check_every: int = 16,
                  reliable_delta: Optional[float] = None, move: float = 0.05, eta: float = 0.5, rho_min: float = 1e-3,
-                 move_min: float = 0.0,
+                 move_min: float = 0.0, mg_smoother: str = "jacobi",
                  governor: Optional[Dict[str, float]] = None, stream=None, kernel_variant: int = 0,
                  tile_tz: int = 0, tile_tx: int = 0, autotune: bool = True, preconditioner: str = "jacobi",
                  mg_sweeps: int = 1, mg_coarse_sweeps: int = 2, objective: str = "mse", symmetry: str = "none",
@@ -78,6 +78,7 @@ class Homogenization:
         s.preconditioner = {"jacobi": N.OTM_PRECOND_JACOBI, "mg": N.OTM_PRECOND_MG}[preconditioner]
         s.mg_sweeps, s.mg_coarse_sweeps = int(mg_sweeps), int(mg_coarse_sweeps)
         s.stall_window = int(stall_window)
+        s.mg_smoother = {"jacobi": N.OTM_MG_JACOBI, "gs8": N.OTM_MG_GS8}[mg_smoother]
         o.move, o.eta, o.rho_min, o.move_min = float(move), float(eta), float(rho_min), float(move_min)
         for key, val in (governor or {}).items():
             setattr(g, key, val)

@@ -914,6 +914,7 @@ int mg_build(otm_ctx* c) {
     if (!H.levels) return fail(c, OTM_EINVAL, "multigrid needs n = m 2^j with m in {3, 4} and n >= 6");
     H.sweeps = c->so.mg_sweeps;
     H.coarse_sweeps = c->so.mg_coarse_sweeps > 0 ? c->so.mg_coarse_sweeps : c->so.mg_sweeps;
+    H.gs = c->so.mg_smoother == OTM_MG_GS8;
     int rc = OTM_OK;
     for (int l = 0; l < H.levels && !rc; ++l) {
         MgLevel& a = H.lv[l];
@@ -1199,6 +1200,7 @@ void otm_default_options(otm_solver_opts* s, otm_oc_opts* o, otm_governor_opts* 
         s->mg_sweeps = 1;
         s->mg_coarse_sweeps = 2;
         s->stall_window = 0;
+        s->mg_smoother = OTM_MG_JACOBI;
     }
     if (o) {
         o->move = 0.05;
@@ -1264,6 +1266,7 @@ int otm_create(const otm_problem* problem, const otm_solver_opts* solver, const 
         int ns[kMgMaxLevels];
         if (c->so.kernel_variant != 0 || c->so.mg_sweeps < 1 ||
             c->so.mg_sweeps > 8 || c->so.mg_coarse_sweeps < 0 || c->so.mg_coarse_sweeps > 8 || (c->so.tile_tx != 0 && c->so.tile_tx != 32 && c->so.tile_tx != 64) ||
+            (c->so.mg_smoother != OTM_MG_JACOBI && c->so.mg_smoother != OTM_MG_GS8) ||
             !mg_levels(problem->n, ns)) {
             delete c;
             return OTM_EINVAL;

@@ -346,6 +346,7 @@ struct MgHierarchy {
     int levels = 0;
     int sweeps = 2;          // damped Jacobi steps before and after the coarse correction (finest level)
     int coarse_sweeps = 2;   // the same on the coarser levels
+    bool gs = false;         // 8-colour Gauss-Seidel sweeps instead of damped Jacobi steps
     float* minv = nullptr;   // inverse of the coarsest operator (at most 64 x 64)
     MgLevel lv[kMgMaxLevels];
 };
@@ -363,7 +364,7 @@ void launch_mg_coarse_solve(int n, const float* minv, const float* f, float* x, 
 // The second-coarsest level (n <= 8, even) and the coarsest below it in one
 // block: x = V(f) with nu relaxation steps per leg, written to x (3 n^3).
 void launch_mg_tail(int n, int nu, const float* f, const float* k, const float* dinv, const float* minv, float* x,
-                    hipStream_t s);
+                    bool gs, hipStream_t s);
 // z = V(r) for the three loads, r = lv[0].f; *z_out receives the level-0
 // buffer that holds z.  The last relaxation writes the per-block sums r.z
 // into partials; returns their block count.

@@ -10,7 +10,10 @@
 // Jacobi (weight 0.9; by Gershgorin every eigenvalue of D^-1 A lies in [0, 2]
 // for any conductivity field), the same number of steps in both legs, so the
 // V-cycle is a symmetric positive definite operator and a valid PCG
-// preconditioner.  Each relaxation step (and the residual before a
+// preconditioner; or the paper's 8-colour Gauss-Seidel (Sec. 2.4: S_v T_v =
+// f_v - M_v, the nodes of one parity class (i mod 2, j mod 2, k mod 2) at a
+// time, which share no element), colours 0..7 before the coarse correction
+// and 7..0 after it, which makes the cycle symmetric as well.  Each relaxation step (and the residual before a
 // restriction) is one z-march pass of the operator kernel with a relaxation
 // epilogue (otm_march2.hip); the coarsest level (at most 4^3 nodes) is solved
 // directly.
@@ -209,6 +212,91 @@ __global__ void __launch_bounds__(kBlock) k_mg_coarse_solve(int N, const float* 
     x[l * N + v] = s0 + s1;
 }
 
+// One colour of the 8-colour Gauss-Seidel relaxation on a level (n even): a
+// thread per 2x2x2 cell updates the cell's node of colour `color` (bits:
+// i mod 2, j mod 2, k mod 2) in place, x_v += D^-1_v (f_v - (A x)_v), i.e.
+// S_v x_v = f_v - M_v with M_v the off-diagonal part of [KT]_v.  Its 26
+// neighbours all have other colours, so no thread reads a value another
+// thread of the pass writes.  FIRST: the first pass of a cycle's first sweep,
+// from x = 0: x_v = D^-1_v f_v and the cell's other seven nodes are set to 0
+// (x needs no clearing).  DOT: every node of the cell is final after this
+// pass (the last colour of the last sweep): the block sums of f . x per load
+// go to partials[block * 3 + load] (r.z of the cycle on the finest level).
+template <bool FIRST, bool DOT>
+__global__ void __launch_bounds__(kBlock) k_mg_gs(int n, int color, const float* __restrict__ dinv,
+                                                 const float* __restrict__ f, const float* __restrict__ k,
+                                                 float* __restrict__ x, double* __restrict__ partials) {
+    const int h = n >> 1;
+    const uint32_t cells = (uint32_t)h * h * h;
+    const uint32_t nn = (uint32_t)n * n * n;
+    double acc[3] = {0.0, 0.0, 0.0};
+    for (uint32_t cidx = blockIdx.x * kBlock + threadIdx.x; cidx < cells; cidx += gridDim.x * kBlock) {
+        const int a = (int)(cidx % h), b = (int)((cidx / h) % h), cz = (int)(cidx / ((uint32_t)h * h));
+        const int i = 2 * a + (color & 1), j = 2 * b + ((color >> 1) & 1), kk = 2 * cz + (color >> 2);
+        const uint32_t v = (uint32_t)i + (uint32_t)n * ((uint32_t)j + (uint32_t)n * (uint32_t)kk);
+        const float dv = dinv[v];
+        if (FIRST) {
+#pragma unroll
+            for (int l = 0; l < 3; ++l) x[l * nn + v] = dv * f[l * nn + v];
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                if (q == color) continue;
+                const uint32_t u = (uint32_t)(2 * a + (q & 1)) +
+                                   (uint32_t)n * ((uint32_t)(2 * b + ((q >> 1) & 1)) + (uint32_t)n * (uint32_t)(2 * cz + (q >> 2)));
+#pragma unroll
+                for (int l = 0; l < 3; ++l) x[l * nn + u] = 0.f;
+            }
+        } else {
+            const Nbr o = nbr_of(i, j, kk, n);
+            float ko[8];
+            load_k8(k, o, ko);
+            NodeCoef<float> cf;
+            node_coefs(ko, cf);
+#pragma unroll
+            for (int l = 0; l < 3; ++l) {
+                const float ax = stencil_node<float, float>(cf, o, x + l * nn);
+                x[l * nn + v] += dv * (f[l * nn + v] - ax);
+            }
+        }
+        if (DOT) {
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+                const uint32_t u = (uint32_t)(2 * a + (q & 1)) +
+                                   (uint32_t)n * ((uint32_t)(2 * b + ((q >> 1) & 1)) + (uint32_t)n * (uint32_t)(2 * cz + (q >> 2)));
+#pragma unroll
+                for (int l = 0; l < 3; ++l) acc[l] += (double)f[l * nn + u] * (double)x[l * nn + u];
+            }
+        }
+    }
+    if (DOT) block_partials_at<3>(acc, partials, blockIdx.x);
+}
+
+// nu sweeps of 8-colour Gauss-Seidel on a level, forward (colours 0..7) or
+// backward (7..0); from_zero: x starts at 0 (forward only).  With partials the
+// last pass also sums f . x per block (at most kMaxBlocks blocks, each
+// striding over the cells); returns that pass's block count.
+int launch_mg_gs(int n, int nu, bool forward, bool from_zero, const float* dinv, const float* f, const float* k,
+                 float* x, double* partials, hipStream_t s) {
+    const int h = n / 2;
+    const int grid = grid_for((int64_t)h * h * h, kMaxBlocks);
+    for (int sw = 0; sw < nu; ++sw)
+        for (int q = 0; q < 8; ++q) {
+            const int color = forward ? q : 7 - q;
+            const bool first = from_zero && sw == 0 && q == 0;
+            const bool dot = partials && sw == nu - 1 && q == 7;
+            if (first)
+                hipLaunchKernelGGL((k_mg_gs<true, false>), dim3(grid), dim3(kBlock), 0, s, n, color, dinv, f, k, x,
+                                   (double*)nullptr);
+            else if (dot)
+                hipLaunchKernelGGL((k_mg_gs<false, true>), dim3(grid), dim3(kBlock), 0, s, n, color, dinv, f, k, x,
+                                   partials);
+            else
+                hipLaunchKernelGGL((k_mg_gs<false, false>), dim3(grid), dim3(kBlock), 0, s, n, color, dinv, f, k, x,
+                                   (double*)nullptr);
+        }
+    return grid;
+}
+
 // The last two levels in one block (the second-coarsest level has at most
 // 8^3 = 512 nodes, one thread each, everything in LDS): the same steps as the
 // level kernels -- nu damped Jacobi steps from zero, the residual, its
@@ -278,9 +366,11 @@ __device__ __forceinline__ void tail_apply(int n, int i, int j, int kk, const fl
 // its restriction, the direct coarse solve, interpolation and correction, nu
 // steps.  f has pitch fp (global memory or LDS); k and D^-1 come from global
 // memory.  The result is left in sx[return value].
+// gs: 8-colour Gauss-Seidel sweeps in place (colours 0..7 before the coarse
+// correction, 7..0 after it) instead of damped Jacobi steps.
 __device__ __forceinline__ int mid_cycle(int n, int nu, const float* f, int fp, const float* __restrict__ k,
                          const float* __restrict__ dinv, const float* __restrict__ minv, float* sk,
-                         float (*sx)[3][kMgTailMax], float (*sc)[3][kMgCoarseMax]) {
+                         float (*sx)[3][kMgTailMax], float (*sc)[3][kMgCoarseMax], bool gs) {
     const int N = n * n * n, nc = n / 2, Nc = nc * nc * nc;
     const int v = threadIdx.x;
     const bool own = v < N;
@@ -301,14 +391,35 @@ __device__ __forceinline__ int mid_cycle(int n, int nu, const float* f, int fp, 
     __syncthreads();
     int cur = 0;
     float y[3];
-    for (int it = 1; it < nu; ++it) {
-        if (own) {
-            tail_apply<kMgTailMax>(n, i, j, kk, sk, sx[cur], y);
+    const int colour = own ? (i & 1) + 2 * (j & 1) + 4 * (kk & 1) : -1;
+    const float dv = own ? dinv[v] : 0.f;
+    // one colour of Gauss-Seidel in place on sx[0]
+    auto gs_colour = [&](int q) {
+        if (colour == q) {
+            tail_apply<kMgTailMax>(n, i, j, kk, sk, sx[0], y);
 #pragma unroll
-            for (int l = 0; l < 3; ++l) sx[cur ^ 1][l][v] = sx[cur][l][v] + wd * (fv[l] - y[l]);
+            for (int l = 0; l < 3; ++l) sx[0][l][v] += dv * (fv[l] - y[l]);
         }
         __syncthreads();
-        cur ^= 1;
+    };
+    if (gs) {
+        if (own) {
+#pragma unroll
+            for (int l = 0; l < 3; ++l) sx[0][l][v] = 0.f;
+        }
+        __syncthreads();
+        for (int it = 0; it < nu; ++it)
+            for (int q = 0; q < 8; ++q) gs_colour(q);
+    } else {
+        for (int it = 1; it < nu; ++it) {
+            if (own) {
+                tail_apply<kMgTailMax>(n, i, j, kk, sk, sx[cur], y);
+#pragma unroll
+                for (int l = 0; l < 3; ++l) sx[cur ^ 1][l][v] = sx[cur][l][v] + wd * (fv[l] - y[l]);
+            }
+            __syncthreads();
+            cur ^= 1;
+        }
     }
     // residual into the other buffer, then its restriction to the coarsest level
     if (own) {
@@ -356,6 +467,11 @@ __device__ __forceinline__ int mid_cycle(int n, int nu, const float* f, int fp, 
         }
     }
     __syncthreads();
+    if (gs) {
+        for (int it = 0; it < nu; ++it)
+            for (int q = 7; q >= 0; --q) gs_colour(q);
+        return 0;
+    }
     for (int it = 0; it < nu; ++it) {
         if (own) {
             tail_apply<kMgTailMax>(n, i, j, kk, sk, sx[cur], y);
@@ -370,12 +486,13 @@ __device__ __forceinline__ int mid_cycle(int n, int nu, const float* f, int fp, 
 
 __global__ void __launch_bounds__(kMgTailMax) k_mg_tail(int n, int nu, const float* __restrict__ f,
                                                        const float* __restrict__ k, const float* __restrict__ dinv,
-                                                       const float* __restrict__ minv, float* __restrict__ xout) {
+                                                       const float* __restrict__ minv, float* __restrict__ xout,
+                                                       int gs) {
     __shared__ float sk[kMgTailMax];
     __shared__ float sx[2][3][kMgTailMax];
     __shared__ float sc[2][3][kMgCoarseMax];
     const int N = n * n * n;
-    const int cur = mid_cycle(n, nu, f, N, k, dinv, minv, sk, sx, sc);
+    const int cur = mid_cycle(n, nu, f, N, k, dinv, minv, sk, sx, sc, gs != 0);
     const int v = threadIdx.x;
     if (v < N) {
 #pragma unroll
@@ -384,8 +501,8 @@ __global__ void __launch_bounds__(kMgTailMax) k_mg_tail(int n, int nu, const flo
 }
 
 void launch_mg_tail(int n, int nu, const float* f, const float* k, const float* dinv, const float* minv, float* x,
-                    hipStream_t s) {
-    hipLaunchKernelGGL(k_mg_tail, dim3(1), dim3(kMgTailMax), 0, s, n, nu, f, k, dinv, minv, x);
+                    bool gs, hipStream_t s) {
+    hipLaunchKernelGGL(k_mg_tail, dim3(1), dim3(kMgTailMax), 0, s, n, nu, f, k, dinv, minv, x, gs ? 1 : 0);
 }
 
 void launch_mg_coarsen(int nc, const float* kf, float* kc, float* dinv_c, hipStream_t s) {
@@ -427,7 +544,10 @@ int mg_vcycle(const MgHierarchy& H, double* partials, int max_blocks, hipStream_
         const MgLevel& a = H.lv[l];
         const int nu = l == 0 ? H.sweeps : H.coarse_sweeps;
         int c = 0;
-        if (nu == 1) {
+        if (H.gs) {  // nu forward sweeps in place on x[0], then the residual
+            launch_mg_gs(a.n, nu, true, true, a.dinv, a.f, a.k, a.x[0], nullptr, s);
+            launch_mg_march(a.n, a.tile, false, MG_RESID, a.x[0], a.dinv, a.f, a.k, a.t, nullptr, s);
+        } else if (nu == 1) {
             launch_mg_march(a.n, a.tile, true, MG_RESID, nullptr, a.dinv, a.f, a.k, a.t, nullptr, s);
         } else {
             launch_mg_march(a.n, a.tile, true, MG_RELAX, nullptr, a.dinv, a.f, a.k, a.x[0], nullptr, s);
@@ -442,7 +562,7 @@ int mg_vcycle(const MgHierarchy& H, double* partials, int max_blocks, hipStream_
     }
     if (tail) {
         const MgLevel& t = H.lv[L - 2];
-        launch_mg_tail(t.n, H.coarse_sweeps, t.f, t.k, t.dinv, H.minv, t.x[0], s);
+        launch_mg_tail(t.n, H.coarse_sweeps, t.f, t.k, t.dinv, H.minv, t.x[0], H.gs, s);
         cur[L - 2] = 0;
     } else {
         const MgLevel& cl = H.lv[L - 1];
@@ -456,6 +576,13 @@ int mg_vcycle(const MgHierarchy& H, double* partials, int max_blocks, hipStream_
         const MgLevel& a = H.lv[l];
         const int nu = l == 0 ? H.sweeps : H.coarse_sweeps;
         int c = cur[l];
+        if (H.gs) {  // x += P x_c, then nu backward sweeps (the adjoint of the way down)
+            launch_mg_prolong(H.lv[l + 1].n, H.lv[l + 1].x[cur[l + 1]], a.x[0], nullptr, nullptr, s);
+            const int g = launch_mg_gs(a.n, nu, false, false, a.dinv, a.f, a.k, a.x[0], l == 0 ? partials : nullptr, s);
+            if (l == 0) nb = g;
+            cur[l] = 0;
+            continue;
+        }
         launch_mg_prolong(H.lv[l + 1].n, H.lv[l + 1].x[cur[l + 1]], a.x[c], nu == 1 ? a.f : nullptr,
                           nu == 1 ? a.dinv : nullptr, s);
         for (int it = 0; it < nu; ++it) {

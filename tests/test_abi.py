@@ -220,3 +220,14 @@ def test_create_rejects_bad_move_floor(L, move_min):
     h = ctypes.c_void_p()
     assert L.otm_create(ctypes.byref(p), None, ctypes.byref(o), None, None, ctypes.byref(h)) == N.OTM_EINVAL
     assert not h.value
+
+
+def test_multigrid_smoother_rejected(L):
+    from paper_2405_19991_amd import _native as N
+    p = N.Problem()
+    p.n, p.k0, p.kmin, p.penal, p.filter_radius, p.vf = 16, 1.0, 1e-3, 3.0, 1.5, 0.3
+    s, o, g = N.default_options()
+    assert s.mg_smoother == N.OTM_MG_JACOBI
+    s.precision, s.preconditioner, s.mg_smoother = N.OTM_MIXED, N.OTM_PRECOND_MG, 2
+    h = ctypes.c_void_p()
+    assert L.otm_create(ctypes.byref(p), ctypes.byref(s), None, None, None, ctypes.byref(h)) == N.OTM_EINVAL
