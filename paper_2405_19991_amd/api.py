@@ -331,12 +331,18 @@ def dumps_log(log) -> str:
 class Batch:
     """Many independent cells of uneven (even) n, stepped together: every
     phase of a design iteration is one launch over all designs, and PCG
-    chunks replay a captured hipGraph.  float64 path."""
+    chunks replay a captured hipGraph.  float64 path.
+
+    iteration: "auto" (the autotuner picks the fused single-pass or the
+    two-pass PCG iteration; with autotune off, the two-pass one), "fused" or
+    "two_pass"."""
+
+    ITERATIONS = {"auto": 0, "fused": 4, "two_pass": 1}
 
     def __init__(self, problems: Sequence[Dict[str, object]], tol: float = 1e-6, max_iter: int = 20000,
                  check_every: int = 16, guess: str = "zero", move: float = 0.05, eta: float = 0.5, move_min: float = 0.0,
                  rho_min: float = 1e-3, governor: Optional[Dict[str, float]] = None, autotune: bool = True,
-                 tile_tx: int = 0, tile_tz: int = 0, stream=None):
+                 tile_tx: int = 0, tile_tz: int = 0, iteration: str = "auto", stream=None):
         L = N.lib()
         arr = (N.Problem * len(problems))()
         self.ns = []
@@ -358,6 +364,7 @@ class Batch:
         s.guess = {"zero": N.OTM_GUESS_ZERO, "previous": N.OTM_GUESS_PREVIOUS}[guess]
         s.tol, s.max_iter, s.check_every = float(tol), int(max_iter), int(check_every)
         s.autotune, s.tile_tx, s.tile_tz = int(bool(autotune)), int(tile_tx), int(tile_tz)
+        s.kernel_variant = self.ITERATIONS[iteration]
         o.move, o.eta, o.rho_min, o.move_min = float(move), float(eta), float(rho_min), float(move_min)
         for key, val in (governor or {}).items():
             setattr(g, key, val)
@@ -413,9 +420,10 @@ class Batch:
         return out
 
     def info(self) -> Dict[str, float]:
-        a = np.zeros(8)
+        a = np.zeros(9)
         self._chk(self._L.otm_batch_info(self._h, _ptr(a)))
-        keys = ["designs", "cells", "work_items", "tile_tx", "tile_tz", "tuned_pass_us", "solve_ms", "step_ms"]
+        keys = ["designs", "cells", "work_items", "tile_tx", "tile_tz", "tuned_iteration_us", "solve_ms", "step_ms",
+                "fused"]
         return dict(zip(keys, a.tolist()))
 
     def governor_state(self, d: int) -> List[float]:

@@ -3,11 +3,12 @@
 // All designs of a batch share one set of arenas; every phase of a design
 // iteration is one launch over the batch's work list (otm_kernels.hip,
 // otm_stencil.hip, otm_march2.hip), with per-design device scalars and a
-// per-design finalize.  A chunk of PCG iterations (direction+operator pass,
-// finalize, update, finalize, repeated) is captured once as a hipGraph and
-// replayed until every design has converged; the tile width and march length
-// of the batched operator pass are chosen by timing the candidates on the
-// batch itself.
+// per-design finalize.  A chunk of PCG iterations -- the fused single pass
+// with its per-design finalize (otm_fused.hip), or the two-pass iteration
+// (direction+operator pass, finalize, update, finalize) -- is captured once
+// as a hipGraph and replayed until every design has converged; the
+// iteration kind, tile width and march length are chosen by timing whole
+// iterations of the candidates on the batch itself.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -51,6 +52,9 @@ struct otm_batch {
     // arenas
     double *rho = nullptr, *rhof = nullptr, *k = nullptr, *dinv = nullptr, *b = nullptr, *x = nullptr;
     double *st = nullptr, *sens = nullptr, *ocq = nullptr, *r = nullptr, *p[2] = {nullptr, nullptr}, *q = nullptr;
+    double *r2 = nullptr, *q2 = nullptr;  // second r, q of the fused iteration (ping-pong)
+    bool fused = false;                   // fused single-pass iteration chosen
+    int fbuf = 0;                         // fused iteration: which r, q, p the next pass reads
     W6* dw6 = nullptr;
     double* dvstar = nullptr;
     double* dmove = nullptr;  // OC move limit per design
@@ -147,13 +151,13 @@ void build_tables(otm_batch* c, int wx, int tz) {
     (void)hipStreamSynchronize(c->stream);
 }
 
-void march_pass(otm_batch* c, const double* po, double* pn) {
+void march_pass(otm_batch* c, const double* po, double* pn, bool fin) {
     if (c->wx == 32)
         launch_b_dir_march2<32, 8>(c->tab, c->march_grid, c->r, c->dinv, po, pn, c->k, c->q, c->partials, c->sc,
-                                   c->stream);
+                                   fin, c->stream);
     else
         launch_b_dir_march2<16, 16>(c->tab, c->march_grid, c->r, c->dinv, po, pn, c->k, c->q, c->partials, c->sc,
-                                    c->stream);
+                                    fin, c->stream);
 }
 
 // check_every PCG iterations (even, so the direction buffers end where they began)
@@ -161,9 +165,22 @@ void pcg_chunk(otm_batch* c) {
     for (int it = 0; it < c->so.check_every; ++it) {
         double* po = c->p[c->pbuf];
         double* pn = c->p[c->pbuf ^ 1];
-        march_pass(c, po, pn);
-        launch_b_update_vec(c->tab, c->update_grid, c->x, c->r, pn, c->q, c->dinv, c->partials, c->sc, c->stream);
+        march_pass(c, po, pn, true);
+        launch_b_update_vec(c->tab, c->update_grid, c->x, c->r, pn, c->q, c->dinv, c->partials, c->sc, true,
+                            c->stream);
         c->pbuf ^= 1;
+    }
+}
+
+// check_every fused passes (even: the buffers end where they began)
+void fused_chunk(otm_batch* c) {
+    double* R[2] = {c->r, c->r2};
+    double* Q[2] = {c->q, c->q2};
+    for (int it = 0; it < c->so.check_every; ++it) {
+        const int cur = c->fbuf, nx = cur ^ 1;
+        launch_b_fused(c->tab, c->wx, c->march_grid, R[cur], Q[cur], c->p[cur], R[nx], Q[nx], c->p[nx], c->x, c->dinv,
+                       c->k, c->partials, c->sc, cur, true, c->stream);
+        c->fbuf = nx;
     }
 }
 
@@ -199,25 +216,61 @@ int max_iters(const otm_batch* c) {
 
 int run_chunk(otm_batch* c) {
     if (!c->use_graph) {
-        pcg_chunk(c);
+        if (c->fused)
+            fused_chunk(c);
+        else
+            pcg_chunk(c);
         return blaunch_ok(c, "pcg chunk");
     }
     if (!c->gexec) {
-        const int pb = c->pbuf;
+        const int pb = c->pbuf, fb = c->fbuf;
         BCHK(c, hipStreamBeginCapture(c->stream, hipStreamCaptureModeThreadLocal));
-        pcg_chunk(c);
+        if (c->fused)
+            fused_chunk(c);
+        else
+            pcg_chunk(c);
         hipGraph_t g = nullptr;
         BCHK(c, hipStreamEndCapture(c->stream, &g));
         c->graph = g;
         BCHK(c, hipGraphInstantiate(&c->gexec, c->graph, nullptr, nullptr, 0));
         c->pbuf = pb;  // capture did not run anything
+        c->fbuf = fb;
     }
     BCHK(c, hipGraphLaunch(c->gexec, c->stream));
     // the chunk has an even number of iterations: pbuf is unchanged
     return OTM_OK;
 }
 
+// The fused iteration (one pass and one per-design finalize per iteration);
+// converged designs are confirmed with their true residual, and loads that
+// miss the tolerance restart.
+int solve_fused(otm_batch* c, bool x_zero) {
+    int rc;
+    if ((rc = reset_solver(c))) return rc;
+    if (x_zero) BCHK(c, hipMemsetAsync(c->x, 0, (size_t)3 * c->total * sizeof(double), c->stream));
+    c->fbuf = 0;
+    launch_b_residual_f(c->tab, c->k, c->b, c->x, c->r, nullptr, c->dinv, true, x_zero ? 1 : 0, c->partials, c->sc,
+                        c->stream);
+    if ((rc = blaunch_ok(c, "residual"))) return rc;
+    if ((rc = sync_sc(c))) return rc;
+    while (!all_inactive(c) && max_iters(c) < c->so.max_iter) {
+        if ((rc = run_chunk(c))) return rc;
+        if ((rc = sync_sc(c))) return rc;
+        if (all_inactive(c)) {
+            double* R[2] = {c->r, c->r2};
+            double* Q[2] = {c->q, c->q2};
+            launch_b_residual_f(c->tab, c->k, c->b, c->x, R[c->fbuf], Q[c->fbuf], c->dinv, false, 0, c->partials,
+                                c->sc, c->stream);
+            if ((rc = sync_sc(c))) return rc;
+        }
+    }
+    launch_b_sum3(c->tab, c->x, 0, c->partials, c->sc, c->stream);
+    launch_b_sub_mean3(c->tab, c->x, 0, c->sc, c->stream);
+    return blaunch_ok(c, "project");
+}
+
 int solve(otm_batch* c, bool x_zero) {
+    if (c->fused) return solve_fused(c, x_zero);
     int rc;
     if ((rc = reset_solver(c))) return rc;
     if (x_zero) BCHK(c, hipMemsetAsync(c->x, 0, (size_t)3 * c->total * sizeof(double), c->stream));
@@ -239,16 +292,33 @@ int solve(otm_batch* c, bool x_zero) {
     return blaunch_ok(c, "project");
 }
 
-// Time the batched operator pass for a (tile width, march length) candidate.
-double time_candidate(otm_batch* c, int wx, int tz) {
+// Time one PCG iteration of a (tile width, march length) candidate: the
+// fused pass, or the direction+operator pass and the update.  The per-design
+// finalizes (one block per design) are left out of both kinds, so that every
+// timed pass runs with the same all-active state.  The fused kind needs at
+// most kMaxBlocks work items.
+double time_candidate(otm_batch* c, int wx, int tz, bool fused) {
     build_tables(c, wx, tz);
+    if (fused && (c->tab.mb_total > kMaxBlocks || !c->r2)) return 1e30;
+    auto iteration = [&](int par) {
+        if (fused) {
+            launch_b_fused(c->tab, c->wx, c->march_grid, par ? c->r2 : c->r, par ? c->q2 : c->q, c->p[par],
+                           par ? c->r : c->r2, par ? c->q : c->q2, c->p[par ^ 1], c->x, c->dinv, c->k, c->partials,
+                           c->sc, par, false, c->stream);
+        } else {
+            march_pass(c, c->p[par], c->p[par ^ 1], false);
+            launch_b_update_vec(c->tab, c->update_grid, c->x, c->r, c->p[par ^ 1], c->q, c->dinv, c->partials,
+                                c->sc, false, c->stream);
+        }
+    };
     hipEvent_t a, b;
     (void)hipEventCreate(&a);
     (void)hipEventCreate(&b);
-    march_pass(c, c->p[0], c->p[1]);
+    iteration(0);
+    iteration(1);
     (void)hipEventRecord(a, c->stream);
-    const int reps = 5;
-    for (int i = 0; i < reps; ++i) march_pass(c, c->p[0], c->p[1]);
+    const int reps = 6;
+    for (int i = 0; i < reps; ++i) iteration(i & 1);
     (void)hipEventRecord(b, c->stream);
     (void)hipEventSynchronize(b);
     float ms = 0.f;
@@ -269,8 +339,9 @@ int autotune_batch(otm_batch* c) {
     {
         std::lock_guard<std::mutex> g(g_btune_mu);
         auto it = g_btune.find(key);
-        if (it != g_btune.end()) {
-            build_tables(c, it->second.first, it->second.second);
+        if (it != g_btune.end()) {  // a negative width marks the fused iteration
+            build_tables(c, std::abs(it->second.first), it->second.second);
+            c->fused = it->second.first < 0;
             return OTM_OK;
         }
     }
@@ -283,15 +354,19 @@ int autotune_batch(otm_batch* c) {
         i = j;
     }
     {
-        std::vector<double> v(3);
+        std::vector<double> v(4);
         if (tune_cache_lookup(fkey, v)) {
             const int wx = (int)v[0], tz = (int)v[1];
+            const bool fused = v[2] != 0.0;
             if ((wx == 16 || wx == 32) && (tz == 4 || tz == 8 || tz == 16 || tz == 32)) {
                 build_tables(c, wx, tz);
-                c->tune_us = v[2];
-                std::lock_guard<std::mutex> g(g_btune_mu);
-                g_btune[key] = {wx, tz};
-                return OTM_OK;
+                if (!fused || (c->r2 && c->tab.mb_total <= kMaxBlocks)) {
+                    c->fused = fused;
+                    c->tune_us = v[3];
+                    std::lock_guard<std::mutex> g(g_btune_mu);
+                    g_btune[key] = {fused ? -wx : wx, tz};
+                    return OTM_OK;
+                }
             }
         }
     }
@@ -301,35 +376,42 @@ int autotune_batch(otm_batch* c) {
         std::memset(&c->h_sc[d], 0, head);
         for (int l = 0; l < 3; ++l) {
             c->h_sc[d].active[l] = 1;
+            c->h_sc[d].alpha[l] = 0.5;
             c->h_sc[d].beta[l] = 0.5;
             c->h_sc[d].rz[l] = 1.0;
         }
         BCHK(c, hipMemcpyAsync(&c->sc[d], &c->h_sc[d], head, hipMemcpyHostToDevice, c->stream));
     }
     const size_t v3 = (size_t)3 * c->total * sizeof(double), v1 = (size_t)c->total * sizeof(double);
-    BCHK(c, hipMemsetAsync(c->r, 0, v3, c->stream));
-    BCHK(c, hipMemsetAsync(c->q, 0, v3, c->stream));
+    for (double* v : {c->r, c->q, c->r2, c->q2, c->p[0], c->p[1], c->x})
+        if (v) BCHK(c, hipMemsetAsync(v, 0, v3, c->stream));
     BCHK(c, hipMemsetAsync(c->k, 0, v1, c->stream));
     BCHK(c, hipMemsetAsync(c->dinv, 0, v1, c->stream));
     int best_wx = 16, best_tz = 8;
+    bool best_fused = false;
     double best = 1e30;
-    for (int wx : {16, 32})
-        for (int tz : {4, 8, 16, 32}) {
-            const double us = time_candidate(c, wx, tz);
-            if (us < 0.98 * best) {  // near-ties keep the earlier candidate
-                best = us;
-                best_wx = wx;
-                best_tz = tz;
+    const int fz_min = c->so.kernel_variant == 4 ? 1 : 0;  // variant 4: the fused iteration only
+    for (int fz = (c->r2 ? 1 : 0); fz >= fz_min; --fz)
+        for (int wx : {16, 32})
+            for (int tz : {4, 8, 16, 32}) {
+                const double us = time_candidate(c, wx, tz, fz != 0);
+                if (us < 0.98 * best) {  // near-ties keep the earlier candidate
+                    best = us;
+                    best_wx = wx;
+                    best_tz = tz;
+                    best_fused = fz != 0;
+                }
             }
-        }
     BCHK(c, hipMemsetAsync(c->p[0], 0, v3, c->stream));
     BCHK(c, hipMemsetAsync(c->p[1], 0, v3, c->stream));
+    BCHK(c, hipMemsetAsync(c->x, 0, v3, c->stream));
     build_tables(c, best_wx, best_tz);
+    c->fused = best_fused;
     BCHK(c, hipStreamSynchronize(c->stream));
     c->tune_us = best;
-    tune_cache_store(fkey, {(double)best_wx, (double)best_tz, best});
+    tune_cache_store(fkey, {(double)best_wx, (double)best_tz, best_fused ? 1.0 : 0.0, best});
     std::lock_guard<std::mutex> g(g_btune_mu);
-    g_btune[key] = {best_wx, best_tz};
+    g_btune[key] = {best_fused ? -best_wx : best_wx, best_tz};
     return OTM_OK;
 }
 
@@ -337,7 +419,8 @@ void free_batch(otm_batch* c) {
     if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
     if (c->graph) (void)hipGraphDestroy(c->graph);
     void* bufs[] = {c->rho, c->rhof, c->k, c->dinv, c->b, c->x, c->st, c->sens, c->ocq, c->r, c->p[0], c->p[1], c->q,
-                    c->dw6, c->dvstar, c->dmove, c->partials, c->sc, c->ddesc, c->eb_design, c->mb_design};
+                    c->r2, c->q2, c->dw6, c->dvstar, c->dmove, c->partials, c->sc, c->ddesc, c->eb_design,
+                    c->mb_design};
     for (void* p : bufs)
         if (p) (void)hipFree(p);
     if (c->h_sc) (void)hipHostFree(c->h_sc);
@@ -375,7 +458,7 @@ int otm_batch_create(const otm_problem* problems, int32_t count, const otm_solve
     if (oc) c->oc = *oc;
     if (gov) c->go = *gov;
     if (c->so.precision != OTM_FP64 || c->so.preconditioner != OTM_PRECOND_JACOBI || !(c->so.tol > 0.0) ||
-        c->so.max_iter < 1 || c->so.check_every < 1) {
+        c->so.max_iter < 1 || c->so.check_every < 1 || c->so.kernel_variant < 0 || c->so.kernel_variant > 5) {
         const int code =
             (c->so.precision != OTM_FP64 || c->so.preconditioner != OTM_PRECOND_JACOBI) ? OTM_EUNSUPPORTED : OTM_EINVAL;
         delete c;
@@ -431,11 +514,18 @@ int otm_batch_create(const otm_problem* problems, int32_t count, const otm_solve
     rc = rc ? rc : balloc(c, &c->p[0], 3 * total);
     rc = rc ? rc : balloc(c, &c->p[1], 3 * total);
     rc = rc ? rc : balloc(c, &c->q, 3 * total);
+    // the fused iteration (kernel variant 0 with autotuning, or 4) ping-pongs r and q
+    const bool may_fuse = c->so.kernel_variant == 4 || (c->so.kernel_variant == 0 && c->so.autotune);
+    if (may_fuse) {
+        rc = rc ? rc : balloc(c, &c->r2, 3 * total);
+        rc = rc ? rc : balloc(c, &c->q2, 3 * total);
+    }
     rc = rc ? rc : balloc(c, &c->dw6, count);
     rc = rc ? rc : balloc(c, &c->dvstar, count);
     rc = rc ? rc : balloc(c, &c->dmove, count);
     c->partial_slots = (int)std::max(max_eb, max_mb);
-    rc = rc ? rc : balloc(c, &c->partials, (int64_t)c->partial_slots * kMaxReduce);
+    rc = rc ? rc : balloc(c, &c->partials, std::max((int64_t)c->partial_slots * kMaxReduce,
+                                                    may_fuse ? 2 * kFusedStride : (int64_t)0));
     rc = rc ? rc : balloc(c, &c->sc, count);
     rc = rc ? rc : balloc(c, &c->ddesc, count);
     rc = rc ? rc : balloc(c, &c->eb_design, max_eb);
@@ -462,6 +552,7 @@ int otm_batch_create(const otm_problem* problems, int32_t count, const otm_solve
     } else {
         const int wx = c->so.tile_tx == 64 ? 32 : 16;
         build_tables(c, wx, c->so.tile_tz > 0 ? std::max(4, c->so.tile_tz) : 8);
+        c->fused = c->so.kernel_variant == 4 && c->r2 && c->tab.mb_total <= kMaxBlocks;
     }
     if (!rc && hipStreamSynchronize(c->stream) != hipSuccess) rc = OTM_EDEVICE;
     if (rc) {
@@ -628,7 +719,7 @@ int otm_batch_device_bytes(const otm_batch* c, int64_t* bytes) {
     return OTM_OK;
 }
 
-int otm_batch_info(const otm_batch* c, double info8[8]) {
+int otm_batch_info(const otm_batch* c, double info8[9]) {
     if (!c || !info8) return OTM_EINVAL;
     info8[0] = (double)c->count;
     info8[1] = (double)c->total;
@@ -638,6 +729,7 @@ int otm_batch_info(const otm_batch* c, double info8[8]) {
     info8[5] = c->tune_us;
     info8[6] = c->t_ms[1];
     info8[7] = c->t_ms[3];
+    info8[8] = c->fused ? 1.0 : 0.0;
     return OTM_OK;
 }
 

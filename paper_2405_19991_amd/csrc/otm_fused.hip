@@ -38,18 +38,14 @@ struct PreF {
     T hr[3], hq[3], hp[3], hdv, kh;                      // one halo node / element
 };
 
-// Partial sums per block, per load l: [l] p.q, [3+l] q.z, [6+l] q.D^-1 q,
-// [9+l] r.z, [12+l] r.r (r, z of the updated residual).
-constexpr int kFusedSums = 15;
-
-// Partial sums of a pass: value-major, one buffer per pass parity.
-constexpr int64_t kFusedStride = (int64_t)kFusedSums * kMaxBlocks;
-
 // CHAIN: the block first reduces the previous pass's partial sums (parity
-// par ^ 1) and advances the state itself; else it takes the state from the
-// scalar block.  Block 0 records the state it ran with as fs[par].
+// par ^ 1, nslots of them) and advances the state itself; else it takes the
+// state from the scalar block.  The design's first tile records the state it
+// ran with as fs[par].  tile: the tile (x, then y, then z) this call
+// computes; slot: where its partial sums go.
 template <typename T, int WX, int TY, bool ALL, bool CHAIN>
-__device__ __forceinline__ void fused_body(int n, int tz, int ntx, int nty, const T* __restrict__ r_in,
+__device__ __forceinline__ void fused_body(int tile, int slot, int nslots, bool first, int n, int tz, int ntx, int nty,
+                                           const T* __restrict__ r_in,
                                            const T* __restrict__ q_in, const T* __restrict__ p_in,
                                            T* __restrict__ r_out, T* __restrict__ q_out, T* __restrict__ p_out,
                                            T* __restrict__ x, const T* __restrict__ dinv, const T* __restrict__ k,
@@ -69,7 +65,7 @@ __device__ __forceinline__ void fused_body(int n, int tz, int ntx, int nty, cons
 
     const int tid = threadIdx.x;
     const int tx = tid % WX, ty = tid / WX;
-    int bid = xcd_tile(blockIdx.x, gridDim.x);  // tiles in x, then y, then z
+    int bid = tile;  // tiles in x, then y, then z
     const int bx = bid % ntx;
     bid /= ntx;
     const int by = bid % nty;
@@ -329,18 +325,18 @@ __device__ __forceinline__ void fused_body(int n, int tz, int ntx, int nty, cons
     __shared__ double tot[kFusedSums];
     auto take_state = [&]() {
         if (CHAIN) {
-            final_sums_vm<kFusedSums>(partials + (par ^ 1) * kFusedStride, gridDim.x, tot);
+            final_sums_vm<kFusedSums>(partials + (par ^ 1) * kFusedStride, nslots, tot);
             if (tid == 0) {
                 FusedState s;
                 fused_advance(sc->fs[par ^ 1], tot, s);
                 st_sh = s;
-                if (blockIdx.x == 0) sc->fs[par] = s;
+                if (first) sc->fs[par] = s;
             }
         } else if (tid == 0) {
             FusedState s;
             fused_state_of(sc, s);
             st_sh = s;
-            if (blockIdx.x == 0) sc->fs[par] = s;
+            if (first) sc->fs[par] = s;
         }
         __syncthreads();
 #pragma unroll
@@ -382,7 +378,7 @@ __device__ __forceinline__ void fused_body(int n, int tz, int ntx, int nty, cons
     double accd[kFusedSums];
 #pragma unroll
     for (int q = 0; q < kFusedSums; ++q) accd[q] = (double)acc[q];
-    block_partials_vm<kFusedSums>(accd, partials + par * kFusedStride, blockIdx.x);
+    block_partials_vm<kFusedSums>(accd, partials + par * kFusedStride, slot);
 }
 
 // Closes a chain of passes: reduces the last pass's partial sums, advances the
@@ -414,8 +410,9 @@ __global__ void __launch_bounds__(WX* TY) __attribute__((amdgpu_waves_per_eu(2))
                 const float* __restrict__ p_in, float* __restrict__ r_out, float* __restrict__ q_out,
                 float* __restrict__ p_out, float* __restrict__ x, const float* __restrict__ dinv,
                 const float* __restrict__ k, double* __restrict__ partials, Scalars* __restrict__ sc, int par) {
-    fused_body<float, WX, TY, ALL, CHAIN>(n, tz, ntx, nty, r_in, q_in, p_in, r_out, q_out, p_out, x, dinv, k,
-                                          partials, sc, par);
+    fused_body<float, WX, TY, ALL, CHAIN>(xcd_tile(blockIdx.x, gridDim.x), blockIdx.x, gridDim.x, blockIdx.x == 0, n, tz,
+                                          ntx, nty, r_in, q_in, p_in, r_out, q_out, p_out, x, dinv, k, partials, sc,
+                                          par);
 }
 
 template <int WX, int TY, bool ALL, bool CHAIN>
@@ -424,8 +421,9 @@ __global__ void __launch_bounds__(WX* TY)
                 const double* __restrict__ p_in, double* __restrict__ r_out, double* __restrict__ q_out,
                 double* __restrict__ p_out, double* __restrict__ x, const double* __restrict__ dinv,
                 const double* __restrict__ k, double* __restrict__ partials, Scalars* __restrict__ sc, int par) {
-    fused_body<double, WX, TY, ALL, CHAIN>(n, tz, ntx, nty, r_in, q_in, p_in, r_out, q_out, p_out, x, dinv, k,
-                                           partials, sc, par);
+    fused_body<double, WX, TY, ALL, CHAIN>(xcd_tile(blockIdx.x, gridDim.x), blockIdx.x, gridDim.x, blockIdx.x == 0, n,
+                                           tz, ntx, nty, r_in, q_in, p_in, r_out, q_out, p_out, x, dinv, k, partials,
+                                           sc, par);
 }
 
 template <typename T, int WX, int TY, bool ALL, bool CHAIN>
@@ -520,16 +518,18 @@ template void launch_fill_const<double>(double*, int64_t, double, hipStream_t);
 // r = b - A x with the float64 operator, stored as TR, with the sums the fused
 // iteration restarts from: per load [l] r.r (float64 r), [3+l] r.D^-1 r and
 // [9+l] q.D^-1 r (stored r), [6+l] b.b.  q may be null (start: no pending step).
+// (bid, nblk: this block's index and the block count of its design;
+// partials: slot bid of the design's range.)
 template <typename TR>
-__global__ void __launch_bounds__(kBlock)
-    k_residual_f(int n, const double* __restrict__ k, const double* __restrict__ b, const double* __restrict__ x,
-                 TR* __restrict__ r, const TR* __restrict__ q, const TR* __restrict__ dinv, int x_zero,
-                 double* __restrict__ partials) {
+__device__ __forceinline__ void b_residual_f(int bid, int nblk, int n, const double* __restrict__ k,
+                                             const double* __restrict__ b, const double* __restrict__ x,
+                                             TR* __restrict__ r, const TR* __restrict__ q,
+                                             const TR* __restrict__ dinv, int x_zero, double* __restrict__ partials) {
     const int64_t nn = (int64_t)n * n * n;
     double acc[12];
 #pragma unroll
     for (int c = 0; c < 12; ++c) acc[c] = 0.0;
-    for (int64_t v = (int64_t)blockIdx.x * kBlock + threadIdx.x; v < nn; v += (int64_t)gridDim.x * kBlock) {
+    for (int64_t v = (int64_t)bid * kBlock + threadIdx.x; v < nn; v += (int64_t)nblk * kBlock) {
         double ax[3] = {0.0, 0.0, 0.0};
         if (!x_zero) {
             int i, j, kk;
@@ -556,7 +556,102 @@ __global__ void __launch_bounds__(kBlock)
             if (q) acc[9 + l] += (double)q[l * nn + v] * zs;
         }
     }
-    block_partials<12>(acc, partials);
+    block_partials_at<12>(acc, partials, bid);
+}
+
+template <typename TR>
+__global__ void __launch_bounds__(kBlock)
+    k_residual_f(int n, const double* __restrict__ k, const double* __restrict__ b, const double* __restrict__ x,
+                 TR* __restrict__ r, const TR* __restrict__ q, const TR* __restrict__ dinv, int x_zero,
+                 double* __restrict__ partials) {
+    b_residual_f<TR>(blockIdx.x, gridDim.x, n, k, b, x, r, q, dinv, x_zero, partials);
+}
+
+// ---- batches of designs (float64) -------------------------------------------
+// The fused pass over a batch's work list of (design, tile) items: each block
+// walks items (contiguous ranges per XCD), the design's first tile records
+// its state, and item i's partial sums go to slot i (value-major, so the
+// batch needs at most kMaxBlocks items).  Every design and load may be
+// inactive (per-design state).
+template <int WX, int TY>
+__global__ void __launch_bounds__(WX* TY) kb_fused(BatchTab t, const double* __restrict__ r_in,
+                                                   const double* __restrict__ q_in, const double* __restrict__ p_in,
+                                                   double* __restrict__ r_out, double* __restrict__ q_out,
+                                                   double* __restrict__ p_out, double* __restrict__ x,
+                                                   const double* __restrict__ dinv, const double* __restrict__ k,
+                                                   double* __restrict__ partials, Scalars* __restrict__ sc, int par) {
+    for (int v = blockIdx.x; v < t.mb_total; v += gridDim.x) {
+        const int item = xcd_tile(v, t.mb_total);
+        const int d = t.mb_design[item];
+        const BatchDesc D = t.desc[d];
+        const int64_t o1 = D.off, o3 = 3 * D.off;
+        __syncthreads();  // the previous item's LDS rings are no longer read
+        fused_body<double, WX, TY, false, false>(item - D.mb_start, item, 0, item == D.mb_start, D.n, D.tz, D.ntx,
+                                                 D.nty, r_in + o3, q_in + o3, p_in + o3, r_out + o3, q_out + o3,
+                                                 p_out + o3, x + o3, dinv + o1, k + o1, partials, sc + d, par);
+    }
+}
+
+// Per design (one block each): reduce the pass's partial sums of the design's
+// items and advance its state (the batch form of k_fused_fin).
+__global__ void __launch_bounds__(kBlock) kb_fused_fin(BatchTab t, const double* __restrict__ partials,
+                                                       Scalars* __restrict__ sc, int par) {
+    const int d = blockIdx.x;
+    const BatchDesc D = t.desc[d];
+    __shared__ double tot[kFusedSums];
+    final_sums_vm<kFusedSums>(partials + par * kFusedStride + D.mb_start, D.mb_count, tot);
+    if (threadIdx.x != 0) return;
+    Scalars* s = sc + d;
+    FusedState st;
+    fused_advance(s->fs[par], tot, st);
+    for (int l = 0; l < 3; ++l) {
+        s->alpha[l] = st.alpha[l];
+        s->beta[l] = st.beta[l];
+        s->rz[l] = st.rz[l];
+        s->pq[l] = st.pq[l];
+        s->qdq[l] = st.qdq[l];
+        s->rr[l] = st.rr[l];
+        s->active[l] = st.active[l];
+        s->iters[l] = st.iters[l];
+    }
+}
+
+__global__ void __launch_bounds__(kBlock) kb_residual_f(BatchTab t, const double* __restrict__ k,
+                                                        const double* __restrict__ b, const double* __restrict__ x,
+                                                        double* __restrict__ r, const double* __restrict__ q,
+                                                        const double* __restrict__ dinv, int x_zero,
+                                                        double* __restrict__ partials) {
+    const int g = blockIdx.x;
+    const int d = t.eb_design[g];
+    const BatchDesc D = t.desc[d];
+    const int64_t o1 = D.off, o3 = 3 * D.off;
+    b_residual_f<double>(g - D.eb_start, D.eb_count, D.n, k + o1, b + o3, x + o3, r + o3, q ? q + o3 : nullptr,
+                         dinv + o1, x_zero, partials + (size_t)D.eb_start * 12);
+}
+
+template <int WX, int TY>
+static void launch_bf(const BatchTab& t, int grid, const double* r_in, const double* q_in, const double* p_in,
+                      double* r_out, double* q_out, double* p_out, double* x, const double* dinv, const double* k,
+                      double* partials, Scalars* sc, int par, hipStream_t s) {
+    hipLaunchKernelGGL((kb_fused<WX, TY>), dim3(grid), dim3(WX * TY), 0, s, t, r_in, q_in, p_in, r_out, q_out, p_out,
+                       x, dinv, k, partials, sc, par);
+}
+
+void launch_b_fused(const BatchTab& t, int wx, int grid, const double* r_in, const double* q_in, const double* p_in,
+                    double* r_out, double* q_out, double* p_out, double* x, const double* dinv, const double* k,
+                    double* partials, Scalars* sc, int par, bool fin, hipStream_t s) {
+    if (wx == 32)
+        launch_bf<32, 8>(t, grid, r_in, q_in, p_in, r_out, q_out, p_out, x, dinv, k, partials, sc, par, s);
+    else
+        launch_bf<16, 16>(t, grid, r_in, q_in, p_in, r_out, q_out, p_out, x, dinv, k, partials, sc, par, s);
+    if (fin) hipLaunchKernelGGL(kb_fused_fin, dim3(t.count), dim3(kBlock), 0, s, t, partials, sc, par);
+}
+
+void launch_b_residual_f(const BatchTab& t, const double* k, const double* b, const double* x, double* r,
+                         const double* q, const double* dinv, bool start, int x_zero, double* partials, Scalars* sc,
+                         hipStream_t s) {
+    hipLaunchKernelGGL(kb_residual_f, dim3(t.eb_total), dim3(kBlock), 0, s, t, k, b, x, r, q, dinv, x_zero, partials);
+    launch_b_finalize(t, start ? FIN_F_START : FIN_F_REFRESH, 0, partials, sc, 0.5, s);
 }
 
 template <typename TR>

@@ -15,10 +15,15 @@ namespace otm {
 constexpr int kBlock = 256;          // threads per block for node/element sweeps
 constexpr int kMaxReduce = 32;       // widest multi-value block reduction
 constexpr int kMaxBlocks = 4096;     // producer blocks per reduction (workspace rows)
+constexpr int kFusedSums = 15;       // partial sums per block of a fused PCG pass, per load l: [l] p.q,
+                                     // [3+l] q.z, [6+l] q.D^-1 q, [9+l] r.z, [12+l] r.r
 constexpr int kOcLevels = 5;         // bisection levels resolved per OC pass
 constexpr int kOcCands = (1 << kOcLevels) - 1;
 // passes that reach the bisection's 200-halving cap, plus the first and a spare
 constexpr int kOcMaxPasses = 200 / kOcLevels + 2;
+// partial sums of a fused pass: value-major (value v of slot b at v * kMaxBlocks + b),
+// one such region per pass parity
+constexpr int64_t kFusedStride = (int64_t)kFusedSums * kMaxBlocks;
 
 // State of the fused PCG iteration between passes (per load): the step and
 // direction weight a pass used, the last reduced dots, and the constants the
@@ -409,19 +414,33 @@ void launch_b_filter(const BatchTab& t, const double* in, double* out, hipStream
 void launch_b_oc_prepare(const BatchTab& t, const double* rho, const double* sens, double eta, double* q,
                          hipStream_t s);
 void launch_b_oc_init(const BatchTab& t, Scalars* sc, const double* vstar, double eta, hipStream_t s);
+// Batched fused PCG pass (float64), followed by its per-design finalize when
+// fin is set (a pass without it leaves every design's state as it was: the
+// autotuner times passes that way); the partials need 2 kFusedStride doubles
+// and the batch at most kMaxBlocks work items.
+void launch_b_fused(const BatchTab& t, int wx, int grid, const double* r_in, const double* q_in, const double* p_in,
+                    double* r_out, double* q_out, double* p_out, double* x, const double* dinv, const double* k,
+                    double* partials, Scalars* sc, int par, bool fin, hipStream_t s);
+// r = b - A x per design with the sums the fused iteration (re)starts from
+// (start: FIN_F_START, else FIN_F_REFRESH with the pending q).
+void launch_b_residual_f(const BatchTab& t, const double* k, const double* b, const double* x, double* r,
+                         const double* q, const double* dinv, bool start, int x_zero, double* partials, Scalars* sc,
+                         hipStream_t s);
 void launch_b_oc_pass(const BatchTab& t, const double* rho, const double* q, const double* moves, double rho_min,
                       double eta, double* partials, Scalars* sc, hipStream_t s);
 void launch_b_oc_apply(const BatchTab& t, double* rho, const double* q, double eta, const double* moves,
                        double rho_min, Scalars* sc, hipStream_t s);
 void launch_b_finalize(const BatchTab& t, int op, int which_mb, double* partials, Scalars* sc, double eta,
                        hipStream_t s);
-// z-march work-list launch (persistent blocks) and vector update, float64
+// z-march work-list launch (persistent blocks) and vector update, float64,
+// each followed by its per-design finalize when fin is set (without it every
+// design's state stays as it was: the autotuner times passes that way)
 template <int WX, int TY>
 void launch_b_dir_march2(const BatchTab& t, int grid, const double* r, const double* dinv, const double* p_old,
-                         double* p_new, const double* k, double* q, double* partials, const Scalars* sc,
+                         double* p_new, const double* k, double* q, double* partials, const Scalars* sc, bool fin,
                          hipStream_t s);
 void launch_b_update_vec(const BatchTab& t, int grid, double* x, double* r, const double* p, const double* q,
-                         const double* dinv, double* partials, const Scalars* sc, hipStream_t s);
+                         const double* dinv, double* partials, const Scalars* sc, bool fin, hipStream_t s);
 
 // Stateless operator y = A x (three loads)
 template <typename T>

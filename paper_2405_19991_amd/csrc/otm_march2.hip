@@ -544,16 +544,16 @@ __global__ void __launch_bounds__(WX* TY) kb_dir_march2(BatchTab t, const double
 
 template <int WX, int TY>
 void launch_b_dir_march2(const BatchTab& t, int grid, const double* r, const double* dinv, const double* p_old,
-                         double* p_new, const double* k, double* q, double* partials, const Scalars* sc,
+                         double* p_new, const double* k, double* q, double* partials, const Scalars* sc, bool fin,
                          hipStream_t s) {
     hipLaunchKernelGGL((kb_dir_march2<WX, TY>), dim3(grid), dim3(kBlock), 0, s, t, r, dinv, p_old, p_new, k, q,
                        partials, sc);
-    launch_b_finalize(t, FIN_PQ, 1, partials, const_cast<Scalars*>(sc), 0.5, s);
+    if (fin) launch_b_finalize(t, FIN_PQ, 1, partials, const_cast<Scalars*>(sc), 0.5, s);
 }
 
 template void launch_b_dir_march2<32, 8>(const BatchTab&, int, const double*, const double*, const double*, double*,
-                                         const double*, double*, double*, const Scalars*, hipStream_t);
+                                         const double*, double*, double*, const Scalars*, bool, hipStream_t);
 template void launch_b_dir_march2<16, 16>(const BatchTab&, int, const double*, const double*, const double*, double*,
-                                          const double*, double*, double*, const Scalars*, hipStream_t);
+                                          const double*, double*, double*, const Scalars*, bool, hipStream_t);
 
 }  // namespace otm

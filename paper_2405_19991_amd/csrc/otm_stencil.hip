@@ -587,9 +587,9 @@ __global__ void __launch_bounds__(kBlock) kb_update_vec(BatchTab t, double* __re
 }
 
 void launch_b_update_vec(const BatchTab& t, int grid, double* x, double* r, const double* p, const double* q,
-                         const double* dinv, double* partials, const Scalars* sc, hipStream_t s) {
+                         const double* dinv, double* partials, const Scalars* sc, bool fin, hipStream_t s) {
     hipLaunchKernelGGL(kb_update_vec, dim3(grid), dim3(kBlock), 0, s, t, x, r, p, q, dinv, partials, sc);
-    launch_b_finalize(t, FIN_UPDATE, 0, partials, const_cast<Scalars*>(sc), 0.5, s);
+    if (fin) launch_b_finalize(t, FIN_UPDATE, 0, partials, const_cast<Scalars*>(sc), 0.5, s);
 }
 
 }  // namespace otm

@@ -111,3 +111,72 @@ def test_batch_full_size_mix_matches_singles_and_oracle():
     rel = np.linalg.norm(np.array(recs[d]["kappa"]) - ref["kappa"]) / np.linalg.norm(ref["kappa"])
     print(f"design {d} (n=32): batch vs oracle {rel:.2e}", flush=True)
     assert rel <= 1e-8
+
+
+@pytest.mark.parametrize("tile_tx,tile_tz", [(32, 4), (64, 8)])
+def test_fused_iteration_matches_two_pass_and_singles(tile_tx, tile_tz):
+    """The batched fused single-pass iteration (one pass and one per-design
+    finalize per PCG step) against the batched two-pass iteration and
+    single-design contexts: same design histories to solve-tolerance
+    rounding, and the per-design iteration counts of a converged solve within
+    a few of the two-pass ones (the fused recurrence rounds differently)."""
+    from paper_2405_19991_amd import Batch, Homogenization
+    probs = problems([8, 16, 12, 16, 6], 21)
+    steps = 3
+    out = {}
+    for it in ("fused", "two_pass"):
+        with Batch(probs, tol=1e-10, autotune=False, tile_tx=tile_tx, tile_tz=tile_tz, iteration=it) as B:
+            assert B.info()["fused"] == (1.0 if it == "fused" else 0.0)
+            for d, p in enumerate(probs):
+                B.set_density(d, p["rho"])
+            recs = [B.step() for _ in range(steps)]
+            out[it] = (recs, [B.get_field(d, "rho") for d in range(len(probs))])
+    (rf, pf), (rt, pt) = out["fused"], out["two_pass"]
+    for s in range(steps):
+        for d in range(len(probs)):
+            np.testing.assert_allclose(rf[s][d]["kappa"], rt[s][d]["kappa"], rtol=1e-9, atol=1e-12)
+            assert rf[s][d]["g"] == pytest.approx(rt[s][d]["g"], rel=1e-8)
+            for a, b in zip(rf[s][d]["pcg_iters"], rt[s][d]["pcg_iters"]):
+                assert abs(a - b) <= max(3, 0.05 * b)
+    for a, b in zip(pf, pt):
+        np.testing.assert_allclose(a, b, rtol=0, atol=1e-8)
+    for d, p in enumerate(probs[:2]):
+        with Homogenization(p["n"], (1.0, 1e-3), p["target"], vf=p["vf"], tol=1e-10) as h:
+            h.set_density(p["rho"])
+            r = h.step()
+        np.testing.assert_allclose(rf[0][d]["kappa"], r["kappa"], rtol=1e-9, atol=1e-12)
+
+
+def test_fused_graph_replay_equals_eager():
+    """The captured fused chunk (ping-pong r, q, p) replayed, with host work
+    and synchronisation between replays, equals eager launches bit for bit."""
+    from paper_2405_19991_amd import Batch
+    probs = problems([16, 8, 12], 23)
+    res = []
+    for use_graph in (True, False):
+        with Batch(probs, tol=1e-9, autotune=False, tile_tz=8, iteration="fused") as B:
+            B.set_graph(use_graph)
+            for d, p in enumerate(probs):
+                B.set_density(d, p["rho"])
+            recs = [B.step() for _ in range(3)]
+            res.append((recs, [B.get_field(d, "rho") for d in range(len(probs))]))
+    (rg, pg), (re_, pe) = res
+    for s in range(3):
+        for d in range(len(probs)):
+            assert rg[s][d]["kappa"] == re_[s][d]["kappa"]
+            assert rg[s][d]["pcg_iters"] == re_[s][d]["pcg_iters"]
+    for a, b in zip(pg, pe):
+        np.testing.assert_array_equal(a, b)
+
+
+def test_fused_first_tensor_matches_oracle():
+    from paper_2405_19991_amd import Batch
+    probs = problems([10, 6, 14], 29)
+    with Batch(probs, tol=1e-11, autotune=False, iteration="fused") as B:
+        for d, p in enumerate(probs):
+            B.set_density(d, p["rho"])
+        recs = B.step()
+    for d, p in enumerate(probs):
+        ref = O.homogenize(p["rho"], O.Params(tol=1e-13))
+        rel = np.linalg.norm(np.array(recs[d]["kappa"]) - ref["kappa"]) / np.linalg.norm(ref["kappa"])
+        assert rel <= 1e-9
