@@ -172,15 +172,16 @@ def cpu_baseline(iters_128: int = 1, iters_64: int = 5, iters_16: int = 30):
     }
 
 
-def batch_leg(steps: int, log):
-    """64 designs, n in {32, 48, 64} (seeded mix), FP64, tol 1e-6: one batched
-    design iteration per step (work-list launches, hipGraph PCG chunks)."""
+def batch_leg(steps: int, log, precision: str = "fp64"):
+    """64 designs, n in {32, 48, 64} (seeded mix), FP64 or mixed, tol 1e-6: one
+    batched design iteration per step (work-list launches, hipGraph PCG
+    chunks)."""
     import time as _t
     import synth
     from paper_2405_19991_amd import Batch
     ws = synth.config4()
     probs = [dict(n=w.n, target=w.target, vf=w.vf) for w in ws]
-    B = Batch(probs, tol=1e-6)
+    B = Batch(probs, tol=1e-6, precision=precision)
     for d, w in enumerate(ws):
         B.set_density(d, w.rho0)
     B.step()  # warm-up (graph capture)
@@ -194,8 +195,9 @@ def batch_leg(steps: int, log):
     info = B.info()
     dev_bytes = B.device_bytes()
     B.close()
-    return {"workload": "batch64_n32-64_fp64", "designs": len(ws), "cells": int(info["cells"]), "device_bytes": dev_bytes,
-            "s_per_oc_iter": (t1 - t0) / steps, "pcg_dof_updates_per_s": iters / (t1 - t0),
+    return {"workload": f"batch64_n32-64_{precision}", "designs": len(ws), "cells": int(info["cells"]),
+            "device_bytes": dev_bytes, "s_per_oc_iter": (t1 - t0) / steps, "pcg_dof_updates_per_s": iters / (t1 - t0),
+            "iteration": "fused" if info["fused"] else "two_pass", "refreshes": int(info["refreshes"]),
             "tile_tx": int(info["tile_tx"]), "tile_tz": int(info["tile_tz"]), "work_items": int(info["work_items"]),
             "steps": steps}
 
@@ -647,6 +649,7 @@ def main():
         out["full_run"] = full_run_leg(w, log)
     if not args.no_batch:
         out["batch"] = batch_leg(args.batch_steps, log)
+        out["batch_mixed"] = batch_leg(args.batch_steps, log, "mixed")
     if not args.no_configs:
         out["configs"] = config_legs(5, log)
     if not args.no_gallery:

@@ -433,15 +433,20 @@ int otm_device_bytes(const otm_ctx* ctx, int64_t* bytes);
  * Many independent cells in one set of device arenas; every phase of a design
  * iteration is one launch over all designs (per-design scalars and
  * reductions), and a chunk of PCG iterations is captured once as a hipGraph
- * and replayed until every design has converged.  float64 path only; every n
- * must be even (4..1024).  Problems may differ in n, target, vf and material
- * constants; solver / OC / governor options are shared.  autotune (solver
- * options) times whole PCG iterations of the fused single-pass iteration and
- * of the two-pass iteration over tile widths and march lengths at creation
- * and keeps the fastest (kernel_variant 4: the fused iteration only; other
- * variants, or autotune off with kernel_variant 0: the two-pass iteration).
- * The fused iteration needs at most 4096 (design, tile) work items.  Errors
- * as for contexts; otm_batch_last_error gives details. */
+ * and replayed until every design has converged.  Every n must be even
+ * (4..1024).  Problems may differ in n, target, vf and material constants;
+ * solver / OC / governor options are shared.  Precision OTM_FP64, or
+ * OTM_MIXED (float32 operator and Krylov vectors, float64 solution, dots and
+ * residual refreshes, as for contexts; fused iteration only, kernel_variant 0
+ * or 4); Jacobi preconditioner only (else OTM_EUNSUPPORTED).  A batch's
+ * solve skips the work of designs whose three loads have stopped.  autotune
+ * (solver options) times whole PCG iterations of the fused single-pass
+ * iteration and of the two-pass iteration over tile widths and march lengths
+ * at creation and keeps the fastest (kernel_variant 4 or OTM_MIXED: the fused
+ * iteration only; other variants, or autotune off with kernel_variant 0: the
+ * two-pass iteration).  The fused iteration needs at most 4096 (design, tile)
+ * work items (OTM_MIXED without such a tile: OTM_EUNSUPPORTED).  Errors as
+ * for contexts; otm_batch_last_error gives details. */
 typedef struct otm_batch otm_batch;
 int otm_batch_create(const otm_problem* problems, int32_t count, const otm_solver_opts* solver,
                      const otm_oc_opts* oc, const otm_governor_opts* gov, void* stream, otm_batch** out);
@@ -457,8 +462,9 @@ int otm_batch_step(otm_batch* batch, otm_iter_record* recs);
 int otm_batch_set_graph(otm_batch* batch, int32_t use_graph);
 /* [designs, total cells, operator work items, tile width, march length of
  *  design 0, tuned PCG iteration us, last solve ms, last step ms, 1 if the
- *  fused single-pass iteration is in use (else 0)] */
-int otm_batch_info(const otm_batch* batch, double info9[9]);
+ *  fused single-pass iteration is in use (else 0), float64 residual
+ *  refreshes of the last solve (OTM_MIXED; else 0)] */
+int otm_batch_info(const otm_batch* batch, double info10[10]);
 /* Adaptive volume bound state of design d (Algorithm 1), the 8 doubles of
  * otm_get_governor; the iteration count is the batch's. */
 int otm_batch_get_governor(const otm_batch* batch, int32_t d, double state8[8]);

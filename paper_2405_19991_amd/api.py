@@ -331,18 +331,20 @@ def dumps_log(log) -> str:
 class Batch:
     """Many independent cells of uneven (even) n, stepped together: every
     phase of a design iteration is one launch over all designs, and PCG
-    chunks replay a captured hipGraph.  float64 path.
+    chunks replay a captured hipGraph.  float64 or mixed precision.
 
-    iteration: "auto" (the autotuner picks the fused single-pass or the
-    two-pass PCG iteration; with autotune off, the two-pass one), "fused" or
-    "two_pass"."""
+    precision: "fp64", or "mixed" (float32 operator and Krylov vectors with
+    float64 residual refreshes; fused iteration only).  iteration: "auto"
+    (the autotuner picks the fused single-pass or the two-pass PCG
+    iteration; with autotune off, the two-pass one), "fused" or "two_pass"."""
 
     ITERATIONS = {"auto": 0, "fused": 4, "two_pass": 1}
 
     def __init__(self, problems: Sequence[Dict[str, object]], tol: float = 1e-6, max_iter: int = 20000,
                  check_every: int = 16, guess: str = "zero", move: float = 0.05, eta: float = 0.5, move_min: float = 0.0,
                  rho_min: float = 1e-3, governor: Optional[Dict[str, float]] = None, autotune: bool = True,
-                 tile_tx: int = 0, tile_tz: int = 0, iteration: str = "auto", stream=None):
+                 tile_tx: int = 0, tile_tz: int = 0, iteration: str = "auto", precision: str = "fp64",
+                 reliable_delta: Optional[float] = None, stream=None):
         L = N.lib()
         arr = (N.Problem * len(problems))()
         self.ns = []
@@ -360,7 +362,9 @@ class Batch:
             p.symmetry = N.OTM_SYM_NONE
             self.ns.append(p.n)
         s, o, g = N.default_options()
-        s.precision = N.OTM_FP64
+        s.precision = {"fp64": N.OTM_FP64, "mixed": N.OTM_MIXED}[precision]
+        if reliable_delta is not None:
+            s.reliable_delta = float(reliable_delta)
         s.guess = {"zero": N.OTM_GUESS_ZERO, "previous": N.OTM_GUESS_PREVIOUS}[guess]
         s.tol, s.max_iter, s.check_every = float(tol), int(max_iter), int(check_every)
         s.autotune, s.tile_tx, s.tile_tz = int(bool(autotune)), int(tile_tx), int(tile_tz)
@@ -420,10 +424,10 @@ class Batch:
         return out
 
     def info(self) -> Dict[str, float]:
-        a = np.zeros(9)
+        a = np.zeros(10)
         self._chk(self._L.otm_batch_info(self._h, _ptr(a)))
         keys = ["designs", "cells", "work_items", "tile_tx", "tile_tz", "tuned_iteration_us", "solve_ms", "step_ms",
-                "fused"]
+                "fused", "refreshes"]
         return dict(zip(keys, a.tolist()))
 
     def governor_state(self, d: int) -> List[float]:

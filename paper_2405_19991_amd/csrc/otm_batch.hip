@@ -1,4 +1,6 @@
-// Host engine for batches of designs with uneven n (float64 path).
+// Host engine for batches of designs with uneven n (float64, or mixed
+// precision: float32 operator and Krylov vectors with float64 residual
+// refreshes, as a single context's OTM_MIXED solve).
 //
 // All designs of a batch share one set of arenas; every phase of a design
 // iteration is one launch over the batch's work list (otm_kernels.hip,
@@ -55,6 +57,12 @@ struct otm_batch {
     double *r2 = nullptr, *q2 = nullptr;  // second r, q of the fused iteration (ping-pong)
     bool fused = false;                   // fused single-pass iteration chosen
     int fbuf = 0;                         // fused iteration: which r, q, p the next pass reads
+    // mixed precision (fused iteration only): float32 r, q, p (ping-pong), the
+    // float32 iterate folded into x at each refresh, float32 k and D^-1
+    bool mixed = false;
+    float *r32[2] = {nullptr, nullptr}, *q32[2] = {nullptr, nullptr}, *p32[2] = {nullptr, nullptr};
+    float *x32 = nullptr, *k32 = nullptr, *dinv32 = nullptr;
+    int refreshes = 0;  // float64 residual refreshes of the last solve
     W6* dw6 = nullptr;
     double* dvstar = nullptr;
     double* dmove = nullptr;  // OC move limit per design
@@ -172,15 +180,40 @@ void pcg_chunk(otm_batch* c) {
     }
 }
 
+// One fused pass reading buffer set par and writing set par ^ 1.
+void fused_pass(otm_batch* c, int par, bool fin) {
+    const int nx = par ^ 1;
+    if (c->mixed) {
+        launch_b_fused<float>(c->tab, c->wx, c->march_grid, c->r32[par], c->q32[par], c->p32[par], c->r32[nx],
+                              c->q32[nx], c->p32[nx], c->x32, c->dinv32, c->k32, c->partials, c->sc, par, fin,
+                              c->stream);
+    } else {
+        double* R[2] = {c->r, c->r2};
+        double* Q[2] = {c->q, c->q2};
+        launch_b_fused<double>(c->tab, c->wx, c->march_grid, R[par], Q[par], c->p[par], R[nx], Q[nx], c->p[nx], c->x,
+                               c->dinv, c->k, c->partials, c->sc, par, fin, c->stream);
+    }
+}
+
 // check_every fused passes (even: the buffers end where they began)
 void fused_chunk(otm_batch* c) {
-    double* R[2] = {c->r, c->r2};
-    double* Q[2] = {c->q, c->q2};
     for (int it = 0; it < c->so.check_every; ++it) {
-        const int cur = c->fbuf, nx = cur ^ 1;
-        launch_b_fused(c->tab, c->wx, c->march_grid, R[cur], Q[cur], c->p[cur], R[nx], Q[nx], c->p[nx], c->x, c->dinv,
-                       c->k, c->partials, c->sc, cur, true, c->stream);
-        c->fbuf = nx;
+        fused_pass(c, c->fbuf, true);
+        c->fbuf ^= 1;
+    }
+}
+
+// float64 residual of every design from its float64 x (start, or a refresh
+// with the pending step of buffer set fbuf)
+void residual_f(otm_batch* c, bool start, bool x_zero) {
+    if (c->mixed) {
+        launch_b_residual_f<float>(c->tab, c->k, c->b, c->x, c->r32[c->fbuf], start ? nullptr : c->q32[c->fbuf],
+                                   c->dinv32, start, x_zero ? 1 : 0, c->partials, c->sc, c->stream);
+    } else {
+        double* R[2] = {c->r, c->r2};
+        double* Q[2] = {c->q, c->q2};
+        launch_b_residual_f<double>(c->tab, c->k, c->b, c->x, R[c->fbuf], start ? nullptr : Q[c->fbuf], c->dinv,
+                                    start, x_zero ? 1 : 0, c->partials, c->sc, c->stream);
     }
 }
 
@@ -243,27 +276,44 @@ int run_chunk(otm_batch* c) {
 
 // The fused iteration (one pass and one per-design finalize per iteration);
 // converged designs are confirmed with their true residual, and loads that
-// miss the tolerance restart.
+// miss the tolerance restart.  Mixed precision: the float32 iterate is folded
+// into the float64 x and the float64 residual replaces the recursive one when
+// every design has stopped, or when some running load's recursive residual
+// has fallen by reliable_delta since its last refresh (the refresh covers
+// every design: a refresh at any chunk boundary is a valid step).
 int solve_fused(otm_batch* c, bool x_zero) {
     int rc;
     if ((rc = reset_solver(c))) return rc;
     if (x_zero) BCHK(c, hipMemsetAsync(c->x, 0, (size_t)3 * c->total * sizeof(double), c->stream));
+    if (c->mixed) BCHK(c, hipMemsetAsync(c->x32, 0, (size_t)3 * c->total * sizeof(float), c->stream));
     c->fbuf = 0;
-    launch_b_residual_f(c->tab, c->k, c->b, c->x, c->r, nullptr, c->dinv, true, x_zero ? 1 : 0, c->partials, c->sc,
-                        c->stream);
+    c->refreshes = 0;
+    residual_f(c, true, x_zero);
     if ((rc = blaunch_ok(c, "residual"))) return rc;
     if ((rc = sync_sc(c))) return rc;
+    std::vector<double> rr_ref(3 * (size_t)c->count);
+    for (int d = 0; d < c->count; ++d)
+        for (int l = 0; l < 3; ++l) rr_ref[3 * d + l] = c->h_sc[d].rr_true[l];
+    const double d2 = c->so.reliable_delta * c->so.reliable_delta;
     while (!all_inactive(c) && max_iters(c) < c->so.max_iter) {
         if ((rc = run_chunk(c))) return rc;
         if ((rc = sync_sc(c))) return rc;
-        if (all_inactive(c)) {
-            double* R[2] = {c->r, c->r2};
-            double* Q[2] = {c->q, c->q2};
-            launch_b_residual_f(c->tab, c->k, c->b, c->x, R[c->fbuf], Q[c->fbuf], c->dinv, false, 0, c->partials,
-                                c->sc, c->stream);
+        bool refresh = all_inactive(c);
+        if (c->mixed)
+            for (int d = 0; d < c->count && !refresh; ++d)
+                for (int l = 0; l < 3; ++l)
+                    if (c->h_sc[d].active[l] && c->h_sc[d].rr[l] < d2 * rr_ref[3 * d + l]) refresh = true;
+        if (refresh) {
+            if (c->mixed) launch_b_accumulate(c->tab, c->x, c->x32, c->stream);
+            residual_f(c, false, false);
+            if ((rc = blaunch_ok(c, "refresh"))) return rc;
             if ((rc = sync_sc(c))) return rc;
+            for (int d = 0; d < c->count; ++d)
+                for (int l = 0; l < 3; ++l) rr_ref[3 * d + l] = c->h_sc[d].rr_true[l];
+            if (c->mixed) ++c->refreshes;
         }
     }
+    if (c->mixed) launch_b_accumulate(c->tab, c->x, c->x32, c->stream);
     launch_b_sum3(c->tab, c->x, 0, c->partials, c->sc, c->stream);
     launch_b_sub_mean3(c->tab, c->x, 0, c->sc, c->stream);
     return blaunch_ok(c, "project");
@@ -299,12 +349,10 @@ int solve(otm_batch* c, bool x_zero) {
 // most kMaxBlocks work items.
 double time_candidate(otm_batch* c, int wx, int tz, bool fused) {
     build_tables(c, wx, tz);
-    if (fused && (c->tab.mb_total > kMaxBlocks || !c->r2)) return 1e30;
+    if (fused && (c->tab.mb_total > kMaxBlocks || !(c->r2 || c->mixed))) return 1e30;
     auto iteration = [&](int par) {
         if (fused) {
-            launch_b_fused(c->tab, c->wx, c->march_grid, par ? c->r2 : c->r, par ? c->q2 : c->q, c->p[par],
-                           par ? c->r : c->r2, par ? c->q : c->q2, c->p[par ^ 1], c->x, c->dinv, c->k, c->partials,
-                           c->sc, par, false, c->stream);
+            fused_pass(c, par, false);
         } else {
             march_pass(c, c->p[par], c->p[par ^ 1], false);
             launch_b_update_vec(c->tab, c->update_grid, c->x, c->r, c->p[par ^ 1], c->q, c->dinv, c->partials,
@@ -336,6 +384,17 @@ int autotune_batch(otm_batch* c) {
     std::vector<int> key;
     for (auto& p : c->prob) key.push_back(p.n);
     std::sort(key.begin(), key.end());
+    // fused only: mixed precision, or kernel variant 4
+    const bool fused_only = c->mixed || c->so.kernel_variant == 4;
+    std::string fkey = "batch";
+    for (size_t i = 0; i < key.size();) {
+        size_t j = i;
+        while (j < key.size() && key[j] == key[i]) ++j;
+        fkey += "_" + std::to_string(key[i]) + "x" + std::to_string(j - i);
+        i = j;
+    }
+    if (c->mixed) fkey += "_mixed";
+    key.insert(key.begin(), {c->mixed ? 1 : 0, fused_only ? 1 : 0});
     {
         std::lock_guard<std::mutex> g(g_btune_mu);
         auto it = g_btune.find(key);
@@ -346,13 +405,7 @@ int autotune_batch(otm_batch* c) {
         }
     }
     // the persistent cache: keyed by the multiset of n (count of each size)
-    std::string fkey = "batch";
-    for (size_t i = 0; i < key.size();) {
-        size_t j = i;
-        while (j < key.size() && key[j] == key[i]) ++j;
-        fkey += "_" + std::to_string(key[i]) + "x" + std::to_string(j - i);
-        i = j;
-    }
+    // and the precision
     {
         std::vector<double> v(4);
         if (tune_cache_lookup(fkey, v)) {
@@ -360,7 +413,7 @@ int autotune_batch(otm_batch* c) {
             const bool fused = v[2] != 0.0;
             if ((wx == 16 || wx == 32) && (tz == 4 || tz == 8 || tz == 16 || tz == 32)) {
                 build_tables(c, wx, tz);
-                if (!fused || (c->r2 && c->tab.mb_total <= kMaxBlocks)) {
+                if (fused ? ((c->r2 || c->mixed) && c->tab.mb_total <= kMaxBlocks) : !fused_only) {
                     c->fused = fused;
                     c->tune_us = v[3];
                     std::lock_guard<std::mutex> g(g_btune_mu);
@@ -385,13 +438,17 @@ int autotune_batch(otm_batch* c) {
     const size_t v3 = (size_t)3 * c->total * sizeof(double), v1 = (size_t)c->total * sizeof(double);
     for (double* v : {c->r, c->q, c->r2, c->q2, c->p[0], c->p[1], c->x})
         if (v) BCHK(c, hipMemsetAsync(v, 0, v3, c->stream));
+    for (float* v : {c->r32[0], c->r32[1], c->q32[0], c->q32[1], c->p32[0], c->p32[1], c->x32})
+        if (v) BCHK(c, hipMemsetAsync(v, 0, v3 / 2, c->stream));
+    for (float* v : {c->k32, c->dinv32})
+        if (v) BCHK(c, hipMemsetAsync(v, 0, v1 / 2, c->stream));
     BCHK(c, hipMemsetAsync(c->k, 0, v1, c->stream));
     BCHK(c, hipMemsetAsync(c->dinv, 0, v1, c->stream));
     int best_wx = 16, best_tz = 8;
     bool best_fused = false;
     double best = 1e30;
-    const int fz_min = c->so.kernel_variant == 4 ? 1 : 0;  // variant 4: the fused iteration only
-    for (int fz = (c->r2 ? 1 : 0); fz >= fz_min; --fz)
+    const int fz_min = fused_only ? 1 : 0;
+    for (int fz = ((c->r2 || c->mixed) ? 1 : 0); fz >= fz_min; --fz)
         for (int wx : {16, 32})
             for (int tz : {4, 8, 16, 32}) {
                 const double us = time_candidate(c, wx, tz, fz != 0);
@@ -402,9 +459,12 @@ int autotune_batch(otm_batch* c) {
                     best_fused = fz != 0;
                 }
             }
-    BCHK(c, hipMemsetAsync(c->p[0], 0, v3, c->stream));
-    BCHK(c, hipMemsetAsync(c->p[1], 0, v3, c->stream));
-    BCHK(c, hipMemsetAsync(c->x, 0, v3, c->stream));
+    if (c->mixed && !best_fused)
+        return bfail(c, OTM_EUNSUPPORTED, "a mixed-precision batch needs at most 4096 (design, tile) items");
+    for (double* v : {c->p[0], c->p[1], c->x})
+        if (v) BCHK(c, hipMemsetAsync(v, 0, v3, c->stream));
+    for (float* v : {c->q32[0], c->q32[1], c->p32[0], c->p32[1], c->x32})
+        if (v) BCHK(c, hipMemsetAsync(v, 0, v3 / 2, c->stream));
     build_tables(c, best_wx, best_tz);
     c->fused = best_fused;
     BCHK(c, hipStreamSynchronize(c->stream));
@@ -418,9 +478,11 @@ int autotune_batch(otm_batch* c) {
 void free_batch(otm_batch* c) {
     if (c->gexec) (void)hipGraphExecDestroy(c->gexec);
     if (c->graph) (void)hipGraphDestroy(c->graph);
-    void* bufs[] = {c->rho, c->rhof, c->k, c->dinv, c->b, c->x, c->st, c->sens, c->ocq, c->r, c->p[0], c->p[1], c->q,
-                    c->r2, c->q2, c->dw6, c->dvstar, c->dmove, c->partials, c->sc, c->ddesc, c->eb_design,
-                    c->mb_design};
+    void* bufs[] = {c->rho,    c->rhof,   c->k,      c->dinv,     c->b,      c->x,        c->st,
+                    c->sens,   c->ocq,    c->r,      c->p[0],     c->p[1],   c->q,        c->r2,
+                    c->q2,     c->r32[0], c->r32[1], c->q32[0],   c->q32[1], c->p32[0],   c->p32[1],
+                    c->x32,    c->k32,    c->dinv32, c->dw6,      c->dvstar, c->dmove,    c->partials,
+                    c->sc,     c->ddesc,  c->eb_design, c->mb_design};
     for (void* p : bufs)
         if (p) (void)hipFree(p);
     if (c->h_sc) (void)hipHostFree(c->h_sc);
@@ -457,10 +519,17 @@ int otm_batch_create(const otm_problem* problems, int32_t count, const otm_solve
     if (solver) c->so = *solver;
     if (oc) c->oc = *oc;
     if (gov) c->go = *gov;
-    if (c->so.precision != OTM_FP64 || c->so.preconditioner != OTM_PRECOND_JACOBI || !(c->so.tol > 0.0) ||
-        c->so.max_iter < 1 || c->so.check_every < 1 || c->so.kernel_variant < 0 || c->so.kernel_variant > 5) {
-        const int code =
-            (c->so.precision != OTM_FP64 || c->so.preconditioner != OTM_PRECOND_JACOBI) ? OTM_EUNSUPPORTED : OTM_EINVAL;
+    c->mixed = c->so.precision == OTM_MIXED;
+    // mixed precision runs the fused iteration only (kernel variant 0 or 4)
+    const bool supported = (c->so.precision == OTM_FP64 || (c->mixed && (c->so.kernel_variant == 0 ||
+                                                                          c->so.kernel_variant == 4))) &&
+                           c->so.preconditioner == OTM_PRECOND_JACOBI;
+    if (!supported || !(c->so.tol > 0.0) || c->so.max_iter < 1 || c->so.check_every < 1 ||
+        c->so.kernel_variant < 0 || c->so.kernel_variant > 5 || !(c->so.reliable_delta > 0.0)) {
+        const bool known = (c->so.precision == OTM_FP64 || c->mixed) && c->so.kernel_variant >= 0 &&
+                           c->so.kernel_variant <= 5 &&
+                           (c->so.preconditioner == OTM_PRECOND_JACOBI || c->so.preconditioner == OTM_PRECOND_MG);
+        const int code = (known && !supported) ? OTM_EUNSUPPORTED : OTM_EINVAL;
         delete c;
         return code;
     }
@@ -510,15 +579,27 @@ int otm_batch_create(const otm_problem* problems, int32_t count, const otm_solve
     rc = rc ? rc : balloc(c, &c->st, total);
     rc = rc ? rc : balloc(c, &c->sens, total);
     rc = rc ? rc : balloc(c, &c->ocq, total);
-    rc = rc ? rc : balloc(c, &c->r, 3 * total);
-    rc = rc ? rc : balloc(c, &c->p[0], 3 * total);
-    rc = rc ? rc : balloc(c, &c->p[1], 3 * total);
-    rc = rc ? rc : balloc(c, &c->q, 3 * total);
-    // the fused iteration (kernel variant 0 with autotuning, or 4) ping-pongs r and q
-    const bool may_fuse = c->so.kernel_variant == 4 || (c->so.kernel_variant == 0 && c->so.autotune);
-    if (may_fuse) {
-        rc = rc ? rc : balloc(c, &c->r2, 3 * total);
-        rc = rc ? rc : balloc(c, &c->q2, 3 * total);
+    // the fused iteration (kernel variant 0 with autotuning, or 4; always in
+    // mixed precision) ping-pongs r and q
+    const bool may_fuse = c->mixed || c->so.kernel_variant == 4 || (c->so.kernel_variant == 0 && c->so.autotune);
+    if (c->mixed) {
+        for (int i = 0; i < 2; ++i) {
+            rc = rc ? rc : balloc(c, &c->r32[i], 3 * total);
+            rc = rc ? rc : balloc(c, &c->q32[i], 3 * total);
+            rc = rc ? rc : balloc(c, &c->p32[i], 3 * total);
+        }
+        rc = rc ? rc : balloc(c, &c->x32, 3 * total);
+        rc = rc ? rc : balloc(c, &c->k32, total);
+        rc = rc ? rc : balloc(c, &c->dinv32, total);
+    } else {
+        rc = rc ? rc : balloc(c, &c->r, 3 * total);
+        rc = rc ? rc : balloc(c, &c->p[0], 3 * total);
+        rc = rc ? rc : balloc(c, &c->p[1], 3 * total);
+        rc = rc ? rc : balloc(c, &c->q, 3 * total);
+        if (may_fuse) {
+            rc = rc ? rc : balloc(c, &c->r2, 3 * total);
+            rc = rc ? rc : balloc(c, &c->q2, 3 * total);
+        }
     }
     rc = rc ? rc : balloc(c, &c->dw6, count);
     rc = rc ? rc : balloc(c, &c->dvstar, count);
@@ -544,15 +625,18 @@ int otm_batch_create(const otm_problem* problems, int32_t count, const otm_solve
     c->volume.assign(count, 0.0);
     c->low.assign(count, 0.0);
     c->have_density.assign(count, 0);
-    (void)hipMemsetAsync(c->x, 0, (size_t)3 * total * sizeof(double), c->stream);
-    (void)hipMemsetAsync(c->p[0], 0, (size_t)3 * total * sizeof(double), c->stream);
-    (void)hipMemsetAsync(c->p[1], 0, (size_t)3 * total * sizeof(double), c->stream);
+    for (double* v : {c->x, c->p[0], c->p[1]})
+        if (v) (void)hipMemsetAsync(v, 0, (size_t)3 * total * sizeof(double), c->stream);
+    for (float* v : {c->q32[0], c->q32[1], c->p32[0], c->p32[1], c->x32})
+        if (v) (void)hipMemsetAsync(v, 0, (size_t)3 * total * sizeof(float), c->stream);
     if (c->so.autotune && c->so.tile_tz == 0 && c->so.tile_tx == 0) {
         rc = autotune_batch(c);
     } else {
         const int wx = c->so.tile_tx == 64 ? 32 : 16;
         build_tables(c, wx, c->so.tile_tz > 0 ? std::max(4, c->so.tile_tz) : 8);
-        c->fused = c->so.kernel_variant == 4 && c->r2 && c->tab.mb_total <= kMaxBlocks;
+        c->fused = (c->mixed || c->so.kernel_variant == 4) && (c->r2 || c->mixed) && c->tab.mb_total <= kMaxBlocks;
+        if (c->mixed && !c->fused)
+            rc = bfail(c, OTM_EUNSUPPORTED, "a mixed-precision batch needs at most 4096 (design, tile) items");
     }
     if (!rc && hipStreamSynchronize(c->stream) != hipSuccess) rc = OTM_EDEVICE;
     if (rc) {
@@ -621,6 +705,7 @@ int otm_batch_step(otm_batch* c, otm_iter_record* recs) {
     launch_b_filter_simp(c->tab, c->rho, c->rhof, c->k, c->partials, c->sc, c->stream);
     launch_b_setup_nodes(c->tab, c->k, c->b, c->dinv, c->partials, c->sc, c->stream);
     launch_b_sub_mean3(c->tab, c->b, 1, c->sc, c->stream);
+    if (c->mixed) launch_b_to_f32(c->tab, c->k, c->dinv, c->k32, c->dinv32, c->stream);
     if ((rc = blaunch_ok(c, "prepare"))) return rc;
     auto t1 = std::chrono::steady_clock::now();
     const bool x_zero = !(c->so.guess == OTM_GUESS_PREVIOUS && c->have_solution);
@@ -719,7 +804,7 @@ int otm_batch_device_bytes(const otm_batch* c, int64_t* bytes) {
     return OTM_OK;
 }
 
-int otm_batch_info(const otm_batch* c, double info8[9]) {
+int otm_batch_info(const otm_batch* c, double info8[10]) {
     if (!c || !info8) return OTM_EINVAL;
     info8[0] = (double)c->count;
     info8[1] = (double)c->total;
@@ -730,6 +815,7 @@ int otm_batch_info(const otm_batch* c, double info8[9]) {
     info8[6] = c->t_ms[1];
     info8[7] = c->t_ms[3];
     info8[8] = c->fused ? 1.0 : 0.0;
+    info8[9] = (double)c->refreshes;
     return OTM_OK;
 }
 

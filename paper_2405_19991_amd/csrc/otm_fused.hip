@@ -22,6 +22,7 @@
 // x is updated in place (own nodes only).  Two x-adjacent nodes per thread with
 // 8-byte accesses, as the pair operator; even n only.
 #include <hip/hip_ext.h>
+#include <type_traits>
 
 #include "otm_device.h"
 
@@ -567,29 +568,53 @@ __global__ void __launch_bounds__(kBlock)
     b_residual_f<TR>(blockIdx.x, gridDim.x, n, k, b, x, r, q, dinv, x_zero, partials);
 }
 
-// ---- batches of designs (float64) -------------------------------------------
+// ---- batches of designs ---------------------------------------------------
 // The fused pass over a batch's work list of (design, tile) items: each block
 // walks items (contiguous ranges per XCD), the design's first tile records
 // its state, and item i's partial sums go to slot i (value-major, so the
 // batch needs at most kMaxBlocks items).  Every design and load may be
-// inactive (per-design state).
-template <int WX, int TY>
-__global__ void __launch_bounds__(WX* TY) kb_fused(BatchTab t, const double* __restrict__ r_in,
-                                                   const double* __restrict__ q_in, const double* __restrict__ p_in,
-                                                   double* __restrict__ r_out, double* __restrict__ q_out,
-                                                   double* __restrict__ p_out, double* __restrict__ x,
-                                                   const double* __restrict__ dinv, const double* __restrict__ k,
-                                                   double* __restrict__ partials, Scalars* __restrict__ sc, int par) {
+// inactive (per-design state); the items of a design whose three loads have
+// all stopped are skipped, and so is its finalize (a stopped design's state
+// is a fixed point of the pass and the finalize).
+__device__ __forceinline__ bool design_live(const Scalars* s) {
+    return (s->active[0] | s->active[1] | s->active[2]) != 0;
+}
+
+template <typename T, int WX, int TY>
+__device__ __forceinline__ void b_fused_items(const BatchTab& t, const T* __restrict__ r_in,
+                                              const T* __restrict__ q_in, const T* __restrict__ p_in,
+                                              T* __restrict__ r_out, T* __restrict__ q_out, T* __restrict__ p_out,
+                                              T* __restrict__ x, const T* __restrict__ dinv, const T* __restrict__ k,
+                                              double* __restrict__ partials, Scalars* __restrict__ sc, int par) {
     for (int v = blockIdx.x; v < t.mb_total; v += gridDim.x) {
         const int item = xcd_tile(v, t.mb_total);
         const int d = t.mb_design[item];
+        if (!design_live(sc + d)) continue;  // uniform over the block
         const BatchDesc D = t.desc[d];
         const int64_t o1 = D.off, o3 = 3 * D.off;
         __syncthreads();  // the previous item's LDS rings are no longer read
-        fused_body<double, WX, TY, false, false>(item - D.mb_start, item, 0, item == D.mb_start, D.n, D.tz, D.ntx,
-                                                 D.nty, r_in + o3, q_in + o3, p_in + o3, r_out + o3, q_out + o3,
-                                                 p_out + o3, x + o3, dinv + o1, k + o1, partials, sc + d, par);
+        fused_body<T, WX, TY, false, false>(item - D.mb_start, item, 0, item == D.mb_start, D.n, D.tz, D.ntx, D.nty,
+                                            r_in + o3, q_in + o3, p_in + o3, r_out + o3, q_out + o3, p_out + o3,
+                                            x + o3, dinv + o1, k + o1, partials, sc + d, par);
     }
+}
+
+template <int WX, int TY>
+__global__ void __launch_bounds__(WX* TY) __attribute__((amdgpu_waves_per_eu(2)))
+    kb_fused_f32(BatchTab t, const float* __restrict__ r_in, const float* __restrict__ q_in,
+                 const float* __restrict__ p_in, float* __restrict__ r_out, float* __restrict__ q_out,
+                 float* __restrict__ p_out, float* __restrict__ x, const float* __restrict__ dinv,
+                 const float* __restrict__ k, double* __restrict__ partials, Scalars* __restrict__ sc, int par) {
+    b_fused_items<float, WX, TY>(t, r_in, q_in, p_in, r_out, q_out, p_out, x, dinv, k, partials, sc, par);
+}
+
+template <int WX, int TY>
+__global__ void __launch_bounds__(WX* TY)
+    kb_fused_f64(BatchTab t, const double* __restrict__ r_in, const double* __restrict__ q_in,
+                 const double* __restrict__ p_in, double* __restrict__ r_out, double* __restrict__ q_out,
+                 double* __restrict__ p_out, double* __restrict__ x, const double* __restrict__ dinv,
+                 const double* __restrict__ k, double* __restrict__ partials, Scalars* __restrict__ sc, int par) {
+    b_fused_items<double, WX, TY>(t, r_in, q_in, p_in, r_out, q_out, p_out, x, dinv, k, partials, sc, par);
 }
 
 // Per design (one block each): reduce the pass's partial sums of the design's
@@ -597,11 +622,12 @@ __global__ void __launch_bounds__(WX* TY) kb_fused(BatchTab t, const double* __r
 __global__ void __launch_bounds__(kBlock) kb_fused_fin(BatchTab t, const double* __restrict__ partials,
                                                        Scalars* __restrict__ sc, int par) {
     const int d = blockIdx.x;
+    Scalars* s = sc + d;
+    if (!design_live(s)) return;  // uniform over the block
     const BatchDesc D = t.desc[d];
     __shared__ double tot[kFusedSums];
     final_sums_vm<kFusedSums>(partials + par * kFusedStride + D.mb_start, D.mb_count, tot);
     if (threadIdx.x != 0) return;
-    Scalars* s = sc + d;
     FusedState st;
     fused_advance(s->fs[par], tot, st);
     for (int l = 0; l < 3; ++l) {
@@ -616,42 +642,96 @@ __global__ void __launch_bounds__(kBlock) kb_fused_fin(BatchTab t, const double*
     }
 }
 
+template <typename TR>
 __global__ void __launch_bounds__(kBlock) kb_residual_f(BatchTab t, const double* __restrict__ k,
                                                         const double* __restrict__ b, const double* __restrict__ x,
-                                                        double* __restrict__ r, const double* __restrict__ q,
-                                                        const double* __restrict__ dinv, int x_zero,
+                                                        TR* __restrict__ r, const TR* __restrict__ q,
+                                                        const TR* __restrict__ dinv, int x_zero,
                                                         double* __restrict__ partials) {
     const int g = blockIdx.x;
     const int d = t.eb_design[g];
     const BatchDesc D = t.desc[d];
     const int64_t o1 = D.off, o3 = 3 * D.off;
-    b_residual_f<double>(g - D.eb_start, D.eb_count, D.n, k + o1, b + o3, x + o3, r + o3, q ? q + o3 : nullptr,
-                         dinv + o1, x_zero, partials + (size_t)D.eb_start * 12);
+    b_residual_f<TR>(g - D.eb_start, D.eb_count, D.n, k + o1, b + o3, x + o3, r + o3, q ? q + o3 : nullptr,
+                     dinv + o1, x_zero, partials + (size_t)D.eb_start * 12);
 }
 
-template <int WX, int TY>
-static void launch_bf(const BatchTab& t, int grid, const double* r_in, const double* q_in, const double* p_in,
-                      double* r_out, double* q_out, double* p_out, double* x, const double* dinv, const double* k,
-                      double* partials, Scalars* sc, int par, hipStream_t s) {
-    hipLaunchKernelGGL((kb_fused<WX, TY>), dim3(grid), dim3(WX * TY), 0, s, t, r_in, q_in, p_in, r_out, q_out, p_out,
-                       x, dinv, k, partials, sc, par);
+// x += x32, x32 = 0 for every design (the float32 iterate folded into the
+// float64 solution)
+__global__ void __launch_bounds__(kBlock) kb_accumulate(BatchTab t, double* __restrict__ x, float* __restrict__ x32) {
+    const int g = blockIdx.x;
+    const int d = t.eb_design[g];
+    const BatchDesc D = t.desc[d];
+    const int64_t o3 = 3 * D.off, cnt = 3 * (int64_t)D.n * D.n * D.n;
+    for (int64_t v = (int64_t)(g - D.eb_start) * kBlock + threadIdx.x; v < cnt; v += (int64_t)D.eb_count * kBlock) {
+        x[o3 + v] += (double)x32[o3 + v];
+        x32[o3 + v] = 0.0f;
+    }
 }
 
-void launch_b_fused(const BatchTab& t, int wx, int grid, const double* r_in, const double* q_in, const double* p_in,
-                    double* r_out, double* q_out, double* p_out, double* x, const double* dinv, const double* k,
-                    double* partials, Scalars* sc, int par, bool fin, hipStream_t s) {
-    if (wx == 32)
-        launch_bf<32, 8>(t, grid, r_in, q_in, p_in, r_out, q_out, p_out, x, dinv, k, partials, sc, par, s);
-    else
-        launch_bf<16, 16>(t, grid, r_in, q_in, p_in, r_out, q_out, p_out, x, dinv, k, partials, sc, par, s);
+// float32 copies of the element conductivities and the inverse diagonal
+__global__ void __launch_bounds__(kBlock) kb_to_f32(BatchTab t, const double* __restrict__ k,
+                                                    const double* __restrict__ dinv, float* __restrict__ k32,
+                                                    float* __restrict__ dinv32) {
+    const int g = blockIdx.x;
+    const int d = t.eb_design[g];
+    const BatchDesc D = t.desc[d];
+    const int64_t o1 = D.off, nn = (int64_t)D.n * D.n * D.n;
+    for (int64_t v = (int64_t)(g - D.eb_start) * kBlock + threadIdx.x; v < nn; v += (int64_t)D.eb_count * kBlock) {
+        k32[o1 + v] = (float)k[o1 + v];
+        dinv32[o1 + v] = (float)dinv[o1 + v];
+    }
+}
+
+template <typename T>
+void launch_b_fused(const BatchTab& t, int wx, int grid, const T* r_in, const T* q_in, const T* p_in, T* r_out,
+                    T* q_out, T* p_out, T* x, const T* dinv, const T* k, double* partials, Scalars* sc, int par,
+                    bool fin, hipStream_t s) {
+    if constexpr (std::is_same<T, float>::value) {
+        if (wx == 32)
+            hipLaunchKernelGGL((kb_fused_f32<32, 8>), dim3(grid), dim3(kBlock), 0, s, t, r_in, q_in, p_in, r_out,
+                               q_out, p_out, x, dinv, k, partials, sc, par);
+        else
+            hipLaunchKernelGGL((kb_fused_f32<16, 16>), dim3(grid), dim3(kBlock), 0, s, t, r_in, q_in, p_in, r_out,
+                               q_out, p_out, x, dinv, k, partials, sc, par);
+    } else {
+        if (wx == 32)
+            hipLaunchKernelGGL((kb_fused_f64<32, 8>), dim3(grid), dim3(kBlock), 0, s, t, r_in, q_in, p_in, r_out,
+                               q_out, p_out, x, dinv, k, partials, sc, par);
+        else
+            hipLaunchKernelGGL((kb_fused_f64<16, 16>), dim3(grid), dim3(kBlock), 0, s, t, r_in, q_in, p_in, r_out,
+                               q_out, p_out, x, dinv, k, partials, sc, par);
+    }
     if (fin) hipLaunchKernelGGL(kb_fused_fin, dim3(t.count), dim3(kBlock), 0, s, t, partials, sc, par);
 }
 
-void launch_b_residual_f(const BatchTab& t, const double* k, const double* b, const double* x, double* r,
-                         const double* q, const double* dinv, bool start, int x_zero, double* partials, Scalars* sc,
-                         hipStream_t s) {
-    hipLaunchKernelGGL(kb_residual_f, dim3(t.eb_total), dim3(kBlock), 0, s, t, k, b, x, r, q, dinv, x_zero, partials);
+template void launch_b_fused<float>(const BatchTab&, int, int, const float*, const float*, const float*, float*,
+                                    float*, float*, float*, const float*, const float*, double*, Scalars*, int, bool,
+                                    hipStream_t);
+template void launch_b_fused<double>(const BatchTab&, int, int, const double*, const double*, const double*,
+                                     double*, double*, double*, double*, const double*, const double*, double*,
+                                     Scalars*, int, bool, hipStream_t);
+
+template <typename TR>
+void launch_b_residual_f(const BatchTab& t, const double* k, const double* b, const double* x, TR* r, const TR* q,
+                         const TR* dinv, bool start, int x_zero, double* partials, Scalars* sc, hipStream_t s) {
+    hipLaunchKernelGGL(kb_residual_f<TR>, dim3(t.eb_total), dim3(kBlock), 0, s, t, k, b, x, r, q, dinv, x_zero,
+                       partials);
     launch_b_finalize(t, start ? FIN_F_START : FIN_F_REFRESH, 0, partials, sc, 0.5, s);
+}
+
+template void launch_b_residual_f<float>(const BatchTab&, const double*, const double*, const double*, float*,
+                                         const float*, const float*, bool, int, double*, Scalars*, hipStream_t);
+template void launch_b_residual_f<double>(const BatchTab&, const double*, const double*, const double*, double*,
+                                          const double*, const double*, bool, int, double*, Scalars*, hipStream_t);
+
+void launch_b_accumulate(const BatchTab& t, double* x, float* x32, hipStream_t s) {
+    hipLaunchKernelGGL(kb_accumulate, dim3(t.eb_total), dim3(kBlock), 0, s, t, x, x32);
+}
+
+void launch_b_to_f32(const BatchTab& t, const double* k, const double* dinv, float* k32, float* dinv32,
+                     hipStream_t s) {
+    hipLaunchKernelGGL(kb_to_f32, dim3(t.eb_total), dim3(kBlock), 0, s, t, k, dinv, k32, dinv32);
 }
 
 template <typename TR>

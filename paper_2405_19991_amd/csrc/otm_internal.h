@@ -414,18 +414,26 @@ void launch_b_filter(const BatchTab& t, const double* in, double* out, hipStream
 void launch_b_oc_prepare(const BatchTab& t, const double* rho, const double* sens, double eta, double* q,
                          hipStream_t s);
 void launch_b_oc_init(const BatchTab& t, Scalars* sc, const double* vstar, double eta, hipStream_t s);
-// Batched fused PCG pass (float64), followed by its per-design finalize when
-// fin is set (a pass without it leaves every design's state as it was: the
-// autotuner times passes that way); the partials need 2 kFusedStride doubles
-// and the batch at most kMaxBlocks work items.
-void launch_b_fused(const BatchTab& t, int wx, int grid, const double* r_in, const double* q_in, const double* p_in,
-                    double* r_out, double* q_out, double* p_out, double* x, const double* dinv, const double* k,
-                    double* partials, Scalars* sc, int par, bool fin, hipStream_t s);
-// r = b - A x per design with the sums the fused iteration (re)starts from
-// (start: FIN_F_START, else FIN_F_REFRESH with the pending q).
-void launch_b_residual_f(const BatchTab& t, const double* k, const double* b, const double* x, double* r,
-                         const double* q, const double* dinv, bool start, int x_zero, double* partials, Scalars* sc,
-                         hipStream_t s);
+// Batched fused PCG pass (float64, or float32 vectors and operator), followed
+// by its per-design finalize when fin is set (a pass without it leaves every
+// design's state as it was: the autotuner times passes that way); the
+// partials need 2 kFusedStride doubles and the batch at most kMaxBlocks work
+// items.  Designs whose loads have all stopped are skipped.
+template <typename T>
+void launch_b_fused(const BatchTab& t, int wx, int grid, const T* r_in, const T* q_in, const T* p_in, T* r_out,
+                    T* q_out, T* p_out, T* x, const T* dinv, const T* k, double* partials, Scalars* sc, int par,
+                    bool fin, hipStream_t s);
+// r = b - A x per design (float64 operator and x; r stored as TR) with the
+// sums the fused iteration (re)starts from (start: FIN_F_START, else
+// FIN_F_REFRESH with the pending q).
+template <typename TR>
+void launch_b_residual_f(const BatchTab& t, const double* k, const double* b, const double* x, TR* r, const TR* q,
+                         const TR* dinv, bool start, int x_zero, double* partials, Scalars* sc, hipStream_t s);
+// x += x32, x32 = 0 per design
+void launch_b_accumulate(const BatchTab& t, double* x, float* x32, hipStream_t s);
+// k32 = (float)k, dinv32 = (float)dinv per design
+void launch_b_to_f32(const BatchTab& t, const double* k, const double* dinv, float* k32, float* dinv32,
+                     hipStream_t s);
 void launch_b_oc_pass(const BatchTab& t, const double* rho, const double* q, const double* moves, double rho_min,
                       double eta, double* partials, Scalars* sc, hipStream_t s);
 void launch_b_oc_apply(const BatchTab& t, double* rho, const double* q, double eta, const double* moves,

@@ -125,6 +125,26 @@ def test_batch_rejects_multigrid(L):
     assert L.otm_batch_create(arr, 1, ctypes.byref(s), None, None, None, ctypes.byref(h)) == N.OTM_EUNSUPPORTED
 
 
+def test_batch_precision_validation(L):
+    """Mixed-precision batches run the fused iteration only; unknown
+    precisions and a non-positive refresh threshold are invalid."""
+    from paper_2405_19991_amd import _native as N
+    arr = (N.Problem * 1)()
+    arr[0].n, arr[0].k0, arr[0].kmin, arr[0].penal, arr[0].filter_radius, arr[0].vf = 16, 1.0, 1e-3, 3.0, 1.5, 0.3
+    h = ctypes.c_void_p()
+    for variant, code in ((1, N.OTM_EUNSUPPORTED), (2, N.OTM_EUNSUPPORTED), (5, N.OTM_EUNSUPPORTED),
+                          (6, N.OTM_EINVAL)):
+        s, o, g = N.default_options()
+        s.precision, s.kernel_variant = N.OTM_MIXED, variant
+        assert L.otm_batch_create(arr, 1, ctypes.byref(s), None, None, None, ctypes.byref(h)) == code
+    s, o, g = N.default_options()
+    s.precision = 7
+    assert L.otm_batch_create(arr, 1, ctypes.byref(s), None, None, None, ctypes.byref(h)) == N.OTM_EINVAL
+    s, o, g = N.default_options()
+    s.precision, s.reliable_delta = N.OTM_MIXED, 0.0
+    assert L.otm_batch_create(arr, 1, ctypes.byref(s), None, None, None, ctypes.byref(h)) == N.OTM_EINVAL
+
+
 def _problem(N, n=8):
     p = N.Problem()
     p.n, p.k0, p.kmin, p.penal, p.filter_radius, p.vf = n, 1.0, 1e-3, 3.0, 1.5, 0.3

@@ -180,3 +180,102 @@ def test_fused_first_tensor_matches_oracle():
         ref = O.homogenize(p["rho"], O.Params(tol=1e-13))
         rel = np.linalg.norm(np.array(recs[d]["kappa"]) - ref["kappa"]) / np.linalg.norm(ref["kappa"])
         assert rel <= 1e-9
+
+
+def test_mixed_batch_matches_oracle_and_fp64_batch():
+    """Mixed precision batch (float32 operator and vectors, float64 residual
+    refreshes): every design's first tensor within the solve tolerance's
+    reach of the oracle's (1e-5 at tol 1e-6, as a single mixed context), every
+    solve converged with its float64 residual under tol, and three design
+    iterations that follow the float64 batch's."""
+    from paper_2405_19991_amd import Batch
+    probs = problems([10, 16, 6, 12], 37)
+    steps = 3
+    out = {}
+    for prec in ("mixed", "fp64"):
+        with Batch(probs, tol=1e-6, autotune=False, tile_tz=8, iteration="fused", precision=prec) as B:
+            assert B.info()["fused"] == 1.0
+            for d, p in enumerate(probs):
+                B.set_density(d, p["rho"])
+            out[prec] = [B.step() for _ in range(steps)]
+            if prec == "mixed":
+                print(f"mixed batch: {B.info()['refreshes']:.0f} refreshes in the last solve", flush=True)
+    for d, p in enumerate(probs):
+        ref = O.homogenize(p["rho"], O.Params(tol=1e-13))
+        rec = out["mixed"][0][d]
+        assert max(rec["rel_residual"]) <= 1e-6
+        rel = np.linalg.norm(np.array(rec["kappa"]) - ref["kappa"]) / np.linalg.norm(ref["kappa"])
+        assert rel <= 1e-5
+    for s in range(steps):
+        for d in range(len(probs)):
+            m, f = out["mixed"][s][d], out["fp64"][s][d]
+            np.testing.assert_allclose(m["kappa"], f["kappa"], rtol=1e-5, atol=1e-9)
+            assert m["g"] == pytest.approx(f["g"], rel=1e-4, abs=1e-9)
+
+
+def test_mixed_batch_matches_single_mixed_contexts():
+    """At tol 1e-9 the mixed batch's tensors equal single mixed contexts' to
+    1e-8 (the tensor is second order in the solution error; the batch
+    refreshes every design when any needs it, so the float32 iterates differ)."""
+    from paper_2405_19991_amd import Batch, Homogenization
+    probs = problems([8, 14, 12], 41)
+    with Batch(probs, tol=1e-9, autotune=False, tile_tx=64, tile_tz=4, precision="mixed") as B:
+        for d, p in enumerate(probs):
+            B.set_density(d, p["rho"])
+        recs = B.step()
+    for d, p in enumerate(probs):
+        with Homogenization(p["n"], (1.0, 1e-3), p["target"], vf=p["vf"], tol=1e-9, precision="mixed") as h:
+            h.set_density(p["rho"])
+            kappa, st = h.homogenize()
+        assert st["converged"] and max(recs[d]["rel_residual"]) <= 1e-9
+        rel = np.linalg.norm(np.array(recs[d]["kappa"]) - np.array(kappa)) / np.linalg.norm(kappa)
+        assert rel <= 1e-8
+
+
+def test_mixed_graph_replay_equals_eager():
+    from paper_2405_19991_amd import Batch
+    probs = problems([16, 8, 12], 43)
+    res = []
+    for use_graph in (True, False):
+        with Batch(probs, tol=1e-7, autotune=False, tile_tz=8, precision="mixed") as B:
+            B.set_graph(use_graph)
+            for d, p in enumerate(probs):
+                B.set_density(d, p["rho"])
+            recs = [B.step() for _ in range(3)]
+            res.append((recs, [B.get_field(d, "rho") for d in range(len(probs))]))
+    (rg, pg), (re_, pe) = res
+    for s in range(3):
+        for d in range(len(probs)):
+            assert rg[s][d]["kappa"] == re_[s][d]["kappa"]
+            assert rg[s][d]["pcg_iters"] == re_[s][d]["pcg_iters"]
+    for a, b in zip(pg, pe):
+        np.testing.assert_array_equal(a, b)
+
+
+def test_mixed_full_size_mix_autotuned():
+    """The 64-design mix in mixed precision with the autotuner (fused
+    candidates only): converged, and the first 32^3 and 64^3 designs' tensors
+    within 1e-5 of single mixed contexts'."""
+    from paper_2405_19991_amd import Batch, Homogenization
+    ws = synth.config4()
+    with Batch([dict(n=w.n, target=w.target, vf=w.vf) for w in ws], tol=1e-6, precision="mixed") as B:
+        info = B.info()
+        print(f"mixed batch: tile {info['tile_tx']:.0f} x tz {info['tile_tz']:.0f}, fused {info['fused']:.0f}",
+              flush=True)
+        assert info["fused"] == 1.0
+        for d, w in enumerate(ws):
+            B.set_density(d, w.rho0)
+        recs = B.step()
+    picks = {}
+    for d, w in enumerate(ws):
+        picks.setdefault(w.n, d)
+    for n in (32, 64):
+        d = picks[n]
+        w = ws[d]
+        assert max(recs[d]["rel_residual"]) <= 1e-6
+        with Homogenization(n, (w.k0, w.kmin), w.target, vf=w.vf, tol=1e-6, precision="mixed") as h:
+            h.set_density(w.rho0)
+            kappa, _ = h.homogenize()
+        rel = np.linalg.norm(np.array(recs[d]["kappa"]) - np.array(kappa)) / np.linalg.norm(kappa)
+        print(f"design {d} (n={n}): mixed batch vs single mixed {rel:.2e}", flush=True)
+        assert rel <= 1e-5
