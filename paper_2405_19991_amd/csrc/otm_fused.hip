@@ -387,10 +387,13 @@ __device__ __forceinline__ void fused_body(int tile, int slot, int nslots, bool 
 __global__ void __launch_bounds__(kBlock) k_fused_fin(int nblocks, const double* __restrict__ partials,
                                                       Scalars* __restrict__ sc, int par) {
     __shared__ double tot[kFusedSums];
-    final_sums_vm<kFusedSums>(partials + par * kFusedStride, nblocks, tot);
+    // the state the pass ran with, loaded while the partial sums are in flight
+    FusedState in;
+    if (threadIdx.x == 0) in = sc->fs[par];
+    final_sums_vm<kFusedSums, 4>(partials + par * kFusedStride, nblocks, tot);
     if (threadIdx.x != 0) return;
     FusedState s;
-    fused_advance(sc->fs[par], tot, s);
+    fused_advance(in, tot, s);
     for (int l = 0; l < 3; ++l) {
         sc->alpha[l] = s.alpha[l];
         sc->beta[l] = s.beta[l];
@@ -626,10 +629,12 @@ __global__ void __launch_bounds__(kBlock) kb_fused_fin(BatchTab t, const double*
     if (!design_live(s)) return;  // uniform over the block
     const BatchDesc D = t.desc[d];
     __shared__ double tot[kFusedSums];
-    final_sums_vm<kFusedSums>(partials + par * kFusedStride + D.mb_start, D.mb_count, tot);
+    FusedState in;
+    if (threadIdx.x == 0) in = s->fs[par];
+    final_sums_vm<kFusedSums, 4>(partials + par * kFusedStride + D.mb_start, D.mb_count, tot);
     if (threadIdx.x != 0) return;
     FusedState st;
-    fused_advance(s->fs[par], tot, st);
+    fused_advance(in, tot, st);
     for (int l = 0; l < 3; ++l) {
         s->alpha[l] = st.alpha[l];
         s->beta[l] = st.beta[l];
