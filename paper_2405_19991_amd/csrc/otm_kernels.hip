@@ -53,7 +53,7 @@ __device__ __forceinline__ double filter_at(const double* in, int n, int i, int 
     return acc;
 }
 
-__device__ __forceinline__ void b_filter(int bid_, int nblk_, int n, FilterW f, const double* __restrict__ in,
+__device__ __forceinline__ void b_filter(int bid_, int nblk_, int n, const FilterW& f, const double* __restrict__ in,
                                                    double* __restrict__ out) {
     const int64_t nn = (int64_t)n * n * n;
     for (int64_t e = (int64_t)bid_ * kBlock + threadIdx.x; e < nn; e += (int64_t)nblk_ * kBlock) {
@@ -67,7 +67,7 @@ __global__ void __launch_bounds__(kBlock) k_filter(int n, FilterW f, const doubl
                                                    double* __restrict__ out) { b_filter(blockIdx.x, gridDim.x, n, f, in, out); }
 
 // rho -> rho~ -> k (SIMP), plus the sums of rho and rho~^p.
-__device__ __forceinline__ void b_filter_simp(int bid_, int nblk_, int n, FilterW f, const double* __restrict__ rho,
+__device__ __forceinline__ void b_filter_simp(int bid_, int nblk_, int n, const FilterW& f, const double* __restrict__ rho,
                                                         double* __restrict__ rhof, double* __restrict__ k,
                                                         float* __restrict__ k32, double k0, double kmin, double p,
                                                         double* partials, unsigned* counter, Scalars* sc) {
@@ -1227,8 +1227,10 @@ __global__ void __launch_bounds__(kBlock) kb_clamp(BatchTab t, double* rho, doub
 __global__ void __launch_bounds__(kBlock) kb_filter_simp(BatchTab t, const double* rho, double* rhof, double* k,
                                                          double* partials, Scalars* sc) {
     OTM_BATCH_ITEM
-    b_filter_simp(lb_, nb_, D.n, D.fw, rho + o1, rhof + o1, k + o1, nullptr, D.k0, D.kmin, D.penal, partials, nullptr,
-                  sc + d_);
+    // the weights are read from the device table: a local copy indexed with
+    // the runtime radius would be placed in scratch memory
+    b_filter_simp(lb_, nb_, D.n, t.desc[d_].fw, rho + o1, rhof + o1, k + o1, nullptr, D.k0, D.kmin, D.penal, partials,
+                  nullptr, sc + d_);
 }
 
 __global__ void __launch_bounds__(kBlock) kb_setup_nodes(BatchTab t, const double* k, double* b, double* dinv,
@@ -1270,7 +1272,7 @@ __global__ void __launch_bounds__(kBlock) kb_sens(BatchTab t, const double* rhof
 
 __global__ void __launch_bounds__(kBlock) kb_filter(BatchTab t, const double* in, double* out) {
     OTM_BATCH_ITEM
-    b_filter(lb_, nb_, D.n, D.fw, in + o1, out + o1);
+    b_filter(lb_, nb_, D.n, t.desc[d_].fw, in + o1, out + o1);
 }
 
 __global__ void __launch_bounds__(kBlock) kb_oc_prepare(BatchTab t, const double* rho, const double* sens, double eta,

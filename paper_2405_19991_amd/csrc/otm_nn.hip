@@ -29,6 +29,7 @@ namespace otm {
 
 typedef short v4s __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));
+typedef unsigned int v4u __attribute__((ext_vector_type(4)));  // 16-byte chunk (a native vector: stays in registers)
 
 constexpr int kNNLayers = 5;
 constexpr int kNNCh[kNNLayers + 1] = {1, 16, 16, 16, 16, 3};
@@ -93,7 +94,7 @@ __global__ void __launch_bounds__(256) k_nn_conv_b(int n, const uint16_t* __rest
         const int x0 = bx * kBX, y0 = by * kBY, z0 = bz * kBZ;
         // stage the halo brick: two 16-byte chunks per voxel, a thread's loads
         // all issued before its first LDS store
-        uint4 buf[kPer];
+        v4u buf[kPer];
 #pragma unroll
         for (int it = 0; it < kPer; ++it) {
             const int c = threadIdx.x + it * 256;
@@ -105,14 +106,14 @@ __global__ void __launch_bounds__(256) k_nn_conv_b(int n, const uint16_t* __rest
                 ys = ys < 0 ? ys + n : (ys >= n ? ys - n : ys);
                 zs = zs < 0 ? zs + n : (zs >= n ? zs - n : zs);
                 const size_t vs = (size_t)xs + (size_t)n * ((size_t)ys + (size_t)n * zs);
-                buf[it] = *reinterpret_cast<const uint4*>(in + vs * 16 + half * 8);
+                buf[it] = *reinterpret_cast<const v4u*>(in + vs * 16 + half * 8);
             }
         }
         __syncthreads();  // the previous brick's reads of the tile are done
 #pragma unroll
         for (int it = 0; it < kPer; ++it) {
             const int c = threadIdx.x + it * 256;
-            if (c < kChunks) *reinterpret_cast<uint4*>(&tile[(c >> 1) * 16 + (c & 1) * 8]) = buf[it];
+            if (c < kChunks) *reinterpret_cast<v4u*>(&tile[(c >> 1) * 16 + (c & 1) * 8]) = buf[it];
         }
         __syncthreads();
         // the wave's four rows (y = 0..3 of brick plane z = wv) as four
