@@ -16,6 +16,7 @@
 // y[v] = b + sum_t W_t x[v + d_t] with periodic wrap.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <new>
@@ -166,76 +167,149 @@ __global__ void __launch_bounds__(256) k_nn_conv_b(int n, const uint16_t* __rest
 }
 
 // Weight and bias gradients of one layer: dW[t][ci][co] = sum_v x[v + d_t][ci] dy[v][co],
-// db[co] = sum_v dy[v][co].  Each wave accumulates the 27 16x16 tiles over its
-// voxel groups (MFMA with the voxels as the reduction dimension) and writes
-// them, with its bias sums, to its own partial slot.
+// db[co] = sum_v dy[v][co].  A block stages a 16x4x4 brick of dy and the
+// brick of x with its one-voxel periodic halo in LDS, with a voxel stride of
+// kWS = 20 channels so that the four lane groups' 2-byte reads of one channel
+// (voxels 4 apart) fall in different banks; wave w accumulates the taps
+// w, w + 4, ... over the brick's 16 rows of 16 voxels (MFMA with the voxels as
+// the reduction dimension: A = x shifted by the tap, 16 ci x 16 voxels; B =
+// dy, 16 voxels x 16 co) and walks its share of the bricks; the block then
+// writes its 27 tiles and (wave 0) its bias sums to its own partial slot.
+constexpr int kWS = 20;
+constexpr int kWSlot = 27 * 256 + 16;  // floats per partial slot
+constexpr int kWSlots = 512;           // partial slots (blocks of the weight gradient)
+
 __global__ void __launch_bounds__(256) k_nn_wgrad(int n, const uint16_t* __restrict__ x, const uint16_t* __restrict__ dy,
-                                                  float* __restrict__ partials /* [waves][27*256 + 16] */) {
+                                                  float* __restrict__ partials /* [blocks][kWSlot] */) {
+    __shared__ __attribute__((aligned(16))) uint16_t xt[kHVox * kWS];
+    __shared__ __attribute__((aligned(16))) uint16_t dt[kBX * kBY * kBZ * kWS];
     const int lane = threadIdx.x & 63;
-    const int wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    const int nwaves = (gridDim.x * blockDim.x) >> 6;
+    const int wv = threadIdx.x >> 6;
     const int c = lane & 15;         // A row = ci ; B column = co
-    const int kq = (lane >> 4) * 4;  // voxel quad within the group
-    v4f acc[27];
+    const int kq = (lane >> 4) * 4;  // the lane's 4 voxels of a 16-voxel row (the reduction index)
+    const int nbx = n / kBX, nby = n / kBY;
+    const int nbricks = nbx * nby * (n / kBZ);
+    constexpr int kT = 7;  // taps per wave (wave 3 has 6)
+    v4f acc[kT];
 #pragma unroll
-    for (int t = 0; t < 27; ++t) acc[t] = (v4f){0.f, 0.f, 0.f, 0.f};
+    for (int j = 0; j < kT; ++j) acc[j] = (v4f){0.f, 0.f, 0.f, 0.f};
     float bsum = 0.f;
-    const int groups_per_row = n / 16;
-    const int64_t ngroups = (int64_t)groups_per_row * n * n;
-    for (int64_t g = wave; g < ngroups; g += nwaves) {
-        const int gx = (int)(g % groups_per_row);
-        const int64_t row = g / groups_per_row;
-        const int y = (int)(row % n), z = (int)(row / n);
-        // B: dy[v_k][co = c] for the lane's 4 voxels k
-        v4s b;
+    constexpr int kChunks = kHVox * 2;
+    constexpr int kPer = (kChunks + 255) / 256;
+    constexpr int kDPer = kBX * kBY * kBZ * 2 / 256;  // dy chunks per thread (2)
+    for (int vb = blockIdx.x; vb < nbricks; vb += gridDim.x) {
+        int b = xcd_tile(vb, nbricks);
+        const int bx = b % nbx;
+        b /= nbx;
+        const int by = b % nby;
+        const int bz = b / nby;
+        const int x0 = bx * kBX, y0 = by * kBY, z0 = bz * kBZ;
+        v4u buf[kPer], dbuf[kDPer];
 #pragma unroll
-        for (int i = 0; i < 4; ++i) {
-            const size_t v = (size_t)(gx * 16 + kq + i) + (size_t)n * ((size_t)y + (size_t)n * z);
-            b[i] = (short)dy[v * 16 + c];
-            bsum += bf2f(dy[v * 16 + c]);
+        for (int it = 0; it < kPer; ++it) {
+            const int ch = threadIdx.x + it * 256;
+            if (ch < kChunks) {
+                const int vox = ch >> 1, half = ch & 1;
+                const int hx = vox % kHX, hy = (vox / kHX) % kHY, hz = vox / (kHX * kHY);
+                int xs = x0 - 1 + hx, ys = y0 - 1 + hy, zs = z0 - 1 + hz;
+                xs = xs < 0 ? xs + n : (xs >= n ? xs - n : xs);
+                ys = ys < 0 ? ys + n : (ys >= n ? ys - n : ys);
+                zs = zs < 0 ? zs + n : (zs >= n ? zs - n : zs);
+                const size_t vs = (size_t)xs + (size_t)n * ((size_t)ys + (size_t)n * zs);
+                buf[it] = *reinterpret_cast<const v4u*>(x + vs * 16 + half * 8);
+            }
         }
 #pragma unroll
-        for (int t = 0; t < 27; ++t) {
-            const int dz = t / 9 - 1, dyy = (t / 3) % 3 - 1, dx = t % 3 - 1;
-            int ys = y + dyy, zs = z + dz;
-            ys = ys < 0 ? ys + n : (ys >= n ? ys - n : ys);
-            zs = zs < 0 ? zs + n : (zs >= n ? zs - n : zs);
-            const size_t rowoff = (size_t)n * ((size_t)ys + (size_t)n * zs);
-            v4s a;
+        for (int it = 0; it < kDPer; ++it) {
+            const int ch = threadIdx.x + it * 256;
+            const int vox = ch >> 1, half = ch & 1;
+            const int ix = vox % kBX, iy = (vox / kBX) % kBY, iz = vox / (kBX * kBY);
+            const size_t vs = (size_t)(x0 + ix) + (size_t)n * ((size_t)(y0 + iy) + (size_t)n * (z0 + iz));
+            dbuf[it] = *reinterpret_cast<const v4u*>(dy + vs * 16 + half * 8);
+        }
+        __syncthreads();  // the previous brick's reads of the tiles are done
+        // 16-byte chunks at 8-byte aligned LDS offsets (voxel stride 40 bytes)
+#pragma unroll
+        for (int it = 0; it < kPer; ++it) {
+            const int ch = threadIdx.x + it * 256;
+            if (ch < kChunks) {
+                uint16_t* dst = &xt[(ch >> 1) * kWS + (ch & 1) * 8];
+                reinterpret_cast<uint2*>(dst)[0] = make_uint2(buf[it].x, buf[it].y);
+                reinterpret_cast<uint2*>(dst)[1] = make_uint2(buf[it].z, buf[it].w);
+            }
+        }
+#pragma unroll
+        for (int it = 0; it < kDPer; ++it) {
+            const int ch = threadIdx.x + it * 256;
+            uint16_t* dst = &dt[(ch >> 1) * kWS + (ch & 1) * 8];
+            reinterpret_cast<uint2*>(dst)[0] = make_uint2(dbuf[it].x, dbuf[it].y);
+            reinterpret_cast<uint2*>(dst)[1] = make_uint2(dbuf[it].z, dbuf[it].w);
+        }
+        __syncthreads();
+#pragma unroll 2
+        for (int row = 0; row < kBY * kBZ; ++row) {
+            const int yk = row % kBY, zk = row / kBY;
+            v4s bv;
 #pragma unroll
             for (int i = 0; i < 4; ++i) {
-                int xs = gx * 16 + kq + i + dx;
-                xs = xs < 0 ? xs + n : (xs >= n ? xs - n : xs);
-                a[i] = (short)x[((size_t)xs + rowoff) * 16 + c];
+                const uint16_t h = dt[((zk * kBY + yk) * kBX + kq + i) * kWS + c];
+                bv[i] = (short)h;
+                if (wv == 0) bsum += bf2f(h);
             }
-            acc[t] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, acc[t], 0, 0, 0);
+#pragma unroll
+            for (int j = 0; j < kT; ++j) {
+                const int t = wv + 4 * j;
+                if (t < 27) {
+                    const int dz = t / 9 - 1, dyy = (t / 3) % 3 - 1, dx = t % 3 - 1;
+                    const int hrow = ((zk + 1 + dz) * kHY + (yk + 1 + dyy)) * kHX + 1 + dx;
+                    v4s av;
+#pragma unroll
+                    for (int i = 0; i < 4; ++i) av[i] = (short)xt[(hrow + kq + i) * kWS + c];
+                    acc[j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc[j], 0, 0, 0);
+                }
+            }
         }
     }
     // D[ci][co]: lane holds co = lane%16, ci = 4(lane/16)+i
-    float* dst = partials + (size_t)wave * (27 * 256 + 16);
+    float* dst = partials + (size_t)blockIdx.x * kWSlot;
 #pragma unroll
-    for (int t = 0; t < 27; ++t)
+    for (int j = 0; j < kT; ++j) {
+        const int t = wv + 4 * j;
+        if (t < 27)
 #pragma unroll
-        for (int i = 0; i < 4; ++i) dst[t * 256 + (kq + i) * 16 + c] = acc[t][i];
-    // bias: lanes with the same co (lane%16) hold disjoint voxel quads
+            for (int i = 0; i < 4; ++i) dst[t * 256 + (kq + i) * 16 + c] = acc[j][i];
+    }
+    // bias (wave 0): lanes with the same co (lane%16) hold disjoint voxel quads
     bsum += __shfl_xor(bsum, 16, 64);
     bsum += __shfl_xor(bsum, 32, 64);
-    if (lane < 16) dst[27 * 256 + lane] = bsum;
+    if (wv == 0 && lane < 16) dst[27 * 256 + lane] = bsum;
 }
 
-// grad[t][ci][co] (+ bias) += sum over waves, in fixed order
-__global__ void __launch_bounds__(256) k_nn_wgrad_reduce(int nwaves, const float* __restrict__ partials,
+// grad[t][ci][co] (+ bias) += the sum over the slots, in a fixed order: a
+// block takes 64 consecutive entries, each of its four waves a quarter of the
+// slots (in order), and the quarters are added in order.
+__global__ void __launch_bounds__(256) k_nn_wgrad_reduce(int nslots, const float* __restrict__ partials,
                                                          float* __restrict__ gw /* [co][ci][27] padded */,
                                                          float* __restrict__ gb) {
-    const int e = blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= 27 * 256 + 16) return;
+    __shared__ float sh[4][64];
+    const int j = threadIdx.x & 63, q = threadIdx.x >> 6;
+    const int e = blockIdx.x * 64 + j;
+    const int per = (nslots + 3) / 4;
     float s = 0.f;
-    for (int w = 0; w < nwaves; ++w) s += partials[(size_t)w * (27 * 256 + 16) + e];
+    if (e < kWSlot) {
+        const int w0 = q * per, w1 = min(nslots, w0 + per);
+#pragma unroll 8
+        for (int w = w0; w < w1; ++w) s += partials[(size_t)w * kWSlot + e];
+    }
+    sh[q][j] = s;
+    __syncthreads();
+    if (q != 0 || e >= kWSlot) return;
+    const float tot = ((sh[0][j] + sh[1][j]) + sh[2][j]) + sh[3][j];
     if (e < 27 * 256) {
         const int t = e / 256, ci = (e / 16) % 16, co = e % 16;
-        gw[(co * 16 + ci) * 27 + t] += s;
+        gw[(co * 16 + ci) * 27 + t] += tot;
     } else {
-        gb[e - 27 * 256] += s;
+        gb[e - 27 * 256] += tot;
     }
 }
 
@@ -361,7 +435,7 @@ struct otm_nn {
     double* partials = nullptr;
     double* sums = nullptr;                 // 6 means + loss
     int adam_t = 0;
-    int nwaves_wgrad = 512;
+
     std::string err;
 };
 
@@ -464,7 +538,7 @@ int otm_nn_create(int32_t n_max, uint64_t seed, void* stream, otm_nn** out) {
     al((void**)&c->gA, (size_t)nn * 16 * 2);
     al((void**)&c->gB, (size_t)nn * 16 * 2);
     al((void**)&c->out, (size_t)nn * 16 * 4);
-    al((void**)&c->wpart, (size_t)c->nwaves_wgrad * (27 * 256 + 16) * 4);
+    al((void**)&c->wpart, (size_t)kWSlots * kWSlot * 4);
     al((void**)&c->partials, (size_t)1024 * 8 * 8);
     al((void**)&c->sums, 16 * 8);
     if (!ok) {
@@ -598,10 +672,11 @@ int otm_nn_accumulate(otm_nn* c, int32_t n, const void* rhof_dev, const void* ch
     uint16_t* gcur = c->gA;
     uint16_t* gnext = c->gB;
     for (int l = kNNLayers - 1; l >= 0; --l) {
-        hipLaunchKernelGGL(k_nn_wgrad, dim3(c->nwaves_wgrad / 4), dim3(256), 0, c->stream, n,
-                           (const uint16_t*)c->act[l], (const uint16_t*)gcur, c->wpart);
-        hipLaunchKernelGGL(k_nn_wgrad_reduce, dim3((27 * 256 + 16 + 255) / 256), dim3(256), 0, c->stream,
-                           c->nwaves_wgrad, (const float*)c->wpart, c->g + (size_t)l * kLayerParams,
+        const int wblocks = std::min((n / kBX) * (n / kBY) * (n / kBZ), kWSlots);
+        hipLaunchKernelGGL(k_nn_wgrad, dim3(wblocks), dim3(256), 0, c->stream, n, (const uint16_t*)c->act[l],
+                           (const uint16_t*)gcur, c->wpart);
+        hipLaunchKernelGGL(k_nn_wgrad_reduce, dim3((kWSlot + 63) / 64), dim3(256), 0, c->stream, wblocks,
+                           (const float*)c->wpart, c->g + (size_t)l * kLayerParams,
                            c->g + (size_t)l * kLayerParams + kNNW);
         if (l > 0) {
             hipLaunchKernelGGL(k_nn_conv_b<NN_DGRAD_MASK>, dim3(conv_bricks(n)), dim3(256), 0, c->stream, n,
