@@ -148,15 +148,25 @@ __device__ __forceinline__ void final_sums_vm(const double* partials, int nblock
 }
 
 // Sum the partial arrays of all blocks (fixed order) -> out[NV] in shared memory.
-template <int NV>
+// U: slots per thread whose loads are all issued before the first addition
+// (the additions keep the slot order b = tid, tid + blockDim, ...).
+template <int NV, int U = 1>
 __device__ __forceinline__ void final_sums(const double* partials, int nblocks, double* out /* shared */) {
     double v[NV];
 #pragma unroll
     for (int i = 0; i < NV; ++i) v[i] = 0.0;
-#pragma unroll 4
-    for (int b = threadIdx.x; b < nblocks; b += blockDim.x) {
+    for (int b0 = threadIdx.x; b0 < nblocks; b0 += U * blockDim.x) {
+        double t[U][NV];
 #pragma unroll
-        for (int i = 0; i < NV; ++i) v[i] += partials[(size_t)b * NV + i];
+        for (int u = 0; u < U; ++u) {
+            const int b = b0 + u * (int)blockDim.x;
+#pragma unroll
+            for (int i = 0; i < NV; ++i) t[u][i] = b < nblocks ? partials[(size_t)b * NV + i] : 0.0;
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u)
+#pragma unroll
+            for (int i = 0; i < NV; ++i) v[i] += t[u][i];
     }
     __shared__ double sh[NV][kBlock / 64];
     wave_reduce<NV>(v);

@@ -616,7 +616,7 @@ __global__ void k_fill_u32(unsigned* p, int count, unsigned v) {
 // stores visible, so producers need no device-scope fences.
 template <int NV>
 __device__ __forceinline__ void fin_sums(const double* partials, int nblocks, double* tot) {
-    final_sums<NV>(partials, nblocks, tot);
+    final_sums<NV, 4>(partials, nblocks, tot);
 }
 
 // The OC candidates' sums (31 per block, slot-major): lane i of each 32-lane
@@ -629,8 +629,17 @@ __device__ __forceinline__ void fin_sums_oc(const double* partials, int nblocks,
     const int g = threadIdx.x / 32, i = threadIdx.x % 32;
     double v = 0.0;
     if (i < kOcCands) {
-#pragma unroll 8
-        for (int b = g; b < nblocks; b += G) v += partials[(size_t)b * kOcCands + i];
+        // four blocks' loads in flight before their additions (in block order)
+        for (int b0 = g; b0 < nblocks; b0 += 4 * G) {
+            double t[4];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const int b = b0 + u * G;
+                t[u] = b < nblocks ? partials[(size_t)b * kOcCands + i] : 0.0;
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) v += t[u];
+        }
     }
     sh[g][i] = v;
     __syncthreads();
