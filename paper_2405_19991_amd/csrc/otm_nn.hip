@@ -31,6 +31,19 @@ namespace otm {
 typedef short v4s __attribute__((ext_vector_type(4)));
 typedef float v4f __attribute__((ext_vector_type(4)));
 typedef unsigned int v4u __attribute__((ext_vector_type(4)));  // 16-byte chunk (a native vector: stays in registers)
+typedef short v8s __attribute__((ext_vector_type(8)));
+typedef __bf16 v8b __attribute__((ext_vector_type(8)));
+
+// D += A B on gfx950's 16x16x32 bf16 MFMA with K = two 16-deep halves: lane
+// group g of A and of B holds elements k = 8 g .. 8 g + 7, the first four
+// taken from (a0, b0) and the last four from (a1, b1); whatever order the
+// unit sums k in, A's and B's element j of a lane group meet, so the result
+// is a0 b0 + a1 b1 summed over the two 16x16x16 operand pairs.
+__device__ __forceinline__ v4f mfma_pair(v4s a0, v4s a1, v4s b0, v4s b1, v4f d) {
+    const v8s a = __builtin_shufflevector(a0, a1, 0, 1, 2, 3, 4, 5, 6, 7);
+    const v8s b = __builtin_shufflevector(b0, b1, 0, 1, 2, 3, 4, 5, 6, 7);
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(v8b, a), __builtin_bit_cast(v8b, b), d, 0, 0, 0);
+}
 
 constexpr int kNNLayers = 5;
 constexpr int kNNCh[kNNLayers + 1] = {1, 16, 16, 16, 16, 3};
@@ -123,19 +136,30 @@ __global__ void __launch_bounds__(256) k_nn_conv_b(int n, const uint16_t* __rest
         v4f acc[kBY];
 #pragma unroll
         for (int yy = 0; yy < kBY; ++yy) acc[yy] = (v4f){0.f, 0.f, 0.f, 0.f};
-#pragma unroll
-        for (int t = 0; t < 27; ++t) {
+        // taps in pairs (2p, 2p + 1) on the 16x16x32 MFMA, tap 26 on the 16x16x16 one
+        auto rows = [&](int t, v4s (&bb)[kBY]) {
             const int dz = t / 9 - 1, dy = (t / 3) % 3 - 1, dx = t % 3 - 1;
-            v4s bb[kBY];
 #pragma unroll
             for (int yy = 0; yy < kBY; ++yy) {
                 const int hv = ((zz + 1 + dz) * kHY + (yy + 1 + dy)) * kHX + (m + 1 + dx);
                 const uint2 raw = *reinterpret_cast<const uint2*>(&tile[hv * 16 + cg]);
                 bb[yy] = *reinterpret_cast<const v4s*>(&raw);
             }
+        };
+#pragma unroll
+        for (int pr = 0; pr < 13; ++pr) {
+            v4s b0[kBY], b1[kBY];
+            rows(2 * pr, b0);
+            rows(2 * pr + 1, b1);
+#pragma unroll
+            for (int yy = 0; yy < kBY; ++yy) acc[yy] = mfma_pair(w[2 * pr], w[2 * pr + 1], b0[yy], b1[yy], acc[yy]);
+        }
+        {
+            v4s b0[kBY];
+            rows(26, b0);
 #pragma unroll
             for (int yy = 0; yy < kBY; ++yy)
-                acc[yy] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(w[t], bb[yy], acc[yy], 0, 0, 0);
+                acc[yy] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(w[26], b0[yy], acc[yy], 0, 0, 0);
         }
 #pragma unroll
         for (int yy = 0; yy < kBY; ++yy) {
@@ -246,26 +270,36 @@ __global__ void __launch_bounds__(256) k_nn_wgrad(int n, const uint16_t* __restr
             reinterpret_cast<uint2*>(dst)[1] = make_uint2(dbuf[it].z, dbuf[it].w);
         }
         __syncthreads();
+        // rows in pairs (K = 32 voxels per 16x16x32 MFMA)
 #pragma unroll 2
-        for (int row = 0; row < kBY * kBZ; ++row) {
-            const int yk = row % kBY, zk = row / kBY;
-            v4s bv;
+        for (int rp = 0; rp < kBY * kBZ / 2; ++rp) {
+            v4s bv[2];
 #pragma unroll
-            for (int i = 0; i < 4; ++i) {
-                const uint16_t h = dt[((zk * kBY + yk) * kBX + kq + i) * kWS + c];
-                bv[i] = (short)h;
-                if (wv == 0) bsum += bf2f(h);
+            for (int h = 0; h < 2; ++h) {
+                const int row = 2 * rp + h;
+                const int yk = row % kBY, zk = row / kBY;
+#pragma unroll
+                for (int i = 0; i < 4; ++i) {
+                    const uint16_t v = dt[((zk * kBY + yk) * kBX + kq + i) * kWS + c];
+                    bv[h][i] = (short)v;
+                    if (wv == 0) bsum += bf2f(v);
+                }
             }
 #pragma unroll
             for (int j = 0; j < kT; ++j) {
                 const int t = wv + 4 * j;
                 if (t < 27) {
                     const int dz = t / 9 - 1, dyy = (t / 3) % 3 - 1, dx = t % 3 - 1;
-                    const int hrow = ((zk + 1 + dz) * kHY + (yk + 1 + dyy)) * kHX + 1 + dx;
-                    v4s av;
+                    v4s av[2];
 #pragma unroll
-                    for (int i = 0; i < 4; ++i) av[i] = (short)xt[(hrow + kq + i) * kWS + c];
-                    acc[j] = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(av, bv, acc[j], 0, 0, 0);
+                    for (int h = 0; h < 2; ++h) {
+                        const int row = 2 * rp + h;
+                        const int yk = row % kBY, zk = row / kBY;
+                        const int hrow = ((zk + 1 + dz) * kHY + (yk + 1 + dyy)) * kHX + 1 + dx;
+#pragma unroll
+                        for (int i = 0; i < 4; ++i) av[h][i] = (short)xt[(hrow + kq + i) * kWS + c];
+                    }
+                    acc[j] = mfma_pair(av[0], av[1], bv[0], bv[1], acc[j]);
                 }
             }
         }
