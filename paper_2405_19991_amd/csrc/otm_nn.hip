@@ -63,19 +63,23 @@ enum { NN_FWD_RELU = 0, NN_FWD_LAST = 1, NN_DGRAD_MASK = 2, NN_DGRAD = 3 };
 // One convolution layer: forward with bias and ReLU, the last layer in FP32,
 // or the input gradient masked by the forward activation.  A block computes a
 // 16x4x4 brick of voxels.  The brick and its one-voxel periodic halo (18x6x6
-// voxels, 16 bf16 channels each, 20.7 KB) are staged in LDS once and read by
+// voxels, 16 bf16 channels each, 25.9 KB at a 40-byte voxel stride) are staged in LDS once and read by
 // all 27 taps, instead of every tap re-reading its shifted voxels from global
 // memory.  Wave w computes the four 16-voxel rows (y = 0..3) of brick plane
 // z = w as four independent chains of 27 MFMAs.
 constexpr int kBX = 16, kBY = 4, kBZ = 4;
 constexpr int kHX = kBX + 2, kHY = kBY + 2, kHZ = kBZ + 2;
 constexpr int kHVox = kHX * kHY * kHZ;
+constexpr int kCS = 20;  // LDS voxel stride of the convolution tile (bf16 elements)
 
 template <int MODE>
 __global__ void __launch_bounds__(256) k_nn_conv_b(int n, const uint16_t* __restrict__ in,
                                                    const uint16_t* __restrict__ wl, const float* __restrict__ bias,
                                                    void* __restrict__ out, const uint16_t* __restrict__ mask) {
-    __shared__ __attribute__((aligned(16))) uint16_t tile[kHVox * 16];
+    // voxel stride 20 channels (40 bytes): the 16 voxels of a row read by one
+    // lane group then fall on 16 distinct bank pairs (a 32-byte stride would
+    // put every fourth voxel on the same banks)
+    __shared__ __attribute__((aligned(16))) uint16_t tile[kHVox * kCS];
     const int lane = threadIdx.x & 63;
     const int wv = threadIdx.x >> 6;
     const int nbx = n / kBX, nby = n / kBY;
@@ -127,7 +131,11 @@ __global__ void __launch_bounds__(256) k_nn_conv_b(int n, const uint16_t* __rest
 #pragma unroll
         for (int it = 0; it < kPer; ++it) {
             const int c = threadIdx.x + it * 256;
-            if (c < kChunks) *reinterpret_cast<v4u*>(&tile[(c >> 1) * 16 + (c & 1) * 8]) = buf[it];
+            if (c < kChunks) {
+                uint16_t* dst = &tile[(c >> 1) * kCS + (c & 1) * 8];  // 8-byte aligned
+                reinterpret_cast<uint2*>(dst)[0] = make_uint2(buf[it].x, buf[it].y);
+                reinterpret_cast<uint2*>(dst)[1] = make_uint2(buf[it].z, buf[it].w);
+            }
         }
         __syncthreads();
         // the wave's four rows (y = 0..3 of brick plane z = wv) as four
@@ -142,7 +150,7 @@ __global__ void __launch_bounds__(256) k_nn_conv_b(int n, const uint16_t* __rest
 #pragma unroll
             for (int yy = 0; yy < kBY; ++yy) {
                 const int hv = ((zz + 1 + dz) * kHY + (yy + 1 + dy)) * kHX + (m + 1 + dx);
-                const uint2 raw = *reinterpret_cast<const uint2*>(&tile[hv * 16 + cg]);
+                const uint2 raw = *reinterpret_cast<const uint2*>(&tile[hv * kCS + cg]);
                 bb[yy] = *reinterpret_cast<const v4s*>(&raw);
             }
         };
