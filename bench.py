@@ -14,6 +14,8 @@ region, (n^3 * sum over loads of PCG iterations) / wall time of the K steps;
 from __future__ import annotations
 
 import argparse
+import functools
+import gc
 import json
 import os
 import sys
@@ -24,6 +26,17 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0   # MI355X HBM3E, published
+
+
+def collected(fn):
+    """Run a leg after a full garbage collection.  main() turns the
+    automatic collector off, so that a collection pass (tens of ms in this
+    process) never lands inside a timed region; each leg starts clean."""
+    @functools.wraps(fn)
+    def run(*a, **k):
+        gc.collect()
+        return fn(*a, **k)
+    return run
 
 
 def parse():
@@ -132,6 +145,7 @@ def cpu_model() -> str:
     return "unknown"
 
 
+@collected
 def cpu_baseline(iters_128: int = 1, iters_64: int = 5, iters_16: int = 30):
     """The CPU FP64 oracle (CSR assembly + plain unpreconditioned CG, OpenMP
     on every host core) timed per design iteration on the three single-cell
@@ -172,6 +186,7 @@ def cpu_baseline(iters_128: int = 1, iters_64: int = 5, iters_16: int = 30):
     }
 
 
+@collected
 def batch_leg(steps: int, log, precision: str = "fp64"):
     """64 designs, n in {32, 48, 64} (seeded mix), FP64 or mixed, tol 1e-6: one
     batched design iteration per step (work-list launches, hipGraph PCG
@@ -187,10 +202,15 @@ def batch_leg(steps: int, log, precision: str = "fp64"):
     B.step()  # warm-up (graph capture)
     t0 = _t.perf_counter()
     iters = 0
+    step_ms = []
     for _ in range(steps):
+        ts = _t.perf_counter()
         recs = B.step()
+        step_ms.append(1e3 * (_t.perf_counter() - ts))
         iters += sum(sum(r["pcg_iters"]) * ws[d].n ** 3 for d, r in enumerate(recs))
-        log(f"batch step: max pcg {max(max(r['pcg_iters']) for r in recs)}, mean g {sum(r['g'] for r in recs) / len(recs):.3e}")
+        inf = B.info()
+        log(f"batch {precision} step: {step_ms[-1]:.1f} ms (library: step {inf['step_ms']:.1f}, solve {inf['solve_ms']:.1f}), "
+            f"max pcg {max(max(r['pcg_iters']) for r in recs)}, mean g {sum(r['g'] for r in recs) / len(recs):.3e}")
     t1 = _t.perf_counter()
     info = B.info()
     dev_bytes = B.device_bytes()
@@ -199,9 +219,10 @@ def batch_leg(steps: int, log, precision: str = "fp64"):
             "device_bytes": dev_bytes, "s_per_oc_iter": (t1 - t0) / steps, "pcg_dof_updates_per_s": iters / (t1 - t0),
             "iteration": "fused" if info["fused"] else "two_pass", "refreshes": int(info["refreshes"]),
             "tile_tx": int(info["tile_tx"]), "tile_tz": int(info["tile_tz"]), "work_items": int(info["work_items"]),
-            "steps": steps}
+            "steps": steps, "step_ms": [round(x, 2) for x in step_ms]}
 
 
+@collected
 def multigrid_leg(w, steps: int, log, sweeps: int = 1, coarse_sweeps: int = 2, smoother: str = "jacobi"):
     """The timed workload's design iterations with one multigrid V-cycle as
     the preconditioner (mixed precision, same start and tolerance; damped
@@ -231,6 +252,7 @@ def multigrid_leg(w, steps: int, log, sweeps: int = 1, coarse_sweeps: int = 2, s
     return out
 
 
+@collected
 def fp64_leg(steps: int, log):
     """The 128^3 anisotropic cell with every vector and the operator in
     float64 (tol 1e-6, zero start), once with the Jacobi and once with the
@@ -266,6 +288,7 @@ def fp64_leg(steps: int, log):
     return out
 
 
+@collected
 def full_run_leg(w, log, iters: int = 150):
     """The 128^3 configuration's whole design run (150 design iterations,
     previous solution as the start, mixed precision, tol 1e-6) with the
@@ -293,6 +316,7 @@ def full_run_leg(w, log, iters: int = 150):
     return {"workload": w.name + "_mixed_150_iterations", "iterations": iters, **out}
 
 
+@collected
 def gallery_leg(iters: int, log, n: int = 32, move: float = 0.02, move_min: float = 0.0, governor=None):
     """Anisotropic-space traversal (Sec. 4.2): the 61 positive-definite targets
     with diagonal [0.3, 0.2, 0.1] as one batch of n^3 designs, IWP start at
@@ -339,6 +363,7 @@ def gallery_leg(iters: int, log, n: int = 32, move: float = 0.02, move_min: floa
     return out
 
 
+@collected
 def config_legs(steps: int, log):
     """Seconds per design iteration of the smaller cells: 16^3 isotropic (FP64,
     tol 1e-8) and 64^3 orthotropic (FP64 and mixed, tol 1e-6); one warm-up
@@ -367,6 +392,7 @@ def config_legs(steps: int, log):
     return out
 
 
+@collected
 def warm_start_leg(weights, log):
     """Time to 1e-6 on the held-out 128^3 cell at design iteration 5: zero
     start (FP64, mixed), previous design iteration's solution, and the trained
@@ -388,6 +414,7 @@ def warm_start_leg(weights, log):
     return ev
 
 
+@collected
 def apply_sizes(reps: int):
     """Stand-alone operator (3 loads, two-node z-march) on random conductivities
     at 128^3 and 256^3 in float32 and float64: microseconds per launch and
@@ -459,6 +486,7 @@ def use_shipped_tuning(retune: bool):
 
 
 def main():
+    gc.disable()  # collections run only between legs (see collected)
     args = parse()
     if args.apply_only:
         apply_only(args)
@@ -502,6 +530,7 @@ def main():
     torch.cuda.synchronize()
     h.pass_timing(reset=True)
     recs = []
+    gc.collect()
     t0 = time.perf_counter()
     for _ in range(args.steps):
         recs.append(h.step())
