@@ -194,9 +194,13 @@ def batch_leg(steps: int, log, precision: str = "fp64"):
     import time as _t
     import synth
     from paper_2405_19991_amd import Batch
+    import torch
     ws = synth.config4()
     probs = [dict(n=w.n, target=w.target, vf=w.vf) for w in ws]
+    torch.cuda.synchronize()
+    free0 = torch.cuda.mem_get_info()[0]
     B = Batch(probs, tol=1e-6, precision=precision)
+    free_min = torch.cuda.mem_get_info()[0]
     for d, w in enumerate(ws):
         B.set_density(d, w.rho0)
     B.step()  # warm-up (graph capture)
@@ -212,11 +216,13 @@ def batch_leg(steps: int, log, precision: str = "fp64"):
         log(f"batch {precision} step: {step_ms[-1]:.1f} ms (library: step {inf['step_ms']:.1f}, solve {inf['solve_ms']:.1f}), "
             f"max pcg {max(max(r['pcg_iters']) for r in recs)}, mean g {sum(r['g'] for r in recs) / len(recs):.3e}")
     t1 = _t.perf_counter()
+    free_min = min(free_min, torch.cuda.mem_get_info()[0])
     info = B.info()
     dev_bytes = B.device_bytes()
     B.close()
     return {"workload": f"batch64_n32-64_{precision}", "designs": len(ws), "cells": int(info["cells"]),
-            "device_bytes": dev_bytes, "s_per_oc_iter": (t1 - t0) / steps, "pcg_dof_updates_per_s": iters / (t1 - t0),
+            "device_bytes": dev_bytes, "device_in_use_peak_bytes": int(free0 - free_min),
+            "s_per_oc_iter": (t1 - t0) / steps, "pcg_dof_updates_per_s": iters / (t1 - t0),
             "iteration": "fused" if info["fused"] else "two_pass", "refreshes": int(info["refreshes"]),
             "tile_tx": int(info["tile_tx"]), "tile_tz": int(info["tile_tz"]), "work_items": int(info["work_items"]),
             "steps": steps, "step_ms": [round(x, 2) for x in step_ms]}
@@ -511,12 +517,24 @@ def main():
     w.tol = args.tol
     n = w.n
     nn = n ** 3
+    # device memory in use (hipMemGetInfo, whole device: the library, the HIP
+    # runtime and torch's cache) before the context exists, then sampled after
+    # its creation (which includes the autotuner's timing) and after every
+    # design iteration; the library allocates nothing per iteration
+    torch.cuda.synchronize()
+    free0, total_mem = torch.cuda.mem_get_info()
+    free_min = [free0]
+
+    def sample_mem():
+        free_min[0] = min(free_min[0], torch.cuda.mem_get_info()[0])
+
     h = Homogenization(n, (w.k0, w.kmin), w.target, vf=w.vf, penal=w.penal, filter_radius=w.rfilter,
                        precision=args.precision, guess=args.guess, tol=w.tol, kernel_variant=args.variant,
                        tile_tx=args.solver_tx, tile_tz=args.solver_tz, preconditioner=args.preconditioner,
                        mg_sweeps=args.mg_sweeps, mg_coarse_sweeps=args.mg_coarse_sweeps,
                        reliable_delta=args.reliable_delta, check_every=args.check_every)
     h.set_density(w.rho0)
+    sample_mem()
     def log(msg):
         print(msg, file=sys.stderr, flush=True)
 
@@ -527,6 +545,7 @@ def main():
         if first_kappa is None:
             first_kappa = r["kappa"]
         log(f"warmup {i}: g={r['g']:.4e} pcg={r['pcg_iters']} ms={r['ms_total']:.1f}")
+        sample_mem()
     torch.cuda.synchronize()
     h.pass_timing(reset=True)
     recs = []
@@ -538,6 +557,7 @@ def main():
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     wall = t1 - t0
+    sample_mem()  # after the timed region (mem_get_info synchronises the device)
     if first_kappa is None:
         first_kappa = recs[0]["kappa"]
     pcg_iters = sum(sum(r["pcg_iters"]) for r in recs)
@@ -649,6 +669,11 @@ def main():
         "solver_tile": tile,
         "tuning": tuning,
         "device_bytes": dev_bytes,
+        "device_memory": {"context_bytes": dev_bytes, "device_in_use_peak_bytes": int(free0 - free_min[0]),
+                          "device_total_bytes": int(total_mem),
+                          "basis": "hipMemGetInfo (whole device) before the context exists, minus its minimum free "
+                                   "memory sampled after creation, after each warm-up and after the timed "
+                                   "iterations: the library, the HIP runtime and torch's cache"},
         "kappa_rel_err_vs_oracle": oracle_tensor_error(w, first_kappa, args.tol),
         "last_g": recs[-1]["g"],
         "last_kappa": recs[-1]["kappa"],
