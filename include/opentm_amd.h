@@ -252,6 +252,8 @@ typedef struct {
     double ms_solve;
     int32_t stop; /* 1 when the stall test of the governor fired */
     double move;  /* OC move limit this iteration's update used */
+    int32_t stalled; /* the solve of this iteration: 0; 1 it stagnated (no 4x residual drop
+                        within stall_window iterations), 2 its residual was not finite */
 } otm_iter_record;
 
 typedef struct otm_ctx otm_ctx;
@@ -456,7 +458,9 @@ int otm_batch_set_density(otm_batch* batch, int32_t d, const double* rho_host, i
 /* OTM_FIELD_RHO, _RHOF, _K, _CHI (3 n_d^3), _SENS, _SENS_ELEM of design d */
 int otm_batch_get_field(otm_batch* batch, int32_t d, int32_t field, double* host_out, int64_t count);
 /* One design iteration for every design; recs (may be NULL) receives count
- * records.  OTM_NOT_CONVERGED if some solve hit max_iter. */
+ * records.  A design whose solve stagnates (the stall_window rule of a
+ * context's solve) stops there, its record says so (stalled), and the others
+ * go on.  OTM_NOT_CONVERGED if some solve hit max_iter or stalled. */
 int otm_batch_step(otm_batch* batch, otm_iter_record* recs);
 /* 1 (default): replay the captured PCG chunk; 0: launch it eagerly. */
 int otm_batch_set_graph(otm_batch* batch, int32_t use_graph);

@@ -100,13 +100,15 @@ class IterRecord(ctypes.Structure):
                 ("volume", ctypes.c_double), ("low_bound", ctypes.c_double), ("vstar", ctypes.c_double),
                 ("lambda_", ctypes.c_double), ("pcg_iters", ctypes.c_int32 * 3),
                 ("rel_residual", ctypes.c_double * 3), ("ms_total", ctypes.c_double),
-                ("ms_solve", ctypes.c_double), ("stop", ctypes.c_int32), ("move", ctypes.c_double)]
+                ("ms_solve", ctypes.c_double), ("stop", ctypes.c_int32), ("move", ctypes.c_double),
+                ("stalled", ctypes.c_int32)]
 
     def to_dict(self):
         return dict(iter=self.iter, g=self.g, kappa=list(self.kappa), volume=self.volume,
                     low_bound=self.low_bound, vstar=self.vstar, lam=self.lambda_,
                     pcg_iters=list(self.pcg_iters), rel_residual=list(self.rel_residual),
-                    ms_total=self.ms_total, ms_solve=self.ms_solve, stop=self.stop, move=self.move)
+                    ms_total=self.ms_total, ms_solve=self.ms_solve, stop=self.stop, move=self.move,
+                    stalled=self.stalled)
 
 
 _lib = None

@@ -344,7 +344,7 @@ class Batch:
                  check_every: int = 16, guess: str = "zero", move: float = 0.05, eta: float = 0.5, move_min: float = 0.0,
                  rho_min: float = 1e-3, governor: Optional[Dict[str, float]] = None, autotune: bool = True,
                  tile_tx: int = 0, tile_tz: int = 0, iteration: str = "auto", precision: str = "fp64",
-                 reliable_delta: Optional[float] = None, stream=None):
+                 reliable_delta: Optional[float] = None, stall_window: int = 0, stream=None):
         L = N.lib()
         arr = (N.Problem * len(problems))()
         self.ns = []
@@ -369,6 +369,7 @@ class Batch:
         s.tol, s.max_iter, s.check_every = float(tol), int(max_iter), int(check_every)
         s.autotune, s.tile_tx, s.tile_tz = int(bool(autotune)), int(tile_tx), int(tile_tz)
         s.kernel_variant = self.ITERATIONS[iteration]
+        s.stall_window = int(stall_window)
         o.move, o.eta, o.rho_min, o.move_min = float(move), float(eta), float(rho_min), float(move_min)
         for key, val in (governor or {}).items():
             setattr(g, key, val)

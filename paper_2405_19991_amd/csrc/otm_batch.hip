@@ -63,6 +63,7 @@ struct otm_batch {
     float *r32[2] = {nullptr, nullptr}, *q32[2] = {nullptr, nullptr}, *p32[2] = {nullptr, nullptr};
     float *x32 = nullptr, *k32 = nullptr, *dinv32 = nullptr;
     int refreshes = 0;  // float64 residual refreshes of the last solve
+    std::vector<int> stalled;  // per design: 0, 1 stagnated, 2 non-finite residual (last solve)
     W6* dw6 = nullptr;
     double* dvstar = nullptr;
     double* dmove = nullptr;  // OC move limit per design
@@ -240,6 +241,72 @@ bool all_inactive(const otm_batch* c) {
     return true;
 }
 
+// Stagnation watch per design, the rule a context's solve uses: a design
+// whose running loads have not cut their recursive residual 4x within its
+// window of iterations (stall_window, else 200 + 10 n), or whose residual is
+// not finite, stops: its loads are switched off on the device and stay off
+// through later confirmation refreshes, and the step reports it.
+struct BatchWatch {
+    std::vector<double> best;
+    std::vector<int> at, window;
+    void start(otm_batch* c) {
+        best.assign(3 * (size_t)c->count, 0.0);
+        at.assign(3 * (size_t)c->count, 0);
+        window.resize(c->count);
+        c->stalled.assign(c->count, 0);
+        for (int d = 0; d < c->count; ++d) {
+            window[d] = c->so.stall_window > 0 ? c->so.stall_window : 200 + 10 * c->prob[d].n;
+            for (int l = 0; l < 3; ++l) {
+                best[3 * d + l] = c->h_sc[d].rr[l];
+                at[3 * d + l] = c->h_sc[d].iters[l];
+            }
+        }
+    }
+    // after a chunk: true when some design got a verdict now
+    bool check(otm_batch* c) {
+        bool any = false;
+        for (int d = 0; d < c->count; ++d) {
+            if (c->stalled[d]) continue;
+            for (int l = 0; l < 3; ++l) {
+                const Scalars& s = c->h_sc[d];
+                if (!s.active[l]) continue;
+                const size_t i = 3 * (size_t)d + l;
+                if (!std::isfinite(s.rr[l])) {
+                    c->stalled[d] = 2;
+                } else if (s.rr[l] <= 0.25 * best[i]) {
+                    best[i] = s.rr[l];
+                    at[i] = s.iters[l];
+                } else if (s.iters[l] - at[i] > window[d]) {
+                    c->stalled[d] = 1;
+                }
+                if (c->stalled[d]) {
+                    any = true;
+                    break;
+                }
+            }
+        }
+        return any;
+    }
+};
+
+// Switch off the loads of every design with a verdict (host copy and device;
+// after a scalar sync the two agree).
+int hold_stalled(otm_batch* c) {
+    const size_t head = offsetof(Scalars, sum_rho);
+    for (int d = 0; d < c->count; ++d) {
+        if (!c->stalled[d]) continue;
+        Scalars& s = c->h_sc[d];
+        if (!(s.active[0] || s.active[1] || s.active[2])) continue;
+        for (int l = 0; l < 3; ++l) {
+            s.active[l] = 0;
+            s.alpha[l] = 0.0;
+            s.beta[l] = 0.0;
+        }
+        BCHK(c, hipMemcpyAsync(&c->sc[d], &c->h_sc[d], head, hipMemcpyHostToDevice, c->stream));
+    }
+    return OTM_OK;
+}
+
 int max_iters(const otm_batch* c) {
     int m = 0;
     for (int d = 0; d < c->count; ++d)
@@ -295,9 +362,12 @@ int solve_fused(otm_batch* c, bool x_zero) {
     for (int d = 0; d < c->count; ++d)
         for (int l = 0; l < 3; ++l) rr_ref[3 * d + l] = c->h_sc[d].rr_true[l];
     const double d2 = c->so.reliable_delta * c->so.reliable_delta;
+    BatchWatch watch;
+    watch.start(c);
     while (!all_inactive(c) && max_iters(c) < c->so.max_iter) {
         if ((rc = run_chunk(c))) return rc;
         if ((rc = sync_sc(c))) return rc;
+        if (watch.check(c) && (rc = hold_stalled(c))) return rc;
         bool refresh = all_inactive(c);
         if (c->mixed)
             for (int d = 0; d < c->count && !refresh; ++d)
@@ -308,6 +378,7 @@ int solve_fused(otm_batch* c, bool x_zero) {
             residual_f(c, false, false);
             if ((rc = blaunch_ok(c, "refresh"))) return rc;
             if ((rc = sync_sc(c))) return rc;
+            if ((rc = hold_stalled(c))) return rc;  // a refresh restarts loads that miss the tolerance
             for (int d = 0; d < c->count; ++d)
                 for (int l = 0; l < 3; ++l) rr_ref[3 * d + l] = c->h_sc[d].rr_true[l];
             if (c->mixed) ++c->refreshes;
@@ -328,13 +399,17 @@ int solve(otm_batch* c, bool x_zero) {
                       c->sc, c->stream);
     if ((rc = blaunch_ok(c, "residual"))) return rc;
     if ((rc = sync_sc(c))) return rc;
+    BatchWatch watch;
+    watch.start(c);
     while (!all_inactive(c) && max_iters(c) < c->so.max_iter) {
         if ((rc = run_chunk(c))) return rc;
         if ((rc = sync_sc(c))) return rc;
+        if (watch.check(c) && (rc = hold_stalled(c))) return rc;
         if (all_inactive(c)) {
             launch_b_residual(c->tab, c->k, c->b, c->x, c->r, c->p[c->pbuf], c->dinv, RES_START, 0, c->partials, c->sc,
                               c->stream);
             if ((rc = sync_sc(c))) return rc;
+            if ((rc = hold_stalled(c))) return rc;
         }
     }
     launch_b_sum3(c->tab, c->x, 0, c->partials, c->sc, c->stream);
@@ -525,7 +600,8 @@ int otm_batch_create(const otm_problem* problems, int32_t count, const otm_solve
                                                                           c->so.kernel_variant == 4))) &&
                            c->so.preconditioner == OTM_PRECOND_JACOBI;
     if (!supported || !(c->so.tol > 0.0) || c->so.max_iter < 1 || c->so.check_every < 1 ||
-        c->so.kernel_variant < 0 || c->so.kernel_variant > 5 || !(c->so.reliable_delta > 0.0)) {
+        c->so.kernel_variant < 0 || c->so.kernel_variant > 5 || !(c->so.reliable_delta > 0.0) ||
+        c->so.stall_window < 0) {
         const bool known = (c->so.precision == OTM_FP64 || c->mixed) && c->so.kernel_variant >= 0 &&
                            c->so.kernel_variant <= 5 &&
                            (c->so.preconditioner == OTM_PRECOND_JACOBI || c->so.preconditioner == OTM_PRECOND_MG);
@@ -729,6 +805,7 @@ int otm_batch_step(otm_batch* c, otm_iter_record* recs) {
         c->low[d] = s.sum_rhofp / nn;
         for (int l = 0; l < 3; ++l)
             if (s.active[l]) conv = false;
+        if (c->stalled[d]) conv = false;
         if (recs) {
             otm_iter_record& R = recs[d];
             R.iter = c->iter;
@@ -740,6 +817,7 @@ int otm_batch_step(otm_batch* c, otm_iter_record* recs) {
                 R.pcg_iters[l] = s.iters[l];
                 R.rel_residual[l] = s.bb[l] > 0.0 ? std::sqrt(s.rr_true[l] / s.bb[l]) : 0.0;
             }
+            R.stalled = c->stalled[d];
         }
         moves[d] = next_move(c->oc, c->gov[d], gg);
         advance_volume_bound(c->go, c->oc.rho_min, c->gov[d], gg, c->low[d], c->volume[d]);

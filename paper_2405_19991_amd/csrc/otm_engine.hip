@@ -1505,6 +1505,7 @@ int otm_step(otm_ctx* c, otm_iter_record* rec) {
         rec->ms_solve = st.ms_solve;
         rec->stop = c->vb.flat >= c->go.stall_iters ? 1 : 0;
         rec->move = move;
+        rec->stalled = st.stalled;
     }
     c->iter += 1;
     return hrc;

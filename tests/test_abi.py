@@ -143,6 +143,9 @@ def test_batch_precision_validation(L):
     s, o, g = N.default_options()
     s.precision, s.reliable_delta = N.OTM_MIXED, 0.0
     assert L.otm_batch_create(arr, 1, ctypes.byref(s), None, None, None, ctypes.byref(h)) == N.OTM_EINVAL
+    s, o, g = N.default_options()
+    s.stall_window = -1
+    assert L.otm_batch_create(arr, 1, ctypes.byref(s), None, None, None, ctypes.byref(h)) == N.OTM_EINVAL
 
 
 def _problem(N, n=8):

@@ -100,3 +100,49 @@ def test_poisoned_network_falls_back_to_zero_start(cell):
     assert used == 0.0 and sl["converged"]
     assert sl["iterations"] == sz["iterations"]
     np.testing.assert_array_equal(kl, kz)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_batch_unreachable_tolerance_stops_each_design(precision):
+    """Batches apply a context's stagnation rule per design: at an
+    unreachable tolerance every design stops after its window (long before
+    max_iter), its record says stalled, the step returns OTM_NOT_CONVERGED,
+    and the solution it keeps still gives the oracle's tensor."""
+    from paper_2405_19991_amd import Batch
+    from paper_2405_19991_amd import _native as N
+    g = synth.rng(71)
+    probs = []
+    for d, n in enumerate((8, 12, 16)):
+        probs.append(dict(n=n, target=synth.random_spd_target(g), vf=0.3,
+                          rho=synth.smoothed_noise(n, 0.15, 0.45, 710 + d)))
+    with Batch(probs, tol=1e-18, precision=precision, autotune=False, iteration="fused", stall_window=60,
+               max_iter=20000) as B:
+        for d, p in enumerate(probs):
+            B.set_density(d, p["rho"])
+        recs = B.step()
+    for d, p in enumerate(probs):
+        r = recs[d]
+        print(f"{precision} design {d} (n={p['n']}): iters {r['pcg_iters']}, rel {r['rel_residual']}, "
+              f"stalled {r['stalled']}", flush=True)
+        assert r["status"] == N.OTM_NOT_CONVERGED
+        assert r["stalled"] == 1
+        assert max(r["pcg_iters"]) < 2000
+        assert max(r["rel_residual"]) < 1e-4
+        ref = O.homogenize(p["rho"], O.Params(tol=1e-13))
+        rel = np.linalg.norm(np.array(r["kappa"]) - ref["kappa"]) / np.linalg.norm(ref["kappa"])
+        assert rel < 1e-9
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_batch_reachable_tolerance_does_not_stall(precision):
+    from paper_2405_19991_amd import Batch
+    from paper_2405_19991_amd import _native as N
+    g = synth.rng(73)
+    probs = [dict(n=n, target=synth.random_spd_target(g), vf=0.3, rho=synth.smoothed_noise(n, 0.15, 0.45, 730 + n))
+             for n in (8, 12, 16)]
+    with Batch(probs, tol=1e-8, precision=precision, autotune=False, iteration="fused", stall_window=60) as B:
+        for d, p in enumerate(probs):
+            B.set_density(d, p["rho"])
+        recs = B.step()
+    for r in recs:
+        assert r["status"] == N.OTM_OK and r["stalled"] == 0 and max(r["rel_residual"]) <= 1e-8
