@@ -94,18 +94,26 @@ def test_batch_full_size_mix_matches_singles_and_oracle():
     for d, w in enumerate(ws):
         B.set_density(d, w.rho0)
     recs = B.step()
-    B.close()
     picks = {}
     for d, w in enumerate(ws):
         picks.setdefault(w.n, d)
+    brho = {d: B.get_field(d, "rho") for d in picks.values()}
+    B.close()
     for n, d in sorted(picks.items()):
         w = ws[d]
         with Homogenization(n, (w.k0, w.kmin), w.target, vf=w.vf, tol=1e-6) as h:
             h.set_density(w.rho0)
             kappa, _ = h.homogenize()
+            h.set_density(w.rho0)
+            r = h.step()
+            rho1 = h.get_field("rho")
         rel = np.linalg.norm(np.array(recs[d]["kappa"]) - np.array(kappa)) / np.linalg.norm(kappa)
-        print(f"design {d} (n={n}): batch vs single {rel:.2e}", flush=True)
+        print(f"design {d} (n={n}): batch vs single {rel:.2e}, updated density max diff "
+              f"{np.max(np.abs(brho[d] - rho1)):.2e}", flush=True)
         assert rel <= 1e-8
+        # the whole design iteration (sensitivities, filter transpose, OC)
+        assert recs[d]["vstar"] == pytest.approx(r["vstar"], rel=1e-12)
+        np.testing.assert_allclose(brho[d], rho1, rtol=0, atol=1e-8)
     d = picks[32]
     ref = O.homogenize(ws[d].rho0, O.Params(tol=1e-12))
     rel = np.linalg.norm(np.array(recs[d]["kappa"]) - ref["kappa"]) / np.linalg.norm(ref["kappa"])
