@@ -334,7 +334,8 @@ class Batch:
     chunks replay a captured hipGraph.  float64 or mixed precision.
 
     precision: "fp64", or "mixed" (float32 operator and Krylov vectors with
-    float64 residual refreshes; fused iteration only).  iteration: "auto"
+    float64 residual refreshes; fused iteration only; reliable_delta defaults
+    to 1e-4 here, since a refresh covers every design).  iteration: "auto"
     (the autotuner picks the fused single-pass or the two-pass PCG
     iteration; with autotune off, the two-pass one), "fused" or "two_pass"."""
 
@@ -365,6 +366,11 @@ class Batch:
         s.precision = {"fp64": N.OTM_FP64, "mixed": N.OTM_MIXED}[precision]
         if reliable_delta is not None:
             s.reliable_delta = float(reliable_delta)
+        elif precision == "mixed":
+            # a batch refreshes every design at once: fewer, deeper refreshes
+            # pay off (1e-4: 27.7 ms per 64-design iteration against 28.8 ms
+            # at a context's 1e-2, same iterations)
+            s.reliable_delta = 1e-4
         s.guess = {"zero": N.OTM_GUESS_ZERO, "previous": N.OTM_GUESS_PREVIOUS}[guess]
         s.tol, s.max_iter, s.check_every = float(tol), int(max_iter), int(check_every)
         s.autotune, s.tile_tx, s.tile_tz = int(bool(autotune)), int(tile_tx), int(tile_tz)
