@@ -357,10 +357,12 @@ int otm_set_governor(otm_ctx* ctx, const double state8[8]);
  * solution chi (the warm start of OTM_GUESS_PREVIOUS; present once a solve
  * has run) and the adaptive volume bound's state (Algorithm 1, as
  * otm_get_governor) go to one binary file that this library writes and reads:
- *   "OTMSTATE" | u32 version 1 | i32 n | u32 flags (bit 0: chi present) |
+ *   "OTMSTATE" | u32 version 2 | i32 n | u32 flags (bit 0: chi present) |
  *   u32 0 | f64[11] k0, kmin, penal, filter radius, target[6], objective |
- *   f64[8] governor state | f64 rho[n^3] | f64 chi[3 n^3] if bit 0 |
- *   u64 FNV-1a hash of every preceding byte; little-endian.
+ *   f64[8] governor state | f64 the objective's last change (memory of the
+ *   adaptive OC step) | f64 rho[n^3] | f64 chi[3 n^3] if bit 0 |
+ *   u64 FNV-1a hash of every preceding byte; little-endian.  Version 1 files
+ *   (no last change; read as 0) load as well.
  * save writes path.tmp and renames it over path.  load restores all three
  * into a context created for the same n and problem constants, after which
  * otm_step continues the interrupted run exactly (same iterates, bit for bit).
@@ -472,6 +474,25 @@ int otm_batch_info(const otm_batch* batch, double info10[10]);
 /* Adaptive volume bound state of design d (Algorithm 1), the 8 doubles of
  * otm_get_governor; the iteration count is the batch's. */
 int otm_batch_get_governor(const otm_batch* batch, int32_t d, double state8[8]);
+/* Checkpoint / resume of a batch run: every design's density, its previous
+ * solution (when a step has run) and its adaptive volume bound state
+ * (Algorithm 1, with the adaptive OC step's memory), plus the batch's
+ * iteration count, in one binary file that this library writes and reads:
+ *   "OTMBATCH" | u32 version 1 | i32 count | u32 flags (bit 0: solutions) |
+ *   i32 iterations done | per design: i32 n | u32 0 | f64[11] k0, kmin,
+ *   penal, filter radius, target[6], objective | f64[8] V*, Df, stalls, gap,
+ *   previous objective, flat count, OC step, last objective change |
+ *   f64 rho of every design in order | f64 chi (3 n^3 each) if bit 0 |
+ *   u64 FNV-1a hash of every preceding byte; little-endian.
+ * save writes path.tmp and renames it over path.  load restores the state
+ * into a batch created for the same designs (count, n and problem constants
+ * in the same order), after which otm_batch_step continues the interrupted
+ * run exactly.  Errors: OTM_EINVAL (null or empty path, other designs),
+ * OTM_ESTATE (save before every design has a density), OTM_EIO (open, read
+ * or write failure; wrong magic, version, size or checksum),
+ * OTM_ENONFINITE, OTM_EDEVICE. */
+int otm_batch_save_state(otm_batch* batch, const char* path);
+int otm_batch_load_state(otm_batch* batch, const char* path);
 /* Device memory the batch holds (its arenas, tables and graph buffers), bytes. */
 int otm_batch_device_bytes(const otm_batch* batch, int64_t* bytes);
 const char* otm_batch_last_error(const otm_batch* batch);

@@ -58,7 +58,8 @@ EXPORTED = [
     "otm_nn_get_grads", "otm_nn_forward", "otm_nn_accumulate", "otm_nn_adam", "otm_nn_zero_grads",
     "otm_nn_last_error", "otm_set_network", "otm_init_density", "otm_apply_device_tiled", "otm_device_bytes",
     "otm_batch_device_bytes", "otm_batch_get_governor", "otm_oc_update_noalloc",
-    "otm_save_state", "otm_load_state", "otm_nn_save", "otm_nn_load",
+    "otm_save_state", "otm_load_state", "otm_nn_save", "otm_nn_load", "otm_batch_save_state",
+    "otm_batch_load_state",
 ]
 
 
@@ -187,6 +188,8 @@ def lib():
         "otm_nn_last_error": ([vp], ctypes.c_char_p),
         "otm_set_network": ([vp, vp], ctypes.c_int),
         "otm_save_state": ([ctx, ctypes.c_char_p], ctypes.c_int),
+        "otm_batch_save_state": ([vp, ctypes.c_char_p], ctypes.c_int),
+        "otm_batch_load_state": ([vp, ctypes.c_char_p], ctypes.c_int),
         "otm_load_state": ([ctx, ctypes.c_char_p], ctypes.c_int),
         "otm_nn_save": ([vp, ctypes.c_char_p], ctypes.c_int),
         "otm_nn_load": ([vp, ctypes.c_char_p], ctypes.c_int),

@@ -422,6 +422,16 @@ class Batch:
     def set_graph(self, on: bool) -> None:
         self._chk(self._L.otm_batch_set_graph(self._h, int(bool(on))))
 
+    def save_state(self, path: str) -> None:
+        """Checkpoint (otm_batch_save_state): every design's density, last
+        solution and governor state, and the iteration count."""
+        self._chk(self._L.otm_batch_save_state(self._h, str(path).encode()))
+
+    def load_state(self, path: str) -> None:
+        """Resume from a file written by save_state for the same designs
+        (otm_batch_load_state)."""
+        self._chk(self._L.otm_batch_load_state(self._h, str(path).encode()))
+
     def step(self) -> List[Dict[str, object]]:
         recs = (N.IterRecord * self.count)()
         status = self._chk(self._L.otm_batch_step(self._h, recs))
@@ -438,7 +448,7 @@ class Batch:
         return dict(zip(keys, a.tolist()))
 
     def governor_state(self, d: int) -> List[float]:
-        """Adaptive volume bound of design d: [V*, Df, stalls, gap, g_prev, flat, iter, 0]."""
+        """Adaptive volume bound of design d: [V*, Df, stalls, gap, g_prev, flat, iter, OC step]."""
         s = np.zeros(8)
         self._chk(self._L.otm_batch_get_governor(self._h, int(d), _ptr(s)))
         return s.tolist()

@@ -17,6 +17,7 @@
 #include <chrono>
 #include <cmath>
 #include <cstddef>
+#include <cstdio>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -860,6 +861,167 @@ int otm_batch_step(otm_batch* c, otm_iter_record* recs) {
     c->t_ms[3] = std::chrono::duration<double, std::milli>(t3 - t0).count();
     c->iter += 1;
     return conv ? OTM_OK : OTM_NOT_CONVERGED;
+}
+
+// ---- checkpoint / resume -----------------------------------------------------
+// A batch run's state, in one little-endian binary file written here:
+//   "OTMBATCH" | u32 version 1 | i32 count | u32 flags (bit 0: solutions
+//   present) | i32 design iterations done | per design: i32 n | u32 0 |
+//   f64 problem[11] (k0, kmin, penal, filter radius, target[6], objective) |
+//   f64 governor[8] (V*, Df, stalls, gap, previous objective, flat count,
+//   OC step, the objective's last change) | then the density arena (every
+//   design's rho[n^3] in order) | the solution arena (3 n^3 per design) if
+//   bit 0 | u64 FNV-1a hash of every preceding byte.
+// Written under path.tmp and renamed over path, so a crash while saving
+// leaves any earlier checkpoint whole.
+namespace {
+const char kBatchMagic[8] = {'O', 'T', 'M', 'B', 'A', 'T', 'C', 'H'};
+constexpr uint32_t kBatchVersion = 1;
+
+void governor_out(const VolumeBound& v, double g[8]) {
+    g[0] = v.vstar;
+    g[1] = v.df;
+    g[2] = (double)v.stalls;
+    g[3] = v.gap;
+    g[4] = v.g_prev;
+    g[5] = (double)v.flat;
+    g[6] = v.move;
+    g[7] = v.dg_prev;
+}
+
+void governor_in(const double g[8], VolumeBound& v) {
+    v.vstar = g[0];
+    v.df = g[1];
+    v.stalls = (int)g[2];
+    v.gap = g[3];
+    v.g_prev = g[4];
+    v.flat = (int)g[5];
+    v.move = g[6] > 0.0 ? g[6] : 0.0;
+    v.dg_prev = g[7];
+}
+}  // namespace
+
+int otm_batch_save_state(otm_batch* c, const char* path) {
+    if (!c || !path || !path[0]) return OTM_EINVAL;
+    for (int d = 0; d < c->count; ++d)
+        if (!c->have_density[d]) return bfail(c, OTM_ESTATE, "every design needs a density to save");
+    std::vector<double> rho((size_t)c->total), chi;
+    BCHK(c, hipMemcpyAsync(rho.data(), c->rho, rho.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    if (c->have_solution) {
+        chi.resize(3 * (size_t)c->total);
+        BCHK(c, hipMemcpyAsync(chi.data(), c->x, chi.size() * sizeof(double), hipMemcpyDeviceToHost, c->stream));
+    }
+    BCHK(c, hipStreamSynchronize(c->stream));
+    const uint32_t version = kBatchVersion, flags = c->have_solution ? 1u : 0u, zero = 0u;
+    const int32_t count = c->count, iter = c->iter;
+    const std::string tmp = std::string(path) + ".tmp";
+    FILE* f = std::fopen(tmp.c_str(), "wb");
+    if (!f) return bfail(c, OTM_EIO, "cannot open " + tmp + " for writing");
+    Fnv1a h;
+    bool ok = true;
+    auto put = [&](const void* p, size_t len) {
+        if (!ok || len == 0) return;
+        h.add(p, len);
+        ok = std::fwrite(p, 1, len, f) == len;
+    };
+    put(kBatchMagic, 8);
+    put(&version, 4);
+    put(&count, 4);
+    put(&flags, 4);
+    put(&iter, 4);
+    for (int d = 0; d < c->count; ++d) {
+        const int32_t n = c->prob[d].n;
+        double sig[11], gov[8];
+        problem_signature(c->prob[d], sig);
+        governor_out(c->gov[d], gov);
+        put(&n, 4);
+        put(&zero, 4);
+        put(sig, sizeof(sig));
+        put(gov, sizeof(gov));
+    }
+    put(rho.data(), rho.size() * sizeof(double));
+    put(chi.data(), chi.size() * sizeof(double));
+    const uint64_t digest = h.h;
+    ok = ok && std::fwrite(&digest, 1, 8, f) == 8;
+    ok = (std::fclose(f) == 0) && ok;
+    if (!ok || std::rename(tmp.c_str(), path) != 0) {
+        std::remove(tmp.c_str());
+        return bfail(c, OTM_EIO, std::string("cannot write ") + path);
+    }
+    return OTM_OK;
+}
+
+int otm_batch_load_state(otm_batch* c, const char* path) {
+    if (!c || !path || !path[0]) return OTM_EINVAL;
+    FILE* f = std::fopen(path, "rb");
+    if (!f) return bfail(c, OTM_EIO, std::string("cannot open ") + path);
+    std::vector<unsigned char> buf;
+    unsigned char chunk[1 << 16];
+    size_t got;
+    while ((got = std::fread(chunk, 1, sizeof(chunk), f)) > 0) buf.insert(buf.end(), chunk, chunk + got);
+    const bool read_err = std::ferror(f) != 0;
+    std::fclose(f);
+    if (read_err) return bfail(c, OTM_EIO, std::string("cannot read ") + path);
+    const size_t top = 8 + 4 * 4, per = 8 + 11 * 8 + 8 * 8;
+    if (buf.size() < top + 8 || std::memcmp(buf.data(), kBatchMagic, 8) != 0)
+        return bfail(c, OTM_EIO, std::string(path) + " is not a batch state file");
+    uint32_t version, flags;
+    int32_t count, iter;
+    std::memcpy(&version, &buf[8], 4);
+    std::memcpy(&count, &buf[12], 4);
+    std::memcpy(&flags, &buf[16], 4);
+    std::memcpy(&iter, &buf[20], 4);
+    if (version != kBatchVersion) return bfail(c, OTM_EIO, "unsupported batch state file version");
+    if (count != c->count) return bfail(c, OTM_EINVAL, "batch state file holds another number of designs");
+    const size_t head = top + (size_t)count * per;
+    if (buf.size() < head + 8) return bfail(c, OTM_EIO, "batch state file is shorter than its header");
+    // The body's size follows from the file's own per-design n, so a whole
+    // file written for other grid sizes is told apart from a damaged one.
+    size_t cells = 0;
+    for (int d = 0; d < count; ++d) {
+        int32_t n;
+        std::memcpy(&n, &buf[top + (size_t)d * per], 4);
+        if (n < 4 || n > 1024) return bfail(c, OTM_EIO, "batch state file holds an invalid grid size");
+        cells += (size_t)n * n * n;
+    }
+    const size_t body = cells * sizeof(double) * ((flags & 1u) ? 4 : 1);
+    if (buf.size() != head + body + 8) return bfail(c, OTM_EIO, "batch state file size does not match its header");
+    Fnv1a h;
+    h.add(buf.data(), head + body);
+    uint64_t digest;
+    std::memcpy(&digest, &buf[head + body], 8);
+    if (digest != h.h) return bfail(c, OTM_EIO, "batch state file checksum mismatch");
+    std::vector<VolumeBound> gov(c->count);
+    for (int d = 0; d < c->count; ++d) {
+        const unsigned char* q = &buf[top + (size_t)d * per];
+        int32_t n;
+        double sig[11], mine[11], g[8];
+        std::memcpy(&n, q, 4);
+        std::memcpy(sig, q + 8, sizeof(sig));
+        std::memcpy(g, q + 8 + sizeof(sig), sizeof(g));
+        problem_signature(c->prob[d], mine);
+        if (n != c->prob[d].n || std::memcmp(sig, mine, sizeof(sig)) != 0)
+            return bfail(c, OTM_EINVAL, "batch state file was written for other problems (n, constants, target or "
+                                        "objective of design " + std::to_string(d) + ")");
+        for (double v : g)
+            if (!std::isfinite(v)) return bfail(c, OTM_ENONFINITE, "non-finite governor state in batch state file");
+        governor_in(g, gov[d]);
+    }
+    if (cells != (size_t)c->total) return bfail(c, OTM_EINVAL, "batch state file was written for other grid sizes");
+    std::vector<double> vals(body / sizeof(double));
+    std::memcpy(vals.data(), &buf[head], body);
+    for (double v : vals)
+        if (!std::isfinite(v)) return bfail(c, OTM_ENONFINITE, "non-finite value in batch state file");
+    BCHK(c, hipMemcpyAsync(c->rho, vals.data(), (size_t)c->total * sizeof(double), hipMemcpyHostToDevice, c->stream));
+    if (flags & 1u)
+        BCHK(c, hipMemcpyAsync(c->x, vals.data() + c->total, 3 * (size_t)c->total * sizeof(double),
+                               hipMemcpyHostToDevice, c->stream));
+    BCHK(c, hipStreamSynchronize(c->stream));  // vals may go
+    c->gov = gov;
+    c->iter = iter;
+    c->have_density.assign(c->count, 1);
+    c->have_solution = (flags & 1u) != 0;
+    return OTM_OK;
 }
 
 int otm_batch_get_governor(const otm_batch* c, int32_t d, double s[8]) {

@@ -1618,36 +1618,18 @@ int otm_set_governor(otm_ctx* c, const double s[8]) {
 
 // ---- checkpoint / resume -----------------------------------------------------
 // A design run's state, in one little-endian binary file written here:
-//   "OTMSTATE" | u32 version 1 | i32 n | u32 flags (bit 0: solution present) |
+//   "OTMSTATE" | u32 version 2 | i32 n | u32 flags (bit 0: solution present) |
 //   u32 0 | f64 problem[11] (k0, kmin, penal, filter radius, target[6],
-//   objective) | f64 governor[8] (as otm_get_governor) | f64 rho[n^3] |
+//   objective) | f64 governor[8] (as otm_get_governor) | f64 the objective's
+//   last change (the adaptive OC step's memory) | f64 rho[n^3] |
 //   f64 chi[3 n^3] if bit 0 | u64 FNV-1a hash of every preceding byte.
+// Version 1 files (without the objective's last change, read as 0) load too.
 // The file is written under path.tmp and renamed over path, so a crash while
 // saving leaves any earlier checkpoint whole.
 namespace {
 
 const char kStateMagic[8] = {'O', 'T', 'M', 'S', 'T', 'A', 'T', 'E'};
-constexpr uint32_t kStateVersion = 1;
-
-struct Fnv1a {
-    uint64_t h = 1469598103934665603ull;
-    void add(const void* p, size_t len) {
-        const unsigned char* b = (const unsigned char*)p;
-        for (size_t i = 0; i < len; ++i) {
-            h ^= b[i];
-            h *= 1099511628211ull;
-        }
-    }
-};
-
-void problem_signature(const otm_problem& p, double out[11]) {
-    out[0] = p.k0;
-    out[1] = p.kmin;
-    out[2] = p.penal;
-    out[3] = p.filter_radius;
-    for (int q = 0; q < 6; ++q) out[4 + q] = p.target[q];
-    out[10] = (double)p.objective;
-}
+constexpr uint32_t kStateVersion = 2;
 
 }  // namespace
 
@@ -1683,6 +1665,7 @@ int otm_save_state(otm_ctx* c, const char* path) {
     put(&zero, 4);
     put(sig, sizeof(sig));
     put(gov, sizeof(gov));
+    put(&c->vb.dg_prev, sizeof(double));
     put(rho.data(), rho.size() * sizeof(double));
     put(chi.data(), chi.size() * sizeof(double));
     const uint64_t digest = h.h;
@@ -1706,15 +1689,16 @@ int otm_load_state(otm_ctx* c, const char* path) {
     const bool read_err = std::ferror(f) != 0;
     std::fclose(f);
     if (read_err) return fail(c, OTM_EIO, std::string("cannot read ") + path);
-    const size_t head = 8 + 4 * 4 + 11 * 8 + 8 * 8;
-    if (buf.size() < head + 8 || std::memcmp(buf.data(), kStateMagic, 8) != 0)
+    const size_t head1 = 8 + 4 * 4 + 11 * 8 + 8 * 8;
+    if (buf.size() < head1 + 8 || std::memcmp(buf.data(), kStateMagic, 8) != 0)
         return fail(c, OTM_EIO, std::string(path) + " is not a state file");
     uint32_t version, flags;
     int32_t n;
     std::memcpy(&version, &buf[8], 4);
     std::memcpy(&n, &buf[12], 4);
     std::memcpy(&flags, &buf[16], 4);
-    if (version != kStateVersion) return fail(c, OTM_EIO, "unsupported state file version");
+    if (version != 1 && version != kStateVersion) return fail(c, OTM_EIO, "unsupported state file version");
+    const size_t head = head1 + (version >= 2 ? 8 : 0);
     if (n != c->n) return fail(c, OTM_EINVAL, "state file holds another resolution");
     const size_t body = (size_t)c->nn * sizeof(double) * ((flags & 1u) ? 4 : 1);
     if (buf.size() != head + body + 8) return fail(c, OTM_EIO, "state file size does not match its header");
@@ -1733,8 +1717,12 @@ int otm_load_state(otm_ctx* c, const char* path) {
     std::memcpy(vals.data(), &buf[head], body);
     for (double v : vals)
         if (!std::isfinite(v)) return fail(c, OTM_ENONFINITE, "non-finite value in state file");
+    double dg_prev = 0.0;
+    if (version >= 2) std::memcpy(&dg_prev, &buf[head1], 8);
+    if (!std::isfinite(dg_prev)) return fail(c, OTM_ENONFINITE, "non-finite value in state file");
     int rc = otm_set_governor(c, gov);
     if (rc) return rc;
+    c->vb.dg_prev = dg_prev;
     HIPCHK(c, hipMemcpyAsync(c->rho, vals.data(), (size_t)c->nn * sizeof(double), hipMemcpyHostToDevice, c->stream));
     if (flags & 1u)
         HIPCHK(c, hipMemcpyAsync(c->x, vals.data() + c->nn, (size_t)(3 * c->nn) * sizeof(double),

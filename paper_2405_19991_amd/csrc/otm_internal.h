@@ -217,6 +217,29 @@ inline void objective_grad(int kind, const double* kappa, const double* target, 
 // Adaptive volume bound V* of the moving-constraint model (Sec. 2.3, model 3;
 // Algorithm 1), kept between design iterations of one design.  Single
 // contexts and batches hold one each and advance it with advance_volume_bound.
+// Host helpers of the checkpoint files (contexts and batches): the FNV-1a
+// 64-bit hash over the bytes written, and the problem constants a file must
+// match to be loaded.
+struct Fnv1a {
+    uint64_t h = 1469598103934665603ull;
+    void add(const void* p, size_t len) {
+        const unsigned char* b = (const unsigned char*)p;
+        for (size_t i = 0; i < len; ++i) {
+            h ^= b[i];
+            h *= 1099511628211ull;
+        }
+    }
+};
+
+inline void problem_signature(const otm_problem& p, double out[11]) {
+    out[0] = p.k0;
+    out[1] = p.kmin;
+    out[2] = p.penal;
+    out[3] = p.filter_radius;
+    for (int q = 0; q < 6; ++q) out[4 + q] = p.target[q];
+    out[10] = (double)p.objective;
+}
+
 struct VolumeBound {
     double vstar = 1.0;   // the bound V* the next OC update enforces
     double df = 1.0;      // decrease factor: the fraction of the gap removed by a shrink
