@@ -110,39 +110,34 @@ __device__ __forceinline__ void block_partials_vm(double (&v)[NV], double* parti
     __syncthreads();
 }
 
-// U: slots per thread whose loads are all issued before the first addition
-// (the additions into v keep the slot order b = tid, tid + blockDim, ...).
-template <int NV, int U = 1>
+// Sum the value-major partials of nblocks blocks (value i of block b at
+// partials[i * kMaxBlocks + b]) -> out[NV] in shared memory.  Wave w takes
+// values w, w + nwaves, ...: lane j adds blocks j, j + 64, j + 128, ... in
+// that order (eight loads in flight before their additions), then the 64
+// lane sums meet in a fixed xor butterfly.  The order depends on nblocks
+// only, so every block size gives the same bits; with at least NV waves
+// (the finalize kernels run 16) each value costs one round of loads.  The
+// loop body runs only for lane < nblocks, so nblocks - 1 is a valid index.
+template <int NV>
 __device__ __forceinline__ void final_sums_vm(const double* partials, int nblocks, double* out /* shared */) {
-    double v[NV];
+    const int lane = threadIdx.x & 63, nw = (int)blockDim.x >> 6;
+    for (int i = (int)threadIdx.x >> 6; i < NV; i += nw) {
+        const double* src = partials + (size_t)i * kMaxBlocks;
+        double s = 0.0;
+        for (int b0 = lane; b0 < nblocks; b0 += 8 * 64) {
+            double t[8];
 #pragma unroll
-    for (int i = 0; i < NV; ++i) v[i] = 0.0;
-    for (int b0 = threadIdx.x; b0 < nblocks; b0 += U * blockDim.x) {
-        double t[U][NV];
+            for (int u = 0; u < 8; ++u) {  // unconditional loads (clamped index), then a select
+                const int b = b0 + 64 * u;
+                const double x = src[b < nblocks ? b : nblocks - 1];
+                t[u] = b < nblocks ? x : 0.0;
+            }
 #pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int b = b0 + u * (int)blockDim.x;
-#pragma unroll
-            for (int i = 0; i < NV; ++i) t[u][i] = b < nblocks ? partials[(size_t)i * kMaxBlocks + b] : 0.0;
+            for (int u = 0; u < 8; ++u) s += t[u];
         }
 #pragma unroll
-        for (int u = 0; u < U; ++u)
-#pragma unroll
-            for (int i = 0; i < NV; ++i) v[i] += t[u][i];
-    }
-    __shared__ double sh[NV][kBlock / 64];
-    wave_reduce<NV>(v);
-    const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
-    if (lane == 0) {
-#pragma unroll
-        for (int i = 0; i < NV; ++i) sh[i][w] = v[i];
-    }
-    __syncthreads();
-    if (threadIdx.x < NV) {
-        double s = 0.0;
-#pragma unroll
-        for (int j = 0; j < kBlock / 64; ++j) s += sh[threadIdx.x][j];
-        out[threadIdx.x] = s;
+        for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+        if (lane == 0) out[i] = s;
     }
     __syncthreads();
 }

@@ -350,8 +350,12 @@ __device__ __forceinline__ void fused_body(int tile, int slot, int nslots, bool 
         }
     };
 
+    // With every load active the first two planes' loads do not depend on the
+    // state (the flags gating them start true; what the state then switches
+    // off is loaded but not used), so they go out before the state read and
+    // its barrier, and the two latencies overlap.
     PreF<T> fa, fb;
-    if (ALL && CHAIN) {
+    if (ALL) {
         load_plane(z0 - 1, fa);
         load_plane(z0, fb);
         take_state();
@@ -383,15 +387,18 @@ __device__ __forceinline__ void fused_body(int tile, int slot, int nslots, bool 
 }
 
 // Closes a chain of passes: reduces the last pass's partial sums, advances the
-// state and writes it to the scalar block (host-visible).
-__global__ void __launch_bounds__(kBlock) k_fused_fin(int nblocks, const double* __restrict__ partials,
+// state and writes it to the scalar block (host-visible).  The last wave has
+// no sum of its own (15 sums, 16 waves): its first lane loads the state the
+// pass ran with while the other waves' partial loads are in flight, and
+// advances it.
+__global__ void __launch_bounds__(kFinThreads) k_fused_fin(int nblocks, const double* __restrict__ partials,
                                                       Scalars* __restrict__ sc, int par) {
     __shared__ double tot[kFusedSums];
-    // the state the pass ran with, loaded while the partial sums are in flight
+    const bool lead = threadIdx.x == blockDim.x - 64;
     FusedState in;
-    if (threadIdx.x == 0) in = sc->fs[par];
-    final_sums_vm<kFusedSums, 4>(partials + par * kFusedStride, nblocks, tot);
-    if (threadIdx.x != 0) return;
+    if (lead) in = sc->fs[par];
+    final_sums_vm<kFusedSums>(partials + par * kFusedStride, nblocks, tot);
+    if (!lead) return;
     FusedState s;
     fused_advance(in, tot, s);
     for (int l = 0; l < 3; ++l) {
@@ -475,7 +482,7 @@ void launch_fused(int n, const TileShape& t, bool all_active, const T* r_in, con
             launch_f<T, false, false>(n, t, r_in, q_in, p_in, r_out, q_out, p_out, x, dinv, k, ws.partials, ws.sc,
                                       par, s, ev0, ev1);
     }
-    if (fin) hipLaunchKernelGGL(k_fused_fin, dim3(1), dim3(kBlock), 0, s, t.blocks, ws.partials, ws.sc, par);
+    if (fin) hipLaunchKernelGGL(k_fused_fin, dim3(1), dim3(kFinThreads), 0, s, t.blocks, ws.partials, ws.sc, par);
 }
 
 template void launch_fused<float>(int, const TileShape&, bool, const float*, const float*, const float*, float*,
@@ -622,17 +629,18 @@ __global__ void __launch_bounds__(WX* TY)
 
 // Per design (one block each): reduce the pass's partial sums of the design's
 // items and advance its state (the batch form of k_fused_fin).
-__global__ void __launch_bounds__(kBlock) kb_fused_fin(BatchTab t, const double* __restrict__ partials,
+__global__ void __launch_bounds__(kFinThreads) kb_fused_fin(BatchTab t, const double* __restrict__ partials,
                                                        Scalars* __restrict__ sc, int par) {
     const int d = blockIdx.x;
     Scalars* s = sc + d;
     if (!design_live(s)) return;  // uniform over the block
     const BatchDesc D = t.desc[d];
     __shared__ double tot[kFusedSums];
+    const bool lead = threadIdx.x == blockDim.x - 64;  // the wave without a sum (as in k_fused_fin)
     FusedState in;
-    if (threadIdx.x == 0) in = s->fs[par];
-    final_sums_vm<kFusedSums, 4>(partials + par * kFusedStride + D.mb_start, D.mb_count, tot);
-    if (threadIdx.x != 0) return;
+    if (lead) in = s->fs[par];
+    final_sums_vm<kFusedSums>(partials + par * kFusedStride + D.mb_start, D.mb_count, tot);
+    if (!lead) return;
     FusedState st;
     fused_advance(in, tot, st);
     for (int l = 0; l < 3; ++l) {
@@ -707,7 +715,7 @@ void launch_b_fused(const BatchTab& t, int wx, int grid, const T* r_in, const T*
             hipLaunchKernelGGL((kb_fused_f64<16, 16>), dim3(grid), dim3(kBlock), 0, s, t, r_in, q_in, p_in, r_out,
                                q_out, p_out, x, dinv, k, partials, sc, par);
     }
-    if (fin) hipLaunchKernelGGL(kb_fused_fin, dim3(t.count), dim3(kBlock), 0, s, t, partials, sc, par);
+    if (fin) hipLaunchKernelGGL(kb_fused_fin, dim3(t.count), dim3(kFinThreads), 0, s, t, partials, sc, par);
 }
 
 template void launch_b_fused<float>(const BatchTab&, int, int, const float*, const float*, const float*, float*,

@@ -17,6 +17,7 @@ constexpr int kMaxReduce = 32;       // widest multi-value block reduction
 constexpr int kMaxBlocks = 4096;     // producer blocks per reduction (workspace rows)
 constexpr int kFusedSums = 15;       // partial sums per block of a fused PCG pass, per load l: [l] p.q,
                                      // [3+l] q.z, [6+l] q.D^-1 q, [9+l] r.z, [12+l] r.r
+constexpr int kFinThreads = 1024;    // fused-pass finalize: one wave per partial sum
 constexpr int kOcLevels = 5;         // bisection levels resolved per OC pass
 constexpr int kOcCands = (1 << kOcLevels) - 1;
 // passes that reach the bisection's 200-halving cap, plus the first and a spare
