@@ -113,6 +113,7 @@ struct otm_ctx {
     // check interval with every load active, bracketed by the launch's own
     // start/end events (hipExtLaunchKernelGGL)
     hipEvent_t pev[2] = {};
+    hipEvent_t cev = nullptr;  // marks the scalar copy of a check (no timing)
     double pass_ms = 0.0;
     int64_t pass_count = 0;
     double pass_bytes = 0.0;  // algorithmic bytes of one sampled launch
@@ -361,18 +362,28 @@ int solve_fused(otm_ctx* c, bool x_zero, bool mixed, const FusedBufs<T>& B, otm_
     int refreshes = 0, launches = 0;
     SolveWatch watch;
     watch.start(c->h_sc, stall_window(c));
+    // The host reads a check's scalars while one more pass (the bridge) runs,
+    // so the copy's round trip does not leave the device idle.  What the
+    // host decides from them still holds a pass later: a load that converged
+    // is left unchanged by the passes after it (no step, no count), and a
+    // residual refresh may come one pass late.  The next chunk is one pass
+    // shorter, so the checks stay check_every passes apart.
+    int bridged = 0;
     while (!all_inactive(c->h_sc) && max_iters(c->h_sc) < c->so.max_iter) {
         const bool all = all_active(c->h_sc);
+        const int len = c->so.check_every - bridged;
+        // h_sc is not read again until the copy below has landed
+        const bool bridge = max_iters(c->h_sc) + c->so.check_every < c->so.max_iter;
         bool sampled = false;
-        for (int it = 0; it < c->so.check_every; ++it) {
+        for (int it = 0; it < len; ++it) {
             const int nx = cur ^ 1;
             // sample the chunk's last pass when every load takes a full step
-            const bool sample = all && launches > 0 && it == c->so.check_every - 1;
+            const bool sample = all && launches > 0 && it == len - 1;
             // chained: passes after the first of a chunk reduce their
             // predecessor's sums themselves and the chunk's last pass is closed
             // by a finalize; else a finalize follows every pass
             const bool chained = c->fused_chain && it > 0;
-            const bool fin = !c->fused_chain || it == c->so.check_every - 1;
+            const bool fin = !c->fused_chain || it == len - 1;
             launch_fused<T>(n, c->tile2, all, B.r[cur], B.q[cur], B.p[cur], B.r[nx], B.q[nx], B.p[nx], B.x, B.dinv,
                             B.k, w, c->stream, cur, chained, fin, sample ? c->pev[0] : nullptr,
                             sample ? c->pev[1] : nullptr);
@@ -380,8 +391,19 @@ int solve_fused(otm_ctx* c, bool x_zero, bool mixed, const FusedBufs<T>& B, otm_
             cur = nx;
             ++launches;
         }
+        HIPCHK(c, hipMemcpyAsync(c->h_sc, c->sc, sizeof(Scalars), hipMemcpyDeviceToHost, c->stream));
+        HIPCHK(c, hipEventRecord(c->cev, c->stream));
+        bridged = 0;
+        if (bridge) {
+            const int nx = cur ^ 1;
+            launch_fused<T>(n, c->tile2, all, B.r[cur], B.q[cur], B.p[cur], B.r[nx], B.q[nx], B.p[nx], B.x, B.dinv,
+                            B.k, w, c->stream, cur, false, true, nullptr, nullptr);
+            cur = nx;
+            ++launches;
+            bridged = 1;
+        }
         if ((rc = check_launch(c, "pcg fused"))) return rc;
-        if ((rc = sync_scalars(c))) return rc;
+        HIPCHK(c, hipEventSynchronize(c->cev));
         // fused pass: r, q, p, x read and written, D^-1 and k read (three loads)
         collect_pass_sample(c, sampled, (double)c->nn * (8.0 * 3 + 1 + 1) * sizeof(T), 4);
         bool refresh = all_inactive(c->h_sc);
@@ -397,6 +419,7 @@ int solve_fused(otm_ctx* c, bool x_zero, bool mixed, const FusedBufs<T>& B, otm_
             if ((rc = sync_scalars(c))) return rc;
             for (int l = 0; l < 3; ++l) rr_ref[l] = c->h_sc->rr_true[l];
             if (mixed) ++refreshes;
+            bridged = 0;  // the scalars now describe the current state
         }
         if (watch.stop(c->h_sc)) break;
     }
@@ -880,6 +903,7 @@ int free_all(otm_ctx* c) {
         if (e) (void)hipEventDestroy(e);
     for (auto& e : c->pev)
         if (e) (void)hipEventDestroy(e);
+    if (c->cev) (void)hipEventDestroy(c->cev);
     if (c->own_stream && c->stream) (void)hipStreamDestroy(c->stream);
     return 0;
 }
@@ -1361,6 +1385,7 @@ int otm_create(const otm_problem* problem, const otm_solver_opts* solver, const 
         if (hipEventCreate(&c->ev[q]) != hipSuccess) rc = OTM_EDEVICE;
     for (int q = 0; q < 2 && !rc; ++q)
         if (hipEventCreate(&c->pev[q]) != hipSuccess) rc = OTM_EDEVICE;
+    if (!rc && hipEventCreateWithFlags(&c->cev, hipEventDisableTiming) != hipSuccess) rc = OTM_EDEVICE;
     if (rc) {
         free_all(c);
         delete c;
