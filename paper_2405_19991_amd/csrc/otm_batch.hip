@@ -225,14 +225,17 @@ int sync_sc(otm_batch* c) {
     return OTM_OK;
 }
 
+// The solver part of every design's scalar block reset (one launch on the
+// device, the host mirror alike); a copy per design cost a blit each.
 int reset_solver(otm_batch* c) {
     const size_t head = offsetof(Scalars, sum_rho);
+    const double tol2 = c->so.tol * c->so.tol;
     for (int d = 0; d < c->count; ++d) {
         std::memset(&c->h_sc[d], 0, head);
-        c->h_sc[d].tol2 = c->so.tol * c->so.tol;
-        BCHK(c, hipMemcpyAsync(&c->sc[d], &c->h_sc[d], head, hipMemcpyHostToDevice, c->stream));
+        c->h_sc[d].tol2 = tol2;
     }
-    return OTM_OK;
+    launch_b_reset_solver(c->sc, c->count, tol2, c->stream);
+    return blaunch_ok(c, "solver reset");
 }
 
 bool all_inactive(const otm_batch* c) {

@@ -422,6 +422,7 @@ void launch_update_vec(int n, T* x, T* r, const T* p, const T* q, const T* dinv,
                        bool fin = true, int fin_op = FIN_UPDATE, float* r32 = nullptr);
 
 // Batched launches (one launch covers every design).
+void launch_b_reset_solver(Scalars* sc, int count, double tol2, hipStream_t s);
 void launch_b_clamp(const BatchTab& t, double* rho, double lo, double hi, hipStream_t s);
 void launch_b_filter_simp(const BatchTab& t, const double* rho, double* rhof, double* k, double* partials,
                           Scalars* sc, hipStream_t s);

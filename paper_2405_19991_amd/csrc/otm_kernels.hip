@@ -1228,6 +1228,19 @@ namespace otm {
     (void)o1;                                                 \
     (void)o3;
 
+// Every design's solver scalars (the fields before sum_rho) cleared and tol^2
+// set, in one launch; the reductions stored after them are kept.
+constexpr int kSolverWords = (int)(offsetof(Scalars, sum_rho) / sizeof(double));
+static_assert(offsetof(Scalars, sum_rho) % sizeof(double) == 0, "solver scalars are whole doubles");
+static_assert(offsetof(Scalars, tol2) % sizeof(double) == 0, "tol2 is a double slot");
+__global__ void __launch_bounds__(kBlock) kb_reset_solver(Scalars* __restrict__ sc, int count, double tol2) {
+    const int i = blockIdx.x * kBlock + threadIdx.x;
+    if (i >= count * kSolverWords) return;
+    const int d = i / kSolverWords, w = i - d * kSolverWords;
+    double* p = reinterpret_cast<double*>(sc + d);
+    p[w] = (w == (int)(offsetof(Scalars, tol2) / sizeof(double))) ? tol2 : 0.0;
+}
+
 __global__ void __launch_bounds__(kBlock) kb_clamp(BatchTab t, double* rho, double lo, double hi) {
     OTM_BATCH_ITEM
     b_clamp(lb_, nb_, (int64_t)D.n * D.n * D.n, rho + o1, lo, hi);
@@ -1346,6 +1359,10 @@ __global__ void __launch_bounds__(kBlock) kb_finalize(BatchTab t, int op, int wh
     b_finalize(op, cnt, partials + (size_t)start * width, sc + d, (int64_t)D.n * D.n * D.n, eta);
 }
 
+void launch_b_reset_solver(Scalars* sc, int count, double tol2, hipStream_t s) {
+    const int threads = count * kSolverWords;
+    hipLaunchKernelGGL(kb_reset_solver, dim3((threads + kBlock - 1) / kBlock), dim3(kBlock), 0, s, sc, count, tol2);
+}
 void launch_b_clamp(const BatchTab& t, double* rho, double lo, double hi, hipStream_t s) {
     hipLaunchKernelGGL(kb_clamp, dim3(t.eb_total), dim3(kBlock), 0, s, t, rho, lo, hi);
 }
