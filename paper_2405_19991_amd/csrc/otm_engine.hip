@@ -783,11 +783,15 @@ int homogenize(otm_ctx* c, double kappa6[6], otm_solve_stats* st_out) {
     if (c->so.guess == OTM_GUESS_USER && c->have_user_guess) have_guess = true;
     c->learned_used = 0;
     if (c->so.guess == OTM_GUESS_LEARNED && c->net && c->n % 16 == 0) {
-        HIPCHK(c, hipStreamSynchronize(c->stream));
+        // the network runs on its own stream: it starts after prepare() and
+        // the solve after it, ordered by events on the device (no host wait)
+        const hipStream_t ns = nn_stream(c->net);
+        HIPCHK(c, hipEventRecord(c->cev, c->stream));
+        HIPCHK(c, hipStreamWaitEvent(ns, c->cev, 0));
         rc = otm_nn_forward(c->net, c->n, c->rhof, c->x);
         if (rc) return fail(c, rc, "network forward failed");
-        // the network runs on its own stream
-        HIPCHK(c, hipDeviceSynchronize());
+        HIPCHK(c, hipEventRecord(c->cev, ns));
+        HIPCHK(c, hipStreamWaitEvent(c->stream, c->cev, 0));
         have_guess = true;
     }
     bool x_zero = true;

@@ -483,4 +483,8 @@ void launch_fill_u32(unsigned* p, int count, unsigned v, hipStream_t s);
 void launch_cast_f64_f32(int64_t count, const double* in, float* out, hipStream_t s);
 void launch_cast_f32_f64(int64_t count, const float* in, double* out, hipStream_t s);
 
+// The stream a network's kernels run on (a context orders its solve after
+// the network's forward pass with an event on it).
+hipStream_t nn_stream(const otm_nn* net);
+
 }  // namespace otm

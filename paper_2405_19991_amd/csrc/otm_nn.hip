@@ -481,6 +481,8 @@ struct otm_nn {
     std::string err;
 };
 
+hipStream_t otm::nn_stream(const otm_nn* net) { return net->stream; }
+
 namespace {
 
 constexpr int kLayerParams = kNNW + 16;
