@@ -404,8 +404,9 @@ int solve_fused(otm_ctx* c, bool x_zero, bool mixed, const FusedBufs<T>& B, otm_
         }
         if ((rc = check_launch(c, "pcg fused"))) return rc;
         HIPCHK(c, hipEventSynchronize(c->cev));
-        // fused pass: r, q, p, x read and written, D^-1 and k read (three loads)
-        collect_pass_sample(c, sampled, (double)c->nn * (8.0 * 3 + 1 + 1) * sizeof(T), 4);
+        // fused pass: r, q, p, x read and written, D^-1 and k read (three loads);
+        // the sample counts only if every load still ran its last pass
+        collect_pass_sample(c, sampled && all_active(c->h_sc), (double)c->nn * (8.0 * 3 + 1 + 1) * sizeof(T), 4);
         bool refresh = all_inactive(c->h_sc);
         if (mixed)
             for (int l = 0; l < 3; ++l)

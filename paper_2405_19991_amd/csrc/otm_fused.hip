@@ -359,6 +359,10 @@ __device__ __forceinline__ void fused_body(int tile, int slot, int nslots, bool 
         load_plane(z0 - 1, fa);
         load_plane(z0, fb);
         take_state();
+        // every load stopped inside the chunk: nothing left to step until the
+        // host sees it (the finalize ignores inactive loads' sums; a restart
+        // recomputes r from x and keeps the last consistent p, q = A p pair)
+        if (!st_sh.active[0] && !st_sh.active[1] && !st_sh.active[2]) return;
     } else {
         take_state();
         load_plane(z0 - 1, fa);
