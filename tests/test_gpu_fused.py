@@ -5,6 +5,8 @@ arithmetic, so it is held to the same oracle tolerances as the other kernels
 (tensor relative error 1e-9 in FP64 solved to 1e-11, 1e-5 mixed), and its
 iteration counts to those of the two-pass iteration.
 """
+import itertools
+
 import numpy as np
 import pytest
 
@@ -177,3 +179,35 @@ def test_chained_inactive_loads_and_oracle():
         kappa, st = h.homogenize()
     assert st["converged"] and st["iterations"][0] == 0 and st["iterations"][1] == 0
     np.testing.assert_allclose(kappa[:3], [k.mean(), k.mean(), 1.0 / np.mean(1.0 / k)], rtol=1e-9)
+
+
+@pytest.mark.parametrize("precision", ["fp64", "mixed"])
+def test_fused_loads_stopping_together(precision):
+    """A density symmetric under every permutation of the axes: the three
+    loads converge within a couple of passes of each other, inside one check
+    interval, so the all-loads passes still queued in that chunk (and the
+    pass bridging the host's check) find every load stopped and return at
+    once.  The tensor matches the oracle; in float64, where only the device
+    decides when a load stops, checking every 16 passes and after every pass
+    give the same iteration counts and the same tensor bit for bit."""
+    n = 24
+    base = synth.smoothed_noise(n, 0.05, 0.95, 91)
+    rho = sum(np.transpose(base, p) for p in itertools.permutations(range(3))) / 6.0
+    tol = 1e-11 if precision == "fp64" else 1e-6
+    ref = O.homogenize(rho, O.Params(tol=1e-13))
+    out = {}
+    for ce in (16, 1):
+        print(f"loads stopping together {precision} check_every={ce}", flush=True)
+        with make(n, rho, precision=precision, tol=tol, kernel_variant=4, check_every=ce) as h:
+            kappa, st = h.homogenize()
+            out[ce] = (np.array(kappa), list(st["iterations"]), h.timings()[7])
+        assert st["converged"]
+    its = out[16][1]
+    assert max(its) - min(its) <= 2, its
+    assert out[16][2] > max(its)  # passes were launched after the last load stopped
+    bar = 1e-9 if precision == "fp64" else 1e-5
+    assert rel_fro(out[16][0], ref["kappa"]) <= bar
+    assert rel_fro(out[1][0], ref["kappa"]) <= bar
+    if precision == "fp64":
+        assert out[16][1] == out[1][1]
+        np.testing.assert_array_equal(out[16][0], out[1][0])
