@@ -119,7 +119,8 @@ int balloc(otm_batch* c, T** p, int64_t n) {
 }
 
 // Work lists for a given z-march tile (tx = 2 wx nodes wide, 256/wx rows) and
-// march length tz; element sweeps use up to 256 blocks per design.
+// march length tz; element sweeps give each thread at least four elements and
+// use up to 256 blocks per design.
 void build_tables(otm_batch* c, int wx, int tz) {
     const int tx = 2 * wx, ty = kBlock / wx;
     c->hdesc.resize(c->count);
@@ -131,7 +132,10 @@ void build_tables(otm_batch* c, int wx, int tz) {
         D.n = n;
         D.off = c->off[d];
         D.eb_start = (int)ebd.size();
-        int64_t nb = (nn + kBlock - 1) / kBlock;
+        // at least four elements per thread: the element sweeps end in block
+        // reductions (up to 31 values for the OC bisection) that a block
+        // with one element per thread spends most of its time on
+        int64_t nb = (nn + 4 * kBlock - 1) / (4 * kBlock);
         D.eb_count = (int)std::min<int64_t>(nb, 256);
         for (int q = 0; q < D.eb_count; ++q) ebd.push_back(d);
         D.ntx = (n + tx - 1) / tx;
