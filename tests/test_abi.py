@@ -254,3 +254,51 @@ def test_multigrid_smoother_rejected(L):
     s.precision, s.preconditioner, s.mg_smoother = N.OTM_MIXED, N.OTM_PRECOND_MG, 2
     h = ctypes.c_void_p()
     assert L.otm_create(ctypes.byref(p), ctypes.byref(s), None, None, None, ctypes.byref(h)) == N.OTM_EINVAL
+
+
+def test_header_is_c_and_layouts_match_binding(L, tmp_path):
+    """The public header compiles as C99 on its own; a C program linked
+    against the library runs the host-only calls (version, default options,
+    initial densities); and every public struct has the size and the field
+    offsets of its ctypes mirror in the Python binding."""
+    import shutil
+    import subprocess
+    from paper_2405_19991_amd import _native as N
+    cc = shutil.which("gcc") or shutil.which("cc")
+    if cc is None:
+        pytest.skip("no C compiler")
+    structs = {"otm_problem": N.Problem, "otm_solver_opts": N.SolverOpts, "otm_oc_opts": N.OcOpts,
+               "otm_governor_opts": N.GovernorOpts, "otm_solve_stats": N.SolveStats,
+               "otm_iter_record": N.IterRecord}
+    src = ["#include <stdio.h>", "#include <stddef.h>", '#include "opentm_amd.h"', "int main(void) {"]
+    cfield = {"lambda_": "lambda"}  # Python keywords carry a trailing underscore in the binding
+    for cname, cls in structs.items():
+        src.append(f'    printf("{cname} %zu\\n", sizeof({cname}));')
+        for fname, _ in cls._fields_:
+            src.append(f'    printf("{cname}.{fname} %zu\\n", offsetof({cname}, {cfield.get(fname, fname)}));')
+    src += ['    printf("version %s\\n", otm_version());',
+            "    otm_solver_opts s; otm_oc_opts o; otm_governor_opts g;",
+            "    otm_default_options(&s, &o, &g);",
+            '    printf("move %.3f\\n", o.move);',
+            "    static double rho[8 * 8 * 8];",
+            "    int rc = otm_init_density(8, OTM_INIT_P, 0.25, rho);",
+            "    int solid = 0;",
+            "    for (int i = 0; i < 512; ++i) solid += rho[i] > 0.5;",
+            '    printf("init %d %d\\n", rc, solid);',
+            "    return 0;", "}"]
+    prog = tmp_path / "abi_check.c"
+    prog.write_text("\n".join(src) + "\n")
+    exe = tmp_path / "abi_check"
+    libdir = os.path.dirname(N.LIBPATH)
+    subprocess.run([cc, "-std=c99", "-Wall", "-Werror", "-I", os.path.join(ROOT, "include"), str(prog),
+                    "-L", libdir, "-lopentm_amd", "-Wl,-rpath," + libdir, "-o", str(exe)], check=True)
+    out = subprocess.run([str(exe)], check=True, capture_output=True, text=True).stdout.split("\n")
+    got = dict(line.split(" ", 1) for line in out if line)
+    for cname, cls in structs.items():
+        assert int(got[cname]) == ctypes.sizeof(cls), cname
+        for fname, _ in cls._fields_:
+            assert int(got[f"{cname}.{fname}"]) == getattr(cls, fname).offset, f"{cname}.{fname}"
+    assert "gfx950" in got["version"]
+    assert float(got["move"]) == 0.05
+    rc, solid = map(int, got["init"].split())
+    assert rc == 0 and solid == round(0.25 * 512)
