@@ -162,6 +162,38 @@ def assemble(k: np.ndarray) -> CSR27:
     return CSR27(n, cols, vals)
 
 
+def apply_at(k_patch: np.ndarray, x_patch: np.ndarray, absolute: bool = False) -> np.ndarray:
+    """(A x) at single nodes from their neighbourhoods, by the definition of
+    the assembled operator A = sum_e k_e P_e^T K P_e (Sec. 2, the discrete
+    periodic cell problem; vertex order l = a + 2b + 4c): the node is vertex
+    (1-cx, 1-cy, 1-cz) of the element whose lower corner sits at
+    node + (cx-1, cy-1, cz-1), and that element's vertex (a, b, c) is the
+    neighbour node + (cx-1+a, cy-1+b, cz-1+c).
+
+    k_patch: (m, 2, 2, 2) conductivities of those eight elements, [cz][cy][cx].
+    x_patch: (m, L, 3, 3, 3) values at node + (dx-1, dy-1, dz-1), [dz][dy][dx].
+    absolute: use |K| entries and |x| (the bound sum_b |A_vb| |x_b| for
+    rounding tolerances).  Returns (m, L).  Plain loops, for sampled nodes of
+    grids too large to assemble."""
+    K = element_matrix()
+    if absolute:
+        K = np.abs(K)
+        x_patch = np.abs(x_patch)
+    k_patch = np.asarray(k_patch, dtype=np.float64)
+    x_patch = np.asarray(x_patch, dtype=np.float64)
+    m, L = x_patch.shape[0], x_patch.shape[1]
+    out = np.zeros((m, L))
+    for cz in (0, 1):
+        for cy in (0, 1):
+            for cx in (0, 1):
+                lv = (1 - cx) + 2 * (1 - cy) + 4 * (1 - cz)
+                ke = k_patch[:, cz, cy, cx][:, None]
+                for l in range(8):
+                    a, b, c = l & 1, (l >> 1) & 1, (l >> 2) & 1
+                    out += ke * K[lv, l] * x_patch[:, :, cz + c, cy + b, cx + a]
+    return out
+
+
 def macro_loads(k: np.ndarray) -> np.ndarray:
     """(3, n, n, n) right-hand sides b^i."""
     k = _c(k)

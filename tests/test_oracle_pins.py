@@ -518,3 +518,39 @@ def test_symmetric_oc_iteration_output_is_exactly_symmetric():
     flat = rho_new.reshape(-1)
     np.testing.assert_array_equal(flat, flat[::-1])
     np.testing.assert_array_equal(s.reshape(-1), s.reshape(-1)[::-1])
+
+
+def patches(k, x, nodes):
+    """Neighbourhoods of the given nodes (i, j, kz) for oracle.apply_at, with
+    periodic wrap: k of the eight incident elements, x of the 27 nodes."""
+    n = k.shape[0]
+    kp = np.empty((len(nodes), 2, 2, 2))
+    xp = np.empty((len(nodes), x.shape[0], 3, 3, 3))
+    for q, (i, j, kz) in enumerate(nodes):
+        for cz in (0, 1):
+            for cy in (0, 1):
+                for cx in (0, 1):
+                    kp[q, cz, cy, cx] = k[(kz + cz - 1) % n, (j + cy - 1) % n, (i + cx - 1) % n]
+        for dz in range(3):
+            for dy in range(3):
+                for dx in range(3):
+                    xp[q, :, dz, dy, dx] = x[:, (kz + dz - 1) % n, (j + dy - 1) % n, (i + dx - 1) % n]
+    return kp, xp
+
+
+@pytest.mark.parametrize("n", [3, 5, 6])
+def test_apply_at_equals_assembled_operator(n):
+    """The node-by-node operator equals the assembled CSR operator at every
+    node (periodic wrap included), and its absolute form bounds it."""
+    g = synth.rng(300 + n)
+    k = g.uniform(1e-3, 1.0, size=(n, n, n))
+    x = g.standard_normal((2, n, n, n))
+    A = O.assemble(k)
+    nodes = [(i, j, kz) for kz in range(n) for j in range(n) for i in range(n)]
+    kp, xp = patches(k, x, nodes)
+    got = O.apply_at(kp, xp)
+    for l in range(2):
+        ref = A.matvec(x[l]).reshape(-1)
+        np.testing.assert_allclose(got[:, l], ref, rtol=0, atol=1e-13 * np.abs(ref).max())
+    bound = O.apply_at(kp, xp, absolute=True)
+    assert np.all(np.abs(got) <= bound * (1 + 1e-12))
