@@ -73,6 +73,11 @@ def test_null_arguments(L):
     assert L.otm_device_bytes(None, ctypes.byref(b)) == N.OTM_EINVAL
     assert L.otm_batch_device_bytes(None, ctypes.byref(b)) == N.OTM_EINVAL
     assert b.value == -1
+    # checkpoint calls: a null handle or an empty path is refused before any file or device access
+    for fn in (L.otm_save_state, L.otm_load_state, L.otm_batch_save_state, L.otm_batch_load_state):
+        assert fn(None, b"/nonexistent/state.otm") == N.OTM_EINVAL
+        assert fn(None, None) == N.OTM_EINVAL
+    assert L.otm_nn_load(None, b"/nonexistent/w.npy") == N.OTM_EINVAL
 
 
 def test_batch_create_rejects_odd_or_bad_sizes(L):
