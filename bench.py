@@ -64,6 +64,7 @@ def parse():
     ap.add_argument("--no-gallery", action="store_true", help="skip the 61-target traversal leg")
     ap.add_argument("--no-full-run", action="store_true", help="skip the 150-iteration design runs")
     ap.add_argument("--no-fp64", action="store_true", help="skip the float64 leg")
+    ap.add_argument("--no-fused-sizes", action="store_true", help="skip the fused pass at 192^3 and 256^3")
     ap.add_argument("--gallery-iters", type=int, default=500)
     ap.add_argument("--gallery-n", type=int, default=32)
     ap.add_argument("--retune", action="store_true",
@@ -399,6 +400,39 @@ def config_legs(steps: int, log):
 
 
 @collected
+@collected
+def fused_sizes_leg(log, sizes=(192, 256)):
+    """The fused PCG pass on larger cells (mixed, Jacobi-PCG, the
+    autotuner's tile): its live per-launch timing over two solves after one
+    design iteration, against the minimum PCG-iteration bytes (76 B/node)
+    and the pass's own schedule (104 B/node).  At 128^3 the pass's vectors
+    largely stay in the 256 MB Infinity Cache between passes; at these
+    sizes they stream from HBM."""
+    import synth
+    from paper_2405_19991_amd import Homogenization
+    out = []
+    for n in sizes:
+        rho = synth.smoothed_noise(n, 0.15, 0.45, 301)
+        with Homogenization(n, (1.0, 1e-3), (0.3, 0.2, 0.1, 0.1, 0.05, 0.05), vf=0.3, precision="mixed",
+                            tol=1e-6) as h:
+            h.set_density(rho)
+            h.step()
+            h.pass_timing(reset=True)
+            h.homogenize()
+            h.homogenize()
+            pt, tile = h.pass_timing(), h.tile()
+        rec = {"n": n, "tile": tile, "kernel": "k_fused_f32" if pt["kernel"] == 4 else "direction+operator",
+               "sampled_launches": pt["launches"], "us_per_launch": pt["us"]}
+        if pt["launches"] > 0 and pt["kernel"] == 4:
+            alg = 76.0 * n ** 3
+            rec.update(alg_bytes_per_launch=alg, frac=alg / (pt["us"] * 1e-6) / 1e9 / HBM_PEAK_GBS,
+                       schedule_frac=pt["bytes"] / (pt["us"] * 1e-6) / 1e9 / HBM_PEAK_GBS)
+            log(f"fused pass {n}^3: {pt['us']:.1f} us, {rec['frac']:.3f} of peak on 76 B/node, "
+                f"{rec['schedule_frac']:.3f} on its schedule")
+        out.append(rec)
+    return out
+
+
 def warm_start_leg(weights, log):
     """Time to 1e-6 on the held-out 128^3 cell at design iteration 5: zero
     start (FP64, mixed), previous design iteration's solution, and the trained
@@ -717,6 +751,8 @@ def main():
                                      governor={"dg_small": 1e-4})
     if not args.no_warm_start and n == 128:
         out["warm_start"] = warm_start_leg(args.weights, log)
+    if not args.no_fused_sizes and args.preconditioner == "jacobi" and args.precision == "mixed" and n == 128:
+        out["fused_sizes"] = fused_sizes_leg(log)
     # the operator in the other precision and at 256^3 (whose buffers exceed
     # the Infinity Cache), best of a few z-march shapes each; last, because
     # seconds of streaming at full bandwidth slow the GPU work right after it
