@@ -39,7 +39,9 @@ from typing import Dict, List, Optional, Sequence
 import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-_LIBPATH = os.path.join(_HERE, "liboracle.so")
+# OTM_ORACLE_LIB may name another build of the same source (the sanitizer
+# check runs the oracle from an instrumented copy)
+_LIBPATH = os.environ.get("OTM_ORACLE_LIB") or os.path.join(_HERE, "liboracle.so")
 _lib = None
 
 _dp = ctypes.POINTER(ctypes.c_double)

@@ -17,5 +17,16 @@ def build(verbose: bool = False) -> str:
     return LIB
 
 
+def build_sanitized(path: str, verbose: bool = False) -> str:
+    """The same source with AddressSanitizer and UndefinedBehaviorSanitizer
+    (undefined behaviour aborts), for the host-side sanitizer check."""
+    cmd = ["gcc", "-O1", "-g", "-std=c11", "-fopenmp", "-fPIC", "-shared", "-fno-omit-frame-pointer",
+           "-fsanitize=address,undefined", "-fno-sanitize-recover=undefined", "-o", path, SRC, "-lm"]
+    if verbose:
+        print(" ".join(cmd), flush=True)
+    subprocess.check_call(cmd)
+    return path
+
+
 if __name__ == "__main__":
     print(build(verbose="-v" in sys.argv))
